@@ -1,0 +1,168 @@
+/*
+ * nof.h -- C ABI of the MI355X (gfx950) density-fitted JK / generalized-Fock
+ * library, the per-iteration hot path of natural-orbital-functional (NOF)
+ * orbital optimisation (DoNOF 2.0, arXiv 2512.13550).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Array arguments are DEVICE pointers (HBM), row-major, owned by the
+ *    caller.  The library never allocates or frees caller memory; scratch
+ *    space is passed in as a caller-owned workspace whose size the matching
+ *    *_ws() query returns.
+ *  - Work is enqueued asynchronously on `stream` (0 = the null stream).
+ *    Scalar results are written to device memory.
+ *  - Return value: NOF_OK (0) or a negative nof_status.  All shape, pointer,
+ *    dtype, precision and workspace checks run on the host before anything is
+ *    launched; on failure nothing is enqueued.  A failed launch returns
+ *    NOF_E_HIP.  Faults inside a kernel surface at the caller's next
+ *    synchronisation, as for any HIP work.
+ *  - No C++ exception crosses this boundary.
+ *  - Entry points are re-entrant; calls on different streams may overlap as
+ *    long as they do not share output or workspace buffers.
+ *
+ * Notation (paper, Theory and NO Optimization sections):
+ *   naux   auxiliary (density-fitting) basis size, index P
+ *   nbf    AO basis size, indices mu, nu
+ *   norb   number of natural orbitals, indices p, q, r, s
+ *   B[P][mu][nu]  RI three-index tensor (ERITYP='RI'), symmetric in (mu,nu)
+ *   C[mu][p]      NO coefficients, column p = orbital p
+ *   b[P][p][q]    = (C^T B^P C)_pq, symmetric in (p,q)
+ *   D[P][p]       = b^P_pp
+ *   J_pq = sum_P D[P][p] D[P][q]      Coulomb integrals (pp|qq)
+ *   K_pq = sum_P (b^P_pq)^2            exchange integrals (pq|qp)
+ *   Eq. (PNOF): E = 2 sum_p n_p h_pp + sum_pq cJ_pq J_pq - sum_pq cK_pq K_pq
+ *     with cJ = A and cK = B + C (L = K for real orbitals).
+ */
+#ifndef NOF_H
+#define NOF_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NOF_OK = 0,
+  NOF_E_NULL = -1,          /* a required pointer is NULL                        */
+  NOF_E_DIM = -2,           /* a size is out of range or inconsistent            */
+  NOF_E_DTYPE = -3,         /* unsupported storage type for this argument        */
+  NOF_E_PREC = -4,          /* unsupported precision mode for this entry point   */
+  NOF_E_WORKSPACE = -5,     /* workspace NULL or smaller than the *_ws() query   */
+  NOF_E_HIP = -6,           /* a HIP runtime call or kernel launch failed        */
+  NOF_E_NOT_CONVERGED = -7, /* iteration cap reached before the tolerance        */
+  NOF_E_ARG = -8,           /* an argument value is invalid (e.g. a handle)      */
+  NOF_E_INTERNAL = -99
+} nof_status;
+
+/* Storage type of a large tensor argument (B, b). */
+typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2 } nof_dtype;
+
+/* Arithmetic used by the matrix-core (MFMA) contractions.
+ *   NOF_P_F64     FP64 MFMA, FP64 accumulation.
+ *   NOF_P_F32     FP32 MFMA, FP32 accumulation inside one auxiliary slab,
+ *                 FP64 across slabs.
+ *   NOF_P_BF16X1  one BF16 product, FP32 accumulation.
+ *   NOF_P_BF16X3  operands split into BF16 hi+lo, products hi*hi+hi*lo+lo*hi.
+ *   NOF_P_BF16X6  operands split into BF16 hi+mid+lo, the six products whose
+ *                 combined order of magnitude is at most two splits down.
+ * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
+typedef enum {
+  NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4
+} nof_prec;
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* nof_status_str(int status);
+
+/* ---------------------------------------------------------------------------
+ * Orbital transformation (Single Point Energy Calculations, ERITYP='RI':
+ * the RI route whose transformation is fourth order).
+ *
+ *   b^P = C^T B^P C  for P = 0..naux-1,   D[P][p] = b^P_pp.
+ *
+ * B   [naux][nbf][nbf], storage Bt (NOF_F64 or NOF_F32).  Must be symmetric
+ *     in (mu,nu): the kernel reads B^P_{nu mu} where the definition has
+ *     B^P_{mu nu}.
+ * C   [nbf][norb] FP64 (the master copy; converted on load for FP32 math).
+ * b   out [naux][norb][norb], storage bt (== Bt); written exactly symmetric.
+ * D   out [naux][norb] FP64, may be NULL.
+ * prec  NOF_P_F64 (Bt = bt = NOF_F64) or NOF_P_F32 (Bt = bt = NOF_F32).
+ * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C).
+ *
+ * With naux = 1 and B = H (the AO one-electron matrix) this yields
+ * h = C^T H C, the one-electron integrals of Eq. (Energy) in the NO basis.
+ * ------------------------------------------------------------------------- */
+size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec);
+int nof_mo_transform(int naux, int nbf, int norb,
+                     const void* B, int Bt, const double* C,
+                     void* b, int bt, double* D,
+                     int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Coulomb and exchange integrals in the NO basis (Eq. PNOF's J and K).
+ *
+ *   J = D^T D            (J_pq = (pp|qq)),   may be NULL to skip
+ *   K_pq = sum_P b_pq^2  (K_pq = (pq|qp)),   may be NULL to skip
+ *
+ * b   [naux][norb][norb] storage bt (NOF_F64 or NOF_F32), symmetric.  Only
+ *     the upper triangle (p <= q) is read for K.
+ * D   [naux][norb] FP64.
+ * J,K out [norb][norb] FP64, exactly symmetric.  Accumulation is FP64 in a
+ *     fixed order, so results repeat bit for bit.
+ * ------------------------------------------------------------------------- */
+size_t nof_jk_diag_ws(int naux, int norb, int bt);
+int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
+                double* J, double* K, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Generalized-Fock (Lagrangian) build and orbital gradient (NO Optimization:
+ * the Lagrangian with multipliers lambda, and g_pq = dE/dy_pq =
+ * 4(lambda_pq - lambda_qp) for the rotation C <- C exp(y)).
+ *
+ * With W = D cJ:
+ *   lambda_rs = n_s h_rs + sum_P b^P_rs W[P][s]
+ *               - sum_P sum_q b^P_rq cK_sq b^P_qs
+ *   grad = 4 (lambda - lambda^T)
+ *
+ * n       [norb] occupation numbers (0 <= n <= 1), FP64.
+ * h       [norb][norb] FP64, h = C^T H C.
+ * cJ, cK  [norb][norb] FP64, must be symmetric (Eq. PNOF coefficients).
+ * lambda  out [norb][norb] FP64.          grad  out, may be NULL.
+ * K_opt   if not NULL, also receives K (same definition as nof_jk_diag),
+ *         formed in the same pass over b as the Coulomb-type term.
+ * prec    NOF_P_F64 (bt = NOF_F64) or NOF_P_F32 (bt = NOF_F32) for the
+ *         exchange-type contraction; the pass over b accumulates in FP64.
+ * ------------------------------------------------------------------------- */
+size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec);
+int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D,
+                 const double* n, const double* h,
+                 const double* cJ, const double* cK,
+                 double* lambda, double* grad, double* K_opt,
+                 int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Energy of Eq. (PNOF):
+ *   E = 2 sum_p n_p h_pp + sum_pq cJ_pq J_pq - sum_pq cK_pq K_pq
+ * All inputs [norb] or [norb][norb] FP64; E is one FP64 device scalar.
+ * Deterministic fixed-order FP64 reduction.
+ * ------------------------------------------------------------------------- */
+int nof_energy(int norb, const double* n, const double* h,
+               const double* J, const double* K,
+               const double* cJ, const double* cK, double* E, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Coefficients of Eq. (PNOF) from the cumulant matrices of the (2,2)-positivity
+ * reconstruction (Theory: cumulant blocks lambda^{sigma sigma} and
+ * lambda^{alpha beta} in terms of Delta and Pi):
+ *   cJ = 2 (n n^T - Delta),   cK = n n^T - Delta - Pi
+ * n [norb]; Delta, Pi, cJ, cK [norb][norb], all FP64.
+ * ------------------------------------------------------------------------- */
+int nof_coeffs_from_cumulant(int norb, const double* n, const double* Delta,
+                             const double* Pi, double* cJ, double* cK,
+                             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NOF_H */

@@ -1,0 +1,253 @@
+// extern "C" entry points declared in include/nof.h: host-side validation,
+// workspace layout and the launch sequence of each call.
+#include <new>
+
+#include "common.h"
+
+using namespace nof;
+
+namespace {
+
+constexpr int kMaxDim = 1 << 20;
+
+bool dim_ok(int x) { return x >= 1 && x <= kMaxDim; }
+
+// Workspace of nof_jk_diag: J split partials, K chunk partials.
+struct JkLayout {
+  int jsplit, jk, kchunks;
+  size_t off_jpart, off_kpart, total;
+};
+JkLayout jk_layout(int naux, int norb) {
+  JkLayout L;
+  const int tn = (norb + 127) / 128;
+  const int tiles = tn * (tn + 1) / 2;
+  int js = 512 / tiles;
+  if (js < 1) js = 1;
+  if (js > naux) js = naux;
+  L.jk = (naux + js - 1) / js;
+  L.jsplit = (naux + L.jk - 1) / L.jk;
+  L.kchunks = kf1_chunks(naux, norb);
+  const size_t n2 = (size_t)norb * norb * sizeof(double);
+  L.off_jpart = 0;
+  L.off_kpart = align256(L.off_jpart + (size_t)L.jsplit * n2);
+  L.total = align256(L.off_kpart + (size_t)L.kchunks * n2);
+  return L;
+}
+
+// Workspace of nof_gen_fock: W, F1/K chunk partials, F2 partials, F1, F2.
+struct FockLayout {
+  int kchunks, f2fold, f2groups;
+  size_t off_W, off_f1part, off_kpart, off_f2part, off_F1, off_F2, total;
+};
+FockLayout fock_layout(int naux, int norb) {
+  FockLayout L;
+  L.kchunks = kf1_chunks(naux, norb);
+  const int tn = (norb + 127) / 128;
+  const int tiles = tn * tn;
+  int groups = (512 + tiles - 1) / tiles;
+  if (groups > naux) groups = naux;
+  if (groups < 1) groups = 1;
+  L.f2fold = (naux + groups - 1) / groups;
+  L.f2groups = (naux + L.f2fold - 1) / L.f2fold;
+  const size_t n2 = (size_t)norb * norb * sizeof(double);
+  L.off_W = 0;
+  L.off_f1part = align256((size_t)naux * norb * sizeof(double));
+  L.off_kpart = align256(L.off_f1part + (size_t)L.kchunks * n2);
+  L.off_f2part = align256(L.off_kpart + (size_t)L.kchunks * n2);
+  L.off_F1 = align256(L.off_f2part + (size_t)L.f2groups * n2);
+  L.off_F2 = align256(L.off_F1 + n2);
+  L.total = align256(L.off_F2 + n2);
+  return L;
+}
+
+bool prec_matches(int prec, int t) {
+  return (prec == NOF_P_F64 && t == NOF_F64) || (prec == NOF_P_F32 && t == NOF_F32);
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return NOF_E_INTERNAL;
+  } catch (...) {
+    return NOF_E_INTERNAL;
+  }
+}
+
+#define NOF_TRY(expr)            \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != NOF_OK) return _rc; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* nof_status_str(int status) {
+  switch (status) {
+    case NOF_OK: return "ok";
+    case NOF_E_NULL: return "required pointer is NULL";
+    case NOF_E_DIM: return "size out of range or inconsistent";
+    case NOF_E_DTYPE: return "unsupported storage type";
+    case NOF_E_PREC: return "unsupported precision mode";
+    case NOF_E_WORKSPACE: return "workspace missing or too small";
+    case NOF_E_HIP: return "HIP runtime call or kernel launch failed";
+    case NOF_E_NOT_CONVERGED: return "iteration limit reached before convergence";
+    case NOF_E_ARG: return "invalid argument value";
+    case NOF_E_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
+  if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
+  if (Bt != bt || !prec_matches(prec, bt)) return 0;
+  return align256((size_t)naux * nbf * norb * dtype_size(bt));
+}
+
+int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const double* C, void* b,
+                     int bt, double* D, int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!B || !C || !b) return NOF_E_NULL;
+    if (Bt != bt || dtype_size(bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    const size_t need = nof_mo_transform_ws(naux, nbf, norb, Bt, bt, prec);
+    if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
+    // Stage 1: T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
+    GemmDesc g1{};
+    g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
+    g1.batch = naux; g1.fold = 1;
+    g1.X = B; g1.ldx = nbf; g1.sx = (long long)nbf * nbf; g1.x_kmajor = true;
+    g1.Y = C; g1.ldy = norb; g1.sy = 0;
+    g1.S = nullptr; g1.lds = 0;
+    g1.Out = ws; g1.ldo = norb; g1.so = (long long)nbf * norb;
+    g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
+    NOF_TRY(gemm_tn(g1, bt, NOF_F64, bt, prec, stream));
+    // Stage 2: b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
+    GemmDesc g2{};
+    g2.M = norb; g2.N = norb; g2.K = nbf; g2.Ktot = 0;
+    g2.batch = naux; g2.fold = 1;
+    g2.X = C; g2.ldx = norb; g2.sx = 0; g2.x_kmajor = true;
+    g2.Y = ws; g2.ldy = norb; g2.sy = (long long)nbf * norb;
+    g2.S = nullptr; g2.lds = 0;
+    g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
+    g2.Dg = D; g2.sd = norb; g2.sym = true;
+    return gemm_tn(g2, NOF_F64, bt, bt, prec, stream);
+  });
+}
+
+size_t nof_jk_diag_ws(int naux, int norb, int bt) {
+  if (!dim_ok(naux) || !dim_ok(norb)) return 0;
+  if (bt != NOF_F64 && bt != NOF_F32) return 0;
+  return jk_layout(naux, norb).total;
+}
+
+int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, double* J, double* K,
+                void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
+    if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
+    if ((K && !b) || (J && !D)) return NOF_E_NULL;
+    const JkLayout L = jk_layout(naux, norb);
+    if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
+    char* w = (char*)ws;
+    const long long n2 = (long long)norb * norb;
+    if (J) {
+      double* jpart = (double*)(w + L.off_jpart);
+      GemmDesc g{};
+      g.M = norb; g.N = norb; g.K = L.jk; g.Ktot = naux;
+      g.batch = L.jsplit; g.fold = 1;
+      g.X = D; g.ldx = norb; g.sx = (long long)L.jk * norb; g.x_kmajor = true;
+      g.Y = D; g.ldy = norb; g.sy = (long long)L.jk * norb;
+      g.S = nullptr; g.lds = 0;
+      g.Out = jpart; g.ldo = norb; g.so = n2;
+      g.Dg = nullptr; g.sd = 0; g.sym = true;
+      NOF_TRY(gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
+      NOF_TRY(reduce_parts(jpart, L.jsplit, n2, norb, false, J, stream));
+    }
+    if (K) {
+      double* kpart = (double*)(w + L.off_kpart);
+      NOF_TRY(kf1_pass(naux, norb, b, bt, nullptr, kpart, nullptr, L.kchunks, stream));
+      NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K, stream));
+    }
+    return NOF_OK;
+  });
+}
+
+size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec) {
+  if (!dim_ok(naux) || !dim_ok(norb)) return 0;
+  if (!prec_matches(prec, bt)) return 0;
+  return fock_layout(naux, norb).total;
+}
+
+int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, const double* n,
+                 const double* h, const double* cJ, const double* cK, double* lambda, double* grad,
+                 double* K_opt, int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!b || !D || !n || !h || !cJ || !cK || !lambda) return NOF_E_NULL;
+    if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    const FockLayout L = fock_layout(naux, norb);
+    if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
+    char* w = (char*)ws;
+    const long long n2 = (long long)norb * norb;
+    double* W = (double*)(w + L.off_W);
+    double* f1part = (double*)(w + L.off_f1part);
+    double* kpart = (double*)(w + L.off_kpart);
+    double* f2part = (double*)(w + L.off_f2part);
+    double* F1 = (double*)(w + L.off_F1);
+    double* F2 = (double*)(w + L.off_F2);
+    // W[P][s] = sum_q D[P][q] cJ[q][s]
+    GemmDesc gw{};
+    gw.M = naux; gw.N = norb; gw.K = norb; gw.Ktot = 0;
+    gw.batch = 1; gw.fold = 1;
+    gw.X = D; gw.ldx = norb; gw.sx = 0; gw.x_kmajor = false;
+    gw.Y = cJ; gw.ldy = norb; gw.sy = 0;
+    gw.S = nullptr; gw.lds = 0;
+    gw.Out = W; gw.ldo = norb; gw.so = 0;
+    gw.Dg = nullptr; gw.sd = 0; gw.sym = false;
+    NOF_TRY(gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
+    // Coulomb-type term F1 (and K) in one pass over the upper half of b
+    NOF_TRY(kf1_pass(naux, norb, b, bt, W, K_opt ? kpart : nullptr, f1part, L.kchunks, stream));
+    NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
+    if (K_opt) NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K_opt, stream));
+    // Exchange-type term F2_rs = sum_P sum_q b^P[q][r] (cK[q][s] b^P[q][s])
+    GemmDesc g2{};
+    g2.M = norb; g2.N = norb; g2.K = norb; g2.Ktot = 0;
+    g2.batch = naux; g2.fold = L.f2fold;
+    g2.X = b; g2.ldx = norb; g2.sx = n2; g2.x_kmajor = true;
+    g2.Y = b; g2.ldy = norb; g2.sy = n2;
+    g2.S = cK; g2.lds = norb;
+    g2.Out = f2part; g2.ldo = norb; g2.so = n2;
+    g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
+    NOF_TRY(gemm_tn(g2, bt, bt, NOF_F64, prec, stream));
+    NOF_TRY(reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream));
+    return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
+  });
+}
+
+int nof_energy(int norb, const double* n, const double* h, const double* J, const double* K,
+               const double* cJ, const double* cK, double* E, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb)) return NOF_E_DIM;
+    if (!n || !h || !J || !K || !cJ || !cK || !E) return NOF_E_NULL;
+    return energy(norb, n, h, J, K, cJ, cK, E, stream);
+  });
+}
+
+int nof_coeffs_from_cumulant(int norb, const double* n, const double* Delta, const double* Pi,
+                             double* cJ, double* cK, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb)) return NOF_E_DIM;
+    if (!n || !Delta || !Pi || !cJ || !cK) return NOF_E_NULL;
+    return coeffs_from_cumulant(norb, n, Delta, Pi, cJ, cK, stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Shared device/host helpers of the HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "nof.h"
+
+namespace nof {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Round a byte count up to a 256-byte boundary (workspace sub-buffers).
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Host-side status from the last launch.
+inline int launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? NOF_OK : NOF_E_HIP;
+}
+
+inline size_t dtype_size(int t) {
+  switch (t) {
+    case NOF_F64: return 8;
+    case NOF_F32: return 4;
+    case NOF_BF16: return 2;
+    default: return 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Internal launchers (defined in the .hip files, called by api.hip).
+// ---------------------------------------------------------------------------
+
+// Batched "TN" matrix product on the matrix cores:
+//   Out_b[m][n] = sum_k X_b(k, m) * Y_b(k, n) * S(k, n)
+// X_b(k,m) = X[b*sx + k*ldx + m]            (x_kmajor)
+//          = X[b*sx + m*ldx + k]            (!x_kmajor)
+// Y_b(k,n) = Y[b*sy + k*ldy + n];  S optional (FP64, shared by all b).
+// sym:  only tiles with tile_m <= tile_n are computed; elements with m <= n
+//       are written to Out[m][n] and Out[n][m]; Dg[b*sd + m] = Out[m][m].
+// fold: batches [c*fold, (c+1)*fold) are accumulated into one result that is
+//       written to Out + c*so (split reduction over the batch index).
+struct GemmDesc {
+  int M, N, K;
+  long long Ktot;    // if > 0: batch b only has k < Ktot - b*K (split-K over batches)
+  int batch;        // number of batches b
+  int fold;         // 1 = independent batches; >1 = accumulate groups of batches
+  const void* X; long long ldx, sx; bool x_kmajor;
+  const void* Y; long long ldy, sy;
+  const double* S; long long lds;
+  void* Out; long long ldo, so;
+  double* Dg; long long sd;
+  bool sym;
+};
+
+// Element types: 0 = f64, 1 = f32.  prec: NOF_P_F64 or NOF_P_F32.
+// X,Y element types given separately so that an FP64 master copy (C) can be
+// consumed by an FP32 contraction.  Out type: f64 or f32.
+int gemm_tn(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
+
+// Pass over the upper triangle of b (HBM bound):
+//   Kpart[c][r][s] = sum_{P in chunk c} b_rs^2              (r <= s)
+//   F1part[c][r][s] += b_rs W[P][s],  F1part[c][s][r] += b_rs W[P][r]
+// Either output may be NULL.
+int kf1_pass(int naux, int norb, const void* b, int bt, const double* W,
+             double* Kpart, double* F1part, int nchunk, hipStream_t st);
+int kf1_chunks(int naux, int norb);
+
+// out[i] = sum_c part[c*stride + i] in fixed order; if sym_upper, element
+// (r,s) is read from (min,max) and written to both (r,s) and (s,r).
+int reduce_parts(const double* part, int nparts, long long stride, int norb,
+                 bool sym_upper, double* out, hipStream_t st);
+
+int lambda_grad(int norb, const double* n, const double* h, const double* F1,
+                const double* F2, double* lam, double* grad, hipStream_t st);
+
+int energy(int norb, const double* n, const double* h, const double* J,
+           const double* K, const double* cJ, const double* cK, double* E,
+           hipStream_t st);
+
+int coeffs_from_cumulant(int norb, const double* n, const double* Delta,
+                         const double* Pi, double* cJ, double* cK, hipStream_t st);
+
+}  // namespace nof

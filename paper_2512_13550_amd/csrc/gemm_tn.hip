@@ -1,0 +1,242 @@
+// Matrix-core contraction used by the orbital transformation (both stages),
+// the exchange-type generalized-Fock term and the small J / W products.
+//
+//   Out_b[m][n] = sum_k X_b(k, m) * Y_b(k, n) * S(k, n)
+//
+// Both operands are consumed "k-major": a row of the LDS tile is one k and
+// holds consecutive m (or n).  That is exactly the layout the 16x16x4 MFMA
+// fragments want (lane l takes row k0 + l/16, column l%16), so fragment reads
+// are single conflict-free ds_read per lane.  Every operand of this library is
+// naturally k-major: B^P (symmetric), C, T^P = B^P C, b^P (symmetric) and D.
+//
+// Work decomposition: 256 threads = 4 waves in a 2x2 arrangement, each wave
+// owns a 64x64 block of the 128x128 output tile as 4x4 MFMA fragments.  K is
+// walked in stages of 16 through double-buffered LDS; global loads for stage
+// s+1 are in flight while stage s is multiplied.  The batch index (auxiliary
+// function P) is the outer grid dimension, remapped so that all tiles of one
+// batch run on the same XCD and share its L2.
+#include "common.h"
+
+namespace nof {
+namespace {
+
+constexpr int BM = 128;            // tile rows (m) == tile cols (n)
+constexpr int KT = 16;             // k per LDS stage
+constexpr int NTHR = 256;
+constexpr int LDSW = BM + 16;      // padded LDS row: k and k+1 land on disjoint bank halves
+constexpr int PER_T = KT * BM / NTHR;  // elements of one operand tile per thread (8)
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4v acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row (within the 16x16 fragment) held by register r of lane l
+  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef f4v acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+// Linear workgroup id -> logical id such that consecutive logical ids share an
+// XCD (the dispatcher deals workgroups to the 8 XCDs round-robin).
+__device__ __forceinline__ int xcd_logical(int w, int G) {
+  const int q = G >> 3, r = G & 7, x = w & 7, i = w >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Tile index -> (tm, tn) over the upper triangle tm <= tn of a T x T grid.
+__device__ __forceinline__ void upper_tile(int t, int T, int& tm, int& tn) {
+  int row = 0;
+  while (t >= T - row) { t -= T - row; ++row; }
+  tm = row;
+  tn = row + t;
+}
+
+template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
+__global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, int ntiles) {
+  typedef Mfma<TC> MF;
+  typedef typename MF::acc_t acc_t;
+  __shared__ TC Xs[2][KT][LDSW];
+  __shared__ TC Ys[2][KT][LDSW];
+
+  const int tid = threadIdx.x;
+  const int l = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  const int group = logical / ntiles;
+  const int tile = logical - group * ntiles;
+  int tm, tn;
+  if (d.sym) upper_tile(tile, tiles_n, tm, tn);
+  else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
+  const int m0 = tm * BM, n0 = tn * BM;
+
+  const int b_lo = group * d.fold;
+  const int b_hi = min(d.batch, b_lo + d.fold);
+  const int nkb = (d.K + KT - 1) / KT;
+  const int nstage = (b_hi - b_lo) * nkb;
+
+  const TX* __restrict__ X = (const TX*)d.X;
+  const TY* __restrict__ Y = (const TY*)d.Y;
+
+  acc_t acc[4][4];
+  d4v acc64[FLUSH64 ? 4 : 1][FLUSH64 ? 4 : 1];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  if (FLUSH64) {
+#pragma unroll
+    for (int i = 0; i < (FLUSH64 ? 4 : 1); ++i)
+#pragma unroll
+      for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) acc64[i][j] = d4v{0, 0, 0, 0};
+  }
+
+  TC xr[PER_T], yr[PER_T];
+
+  auto load = [&](int s) {
+    const int bb = b_lo + s / nkb;
+    const int k0 = (s % nkb) * KT;
+    const long long xb = (long long)bb * d.sx, yb = (long long)bb * d.sy;
+#pragma unroll
+    for (int j = 0; j < PER_T; ++j) {
+      const int e = tid + NTHR * j;
+      int kx, mx;
+      if (XK) { kx = e / BM; mx = e % BM; } else { mx = e / KT; kx = e % KT; }
+      const int gk = k0 + kx, gm = m0 + mx;
+      const bool kin = gk < d.K && (d.Ktot <= 0 || (long long)bb * d.K + gk < d.Ktot);
+      TC v = 0;
+      if (kin && gm < d.M)
+        v = XK ? (TC)X[xb + (long long)gk * d.ldx + gm] : (TC)X[xb + (long long)gm * d.ldx + gk];
+      xr[j] = v;
+      const int ky = e / BM, ny = e % BM;
+      const int gky = k0 + ky, gn = n0 + ny;
+      const bool kin_y = gky < d.K && (d.Ktot <= 0 || (long long)bb * d.K + gky < d.Ktot);
+      TC u = 0;
+      if (kin_y && gn < d.N) {
+        if (d.S) u = (TC)((double)Y[yb + (long long)gky * d.ldy + gn] * d.S[(long long)gky * d.lds + gn]);
+        else u = (TC)Y[yb + (long long)gky * d.ldy + gn];
+      }
+      yr[j] = u;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < PER_T; ++j) {
+      const int e = tid + NTHR * j;
+      int kx, mx;
+      if (XK) { kx = e / BM; mx = e % BM; } else { mx = e / KT; kx = e % KT; }
+      Xs[buf][kx][mx] = xr[j];
+      Ys[buf][e / BM][e % BM] = yr[j];
+    }
+  };
+
+  if (nstage > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstage) load(s + 1);
+#pragma unroll
+    for (int kk = 0; kk < KT / 4; ++kk) {
+      TC a[4], bv[4];
+      const int kr = kk * 4 + (l >> 4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Xs[buf][kr][wm * 64 + i * 16 + (l & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Ys[buf][kr][wn * 64 + j * 16 + (l & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(a[i], bv[j], acc[i][j]);
+    }
+    if (FLUSH64 && ((s + 1) % nkb == 0)) {
+      // end of one batch: fold the FP32 partial into FP64
+#pragma unroll
+      for (int i = 0; i < (FLUSH64 ? 4 : 1); ++i)
+#pragma unroll
+        for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = acc_t{0, 0, 0, 0};
+        }
+    }
+    if (s + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue
+  TO* __restrict__ Out = (TO*)d.Out;
+  const long long ob = (long long)(d.fold == 1 ? b_lo : group) * d.so;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 64 + i * 16 + MF::row(l, r);
+        const int gn = n0 + wn * 64 + j * 16 + (l & 15);
+        double v;
+        if (FLUSH64) v = acc64[FLUSH64 ? i : 0][FLUSH64 ? j : 0][r];
+        else v = (double)acc[i][j][r];
+        if (gm >= d.M || gn >= d.N) continue;
+        if (!d.sym) {
+          Out[ob + (long long)gm * d.ldo + gn] = (TO)v;
+        } else if (gm <= gn) {
+          Out[ob + (long long)gm * d.ldo + gn] = (TO)v;
+          Out[ob + (long long)gn * d.ldo + gm] = (TO)v;
+          if (gm == gn && d.Dg) d.Dg[(long long)b_lo * d.sd + gm] = v;
+        }
+      }
+}
+
+template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
+int launch(const GemmDesc& d, hipStream_t st) {
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int tiles_n = (d.N + BM - 1) / BM;
+  const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
+  const int ngroups = (d.batch + d.fold - 1) / d.fold;
+  const long long G = (long long)ntiles * ngroups;
+  if (G <= 0) return NOF_OK;
+  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  hipLaunchKernelGGL((k_gemm_tn<TC, TX, TY, TO, XK, FLUSH64>), dim3((unsigned)G), dim3(NTHR), 0, st,
+                     d, tiles_n, ntiles);
+  return launch_status();
+}
+
+}  // namespace
+
+int gemm_tn(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st) {
+  if (d.sym && d.M != d.N) return NOF_E_DIM;
+  if (d.fold < 1 || d.batch < 0) return NOF_E_DIM;
+  if (prec == NOF_P_F64) {
+    if (x_t != NOF_F64 || y_t != NOF_F64 || out_t != NOF_F64) return NOF_E_DTYPE;
+    return d.x_kmajor ? launch<double, double, double, double, true, false>(d, st)
+                      : launch<double, double, double, double, false, false>(d, st);
+  }
+  if (prec == NOF_P_F32) {
+    const bool flush = d.fold > 1;
+    if (!d.x_kmajor) return NOF_E_DTYPE;
+    if (x_t == NOF_F32 && y_t == NOF_F64 && out_t == NOF_F32 && !flush)
+      return launch<float, float, double, float, true, false>(d, st);
+    if (x_t == NOF_F64 && y_t == NOF_F32 && out_t == NOF_F32 && !flush)
+      return launch<float, double, float, float, true, false>(d, st);
+    if (x_t == NOF_F32 && y_t == NOF_F32 && out_t == NOF_F64)
+      return flush ? launch<float, float, float, double, true, true>(d, st)
+                   : launch<float, float, float, double, true, false>(d, st);
+    if (x_t == NOF_F32 && y_t == NOF_F32 && out_t == NOF_F32 && !flush)
+      return launch<float, float, float, float, true, false>(d, st);
+    return NOF_E_DTYPE;
+  }
+  return NOF_E_PREC;
+}
+
+}  // namespace nof

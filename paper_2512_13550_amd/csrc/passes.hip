@@ -1,0 +1,263 @@
+// Bandwidth-bound and small FP64 kernels of the JK / generalized-Fock build.
+#include "common.h"
+
+namespace nof {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Exchange and Coulomb-type pass over the unique half of b.
+//
+// Tile = 16 rows (r) x 64 columns (s) of the norb x norb plane; one workgroup
+// walks one tile through a contiguous chunk of auxiliary slabs P.  Thread
+// (ty, tx) owns column s = tile_col*64 + tx and rows r = tile_row*16 + 4*ty + i.
+// A wave reads 64 consecutive s of one row: 512-byte (FP64) or 256-byte (FP32)
+// coalesced segments.  W (naux x norb, FP64) is L2 resident.
+// ---------------------------------------------------------------------------
+constexpr int KF_R = 16, KF_C = 64, KF_THR = 256;
+
+__device__ __forceinline__ void kf_tile(int t, int ntc, int ntr, int& tr, int& tc) {
+  // tiles are listed column-block by column-block; column block tc holds the
+  // row blocks 0 .. min(ntr, (tc*64+63)/16 + 1) - 1 (those touching r <= s)
+  for (tc = 0; tc < ntc; ++tc) {
+    int cnt = (tc * KF_C + KF_C - 1) / KF_R + 1;
+    if (cnt > ntr) cnt = ntr;
+    if (t < cnt) { tr = t; return; }
+    t -= cnt;
+  }
+  tr = -1;
+}
+
+template <typename TB>
+__global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __restrict__ b,
+                                                const double* __restrict__ W,
+                                                double* __restrict__ Kpart,
+                                                double* __restrict__ F1part, int pchunk,
+                                                int ntiles, int ntr, int ntc) {
+  const int tile = blockIdx.x % ntiles;
+  const int chunk = blockIdx.x / ntiles;
+  int tr, tc;
+  kf_tile(tile, ntc, ntr, tr, tc);
+  if (tr < 0) return;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int s = tc * KF_C + tx;
+  const int r0 = tr * KF_R + ty * 4;
+  const int p_lo = chunk * pchunk;
+  const int p_hi = min(naux, p_lo + pchunk);
+  const long long plane = (long long)norb * norb;
+
+  bool act[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) act[i] = (s < norb) && (r0 + i < norb) && (r0 + i <= s);
+
+  double k[4] = {0, 0, 0, 0}, frs[4] = {0, 0, 0, 0}, fsr[4] = {0, 0, 0, 0};
+  const bool wantF = F1part != nullptr;
+  int P = p_lo;
+  for (; P + 1 < p_hi; P += 2) {
+    TB v0[4], v1[4];
+    const TB* b0 = b + (long long)P * plane;
+    const TB* b1 = b0 + plane;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v0[i] = act[i] ? b0[(long long)(r0 + i) * norb + s] : (TB)0;
+      v1[i] = act[i] ? b1[(long long)(r0 + i) * norb + s] : (TB)0;
+    }
+    double ws0 = 0, ws1 = 0, wr0[4], wr1[4];
+    if (wantF) {
+      ws0 = s < norb ? W[(long long)P * norb + s] : 0.0;
+      ws1 = s < norb ? W[(long long)(P + 1) * norb + s] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        wr0[i] = (r0 + i < norb) ? W[(long long)P * norb + r0 + i] : 0.0;
+        wr1[i] = (r0 + i < norb) ? W[(long long)(P + 1) * norb + r0 + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double a0 = (double)v0[i], a1 = (double)v1[i];
+      k[i] = fma(a0, a0, k[i]);
+      k[i] = fma(a1, a1, k[i]);
+      if (wantF) {
+        frs[i] = fma(a0, ws0, frs[i]);
+        frs[i] = fma(a1, ws1, frs[i]);
+        fsr[i] = fma(a0, wr0[i], fsr[i]);
+        fsr[i] = fma(a1, wr1[i], fsr[i]);
+      }
+    }
+  }
+  for (; P < p_hi; ++P) {
+    const TB* b0 = b + (long long)P * plane;
+    const double ws0 = (wantF && s < norb) ? W[(long long)P * norb + s] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double a0 = act[i] ? (double)b0[(long long)(r0 + i) * norb + s] : 0.0;
+      k[i] = fma(a0, a0, k[i]);
+      if (wantF) {
+        const double wr = (r0 + i < norb) ? W[(long long)P * norb + r0 + i] : 0.0;
+        frs[i] = fma(a0, ws0, frs[i]);
+        fsr[i] = fma(a0, wr, fsr[i]);
+      }
+    }
+  }
+  const long long cb = (long long)chunk * plane;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (!act[i]) continue;
+    const int r = r0 + i;
+    if (Kpart) Kpart[cb + (long long)r * norb + s] = k[i];
+    if (wantF) {
+      F1part[cb + (long long)r * norb + s] = frs[i];
+      if (r != s) F1part[cb + (long long)s * norb + r] = fsr[i];
+    }
+  }
+}
+
+__global__ void k_reduce(const double* __restrict__ part, int nparts, long long stride, int norb,
+                         int sym_upper, double* __restrict__ out) {
+  const long long n2 = (long long)norb * norb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    long long src = i;
+    if (sym_upper) {
+      const int r = (int)(i / norb), s = (int)(i - (long long)r * norb);
+      src = r <= s ? i : (long long)s * norb + r;
+    }
+    double a = 0.0;
+    for (int c = 0; c < nparts; ++c) a += part[(long long)c * stride + src];
+    out[i] = a;
+  }
+}
+
+__global__ void k_lambda(int norb, const double* __restrict__ n, const double* __restrict__ h,
+                         const double* __restrict__ F1, const double* __restrict__ F2,
+                         double* __restrict__ lam, double* __restrict__ grad) {
+  const long long n2 = (long long)norb * norb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / norb), s = (int)(i - (long long)r * norb);
+    const long long t = (long long)s * norb + r;
+    const double l_rs = n[s] * h[i] + F1[i] - F2[i];
+    lam[i] = l_rs;
+    if (grad) {
+      const double l_sr = n[r] * h[t] + F1[t] - F2[t];
+      grad[i] = 4.0 * (l_rs - l_sr);
+    }
+  }
+}
+
+constexpr int E_THR = 1024;
+__global__ __launch_bounds__(E_THR) void k_energy(int norb, const double* __restrict__ n,
+                                                  const double* __restrict__ h,
+                                                  const double* __restrict__ J,
+                                                  const double* __restrict__ K,
+                                                  const double* __restrict__ cJ,
+                                                  const double* __restrict__ cK,
+                                                  double* __restrict__ E) {
+  __shared__ double red[E_THR];
+  const long long n2 = (long long)norb * norb;
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < n2; i += E_THR) a += cJ[i] * J[i] - cK[i] * K[i];
+  for (int p = threadIdx.x; p < norb; p += E_THR) a += 2.0 * n[p] * h[(long long)p * norb + p];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = E_THR / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *E = red[0];
+}
+
+__global__ void k_coeffs(int norb, const double* __restrict__ n, const double* __restrict__ Delta,
+                         const double* __restrict__ Pi, double* __restrict__ cJ,
+                         double* __restrict__ cK) {
+  const long long n2 = (long long)norb * norb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(i / norb), q = (int)(i - (long long)p * norb);
+    const double nn = n[p] * n[q];
+    const double d = Delta ? Delta[i] : 0.0;
+    const double pi = Pi ? Pi[i] : 0.0;
+    cJ[i] = 2.0 * (nn - d);
+    cK[i] = nn - d - pi;
+  }
+}
+
+inline int grid_for(long long n, int thr) {
+  long long g = (n + thr - 1) / thr;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+void kf_geometry(int norb, int& ntr, int& ntc, int& ntiles) {
+  ntr = (norb + KF_R - 1) / KF_R;
+  ntc = (norb + KF_C - 1) / KF_C;
+  ntiles = 0;
+  for (int tc = 0; tc < ntc; ++tc) {
+    int cnt = (tc * KF_C + KF_C - 1) / KF_R + 1;
+    ntiles += cnt > ntr ? ntr : cnt;
+  }
+}
+
+}  // namespace
+
+int kf1_chunks(int naux, int norb) {
+  int ntr, ntc, ntiles;
+  kf_geometry(norb, ntr, ntc, ntiles);
+  int nc = (2048 + ntiles - 1) / ntiles;
+  if (nc > naux) nc = naux;
+  if (nc < 1) nc = 1;
+  return nc;
+}
+
+int kf1_pass(int naux, int norb, const void* b, int bt, const double* W, double* Kpart,
+             double* F1part, int nchunk, hipStream_t st) {
+  int ntr, ntc, ntiles;
+  kf_geometry(norb, ntr, ntc, ntiles);
+  const int pchunk = (naux + nchunk - 1) / nchunk;
+  const int nc = (naux + pchunk - 1) / pchunk;
+  if (nc > nchunk) return NOF_E_INTERNAL;
+  const long long G = (long long)ntiles * nchunk;
+  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  // chunks beyond nc (when pchunk rounding leaves them empty) write zeros
+  if (bt == NOF_F64)
+    hipLaunchKernelGGL(k_kf1<double>, dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
+                       (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+  else if (bt == NOF_F32)
+    hipLaunchKernelGGL(k_kf1<float>, dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
+                       (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+  else
+    return NOF_E_DTYPE;
+  return launch_status();
+}
+
+int reduce_parts(const double* part, int nparts, long long stride, int norb, bool sym_upper,
+                 double* out, hipStream_t st) {
+  const long long n2 = (long long)norb * norb;
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n2, 256)), dim3(256), 0, st, part, nparts, stride,
+                     norb, sym_upper ? 1 : 0, out);
+  return launch_status();
+}
+
+int lambda_grad(int norb, const double* n, const double* h, const double* F1, const double* F2,
+                double* lam, double* grad, hipStream_t st) {
+  const long long n2 = (long long)norb * norb;
+  hipLaunchKernelGGL(k_lambda, dim3(grid_for(n2, 256)), dim3(256), 0, st, norb, n, h, F1, F2, lam,
+                     grad);
+  return launch_status();
+}
+
+int energy(int norb, const double* n, const double* h, const double* J, const double* K,
+           const double* cJ, const double* cK, double* E, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(E_THR), 0, st, norb, n, h, J, K, cJ, cK, E);
+  return launch_status();
+}
+
+int coeffs_from_cumulant(int norb, const double* n, const double* Delta, const double* Pi,
+                         double* cJ, double* cK, hipStream_t st) {
+  const long long n2 = (long long)norb * norb;
+  hipLaunchKernelGGL(k_coeffs, dim3(grid_for(n2, 256)), dim3(256), 0, st, norb, n, Delta, Pi, cJ,
+                     cK);
+  return launch_status();
+}
+
+}  // namespace nof

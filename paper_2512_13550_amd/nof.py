@@ -1,0 +1,176 @@
+"""ctypes binding of libnof.so (the C ABI declared in include/nof.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors must be contiguous and live on the GPU; workspaces are
+allocated here as caller-owned device buffers and passed in.  The import fails
+loudly if the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnof.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_13550_amd.build`")
+lib = ctypes.CDLL(LIB_PATH)
+
+# status codes and enums (mirror include/nof.h)
+OK, E_NULL, E_DIM, E_DTYPE, E_PREC, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_ARG = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F64, F32, BF16 = 0, 1, 2
+P_F64, P_F32, P_BF16X1, P_BF16X3, P_BF16X6 = 0, 1, 2, 3, 4
+
+_vp, _i, _sz, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+
+
+def _sig(name, res, *args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("nof_status_str", ctypes.c_char_p, _i)
+_sig("nof_mo_transform_ws", _sz, _i, _i, _i, _i, _i, _i)
+_sig("nof_mo_transform", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
+_sig("nof_jk_diag_ws", _sz, _i, _i, _i)
+_sig("nof_jk_diag", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
+_sig("nof_gen_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp)
+_sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nof_coeffs_from_cumulant", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp)
+
+DECLARED = [
+    "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_jk_diag_ws", "nof_jk_diag",
+    "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
+]
+
+
+class NofError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib.nof_status_str(code).decode()} (status {code})")
+
+
+def check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise NofError(rc, where)
+
+
+_TDT = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_PREC_OF = {F64: P_F64, F32: P_F32}
+
+
+def _p(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _f64(t, name):
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    return _p(t)
+
+
+def stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
+    """b^P = C^T B^P C and D[P][p] = b^P_pp (nof_mo_transform)."""
+    naux, nbf, _ = B.shape
+    norb = C.shape[1]
+    bt = _TDT[B.dtype]
+    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    if b is None:
+        b = torch.empty((naux, norb, norb), dtype=B.dtype, device=B.device)
+    if D is None:
+        D = torch.empty((naux, norb), dtype=torch.float64, device=B.device)
+    need = lib.nof_mo_transform_ws(naux, nbf, norb, bt, bt, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, B.device)
+    check(lib.nof_mo_transform(naux, nbf, norb, _p(B), bt, _f64(C, "C"), _p(b), bt, _p(D), prec,
+                               _p(ws), ws.numel(), stream_handle(stream)), "nof_mo_transform")
+    return b, D
+
+
+def one_electron(H, C, stream=None):
+    """h = C^T H C through the same transform with naux = 1."""
+    b, _ = mo_transform(H.reshape(1, *H.shape), C, prec=P_F64, stream=stream)
+    return b[0]
+
+
+def jk_diag(b, D, want_J=True, want_K=True, J=None, K=None, ws=None, stream=None):
+    naux, norb, _ = b.shape
+    bt = _TDT[b.dtype]
+    dev = b.device
+    if want_J and J is None:
+        J = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    if want_K and K is None:
+        K = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    need = lib.nof_jk_diag_ws(naux, norb, bt)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    check(lib.nof_jk_diag(naux, norb, _p(b), bt, _f64(D, "D"), _p(J) if want_J else None,
+                          _p(K) if want_K else None, _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_jk_diag")
+    return (J if want_J else None), (K if want_K else None)
+
+
+def gen_fock(b, D, n, h, cJ, cK, want_grad=True, want_K=False, prec=None, out=None, ws=None,
+             stream=None):
+    """lambda, grad (and optionally K) of the generalized-Fock build (nof_gen_fock)."""
+    naux, norb, _ = b.shape
+    bt = _TDT[b.dtype]
+    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    dev = b.device
+    if out is None:
+        out = {}
+    lam = out.get("lam")
+    if lam is None:
+        lam = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    g = out.get("g") if want_grad else None
+    if want_grad and g is None:
+        g = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    K = out.get("K") if want_K else None
+    if want_K and K is None:
+        K = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    need = lib.nof_gen_fock_ws(naux, norb, bt, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    check(lib.nof_gen_fock(naux, norb, _p(b), bt, _f64(D, "D"), _f64(n, "n"), _f64(h, "h"),
+                           _f64(cJ, "cJ"), _f64(cK, "cK"), _p(lam), _p(g), _p(K), prec, _p(ws),
+                           ws.numel(), stream_handle(stream)), "nof_gen_fock")
+    return lam, g, K
+
+
+def energy(n, h, J, K, cJ, cK, E=None, stream=None):
+    norb = n.shape[0]
+    if E is None:
+        E = torch.empty((), dtype=torch.float64, device=n.device)
+    check(lib.nof_energy(norb, _f64(n, "n"), _f64(h, "h"), _f64(J, "J"), _f64(K, "K"),
+                         _f64(cJ, "cJ"), _f64(cK, "cK"), _p(E), stream_handle(stream)), "nof_energy")
+    return E
+
+
+def coeffs_from_cumulant(n, Delta, Pi, stream=None):
+    norb = n.shape[0]
+    cJ = torch.empty((norb, norb), dtype=torch.float64, device=n.device)
+    cK = torch.empty_like(cJ)
+    check(lib.nof_coeffs_from_cumulant(norb, _f64(n, "n"), _f64(Delta, "Delta"), _f64(Pi, "Pi"),
+                                       _p(cJ), _p(cK), stream_handle(stream)), "nof_coeffs_from_cumulant")
+    return cJ, cK

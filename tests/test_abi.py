@@ -1,0 +1,75 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    path = os.path.join(ROOT, "paper_2512_13550_amd", "libnof.so")
+    if not os.path.exists(path):
+        pytest.fail("libnof.so not built (run __graft_entry__.build())")
+    import paper_2512_13550_amd.nof as nof
+    return nof
+
+
+def declared_symbols():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(nof_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    nof = _lib()
+    syms = declared_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(nof.lib, s), s
+    assert set(nof.DECLARED) <= set(syms)
+
+
+FAKE = ctypes.c_void_p(4096)   # never dereferenced: validation fails before any launch
+
+
+def test_status_strings():
+    nof = _lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -99, 12345):
+        assert isinstance(nof.lib.nof_status_str(code), bytes)
+
+
+def test_transform_validation():
+    nof = _lib()
+    L = nof.lib
+    assert L.nof_mo_transform(0, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 0, FAKE, 1 << 20, None) == nof.E_DIM
+    assert L.nof_mo_transform(2, 4, 4, None, 0, FAKE, FAKE, 0, None, 0, FAKE, 1 << 20, None) == nof.E_NULL
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 1, None, 0, FAKE, 1 << 20, None) == nof.E_DTYPE
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 1, FAKE, 1 << 20, None) == nof.E_PREC
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 7, FAKE, 1 << 20, None) == nof.E_PREC
+    need = L.nof_mo_transform_ws(2, 4, 4, 0, 0, 0)
+    assert need >= 2 * 4 * 4 * 8
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 0, FAKE, need - 1, None) == nof.E_WORKSPACE
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 0, None, need, None) == nof.E_WORKSPACE
+
+
+def test_jk_and_fock_validation():
+    nof = _lib()
+    L = nof.lib
+    assert L.nof_jk_diag(-1, 4, FAKE, 0, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == nof.E_DIM
+    assert L.nof_jk_diag(3, 4, None, 0, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == nof.E_NULL
+    assert L.nof_jk_diag(3, 4, FAKE, 2, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == nof.E_DTYPE
+    assert L.nof_jk_diag(3, 4, FAKE, 0, FAKE, FAKE, FAKE, FAKE, 8, None) == nof.E_WORKSPACE
+    args = [FAKE] * 6   # D, n, h, cJ, cK, lambda
+    assert L.nof_gen_fock(3, 4, FAKE, 0, *args, None, None, 0, FAKE, 8, None) == nof.E_WORKSPACE
+    assert L.nof_gen_fock(3, 4, FAKE, 0, FAKE, FAKE, FAKE, FAKE, None, FAKE, None, None, 0, FAKE, 1 << 30, None) == nof.E_NULL
+    assert L.nof_gen_fock(3, 4, FAKE, 0, *args, None, None, 1, FAKE, 1 << 30, None) == nof.E_PREC
+    assert L.nof_energy(0, *([FAKE] * 7), None) == nof.E_DIM
+    assert L.nof_energy(4, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, None) == nof.E_NULL
+    assert L.nof_coeffs_from_cumulant(4, FAKE, None, FAKE, FAKE, FAKE, None) == nof.E_NULL
