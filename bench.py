@@ -1,0 +1,232 @@
+#!/usr/bin/env python
+"""Benchmark of one orbital-optimisation iteration of the density-fitted JK +
+generalized-Fock build on one MI355X.
+
+Workload (default "c500"): Nbf=500, Naux=2000, Norb=500, synthetic
+hydrogen-chain-shaped inputs (see paper_2512_13550_amd/inputs.py), 125
+strongly occupied orbitals each paired with three weak ones, ten iterations
+each preceded by a small random orthogonal rotation of C.
+
+One step = one iteration: C <- C exp(eps Y_i) (FP64 rotation on the GPU),
+b = C^T B C and D, h = C^T H C, J, and in one call lambda, g and K, then E.
+All inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  `value` is the algorithmic TFLOP/s of the FP64 path;
+`forms` holds the FP32 form on the same workload with its error against the
+FP64 GPU result; `roofline` describes the dominant kernel (the first stage of
+the orbital transformation) timed with HIP events on the launch stream;
+`cpu_baseline` is the FP64 CPU oracle timed on a bounded slab sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s (MI355X datasheet)
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_flops(nbf, naux, norb):
+    a1 = 2.0 * naux * nbf * nbf * norb                 # T^P = B^P C
+    a2 = 1.0 * naux * nbf * norb * (norb + 1)          # b^P = C^T T^P, symmetric half
+    a6 = 2.0 * naux * norb ** 3                        # exchange-type Fock contraction
+    small = 6.0 * naux * norb * norb                   # J, K, W, F1
+    return dict(a1=a1, a2=a2, a6=a6, small=small, total=a1 + a2 + a6 + small)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c500")
+    ap.add_argument("--forms", default="f32", help="comma list of extra forms: f32")
+    ap.add_argument("--cpu-slabs", type=int, default=160,
+                    help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2512_13550_amd.nof as nof
+    from paper_2512_13550_amd import inputs
+
+    w = inputs.WORKLOADS[args.workload]
+    nbf, naux, norb = w.nbf, w.naux, w.norb
+    t0 = time.time()
+    print(f"# generating {w.name}: nbf={nbf} naux={naux} norb={norb}", file=sys.stderr, flush=True)
+    B_h = inputs.make_B(w.seed, nbf, naux, w.decay, threads=16)
+    C0 = inputs.make_C(w.seed, nbf, norb)
+    H_h = inputs.make_H(w.seed, nbf)
+    n_h = inputs.make_occupations(w.seed, norb, w.nstrong)
+    total_iters = max(args.warmup + args.steps, w.iters)
+    Ys = [inputs.make_antisym(w.seed, it, norb) for it in range(total_iters)]
+    print(f"# inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    B64 = torch.from_numpy(B_h).to(dev)
+    H = torch.from_numpy(H_h).to(dev)
+    n = torch.from_numpy(n_h).to(dev)
+    Yd = [torch.from_numpy(Y).to(dev) for Y in Ys]
+    Z = torch.zeros((norb, norb), dtype=torch.float64, device=dev)
+    # HF-like reconstruction (Delta = Pi = 0): dense coefficient matrices
+    cJ, cK = nof.coeffs_from_cumulant(n, Z, Z)
+
+    flops = algorithmic_flops(nbf, naux, norb)
+
+    def run(B, prec_name, steps, warmup):
+        dt = torch.float64 if prec_name == "f64" else torch.float32
+        prec = nof.P_F64 if prec_name == "f64" else nof.P_F32
+        C = torch.from_numpy(C0).to(dev)
+        Cn = torch.empty_like(C)
+        T = torch.empty((naux, nbf, norb), dtype=dt, device=dev)
+        b = torch.empty((naux, norb, norb), dtype=dt, device=dev)
+        D = torch.empty((naux, norb), dtype=torch.float64, device=dev)
+        out = {"lam": torch.empty_like(Z), "g": torch.empty_like(Z), "K": torch.empty_like(Z)}
+        J = torch.empty_like(Z)
+        E = torch.empty((), dtype=torch.float64, device=dev)
+        rot = nof.Rotation(norb, nbf, dev)
+        ws_f = nof.workspace(nof.lib.nof_gen_fock_ws(naux, norb, nof._TDT[dt], prec), dev)
+        ws_j = nof.workspace(nof.lib.nof_jk_diag_ws(naux, norb, nof._TDT[dt]), dev)
+        Es = []
+        nev = 7
+        evs = []
+
+        def one(it, record):
+            nonlocal C, Cn
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(nev)] if record else None
+            if record: e[0].record()
+            rot.apply(C, Yd[it], Cn)                                  # A9: C <- C exp(eps Y)
+            C, Cn = Cn, C
+            if record: e[1].record()
+            nof.transform_stage1(B, C, T, prec=prec)                  # A1
+            if record: e[2].record()
+            nof.transform_stage2(T, C, b, D, prec=prec)               # A2
+            if record: e[3].record()
+            h = nof.one_electron(H, C)
+            nof.jk_diag(b, D, want_J=True, want_K=False, J=J, ws=ws_j)   # A3
+            if record: e[4].record()
+            nof.gen_fock(b, D, n, h, cJ, cK, want_grad=True, want_K=True, prec=prec,
+                         out=out, ws=ws_f)                            # A4-A7
+            if record: e[5].record()
+            nof.energy(n, h, J, out["K"], cJ, cK, E=E)                # A8
+            if record: e[6].record()
+            return e
+
+        for it in range(warmup):
+            one(it, False)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for k in range(steps):
+            evs.append(one(warmup + k, True))
+            Es.append(E.clone())
+        stop.record()
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        seg = np.array([[ev[i].elapsed_time(ev[i + 1]) for i in range(nev - 1)] for ev in evs])
+        res = dict(ms_per_step=total_ms / steps, seg_ms=seg.mean(axis=0).tolist(),
+                   E=[float(x) for x in Es], J=J.clone(), K=out["K"].clone(),
+                   lam=out["lam"].clone(), g=out["g"].clone())
+        del T, b
+        torch.cuda.empty_cache()
+        return res
+
+    print("# timing fp64", file=sys.stderr, flush=True)
+    r64 = run(B64, "f64", args.steps, args.warmup)
+    seg_names = ["rotate", "a1_transform_stage1", "a2_transform_stage2", "h_and_J",
+                 "fock_K_lambda_grad", "energy"]
+    ms = r64["ms_per_step"]
+    value = flops["total"] / (ms * 1e-3) / 1e12
+    a1_ms = r64["seg_ms"][1]
+    a1_tf = flops["a1"] / (a1_ms * 1e-3) / 1e12
+
+    forms = {}
+    for f in [x for x in args.forms.split(",") if x]:
+        if f == "f32":
+            print("# timing fp32", file=sys.stderr, flush=True)
+            B32 = B64.to(torch.float32)
+            r = run(B32, "f32", args.steps, args.warmup)
+            del B32
+            torch.cuda.empty_cache()
+            dE = max(abs(a - b_) for a, b_ in zip(r["E"], r64["E"]))
+            forms["f32"] = dict(
+                ms_per_step=r["ms_per_step"],
+                tflops=flops["total"] / (r["ms_per_step"] * 1e-3) / 1e12,
+                max_abs_dE_Eh=dE,
+                max_abs_dJ=float((r["J"] - r64["J"]).abs().max()),
+                max_abs_dK=float((r["K"] - r64["K"]).abs().max()),
+                max_abs_dlambda=float((r["lam"] - r64["lam"]).abs().max()),
+                stage_ms=dict(zip(seg_names, r["seg_ms"])),
+                meets_dE_1e6=bool(dE <= 1e-6),
+            )
+
+    cpu = None
+    if args.cpu_slabs > 0:
+        cpu = cpu_baseline(B_h, C0, H_h, n_h, w, args.cpu_slabs)
+
+    line = {
+        "metric": "JK+gen-Fock build ms/iter and TFLOP/s; BF16 vs FP64 on one GPU at |dE|<=1e-6 Eh",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: Nbf={nbf} Naux={naux} Norb={norb}, one orbital-optimisation "
+                               f"iteration (rotation + transform + J/K + gen-Fock + energy), "
+                               f"{w.nstrong} strong orbitals x {w.ng} weak partners",
+                   "nbf": nbf, "naux": naux, "norb": norb, "seed": w.seed},
+        "E_last": r64["E"][-1],
+        "algorithmic_flops_per_step": flops["total"],
+        "stage_ms": dict(zip(seg_names, r64["seg_ms"])),
+        "roofline": {"bound": "mfma", "kernel": "transform stage 1 (T^P = B^P C), FP64 MFMA",
+                     "achieved": a1_tf, "peak": PEAK["f64"], "unit": "TFLOP/s",
+                     "frac": a1_tf / PEAK["f64"], "traffic": None,
+                     "flops_per_launch": flops["a1"], "avg_launch_ms": a1_ms},
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(B_h, C0, H_h, n_h, w, slabs):
+    """The FP64 oracle, as it stands, on the first `slabs` auxiliary slabs."""
+    from oracle import dfjk
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    slabs = min(slabs, w.naux)
+    Bs = B_h[:slabs]
+    nn = np.outer(n_h, n_h)
+    cJ, cK = 2.0 * nn, nn
+    print(f"# cpu oracle sample: {slabs} slabs", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    dfjk.iteration(Bs, C0, H_h, n_h, cJ, cK)
+    dt = time.perf_counter() - t0
+    f = algorithmic_flops(w.nbf, slabs, w.norb)["total"]
+    return {"value": f / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{slabs} of {w.naux} auxiliary slabs of {w.name}, one iteration, "
+                      f"{dt:.2f} s; full-iteration estimate {dt * w.naux / slabs:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

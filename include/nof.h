@@ -99,6 +99,18 @@ int nof_mo_transform(int naux, int nbf, int norb,
                      void* b, int bt, double* D,
                      int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The two stages of nof_mo_transform as separate calls (same arguments and
+ * rules), for callers that keep the half-transformed tensor or time the stages:
+ *   stage 1:  T[P][mu][q] = (B^P C)_{mu q}        T: [naux][nbf][norb], storage Tt
+ *   stage 2:  b^P = C^T T^P, D[P][p] = b^P_pp     (exactly symmetric b)
+ * Tt must equal Bt (stage 1) and bt (stage 2). */
+int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt,
+                            const double* C, void* T, int Tt, int prec,
+                            hipStream_t stream);
+int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt,
+                            const double* C, void* b, int bt, double* D, int prec,
+                            hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Coulomb and exchange integrals in the NO basis (Eq. PNOF's J and K).
  *
@@ -161,6 +173,31 @@ int nof_energy(int norb, const double* n, const double* h,
 int nof_coeffs_from_cumulant(int norb, const double* n, const double* Delta,
                              const double* Pi, double* cJ, double* cK,
                              hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Orbital-rotation step, FP64 (NO Optimization: the NOs are updated by a
+ * unitary transformation U = exp(y) of an antisymmetric y; orbitals are the
+ * columns of C, so C <- C U; y comes from ADAM on the orbital gradient).
+ *
+ * nof_expm_antisym: U = exp(y), y [norb][norb] antisymmetric FP64.  Scaling
+ *   and squaring with a degree-12 Taylor polynomial; the scaling power is
+ *   chosen on the device (||y/2^s||_1 <= 1/4, s <= 16), so the call never
+ *   synchronises.  Accuracy is about 1e-15 for ||y||_1 <= 2^14.
+ * nof_rotate_orbitals: Cout = C U, C and Cout [nbf][norb] (must not alias),
+ *   U [norb][norb].
+ * nof_adam_step: element-wise ADAM (Kingma and Ba) on the gradient g:
+ *   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+ *   y = -lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),
+ *   t >= 1 is the step counter.  For antisymmetric g, y is exactly
+ *   antisymmetric.  m, v [norb][norb] are caller-owned state (zero at t = 1).
+ * ------------------------------------------------------------------------- */
+size_t nof_expm_antisym_ws(int norb);
+int nof_expm_antisym(int norb, const double* y, double* U, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout,
+                        hipStream_t stream);
+int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double lr,
+                  double beta1, double beta2, double eps, double* y, hipStream_t stream);
 
 #ifdef __cplusplus
 }

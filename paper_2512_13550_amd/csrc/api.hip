@@ -107,6 +107,48 @@ size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec
   return align256((size_t)naux * nbf * norb * dtype_size(bt));
 }
 
+int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, const double* C,
+                            void* T, int Tt, int prec, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!B || !C || !T) return NOF_E_NULL;
+    if (Bt != Tt || dtype_size(Bt) == 0 || Bt == NOF_BF16) return NOF_E_DTYPE;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (!prec_matches(prec, Bt)) return NOF_E_PREC;
+    // T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
+    GemmDesc g1{};
+    g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
+    g1.batch = naux; g1.fold = 1;
+    g1.X = B; g1.ldx = nbf; g1.sx = (long long)nbf * nbf; g1.x_kmajor = true;
+    g1.Y = C; g1.ldy = norb; g1.sy = 0;
+    g1.S = nullptr; g1.lds = 0;
+    g1.Out = T; g1.ldo = norb; g1.so = (long long)nbf * norb;
+    g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
+    return gemm_tn(g1, Bt, NOF_F64, Tt, prec, stream);
+  });
+}
+
+int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, const double* C,
+                            void* b, int bt, double* D, int prec, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!T || !C || !b) return NOF_E_NULL;
+    if (Tt != bt || dtype_size(bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    // b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
+    GemmDesc g2{};
+    g2.M = norb; g2.N = norb; g2.K = nbf; g2.Ktot = 0;
+    g2.batch = naux; g2.fold = 1;
+    g2.X = C; g2.ldx = norb; g2.sx = 0; g2.x_kmajor = true;
+    g2.Y = T; g2.ldy = norb; g2.sy = (long long)nbf * norb;
+    g2.S = nullptr; g2.lds = 0;
+    g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
+    g2.Dg = D; g2.sd = norb; g2.sym = true;
+    return gemm_tn(g2, NOF_F64, Tt, bt, prec, stream);
+  });
+}
+
 int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const double* C, void* b,
                      int bt, double* D, int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
   return guarded([&]() -> int {
@@ -117,26 +159,8 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     const size_t need = nof_mo_transform_ws(naux, nbf, norb, Bt, bt, prec);
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
-    // Stage 1: T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
-    GemmDesc g1{};
-    g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
-    g1.batch = naux; g1.fold = 1;
-    g1.X = B; g1.ldx = nbf; g1.sx = (long long)nbf * nbf; g1.x_kmajor = true;
-    g1.Y = C; g1.ldy = norb; g1.sy = 0;
-    g1.S = nullptr; g1.lds = 0;
-    g1.Out = ws; g1.ldo = norb; g1.so = (long long)nbf * norb;
-    g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
-    NOF_TRY(gemm_tn(g1, bt, NOF_F64, bt, prec, stream));
-    // Stage 2: b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
-    GemmDesc g2{};
-    g2.M = norb; g2.N = norb; g2.K = nbf; g2.Ktot = 0;
-    g2.batch = naux; g2.fold = 1;
-    g2.X = C; g2.ldx = norb; g2.sx = 0; g2.x_kmajor = true;
-    g2.Y = ws; g2.ldy = norb; g2.sy = (long long)nbf * norb;
-    g2.S = nullptr; g2.lds = 0;
-    g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
-    g2.Dg = D; g2.sd = norb; g2.sym = true;
-    return gemm_tn(g2, NOF_F64, bt, bt, prec, stream);
+    NOF_TRY(nof_mo_transform_stage1(naux, nbf, norb, B, Bt, C, ws, bt, prec, stream));
+    return nof_mo_transform_stage2(naux, nbf, norb, ws, bt, C, b, bt, D, prec, stream);
   });
 }
 
@@ -247,6 +271,50 @@ int nof_coeffs_from_cumulant(int norb, const double* n, const double* Delta, con
     if (!dim_ok(norb)) return NOF_E_DIM;
     if (!n || !Delta || !Pi || !cJ || !cK) return NOF_E_NULL;
     return coeffs_from_cumulant(norb, n, Delta, Pi, cJ, cK, stream);
+  });
+}
+
+size_t nof_expm_antisym_ws(int norb) {
+  if (!dim_ok(norb)) return 0;
+  return expm_ws(norb);
+}
+
+int nof_expm_antisym(int norb, const double* y, double* U, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb)) return NOF_E_DIM;
+    if (!y || !U) return NOF_E_NULL;
+    if (!ws || ws_bytes < expm_ws(norb)) return NOF_E_WORKSPACE;
+    return expm_antisym(norb, y, U, ws, stream);
+  });
+}
+
+int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout,
+                        hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!C || !U || !Cout) return NOF_E_NULL;
+    if (C == Cout) return NOF_E_ARG;
+    // Cout[mu][p] = sum_q C[mu][q] U[q][p]: X(k=q, m=mu) = C[mu][q]
+    GemmDesc g{};
+    g.M = nbf; g.N = norb; g.K = norb; g.Ktot = 0;
+    g.batch = 1; g.fold = 1;
+    g.X = C; g.ldx = norb; g.sx = 0; g.x_kmajor = false;
+    g.Y = U; g.ldy = norb; g.sy = 0;
+    g.Out = Cout; g.ldo = norb; g.so = 0;
+    return gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream);
+  });
+}
+
+int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
+                  double beta2, double eps, double* y, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb)) return NOF_E_DIM;
+    if (!g || !m || !v || !y) return NOF_E_NULL;
+    if (t < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+        !(eps >= 0.0))
+      return NOF_E_ARG;
+    return adam_step(norb, g, m, v, t, lr, beta1, beta2, eps, y, stream);
   });
 }
 

@@ -56,6 +56,7 @@ struct GemmDesc {
   void* Out; long long ldo, so;
   double* Dg; long long sd;
   bool sym;
+  const int* pred; int pred_gt;   // if pred: run only when *pred > pred_gt (else write nothing)
 };
 
 // Element types: 0 = f64, 1 = f32.  prec: NOF_P_F64 or NOF_P_F32.
@@ -82,6 +83,12 @@ int lambda_grad(int norb, const double* n, const double* h, const double* F1,
 int energy(int norb, const double* n, const double* h, const double* J,
            const double* K, const double* cJ, const double* cK, double* E,
            hipStream_t st);
+
+// FP64 orbital-rotation helpers (rotation.hip).
+size_t expm_ws(int norb);
+int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st);
+int adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
+              double beta2, double eps, double* y, hipStream_t st);
 
 int coeffs_from_cumulant(int norb, const double* n, const double* Delta,
                          const double* Pi, double* cJ, double* cK, hipStream_t st);

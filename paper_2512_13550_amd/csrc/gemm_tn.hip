@@ -65,6 +65,7 @@ __global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, in
   __shared__ TC Xs[2][KT][LDSW];
   __shared__ TC Ys[2][KT][LDSW];
 
+  if (d.pred && *d.pred <= d.pred_gt) return;
   const int tid = threadIdx.x;
   const int l = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;

@@ -36,16 +36,24 @@ def _sig(name, res, *args):
 _sig("nof_status_str", ctypes.c_char_p, _i)
 _sig("nof_mo_transform_ws", _sz, _i, _i, _i, _i, _i, _i)
 _sig("nof_mo_transform", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
+_sig("nof_mo_transform_stage1", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp)
+_sig("nof_mo_transform_stage2", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp)
 _sig("nof_jk_diag_ws", _sz, _i, _i, _i)
 _sig("nof_jk_diag", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_gen_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp)
 _sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_coeffs_from_cumulant", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nof_expm_antisym_ws", _sz, _i)
+_sig("nof_expm_antisym", _i, _i, _vp, _vp, _vp, _sz, _vp)
+_sig("nof_rotate_orbitals", _i, _i, _i, _vp, _vp, _vp, _vp)
+_sig("nof_adam_step", _i, _i, _vp, _vp, _vp, _i, _d, _d, _d, _d, _vp, _vp)
 
 DECLARED = [
-    "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_jk_diag_ws", "nof_jk_diag",
+    "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
+    "nof_mo_transform_stage2", "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
+    "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals", "nof_adam_step",
 ]
 
 
@@ -105,6 +113,27 @@ def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
         ws = workspace(need, B.device)
     check(lib.nof_mo_transform(naux, nbf, norb, _p(B), bt, _f64(C, "C"), _p(b), bt, _p(D), prec,
                                _p(ws), ws.numel(), stream_handle(stream)), "nof_mo_transform")
+    return b, D
+
+
+def transform_stage1(B, C, T, prec=None, stream=None):
+    """T^P = B^P C (first half of nof_mo_transform) into caller-owned T."""
+    naux, nbf, _ = B.shape
+    norb = C.shape[1]
+    bt = _TDT[B.dtype]
+    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    check(lib.nof_mo_transform_stage1(naux, nbf, norb, _p(B), bt, _f64(C, "C"), _p(T), _TDT[T.dtype],
+                                      prec, stream_handle(stream)), "nof_mo_transform_stage1")
+    return T
+
+
+def transform_stage2(T, C, b, D, prec=None, stream=None):
+    """b^P = C^T T^P and D (second half of nof_mo_transform)."""
+    naux, nbf, norb = T.shape
+    bt = _TDT[b.dtype]
+    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    check(lib.nof_mo_transform_stage2(naux, nbf, norb, _p(T), _TDT[T.dtype], _f64(C, "C"), _p(b), bt,
+                                      _p(D), prec, stream_handle(stream)), "nof_mo_transform_stage2")
     return b, D
 
 
@@ -174,3 +203,48 @@ def coeffs_from_cumulant(n, Delta, Pi, stream=None):
     check(lib.nof_coeffs_from_cumulant(norb, _f64(n, "n"), _f64(Delta, "Delta"), _f64(Pi, "Pi"),
                                        _p(cJ), _p(cK), stream_handle(stream)), "nof_coeffs_from_cumulant")
     return cJ, cK
+
+
+def expm_antisym(y, U=None, ws=None, stream=None):
+    """U = exp(y) for antisymmetric y (nof_expm_antisym)."""
+    norb = y.shape[0]
+    if U is None:
+        U = torch.empty_like(y)
+    need = lib.nof_expm_antisym_ws(norb)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, y.device)
+    check(lib.nof_expm_antisym(norb, _f64(y, "y"), _p(U), _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_expm_antisym")
+    return U
+
+
+def rotate_orbitals(C, U, Cout=None, stream=None):
+    """Cout = C U (nof_rotate_orbitals)."""
+    nbf, norb = C.shape
+    if Cout is None:
+        Cout = torch.empty_like(C)
+    check(lib.nof_rotate_orbitals(nbf, norb, _f64(C, "C"), _f64(U, "U"), _p(Cout),
+                                  stream_handle(stream)), "nof_rotate_orbitals")
+    return Cout
+
+
+def adam_step(g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, y=None, stream=None):
+    """One ADAM step on the orbital gradient; returns the rotation generator y."""
+    norb = g.shape[0]
+    if y is None:
+        y = torch.empty_like(g)
+    check(lib.nof_adam_step(norb, _f64(g, "g"), _f64(m, "m"), _f64(v, "v"), int(t), lr, beta1, beta2,
+                            eps, _p(y), stream_handle(stream)), "nof_adam_step")
+    return y
+
+
+class Rotation:
+    """Preallocated FP64 rotation step C <- C exp(y) (workspace reused)."""
+
+    def __init__(self, norb, nbf, device):
+        self.U = torch.empty((norb, norb), dtype=torch.float64, device=device)
+        self.ws = workspace(lib.nof_expm_antisym_ws(norb), device)
+
+    def apply(self, C, y, Cout, stream=None):
+        expm_antisym(y, self.U, self.ws, stream)
+        return rotate_orbitals(C, self.U, Cout, stream)
