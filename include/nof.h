@@ -181,10 +181,10 @@ int nof_coeffs_from_cumulant(int norb, const double* n, const double* Delta,
  *
  * nof_expm_antisym: U = exp(y), y [norb][norb] antisymmetric FP64.  Scaling
  *   and squaring with a degree-12 Taylor polynomial; the scaling power is
- *   chosen on the device (||y/2^s||_1 <= 1/4, s <= 16), so the call never
- *   synchronises.  Accuracy is about 1e-15 for ||y||_1 <= 2^14.
+ *   chosen on the device (||y/2^s||_F <= 1/4, s <= 16), so the call never
+ *   synchronises.  Accuracy is about 1e-15 for ||y||_F <= 2^14.
  * nof_rotate_orbitals: Cout = C U, C and Cout [nbf][norb] (must not alias),
- *   U [norb][norb].
+ *   U [norb][norb]; ws of nof_rotate_orbitals_ws() bytes.
  * nof_adam_step: element-wise ADAM (Kingma and Ba) on the gradient g:
  *   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
  *   y = -lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),
@@ -194,8 +194,9 @@ int nof_coeffs_from_cumulant(int norb, const double* n, const double* Delta,
 size_t nof_expm_antisym_ws(int norb);
 int nof_expm_antisym(int norb, const double* y, double* U, void* ws, size_t ws_bytes,
                      hipStream_t stream);
+size_t nof_rotate_orbitals_ws(int nbf, int norb);
 int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout,
-                        hipStream_t stream);
+                        void* ws, size_t ws_bytes, hipStream_t stream);
 int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double lr,
                   double beta1, double beta2, double eps, double* y, hipStream_t stream);
 

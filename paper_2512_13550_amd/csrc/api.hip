@@ -289,20 +289,19 @@ int nof_expm_antisym(int norb, const double* y, double* U, void* ws, size_t ws_b
   });
 }
 
+size_t nof_rotate_orbitals_ws(int nbf, int norb) {
+  if (!dim_ok(nbf) || !dim_ok(norb)) return 0;
+  return rotate_ws(nbf, norb);
+}
+
 int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout,
-                        hipStream_t stream) {
+                        void* ws, size_t ws_bytes, hipStream_t stream) {
   return guarded([&]() -> int {
     if (!dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!C || !U || !Cout) return NOF_E_NULL;
     if (C == Cout) return NOF_E_ARG;
-    // Cout[mu][p] = sum_q C[mu][q] U[q][p]: X(k=q, m=mu) = C[mu][q]
-    GemmDesc g{};
-    g.M = nbf; g.N = norb; g.K = norb; g.Ktot = 0;
-    g.batch = 1; g.fold = 1;
-    g.X = C; g.ldx = norb; g.sx = 0; g.x_kmajor = false;
-    g.Y = U; g.ldy = norb; g.sy = 0;
-    g.Out = Cout; g.ldo = norb; g.so = 0;
-    return gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream);
+    if (!ws || ws_bytes < rotate_ws(nbf, norb)) return NOF_E_WORKSPACE;
+    return rotate_orbitals(nbf, norb, C, U, Cout, ws, stream);
   });
 }
 

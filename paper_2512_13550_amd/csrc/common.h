@@ -86,6 +86,9 @@ int energy(int norb, const double* n, const double* h, const double* J,
 
 // FP64 orbital-rotation helpers (rotation.hip).
 size_t expm_ws(int norb);
+size_t rotate_ws(int nbf, int norb);
+int rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout, void* ws,
+                    hipStream_t st);
 int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st);
 int adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
               double beta2, double eps, double* y, hipStream_t st);

@@ -58,7 +58,7 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& tm, int& tn) {
   tn = row + t;
 }
 
-template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
+template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64, bool HAS_S>
 __global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, int ntiles) {
   typedef Mfma<TC> MF;
   typedef typename MF::acc_t acc_t;
@@ -85,6 +85,17 @@ __global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, in
 
   const TX* __restrict__ X = (const TX*)d.X;
   const TY* __restrict__ Y = (const TY*)d.Y;
+  const double* __restrict__ S = d.S;
+
+  // Stage-invariant part of this thread's load pattern.  Element j of a
+  // k-major operand tile is (k = k_t + 2j, col = c_t): a wave covers 64
+  // consecutive columns of one row.  For an m-major X, element j is
+  // (k = tid % 16, m = tid / 16 + 16 j).
+  const int c_t = tid & (BM - 1);
+  const int k_t = tid >> 7;
+  const bool xm_ok = XK ? (m0 + c_t < d.M) : true;
+  const bool yn_ok = n0 + c_t < d.N;
+  const int xk_t = tid & (KT - 1), xm_t = tid >> 4;
 
   acc_t acc[4][4];
   d4v acc64[FLUSH64 ? 4 : 1][FLUSH64 ? 4 : 1];
@@ -99,42 +110,46 @@ __global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, in
       for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) acc64[i][j] = d4v{0, 0, 0, 0};
   }
 
-  TC xr[PER_T], yr[PER_T];
+  TX xr[PER_T];
+  TY yr[PER_T];
+  double sr[HAS_S ? PER_T : 1];
 
   auto load = [&](int s) {
     const int bb = b_lo + s / nkb;
-    const int k0 = (s % nkb) * KT;
-    const long long xb = (long long)bb * d.sx, yb = (long long)bb * d.sy;
+    const int k0 = (s - (bb - b_lo) * nkb) * KT;
+    int klim = d.K - k0;                                   // rows of this stage that exist
+    if (d.Ktot > 0) {
+      const long long r = d.Ktot - (long long)bb * d.K - k0;
+      if (r < klim) klim = (int)(r < 0 ? 0 : r);
+    }
+    if (XK) {
+      const TX* px = X + (long long)bb * d.sx + (long long)(k0 + k_t) * d.ldx + (m0 + c_t);
+#pragma unroll
+      for (int j = 0; j < PER_T; ++j)
+        xr[j] = (xm_ok && k_t + 2 * j < klim) ? px[(long long)(2 * j) * d.ldx] : (TX)0;
+    } else {
+      const TX* px = X + (long long)bb * d.sx + (long long)(m0 + xm_t) * d.ldx + (k0 + xk_t);
+      const bool kin = xk_t < klim;
+#pragma unroll
+      for (int j = 0; j < PER_T; ++j)
+        xr[j] = (kin && m0 + xm_t + 16 * j < d.M) ? px[(long long)(16 * j) * d.ldx] : (TX)0;
+    }
+    const long long yoff = (long long)(k0 + k_t) * d.ldy + (n0 + c_t);
+    const TY* py = Y + (long long)bb * d.sy + yoff;
 #pragma unroll
     for (int j = 0; j < PER_T; ++j) {
-      const int e = tid + NTHR * j;
-      int kx, mx;
-      if (XK) { kx = e / BM; mx = e % BM; } else { mx = e / KT; kx = e % KT; }
-      const int gk = k0 + kx, gm = m0 + mx;
-      const bool kin = gk < d.K && (d.Ktot <= 0 || (long long)bb * d.K + gk < d.Ktot);
-      TC v = 0;
-      if (kin && gm < d.M)
-        v = XK ? (TC)X[xb + (long long)gk * d.ldx + gm] : (TC)X[xb + (long long)gm * d.ldx + gk];
-      xr[j] = v;
-      const int ky = e / BM, ny = e % BM;
-      const int gky = k0 + ky, gn = n0 + ny;
-      const bool kin_y = gky < d.K && (d.Ktot <= 0 || (long long)bb * d.K + gky < d.Ktot);
-      TC u = 0;
-      if (kin_y && gn < d.N) {
-        if (d.S) u = (TC)((double)Y[yb + (long long)gky * d.ldy + gn] * d.S[(long long)gky * d.lds + gn]);
-        else u = (TC)Y[yb + (long long)gky * d.ldy + gn];
-      }
-      yr[j] = u;
+      const bool ok = yn_ok && k_t + 2 * j < klim;
+      yr[j] = ok ? py[(long long)(2 * j) * d.ldy] : (TY)0;
+      if (HAS_S) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + k_t + 2 * j) * d.lds + (n0 + c_t)] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < PER_T; ++j) {
-      const int e = tid + NTHR * j;
-      int kx, mx;
-      if (XK) { kx = e / BM; mx = e % BM; } else { mx = e / KT; kx = e % KT; }
-      Xs[buf][kx][mx] = xr[j];
-      Ys[buf][e / BM][e % BM] = yr[j];
+      if (XK) Xs[buf][k_t + 2 * j][c_t] = (TC)xr[j];
+      else Xs[buf][xk_t][xm_t + 16 * j] = (TC)xr[j];
+      if (HAS_S) Ys[buf][k_t + 2 * j][c_t] = (TC)((double)yr[j] * sr[HAS_S ? j : 0]);
+      else Ys[buf][k_t + 2 * j][c_t] = (TC)yr[j];
     }
   };
 
@@ -201,6 +216,7 @@ __global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, in
 
 template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
 int launch(const GemmDesc& d, hipStream_t st) {
+  if (!XK && PER_T * 16 > BM) return NOF_E_INTERNAL;
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tiles_n = (d.N + BM - 1) / BM;
   const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
@@ -208,8 +224,12 @@ int launch(const GemmDesc& d, hipStream_t st) {
   const long long G = (long long)ntiles * ngroups;
   if (G <= 0) return NOF_OK;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
-  hipLaunchKernelGGL((k_gemm_tn<TC, TX, TY, TO, XK, FLUSH64>), dim3((unsigned)G), dim3(NTHR), 0, st,
-                     d, tiles_n, ntiles);
+  if (d.S)
+    hipLaunchKernelGGL((k_gemm_tn<TC, TX, TY, TO, XK, FLUSH64, true>), dim3((unsigned)G), dim3(NTHR),
+                       0, st, d, tiles_n, ntiles);
+  else
+    hipLaunchKernelGGL((k_gemm_tn<TC, TX, TY, TO, XK, FLUSH64, false>), dim3((unsigned)G), dim3(NTHR),
+                       0, st, d, tiles_n, ntiles);
   return launch_status();
 }
 

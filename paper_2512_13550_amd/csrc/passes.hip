@@ -7,17 +7,18 @@ namespace {
 // ---------------------------------------------------------------------------
 // Exchange and Coulomb-type pass over the unique half of b.
 //
-// Tile = 16 rows (r) x 64 columns (s) of the norb x norb plane; one workgroup
-// walks one tile through a contiguous chunk of auxiliary slabs P.  Thread
-// (ty, tx) owns column s = tile_col*64 + tx and rows r = tile_row*16 + 4*ty + i.
-// A wave reads 64 consecutive s of one row: 512-byte (FP64) or 256-byte (FP32)
-// coalesced segments.  W (naux x norb, FP64) is L2 resident.
+// Tile = 16 rows (r) x 128 columns (s) of the norb x norb plane; one
+// workgroup walks one tile through a contiguous chunk of auxiliary slabs P.
+// Thread (ty, tx) owns columns s = tile_col*128 + 2*tx + {0,1} and rows
+// r = tile_row*16 + 4*ty + {0..3}; each row is fetched as one 2-element vector
+// (16 B in FP64), so a wave reads 1 KiB contiguous per row and slab.  Four
+// slabs are in flight per iteration.  W (naux x norb, FP64) is L2 resident.
 // ---------------------------------------------------------------------------
-constexpr int KF_R = 16, KF_C = 64, KF_THR = 256;
+constexpr int KF_R = 16, KF_C = 128, KF_THR = 256, KF_U = 4;
 
 __device__ __forceinline__ void kf_tile(int t, int ntc, int ntr, int& tr, int& tc) {
   // tiles are listed column-block by column-block; column block tc holds the
-  // row blocks 0 .. min(ntr, (tc*64+63)/16 + 1) - 1 (those touching r <= s)
+  // row blocks 0 .. min(ntr, (tc*128+127)/16 + 1) - 1 (those touching r <= s)
   for (tc = 0; tc < ntc; ++tc) {
     int cnt = (tc * KF_C + KF_C - 1) / KF_R + 1;
     if (cnt > ntr) cnt = ntr;
@@ -27,88 +28,107 @@ __device__ __forceinline__ void kf_tile(int t, int ntc, int ntr, int& tr, int& t
   tr = -1;
 }
 
-template <typename TB>
+template <typename TB> struct Vec2;
+template <> struct Vec2<double> { typedef double2 t; };
+template <> struct Vec2<float> { typedef float2 t; };
+
+// VEC: norb even, so every row segment starting at an even column is aligned.
+template <typename TB, bool VEC>
 __global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __restrict__ b,
                                                 const double* __restrict__ W,
                                                 double* __restrict__ Kpart,
                                                 double* __restrict__ F1part, int pchunk,
                                                 int ntiles, int ntr, int ntc) {
+  typedef typename Vec2<TB>::t V2;
   const int tile = blockIdx.x % ntiles;
   const int chunk = blockIdx.x / ntiles;
   int tr, tc;
   kf_tile(tile, ntc, ntr, tr, tc);
   if (tr < 0) return;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int s = tc * KF_C + tx;
+  const int s0 = tc * KF_C + 2 * tx;
   const int r0 = tr * KF_R + ty * 4;
   const int p_lo = chunk * pchunk;
   const int p_hi = min(naux, p_lo + pchunk);
   const long long plane = (long long)norb * norb;
-
-  bool act[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) act[i] = (s < norb) && (r0 + i < norb) && (r0 + i <= s);
-
-  double k[4] = {0, 0, 0, 0}, frs[4] = {0, 0, 0, 0}, fsr[4] = {0, 0, 0, 0};
   const bool wantF = F1part != nullptr;
-  int P = p_lo;
-  for (; P + 1 < p_hi; P += 2) {
-    TB v0[4], v1[4];
-    const TB* b0 = b + (long long)P * plane;
-    const TB* b1 = b0 + plane;
+
+  bool act[4][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v0[i] = act[i] ? b0[(long long)(r0 + i) * norb + s] : (TB)0;
-      v1[i] = act[i] ? b1[(long long)(r0 + i) * norb + s] : (TB)0;
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      act[i][c] = (s0 + c < norb) && (r0 + i < norb) && (r0 + i <= s0 + c);
+  bool rowany[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) rowany[i] = act[i][0] || act[i][1];
+
+  double k[4][2] = {}, frs[4][2] = {}, fsr[4][2] = {};
+
+  auto fetch = [&](int P, int i, TB& v0, TB& v1) {
+    const TB* row = b + (long long)P * plane + (long long)(r0 + i) * norb + s0;
+    if (VEC) {
+      V2 v = rowany[i] ? *(const V2*)row : V2{0, 0};
+      v0 = act[i][0] ? v.x : (TB)0;
+      v1 = act[i][1] ? v.y : (TB)0;
+    } else {
+      v0 = act[i][0] ? row[0] : (TB)0;
+      v1 = act[i][1] ? row[1] : (TB)0;
     }
-    double ws0 = 0, ws1 = 0, wr0[4], wr1[4];
+  };
+  auto accum = [&](int P, const TB (&v)[4][2]) {
+    double ws0 = 0.0, ws1 = 0.0, wr[4] = {0, 0, 0, 0};
     if (wantF) {
-      ws0 = s < norb ? W[(long long)P * norb + s] : 0.0;
-      ws1 = s < norb ? W[(long long)(P + 1) * norb + s] : 0.0;
+      const double* wp = W + (long long)P * norb;
+      ws0 = s0 < norb ? wp[s0] : 0.0;
+      ws1 = s0 + 1 < norb ? wp[s0 + 1] : 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        wr0[i] = (r0 + i < norb) ? W[(long long)P * norb + r0 + i] : 0.0;
-        wr1[i] = (r0 + i < norb) ? W[(long long)(P + 1) * norb + r0 + i] : 0.0;
-      }
+      for (int i = 0; i < 4; ++i) wr[i] = (r0 + i < norb) ? wp[r0 + i] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double a0 = (double)v0[i], a1 = (double)v1[i];
-      k[i] = fma(a0, a0, k[i]);
-      k[i] = fma(a1, a1, k[i]);
+      const double a0 = (double)v[i][0], a1 = (double)v[i][1];
+      k[i][0] = fma(a0, a0, k[i][0]);
+      k[i][1] = fma(a1, a1, k[i][1]);
       if (wantF) {
-        frs[i] = fma(a0, ws0, frs[i]);
-        frs[i] = fma(a1, ws1, frs[i]);
-        fsr[i] = fma(a0, wr0[i], fsr[i]);
-        fsr[i] = fma(a1, wr1[i], fsr[i]);
+        frs[i][0] = fma(a0, ws0, frs[i][0]);
+        frs[i][1] = fma(a1, ws1, frs[i][1]);
+        fsr[i][0] = fma(a0, wr[i], fsr[i][0]);
+        fsr[i][1] = fma(a1, wr[i], fsr[i][1]);
       }
     }
+  };
+
+  int P = p_lo;
+  for (; P + KF_U <= p_hi; P += KF_U) {
+    TB v[KF_U][4][2];
+#pragma unroll
+    for (int u = 0; u < KF_U; ++u)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fetch(P + u, i, v[u][i][0], v[u][i][1]);
+#pragma unroll
+    for (int u = 0; u < KF_U; ++u) accum(P + u, v[u]);
   }
   for (; P < p_hi; ++P) {
-    const TB* b0 = b + (long long)P * plane;
-    const double ws0 = (wantF && s < norb) ? W[(long long)P * norb + s] : 0.0;
+    TB v[4][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double a0 = act[i] ? (double)b0[(long long)(r0 + i) * norb + s] : 0.0;
-      k[i] = fma(a0, a0, k[i]);
-      if (wantF) {
-        const double wr = (r0 + i < norb) ? W[(long long)P * norb + r0 + i] : 0.0;
-        frs[i] = fma(a0, ws0, frs[i]);
-        fsr[i] = fma(a0, wr, fsr[i]);
-      }
-    }
+    for (int i = 0; i < 4; ++i) fetch(P, i, v[i][0], v[i][1]);
+    accum(P, v);
   }
+
   const long long cb = (long long)chunk * plane;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (!act[i]) continue;
-    const int r = r0 + i;
-    if (Kpart) Kpart[cb + (long long)r * norb + s] = k[i];
-    if (wantF) {
-      F1part[cb + (long long)r * norb + s] = frs[i];
-      if (r != s) F1part[cb + (long long)s * norb + r] = fsr[i];
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (!act[i][c]) continue;
+      const int r = r0 + i, s = s0 + c;
+      if (Kpart) Kpart[cb + (long long)r * norb + s] = k[i][c];
+      if (wantF) {
+        F1part[cb + (long long)r * norb + s] = frs[i][c];
+        if (r != s) F1part[cb + (long long)s * norb + r] = fsr[i][c];
+      }
     }
-  }
 }
 
 __global__ void k_reduce(const double* __restrict__ part, int nparts, long long stride, int norb,
@@ -219,14 +239,24 @@ int kf1_pass(int naux, int norb, const void* b, int bt, const double* W, double*
   const long long G = (long long)ntiles * nchunk;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
   // chunks beyond nc (when pchunk rounding leaves them empty) write zeros
-  if (bt == NOF_F64)
-    hipLaunchKernelGGL(k_kf1<double>, dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
-                       (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
-  else if (bt == NOF_F32)
-    hipLaunchKernelGGL(k_kf1<float>, dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
-                       (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
-  else
+  const bool vec = (norb % 2) == 0 && ((uintptr_t)b % 16) == 0;
+  if (bt == NOF_F64) {
+    if (vec)
+      hipLaunchKernelGGL((k_kf1<double, true>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
+                         (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+    else
+      hipLaunchKernelGGL((k_kf1<double, false>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux,
+                         norb, (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+  } else if (bt == NOF_F32) {
+    if (vec)
+      hipLaunchKernelGGL((k_kf1<float, true>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
+                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+    else
+      hipLaunchKernelGGL((k_kf1<float, false>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
+                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+  } else {
     return NOF_E_DTYPE;
+  }
   return launch_status();
 }
 

@@ -4,9 +4,11 @@
 // exp(y) is evaluated by scaling and squaring with a degree-12 Taylor
 // polynomial (Higham, "The scaling and squaring method for the matrix
 // exponential revisited", SIAM J. Matrix Anal. Appl. 26 (2005)): the scaling
-// power s is chosen on the device from ||y||_1 so that ||y / 2^s||_1 <= 1/4,
-// where the truncation error is below 3e-18; the polynomial is applied in
-// Horner form and then squared s times.  Nothing is read back to the host,
+// power s is chosen on the device from the Frobenius norm so that
+// ||y / 2^s||_F <= 1/4, where the truncation error is below 3e-18; the
+// polynomial is applied in Horner form and then squared s times.  Every
+// product is a split-K matrix-core GEMM (the matrices are small, so the K
+// dimension is spread over workgroups) followed by a fixed-order combine.  Nothing is read back to the host,
 // so the whole step stays asynchronous (and graph capturable): the squaring
 // launches beyond s exit immediately.
 #include <math.h>
@@ -17,7 +19,7 @@ namespace nof {
 namespace {
 
 constexpr int kTaylor = 12;
-constexpr int kMaxSquare = 16;      // ||y||_1 up to 2^16 / 4
+constexpr int kMaxSquare = 16;      // ||y||_F up to 2^16 / 4
 constexpr double kTheta = 0.25;
 
 struct ExpmScratch {
@@ -26,23 +28,22 @@ struct ExpmScratch {
   double scale;   // 2^-s
 };
 
-__global__ __launch_bounds__(1024) void k_norm1(int norb, const double* __restrict__ y,
-                                                ExpmScratch* __restrict__ sc) {
+// ||y||_F (a sub-multiplicative norm, so the Taylor truncation bound holds for
+// it) -> scaling power s with ||y||_F / 2^s <= 1/4.
+__global__ __launch_bounds__(1024) void k_norm_scale(int norb, const double* __restrict__ y,
+                                                     ExpmScratch* __restrict__ sc) {
   __shared__ double red[1024];
-  double mx = 0.0;
-  for (int j = threadIdx.x; j < norb; j += 1024) {
-    double c = 0.0;
-    for (int i = 0; i < norb; ++i) c += fabs(y[(long long)i * norb + j]);
-    mx = fmax(mx, c);
-  }
-  red[threadIdx.x] = mx;
+  const long long n2 = (long long)norb * norb;
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < n2; i += 1024) a = fma(y[i], y[i], a);
+  red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double nrm = red[0];
+    const double nrm = sqrt(red[0]);
     int s = 0;
     double sc_ = 1.0;
     while (nrm * sc_ > kTheta && s < kMaxSquare) { ++s; sc_ *= 0.5; }
@@ -51,24 +52,22 @@ __global__ __launch_bounds__(1024) void k_norm1(int norb, const double* __restri
   }
 }
 
-__global__ void k_identity(int norb, double* __restrict__ R) {
-  const long long n2 = (long long)norb * norb;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+// out = diag_c * I + coef * sum_c part[c]   (fixed summation order);
+// coef = coef_mul * sc->scale when sc is given.  If pred is given the kernel
+// runs only when *pred > pred_gt.
+__global__ void k_combine(int rows, int cols, const double* __restrict__ part, int nparts,
+                          long long stride, double diag_c, double coef_mul,
+                          const ExpmScratch* __restrict__ sc, const int* __restrict__ pred,
+                          int pred_gt, double* __restrict__ out) {
+  if (pred && *pred <= pred_gt) return;
+  const double coef = sc ? coef_mul * sc->scale : coef_mul;
+  const long long n = (long long)rows * cols;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(i / norb), c = (int)(i - (long long)r * norb);
-    R[i] = r == c ? 1.0 : 0.0;
-  }
-}
-
-// R = I - (2^-s / k) * Tm, where Tm = y^T R_prev = -(y R_prev)
-__global__ void k_horner(int norb, const double* __restrict__ Tm, double k,
-                         const ExpmScratch* __restrict__ sc, double* __restrict__ R) {
-  const double a = sc->scale / k;
-  const long long n2 = (long long)norb * norb;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(i / norb), c = (int)(i - (long long)r * norb);
-    R[i] = (r == c ? 1.0 : 0.0) - a * Tm[i];
+    double a = 0.0;
+    for (int c = 0; c < nparts; ++c) a += part[(long long)c * stride + i];
+    const int r = (int)(i / cols), q = (int)(i - (long long)r * cols);
+    out[i] = (r == q ? diag_c : 0.0) + coef * a;
   }
 }
 
@@ -104,22 +103,61 @@ inline int grid_for(long long n, int thr) {
   return (int)g;
 }
 
-GemmDesc square_desc(int norb, const double* Rin, double* Rout) {
-  // Rout = Rin Rin: X(k,m) = Rin[m][k] (row-major Rin read as [m][k])
+// Split-K plan for the small square products of this file.
+int split_for(int rows, int cols, int K) {
+  const int tiles = ((rows + 127) / 128) * ((cols + 127) / 128);
+  int ns = (384 + tiles - 1) / tiles;
+  const int maxs = (K + 15) / 16;          // at least one 16-deep stage per split
+  if (ns > maxs) ns = maxs;
+  if (ns > 32) ns = 32;
+  if (ns < 1) ns = 1;
+  return ns;
+}
+
+// part[c] = sum over k in split c of X(k, m) Y(k, n); X given k-major or m-major.
+int gemm_split(int M, int N, int K, const double* X, bool x_kmajor, long long ldx, const double* Y,
+               long long ldy, double* part, int nsplit, const int* pred, int pred_gt,
+               hipStream_t st) {
+  const int kc = (K + nsplit - 1) / nsplit;
   GemmDesc g{};
-  g.M = norb; g.N = norb; g.K = norb; g.Ktot = 0;
-  g.batch = 1; g.fold = 1;
-  g.X = Rin; g.ldx = norb; g.sx = 0; g.x_kmajor = false;
-  g.Y = Rin; g.ldy = norb; g.sy = 0;
-  g.Out = Rout; g.ldo = norb; g.so = 0;
-  return g;
+  g.M = M; g.N = N; g.K = kc; g.Ktot = K;
+  g.batch = nsplit; g.fold = 1;
+  g.X = X; g.ldx = ldx; g.sx = x_kmajor ? (long long)kc * ldx : (long long)kc; g.x_kmajor = x_kmajor;
+  g.Y = Y; g.ldy = ldy; g.sy = (long long)kc * ldy;
+  g.Out = part; g.ldo = N; g.so = (long long)M * N;
+  g.pred = pred; g.pred_gt = pred_gt;
+  return gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+}
+
+int combine(int rows, int cols, const double* part, int nparts, double diag_c, double coef_mul,
+            const ExpmScratch* sc, const int* pred, int pred_gt, double* out, hipStream_t st) {
+  const long long n = (long long)rows * cols;
+  hipLaunchKernelGGL(k_combine, dim3(grid_for(n, 256)), dim3(256), 0, st, rows, cols, part, nparts,
+                     n, diag_c, coef_mul, sc, pred, pred_gt, out);
+  return launch_status();
 }
 
 }  // namespace
 
 size_t expm_ws(int norb) {
-  const size_t n2 = (size_t)norb * norb * sizeof(double);
-  return align256(sizeof(ExpmScratch)) + 3 * align256(n2);
+  const size_t n2 = align256((size_t)norb * norb * sizeof(double));
+  const int ns = split_for(norb, norb, norb);
+  return align256(sizeof(ExpmScratch)) + 2 * n2 + (size_t)ns * n2;
+}
+
+size_t rotate_ws(int nbf, int norb) {
+  const int ns = split_for(nbf, norb, norb);
+  return (size_t)ns * align256((size_t)nbf * norb * sizeof(double));
+}
+
+int rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout, void* ws,
+                    hipStream_t st) {
+  const int ns = split_for(nbf, norb, norb);
+  double* part = (double*)ws;
+  // Cout[mu][p] = sum_q C[mu][q] U[q][p]: X(k=q, m=mu) = C[mu][q] (m-major)
+  int rc = gemm_split(nbf, norb, norb, C, false, norb, U, norb, part, ns, nullptr, 0, st);
+  if (rc != NOF_OK) return rc;
+  return combine(nbf, norb, part, ns, 0.0, 1.0, nullptr, nullptr, 0, Cout, st);
 }
 
 int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st) {
@@ -128,39 +166,37 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st)
   const size_t n2b = align256((size_t)norb * norb * sizeof(double));
   double* A = (double*)(w + align256(sizeof(ExpmScratch)));
   double* Bm = (double*)((char*)A + n2b);
-  double* Tm = (double*)((char*)Bm + n2b);
-  const long long n2 = (long long)norb * norb;
-  const int gr = grid_for(n2, 256);
-  hipLaunchKernelGGL(k_norm1, dim3(1), dim3(1024), 0, st, norb, y, sc);
-  hipLaunchKernelGGL(k_identity, dim3(gr), dim3(256), 0, st, norb, A);
+  double* part = (double*)((char*)Bm + n2b);
+  const int ns = split_for(norb, norb, norb);
+  hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(1024), 0, st, norb, y, sc);
   int rc = launch_status();
   if (rc != NOF_OK) return rc;
-  // Horner: R <- I + (x/k) R for k = 12..1, x = y / 2^s
-  for (int k = kTaylor; k >= 1; --k) {
-    GemmDesc g{};
-    g.M = norb; g.N = norb; g.K = norb; g.Ktot = 0;
-    g.batch = 1; g.fold = 1;
-    g.X = y; g.ldx = norb; g.sx = 0; g.x_kmajor = true;     // y^T R
-    g.Y = A; g.ldy = norb; g.sy = 0;
-    g.Out = Tm; g.ldo = norb; g.so = 0;
-    rc = gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+  // Horner with x = y / 2^s:  R_12 = I + x/12,  R_k = I + (x/k) R_{k+1}.
+  // y^T = -y, so x R = -(2^-s) y^T R and y^T R is a k-major product.
+  // First step: R_12 = I - (2^-s/12) y^T I = I + x/12 computed as a product too.
+  hipLaunchKernelGGL(k_combine, dim3(grid_for((long long)norb * norb, 256)), dim3(256), 0, st, norb,
+                     norb, y, 1, 0LL, 1.0, 1.0 / kTaylor, sc, nullptr, 0, A);
+  rc = launch_status();
+  if (rc != NOF_OK) return rc;
+  for (int k = kTaylor - 1; k >= 1; --k) {
+    rc = gemm_split(norb, norb, norb, y, true, norb, A, norb, part, ns, nullptr, 0, st);
     if (rc != NOF_OK) return rc;
-    hipLaunchKernelGGL(k_horner, dim3(gr), dim3(256), 0, st, norb, Tm, (double)k, sc, A);
-    rc = launch_status();
+    rc = combine(norb, norb, part, ns, 1.0, -1.0 / k, sc, nullptr, 0, A, st);
     if (rc != NOF_OK) return rc;
   }
   // squarings i = 0 .. s-1, ping-pong A -> B -> A ...
   double* cur = A;
   double* nxt = Bm;
   for (int i = 0; i < kMaxSquare; ++i) {
-    GemmDesc g = square_desc(norb, cur, nxt);
-    g.pred = &sc->s;
-    g.pred_gt = i;
-    rc = gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+    // nxt = cur cur: X(k, m) = cur[m][k] (m-major)
+    rc = gemm_split(norb, norb, norb, cur, false, norb, cur, norb, part, ns, &sc->s, i, st);
+    if (rc != NOF_OK) return rc;
+    rc = combine(norb, norb, part, ns, 0.0, 1.0, nullptr, &sc->s, i, nxt, st);
     if (rc != NOF_OK) return rc;
     double* t = cur; cur = nxt; nxt = t;
   }
-  hipLaunchKernelGGL(k_select, dim3(gr), dim3(256), 0, st, norb, A, Bm, sc, U);
+  hipLaunchKernelGGL(k_select, dim3(grid_for((long long)norb * norb, 256)), dim3(256), 0, st, norb,
+                     A, Bm, sc, U);
   return launch_status();
 }
 

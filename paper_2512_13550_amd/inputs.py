@@ -65,17 +65,31 @@ def _slab_rng(seed: int, P: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(P), 0xB])))
 
 
+_DAMP_CACHE: dict = {}
+
+
+def _damping(nbf: int, decay: float) -> np.ndarray:
+    key = (nbf, float(decay))
+    d = _DAMP_CACHE.get(key)
+    if d is None:
+        idx = np.arange(nbf)
+        d = np.exp(-np.abs(idx[:, None] - idx[None, :]) / decay)
+        _DAMP_CACHE[key] = d
+    return d
+
+
 def make_B_slab(seed: int, P: int, nbf: int, naux: int, decay: float,
                 dtype=np.float64) -> np.ndarray:
-    """One slab B[P] (nbf x nbf, symmetric), reproducible from (seed, P) alone."""
+    """One slab B[P] (nbf x nbf, symmetric), reproducible from (seed, P) alone.
+
+    An nbf x nbf standard-normal draw; its upper triangle (with the diagonal)
+    is kept and mirrored, scaled to variance 1/naux, then damped."""
     rng = _slab_rng(seed, P)
-    iu = np.triu_indices(nbf)
-    vals = rng.standard_normal(iu[0].size) * (1.0 / math.sqrt(naux))
-    S = np.zeros((nbf, nbf), dtype=np.float64)
-    S[iu] = vals
-    S = S + np.triu(S, 1).T
-    idx = np.arange(nbf)
-    S *= np.exp(-np.abs(idx[:, None] - idx[None, :]) / decay)
+    G = rng.standard_normal((nbf, nbf))
+    U = np.triu(G)
+    S = U + U.T
+    S[np.diag_indices(nbf)] *= 0.5
+    S *= _damping(nbf, decay) * (1.0 / math.sqrt(naux))
     return S.astype(dtype, copy=False)
 
 

@@ -46,14 +46,16 @@ _sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_coeffs_from_cumulant", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_expm_antisym_ws", _sz, _i)
 _sig("nof_expm_antisym", _i, _i, _vp, _vp, _vp, _sz, _vp)
-_sig("nof_rotate_orbitals", _i, _i, _i, _vp, _vp, _vp, _vp)
+_sig("nof_rotate_orbitals_ws", _sz, _i, _i)
+_sig("nof_rotate_orbitals", _i, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_adam_step", _i, _i, _vp, _vp, _vp, _i, _d, _d, _d, _d, _vp, _vp)
 
 DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
     "nof_mo_transform_stage2", "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
-    "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals", "nof_adam_step",
+    "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
+    "nof_adam_step",
 ]
 
 
@@ -218,12 +220,15 @@ def expm_antisym(y, U=None, ws=None, stream=None):
     return U
 
 
-def rotate_orbitals(C, U, Cout=None, stream=None):
+def rotate_orbitals(C, U, Cout=None, ws=None, stream=None):
     """Cout = C U (nof_rotate_orbitals)."""
     nbf, norb = C.shape
     if Cout is None:
         Cout = torch.empty_like(C)
-    check(lib.nof_rotate_orbitals(nbf, norb, _f64(C, "C"), _f64(U, "U"), _p(Cout),
+    need = lib.nof_rotate_orbitals_ws(nbf, norb)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, C.device)
+    check(lib.nof_rotate_orbitals(nbf, norb, _f64(C, "C"), _f64(U, "U"), _p(Cout), _p(ws), ws.numel(),
                                   stream_handle(stream)), "nof_rotate_orbitals")
     return Cout
 
@@ -244,7 +249,8 @@ class Rotation:
     def __init__(self, norb, nbf, device):
         self.U = torch.empty((norb, norb), dtype=torch.float64, device=device)
         self.ws = workspace(lib.nof_expm_antisym_ws(norb), device)
+        self.ws_rot = workspace(lib.nof_rotate_orbitals_ws(nbf, norb), device)
 
     def apply(self, C, y, Cout, stream=None):
         expm_antisym(y, self.U, self.ws, stream)
-        return rotate_orbitals(C, self.U, Cout, stream)
+        return rotate_orbitals(C, self.U, Cout, self.ws_rot, stream)
