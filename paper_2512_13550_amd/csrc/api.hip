@@ -124,6 +124,7 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     g1.S = nullptr; g1.lds = 0;
     g1.Out = T; g1.ldo = norb; g1.so = (long long)nbf * norb;
     g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
+    g1.role = GemmRole::TransformStage1;
     return gemm_tn(g1, Bt, NOF_F64, Tt, prec, stream);
   });
 }
@@ -145,6 +146,7 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     g2.S = nullptr; g2.lds = 0;
     g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
     g2.Dg = D; g2.sd = norb; g2.sym = true;
+    g2.role = GemmRole::TransformStage2;
     return gemm_tn(g2, NOF_F64, Tt, bt, prec, stream);
   });
 }
@@ -250,6 +252,7 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     g2.S = cK; g2.lds = norb;
     g2.Out = f2part; g2.ldo = norb; g2.so = n2;
     g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
+    g2.role = GemmRole::ExchangeFock;
     NOF_TRY(gemm_tn(g2, bt, bt, NOF_F64, prec, stream));
     NOF_TRY(reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream));
     return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);

@@ -45,6 +45,8 @@ inline size_t dtype_size(int t) {
 //       are written to Out[m][n] and Out[n][m]; Dg[b*sd + m] = Out[m][m].
 // fold: batches [c*fold, (c+1)*fold) are accumulated into one result that is
 //       written to Out + c*so (split reduction over the batch index).
+enum class GemmRole : int { Small = 0, TransformStage1, TransformStage2, ExchangeFock };
+
 struct GemmDesc {
   int M, N, K;
   long long Ktot;    // if > 0: batch b only has k < Ktot - b*K (split-K over batches)
@@ -57,6 +59,7 @@ struct GemmDesc {
   double* Dg; long long sd;
   bool sym;
   const int* pred; int pred_gt;   // if pred: run only when *pred > pred_gt (else write nothing)
+  GemmRole role;                   // selects the kernel symbol (profiling attribution only)
 };
 
 // Element types: 0 = f64, 1 = f32.  prec: NOF_P_F64 or NOF_P_F32.

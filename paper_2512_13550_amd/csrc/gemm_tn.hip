@@ -59,7 +59,7 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& tm, int& tn) {
 }
 
 template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64, bool HAS_S>
-__global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, int ntiles) {
+__device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int ntiles) {
   typedef Mfma<TC> MF;
   typedef typename MF::acc_t acc_t;
   __shared__ TC Xs[2][KT][LDSW];
@@ -214,6 +214,19 @@ __global__ __launch_bounds__(NTHR, 2) void k_gemm_tn(GemmDesc d, int tiles_n, in
       }
 }
 
+// One kernel symbol per role, so that profiles attribute time per step.
+#define NOF_GEMM_KERNEL(NAME)                                                              \
+  template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64,     \
+            bool HAS_S>                                                                    \
+  __global__ __launch_bounds__(NTHR, 2) void NAME(GemmDesc d, int tiles_n, int ntiles) {   \
+    gemm_body<TC, TX, TY, TO, XK, FLUSH64, HAS_S>(d, tiles_n, ntiles);                    \
+  }
+NOF_GEMM_KERNEL(k_transform_stage1)
+NOF_GEMM_KERNEL(k_transform_stage2)
+NOF_GEMM_KERNEL(k_exchange_fock)
+NOF_GEMM_KERNEL(k_gemm_small)
+#undef NOF_GEMM_KERNEL
+
 template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
 int launch(const GemmDesc& d, hipStream_t st) {
   if (!XK && PER_T * 16 > BM) return NOF_E_INTERNAL;
@@ -224,12 +237,22 @@ int launch(const GemmDesc& d, hipStream_t st) {
   const long long G = (long long)ntiles * ngroups;
   if (G <= 0) return NOF_OK;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
-  if (d.S)
-    hipLaunchKernelGGL((k_gemm_tn<TC, TX, TY, TO, XK, FLUSH64, true>), dim3((unsigned)G), dim3(NTHR),
-                       0, st, d, tiles_n, ntiles);
-  else
-    hipLaunchKernelGGL((k_gemm_tn<TC, TX, TY, TO, XK, FLUSH64, false>), dim3((unsigned)G), dim3(NTHR),
-                       0, st, d, tiles_n, ntiles);
+#define NOF_LAUNCH(NAME)                                                                      \
+  do {                                                                                        \
+    if (d.S)                                                                                  \
+      hipLaunchKernelGGL((NAME<TC, TX, TY, TO, XK, FLUSH64, true>), dim3((unsigned)G),        \
+                         dim3(NTHR), 0, st, d, tiles_n, ntiles);                              \
+    else                                                                                      \
+      hipLaunchKernelGGL((NAME<TC, TX, TY, TO, XK, FLUSH64, false>), dim3((unsigned)G),       \
+                         dim3(NTHR), 0, st, d, tiles_n, ntiles);                              \
+  } while (0)
+  switch (d.role) {
+    case GemmRole::TransformStage1: NOF_LAUNCH(k_transform_stage1); break;
+    case GemmRole::TransformStage2: NOF_LAUNCH(k_transform_stage2); break;
+    case GemmRole::ExchangeFock: NOF_LAUNCH(k_exchange_fock); break;
+    default: NOF_LAUNCH(k_gemm_small); break;
+  }
+#undef NOF_LAUNCH
   return launch_status();
 }
 
