@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c500")
-    ap.add_argument("--forms", default="f32", help="comma list of extra forms: f32")
+    ap.add_argument("--forms", default="f32,bf16x3,bf16x6,bf16B",
+                    help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16B (B stored in BF16)")
     ap.add_argument("--cpu-slabs", type=int, default=160,
                     help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
     return ap.parse_args()
@@ -84,9 +85,12 @@ def main():
 
     flops = algorithmic_flops(nbf, naux, norb)
 
+    PRECS = {"f64": nof.P_F64, "f32": nof.P_F32, "bf16x1": nof.P_BF16X1, "bf16x3": nof.P_BF16X3,
+             "bf16x6": nof.P_BF16X6, "bf16B": nof.P_BF16X6}
+
     def run(B, prec_name, steps, warmup):
         dt = torch.float64 if prec_name == "f64" else torch.float32
-        prec = nof.P_F64 if prec_name == "f64" else nof.P_F32
+        prec = PRECS[prec_name]
         C = torch.from_numpy(C0).to(dev)
         Cn = torch.empty_like(C)
         T = torch.empty((naux, nbf, norb), dtype=dt, device=dev)
@@ -153,24 +157,32 @@ def main():
     a1_tf = flops["a1"] / (a1_ms * 1e-3) / 1e12
 
     forms = {}
+    B32 = None
     for f in [x for x in args.forms.split(",") if x]:
-        if f == "f32":
-            print("# timing fp32", file=sys.stderr, flush=True)
-            B32 = B64.to(torch.float32)
-            r = run(B32, "f32", args.steps, args.warmup)
-            del B32
-            torch.cuda.empty_cache()
-            dE = max(abs(a - b_) for a, b_ in zip(r["E"], r64["E"]))
-            forms["f32"] = dict(
-                ms_per_step=r["ms_per_step"],
-                tflops=flops["total"] / (r["ms_per_step"] * 1e-3) / 1e12,
-                max_abs_dE_Eh=dE,
-                max_abs_dJ=float((r["J"] - r64["J"]).abs().max()),
-                max_abs_dK=float((r["K"] - r64["K"]).abs().max()),
-                max_abs_dlambda=float((r["lam"] - r64["lam"]).abs().max()),
-                stage_ms=dict(zip(seg_names, r["seg_ms"])),
-                meets_dE_1e6=bool(dE <= 1e-6),
-            )
+        print(f"# timing {f}", file=sys.stderr, flush=True)
+        if f == "bf16B":
+            Bf = B64.to(torch.bfloat16)
+        else:
+            if B32 is None:
+                B32 = B64.to(torch.float32)
+            Bf = B32
+        r = run(Bf, f, args.steps, args.warmup)
+        del Bf
+        torch.cuda.empty_cache()
+        dE = max(abs(a - b_) for a, b_ in zip(r["E"], r64["E"]))
+        forms[f] = dict(
+            ms_per_step=r["ms_per_step"],
+            tflops=flops["total"] / (r["ms_per_step"] * 1e-3) / 1e12,
+            speedup_vs_f64=ms / r["ms_per_step"],
+            max_abs_dE_Eh=dE,
+            max_abs_dJ=float((r["J"] - r64["J"]).abs().max()),
+            max_abs_dK=float((r["K"] - r64["K"]).abs().max()),
+            max_abs_dlambda=float((r["lam"] - r64["lam"]).abs().max()),
+            stage_ms=dict(zip(seg_names, r["seg_ms"])),
+            meets_dE_1e6=bool(dE <= 1e-6),
+        )
+    del B32
+    torch.cuda.empty_cache()
 
     cpu = None
     if args.cpu_slabs > 0:

@@ -60,8 +60,20 @@ FockLayout fock_layout(int naux, int norb) {
   return L;
 }
 
+bool prec_ok(int prec) {
+  return prec == NOF_P_F64 || prec == NOF_P_F32 || is_bf16_prec(prec);
+}
+
+// Storage of b (and of the half-transformed T) for a precision mode.
 bool prec_matches(int prec, int t) {
-  return (prec == NOF_P_F64 && t == NOF_F64) || (prec == NOF_P_F32 && t == NOF_F32);
+  return (prec == NOF_P_F64 && t == NOF_F64) || (prec == NOF_P_F32 && t == NOF_F32) ||
+         (is_bf16_prec(prec) && t == NOF_F32);
+}
+
+// Storage of B for a precision mode: as b, or BF16 for the 3-piece split forms.
+bool b_input_ok(int prec, int Bt) {
+  if (prec_matches(prec, Bt)) return true;
+  return Bt == NOF_BF16 && (prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6);
 }
 
 template <class F>
@@ -103,7 +115,7 @@ const char* nof_status_str(int status) {
 
 size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
-  if (Bt != bt || !prec_matches(prec, bt)) return 0;
+  if (!prec_matches(prec, bt) || !b_input_ok(prec, Bt)) return 0;
   return align256((size_t)naux * nbf * norb * dtype_size(bt));
 }
 
@@ -112,9 +124,10 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
   return guarded([&]() -> int {
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!B || !C || !T) return NOF_E_NULL;
-    if (Bt != Tt || dtype_size(Bt) == 0 || Bt == NOF_BF16) return NOF_E_DTYPE;
-    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
-    if (!prec_matches(prec, Bt)) return NOF_E_PREC;
+    if (dtype_size(Bt) == 0 || dtype_size(Tt) == 0) return NOF_E_DTYPE;
+    if (!prec_ok(prec)) return NOF_E_PREC;
+    if (!prec_matches(prec, Tt)) return NOF_E_PREC;
+    if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
     // T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
     GemmDesc g1{};
     g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
@@ -125,7 +138,7 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     g1.Out = T; g1.ldo = norb; g1.so = (long long)nbf * norb;
     g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
     g1.role = GemmRole::TransformStage1;
-    return gemm_tn(g1, Bt, NOF_F64, Tt, prec, stream);
+    return gemm_any(g1, Bt, NOF_F64, Tt, prec, stream);
   });
 }
 
@@ -135,7 +148,7 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!T || !C || !b) return NOF_E_NULL;
     if (Tt != bt || dtype_size(bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
-    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     // b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
     GemmDesc g2{};
@@ -147,7 +160,7 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
     g2.Dg = D; g2.sd = norb; g2.sym = true;
     g2.role = GemmRole::TransformStage2;
-    return gemm_tn(g2, NOF_F64, Tt, bt, prec, stream);
+    return gemm_any(g2, NOF_F64, Tt, bt, prec, stream);
   });
 }
 
@@ -156,9 +169,10 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
   return guarded([&]() -> int {
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!B || !C || !b) return NOF_E_NULL;
-    if (Bt != bt || dtype_size(bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
-    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (dtype_size(bt) == 0 || dtype_size(Bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
+    if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
     const size_t need = nof_mo_transform_ws(naux, nbf, norb, Bt, bt, prec);
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
     NOF_TRY(nof_mo_transform_stage1(naux, nbf, norb, B, Bt, C, ws, bt, prec, stream));
@@ -217,7 +231,7 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
     if (!b || !D || !n || !h || !cJ || !cK || !lambda) return NOF_E_NULL;
     if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
-    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     const FockLayout L = fock_layout(naux, norb);
     if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
@@ -253,7 +267,7 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     g2.Out = f2part; g2.ldo = norb; g2.so = n2;
     g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
     g2.role = GemmRole::ExchangeFock;
-    NOF_TRY(gemm_tn(g2, bt, bt, NOF_F64, prec, stream));
+    NOF_TRY(gemm_any(g2, bt, bt, NOF_F64, prec, stream));
     NOF_TRY(reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream));
     return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
   });

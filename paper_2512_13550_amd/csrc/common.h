@@ -67,6 +67,18 @@ struct GemmDesc {
 // consumed by an FP32 contraction.  Out type: f64 or f32.
 int gemm_tn(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
 
+// Split-precision BF16 form of the same contract (gemm_bf16.hip); prec is one
+// of NOF_P_BF16X1/X3/X6; x_t may be NOF_BF16 for the first transform stage.
+int gemm_bf16(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
+
+inline bool is_bf16_prec(int prec) {
+  return prec == NOF_P_BF16X1 || prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6;
+}
+inline int gemm_any(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st) {
+  return is_bf16_prec(prec) ? gemm_bf16(d, x_t, y_t, out_t, prec, st)
+                            : gemm_tn(d, x_t, y_t, out_t, prec, st);
+}
+
 // Pass over the upper triangle of b (HBM bound):
 //   Kpart[c][r][s] = sum_{P in chunk c} b_rs^2              (r <= s)
 //   F1part[c][r][s] += b_rs W[P][s],  F1part[c][s][r] += b_rs W[P][r]

@@ -101,19 +101,27 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 # ---------------------------------------------------------------------------
 def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
-    """b^P = C^T B^P C and D[P][p] = b^P_pp (nof_mo_transform)."""
+    """b^P = C^T B^P C and D[P][p] = b^P_pp (nof_mo_transform).
+
+    prec defaults to the arithmetic of B's storage (FP64 or FP32); the BF16
+    split forms (P_BF16X1/X3/X6) take B in FP32 (or BF16 for X3/X6) and
+    produce b in FP32."""
     naux, nbf, _ = B.shape
     norb = C.shape[1]
-    bt = _TDT[B.dtype]
-    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    Bt = _TDT[B.dtype]
+    prec = _PREC_OF.get(Bt, P_F64) if prec is None else prec
+    bdtype = torch.float64 if prec == P_F64 else torch.float32
     if b is None:
-        b = torch.empty((naux, norb, norb), dtype=B.dtype, device=B.device)
+        b = torch.empty((naux, norb, norb), dtype=bdtype, device=B.device)
+    bt = _TDT[b.dtype]
     if D is None:
         D = torch.empty((naux, norb), dtype=torch.float64, device=B.device)
-    need = lib.nof_mo_transform_ws(naux, nbf, norb, bt, bt, prec)
+    need = lib.nof_mo_transform_ws(naux, nbf, norb, Bt, bt, prec)
+    if need == 0:
+        raise NofError(E_DTYPE, "nof_mo_transform_ws")
     if ws is None or ws.numel() < need:
         ws = workspace(need, B.device)
-    check(lib.nof_mo_transform(naux, nbf, norb, _p(B), bt, _f64(C, "C"), _p(b), bt, _p(D), prec,
+    check(lib.nof_mo_transform(naux, nbf, norb, _p(B), Bt, _f64(C, "C"), _p(b), bt, _p(D), prec,
                                _p(ws), ws.numel(), stream_handle(stream)), "nof_mo_transform")
     return b, D
 

@@ -50,7 +50,8 @@ def test_transform_validation():
     L = nof.lib
     assert L.nof_mo_transform(0, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 0, FAKE, 1 << 20, None) == nof.E_DIM
     assert L.nof_mo_transform(2, 4, 4, None, 0, FAKE, FAKE, 0, None, 0, FAKE, 1 << 20, None) == nof.E_NULL
-    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 1, None, 0, FAKE, 1 << 20, None) == nof.E_DTYPE
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 2, None, 0, FAKE, 1 << 20, None) == nof.E_DTYPE
+    assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 1, None, 0, FAKE, 1 << 20, None) == nof.E_PREC
     assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 1, FAKE, 1 << 20, None) == nof.E_PREC
     assert L.nof_mo_transform(2, 4, 4, FAKE, 0, FAKE, FAKE, 0, None, 7, FAKE, 1 << 20, None) == nof.E_PREC
     need = L.nof_mo_transform_ws(2, 4, 4, 0, 0, 0)
