@@ -81,14 +81,19 @@ const char* nof_status_str(int status);
  *
  *   b^P = C^T B^P C  for P = 0..naux-1,   D[P][p] = b^P_pp.
  *
- * B   [naux][nbf][nbf], storage Bt (NOF_F64 or NOF_F32).  Must be symmetric
- *     in (mu,nu): the kernel reads B^P_{nu mu} where the definition has
- *     B^P_{mu nu}.
- * C   [nbf][norb] FP64 (the master copy; converted on load for FP32 math).
- * b   out [naux][norb][norb], storage bt (== Bt); written exactly symmetric.
+ * B   [naux][nbf][nbf], storage Bt.  Must be symmetric in (mu,nu): the
+ *     kernel reads B^P_{nu mu} where the definition has B^P_{mu nu}.
+ * C   [nbf][norb] FP64 (the master copy; converted or split on load).
+ * b   out [naux][norb][norb], storage bt; written exactly symmetric.
  * D   out [naux][norb] FP64, may be NULL.
- * prec  NOF_P_F64 (Bt = bt = NOF_F64) or NOF_P_F32 (Bt = bt = NOF_F32).
- * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C).
+ * prec / storage:
+ *     NOF_P_F64            Bt = bt = NOF_F64
+ *     NOF_P_F32            Bt = bt = NOF_F32
+ *     NOF_P_BF16X1/X3/X6   Bt = NOF_F32 (or NOF_BF16 with X3/X6), bt = NOF_F32;
+ *                          B and T are split into BF16 pieces in the loaders,
+ *                          C once per call (three pieces for a BF16-stored B).
+ * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C and
+ *     the BF16 pieces of C).
  *
  * With naux = 1 and B = H (the AO one-electron matrix) this yields
  * h = C^T H C, the one-electron integrals of Eq. (Energy) in the NO basis.
@@ -103,13 +108,16 @@ int nof_mo_transform(int naux, int nbf, int norb,
  * rules), for callers that keep the half-transformed tensor or time the stages:
  *   stage 1:  T[P][mu][q] = (B^P C)_{mu q}        T: [naux][nbf][norb], storage Tt
  *   stage 2:  b^P = C^T T^P, D[P][p] = b^P_pp     (exactly symmetric b)
- * Tt must equal Bt (stage 1) and bt (stage 2). */
+ * Tt is the storage of b for the precision mode.  ws (at least
+ * nof_mo_transform_stage_ws() bytes) holds the BF16 pieces of C in the split
+ * forms; FP64/FP32 ignore it (it may be NULL). */
+size_t nof_mo_transform_stage_ws(int nbf, int norb, int prec);
 int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt,
                             const double* C, void* T, int Tt, int prec,
-                            hipStream_t stream);
+                            void* ws, size_t ws_bytes, hipStream_t stream);
 int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt,
                             const double* C, void* b, int bt, double* D, int prec,
-                            hipStream_t stream);
+                            void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Coulomb and exchange integrals in the NO basis (Eq. PNOF's J and K).

@@ -113,14 +113,32 @@ const char* nof_status_str(int status) {
   }
 }
 
+// Bytes of the per-call scratch of one transform stage (bf16 planes of C).
+size_t stage_ws(int nbf, int norb, int prec, int Bt) {
+  if (!is_bf16_prec(prec)) return 256;
+  const int np = Bt == NOF_BF16 ? 3 : bf16_pieces(prec);
+  return align256((size_t)np * norb * presplit_ldk(nbf) * 2);
+}
+
+int split_C(int nbf, int norb, const double* C, int prec, int Bt, void* ws, hipStream_t stream) {
+  const int np = Bt == NOF_BF16 ? 3 : bf16_pieces(prec);
+  return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream);
+}
+
+size_t nof_mo_transform_stage_ws(int nbf, int norb, int prec) {
+  if (!dim_ok(nbf) || !dim_ok(norb) || !prec_ok(prec)) return 0;
+  return stage_ws(nbf, norb, prec, NOF_BF16);
+}
+
 size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt) || !b_input_ok(prec, Bt)) return 0;
-  return align256((size_t)naux * nbf * norb * dtype_size(bt));
+  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(nbf, norb, prec, NOF_BF16);
 }
 
 int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, const double* C,
-                            void* T, int Tt, int prec, hipStream_t stream) {
+                            void* T, int Tt, int prec, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
   return guarded([&]() -> int {
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!B || !C || !T) return NOF_E_NULL;
@@ -128,6 +146,8 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, Tt)) return NOF_E_PREC;
     if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
+    const bool bf = is_bf16_prec(prec);
+    if (bf && (!ws || ws_bytes < stage_ws(nbf, norb, prec, Bt))) return NOF_E_WORKSPACE;
     // T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
     GemmDesc g1{};
     g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
@@ -138,18 +158,24 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     g1.Out = T; g1.ldo = norb; g1.so = (long long)nbf * norb;
     g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
     g1.role = GemmRole::TransformStage1;
-    return gemm_any(g1, Bt, NOF_F64, Tt, prec, stream);
+    if (!bf) return gemm_tn(g1, Bt, NOF_F64, Tt, prec, stream);
+    NOF_TRY(split_C(nbf, norb, C, prec, Bt, ws, stream));
+    g1.Y = ws; g1.ldy = presplit_ldk(nbf); g1.psy = (long long)norb * presplit_ldk(nbf);
+    return gemm_bf16(g1, Bt, NOF_BF16, Tt, prec, stream);
   });
 }
 
 int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, const double* C,
-                            void* b, int bt, double* D, int prec, hipStream_t stream) {
+                            void* b, int bt, double* D, int prec, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
   return guarded([&]() -> int {
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!T || !C || !b) return NOF_E_NULL;
     if (Tt != bt || dtype_size(bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    const bool bf = is_bf16_prec(prec);
+    if (bf && (!ws || ws_bytes < stage_ws(nbf, norb, prec, NOF_F32))) return NOF_E_WORKSPACE;
     // b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
     GemmDesc g2{};
     g2.M = norb; g2.N = norb; g2.K = nbf; g2.Ktot = 0;
@@ -160,7 +186,10 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
     g2.Dg = D; g2.sd = norb; g2.sym = true;
     g2.role = GemmRole::TransformStage2;
-    return gemm_any(g2, NOF_F64, Tt, bt, prec, stream);
+    if (!bf) return gemm_tn(g2, NOF_F64, Tt, bt, prec, stream);
+    NOF_TRY(split_C(nbf, norb, C, prec, NOF_F32, ws, stream));
+    g2.X = ws; g2.ldx = presplit_ldk(nbf); g2.psx = (long long)norb * presplit_ldk(nbf);
+    return gemm_bf16(g2, NOF_BF16, Tt, bt, prec, stream);
   });
 }
 
@@ -175,8 +204,11 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
     if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
     const size_t need = nof_mo_transform_ws(naux, nbf, norb, Bt, bt, prec);
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
-    NOF_TRY(nof_mo_transform_stage1(naux, nbf, norb, B, Bt, C, ws, bt, prec, stream));
-    return nof_mo_transform_stage2(naux, nbf, norb, ws, bt, C, b, bt, D, prec, stream);
+    const size_t tbytes = align256((size_t)naux * nbf * norb * dtype_size(bt));
+    char* sws = (char*)ws + tbytes;
+    const size_t sbytes = ws_bytes - tbytes;
+    NOF_TRY(nof_mo_transform_stage1(naux, nbf, norb, B, Bt, C, ws, bt, prec, sws, sbytes, stream));
+    return nof_mo_transform_stage2(naux, nbf, norb, ws, bt, C, b, bt, D, prec, sws, sbytes, stream);
   });
 }
 

@@ -60,6 +60,7 @@ struct GemmDesc {
   bool sym;
   const int* pred; int pred_gt;   // if pred: run only when *pred > pred_gt (else write nothing)
   GemmRole role;                   // selects the kernel symbol (profiling attribution only)
+  long long psx, psy;              // plane strides of pre-split bf16 operands (gemm_bf16)
 };
 
 // Element types: 0 = f64, 1 = f32.  prec: NOF_P_F64 or NOF_P_F32.
@@ -70,6 +71,11 @@ int gemm_tn(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_
 // Split-precision BF16 form of the same contract (gemm_bf16.hip); prec is one
 // of NOF_P_BF16X1/X3/X6; x_t may be NOF_BF16 for the first transform stage.
 int gemm_bf16(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
+// Split a k-major FP64 matrix into np bf16 planes [np][ncol][ldk] (gemm_bf16.hip).
+int presplit_bf16(const double* A, int K, int ncol, int lda, int ldk, int np, void* out,
+                  hipStream_t st);
+inline int bf16_pieces(int prec) { return prec == NOF_P_BF16X1 ? 1 : prec == NOF_P_BF16X3 ? 2 : 3; }
+inline long long presplit_ldk(int K) { return ((long long)K + 31) / 32 * 32; }
 
 inline bool is_bf16_prec(int prec) {
   return prec == NOF_P_BF16X1 || prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6;

@@ -36,8 +36,9 @@ def _sig(name, res, *args):
 _sig("nof_status_str", ctypes.c_char_p, _i)
 _sig("nof_mo_transform_ws", _sz, _i, _i, _i, _i, _i, _i)
 _sig("nof_mo_transform", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
-_sig("nof_mo_transform_stage1", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp)
-_sig("nof_mo_transform_stage2", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp)
+_sig("nof_mo_transform_stage_ws", _sz, _i, _i, _i)
+_sig("nof_mo_transform_stage1", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _sz, _vp)
+_sig("nof_mo_transform_stage2", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
 _sig("nof_jk_diag_ws", _sz, _i, _i, _i)
 _sig("nof_jk_diag", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
@@ -52,7 +53,7 @@ _sig("nof_adam_step", _i, _i, _vp, _vp, _vp, _i, _d, _d, _d, _d, _vp, _vp)
 
 DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
-    "nof_mo_transform_stage2", "nof_jk_diag_ws", "nof_jk_diag",
+    "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_adam_step",
@@ -126,24 +127,35 @@ def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
     return b, D
 
 
-def transform_stage1(B, C, T, prec=None, stream=None):
+def _stage_ws(nbf, norb, prec, device, ws):
+    need = lib.nof_mo_transform_stage_ws(nbf, norb, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, device)
+    return ws
+
+
+def transform_stage1(B, C, T, prec=None, ws=None, stream=None):
     """T^P = B^P C (first half of nof_mo_transform) into caller-owned T."""
     naux, nbf, _ = B.shape
     norb = C.shape[1]
     bt = _TDT[B.dtype]
     prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    ws = _stage_ws(nbf, norb, prec, B.device, ws)
     check(lib.nof_mo_transform_stage1(naux, nbf, norb, _p(B), bt, _f64(C, "C"), _p(T), _TDT[T.dtype],
-                                      prec, stream_handle(stream)), "nof_mo_transform_stage1")
+                                      prec, _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_mo_transform_stage1")
     return T
 
 
-def transform_stage2(T, C, b, D, prec=None, stream=None):
+def transform_stage2(T, C, b, D, prec=None, ws=None, stream=None):
     """b^P = C^T T^P and D (second half of nof_mo_transform)."""
     naux, nbf, norb = T.shape
     bt = _TDT[b.dtype]
     prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    ws = _stage_ws(nbf, norb, prec, T.device, ws)
     check(lib.nof_mo_transform_stage2(naux, nbf, norb, _p(T), _TDT[T.dtype], _f64(C, "C"), _p(b), bt,
-                                      _p(D), prec, stream_handle(stream)), "nof_mo_transform_stage2")
+                                      _p(D), prec, _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_mo_transform_stage2")
     return b, D
 
 
