@@ -1,0 +1,89 @@
+"""Occupation-dependent coefficients of Eq. (PNOF) for the functionals used here.
+
+The paper cites the explicit functionals out (Table 1 lists PNOF5, PNOF7, GNOF,
+GNOFm).  Two reconstructions are provided, both in the (Delta, Pi) form of the
+(2,2)-positivity cumulant (Theory: sigma-sigma and alpha-beta blocks), which
+``dfjk.coeffs_from_cumulant`` turns into cJ = 2(nn^T - Delta) and
+cK = nn^T - Delta - Pi:
+
+* "hf":    Delta = Pi = 0 (the HF-like term of the cumulant expansion alone);
+* "pnof5": the independent-pair model on the orbital-pairing structure
+  (subspaces Omega_g of one strong and N_g weak orbitals, Eq. OmegaG):
+  Delta_pq = n_p n_q and Pi_pq = sign * sqrt(n_p n_q) inside one subspace
+  (sign -1 when the strong orbital is involved, +1 between two weak orbitals,
+  Pi_pp = n_p), zero between subspaces.  The formulas follow the cited
+  literature (parity unpinned as a functional; its energy is pinned against
+  the exact two-electron two-orbital result and the spin-orbital 2RDM).
+
+``members`` is an (ns, ng+1) integer array: row g lists the strong orbital of
+subspace g first, then its weak orbitals.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def group_of(norb, members):
+    grp = -np.ones(norb, dtype=np.int64)
+    strong = np.zeros(norb, dtype=bool)
+    for g, row in enumerate(members):
+        grp[row] = g
+        strong[row[0]] = True
+    return grp, strong
+
+
+def delta_pi(n, members, functional):
+    m = len(n)
+    if functional == "hf":
+        return np.zeros((m, m)), np.zeros((m, m))
+    if functional != "pnof5":
+        raise ValueError(functional)
+    grp, strong = group_of(m, members)
+    Delta = np.zeros((m, m))
+    Pi = np.zeros((m, m))
+    for row in members:
+        for p in row:
+            for q in row:
+                Delta[p, q] = n[p] * n[q]
+                if p == q:
+                    Pi[p, q] = n[p]
+                else:
+                    sgn = -1.0 if (strong[p] or strong[q]) else 1.0
+                    Pi[p, q] = sgn * np.sqrt(n[p] * n[q])
+    return Delta, Pi
+
+
+def coefficients(n, members, functional):
+    """cJ, cK of Eq. (PNOF) for the chosen functional."""
+    from oracle.dfjk import coeffs_from_cumulant
+    Delta, Pi = delta_pi(n, members, functional)
+    return coeffs_from_cumulant(n, Delta, Pi)
+
+
+def energy_of_n(n, hdiag, J, K, members, functional):
+    """Eq. (PNOF) at fixed h, J, K as a function of the occupations."""
+    cJ, cK = coefficients(n, members, functional)
+    return float(2.0 * np.dot(n, hdiag) + np.sum(cJ * J) - np.sum(cK * K))
+
+
+def denergy_dn(n, hdiag, J, K, members, functional, nfloor=1e-300):
+    """dE/dn_r, differentiated by hand from the coefficient definitions."""
+    M = 2.0 * J - K
+    g = 2.0 * hdiag + 2.0 * (M @ n)                     # HF-like part, all pairs
+    if functional == "hf":
+        return g
+    grp, strong = group_of(len(n), members)
+    for row in members:
+        for r in row:
+            # remove the intra-subspace (and diagonal) pairs from the HF-like part
+            for q in row:
+                g[r] -= 2.0 * n[q] * M[r, q]
+            # diagonal: -cK_rr K_rr with cK_rr = -n_r  ->  + n_r J_rr
+            g[r] += J[r, r]
+            # intra-subspace exchange: -sum_{q != r} cK_rq K_rq, cK_rq = -Pi_rq
+            for q in row:
+                if q == r:
+                    continue
+                sgn = -1.0 if (strong[r] or strong[q]) else 1.0
+                g[r] += sgn * 0.5 * np.sqrt(n[q] / max(n[r], nfloor)) * K[r, q] * 2.0
+    return g

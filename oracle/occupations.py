@@ -1,0 +1,177 @@
+"""Occupation-number (ON) mappings and optimisation (Occupation Number
+Optimization section).
+
+The ONs of each subspace Omega_g (one strong orbital g, N_g weak orbitals) are
+expressed through N_g unconstrained variables so that the pairing sum rule of
+Eq. (sum1), n_g + sum_i n_{p_i} = 1, and 0 <= n <= 1 hold automatically:
+
+trigonometric:  n_g = (1 + cos^2 gamma_g) / 2, hole h_g = 1 - n_g,
+                n_{p_i} = h_g cos^2 theta_1 ... cos^2 theta_{i-1} sin^2 theta_i (i < N_g),
+                n_{p_Ng} = h_g cos^2 theta_1 ... cos^2 theta_{Ng-1};
+                variables per subspace: (gamma_g, theta_1 .. theta_{Ng-1}).
+softmax:        n_g = 1 / (1 + sum_k exp(gamma_k)), n_{p_i} = n_g exp(gamma_i);
+                variables per subspace: (gamma_1 .. gamma_Ng).
+
+gamma is stored (ns, ng).  The optimiser (parity reference for the GPU) is a
+limited-memory BFGS with a backtracking Armijo line search.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import functionals
+
+
+def occupations(gamma, members, norb, mapping):
+    gamma = np.asarray(gamma, dtype=np.float64)
+    ns, ng = gamma.shape
+    n = np.zeros(norb)
+    for g in range(ns):
+        row = members[g]
+        if mapping == "trig":
+            ng_ = 0.5 * (1.0 + np.cos(gamma[g, 0]) ** 2)
+            hole = 1.0 - ng_
+            n[row[0]] = ng_
+            P = 1.0
+            for i in range(1, ng):
+                th = gamma[g, i]
+                n[row[i]] = hole * P * np.sin(th) ** 2
+                P *= np.cos(th) ** 2
+            n[row[ng]] = hole * P
+        elif mapping == "softmax":
+            e = np.exp(gamma[g])
+            ng_ = 1.0 / (1.0 + e.sum())
+            n[row[0]] = ng_
+            n[row[1:]] = ng_ * e
+        else:
+            raise ValueError(mapping)
+    return n
+
+
+def chain_rule(gamma, members, norb, mapping, dEdn):
+    """dE/dgamma from dE/dn through the mapping's Jacobian (written out)."""
+    gamma = np.asarray(gamma, dtype=np.float64)
+    ns, ng = gamma.shape
+    out = np.zeros_like(gamma)
+    n = occupations(gamma, members, norb, mapping)
+    for g in range(ns):
+        row = members[g]
+        gn = dEdn[row]
+        if mapping == "softmax":
+            nn_ = n[row]
+            gbar = np.dot(gn, nn_)
+            out[g] = nn_[1:] * (gn[1:] - gbar)
+            continue
+        cg, sg = np.cos(gamma[g, 0]), np.sin(gamma[g, 0])
+        hole = 1.0 - 0.5 * (1.0 + cg * cg)
+        # weak part: n_{p_i} = hole * Pprev_i * t_i
+        c = np.cos(gamma[g, 1:]); s = np.sin(gamma[g, 1:])
+        t = np.append(s * s, 1.0)                     # t_i, i = 1..ng
+        Pprev = np.ones(ng)                           # prod_{l < i} c_l^2
+        for i in range(1, ng):
+            Pprev[i] = Pprev[i - 1] * c[i - 1] ** 2
+        gw = gn[1:]
+        dE_dhole = float(np.sum(gw * Pprev * t))
+        out[g, 0] = cg * sg * (dE_dhole - gn[0])
+        # theta_j (j = 1..ng-1): reverse accumulation
+        R = gw[ng - 1]                                # R_{ng-1} = g_ng
+        for j in range(ng - 1, 0, -1):                # j = ng-1 .. 1
+            out[g, j] = 2.0 * s[j - 1] * c[j - 1] * hole * Pprev[j - 1] * (gw[j - 1] - R)
+            R = gw[j - 1] * t[j - 1] + c[j - 1] ** 2 * R
+    return out
+
+
+def energy_and_grad(gamma, members, norb, mapping, hdiag, J, K, functional):
+    n = occupations(gamma, members, norb, mapping)
+    E = functionals.energy_of_n(n, hdiag, J, K, members, functional)
+    dn = functionals.denergy_dn(n, hdiag, J, K, members, functional)
+    return E, chain_rule(gamma, members, norb, mapping, dn), n
+
+
+def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxit=2000,
+                   tol=1e-8, etol=1e-14, memory=8, c1=1e-4, max_backtrack=50, step0=0.1):
+    """Limited-memory BFGS (Nocedal, Math. Comp. 35 (1980)): two-loop recursion
+    over the last `memory` (s, y) pairs with initial scaling s.y / y.y, then a
+    backtracking Armijo line search from step 1 (from `step0` / max|g| on the
+    first iteration or after a reset).  Pairs with s.y <= 0 are skipped; a
+    non-descent direction resets the memory.  Converged when max|dE/dgamma| <=
+    tol, or when two consecutive steps change E by at most etol * max(1, |E|)
+    (the FP64 floor of the energy, like an energy threshold NTHRESHE).
+
+    Returns (gamma, n, E, iterations, converged)."""
+    shape = np.shape(gamma0)
+    x = np.array(gamma0, dtype=np.float64).ravel()
+
+    def f(v):
+        E, g, n = energy_and_grad(v.reshape(shape), members, norb, mapping, hdiag, J, K, functional)
+        return E, g.ravel(), n
+
+    E, g, n = f(x)
+    S, Y = [], []
+    it = 0
+    flat = 0
+    while it < maxit and np.max(np.abs(g)) > tol and flat < 2:
+        q = g.copy()
+        al = []
+        for s_, y_ in zip(reversed(S), reversed(Y)):
+            a = np.dot(s_, q) / np.dot(s_, y_)
+            al.append(a)
+            q = q - a * y_
+        if S:
+            r = q * (np.dot(S[-1], Y[-1]) / np.dot(Y[-1], Y[-1]))
+        else:
+            r = q * (step0 / np.max(np.abs(g)))
+        for (s_, y_), a in zip(zip(S, Y), reversed(al)):
+            bcoef = np.dot(y_, r) / np.dot(s_, y_)
+            r = r + s_ * (a - bcoef)
+        d = -r
+        gd = float(np.dot(g, d))
+        if not gd < 0.0:
+            S, Y = [], []
+            d = -g * (step0 / np.max(np.abs(g)))
+            gd = float(np.dot(g, d))
+        t = 1.0
+        for _ in range(max_backtrack):
+            xt = x + t * d
+            Et, gt, nt = f(xt)
+            if Et <= E + c1 * t * gd:
+                break
+            t *= 0.5
+        s_ = xt - x
+        y_ = gt - g
+        if np.dot(s_, y_) > 0.0:
+            S.append(s_); Y.append(y_)
+            if len(S) > memory:
+                S.pop(0); Y.pop(0)
+        flat = flat + 1 if abs(Et - E) <= etol * max(1.0, abs(E)) else 0
+        x, E, g, n = xt, Et, gt, nt
+        it += 1
+    return x.reshape(shape), n, E, it, bool(np.max(np.abs(g)) <= tol or flat >= 2)
+
+
+def aufbau_members(hdiag, ns, ng):
+    """Orbital roles from the one-electron energies: the ns lowest h_pp are the
+    strong orbitals (ascending), the next ns*ng the weak ones, paired in the
+    mirrored order of the pairing figure."""
+    order = np.argsort(hdiag, kind="stable")
+    members = np.zeros((ns, ng + 1), dtype=np.int64)
+    for g in range(ns):
+        members[g, 0] = order[g]
+        for i in range(ng):
+            members[g, 1 + i] = order[ns + (ns - 1 - g) + i * ns]
+    return members
+
+
+def inverse_trig(n, members, ng):
+    """gamma with occupations(gamma) = n for a feasible n (n_g >= 1/2)."""
+    gamma = np.zeros((len(members), ng))
+    for g, row in enumerate(members):
+        ngv = n[row[0]]
+        gamma[g, 0] = np.arccos(np.sqrt(np.clip(2.0 * ngv - 1.0, 0.0, 1.0)))
+        hole = 1.0 - ngv
+        rem = hole
+        for i in range(1, ng):
+            frac = n[row[i]] / rem if rem > 0 else 0.0
+            gamma[g, i] = np.arcsin(np.sqrt(np.clip(frac, 0.0, 1.0)))
+            rem -= n[row[i]]
+    return gamma

@@ -1,0 +1,121 @@
+"""Pins of the occupation mappings, the functional's dE/dn and the ON optimiser."""
+import numpy as np
+import pytest
+
+from oracle import dfjk, functionals, occupations
+from paper_2512_13550_amd import inputs
+
+
+def members_of(ns, ng, norb=None):
+    norb = ns * (ng + 1) if norb is None else norb
+    return np.array(inputs.pairing(norb, ns, ng)), norb
+
+
+@pytest.mark.parametrize("mapping", ["trig", "softmax"])
+@pytest.mark.parametrize("ng", [1, 2, 3, 5])
+def test_sum_rule_and_bounds(mapping, ng):
+    ns = 7
+    members, norb = members_of(ns, ng)
+    rng = np.random.default_rng(ng)
+    for _ in range(20):
+        gamma = rng.uniform(-4, 4, (ns, ng))
+        n = occupations.occupations(gamma, members, norb, mapping)
+        for row in members:
+            assert abs(n[row].sum() - 1.0) < 1e-14
+        assert np.all(n >= 0) and np.all(n <= 1)
+        if mapping == "trig":
+            assert np.all(n[members[:, 0]] >= 0.5 - 1e-15)
+        else:
+            assert np.all(n > 0)
+
+
+def test_trig_inverse_roundtrip():
+    ns, ng = 6, 3
+    members, norb = members_of(ns, ng)
+    rng = np.random.default_rng(3)
+    gamma = rng.uniform(0.05, 1.5, (ns, ng))
+    n = occupations.occupations(gamma, members, norb, "trig")
+    g2 = occupations.inverse_trig(n, members, ng)
+    assert np.allclose(occupations.occupations(g2, members, norb, "trig"), n, atol=1e-14)
+
+
+def _jk(norb, seed):
+    B = inputs.make_B(seed, norb, 3 * norb, 4.0, threads=1)
+    C = inputs.make_C(seed, norb, norb)
+    H = inputs.make_H(seed, norb)
+    b, _ = dfjk.mo_transform(B, C)
+    J, K = dfjk.jk(b)
+    return np.diag(dfjk.one_electron(H, C)).copy(), J, K
+
+
+@pytest.mark.parametrize("functional", ["hf", "pnof5"])
+def test_dEdn_against_finite_differences(functional):
+    ns, ng = 3, 2
+    members, norb = members_of(ns, ng)
+    hd, J, K = _jk(norb, 1)
+    rng = np.random.default_rng(0)
+    n = rng.uniform(0.05, 0.9, norb)
+    g = functionals.denergy_dn(n, hd, J, K, members, functional)
+    eps = 1e-6
+    for r in range(norb):
+        e = np.zeros(norb); e[r] = eps
+        fd = (functionals.energy_of_n(n + e, hd, J, K, members, functional)
+              - functionals.energy_of_n(n - e, hd, J, K, members, functional)) / (2 * eps)
+        assert abs(fd - g[r]) < 1e-7 * max(1.0, abs(g[r]))
+
+
+@pytest.mark.parametrize("mapping", ["trig", "softmax"])
+@pytest.mark.parametrize("functional", ["hf", "pnof5"])
+def test_dEdgamma_against_finite_differences(mapping, functional):
+    ns, ng = 3, 3
+    members, norb = members_of(ns, ng)
+    hd, J, K = _jk(norb, 2)
+    rng = np.random.default_rng(1)
+    gamma = rng.uniform(0.2, 1.3, (ns, ng))
+    _, grad, _ = occupations.energy_and_grad(gamma, members, norb, mapping, hd, J, K, functional)
+    eps = 1e-6
+    for g in range(ns):
+        for i in range(ng):
+            d = np.zeros_like(gamma); d[g, i] = eps
+            Ep = occupations.energy_and_grad(gamma + d, members, norb, mapping, hd, J, K, functional)[0]
+            Em = occupations.energy_and_grad(gamma - d, members, norb, mapping, hd, J, K, functional)[0]
+            assert abs((Ep - Em) / (2 * eps) - grad[g, i]) < 1e-7 * max(1.0, abs(grad[g, i]))
+
+
+def test_two_electron_two_orbital_exact_minimum():
+    """One electron pair in two orbitals: the PNOF5 energy at its minimum over
+    the trigonometric variable is the lower eigenvalue of the 2x2 problem
+    [[a, -K], [-K, b]] with a = 2h_gg + J_gg, b = 2h_pp + J_pp (all PNOFs are
+    exact for two electrons)."""
+    members = np.array([[0, 1]])
+    for seed in range(5):
+        hd, J, K = _jk(2, 10 + seed)
+        a, b = 2 * hd[0] + J[0, 0], 2 * hd[1] + J[1, 1]
+        if a > b:      # the strong orbital must be the lower one for n_g >= 1/2
+            hd = hd[::-1].copy(); J = J[::-1, ::-1].copy(); K = K[::-1, ::-1].copy()
+            a, b = b, a
+        exact = 0.5 * (a + b) - np.sqrt(0.25 * (a - b) ** 2 + K[0, 1] ** 2)
+        x, n, E, it, ok = occupations.optimize_lbfgs(np.array([[0.3]]), members, 2, "trig", hd, J, K,
+                                                  "pnof5", tol=1e-10, maxit=2000)
+        assert ok
+        assert abs(E - exact) < 1e-12 * max(1.0, abs(exact))
+
+
+@pytest.mark.parametrize("mapping", ["trig", "softmax"])
+def test_optimizer_reaches_a_stationary_minimum(mapping):
+    from scipy.optimize import minimize
+    ns, ng = 4, 3
+    norb = ns * (ng + 1)
+    hd, J, K = _jk(norb, 5)
+    members = occupations.aufbau_members(hd, ns, ng)
+    x0 = np.full((ns, ng), 0.3 if mapping == "trig" else -3.0)
+    x, n, E, it, ok = occupations.optimize_lbfgs(x0, members, norb, mapping, hd, J, K, "pnof5",
+                                              tol=1e-8, maxit=5000)
+    assert ok, it
+    f = lambda v: occupations.energy_and_grad(v.reshape(ns, ng), members, norb, mapping, hd, J, K, "pnof5")[0]
+    jac = lambda v: occupations.energy_and_grad(v.reshape(ns, ng), members, norb, mapping, hd, J, K, "pnof5")[1].ravel()
+    res = minimize(f, x0.ravel(), jac=jac, method="L-BFGS-B", options=dict(gtol=1e-11, ftol=1e-15, maxiter=10000))
+    # an independent library optimiser from the same start finds no lower energy,
+    # and the gradient vanishes at the returned point
+    assert E <= res.fun + 1e-9 * max(1.0, abs(E))
+    assert np.max(np.abs(jac(x.ravel()))) < 1e-6
