@@ -89,14 +89,16 @@ def energy_and_grad(gamma, members, norb, mapping, hdiag, J, K, functional):
 
 
 def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxit=2000,
-                   tol=1e-8, etol=1e-14, memory=8, c1=1e-4, max_backtrack=50, step0=0.1):
+                   tol=1e-8, etol=1e-14, loose=1e-5, memory=8, c1=1e-4, max_backtrack=50,
+                   step0=0.1):
     """Limited-memory BFGS (Nocedal, Math. Comp. 35 (1980)): two-loop recursion
     over the last `memory` (s, y) pairs with initial scaling s.y / y.y, then a
     backtracking Armijo line search from step 1 (from `step0` / max|g| on the
     first iteration or after a reset).  Pairs with s.y <= 0 are skipped; a
-    non-descent direction resets the memory.  Converged when max|dE/dgamma| <=
-    tol, or when two consecutive steps change E by at most etol * max(1, |E|)
-    (the FP64 floor of the energy, like an energy threshold NTHRESHE).
+    non-descent direction, or a line search that needed half of its halvings,
+    resets the memory.  Converged when max|dE/dgamma| <= tol, or when
+    max|dE/dgamma| <= loose and two consecutive steps change E by at most
+    etol * max(1, |E|) (the FP64 floor of the energy).
 
     Returns (gamma, n, E, iterations, converged)."""
     shape = np.shape(gamma0)
@@ -131,7 +133,8 @@ def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxi
             d = -g * (step0 / np.max(np.abs(g)))
             gd = float(np.dot(g, d))
         t = 1.0
-        for _ in range(max_backtrack):
+        nb = 0
+        for nb in range(max_backtrack):
             xt = x + t * d
             Et, gt, nt = f(xt)
             if Et <= E + c1 * t * gd:
@@ -139,11 +142,14 @@ def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxi
             t *= 0.5
         s_ = xt - x
         y_ = gt - g
-        if np.dot(s_, y_) > 0.0:
+        if nb >= max_backtrack // 2:
+            S, Y = [], []                      # poor direction: restart the memory
+        elif np.dot(s_, y_) > 0.0:
             S.append(s_); Y.append(y_)
             if len(S) > memory:
                 S.pop(0); Y.pop(0)
-        flat = flat + 1 if abs(Et - E) <= etol * max(1.0, abs(E)) else 0
+        small = np.max(np.abs(gt)) <= loose
+        flat = flat + 1 if (small and abs(Et - E) <= etol * max(1.0, abs(E))) else 0
         x, E, g, n = xt, Et, gt, nt
         it += 1
     return x.reshape(shape), n, E, it, bool(np.max(np.abs(g)) <= tol or flat >= 2)

@@ -108,6 +108,7 @@ def test_optimizer_reaches_a_stationary_minimum(mapping):
     norb = ns * (ng + 1)
     hd, J, K = _jk(norb, 5)
     members = occupations.aufbau_members(hd, ns, ng)
+    hd[members[:, 0]] -= 1.0          # occupied/virtual gap of the synthetic ON instance
     x0 = np.full((ns, ng), 0.3 if mapping == "trig" else -3.0)
     x, n, E, it, ok = occupations.optimize_lbfgs(x0, members, norb, mapping, hd, J, K, "pnof5",
                                               tol=1e-8, maxit=5000)
