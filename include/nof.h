@@ -208,6 +208,54 @@ int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, dou
 int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double lr,
                   double beta1, double beta2, double eps, double* y, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Occupation-number update at fixed orbitals, FP64 (Occupation Number
+ * Optimization; orbital-pairing structure of Eq. OmegaG and sum rule Eq. sum1).
+ *
+ * members  [ns][ng+1] int, device: subspace g lists its strongly occupied
+ *          orbital first, then its ng weak orbitals (distinct, < norb).
+ *          Orbitals in no subspace have n = 0.  Out-of-range entries are
+ *          detected on the device: info[2] = NOF_E_ARG and nothing else is
+ *          written.
+ * map      NOF_MAP_TRIG: n_g = (1 + cos^2 x_g)/2, n_{p_i} = h_g prod_{j<i}
+ *          cos^2 x_j sin^2 x_i, the last weak orbital takes the rest;
+ *          NOF_MAP_SOFTMAX: n_g = 1/(1 + sum_k e^{x_k}), n_{p_i} = n_g e^{x_i}.
+ * gamma    [ns][ng] variables (trig: x_g then x_1..x_{ng-1}; softmax x_1..x_ng).
+ * func     NOF_FUNC_HF (Delta = Pi = 0) or NOF_FUNC_PNOF5 (independent pairs:
+ *          Delta_pq = n_p n_q and Pi_pq = -+sqrt(n_p n_q) within a subspace,
+ *          Pi_pp = n_p; see nof_functional_coeffs).
+ * hdiag    h_pp = hdiag[p * hstride] (hstride = norb + 1 reads the diagonal of
+ *          a full h).  J, K [norb][norb] FP64.
+ * E = 2 sum_p n_p h_pp + sum_pq cJ(n)_pq J_pq - sum_pq cK(n)_pq K_pq.
+ *
+ * nof_occ_energy_grad: n [norb], E (scalar), dEdgamma [ns][ng]; any output may
+ *   be NULL.
+ * nof_occ_optimize: L-BFGS (memory 8, two-loop recursion, Armijo backtracking
+ *   from step 1, initial step 0.1/max|g|) on gamma in place, in one
+ *   workgroup with no host round trip.  Stops when max|dE/dgamma| <= tol, or
+ *   when max|dE/dgamma| <= 1e-5 and two consecutive steps change E by at
+ *   most 1e-14 max(1,|E|), or after maxit iterations.  info[0] = iterations,
+ *   info[1] = 1 if converged, info[2] = 0 or a device-detected status.
+ * nof_functional_coeffs: cJ = 2(nn^T - Delta), cK = nn^T - Delta - Pi for
+ *   the functional (Eq. PNOF coefficients for the NO step); info may be NULL.
+ * ws: nof_occ_ws() bytes (all three calls).
+ * ------------------------------------------------------------------------- */
+typedef enum { NOF_MAP_TRIG = 0, NOF_MAP_SOFTMAX = 1 } nof_map;
+typedef enum { NOF_FUNC_HF = 0, NOF_FUNC_PNOF5 = 1 } nof_functional;
+size_t nof_occ_ws(int norb, int ns, int ng);
+int nof_occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int func,
+                        const double* gamma, const double* hdiag, int hstride,
+                        const double* J, const double* K, double* n, double* E,
+                        double* dEdgamma, int* info, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+int nof_occ_optimize(int norb, int ns, int ng, const int* members, int map, int func,
+                     const double* hdiag, int hstride, const double* J, const double* K,
+                     double* gamma, double* n, double* E, int* info, int maxit, double tol,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func,
+                          const double* n, double* cJ, double* cK, int* info, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -366,4 +366,57 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
   });
 }
 
+namespace {
+bool occ_args_ok(int norb, int ns, int ng, int map, int func) {
+  if (!dim_ok(norb) || ns < 1 || ng < 1 || (long long)ns * (ng + 1) > norb) return false;
+  if (map != NOF_MAP_TRIG && map != NOF_MAP_SOFTMAX) return false;
+  if (func != NOF_FUNC_HF && func != NOF_FUNC_PNOF5) return false;
+  return true;
+}
+}  // namespace
+
+size_t nof_occ_ws(int norb, int ns, int ng) {
+  if (!dim_ok(norb) || ns < 1 || ng < 1 || (long long)ns * (ng + 1) > norb) return 0;
+  return occ_ws(norb, ns, ng);
+}
+
+int nof_occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int func,
+                        const double* gamma, const double* hdiag, int hstride, const double* J,
+                        const double* K, double* n, double* E, double* dEdgamma, int* info,
+                        void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!occ_args_ok(norb, ns, ng, map, func)) return NOF_E_DIM;
+    if (hstride < 1) return NOF_E_ARG;
+    if (!members || !gamma || !hdiag || !J || !K) return NOF_E_NULL;
+    if (!ws || ws_bytes < occ_ws(norb, ns, ng)) return NOF_E_WORKSPACE;
+    return occ_energy_grad(norb, ns, ng, members, map, func, gamma, hdiag, hstride, J, K, n, E,
+                           dEdgamma, info, ws, stream);
+  });
+}
+
+int nof_occ_optimize(int norb, int ns, int ng, const int* members, int map, int func,
+                     const double* hdiag, int hstride, const double* J, const double* K,
+                     double* gamma, double* n, double* E, int* info, int maxit, double tol,
+                     void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!occ_args_ok(norb, ns, ng, map, func)) return NOF_E_DIM;
+    if (hstride < 1 || maxit < 0 || !(tol >= 0.0)) return NOF_E_ARG;
+    if (!members || !gamma || !hdiag || !J || !K) return NOF_E_NULL;
+    if (!ws || ws_bytes < occ_ws(norb, ns, ng)) return NOF_E_WORKSPACE;
+    return occ_optimize(norb, ns, ng, members, map, func, hdiag, hstride, J, K, gamma, n, E, info,
+                        maxit, tol, ws, stream);
+  });
+}
+
+int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func, const double* n,
+                          double* cJ, double* cK, int* info, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!occ_args_ok(norb, ns, ng, NOF_MAP_TRIG, func)) return NOF_E_DIM;
+    if (!members || !n || !cJ || !cK) return NOF_E_NULL;
+    if (!ws || ws_bytes < occ_ws(norb, ns, ng)) return NOF_E_WORKSPACE;
+    return functional_coeffs(norb, ns, ng, members, func, n, cJ, cK, ws, info, stream);
+  });
+}
+
 }  // extern "C"

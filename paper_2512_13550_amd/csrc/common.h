@@ -114,6 +114,19 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st)
 int adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
               double beta2, double eps, double* y, hipStream_t st);
 
+// Occupation update (occupations.hip).
+size_t occ_ws(int norb, int ns, int ng);
+int occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int func,
+                    const double* gamma, const double* hdiag, int hstride, const double* J,
+                    const double* K, double* n, double* E, double* dEdgamma, int* info, void* ws,
+                    hipStream_t st);
+int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func,
+                 const double* hdiag, int hstride, const double* J, const double* K,
+                 double* gamma, double* n, double* E, int* info, int maxit, double tol, void* ws,
+                 hipStream_t st);
+int functional_coeffs(int norb, int ns, int ng, const int* members, int func, const double* n,
+                      double* cJ, double* cK, void* ws, int* bad, hipStream_t st);
+
 int coeffs_from_cumulant(int norb, const double* n, const double* Delta,
                          const double* Pi, double* cJ, double* cK, hipStream_t st);
 

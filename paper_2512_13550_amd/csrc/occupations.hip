@@ -1,0 +1,478 @@
+// Occupation-number optimisation at fixed natural orbitals, FP64 (Occupation
+// Number Optimization section): the ONs of each subspace Omega_g (one strong
+// orbital and N_g weak ones, pairing sum rule of Eq. sum1) are generated from
+// unconstrained variables by the trigonometric or the softmax mapping, the
+// energy of Eq. (PNOF) is evaluated from h_pp, J and K with the coefficients of
+// the chosen functional, and an L-BFGS iteration (two-loop recursion, Armijo
+// backtracking) minimises it.
+//
+// The whole optimisation runs in one workgroup of 1024 threads (16 waves):
+// every function evaluation is a matrix-vector product with M = 2J - K (one
+// wave per row, lanes striding the row, butterfly reduction) plus per-orbital
+// and per-subspace work; vectors live in the caller's workspace (L2 resident)
+// and every reduction uses a fixed tree, so runs repeat bit for bit.  The
+// loop needs no host round trip.
+#include <math.h>
+
+#include "common.h"
+
+namespace nof {
+namespace {
+
+constexpr int OT = 1024;       // threads of the optimiser workgroup
+constexpr int OW = OT / 64;    // waves
+constexpr int LM = 8;          // L-BFGS memory
+
+struct OccProblem {
+  int norb, ns, ng, map, func;
+  const int* members;          // [ns][ng+1]
+  const double* hdiag; int hstride;
+  const double* J; const double* K;
+  const double* M;             // 2J - K (workspace)
+  int* grp;                    // [norb] subspace of each orbital, -1 if none
+  int* pos;                    // [norb] position inside the subspace (0 = strong)
+};
+
+struct OccWs {
+  double *x, *g, *d, *xt, *gt, *S, *Y, *n, *nt, *dn, *v, *sy, *yy;
+  int *grp, *pos;
+  double* M;
+};
+
+// Workspace layout (all sub-buffers 256-byte aligned).
+struct OccLayout {
+  size_t off[16];
+  size_t total;
+};
+OccLayout occ_layout(int norb, int ns, int ng) {
+  OccLayout L;
+  const size_t nv = (size_t)ns * ng;
+  const size_t sz[16] = {(size_t)norb * norb * 8, nv * 8, nv * 8, nv * 8, nv * 8, nv * 8,
+                         LM * nv * 8, LM * nv * 8, (size_t)norb * 8, (size_t)norb * 8,
+                         (size_t)norb * 8, (size_t)norb * 8, LM * 8, LM * 8,
+                         (size_t)norb * 4, (size_t)norb * 4};
+  size_t o = 0;
+  for (int i = 0; i < 16; ++i) {
+    L.off[i] = o;
+    o = align256(o + sz[i]);
+  }
+  L.total = o;
+  return L;
+}
+OccWs occ_ws_ptrs(void* ws, int norb, int ns, int ng) {
+  const OccLayout L = occ_layout(norb, ns, ng);
+  char* b = (char*)ws;
+  OccWs w;
+  w.M = (double*)(b + L.off[0]);
+  w.x = (double*)(b + L.off[1]);
+  w.g = (double*)(b + L.off[2]);
+  w.d = (double*)(b + L.off[3]);
+  w.xt = (double*)(b + L.off[4]);
+  w.gt = (double*)(b + L.off[5]);
+  w.S = (double*)(b + L.off[6]);
+  w.Y = (double*)(b + L.off[7]);
+  w.n = (double*)(b + L.off[8]);
+  w.nt = (double*)(b + L.off[9]);
+  w.dn = (double*)(b + L.off[10]);
+  w.v = (double*)(b + L.off[11]);
+  w.sy = (double*)(b + L.off[12]);
+  w.yy = (double*)(b + L.off[13]);
+  w.grp = (int*)(b + L.off[14]);
+  w.pos = (int*)(b + L.off[15]);
+  return w;
+}
+
+// ---- block-wide deterministic reductions -----------------------------------
+__device__ double block_sum(double a, double* red) {
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = OT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ double block_max(double a, double* red) {
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = OT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ double dot(const double* a, const double* b, int n, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += OT) s = fma(a[i], b[i], s);
+  return block_sum(s, red);
+}
+
+// ---- the mapping ------------------------------------------------------------
+// n for subspace g from its variables x[g*ng ..]; writes n[members]
+__device__ void map_group(const OccProblem& P, const double* x, double* n, int g) {
+  const int* row = P.members + (long long)g * (P.ng + 1);
+  const double* xg = x + (long long)g * P.ng;
+  if (P.map == NOF_MAP_TRIG) {
+    const double c = cos(xg[0]);
+    const double ngv = 0.5 * (1.0 + c * c);
+    const double hole = 1.0 - ngv;
+    n[row[0]] = ngv;
+    double Pp = 1.0;
+    for (int i = 1; i < P.ng; ++i) {
+      const double s = sin(xg[i]), ci = cos(xg[i]);
+      n[row[i]] = hole * Pp * s * s;
+      Pp *= ci * ci;
+    }
+    n[row[P.ng]] = hole * Pp;
+  } else {
+    double sum = 0.0;
+    for (int i = 0; i < P.ng; ++i) sum += exp(xg[i]);
+    const double ngv = 1.0 / (1.0 + sum);
+    n[row[0]] = ngv;
+    for (int i = 0; i < P.ng; ++i) n[row[1 + i]] = ngv * exp(xg[i]);
+  }
+}
+
+// dE/dx for subspace g from dE/dn (chain rule through the mapping)
+__device__ void chain_group(const OccProblem& P, const double* x, const double* n,
+                            const double* dn, double* gx, int g) {
+  const int* row = P.members + (long long)g * (P.ng + 1);
+  const double* xg = x + (long long)g * P.ng;
+  double* og = gx + (long long)g * P.ng;
+  const int ng = P.ng;
+  if (P.map == NOF_MAP_SOFTMAX) {
+    double gbar = 0.0;
+    for (int i = 0; i <= ng; ++i) gbar += dn[row[i]] * n[row[i]];
+    for (int i = 0; i < ng; ++i) og[i] = n[row[1 + i]] * (dn[row[1 + i]] - gbar);
+    return;
+  }
+  const double cg = cos(xg[0]), sg = sin(xg[0]);
+  const double hole = 1.0 - 0.5 * (1.0 + cg * cg);
+  // n_{p_i} = hole * Pprev_i * t_i,  i = 1..ng (Pprev_1 = 1, t_ng = 1)
+  double dE_dhole = 0.0;
+  double Pp = 1.0;
+  for (int i = 1; i <= ng; ++i) {
+    const double t = i < ng ? sin(xg[i]) * sin(xg[i]) : 1.0;
+    dE_dhole += dn[row[i]] * Pp * t;
+    if (i < ng) Pp *= cos(xg[i]) * cos(xg[i]);
+  }
+  og[0] = cg * sg * (dE_dhole - dn[row[0]]);
+  // reverse accumulation over theta_j, j = ng-1 .. 1
+  double R = dn[row[ng]];
+  for (int j = ng - 1; j >= 1; --j) {
+    double Pj = 1.0;                          // prod_{l < j} cos^2 theta_l
+    for (int l = 1; l < j; ++l) Pj *= cos(xg[l]) * cos(xg[l]);
+    const double s = sin(xg[j]), c = cos(xg[j]);
+    og[j] = 2.0 * s * c * hole * Pj * (dn[row[j]] - R);
+    R = dn[row[j]] * s * s + c * c * R;
+  }
+}
+
+// ---- one function evaluation: E(x), n(x), dE/dx ----------------------------
+__device__ double evaluate(const OccProblem& P, const double* x, double* n, double* dn,
+                           double* v, double* gx, double* red) {
+  const int tid = threadIdx.x;
+  for (int r = tid; r < P.norb; r += OT) n[r] = 0.0;
+  __syncthreads();
+  for (int g = tid; g < P.ns; g += OT) map_group(P, x, n, g);
+  __syncthreads();
+  // v = M n, one wave per row
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int r = wv; r < P.norb; r += OW) {
+    const double* Mr = P.M + (long long)r * P.norb;
+    double s = 0.0;
+    for (int q = lane; q < P.norb; q += 64) s = fma(Mr[q], n[q], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) v[r] = s;
+  }
+  __syncthreads();
+  double e = 0.0;
+  for (int r = tid; r < P.norb; r += OT) {
+    const double hr = P.hdiag[(long long)r * P.hstride];
+    const double nr = n[r];
+    double d = 2.0 * hr + 2.0 * v[r];
+    e += 2.0 * nr * hr + nr * v[r];
+    const int g = P.grp[r];
+    if (P.func == NOF_FUNC_PNOF5 && g >= 0) {
+      const int* row = P.members + (long long)g * (P.ng + 1);
+      const bool rstrong = P.pos[r] == 0;
+      const double Jrr = P.J[(long long)r * P.norb + r];
+      d += Jrr;
+      e += nr * Jrr;
+      for (int i = 0; i <= P.ng; ++i) {
+        const int q = row[i];
+        const double nq = n[q];
+        const double Mrq = P.M[(long long)r * P.norb + q];
+        d -= 2.0 * nq * Mrq;
+        e -= nr * nq * Mrq;
+        if (q != r) {
+          const double sgn = (rstrong || i == 0) ? -1.0 : 1.0;
+          const double Krq = P.K[(long long)r * P.norb + q];
+          d += sgn * sqrt(nq / fmax(nr, 1e-300)) * Krq;
+          e += sgn * sqrt(nr * nq) * Krq;
+        }
+      }
+    }
+    dn[r] = d;
+  }
+  const double E = block_sum(e, red);
+  for (int g = tid; g < P.ns; g += OT) chain_group(P, x, n, dn, gx, g);
+  __syncthreads();
+  return E;
+}
+
+__device__ bool setup(OccProblem& P, OccWs& w, int* info, double* red) {
+  const int tid = threadIdx.x;
+  P.grp = w.grp;
+  P.pos = w.pos;
+  for (int r = tid; r < P.norb; r += OT) { w.grp[r] = -1; w.pos[r] = -1; }
+  __syncthreads();
+  int bad = 0;
+  for (int g = tid; g < P.ns; g += OT)
+    for (int i = 0; i <= P.ng; ++i) {
+      const int q = P.members[(long long)g * (P.ng + 1) + i];
+      if (q < 0 || q >= P.norb) { bad = 1; continue; }
+      w.grp[q] = g;
+      w.pos[q] = i;
+    }
+  const double anybad = block_max((double)bad, red);
+  if (anybad > 0.0) {
+    if (tid == 0 && info) info[2] = NOF_E_ARG;
+    return false;
+  }
+  return true;
+}
+
+__global__ void k_build_M(long long n2, const double* __restrict__ J, const double* __restrict__ K,
+                          double* __restrict__ M) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x)
+    M[i] = 2.0 * J[i] - K[i];
+}
+
+__global__ __launch_bounds__(OT) void k_occ_eval(OccProblem P, OccWs w, const double* gamma,
+                                                 double* n_out, double* E_out, double* g_out,
+                                                 int* info) {
+  __shared__ double red[OT];
+  if (!setup(P, w, info, red)) return;
+  const double E = evaluate(P, gamma, w.n, w.dn, w.v, w.g, red);
+  const int nv = P.ns * P.ng;
+  for (int i = threadIdx.x; i < nv; i += OT) if (g_out) g_out[i] = w.g[i];
+  for (int r = threadIdx.x; r < P.norb; r += OT) if (n_out) n_out[r] = w.n[r];
+  if (threadIdx.x == 0) {
+    if (E_out) *E_out = E;
+    if (info) info[2] = 0;
+  }
+}
+
+struct LbfgsParams {
+  int maxit, maxbt;
+  double tol, etol, loose, c1, step0;
+};
+
+__global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsParams L,
+                                                  double* gamma, double* n_out, double* E_out,
+                                                  int* info) {
+  __shared__ double red[OT];
+  if (!setup(P, w, info, red)) return;
+  const int tid = threadIdx.x;
+  const int nv = P.ns * P.ng;
+  for (int i = tid; i < nv; i += OT) w.x[i] = gamma[i];
+  __syncthreads();
+  double E = evaluate(P, w.x, w.n, w.dn, w.v, w.g, red);
+  int it = 0, flat = 0, mcount = 0, head = 0;
+  double gmax = 0.0;
+  while (true) {
+    double gl = 0.0;
+    for (int i = tid; i < nv; i += OT) gl = fmax(gl, fabs(w.g[i]));
+    gmax = block_max(gl, red);
+    if (it >= L.maxit || gmax <= L.tol || flat >= 2) break;
+    // two-loop recursion: d = H g
+    for (int i = tid; i < nv; i += OT) w.d[i] = w.g[i];
+    __syncthreads();
+    double alph[LM];
+    for (int k = 0; k < mcount; ++k) {
+      const int idx = (head - 1 - k + LM) % LM;
+      const double a = dot(w.S + (long long)idx * nv, w.d, nv, red) / w.sy[idx];
+      alph[k] = a;
+      for (int i = tid; i < nv; i += OT) w.d[i] -= a * w.Y[(long long)idx * nv + i];
+      __syncthreads();
+    }
+    const double scale = mcount > 0 ? w.sy[(head - 1 + LM) % LM] / w.yy[(head - 1 + LM) % LM]
+                                    : L.step0 / gmax;
+    for (int i = tid; i < nv; i += OT) w.d[i] *= scale;
+    __syncthreads();
+    for (int k = mcount - 1; k >= 0; --k) {
+      const int idx = (head - 1 - k + LM) % LM;
+      const double bcoef = dot(w.Y + (long long)idx * nv, w.d, nv, red) / w.sy[idx];
+      for (int i = tid; i < nv; i += OT) w.d[i] += w.S[(long long)idx * nv + i] * (alph[k] - bcoef);
+      __syncthreads();
+    }
+    for (int i = tid; i < nv; i += OT) w.d[i] = -w.d[i];
+    __syncthreads();
+    double gd = dot(w.g, w.d, nv, red);
+    if (!(gd < 0.0)) {
+      mcount = 0;
+      for (int i = tid; i < nv; i += OT) w.d[i] = -w.g[i] * (L.step0 / gmax);
+      __syncthreads();
+      gd = dot(w.g, w.d, nv, red);
+    }
+    // backtracking Armijo line search
+    double t = 1.0, Et = 0.0;
+    int nb = 0;
+    for (nb = 0; nb < L.maxbt; ++nb) {
+      for (int i = tid; i < nv; i += OT) w.xt[i] = w.x[i] + t * w.d[i];
+      __syncthreads();
+      Et = evaluate(P, w.xt, w.nt, w.dn, w.v, w.gt, red);
+      if (Et <= E + L.c1 * t * gd) break;
+      t *= 0.5;
+    }
+    if (nb == L.maxbt) nb = L.maxbt - 1;
+    // new pair s = xt - x, y = gt - g into slot head
+    double* Sh = w.S + (long long)head * nv;
+    double* Yh = w.Y + (long long)head * nv;
+    for (int i = tid; i < nv; i += OT) {
+      Sh[i] = w.xt[i] - w.x[i];
+      Yh[i] = w.gt[i] - w.g[i];
+    }
+    __syncthreads();
+    if (nb >= L.maxbt / 2) {
+      mcount = 0;
+    } else {
+      const double sy = dot(Sh, Yh, nv, red);
+      if (sy > 0.0) {
+        const double yy = dot(Yh, Yh, nv, red);
+        if (tid == 0) { w.sy[head] = sy; w.yy[head] = yy; }
+        head = (head + 1) % LM;
+        mcount = mcount < LM ? mcount + 1 : LM;
+      }
+    }
+    double gl2 = 0.0;
+    for (int i = tid; i < nv; i += OT) gl2 = fmax(gl2, fabs(w.gt[i]));
+    const double gtmax = block_max(gl2, red);
+    const bool small = gtmax <= L.loose;
+    flat = (small && fabs(Et - E) <= L.etol * fmax(1.0, fabs(E))) ? flat + 1 : 0;
+    for (int i = tid; i < nv; i += OT) { w.x[i] = w.xt[i]; w.g[i] = w.gt[i]; }
+    for (int r = tid; r < P.norb; r += OT) w.n[r] = w.nt[r];
+    __syncthreads();
+    E = Et;
+    ++it;
+  }
+  for (int i = tid; i < nv; i += OT) gamma[i] = w.x[i];
+  for (int r = tid; r < P.norb; r += OT) if (n_out) n_out[r] = w.n[r];
+  if (tid == 0) {
+    if (E_out) *E_out = E;
+    if (info) {
+      info[0] = it;
+      info[1] = (gmax <= L.tol || flat >= 2) ? 1 : 0;
+      info[2] = 0;
+    }
+  }
+}
+
+// cJ = 2(nn^T - Delta), cK = nn^T - Delta - Pi for the HF-like or PNOF5 functional
+__global__ void k_func_coeffs(int norb, int ng, int func, const double* __restrict__ n,
+                              const int* __restrict__ grp, const int* __restrict__ pos,
+                              double* __restrict__ cJ, double* __restrict__ cK) {
+  const long long n2 = (long long)norb * norb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(i / norb), q = (int)(i - (long long)p * norb);
+    const double nn = n[p] * n[q];
+    double dl = 0.0, pi = 0.0;
+    if (func == NOF_FUNC_PNOF5 && grp[p] >= 0 && grp[p] == grp[q]) {
+      dl = nn;
+      if (p == q) pi = n[p];
+      else pi = ((pos[p] == 0 || pos[q] == 0) ? -1.0 : 1.0) * sqrt(nn);
+    }
+    cJ[i] = 2.0 * (nn - dl);
+    cK[i] = nn - dl - pi;
+  }
+}
+
+__global__ void k_group_index(int norb, int ns, int ng, const int* __restrict__ members,
+                              int* __restrict__ grp, int* __restrict__ pos, int* __restrict__ bad) {
+  // single block: clear, then fill
+  for (int r = threadIdx.x; r < norb; r += blockDim.x) { grp[r] = -1; pos[r] = -1; }
+  __syncthreads();
+  for (int g = threadIdx.x; g < ns; g += blockDim.x)
+    for (int i = 0; i <= ng; ++i) {
+      const int q = members[(long long)g * (ng + 1) + i];
+      if (q < 0 || q >= norb) {
+        if (bad) bad[2] = NOF_E_ARG;
+        continue;
+      }
+      grp[q] = g;
+      pos[q] = i;
+    }
+}
+
+OccProblem make_problem(int norb, int ns, int ng, const int* members, int map, int func,
+                        const double* hdiag, int hstride, const double* J, const double* K,
+                        const OccWs& w) {
+  OccProblem P;
+  P.norb = norb; P.ns = ns; P.ng = ng; P.map = map; P.func = func;
+  P.members = members; P.hdiag = hdiag; P.hstride = hstride; P.J = J; P.K = K;
+  P.M = w.M; P.grp = w.grp; P.pos = w.pos;
+  return P;
+}
+
+int build_M(int norb, const double* J, const double* K, double* M, hipStream_t st) {
+  const long long n2 = (long long)norb * norb;
+  long long g = (n2 + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_build_M, dim3((unsigned)g), dim3(256), 0, st, n2, J, K, M);
+  return launch_status();
+}
+
+}  // namespace
+
+size_t occ_ws(int norb, int ns, int ng) { return occ_layout(norb, ns, ng).total; }
+
+int occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int func,
+                    const double* gamma, const double* hdiag, int hstride, const double* J,
+                    const double* K, double* n, double* E, double* dEdgamma, int* info, void* ws,
+                    hipStream_t st) {
+  OccWs w = occ_ws_ptrs(ws, norb, ns, ng);
+  int rc = build_M(norb, J, K, w.M, st);
+  if (rc != NOF_OK) return rc;
+  OccProblem P = make_problem(norb, ns, ng, members, map, func, hdiag, hstride, J, K, w);
+  hipLaunchKernelGGL(k_occ_eval, dim3(1), dim3(OT), 0, st, P, w, gamma, n, E, dEdgamma, info);
+  return launch_status();
+}
+
+int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func,
+                 const double* hdiag, int hstride, const double* J, const double* K,
+                 double* gamma, double* n, double* E, int* info, int maxit, double tol, void* ws,
+                 hipStream_t st) {
+  OccWs w = occ_ws_ptrs(ws, norb, ns, ng);
+  int rc = build_M(norb, J, K, w.M, st);
+  if (rc != NOF_OK) return rc;
+  OccProblem P = make_problem(norb, ns, ng, members, map, func, hdiag, hstride, J, K, w);
+  LbfgsParams L;
+  L.maxit = maxit; L.maxbt = 50; L.tol = tol; L.etol = 1e-14; L.loose = 1e-5; L.c1 = 1e-4;
+  L.step0 = 0.1;
+  hipLaunchKernelGGL(k_occ_lbfgs, dim3(1), dim3(OT), 0, st, P, w, L, gamma, n, E, info);
+  return launch_status();
+}
+
+int functional_coeffs(int norb, int ns, int ng, const int* members, int func, const double* n,
+                      double* cJ, double* cK, void* ws, int* bad, hipStream_t st) {
+  OccWs w = occ_ws_ptrs(ws, norb, ns, ng);
+  hipLaunchKernelGGL(k_group_index, dim3(1), dim3(1024), 0, st, norb, ns, ng, members, w.grp,
+                     w.pos, bad);
+  int rc = launch_status();
+  if (rc != NOF_OK) return rc;
+  const long long n2 = (long long)norb * norb;
+  long long g = (n2 + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_func_coeffs, dim3((unsigned)g), dim3(256), 0, st, norb, ng, func, n, w.grp,
+                     w.pos, cJ, cK);
+  return launch_status();
+}
+
+}  // namespace nof

@@ -50,13 +50,23 @@ _sig("nof_expm_antisym", _i, _i, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_rotate_orbitals_ws", _sz, _i, _i)
 _sig("nof_rotate_orbitals", _i, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_adam_step", _i, _i, _vp, _vp, _vp, _i, _d, _d, _d, _d, _vp, _vp)
+_sig("nof_occ_ws", _sz, _i, _i, _i)
+_sig("nof_occ_energy_grad", _i, _i, _i, _i, _vp, _i, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+     _sz, _vp)
+_sig("nof_occ_optimize", _i, _i, _i, _i, _vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i, _d, _vp,
+     _sz, _vp)
+_sig("nof_functional_coeffs", _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
+
+MAP_TRIG, MAP_SOFTMAX = 0, 1
+FUNC_HF, FUNC_PNOF5 = 0, 1
 
 DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
     "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
-    "nof_adam_step",
+    "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
+    "nof_functional_coeffs",
 ]
 
 
@@ -274,3 +284,59 @@ class Rotation:
     def apply(self, C, y, Cout, stream=None):
         expm_antisym(y, self.U, self.ws, stream)
         return rotate_orbitals(C, self.U, Cout, self.ws_rot, stream)
+
+
+def _i32(t, name):
+    if t.dtype != torch.int32:
+        raise TypeError(f"{name} must be int32")
+    return _p(t)
+
+
+class Occupations:
+    """Occupation-number update at fixed orbitals for one pairing structure."""
+
+    def __init__(self, norb, members, mapping=MAP_TRIG, functional=FUNC_PNOF5):
+        self.norb = int(norb)
+        self.members = members.to(torch.int32).contiguous()
+        self.ns, ng1 = self.members.shape
+        self.ng = ng1 - 1
+        self.map, self.func = int(mapping), int(functional)
+        dev = self.members.device
+        self.ws = workspace(lib.nof_occ_ws(self.norb, self.ns, self.ng), dev)
+        self.info = torch.zeros(4, dtype=torch.int32, device=dev)
+
+    def _h(self, h):
+        # a full [norb][norb] h is read along its diagonal, a [norb] vector directly
+        return (_f64(h, "h"), self.norb + 1) if h.dim() == 2 else (_f64(h, "h"), 1)
+
+    def energy_grad(self, gamma, h, J, K, stream=None):
+        dev = gamma.device
+        n = torch.empty(self.norb, dtype=torch.float64, device=dev)
+        E = torch.empty((), dtype=torch.float64, device=dev)
+        g = torch.empty_like(gamma)
+        hp, hs = self._h(h)
+        check(lib.nof_occ_energy_grad(self.norb, self.ns, self.ng, _p(self.members), self.map, self.func,
+                                      _f64(gamma, "gamma"), hp, hs, _f64(J, "J"), _f64(K, "K"), _p(n),
+                                      _p(E), _p(g), _p(self.info), _p(self.ws), self.ws.numel(),
+                                      stream_handle(stream)), "nof_occ_energy_grad")
+        return E, g, n
+
+    def optimize(self, gamma, h, J, K, maxit=2000, tol=1e-8, stream=None):
+        """L-BFGS in place on gamma; returns (E, n, info) with info = [iters, converged, status]."""
+        dev = gamma.device
+        n = torch.empty(self.norb, dtype=torch.float64, device=dev)
+        E = torch.empty((), dtype=torch.float64, device=dev)
+        hp, hs = self._h(h)
+        check(lib.nof_occ_optimize(self.norb, self.ns, self.ng, _p(self.members), self.map, self.func,
+                                   hp, hs, _f64(J, "J"), _f64(K, "K"), _f64(gamma, "gamma"), _p(n), _p(E),
+                                   _p(self.info), int(maxit), float(tol), _p(self.ws), self.ws.numel(),
+                                   stream_handle(stream)), "nof_occ_optimize")
+        return E, n, self.info
+
+    def coefficients(self, n, stream=None):
+        cJ = torch.empty((self.norb, self.norb), dtype=torch.float64, device=n.device)
+        cK = torch.empty_like(cJ)
+        check(lib.nof_functional_coeffs(self.norb, self.ns, self.ng, _p(self.members), self.func,
+                                        _f64(n, "n"), _p(cJ), _p(cK), _p(self.info), _p(self.ws),
+                                        self.ws.numel(), stream_handle(stream)), "nof_functional_coeffs")
+        return cJ, cK
