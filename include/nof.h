@@ -256,6 +256,55 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
                           const double* n, double* cJ, double* cK, int* info, void* ws,
                           size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: ninst instances sharing one B (for example the finite-field
+ * instances H_i = H + F_i d of the nonlinear-optical-properties workflow),
+ * each with its own C_i, H_i, occupations and coefficients.  One iteration
+ * produces, for every instance, the same lambda_i, g_i and E_i as
+ * nof_mo_transform + nof_jk_diag + nof_gen_fock + nof_energy would, but B is
+ * read once for all instances (their C_i are packed side by side) and every
+ * later step is a single instance-batched launch.
+ *
+ *   B      [naux][nbf][nbf], storage NOF_F64 (prec NOF_P_F64) or NOF_F32
+ *          (prec NOF_P_F32: FP32 matrix-core products, FP64 reductions)
+ *   C      [ninst][nbf][norb]     H  [ninst][nbf][nbf]    n  [ninst][norb]
+ *   cJ, cK [ninst][norb][norb] (symmetric)
+ *   E      out [ninst]      lambda, grad  out [ninst][norb][norb] (grad may be NULL)
+ *   ws     nof_plan_ws(plan) bytes; it also holds b_i, J_i, K_i between calls.
+ *
+ * nof_plan_create / nof_plan_destroy: host object holding sizes, the tuned
+ *   configuration and, once captured, a HIP graph of one iteration.
+ * nof_plan_autotune: runs one iteration, then times each candidate workgroup
+ *   tile (128 or 64) of the two transform stages and the exchange-type
+ *   contraction, and its split over P, keeping the fastest; finishes with one
+ *   iteration in the chosen configuration.  Synchronises `stream`.
+ * nof_plan_get_config / nof_plan_set_config: int[4] = {tile stage 1, tile
+ *   stage 2, tile exchange, P-split count of the exchange term}, so a caller
+ *   can cache a tuning result.
+ * nof_plan_capture: records one iteration on `stream` (not the null stream)
+ *   into a graph bound to these exact pointers; nof_plan_launch replays it
+ *   (one hipGraphLaunch), reading the current contents of the inputs.
+ * ------------------------------------------------------------------------- */
+typedef struct nof_plan_s* nof_plan;
+int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int prec);
+size_t nof_plan_ws(nof_plan plan);
+int nof_plan_get_config(nof_plan plan, int* cfg);
+int nof_plan_set_config(nof_plan plan, const int* cfg);
+int nof_plan_iteration(nof_plan plan, const void* B, const double* C, const double* H,
+                       const double* n, const double* cJ, const double* cK, double* E,
+                       double* lambda, double* grad, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const double* H,
+                      const double* n, const double* cJ, const double* cK, double* E,
+                      double* lambda, double* grad, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+int nof_plan_capture(nof_plan plan, const void* B, const double* C, const double* H,
+                     const double* n, const double* cJ, const double* cK, double* E,
+                     double* lambda, double* grad, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+int nof_plan_launch(nof_plan plan, hipStream_t stream);
+int nof_plan_destroy(nof_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

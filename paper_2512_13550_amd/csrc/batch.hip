@@ -1,0 +1,427 @@
+// Batched form: many instances that share the three-index tensor B but carry
+// their own orbitals C_i, one-electron matrix H_i, occupations and
+// coefficients (e.g. the finite-field instances of the nonlinear-optics
+// workflow: H_i = H + F_i d, one field per instance).
+//
+// One iteration for all instances:
+//   1. the C_i are packed side by side, C_all[nu][i*norb + q], so the first
+//      transform stage reads B once for every instance: T_all = B^P C_all;
+//   2. b_i^P = C_i^T T_i^P, D_i (one launch over (instance, P));
+//   3. h_i = C_i^T H_i C_i, J_i = D_i^T D_i, W_i = D_i cJ_i (instance-batched);
+//   4. one pass over every b_i for K_i and the Coulomb-type term;
+//   5. the exchange-type term per instance (split over P), lambda_i, g_i, E_i.
+// Every step is an instance-batched launch on the caller's stream, so the
+// iteration can be captured once into a HIP graph and replayed with a single
+// hipGraphLaunch.  The workgroup tile of each matrix product (128 or 64) and
+// the P-split of the exchange term are chosen by timing the candidates
+// (nof_plan_autotune).
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+struct nof_plan_s {
+  int ninst, naux, nbf, norb, prec, bt;
+  int tile_s1, tile_s2, tile_f2, f2gpi;    // tuned choices
+  int kchunks;
+  size_t off[16];
+  size_t total;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool captured;
+};
+
+namespace nof {
+namespace {
+
+enum {
+  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_N
+};
+
+void plan_layout(nof_plan_s* p) {
+  const size_t ni = p->ninst, na = p->naux, nb = p->nbf, no = p->norb;
+  const size_t es = dtype_size(p->bt);
+  const size_t n2 = no * no * 8;
+  const int f2groups = p->ninst * p->f2gpi;
+  size_t sz[O_N];
+  sz[O_CALL] = nb * ni * no * 8;
+  sz[O_T] = na * nb * ni * no * es;
+  sz[O_B] = ni * na * no * no * es;
+  sz[O_D] = ni * na * no * 8;
+  sz[O_TH] = ni * nb * no * 8;
+  sz[O_H] = ni * n2;
+  sz[O_J] = ni * n2;
+  sz[O_K] = ni * n2;
+  sz[O_W] = ni * na * no * 8;
+  sz[O_KP] = ni * p->kchunks * n2;
+  sz[O_F1P] = ni * p->kchunks * n2;
+  sz[O_F2P] = (size_t)f2groups * n2;
+  sz[O_F1] = ni * n2;
+  sz[O_F2] = ni * n2;
+  size_t o = 0;
+  for (int i = 0; i < O_N; ++i) {
+    p->off[i] = o;
+    o = align256(o + sz[i]);
+  }
+  p->total = o;
+}
+
+__global__ void k_pack_C(int ninst, int nbf, int norb, const double* __restrict__ C,
+                         double* __restrict__ Call) {
+  const long long n = (long long)ninst * nbf * norb;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long i = e / ((long long)nbf * norb);
+    const long long r = e - i * nbf * norb;
+    const long long nu = r / norb, q = r - nu * norb;
+    Call[nu * ninst * norb + i * norb + q] = C[e];
+  }
+}
+
+struct Args {
+  const void* B;
+  const double *C, *H, *n, *cJ, *cK;
+  double *E, *lam, *grad;
+  char* ws;
+};
+
+// Stage kernels of one iteration.  Each returns a status.
+int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long ldc = (long long)p->ninst * p->norb;
+  GemmDesc g{};
+  g.M = p->nbf; g.N = p->ninst * p->norb; g.K = p->nbf;
+  g.batch = p->naux; g.fold = 1;
+  g.X = a.B; g.ldx = p->nbf; g.sx = (long long)p->nbf * p->nbf; g.x_kmajor = true;
+  g.Y = a.ws + p->off[O_CALL]; g.ldy = ldc; g.sy = 0;
+  g.Out = a.ws + p->off[O_T]; g.ldo = ldc; g.so = (long long)p->nbf * ldc;
+  g.role = GemmRole::TransformStage1;
+  g.tile = p->tile_s1;
+  return gemm_tn(g, p->bt, NOF_F64, p->bt, p->prec, st);
+}
+
+int run_stage2(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long ldc = (long long)p->ninst * p->norb;
+  const long long n2 = (long long)p->norb * p->norb;
+  GemmDesc g{};
+  g.M = p->norb; g.N = p->norb; g.K = p->nbf;
+  g.batch = p->ninst * p->naux; g.fold = 1; g.binner = p->naux;
+  g.X = a.C; g.ldx = p->norb; g.sx = 0; g.sx2 = (long long)p->nbf * p->norb; g.x_kmajor = true;
+  g.Y = a.ws + p->off[O_T]; g.ldy = ldc; g.sy = (long long)p->nbf * ldc; g.sy2 = p->norb;
+  g.Out = a.ws + p->off[O_B]; g.ldo = p->norb; g.so = n2; g.so2 = (long long)p->naux * n2;
+  g.Dg = (double*)(a.ws + p->off[O_D]); g.sd = p->norb; g.sd2 = (long long)p->naux * p->norb;
+  g.sym = true;
+  g.role = GemmRole::TransformStage2;
+  g.tile = p->tile_s2;
+  return gemm_tn(g, NOF_F64, p->bt, p->bt, p->prec, st);
+}
+
+int run_small(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long n2 = (long long)p->norb * p->norb;
+  double* Th = (double*)(a.ws + p->off[O_TH]);
+  double* h = (double*)(a.ws + p->off[O_H]);
+  double* D = (double*)(a.ws + p->off[O_D]);
+  double* J = (double*)(a.ws + p->off[O_J]);
+  double* W = (double*)(a.ws + p->off[O_W]);
+  // h_i = C_i^T H_i C_i
+  GemmDesc g1{};
+  g1.M = p->nbf; g1.N = p->norb; g1.K = p->nbf; g1.batch = p->ninst; g1.fold = 1;
+  g1.X = a.H; g1.ldx = p->nbf; g1.sx = (long long)p->nbf * p->nbf; g1.x_kmajor = true;
+  g1.Y = a.C; g1.ldy = p->norb; g1.sy = (long long)p->nbf * p->norb;
+  g1.Out = Th; g1.ldo = p->norb; g1.so = (long long)p->nbf * p->norb;
+  int rc = gemm_tn(g1, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+  if (rc != NOF_OK) return rc;
+  GemmDesc g2{};
+  g2.M = p->norb; g2.N = p->norb; g2.K = p->nbf; g2.batch = p->ninst; g2.fold = 1;
+  g2.X = a.C; g2.ldx = p->norb; g2.sx = (long long)p->nbf * p->norb; g2.x_kmajor = true;
+  g2.Y = Th; g2.ldy = p->norb; g2.sy = (long long)p->nbf * p->norb;
+  g2.Out = h; g2.ldo = p->norb; g2.so = n2; g2.sym = true;
+  rc = gemm_tn(g2, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+  if (rc != NOF_OK) return rc;
+  // J_i = D_i^T D_i
+  GemmDesc gj{};
+  gj.M = p->norb; gj.N = p->norb; gj.K = p->naux; gj.batch = p->ninst; gj.fold = 1;
+  gj.X = D; gj.ldx = p->norb; gj.sx = (long long)p->naux * p->norb; gj.x_kmajor = true;
+  gj.Y = D; gj.ldy = p->norb; gj.sy = (long long)p->naux * p->norb;
+  gj.Out = J; gj.ldo = p->norb; gj.so = n2; gj.sym = true;
+  rc = gemm_tn(gj, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+  if (rc != NOF_OK) return rc;
+  // W_i = D_i cJ_i
+  GemmDesc gw{};
+  gw.M = p->naux; gw.N = p->norb; gw.K = p->norb; gw.batch = p->ninst; gw.fold = 1;
+  gw.X = D; gw.ldx = p->norb; gw.sx = (long long)p->naux * p->norb; gw.x_kmajor = false;
+  gw.Y = a.cJ; gw.ldy = p->norb; gw.sy = n2;
+  gw.Out = W; gw.ldo = p->norb; gw.so = (long long)p->naux * p->norb;
+  return gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+}
+
+int run_pass(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long n2 = (long long)p->norb * p->norb;
+  double* kp = (double*)(a.ws + p->off[O_KP]);
+  double* f1p = (double*)(a.ws + p->off[O_F1P]);
+  int rc = kf1_pass(p->naux, p->norb, a.ws + p->off[O_B], p->bt, (double*)(a.ws + p->off[O_W]), kp,
+                    f1p, p->kchunks, st, p->ninst, (long long)p->naux * n2,
+                    (long long)p->naux * p->norb, (long long)p->kchunks * n2);
+  if (rc != NOF_OK) return rc;
+  rc = reduce_parts(f1p, p->kchunks, n2, p->norb, false, (double*)(a.ws + p->off[O_F1]), st,
+                    p->ninst, (long long)p->kchunks * n2, n2);
+  if (rc != NOF_OK) return rc;
+  return reduce_parts(kp, p->kchunks, n2, p->norb, true, (double*)(a.ws + p->off[O_K]), st,
+                      p->ninst, (long long)p->kchunks * n2, n2);
+}
+
+int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long n2 = (long long)p->norb * p->norb;
+  const int fold = (p->naux + p->f2gpi - 1) / p->f2gpi;
+  const int gpi = (p->naux + fold - 1) / fold;
+  double* f2p = (double*)(a.ws + p->off[O_F2P]);
+  GemmDesc g{};
+  g.M = p->norb; g.N = p->norb; g.K = p->norb;
+  g.batch = p->ninst * p->naux; g.fold = fold; g.binner = p->naux;
+  g.X = a.ws + p->off[O_B]; g.ldx = p->norb; g.sx = n2; g.sx2 = (long long)p->naux * n2;
+  g.x_kmajor = true;
+  g.Y = a.ws + p->off[O_B]; g.ldy = p->norb; g.sy = n2; g.sy2 = (long long)p->naux * n2;
+  g.S = a.cK; g.lds = p->norb; g.ss2 = n2;
+  g.Out = f2p; g.ldo = p->norb; g.so = n2;
+  g.role = GemmRole::ExchangeFock;
+  g.tile = p->tile_f2;
+  int rc = gemm_tn(g, p->bt, p->bt, NOF_F64, p->prec, st);
+  if (rc != NOF_OK) return rc;
+  return reduce_parts(f2p, gpi, n2, p->norb, false, (double*)(a.ws + p->off[O_F2]), st, p->ninst,
+                      (long long)gpi * n2, n2);
+}
+
+int run_tail(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long n2 = (long long)p->norb * p->norb;
+  const double* h = (const double*)(a.ws + p->off[O_H]);
+  int rc = lambda_grad(p->norb, a.n, h, (double*)(a.ws + p->off[O_F1]),
+                       (double*)(a.ws + p->off[O_F2]), a.lam, a.grad, st, p->ninst, p->norb, n2,
+                       n2);
+  if (rc != NOF_OK) return rc;
+  // energy: h, cJ, cK stride n2 per instance; J, K stride n2
+  return energy(p->norb, a.n, h, (double*)(a.ws + p->off[O_J]), (double*)(a.ws + p->off[O_K]),
+                a.cJ, a.cK, a.E, st, p->ninst, p->norb, n2, n2);
+}
+
+int run_iteration(nof_plan_s* p, const Args& a, hipStream_t st) {
+  const long long n = (long long)p->ninst * p->nbf * p->norb;
+  long long gpk = (n + 255) / 256;
+  if (gpk > 4096) gpk = 4096;
+  hipLaunchKernelGGL(k_pack_C, dim3((unsigned)gpk), dim3(256), 0, st, p->ninst, p->nbf, p->norb,
+                     a.C, (double*)(a.ws + p->off[O_CALL]));
+  int rc = launch_status();
+  if (rc != NOF_OK) return rc;
+  if ((rc = run_stage1(p, a, st)) != NOF_OK) return rc;
+  if ((rc = run_stage2(p, a, st)) != NOF_OK) return rc;
+  if ((rc = run_small(p, a, st)) != NOF_OK) return rc;
+  if ((rc = run_pass(p, a, st)) != NOF_OK) return rc;
+  if ((rc = run_f2(p, a, st)) != NOF_OK) return rc;
+  return run_tail(p, a, st);
+}
+
+// Time `reps` launches of one stage; returns milliseconds per launch or -1.
+template <class F>
+float time_stage(F&& f, hipStream_t st, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.f; }
+  float ms = -1.f;
+  if (f() == NOF_OK && hipEventRecord(e0, st) == hipSuccess) {
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) ok = f() == NOF_OK;
+    if (ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / reps;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+}  // namespace
+}  // namespace nof
+
+using namespace nof;
+
+namespace {
+template <class F>
+int guarded_b(F&& f) {
+  try {
+    return f();
+  } catch (...) {
+    return NOF_E_INTERNAL;
+  }
+}
+bool plan_ok(const nof_plan_s* p) { return p != nullptr; }
+int f2_target_gpi(const nof_plan_s* p, int tile) {
+  const int tn = (p->norb + tile - 1) / tile;
+  const long long tiles = (long long)tn * tn * p->ninst;
+  long long g = (768 + tiles - 1) / tiles;
+  if (g < 1) g = 1;
+  if (g > p->naux) g = p->naux;
+  return (int)g;
+}
+}  // namespace
+
+extern "C" {
+
+int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int prec) {
+  return guarded_b([&]() -> int {
+    if (!plan) return NOF_E_NULL;
+    *plan = nullptr;
+    if (ninst < 1 || ninst > 4096 || naux < 1 || nbf < 1 || norb < 1 || naux > (1 << 20) ||
+        nbf > (1 << 16) || norb > (1 << 16))
+      return NOF_E_DIM;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    nof_plan_s* p = new nof_plan_s();
+    p->ninst = ninst; p->naux = naux; p->nbf = nbf; p->norb = norb; p->prec = prec;
+    p->bt = prec == NOF_P_F64 ? NOF_F64 : NOF_F32;
+    p->tile_s1 = 128; p->tile_s2 = 128; p->tile_f2 = 128;
+    p->f2gpi = 1;
+    // the exchange partial buffer is sized for the largest split the tuner may pick
+    p->kchunks = kf1_chunks(naux, norb);
+    const int gmax = f2_target_gpi(p, 64) * 4 > naux ? naux : f2_target_gpi(p, 64) * 4;
+    p->f2gpi = gmax;
+    plan_layout(p);
+    p->f2gpi = f2_target_gpi(p, 128);
+    p->graph = nullptr; p->exec = nullptr; p->captured = false;
+    *plan = p;
+    return NOF_OK;
+  });
+}
+
+size_t nof_plan_ws(nof_plan plan) { return plan_ok(plan) ? plan->total : 0; }
+
+int nof_plan_get_config(nof_plan plan, int* cfg) {
+  if (!plan_ok(plan) || !cfg) return NOF_E_NULL;
+  cfg[0] = plan->tile_s1; cfg[1] = plan->tile_s2; cfg[2] = plan->tile_f2; cfg[3] = plan->f2gpi;
+  return NOF_OK;
+}
+
+int nof_plan_set_config(nof_plan plan, const int* cfg) {
+  if (!plan_ok(plan) || !cfg) return NOF_E_NULL;
+  for (int i = 0; i < 3; ++i)
+    if (cfg[i] != 64 && cfg[i] != 128) return NOF_E_ARG;
+  const int gmax = f2_target_gpi(plan, 64) * 4 > plan->naux ? plan->naux : f2_target_gpi(plan, 64) * 4;
+  if (cfg[3] < 1 || cfg[3] > gmax) return NOF_E_ARG;
+  if (plan->captured) return NOF_E_ARG;
+  plan->tile_s1 = cfg[0]; plan->tile_s2 = cfg[1]; plan->tile_f2 = cfg[2]; plan->f2gpi = cfg[3];
+  return NOF_OK;
+}
+
+#define NOF_PLAN_ARGS_CHECK()                                                            \
+  if (!plan_ok(plan)) return NOF_E_NULL;                                                 \
+  if (!B || !C || !H || !n || !cJ || !cK || !E || !lambda) return NOF_E_NULL;            \
+  if (!ws || ws_bytes < plan->total) return NOF_E_WORKSPACE;
+
+int nof_plan_iteration(nof_plan plan, const void* B, const double* C, const double* H,
+                       const double* n, const double* cJ, const double* cK, double* E,
+                       double* lambda, double* grad, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  return guarded_b([&]() -> int {
+    NOF_PLAN_ARGS_CHECK();
+    Args a{B, C, H, n, cJ, cK, E, lambda, grad, (char*)ws};
+    return run_iteration(plan, a, stream);
+  });
+}
+
+int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const double* H,
+                      const double* n, const double* cJ, const double* cK, double* E,
+                      double* lambda, double* grad, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  return guarded_b([&]() -> int {
+    NOF_PLAN_ARGS_CHECK();
+    if (plan->captured) return NOF_E_ARG;
+    Args a{B, C, H, n, cJ, cK, E, lambda, grad, (char*)ws};
+    int rc = run_iteration(plan, a, stream);        // fills T, b, W with valid data
+    if (rc != NOF_OK) return rc;
+    const int reps = 3;
+    const int tiles[2] = {128, 64};
+    float best = -1.f;
+    int bt1 = plan->tile_s1;
+    for (int t : tiles) {
+      plan->tile_s1 = t;
+      const float ms = time_stage([&]() { return run_stage1(plan, a, stream); }, stream, reps);
+      if (ms > 0.f && (best < 0.f || ms < best)) { best = ms; bt1 = t; }
+    }
+    plan->tile_s1 = bt1;
+    best = -1.f;
+    int bt2 = plan->tile_s2;
+    for (int t : tiles) {
+      plan->tile_s2 = t;
+      const float ms = time_stage([&]() { return run_stage2(plan, a, stream); }, stream, reps);
+      if (ms > 0.f && (best < 0.f || ms < best)) { best = ms; bt2 = t; }
+    }
+    plan->tile_s2 = bt2;
+    best = -1.f;
+    int btf = plan->tile_f2, bg = plan->f2gpi;
+    const int gmax = f2_target_gpi(plan, 64) * 4 > plan->naux ? plan->naux : f2_target_gpi(plan, 64) * 4;
+    for (int t : tiles) {
+      const int g0 = f2_target_gpi(plan, t);
+      const int cands[3] = {g0 / 2 > 0 ? g0 / 2 : 1, g0, 2 * g0};
+      for (int g : cands) {
+        if (g > gmax) continue;
+        plan->tile_f2 = t;
+        plan->f2gpi = g;
+        const float ms = time_stage([&]() { return run_f2(plan, a, stream); }, stream, reps);
+        if (ms > 0.f && (best < 0.f || ms < best)) { best = ms; btf = t; bg = g; }
+      }
+    }
+    plan->tile_f2 = btf;
+    plan->f2gpi = bg;
+    // leave the outputs consistent with the chosen configuration
+    return run_iteration(plan, a, stream);
+  });
+}
+
+int nof_plan_capture(nof_plan plan, const void* B, const double* C, const double* H,
+                     const double* n, const double* cJ, const double* cK, double* E,
+                     double* lambda, double* grad, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  return guarded_b([&]() -> int {
+    NOF_PLAN_ARGS_CHECK();
+    if (stream == nullptr) return NOF_E_ARG;      // the null stream cannot be captured
+    if (plan->captured) {
+      (void)hipGraphExecDestroy(plan->exec);
+      (void)hipGraphDestroy(plan->graph);
+      plan->captured = false;
+    }
+    Args a{B, C, H, n, cJ, cK, E, lambda, grad, (char*)ws};
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return NOF_E_HIP;
+    const int rc = run_iteration(plan, a, stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(stream, &g);
+    if (rc != NOF_OK || ec != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != NOF_OK ? rc : NOF_E_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return NOF_E_HIP;
+    }
+    plan->graph = g;
+    plan->exec = ex;
+    plan->captured = true;
+    return NOF_OK;
+  });
+}
+
+int nof_plan_launch(nof_plan plan, hipStream_t stream) {
+  if (!plan_ok(plan)) return NOF_E_NULL;
+  if (!plan->captured) return NOF_E_ARG;
+  return hipGraphLaunch(plan->exec, stream) == hipSuccess ? NOF_OK : NOF_E_HIP;
+}
+
+int nof_plan_destroy(nof_plan plan) {
+  if (!plan) return NOF_OK;
+  if (plan->captured) {
+    (void)hipGraphExecDestroy(plan->exec);
+    (void)hipGraphDestroy(plan->graph);
+  }
+  delete plan;
+  return NOF_OK;
+}
+
+}  // extern "C"

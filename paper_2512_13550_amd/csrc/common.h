@@ -61,6 +61,12 @@ struct GemmDesc {
   const int* pred; int pred_gt;   // if pred: run only when *pred > pred_gt (else write nothing)
   GemmRole role;                   // selects the kernel symbol (profiling attribution only)
   long long psx, psy;              // plane strides of pre-split bf16 operands (gemm_bf16)
+  // Two-level batching (binner > 0): batch b = outer * binner + inner; operand
+  // offsets inner * s? + outer * s?2; fold groups never cross an outer index,
+  // and with fold > 1 partial results go to Out + group * so.
+  int binner;
+  long long sx2, sy2, so2, sd2, ss2;
+  int tile;                        // workgroup tile edge of gemm_tn: 128 (default) or 64
 };
 
 // Element types: 0 = f64, 1 = f32.  prec: NOF_P_F64 or NOF_P_F32.
@@ -90,20 +96,25 @@ inline int gemm_any(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hi
 //   F1part[c][r][s] += b_rs W[P][s],  F1part[c][s][r] += b_rs W[P][r]
 // Either output may be NULL.
 int kf1_pass(int naux, int norb, const void* b, int bt, const double* W,
-             double* Kpart, double* F1part, int nchunk, hipStream_t st);
+             double* Kpart, double* F1part, int nchunk, hipStream_t st, int ninst = 1,
+             long long bstride = 0, long long wstride = 0, long long pstride = 0);
 int kf1_chunks(int naux, int norb);
 
 // out[i] = sum_c part[c*stride + i] in fixed order; if sym_upper, element
 // (r,s) is read from (min,max) and written to both (r,s) and (s,r).
 int reduce_parts(const double* part, int nparts, long long stride, int norb,
-                 bool sym_upper, double* out, hipStream_t st);
+                 bool sym_upper, double* out, hipStream_t st, int ninst = 1,
+                 long long pinst = 0, long long oinst = 0);
 
+// Instance-batched forms (grid dimension over instances with the given strides).
 int lambda_grad(int norb, const double* n, const double* h, const double* F1,
-                const double* F2, double* lam, double* grad, hipStream_t st);
+                const double* F2, double* lam, double* grad, hipStream_t st, int ninst = 1,
+                long long nstride = 0, long long mstride = 0, long long fstride = 0);
 
 int energy(int norb, const double* n, const double* h, const double* J,
            const double* K, const double* cJ, const double* cK, double* E,
-           hipStream_t st);
+           hipStream_t st, int ninst = 1, long long nstride = 0, long long mstride = 0,
+           long long jstride = 0);
 
 // FP64 orbital-rotation helpers (rotation.hip).
 size_t expm_ws(int norb);

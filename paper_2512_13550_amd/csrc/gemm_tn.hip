@@ -20,11 +20,8 @@
 namespace nof {
 namespace {
 
-constexpr int BM = 128;            // tile rows (m) == tile cols (n)
 constexpr int KT = 16;             // k per LDS stage
 constexpr int NTHR = 256;
-constexpr int LDSW = BM + 16;      // padded LDS row: k and k+1 land on disjoint bank halves
-constexpr int PER_T = KT * BM / NTHR;  // elements of one operand tile per thread (8)
 
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
@@ -58,12 +55,18 @@ __device__ __forceinline__ void upper_tile(int t, int T, int& tm, int& tn) {
   tn = row + t;
 }
 
-template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64, bool HAS_S>
+// FM x FN fragments per wave; the workgroup tile is (32 FM) x (32 FN).
+template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64, bool HAS_S,
+          int FM, int FN>
 __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int ntiles) {
   typedef Mfma<TC> MF;
   typedef typename MF::acc_t acc_t;
-  __shared__ TC Xs[2][KT][LDSW];
-  __shared__ TC Ys[2][KT][LDSW];
+  constexpr int BMt = 32 * FM, BNt = 32 * FN;
+  constexpr int RX = NTHR / BMt, RY = NTHR / BNt;     // k rows per loader pass
+  constexpr int PX = KT / RX, PY = KT / RY;           // operand elements per thread
+  // padded LDS rows: k and k+1 land on disjoint bank halves
+  __shared__ TC Xs[2][KT][BMt + 16];
+  __shared__ TC Ys[2][KT][BNt + 16];
 
   if (d.pred && *d.pred <= d.pred_gt) return;
   const int tid = threadIdx.x;
@@ -76,43 +79,54 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   int tm, tn;
   if (d.sym) upper_tile(tile, tiles_n, tm, tn);
   else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
-  const int m0 = tm * BM, n0 = tn * BM;
+  const int m0 = tm * BMt, n0 = tn * BNt;
 
-  const int b_lo = group * d.fold;
-  const int b_hi = min(d.batch, b_lo + d.fold);
+  // batches of this group: [b_lo, b_hi) of the inner index, for outer index `outer`
+  int outer = 0, b_lo, b_hi;
+  if (d.binner > 0) {
+    const int gpi = (d.binner + d.fold - 1) / d.fold;
+    outer = group / gpi;
+    b_lo = (group - outer * gpi) * d.fold;
+    b_hi = min(d.binner, b_lo + d.fold);
+  } else {
+    b_lo = group * d.fold;
+    b_hi = min(d.batch, b_lo + d.fold);
+  }
+  const long long xo = (long long)outer * d.sx2, yo = (long long)outer * d.sy2;
+  const double* __restrict__ Sg = d.S ? d.S + (long long)outer * d.ss2 : nullptr;
   const int nkb = (d.K + KT - 1) / KT;
   const int nstage = (b_hi - b_lo) * nkb;
 
-  const TX* __restrict__ X = (const TX*)d.X;
-  const TY* __restrict__ Y = (const TY*)d.Y;
-  const double* __restrict__ S = d.S;
+  const TX* __restrict__ X = (const TX*)d.X + xo;
+  const TY* __restrict__ Y = (const TY*)d.Y + yo;
+  const double* __restrict__ S = Sg;
 
   // Stage-invariant part of this thread's load pattern.  Element j of a
-  // k-major operand tile is (k = k_t + 2j, col = c_t): a wave covers 64
+  // k-major operand tile is (k = k_t + R j, col = c_t): a wave covers 64
   // consecutive columns of one row.  For an m-major X, element j is
   // (k = tid % 16, m = tid / 16 + 16 j).
-  const int c_t = tid & (BM - 1);
-  const int k_t = tid >> 7;
-  const bool xm_ok = XK ? (m0 + c_t < d.M) : true;
-  const bool yn_ok = n0 + c_t < d.N;
+  const int cx_t = tid % BMt, kx_t = tid / BMt;
+  const int cy_t = tid % BNt, ky_t = tid / BNt;
+  const bool xm_ok = XK ? (m0 + cx_t < d.M) : true;
+  const bool yn_ok = n0 + cy_t < d.N;
   const int xk_t = tid & (KT - 1), xm_t = tid >> 4;
 
-  acc_t acc[4][4];
-  d4v acc64[FLUSH64 ? 4 : 1][FLUSH64 ? 4 : 1];
+  acc_t acc[FM][FN];
+  d4v acc64[FLUSH64 ? FM : 1][FLUSH64 ? FN : 1];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
   if (FLUSH64) {
 #pragma unroll
-    for (int i = 0; i < (FLUSH64 ? 4 : 1); ++i)
+    for (int i = 0; i < (FLUSH64 ? FM : 1); ++i)
 #pragma unroll
-      for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) acc64[i][j] = d4v{0, 0, 0, 0};
+      for (int j = 0; j < (FLUSH64 ? FN : 1); ++j) acc64[i][j] = d4v{0, 0, 0, 0};
   }
 
-  TX xr[PER_T];
-  TY yr[PER_T];
-  double sr[HAS_S ? PER_T : 1];
+  TX xr[PX];
+  TY yr[PY];
+  double sr[HAS_S ? PY : 1];
 
   auto load = [&](int s) {
     const int bb = b_lo + s / nkb;
@@ -123,33 +137,36 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
       if (r < klim) klim = (int)(r < 0 ? 0 : r);
     }
     if (XK) {
-      const TX* px = X + (long long)bb * d.sx + (long long)(k0 + k_t) * d.ldx + (m0 + c_t);
+      const TX* px = X + (long long)bb * d.sx + (long long)(k0 + kx_t) * d.ldx + (m0 + cx_t);
 #pragma unroll
-      for (int j = 0; j < PER_T; ++j)
-        xr[j] = (xm_ok && k_t + 2 * j < klim) ? px[(long long)(2 * j) * d.ldx] : (TX)0;
+      for (int j = 0; j < PX; ++j)
+        xr[j] = (xm_ok && kx_t + RX * j < klim) ? px[(long long)(RX * j) * d.ldx] : (TX)0;
     } else {
       const TX* px = X + (long long)bb * d.sx + (long long)(m0 + xm_t) * d.ldx + (k0 + xk_t);
       const bool kin = xk_t < klim;
 #pragma unroll
-      for (int j = 0; j < PER_T; ++j)
+      for (int j = 0; j < PX; ++j)
         xr[j] = (kin && m0 + xm_t + 16 * j < d.M) ? px[(long long)(16 * j) * d.ldx] : (TX)0;
     }
-    const long long yoff = (long long)(k0 + k_t) * d.ldy + (n0 + c_t);
+    const long long yoff = (long long)(k0 + ky_t) * d.ldy + (n0 + cy_t);
     const TY* py = Y + (long long)bb * d.sy + yoff;
 #pragma unroll
-    for (int j = 0; j < PER_T; ++j) {
-      const bool ok = yn_ok && k_t + 2 * j < klim;
-      yr[j] = ok ? py[(long long)(2 * j) * d.ldy] : (TY)0;
-      if (HAS_S) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + k_t + 2 * j) * d.lds + (n0 + c_t)] : 0.0;
+    for (int j = 0; j < PY; ++j) {
+      const bool ok = yn_ok && ky_t + RY * j < klim;
+      yr[j] = ok ? py[(long long)(RY * j) * d.ldy] : (TY)0;
+      if (HAS_S) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < PER_T; ++j) {
-      if (XK) Xs[buf][k_t + 2 * j][c_t] = (TC)xr[j];
+    for (int j = 0; j < PX; ++j) {
+      if (XK) Xs[buf][kx_t + RX * j][cx_t] = (TC)xr[j];
       else Xs[buf][xk_t][xm_t + 16 * j] = (TC)xr[j];
-      if (HAS_S) Ys[buf][k_t + 2 * j][c_t] = (TC)((double)yr[j] * sr[HAS_S ? j : 0]);
-      else Ys[buf][k_t + 2 * j][c_t] = (TC)yr[j];
+    }
+#pragma unroll
+    for (int j = 0; j < PY; ++j) {
+      if (HAS_S) Ys[buf][ky_t + RY * j][cy_t] = (TC)((double)yr[j] * sr[HAS_S ? j : 0]);
+      else Ys[buf][ky_t + RY * j][cy_t] = (TC)yr[j];
     }
   };
 
@@ -163,23 +180,23 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     if (s + 1 < nstage) load(s + 1);
 #pragma unroll
     for (int kk = 0; kk < KT / 4; ++kk) {
-      TC a[4], bv[4];
+      TC a[FM], bv[FN];
       const int kr = kk * 4 + (l >> 4);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Xs[buf][kr][wm * 64 + i * 16 + (l & 15)];
+      for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kr][wm * 16 * FM + i * 16 + (l & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Ys[buf][kr][wn * 64 + j * 16 + (l & 15)];
+      for (int j = 0; j < FN; ++j) bv[j] = Ys[buf][kr][wn * 16 * FN + j * 16 + (l & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(a[i], bv[j], acc[i][j]);
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::op(a[i], bv[j], acc[i][j]);
     }
     if (FLUSH64 && ((s + 1) % nkb == 0)) {
       // end of one batch: fold the FP32 partial into FP64
 #pragma unroll
-      for (int i = 0; i < (FLUSH64 ? 4 : 1); ++i)
+      for (int i = 0; i < (FLUSH64 ? FM : 1); ++i)
 #pragma unroll
-        for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) {
+        for (int j = 0; j < (FLUSH64 ? FN : 1); ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
           acc[i][j] = acc_t{0, 0, 0, 0};
@@ -191,15 +208,17 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
 
   // Epilogue
   TO* __restrict__ Out = (TO*)d.Out;
-  const long long ob = (long long)(d.fold == 1 ? b_lo : group) * d.so;
+  const long long ob = d.fold == 1 ? (long long)b_lo * d.so + (long long)outer * d.so2
+                                   : (long long)group * d.so;
+  double* __restrict__ Dg = d.Dg ? d.Dg + (long long)b_lo * d.sd + (long long)outer * d.sd2 : nullptr;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * 64 + i * 16 + MF::row(l, r);
-        const int gn = n0 + wn * 64 + j * 16 + (l & 15);
+        const int gm = m0 + wm * 16 * FM + i * 16 + MF::row(l, r);
+        const int gn = n0 + wn * 16 * FN + j * 16 + (l & 15);
         double v;
         if (FLUSH64) v = acc64[FLUSH64 ? i : 0][FLUSH64 ? j : 0][r];
         else v = (double)acc[i][j][r];
@@ -209,7 +228,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
         } else if (gm <= gn) {
           Out[ob + (long long)gm * d.ldo + gn] = (TO)v;
           Out[ob + (long long)gn * d.ldo + gm] = (TO)v;
-          if (gm == gn && d.Dg) d.Dg[(long long)b_lo * d.sd + gm] = v;
+          if (gm == gn && Dg) Dg[gm] = v;
         }
       }
 }
@@ -217,9 +236,9 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
 // One kernel symbol per role, so that profiles attribute time per step.
 #define NOF_GEMM_KERNEL(NAME)                                                              \
   template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64,     \
-            bool HAS_S>                                                                    \
+            bool HAS_S, int FM, int FN>                                                    \
   __global__ __launch_bounds__(NTHR, 2) void NAME(GemmDesc d, int tiles_n, int ntiles) {   \
-    gemm_body<TC, TX, TY, TO, XK, FLUSH64, HAS_S>(d, tiles_n, ntiles);                    \
+    gemm_body<TC, TX, TY, TO, XK, FLUSH64, HAS_S, FM, FN>(d, tiles_n, ntiles);            \
   }
 NOF_GEMM_KERNEL(k_transform_stage1)
 NOF_GEMM_KERNEL(k_transform_stage2)
@@ -227,23 +246,30 @@ NOF_GEMM_KERNEL(k_exchange_fock)
 NOF_GEMM_KERNEL(k_gemm_small)
 #undef NOF_GEMM_KERNEL
 
-template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
-int launch(const GemmDesc& d, hipStream_t st) {
-  if (!XK && PER_T * 16 > BM) return NOF_E_INTERNAL;
-  const int tiles_m = (d.M + BM - 1) / BM;
-  const int tiles_n = (d.N + BM - 1) / BM;
+template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64, int FM, int FN>
+int launch_shape(const GemmDesc& d, hipStream_t st) {
+  constexpr int BMt = 32 * FM, BNt = 32 * FN;
+  if (d.sym && BMt != BNt) return NOF_E_INTERNAL;
+  const int tiles_m = (d.M + BMt - 1) / BMt;
+  const int tiles_n = (d.N + BNt - 1) / BNt;
   const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
-  const int ngroups = (d.batch + d.fold - 1) / d.fold;
+  long long ngroups;
+  if (d.binner > 0) {
+    if (d.batch % d.binner != 0) return NOF_E_DIM;
+    ngroups = (long long)(d.batch / d.binner) * ((d.binner + d.fold - 1) / d.fold);
+  } else {
+    ngroups = (d.batch + d.fold - 1) / d.fold;
+  }
   const long long G = (long long)ntiles * ngroups;
   if (G <= 0) return NOF_OK;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
 #define NOF_LAUNCH(NAME)                                                                      \
   do {                                                                                        \
     if (d.S)                                                                                  \
-      hipLaunchKernelGGL((NAME<TC, TX, TY, TO, XK, FLUSH64, true>), dim3((unsigned)G),        \
+      hipLaunchKernelGGL((NAME<TC, TX, TY, TO, XK, FLUSH64, true, FM, FN>), dim3((unsigned)G), \
                          dim3(NTHR), 0, st, d, tiles_n, ntiles);                              \
     else                                                                                      \
-      hipLaunchKernelGGL((NAME<TC, TX, TY, TO, XK, FLUSH64, false>), dim3((unsigned)G),       \
+      hipLaunchKernelGGL((NAME<TC, TX, TY, TO, XK, FLUSH64, false, FM, FN>), dim3((unsigned)G), \
                          dim3(NTHR), 0, st, d, tiles_n, ntiles);                              \
   } while (0)
   switch (d.role) {
@@ -254,6 +280,12 @@ int launch(const GemmDesc& d, hipStream_t st) {
   }
 #undef NOF_LAUNCH
   return launch_status();
+}
+
+template <typename TC, typename TX, typename TY, typename TO, bool XK, bool FLUSH64>
+int launch(const GemmDesc& d, hipStream_t st) {
+  if (d.tile == 64) return launch_shape<TC, TX, TY, TO, XK, FLUSH64, 2, 2>(d, st);
+  return launch_shape<TC, TX, TY, TO, XK, FLUSH64, 4, 4>(d, st);
 }
 
 }  // namespace

@@ -33,15 +33,22 @@ template <> struct Vec2<double> { typedef double2 t; };
 template <> struct Vec2<float> { typedef float2 t; };
 
 // VEC: norb even, so every row segment starting at an even column is aligned.
+// Instance i (blockIdx.y) reads b + i*bstride, W + i*wstride and writes its
+// partials at + i*pstride.
 template <typename TB, bool VEC>
 __global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __restrict__ b,
                                                 const double* __restrict__ W,
                                                 double* __restrict__ Kpart,
                                                 double* __restrict__ F1part, int pchunk,
-                                                int ntiles, int ntr, int ntc) {
+                                                int ntiles, int ntr, int ntc, long long bstride,
+                                                long long wstride, long long pstride) {
   typedef typename Vec2<TB>::t V2;
   const int tile = blockIdx.x % ntiles;
   const int chunk = blockIdx.x / ntiles;
+  b += (long long)blockIdx.y * bstride;
+  if (W) W += (long long)blockIdx.y * wstride;
+  if (Kpart) Kpart += (long long)blockIdx.y * pstride;
+  if (F1part) F1part += (long long)blockIdx.y * pstride;
   int tr, tc;
   kf_tile(tile, ntc, ntr, tr, tc);
   if (tr < 0) return;
@@ -132,8 +139,10 @@ __global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __
 }
 
 __global__ void k_reduce(const double* __restrict__ part, int nparts, long long stride, int norb,
-                         int sym_upper, double* __restrict__ out) {
+                         int sym_upper, double* __restrict__ out, long long pinst, long long oinst) {
   const long long n2 = (long long)norb * norb;
+  part += (long long)blockIdx.y * pinst;
+  out += (long long)blockIdx.y * oinst;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x) {
     long long src = i;
@@ -149,8 +158,16 @@ __global__ void k_reduce(const double* __restrict__ part, int nparts, long long 
 
 __global__ void k_lambda(int norb, const double* __restrict__ n, const double* __restrict__ h,
                          const double* __restrict__ F1, const double* __restrict__ F2,
-                         double* __restrict__ lam, double* __restrict__ grad) {
+                         double* __restrict__ lam, double* __restrict__ grad, long long nstride,
+                         long long mstride, long long fstride) {
   const long long n2 = (long long)norb * norb;
+  const long long y = blockIdx.y;
+  n += y * nstride;
+  h += y * mstride;
+  lam += y * mstride;
+  if (grad) grad += y * mstride;
+  F1 += y * fstride;
+  F2 += y * fstride;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x) {
     const int r = (int)(i / norb), s = (int)(i - (long long)r * norb);
@@ -171,9 +188,18 @@ __global__ __launch_bounds__(E_THR) void k_energy(int norb, const double* __rest
                                                   const double* __restrict__ K,
                                                   const double* __restrict__ cJ,
                                                   const double* __restrict__ cK,
-                                                  double* __restrict__ E) {
+                                                  double* __restrict__ E, long long nstride,
+                                                  long long mstride, long long jstride) {
   __shared__ double red[E_THR];
   const long long n2 = (long long)norb * norb;
+  const long long y = blockIdx.x;
+  n += y * nstride;
+  h += y * mstride;
+  cJ += y * mstride;
+  cK += y * mstride;
+  J += y * jstride;
+  K += y * jstride;
+  E += y;
   double a = 0.0;
   for (long long i = threadIdx.x; i < n2; i += E_THR) a += cJ[i] * J[i] - cK[i] * K[i];
   for (int p = threadIdx.x; p < norb; p += E_THR) a += 2.0 * n[p] * h[(long long)p * norb + p];
@@ -230,30 +256,37 @@ int kf1_chunks(int naux, int norb) {
 }
 
 int kf1_pass(int naux, int norb, const void* b, int bt, const double* W, double* Kpart,
-             double* F1part, int nchunk, hipStream_t st) {
+             double* F1part, int nchunk, hipStream_t st, int ninst, long long bstride,
+             long long wstride, long long pstride) {
   int ntr, ntc, ntiles;
   kf_geometry(norb, ntr, ntc, ntiles);
   const int pchunk = (naux + nchunk - 1) / nchunk;
   const int nc = (naux + pchunk - 1) / pchunk;
   if (nc > nchunk) return NOF_E_INTERNAL;
   const long long G = (long long)ntiles * nchunk;
-  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  if (G > 0x7fffffffLL || ninst < 1 || ninst > 65535) return NOF_E_DIM;
   // chunks beyond nc (when pchunk rounding leaves them empty) write zeros
-  const bool vec = (norb % 2) == 0 && ((uintptr_t)b % 16) == 0;
+  const dim3 grid((unsigned)G, (unsigned)ninst);
+  const size_t esz = bt == NOF_F64 ? 8 : 4;
+  const bool vec = (norb % 2) == 0 && ((uintptr_t)b % 16) == 0 && ((bstride * esz) % 16) == 0;
   if (bt == NOF_F64) {
     if (vec)
-      hipLaunchKernelGGL((k_kf1<double, true>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
-                         (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+      hipLaunchKernelGGL((k_kf1<double, true>), grid, dim3(KF_THR), 0, st, naux, norb,
+                         (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
+                         wstride, pstride);
     else
-      hipLaunchKernelGGL((k_kf1<double, false>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux,
-                         norb, (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+      hipLaunchKernelGGL((k_kf1<double, false>), grid, dim3(KF_THR), 0, st, naux, norb,
+                         (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
+                         wstride, pstride);
   } else if (bt == NOF_F32) {
     if (vec)
-      hipLaunchKernelGGL((k_kf1<float, true>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
-                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+      hipLaunchKernelGGL((k_kf1<float, true>), grid, dim3(KF_THR), 0, st, naux, norb,
+                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
+                         wstride, pstride);
     else
-      hipLaunchKernelGGL((k_kf1<float, false>), dim3((unsigned)G), dim3(KF_THR), 0, st, naux, norb,
-                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc);
+      hipLaunchKernelGGL((k_kf1<float, false>), grid, dim3(KF_THR), 0, st, naux, norb,
+                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
+                         wstride, pstride);
   } else {
     return NOF_E_DTYPE;
   }
@@ -261,24 +294,27 @@ int kf1_pass(int naux, int norb, const void* b, int bt, const double* W, double*
 }
 
 int reduce_parts(const double* part, int nparts, long long stride, int norb, bool sym_upper,
-                 double* out, hipStream_t st) {
+                 double* out, hipStream_t st, int ninst, long long pinst, long long oinst) {
   const long long n2 = (long long)norb * norb;
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n2, 256)), dim3(256), 0, st, part, nparts, stride,
-                     norb, sym_upper ? 1 : 0, out);
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, part, nparts,
+                     stride, norb, sym_upper ? 1 : 0, out, pinst, oinst);
   return launch_status();
 }
 
 int lambda_grad(int norb, const double* n, const double* h, const double* F1, const double* F2,
-                double* lam, double* grad, hipStream_t st) {
+                double* lam, double* grad, hipStream_t st, int ninst, long long nstride,
+                long long mstride, long long fstride) {
   const long long n2 = (long long)norb * norb;
-  hipLaunchKernelGGL(k_lambda, dim3(grid_for(n2, 256)), dim3(256), 0, st, norb, n, h, F1, F2, lam,
-                     grad);
+  hipLaunchKernelGGL(k_lambda, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, n, h, F1,
+                     F2, lam, grad, nstride, mstride, fstride);
   return launch_status();
 }
 
 int energy(int norb, const double* n, const double* h, const double* J, const double* K,
-           const double* cJ, const double* cK, double* E, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(E_THR), 0, st, norb, n, h, J, K, cJ, cK, E);
+           const double* cJ, const double* cK, double* E, hipStream_t st, int ninst,
+           long long nstride, long long mstride, long long jstride) {
+  hipLaunchKernelGGL(k_energy, dim3(ninst), dim3(E_THR), 0, st, norb, n, h, J, K, cJ, cK, E,
+                     nstride, mstride, jstride);
   return launch_status();
 }
 

@@ -210,3 +210,18 @@ def pairing(norb: int, nstrong: int, ng: int):
         assert all(w < norb for w in weak)
         groups.append([g] + weak)
     return groups
+
+
+def field_instances(seed: int, nbf: int, norb: int, nstrong: int, ninst: int = 25,
+                    h: float = 1e-3):
+    """Finite-field instances sharing one B: the i-th has its own C_i (seeded
+    QR), H_i = H + F_i d_axis (base H plus field times a random symmetric
+    dipole matrix) and its own occupations.  Fields: 0 and +/- h 2^k, k=0..3,
+    along x, y, z (25 instances), truncated to ``ninst``."""
+    fields = field_strengths(h)[:ninst]
+    H0 = make_H(seed, nbf)
+    d = make_dipoles(seed, nbf)
+    C = np.stack([make_C(seed + 17 * (i + 1), nbf, norb) for i in range(len(fields))])
+    H = np.stack([H0 + F * d[axis] for axis, F in fields])
+    n = np.stack([make_occupations(seed + 31 * (i + 1), norb, nstrong) for i in range(len(fields))])
+    return dict(C=C, H=H, n=n, fields=fields)

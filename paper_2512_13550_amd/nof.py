@@ -56,6 +56,16 @@ _sig("nof_occ_energy_grad", _i, _i, _i, _i, _vp, _i, _i, _vp, _vp, _i, _vp, _vp,
 _sig("nof_occ_optimize", _i, _i, _i, _i, _vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i, _d, _vp,
      _sz, _vp)
 _sig("nof_functional_coeffs", _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
+_PLAN_ARGS = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_sig("nof_plan_create", _i, ctypes.POINTER(_vp), _i, _i, _i, _i, _i)
+_sig("nof_plan_ws", _sz, _vp)
+_sig("nof_plan_get_config", _i, _vp, ctypes.POINTER(_i))
+_sig("nof_plan_set_config", _i, _vp, ctypes.POINTER(_i))
+_sig("nof_plan_iteration", _i, *_PLAN_ARGS)
+_sig("nof_plan_autotune", _i, *_PLAN_ARGS)
+_sig("nof_plan_capture", _i, *_PLAN_ARGS)
+_sig("nof_plan_launch", _i, _vp, _vp)
+_sig("nof_plan_destroy", _i, _vp)
 
 MAP_TRIG, MAP_SOFTMAX = 0, 1
 FUNC_HF, FUNC_PNOF5 = 0, 1
@@ -66,7 +76,9 @@ DECLARED = [
     "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
-    "nof_functional_coeffs",
+    "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
+    "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
+    "nof_plan_launch", "nof_plan_destroy",
 ]
 
 
@@ -340,3 +352,64 @@ class Occupations:
                                         _f64(n, "n"), _p(cJ), _p(cK), _p(self.info), _p(self.ws),
                                         self.ws.numel(), stream_handle(stream)), "nof_functional_coeffs")
         return cJ, cK
+
+
+class BatchPlan:
+    """Batched iteration for ninst instances sharing B (nof_plan_*).
+
+    Inputs are bound at construction (their device buffers are read on every
+    call, so update them in place between iterations)."""
+
+    def __init__(self, B, C, H, n, cJ, cK, prec=None):
+        self.ninst, nbf, norb = C.shape
+        naux = B.shape[0]
+        bt = _TDT[B.dtype]
+        self.prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+        self.handle = _vp()
+        check(lib.nof_plan_create(ctypes.byref(self.handle), self.ninst, naux, nbf, norb, self.prec),
+              "nof_plan_create")
+        dev = B.device
+        self.ws = workspace(lib.nof_plan_ws(self.handle), dev)
+        self.inputs = (B, C, H, n, cJ, cK)
+        for t, name in zip(self.inputs[1:], ("C", "H", "n", "cJ", "cK")):
+            _f64(t, name)
+        self.E = torch.empty(self.ninst, dtype=torch.float64, device=dev)
+        self.lam = torch.empty((self.ninst, norb, norb), dtype=torch.float64, device=dev)
+        self.g = torch.empty_like(self.lam)
+
+    def _args(self):
+        B, C, H, n, cJ, cK = self.inputs
+        return (self.handle, _p(B), _p(C), _p(H), _p(n), _p(cJ), _p(cK), _p(self.E), _p(self.lam),
+                _p(self.g), _p(self.ws), self.ws.numel())
+
+    def iteration(self, stream=None):
+        check(lib.nof_plan_iteration(*self._args(), stream_handle(stream)), "nof_plan_iteration")
+        return self.E, self.lam, self.g
+
+    def autotune(self, stream=None):
+        check(lib.nof_plan_autotune(*self._args(), stream_handle(stream)), "nof_plan_autotune")
+        return self.config
+
+    def capture(self, stream):
+        check(lib.nof_plan_capture(*self._args(), stream_handle(stream)), "nof_plan_capture")
+
+    def launch(self, stream):
+        check(lib.nof_plan_launch(self.handle, stream_handle(stream)), "nof_plan_launch")
+        return self.E, self.lam, self.g
+
+    @property
+    def config(self):
+        cfg = (ctypes.c_int * 4)()
+        check(lib.nof_plan_get_config(self.handle, cfg), "nof_plan_get_config")
+        return list(cfg)
+
+    @config.setter
+    def config(self, cfg):
+        arr = (ctypes.c_int * 4)(*[int(x) for x in cfg])
+        check(lib.nof_plan_set_config(self.handle, arr), "nof_plan_set_config")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.nof_plan_destroy(h)
+            self.handle = None

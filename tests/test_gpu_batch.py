@@ -1,0 +1,112 @@
+"""Batched finite-field form: one plan for many instances sharing B, checked
+against the single-instance C ABI (same library, already pinned to the
+oracle) and directly against the oracle; every tile configuration, the
+autotuner, and graph capture with several replays."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dfjk, functionals
+from paper_2512_13550_amd import inputs
+from gpu_util import dev, host, need_gpu, normwise
+
+pytestmark = pytest.mark.gpu
+
+
+def instances(nbf, naux, norb, ninst, seed, ns):
+    B = inputs.make_B(seed, nbf, naux, 25.0)
+    fi = inputs.field_instances(seed, nbf, norb, ns, ninst)
+    ng = max(1, (norb - ns) // ns)
+    members = np.array(inputs.pairing(norb, ns, ng))
+    cJ = np.empty((ninst, norb, norb)); cK = np.empty_like(cJ)
+    for i in range(ninst):
+        cJ[i], cK[i] = functionals.coefficients(fi["n"][i], members, "pnof5")
+    return B, fi["C"], fi["H"], fi["n"], cJ, cK
+
+
+def single(nof, Bd, C, H, n, cJ, cK, prec):
+    Cd = dev(C)
+    b, D = nof.mo_transform(Bd, Cd, prec=prec)
+    h = nof.one_electron(dev(H), Cd)
+    J, K = nof.jk_diag(b, D)
+    lam, g, _ = nof.gen_fock(b, D, dev(n), h, dev(cJ), dev(cK), prec=prec)
+    E = nof.energy(dev(n), h, J, K, dev(cJ), dev(cK))
+    return float(E), host(lam), host(g)
+
+
+@pytest.mark.parametrize("prec_name", ["f64", "f32"])
+def test_batch_matches_single_instance_every_config(prec_name):
+    nof = need_gpu()
+    ninst, nbf, naux, norb = 6, 130, 90, 110
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3001, 27)
+    tdt = torch.float64 if prec_name == "f64" else torch.float32
+    prec = nof.P_F64 if prec_name == "f64" else nof.P_F32
+    Bd = dev(B, tdt)
+    plan = nof.BatchPlan(Bd, dev(C), dev(H), dev(n), dev(cJ), dev(cK), prec=prec)
+    ref = [single(nof, Bd, C[i], H[i], n[i], cJ[i], cK[i], prec) for i in range(ninst)]
+    tol = 1e-12 if prec_name == "f64" else 2e-6
+    for cfg in ([128, 128, 128, 1], [64, 64, 64, 2], [64, 128, 64, 1], [128, 64, 128, 3]):
+        plan.config = cfg
+        E, lam, g = plan.iteration()
+        torch.cuda.synchronize()
+        for i in range(ninst):
+            assert abs(float(E[i]) - ref[i][0]) <= tol * abs(ref[i][0]), (cfg, i)
+            assert normwise(host(lam[i]), ref[i][1]) <= tol, (cfg, i)
+            assert normwise(host(g[i]), ref[i][2]) <= tol * 10, (cfg, i)
+    if prec_name == "f64":
+        for i in (0, ninst - 1):
+            o = dfjk.iteration(B, C[i], H[i], n[i], cJ[i], cK[i])
+            assert abs(float(E[i]) - o["E"]) <= 1e-10 * abs(o["E"])
+            assert normwise(host(lam[i]), o["lam"]) <= 1e-10
+
+
+def test_autotune_and_graph_replays():
+    nof = need_gpu()
+    ninst, nbf, naux, norb = 9, 100, 70, 96
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3002, 24)
+    Cd = dev(C)
+    plan = nof.BatchPlan(dev(B), Cd, dev(H), dev(n), dev(cJ), dev(cK))
+    cfg = plan.autotune()
+    print("tuned config", cfg, flush=True)
+    assert cfg[0] in (64, 128) and cfg[1] in (64, 128) and cfg[2] in (64, 128) and cfg[3] >= 1
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(s)
+    s.synchronize()
+    rng = np.random.default_rng(0)
+    for rep in range(3):
+        # eager work between replays: new orbitals written in place
+        y = inputs.make_antisym(7, rep, norb, 0.05)
+        C2 = np.stack([C[i] @ np.asarray(__import__("scipy").linalg.expm(y)) for i in range(ninst)])
+        Cd.copy_(dev(C2))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            plan.launch(s)
+        s.synchronize()
+        Eg, lg, gg = host(plan.E).copy(), host(plan.lam).copy(), host(plan.g).copy()
+        E2, l2, g2 = plan.iteration()
+        torch.cuda.synchronize()
+        assert np.array_equal(Eg, host(E2)), rep
+        assert np.array_equal(lg, host(l2)), rep
+        assert np.array_equal(gg, host(g2)), rep
+        o = dfjk.iteration(B, C2[rep], H[rep], n[rep], cJ[rep], cK[rep])
+        assert abs(Eg[rep] - o["E"]) <= 1e-10 * abs(o["E"])
+
+
+def test_field_workload_fp32_against_oracle():
+    """The 25-instance field workload (Nbf=300, Naux=1200, Norb=300) in FP32
+    with tuned tiles, checked on two instances against the FP64 oracle."""
+    nof = need_gpu()
+    w = inputs.WORKLOADS["field300"]
+    print("case field300 fp32", flush=True)
+    B, C, H, n, cJ, cK = instances(w.nbf, w.naux, w.norb, 25, w.seed, w.nstrong)
+    plan = nof.BatchPlan(dev(B, torch.float32), dev(C), dev(H), dev(n), dev(cJ), dev(cK),
+                         prec=nof.P_F32)
+    plan.autotune()
+    E, lam, g = plan.iteration()
+    torch.cuda.synchronize()
+    for i in (0, 24):
+        o = dfjk.iteration(B, C[i], H[i], n[i], cJ[i], cK[i])
+        print("field instance", i, "dE", float(E[i]) - o["E"], flush=True)
+        assert abs(float(E[i]) - o["E"]) <= 1e-7 * abs(o["E"])
+        assert normwise(host(lam[i]), o["lam"]) <= 2e-6
