@@ -305,6 +305,48 @@ int nof_plan_capture(nof_plan plan, const void* B, const double* C, const double
 int nof_plan_launch(nof_plan plan, hipStream_t stream);
 int nof_plan_destroy(nof_plan plan);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start of the occupation update (not part of the paper's method:
+ * its prediction is always refined by nof_occ_optimize).
+ *
+ * Network: 5 -> 128 -> 128 -> 1, tanh hidden units, output angle
+ * theta = (pi/2) sigmoid(z) with n = cos^2 theta.  params is one FP32 vector of
+ * nof_mlp_nparams() values: W1 [5][128], b1 [128], W2 [128][128], b2 [128],
+ * w3 [128], b3 (row-major, inputs first: h1 = tanh(x W1 + b1)).
+ *
+ * nof_mlp_features: X [norb][5] FP32 = per-feature z-scores over the orbitals
+ *   of (J_pp, K_pp, h_pp, mean_q J_pq, mean_q K_pq); h_pp = hdiag[p*hstride];
+ *   ws: nof_mlp_features_ws(norb) bytes.
+ * nof_mlp_targets: theta = arccos(sqrt(n)) (FP32) for n [count] (FP64, clamped
+ *   to [0, 1]): the training target whose cos^2 is the occupation.
+ * nof_mlp_forward: theta [rows] for X [rows][5].
+ * nof_mlp_loss_grad: loss = mean_r (theta_r - target_r)^2 (device scalar, may
+ *   be NULL) and its gradient grad [nparams]; partial sums per block of 64
+ *   rows are reduced in a fixed order in FP64.  ws: nof_mlp_ws(rows) bytes.
+ * nof_mlp_adam: in-place ADAM step on params with FP32 moments m, v (t >= 1).
+ * nof_mlp_warm_gamma: variables gamma [ns][ng] (FP64) of the occupation map
+ *   from predicted angles: n = cos^2 theta rescaled to sum to one in each
+ *   subspace, every share raised to at least nfloor (0 <= nfloor < 1/(ng+1))
+ *   and renormalised (with n_g raised to 1/2 for the trigonometric map), then
+ *   the inverse map (softmax: gamma_i = ln(n_{p_i}/n_g)).  ng <= 64.  Bad
+ *   member indices set info[2] = NOF_E_ARG (info may be NULL).
+ * ------------------------------------------------------------------------- */
+int nof_mlp_nparams(void);
+size_t nof_mlp_ws(int rows);
+size_t nof_mlp_features_ws(int norb);
+int nof_mlp_features(int norb, const double* hdiag, int hstride, const double* J,
+                     const double* K, float* X, void* ws, size_t ws_bytes, hipStream_t stream);
+int nof_mlp_targets(int n, const double* occ, float* theta, hipStream_t stream);
+int nof_mlp_forward(int rows, const float* X, const float* params, float* theta,
+                    hipStream_t stream);
+int nof_mlp_loss_grad(int rows, const float* X, const float* target, const float* params,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+int nof_mlp_adam(int nparams, float* params, const float* grad, float* m, float* v, int t,
+                 float lr, float beta1, float beta2, float eps, hipStream_t stream);
+int nof_mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map,
+                       const float* theta, double nfloor, double* gamma, int* info,
+                       hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,10 +99,11 @@ def target_angles(n):
     return np.arccos(np.sqrt(np.clip(n, 0.0, 1.0)))
 
 
-def warm_gamma(theta, members, mapping):
-    """Occupations cos^2(theta) projected onto each subspace's sum rule, then
-    mapped back to the optimiser's variables (softmax: gamma_i = log(n_pi/n_g);
-    trigonometric: the inverse trigonometric map with n_g >= 1/2)."""
+def warm_gamma(theta, members, mapping, nfloor=1e-12):
+    """Occupations cos^2(theta) projected onto each subspace's sum rule (each
+    share at least nfloor), then mapped back to the optimiser's variables
+    (softmax: gamma_i = log(n_pi/n_g); trigonometric: the inverse
+    trigonometric map with n_g >= 1/2)."""
     from oracle.occupations import inverse_trig
     n = np.cos(theta) ** 2
     ns, ng1 = members.shape
@@ -111,7 +112,7 @@ def warm_gamma(theta, members, mapping):
     for row in members:
         tot = n[row].sum()
         vals = n[row] / tot if tot > 0 else np.full(ng1, 1.0 / ng1)
-        vals = np.clip(vals, 1e-12, None)
+        vals = np.clip(vals, nfloor, None)
         if mapping == "trig" and vals[0] < 0.5:
             rest = vals[1:].sum()
             vals[1:] *= 0.5 / rest

@@ -419,4 +419,77 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
   });
 }
 
+int nof_mlp_nparams(void) { return mlp_nparams(); }
+
+int nof_mlp_targets(int n, const double* occ, float* theta, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (n < 1) return NOF_E_DIM;
+    if (!occ || !theta) return NOF_E_NULL;
+    return mlp_targets(n, occ, theta, stream);
+  });
+}
+
+size_t nof_mlp_ws(int rows) {
+  if (rows < 1) return 0;
+  return mlp_ws(rows);
+}
+
+size_t nof_mlp_features_ws(int norb) {
+  if (!dim_ok(norb)) return 0;
+  return align256((size_t)norb * 5 * sizeof(double));
+}
+
+int nof_mlp_features(int norb, const double* hdiag, int hstride, const double* J, const double* K,
+                     float* X, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb)) return NOF_E_DIM;
+    if (hstride < 1) return NOF_E_ARG;
+    if (!hdiag || !J || !K || !X) return NOF_E_NULL;
+    if (!ws || ws_bytes < nof_mlp_features_ws(norb)) return NOF_E_WORKSPACE;
+    return mlp_features(norb, hdiag, hstride, J, K, X, ws, stream);
+  });
+}
+
+int nof_mlp_forward(int rows, const float* X, const float* params, float* theta,
+                    hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (rows < 1 || rows > (1 << 28)) return NOF_E_DIM;
+    if (!X || !params || !theta) return NOF_E_NULL;
+    return mlp_forward(rows, X, params, theta, stream);
+  });
+}
+
+int nof_mlp_loss_grad(int rows, const float* X, const float* target, const float* params,
+                      float* grad, float* loss, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (rows < 1 || rows > (1 << 28)) return NOF_E_DIM;
+    if (!X || !target || !params || !grad) return NOF_E_NULL;
+    if (!ws || ws_bytes < mlp_ws(rows)) return NOF_E_WORKSPACE;
+    return mlp_loss_grad(rows, X, target, params, grad, loss, ws, stream);
+  });
+}
+
+int nof_mlp_adam(int nparams, float* params, const float* grad, float* m, float* v, int t,
+                 float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (nparams < 1) return NOF_E_DIM;
+    if (!params || !grad || !m || !v) return NOF_E_NULL;
+    if (t < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+      return NOF_E_ARG;
+    return mlp_adam(nparams, params, grad, m, v, t, lr, beta1, beta2, eps, stream);
+  });
+}
+
+int nof_mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map, const float* theta,
+                       double nfloor, double* gamma, int* info, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb) || ns < 1 || ng < 1 || ng > 64 || (long long)ns * (ng + 1) > norb)
+      return NOF_E_DIM;
+    if (map != NOF_MAP_TRIG && map != NOF_MAP_SOFTMAX) return NOF_E_ARG;
+    if (!(nfloor >= 0.0 && nfloor < 1.0 / (ng + 1))) return NOF_E_ARG;
+    if (!members || !theta || !gamma) return NOF_E_NULL;
+    return mlp_warm_gamma(norb, ns, ng, members, map, theta, nfloor, gamma, info, stream);
+  });
+}
+
 }  // extern "C"

@@ -138,6 +138,20 @@ int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func
 int functional_coeffs(int norb, int ns, int ng, const int* members, int func, const double* n,
                       double* cJ, double* cK, void* ws, int* bad, hipStream_t st);
 
+// Learned warm start (mlp.hip).
+int mlp_nparams();
+int mlp_targets(int n, const double* occ, float* theta, hipStream_t st);
+size_t mlp_ws(int rows);
+int mlp_forward(int rows, const float* X, const float* P, float* theta, hipStream_t st);
+int mlp_loss_grad(int rows, const float* X, const float* target, const float* P, float* grad,
+                  float* loss, void* ws, hipStream_t st);
+int mlp_adam(int n, float* p, const float* g, float* m, float* v, int t, float lr, float b1,
+             float b2, float eps, hipStream_t st);
+int mlp_features(int norb, const double* hdiag, int hstride, const double* J, const double* K,
+                 float* X, void* ws, hipStream_t st);
+int mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map, const float* theta,
+                   double nfloor, double* gamma, int* info, hipStream_t st);
+
 int coeffs_from_cumulant(int norb, const double* n, const double* Delta,
                          const double* Pi, double* cJ, double* cK, hipStream_t st);
 

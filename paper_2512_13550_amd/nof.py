@@ -66,6 +66,16 @@ _sig("nof_plan_autotune", _i, *_PLAN_ARGS)
 _sig("nof_plan_capture", _i, *_PLAN_ARGS)
 _sig("nof_plan_launch", _i, _vp, _vp)
 _sig("nof_plan_destroy", _i, _vp)
+_sig("nof_mlp_nparams", _i)
+_sig("nof_mlp_ws", _sz, _i)
+_sig("nof_mlp_features_ws", _sz, _i)
+_sig("nof_mlp_features", _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("nof_mlp_forward", _i, _i, _vp, _vp, _vp, _vp)
+_sig("nof_mlp_targets", _i, _i, _vp, _vp, _vp)
+_sig("nof_mlp_loss_grad", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("nof_mlp_adam", _i, _i, _vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+     ctypes.c_float, _vp)
+_sig("nof_mlp_warm_gamma", _i, _i, _i, _i, _vp, _i, _vp, _d, _vp, _vp, _vp)
 
 MAP_TRIG, MAP_SOFTMAX = 0, 1
 FUNC_HF, FUNC_PNOF5 = 0, 1
@@ -78,7 +88,8 @@ DECLARED = [
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
-    "nof_plan_launch", "nof_plan_destroy",
+    "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
+    "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
 ]
 
 
@@ -413,3 +424,66 @@ class BatchPlan:
         if h is not None and h.value:
             lib.nof_plan_destroy(h)
             self.handle = None
+
+
+def _f32(t, name):
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return _p(t)
+
+
+def mlp_features(h, J, K, stream=None):
+    """[norb][5] standardised FP32 features (nof_mlp_features); h full or its diagonal."""
+    norb = J.shape[0]
+    X = torch.empty((norb, 5), dtype=torch.float32, device=J.device)
+    ws = workspace(lib.nof_mlp_features_ws(norb), J.device)
+    hs = norb + 1 if h.dim() == 2 else 1
+    check(lib.nof_mlp_features(norb, _f64(h, "h"), hs, _f64(J, "J"), _f64(K, "K"), _p(X), _p(ws),
+                               ws.numel(), stream_handle(stream)), "nof_mlp_features")
+    return X
+
+
+def mlp_targets(n, stream=None):
+    theta = torch.empty(n.numel(), dtype=torch.float32, device=n.device)
+    check(lib.nof_mlp_targets(n.numel(), _f64(n, "n"), _p(theta), stream_handle(stream)), "nof_mlp_targets")
+    return theta
+
+
+def mlp_forward(X, params, theta=None, stream=None):
+    rows = X.shape[0]
+    if theta is None:
+        theta = torch.empty(rows, dtype=torch.float32, device=X.device)
+    check(lib.nof_mlp_forward(rows, _f32(X, "X"), _f32(params, "params"), _p(theta),
+                              stream_handle(stream)), "nof_mlp_forward")
+    return theta
+
+
+def mlp_loss_grad(X, target, params, grad=None, loss=None, ws=None, stream=None):
+    rows = X.shape[0]
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float32, device=X.device)
+    need = lib.nof_mlp_ws(rows)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, X.device)
+    check(lib.nof_mlp_loss_grad(rows, _f32(X, "X"), _f32(target, "target"), _f32(params, "params"),
+                                _p(grad), _p(loss), _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(lib.nof_mlp_adam(params.numel(), _f32(params, "params"), _f32(grad, "grad"), _f32(m, "m"),
+                           _f32(v, "v"), int(t), lr, beta1, beta2, eps, stream_handle(stream)),
+          "nof_mlp_adam")
+
+
+def mlp_warm_gamma(theta, members, mapping, norb, nfloor=1e-12, info=None, stream=None):
+    ns, ng1 = members.shape
+    gamma = torch.empty((ns, ng1 - 1), dtype=torch.float64, device=theta.device)
+    check(lib.nof_mlp_warm_gamma(norb, ns, ng1 - 1, _i32(members, "members"), int(mapping),
+                                 _f32(theta, "theta"), float(nfloor), _p(gamma), _p(info),
+                                 stream_handle(stream)),
+          "nof_mlp_warm_gamma")
+    return gamma
