@@ -157,7 +157,8 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     g1.S = nullptr; g1.lds = 0;
     g1.Out = T; g1.ldo = norb; g1.so = (long long)nbf * norb;
     g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
-    g1.role = GemmRole::TransformStage1;
+    // the one-electron transform (naux = 1) is attributed to the small products
+    g1.role = naux > 1 ? GemmRole::TransformStage1 : GemmRole::Small;
     if (!bf) return gemm_tn(g1, Bt, NOF_F64, Tt, prec, stream);
     NOF_TRY(split_C(nbf, norb, C, prec, Bt, ws, stream));
     g1.Y = ws; g1.ldy = presplit_ldk(nbf); g1.psy = (long long)norb * presplit_ldk(nbf);
@@ -185,7 +186,7 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     g2.S = nullptr; g2.lds = 0;
     g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
     g2.Dg = D; g2.sd = norb; g2.sym = true;
-    g2.role = GemmRole::TransformStage2;
+    g2.role = naux > 1 ? GemmRole::TransformStage2 : GemmRole::Small;
     if (!bf) return gemm_tn(g2, NOF_F64, Tt, bt, prec, stream);
     NOF_TRY(split_C(nbf, norb, C, prec, NOF_F32, ws, stream));
     g2.X = ws; g2.ldx = presplit_ldk(nbf); g2.psx = (long long)norb * presplit_ldk(nbf);
