@@ -334,9 +334,11 @@ def run_warmstart(nof, ntrain, nheld=20):
     t0 = time.time()
     fac = warmstart.InstanceFactory(nof, gap=0.5)
     rng = np.random.default_rng(4000)
-    X, T, it_train = warmstart.build_dataset(nof, fac, range(4000, 4000 + ntrain), (100, 200), (15, 50), rng)
+    log = lambda m: print(f"# warmstart {m}", file=sys.stderr, flush=True)
+    X, T, it_train = warmstart.build_dataset(nof, fac, range(4000, 4000 + ntrain), (100, 200), (15, 50), rng,
+                                             log=log)
     t_data = time.time() - t0
-    params, hist = warmstart.train(nof, X, T, epochs=40, batch=4096, lr=2e-3, seed=1)
+    params, hist = warmstart.train(nof, X, T, epochs=40, batch=4096, lr=2e-3, seed=1, log=log)
     t_train = time.time() - t0 - t_data
     rows = warmstart.evaluate(nof, fac, params, range(9000, 9000 + nheld), 500, 125)
     cold = np.array([r["iters_cold"] for r in rows]); warm = np.array([r["iters_warm"] for r in rows])

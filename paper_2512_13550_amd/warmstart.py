@@ -78,10 +78,12 @@ def solve(inst, gamma0, maxit=3000, tol=1e-8):
     return float(E), n, int(info[0]), bool(info[1]), g
 
 
-def build_dataset(nof, factory, seeds, sizes, ns_range, rng):
+def build_dataset(nof, factory, seeds, sizes, ns_range, rng, log=None):
     """Features and target angles of the converged ONs of each instance."""
     Xs, Ts, iters = [], [], []
-    for s in seeds:
+    for k, s in enumerate(seeds):
+        if log and k % 500 == 0:
+            log(f"instance {k}")
         nbf = int(rng.choice(sizes))
         ns = int(rng.integers(ns_range[0], ns_range[1] + 1))
         inst = factory.make(int(s), nbf, ns)
