@@ -155,12 +155,17 @@ def make_H(seed: int, nbf: int) -> np.ndarray:
 
 
 def make_occupations(seed: int, norb: int, nstrong: int) -> np.ndarray:
-    """Strong orbitals first: 1-U(1e-3,5e-2); the rest U(0,2e-2); sum = nstrong."""
+    """Strong orbitals first: 1-U(1e-3,5e-2); the rest U(0,2e-2); the weak
+    occupations are then rescaled so that the total is nstrong (the number of
+    electron pairs).  Rescaling only the weak part keeps every n in [0, 1]
+    even when half of the orbitals are strong."""
     rng = np.random.default_rng([int(seed), 0x0])
     n = np.empty(norb)
     n[:nstrong] = 1.0 - rng.uniform(1e-3, 5e-2, nstrong)
     n[nstrong:] = rng.uniform(0.0, 2e-2, norb - nstrong)
-    n *= nstrong / n.sum()
+    weak = n[nstrong:].sum()
+    if norb > nstrong and weak > 0:
+        n[nstrong:] *= (nstrong - n[:nstrong].sum()) / weak
     assert np.all(n >= 0.0) and np.all(n <= 1.0)
     return n
 

@@ -1,0 +1,108 @@
+"""Parity at the benchmark's full sizes, in its launch configuration.
+
+c500 (Nbf=500, Naux=2000, Norb=500): the whole iteration as bench.py runs it
+(stage 1, stage 2, h, J, generalized Fock with fused K, energy) against the
+complete FP64 oracle, element by element, for the FP64, FP32 and BF16 x6 forms.
+
+chain1000 (Nbf=1000, Naux=4000, Norb=1000): FP64 against the oracle on
+sampled outputs it computes slab by slab (b elements, J and K on a sample of
+orbitals), the orthogonal sum rules that hold at any size, and the BF16 x6
+form's energy error against the FP64 GPU result.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dfjk
+from paper_2512_13550_amd import inputs
+from gpu_util import dev, host, need_gpu, normwise
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_step(nof, B, C, H, n, cJ, cK, prec, dt):
+    naux, nbf, _ = B.shape
+    norb = C.shape[1]
+    T = torch.empty((naux, nbf, norb), dtype=dt, device="cuda")
+    b = torch.empty((naux, norb, norb), dtype=dt, device="cuda")
+    D = torch.empty((naux, norb), dtype=torch.float64, device="cuda")
+    nof.transform_stage1(B, C, T, prec=prec)
+    nof.transform_stage2(T, C, b, D, prec=prec)
+    del T
+    h = nof.one_electron(H, C)
+    J, _ = nof.jk_diag(b, D, want_K=False)
+    lam, g, K = nof.gen_fock(b, D, n, h, cJ, cK, want_K=True, prec=prec)
+    E = nof.energy(n, h, J, K, cJ, cK)
+    torch.cuda.synchronize()
+    return b, D, dict(h=host(h), J=host(J), K=host(K), lam=host(lam), g=host(g), E=float(E))
+
+
+def test_c500_full_iteration_all_forms():
+    nof = need_gpu()
+    w = inputs.WORKLOADS["c500"]
+    print("case c500 full", flush=True)
+    B = inputs.make_B(w.seed, w.nbf, w.naux, w.decay, threads=16)
+    C = inputs.make_C(w.seed, w.nbf, w.norb)
+    H = inputs.make_H(w.seed, w.nbf)
+    n = inputs.make_occupations(w.seed, w.norb, w.nstrong)
+    nn = np.outer(n, n)
+    cJ, cK = 2.0 * nn, nn
+    ref = dfjk.iteration(B, C, H, n, cJ, cK)
+    print("oracle E", ref["E"], flush=True)
+    Cd, Hd, nd, cJd, cKd = dev(C), dev(H), dev(n), dev(cJ), dev(cK)
+    bounds = {"f64": (1e-10, 1e-10), "f32": (2e-6, 1e-8), "bf16x6": (5e-7, 2e-9)}
+    for form, prec, dt in (("f64", nof.P_F64, torch.float64), ("f32", nof.P_F32, torch.float32),
+                           ("bf16x6", nof.P_BF16X6, torch.float32)):
+        Bd = dev(B, torch.float64 if form == "f64" else torch.float32)
+        b, D, got = gpu_step(nof, Bd, Cd, Hd, nd, cJd, cKd, prec, dt)
+        del Bd
+        errs = {k: normwise(got[k], ref[k]) for k in ("h", "J", "K", "lam", "g")}
+        errs["b"] = normwise(host(b), ref["b"])
+        errs["D"] = normwise(host(D), ref["D"])
+        errs["E"] = abs(got["E"] - ref["E"]) / abs(ref["E"])
+        print(form, {k: f"{v:.2e}" for k, v in errs.items()}, "dE Eh", got["E"] - ref["E"], flush=True)
+        del b, D
+        torch.cuda.empty_cache()
+        tol, tolE = bounds[form]
+        for k in ("b", "D", "J", "K", "lam"):
+            assert errs[k] <= tol, (form, k, errs[k])
+        assert errs["E"] <= tolE, (form, errs["E"])
+
+
+def test_chain1000_sampled_and_precision_form():
+    nof = need_gpu()
+    w = inputs.WORKLOADS["chain1000"]
+    print("case chain1000", flush=True)
+    B = inputs.make_B(w.seed, w.nbf, w.naux, w.decay, threads=16)
+    C = inputs.make_C(w.seed, w.nbf, w.norb)
+    H = inputs.make_H(w.seed, w.nbf)
+    n = inputs.make_occupations(w.seed, w.norb, w.nstrong)
+    nn = np.outer(n, n)
+    Cd, Hd, nd, cJd, cKd = dev(C), dev(H), dev(n), dev(2.0 * nn), dev(nn)
+    Bd = dev(B)
+    b, D, got64 = gpu_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_F64, torch.float64)
+    # sampled oracle values, slab by slab
+    rng = np.random.default_rng(0)
+    S = np.sort(rng.choice(w.norb, 6, replace=False))
+    CS = C[:, S]
+    bSS = np.einsum("mp,Pmn,nq->Ppq", CS, B, CS, optimize=True)      # b^P on the sample, all P
+    DS = np.diagonal(bSS, axis1=1, axis2=2)
+    J_ref = DS.T @ DS
+    K_ref = np.einsum("Ppq,Ppq->pq", bSS, bSS)
+    bh = host(b[:, S][:, :, S])
+    assert normwise(bh, bSS) <= 1e-10
+    assert normwise(got64["J"][np.ix_(S, S)], J_ref) <= 1e-10
+    assert normwise(got64["K"][np.ix_(S, S)], K_ref) <= 1e-10
+    # orthogonal sum rules (Norb = Nbf): sum K = sum_P ||B^P||_F^2, sum J = sum_P (tr B^P)^2
+    sK = float(np.einsum("Pmn,Pmn->", B, B))
+    sJ = float(np.sum(np.trace(B, axis1=1, axis2=2) ** 2))
+    assert abs(got64["K"].sum() - sK) <= 1e-10 * sK
+    assert abs(got64["J"].sum() - sJ) <= 1e-10 * sJ
+    del b, D, Bd
+    torch.cuda.empty_cache()
+    Bd = dev(B, torch.float32)
+    b, D, got = gpu_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_BF16X6, torch.float32)
+    dE = got["E"] - got64["E"]
+    print("chain1000 E64", got64["E"], "bf16x6 dE (Eh)", dE, "max dJ", np.abs(got["J"] - got64["J"]).max(),
+          "max dK", np.abs(got["K"] - got64["K"]).max(), flush=True)
+    assert abs(dE) <= 2e-9 * abs(got64["E"])
