@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c500")
     ap.add_argument("--forms", default="f32,bf16x3,bf16x6,bf16B",
-                    help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16B (B stored in BF16)")
+                    help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16x10, "
+                         "bf16B (B stored in BF16)")
     ap.add_argument("--cpu-slabs", type=int, default=160,
                     help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--batched", type=int, default=1,
@@ -120,7 +121,8 @@ def main():
     flops = algorithmic_flops(nbf, naux, norb)
 
     PRECS = {"f64": nof.P_F64, "f32": nof.P_F32, "bf16x1": nof.P_BF16X1, "bf16x3": nof.P_BF16X3,
-             "bf16x6": nof.P_BF16X6, "bf16B": nof.P_BF16X6}
+             "bf16x6": nof.P_BF16X6, "bf16x10": nof.P_BF16X10,
+             "bf16B": nof.P_BF16X6}
 
     def run(B, prec_name, steps, warmup):
         dt = torch.float64 if prec_name == "f64" else torch.float32

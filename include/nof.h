@@ -66,10 +66,17 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2 } nof_dtype;
  *   NOF_P_BF16X1  one BF16 product, FP32 accumulation.
  *   NOF_P_BF16X3  operands split into BF16 hi+lo, products hi*hi+hi*lo+lo*hi.
  *   NOF_P_BF16X6  operands split into BF16 hi+mid+lo, the six products whose
- *                 combined order of magnitude is at most two splits down.
+ *                 combined order of magnitude is at most two splits down;
+ *                 every 32-deep stage is added into FP64 accumulators.
+ *   NOF_P_BF16X10 fixed-point split: per row of an operand and 32-deep
+ *                 stage, four BF16 pieces on the grids 2^(E-8)..2^(E-32)
+ *                 below the stage's largest magnitude 2^E; the ten products
+ *                 of order <= 3.  The leading products of a stage sum
+ *                 exactly in FP32 and are added to FP64 every stage.
  * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
 typedef enum {
-  NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4
+  NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4,
+  NOF_P_BF16X10 = 5
 } nof_prec;
 
 /* Human-readable text for a status code (static storage, never NULL). */
@@ -89,9 +96,10 @@ const char* nof_status_str(int status);
  * prec / storage:
  *     NOF_P_F64            Bt = bt = NOF_F64
  *     NOF_P_F32            Bt = bt = NOF_F32
- *     NOF_P_BF16X1/X3/X6   Bt = NOF_F32 (or NOF_BF16 with X3/X6), bt = NOF_F32;
+ *     NOF_P_BF16X1..X10    Bt = NOF_F32 (or NOF_BF16 with X3/X6), bt = NOF_F32;
  *                          B and T are split into BF16 pieces in the loaders,
- *                          C once per call (three pieces for a BF16-stored B).
+ *                          C once per call (three pieces for a BF16-stored B,
+ *                          four with X10).
  * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C and
  *     the BF16 pieces of C).
  *

@@ -1,5 +1,6 @@
 // extern "C" entry points declared in include/nof.h: host-side validation,
 // workspace layout and the launch sequence of each call.
+#include <algorithm>
 #include <new>
 
 #include "common.h"
@@ -122,18 +123,20 @@ size_t stage_ws(int nbf, int norb, int prec, int Bt) {
 
 int split_C(int nbf, int norb, const double* C, int prec, int Bt, void* ws, hipStream_t stream) {
   const int np = Bt == NOF_BF16 ? 3 : bf16_pieces(prec);
-  return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream);
+  return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream,
+                       prec == NOF_P_BF16X10);
 }
 
 size_t nof_mo_transform_stage_ws(int nbf, int norb, int prec) {
   if (!dim_ok(nbf) || !dim_ok(norb) || !prec_ok(prec)) return 0;
-  return stage_ws(nbf, norb, prec, NOF_BF16);
+  // B may be given in FP32 or BF16: size for the larger of the two splits of C
+  return std::max(stage_ws(nbf, norb, prec, NOF_F32), stage_ws(nbf, norb, prec, NOF_BF16));
 }
 
 size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt) || !b_input_ok(prec, Bt)) return 0;
-  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(nbf, norb, prec, NOF_BF16);
+  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(nbf, norb, prec, Bt);
 }
 
 int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, const double* C,

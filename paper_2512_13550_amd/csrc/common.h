@@ -75,16 +75,20 @@ struct GemmDesc {
 int gemm_tn(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
 
 // Split-precision BF16 form of the same contract (gemm_bf16.hip); prec is one
-// of NOF_P_BF16X1/X3/X6; x_t may be NOF_BF16 for the first transform stage.
+// of NOF_P_BF16X1/X3/X6/X10; x_t may be NOF_BF16 for the first transform stage.
 int gemm_bf16(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
 // Split a k-major FP64 matrix into np bf16 planes [np][ncol][ldk] (gemm_bf16.hip).
+// fixed: the four fixed-point planes of the x10 form (np = 4, ldk % 32 == 0).
 int presplit_bf16(const double* A, int K, int ncol, int lda, int ldk, int np, void* out,
-                  hipStream_t st);
-inline int bf16_pieces(int prec) { return prec == NOF_P_BF16X1 ? 1 : prec == NOF_P_BF16X3 ? 2 : 3; }
+                  hipStream_t st, bool fixed = false);
+inline int bf16_pieces(int prec) {
+  return prec == NOF_P_BF16X1 ? 1 : prec == NOF_P_BF16X3 ? 2 : prec == NOF_P_BF16X10 ? 4 : 3;
+}
 inline long long presplit_ldk(int K) { return ((long long)K + 31) / 32 * 32; }
 
 inline bool is_bf16_prec(int prec) {
-  return prec == NOF_P_BF16X1 || prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6;
+  return prec == NOF_P_BF16X1 || prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6 ||
+         prec == NOF_P_BF16X10;
 }
 inline int gemm_any(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st) {
   return is_bf16_prec(prec) ? gemm_bf16(d, x_t, y_t, out_t, prec, st)

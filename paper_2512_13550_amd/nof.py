@@ -21,7 +21,7 @@ lib = ctypes.CDLL(LIB_PATH)
 # status codes and enums (mirror include/nof.h)
 OK, E_NULL, E_DIM, E_DTYPE, E_PREC, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_ARG = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32, BF16 = 0, 1, 2
-P_F64, P_F32, P_BF16X1, P_BF16X3, P_BF16X6 = 0, 1, 2, 3, 4
+P_F64, P_F32, P_BF16X1, P_BF16X3, P_BF16X6, P_BF16X10 = 0, 1, 2, 3, 4, 5
 
 _vp, _i, _sz, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
 

@@ -10,6 +10,17 @@ safety factor of ~10 on the observed errors:
 and the energy |dE|/|E| <= 2e-2, 1e-5, 5e-8 respectively.  B stored in BF16 is
 compared against the oracle evaluated on the BF16-rounded B (the arithmetic
 error alone), with the x6 bounds.
+
+x10 (fixed-point pieces, exact leading products) is compared against the
+oracle on the FP32-rounded B, so that only the arithmetic remains: the
+representation error of four pieces is 2^-33 of a stage's largest element and
+the dropped products are of order 2^-32, so what is left is the FP32 storage of
+T and b (unit roundoff u = 2^-24, twice: normwise <= 2u = 1.2e-7), bound 3e-7;
+the energy, a sum over those stored values, |dE|/|E| <= 2e-8 (observed <= 4.3e-9).
+A cancellation case pins the exactness itself: with paired rows whose products
+cancel, the exact result is zero and x10 must return it to 2^-30 of the sum of
+the |products| (element-wise split pieces with the matrix cores' alignment
+leave errors of order 2^-24 of the largest product there).
 """
 import numpy as np
 import pytest
@@ -51,6 +62,63 @@ def test_bf16_split_forms(mode, nbf, naux, norb, seed):
     for k in ("b", "J", "K", "lam"):
         assert errs[k] <= tol, (k, errs[k])
     assert errs["E"] <= tolE
+
+
+@pytest.mark.parametrize("nbf,naux,norb,seed", [(48, 192, 48, 0), (300, 40, 260, 1), (130, 7, 97, 5)])
+def test_bf16_x10_fixed_point(nbf, naux, norb, seed):
+    nof = need_gpu()
+    print(f"case bf16 x10 nbf={nbf} naux={naux} norb={norb}", flush=True)
+    B, C, H, n, cJ, cK = case(nbf, naux, norb, seed)
+    B32 = B.astype(np.float32)
+    ref = dfjk.iteration(B32.astype(np.float64), C, H, n, cJ, cK)
+    got = run_gpu(nof, dev(B32, torch.float32), C, H, n, cJ, cK, nof.P_BF16X10)
+    errs = {k: normwise(got[k], ref[k]) for k in ("b", "J", "K", "lam", "g")}
+    errs["E"] = abs(got["E"] - ref["E"]) / abs(ref["E"])
+    print("x10", errs, flush=True)
+    for k in ("b", "J", "K", "lam"):
+        assert errs[k] <= 3e-7, (k, errs[k])
+    assert errs["E"] <= 2e-8
+
+
+def paired(rng, nrow, ncol, sign):
+    """Rows 2k and 2k+1 equal (sign=+1) or opposite (sign=-1), entries with
+    magnitudes spread over 2^-12..1."""
+    half = rng.standard_normal((nrow // 2, ncol)) * 2.0 ** rng.uniform(-12, 0, (nrow // 2, ncol))
+    out = np.empty((nrow, ncol))
+    out[0::2] = half
+    out[1::2] = sign * half
+    return out
+
+
+def test_bf16_x10_cancellation():
+    nof = need_gpu()
+    print("case bf16 x10 cancellation", flush=True)
+    rng = np.random.default_rng(7)
+    naux, nbf, norb = 3, 96, 80
+    # stage 1: B = V M V^T with V_k = e_2k - e_2k+1 (symmetric, B[:, 2k+1] = -B[:, 2k]);
+    # C with rows 2k and 2k+1 equal, so V^T C = 0 and T = B C = 0 exactly.
+    M = rng.standard_normal((naux, nbf // 2, nbf // 2)) * 2.0 ** rng.uniform(-12, 0, (naux, nbf // 2, nbf // 2))
+    M = 0.5 * (M + M.transpose(0, 2, 1))
+    V = np.zeros((nbf, nbf // 2))
+    V[0::2, np.arange(nbf // 2)] = 1.0
+    V[1::2, np.arange(nbf // 2)] = -1.0
+    B = np.einsum("ak,Pkl,bl->Pab", V, M, V).astype(np.float32)
+    C = paired(rng, nbf, norb, +1.0)
+    T = torch.empty((naux, nbf, norb), dtype=torch.float32, device="cuda")
+    nof.transform_stage1(dev(B, torch.float32), dev(C), T, prec=nof.P_BF16X10)
+    scale1 = np.einsum("Pab,bq->Paq", np.abs(B.astype(np.float64)), np.abs(C))
+    r1 = float(np.max(np.abs(host(T)) / scale1))
+    # stage 2: T with rows 2k+1 = -(rows 2k), C with rows 2k and 2k+1 equal: b = C^T T = 0
+    T2 = np.stack([paired(rng, nbf, norb, -1.0) for _ in range(naux)]).astype(np.float32)
+    b = torch.empty((naux, norb, norb), dtype=torch.float32, device="cuda")
+    D = torch.empty((naux, norb), dtype=torch.float64, device="cuda")
+    nof.transform_stage2(dev(T2, torch.float32), dev(C), b, D, prec=nof.P_BF16X10)
+    torch.cuda.synchronize()
+    scale2 = np.einsum("ap,Paq->Ppq", np.abs(C), np.abs(T2.astype(np.float64)))
+    r2 = float(np.max(np.abs(host(b)) / scale2))
+    r2d = float(np.max(np.abs(host(D)) / np.diagonal(scale2, axis1=1, axis2=2)))
+    print("x10 cancellation |out| / sum|products|:", r1, r2, r2d, flush=True)
+    assert r1 <= 2.0 ** -30 and r2 <= 2.0 ** -30 and r2d <= 2.0 ** -30
 
 
 @pytest.mark.parametrize("nbf,naux,norb,seed", [(48, 192, 48, 0), (300, 40, 260, 1)])
