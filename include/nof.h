@@ -56,8 +56,10 @@ typedef enum {
   NOF_E_INTERNAL = -99
 } nof_status;
 
-/* Storage type of a large tensor argument (B, b). */
-typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2 } nof_dtype;
+/* Storage type of a large tensor argument (B, b).
+ *   NOF_BF16X4  B as the four fixed-point BF16 planes written by nof_split_B
+ *               (NOF_P_BF16X10 only). */
+typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3 } nof_dtype;
 
 /* Arithmetic used by the matrix-core (MFMA) contractions.
  *   NOF_P_F64     FP64 MFMA, FP64 accumulation.
@@ -83,6 +85,25 @@ typedef enum {
 const char* nof_status_str(int status);
 
 /* ---------------------------------------------------------------------------
+ * Fixed-point split of the three-index tensor for NOF_P_BF16X10, done once
+ * per B (every orbital iteration reuses B; Single Point Energy Calculations,
+ * ERITYP='RI').  Row (P, mu) of B^P is cut into 32-deep blocks of nu; with
+ * 2^E above the largest |value| of a block, each value becomes
+ *   v = sum_{q<4} n_q 2^(E-8(q+1)) + r,  n_q integers (exact in BF16),
+ *   |n_0| <= 256, |n_q| <= 128 (q > 0), |r| <= 2^(E-33).
+ * B       [naux][nbf][nbf] FP64 or FP32 (Bt), symmetric, device.
+ * planes  out, at least nof_split_B_bytes(naux, nbf) bytes, device (caller
+ *         owned); layout [4][naux][nbf][ldk], ldk = nbf rounded up to a
+ *         multiple of 32, zero for nu >= nbf.  Pass it as B with
+ *         Bt = NOF_BF16X4 to nof_mo_transform / nof_mo_transform_stage1.
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_DTYPE (Bt not F64/F32),
+ *         NOF_E_WORKSPACE (planes_bytes too small), NOF_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t nof_split_B_bytes(int naux, int nbf);
+int nof_split_B(int naux, int nbf, const void* B, int Bt, void* planes, size_t planes_bytes,
+                hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Orbital transformation (Single Point Energy Calculations, ERITYP='RI':
  * the RI route whose transformation is fourth order).
  *
@@ -96,8 +117,10 @@ const char* nof_status_str(int status);
  * prec / storage:
  *     NOF_P_F64            Bt = bt = NOF_F64
  *     NOF_P_F32            Bt = bt = NOF_F32
- *     NOF_P_BF16X1..X10    Bt = NOF_F32 (or NOF_BF16 with X3/X6), bt = NOF_F32;
- *                          B and T are split into BF16 pieces in the loaders,
+ *     NOF_P_BF16X1..X10    Bt = NOF_F32 (or NOF_BF16 with X3/X6, or
+ *                          NOF_BF16X4 with X10), bt = NOF_F32;
+ *                          B and T are split into BF16 pieces in the loaders
+ *                          (B not at all when given as NOF_BF16X4 planes),
  *                          C once per call (three pieces for a BF16-stored B,
  *                          four with X10).
  * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C and
@@ -118,8 +141,10 @@ int nof_mo_transform(int naux, int nbf, int norb,
  *   stage 2:  b^P = C^T T^P, D[P][p] = b^P_pp     (exactly symmetric b)
  * Tt is the storage of b for the precision mode.  ws (at least
  * nof_mo_transform_stage_ws() bytes) holds the BF16 pieces of C in the split
- * forms; FP64/FP32 ignore it (it may be NULL). */
-size_t nof_mo_transform_stage_ws(int nbf, int norb, int prec);
+ * forms (and, for X10, the grid exponents of the operand split in the
+ * loader: rows of an FP32 B, columns of T); FP64/FP32 ignore it (it may be
+ * NULL).  The stages share nothing through ws. */
+size_t nof_mo_transform_stage_ws(int naux, int nbf, int norb, int prec);
 int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt,
                             const double* C, void* T, int Tt, int prec,
                             void* ws, size_t ws_bytes, hipStream_t stream);

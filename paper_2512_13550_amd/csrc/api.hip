@@ -73,6 +73,7 @@ bool prec_matches(int prec, int t) {
 
 // Storage of B for a precision mode: as b, or BF16 for the 3-piece split forms.
 bool b_input_ok(int prec, int Bt) {
+  if (Bt == NOF_BF16X4) return prec == NOF_P_BF16X10;
   if (prec_matches(prec, Bt)) return true;
   return Bt == NOF_BF16 && (prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6);
 }
@@ -114,29 +115,49 @@ const char* nof_status_str(int status) {
   }
 }
 
-// Bytes of the per-call scratch of one transform stage (bf16 planes of C).
-size_t stage_ws(int nbf, int norb, int prec, int Bt) {
+// Bytes of the per-call scratch of one transform stage: the BF16 planes of C
+// and, for x10, the grid exponents of the operand split in the loader.
+size_t fx_planes_bytes(int nbf, int norb) { return align256((size_t)4 * norb * presplit_ldk(nbf) * 2); }
+
+size_t stage_ws(int naux, int nbf, int norb, int prec, int Bt) {
   if (!is_bf16_prec(prec)) return 256;
+  if (prec == NOF_P_BF16X10)
+    return fx_planes_bytes(nbf, norb) + align256((size_t)naux * std::max(nbf, norb) * sizeof(int));
   const int np = Bt == NOF_BF16 ? 3 : bf16_pieces(prec);
   return align256((size_t)np * norb * presplit_ldk(nbf) * 2);
 }
 
 int split_C(int nbf, int norb, const double* C, int prec, int Bt, void* ws, hipStream_t stream) {
   const int np = Bt == NOF_BF16 ? 3 : bf16_pieces(prec);
-  return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream,
-                       prec == NOF_P_BF16X10);
+  return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream);
 }
 
-size_t nof_mo_transform_stage_ws(int nbf, int norb, int prec) {
-  if (!dim_ok(nbf) || !dim_ok(norb) || !prec_ok(prec)) return 0;
+size_t nof_mo_transform_stage_ws(int naux, int nbf, int norb, int prec) {
+  if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb) || !prec_ok(prec)) return 0;
   // B may be given in FP32 or BF16: size for the larger of the two splits of C
-  return std::max(stage_ws(nbf, norb, prec, NOF_F32), stage_ws(nbf, norb, prec, NOF_BF16));
+  return std::max(stage_ws(naux, nbf, norb, prec, NOF_F32), stage_ws(naux, nbf, norb, prec, NOF_BF16));
 }
 
 size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt) || !b_input_ok(prec, Bt)) return 0;
-  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(nbf, norb, prec, Bt);
+  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(naux, nbf, norb, prec, Bt);
+}
+
+size_t nof_split_B_bytes(int naux, int nbf) {
+  if (!dim_ok(naux) || !dim_ok(nbf)) return 0;
+  return (size_t)4 * naux * nbf * presplit_ldk(nbf) * 2;
+}
+
+int nof_split_B(int naux, int nbf, const void* B, int Bt, void* planes, size_t planes_bytes,
+                hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(nbf)) return NOF_E_DIM;
+    if (!B || !planes) return NOF_E_NULL;
+    if (Bt != NOF_F64 && Bt != NOF_F32) return NOF_E_DTYPE;
+    if (planes_bytes < nof_split_B_bytes(naux, nbf)) return NOF_E_WORKSPACE;
+    return fx_split_rows(B, Bt, (long long)naux * nbf, nbf, (int)presplit_ldk(nbf), planes, stream);
+  });
 }
 
 int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, const double* C,
@@ -150,7 +171,29 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     if (!prec_matches(prec, Tt)) return NOF_E_PREC;
     if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
     const bool bf = is_bf16_prec(prec);
-    if (bf && (!ws || ws_bytes < stage_ws(nbf, norb, prec, Bt))) return NOF_E_WORKSPACE;
+    if (bf && (!ws || ws_bytes < stage_ws(naux, nbf, norb, prec, Bt))) return NOF_E_WORKSPACE;
+    if (prec == NOF_P_BF16X10) {
+      // fixed-point form: C planes (one grid per column), B planes or FP32 B
+      // with one grid per row (B^P symmetric: row mu = column mu)
+      const long long ldk = presplit_ldk(nbf);
+      char* w = (char*)ws;
+      int* ex = (int*)(w + fx_planes_bytes(nbf, norb));
+      NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
+      FxDesc f{};
+      f.M = nbf; f.N = norb; f.K = nbf; f.batch = naux;
+      const bool planes = Bt == NOF_BF16X4;
+      f.X = B;
+      if (planes) {
+        f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
+      } else {
+        NOF_TRY(fx_row_exps(B, Bt, (long long)naux * nbf, nbf, ex, stream));
+        f.ldx = nbf; f.sx = (long long)nbf * nbf; f.ex = ex; f.sex = nbf;
+      }
+      f.Y = w; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk;
+      f.Out = (float*)T; f.ldo = norb; f.so = (long long)nbf * norb;
+      f.sym = false; f.role = 1;
+      return gemm_fx(f, planes, true, stream);
+    }
     // T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
     GemmDesc g1{};
     g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
@@ -179,7 +222,23 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     const bool bf = is_bf16_prec(prec);
-    if (bf && (!ws || ws_bytes < stage_ws(nbf, norb, prec, NOF_F32))) return NOF_E_WORKSPACE;
+    if (bf && (!ws || ws_bytes < stage_ws(naux, nbf, norb, prec, NOF_F32))) return NOF_E_WORKSPACE;
+    if (prec == NOF_P_BF16X10) {
+      // fixed-point form: C planes, T split in the loader on one grid per
+      // column q of T^P (a pass over T finds them)
+      const long long ldk = presplit_ldk(nbf);
+      char* w = (char*)ws;
+      int* ey = (int*)(w + fx_planes_bytes(nbf, norb));
+      NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
+      NOF_TRY(fx_col_exps((const float*)T, naux, nbf, norb, (long long)nbf * norb, ey, stream));
+      FxDesc f{};
+      f.M = norb; f.N = norb; f.K = nbf; f.batch = naux;
+      f.X = w; f.ldx = ldk; f.sx = 0; f.psx = (long long)norb * ldk;
+      f.Y = T; f.ldy = norb; f.sy = (long long)nbf * norb; f.ey = ey; f.sey = norb;
+      f.Out = (float*)b; f.ldo = norb; f.so = (long long)norb * norb;
+      f.Dg = D; f.sd = norb; f.sym = true; f.role = 2;
+      return gemm_fx(f, true, false, stream);
+    }
     // b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
     GemmDesc g2{};
     g2.M = norb; g2.N = norb; g2.K = nbf; g2.Ktot = 0;

@@ -28,6 +28,7 @@ inline size_t dtype_size(int t) {
     case NOF_F64: return 8;
     case NOF_F32: return 4;
     case NOF_BF16: return 2;
+    case NOF_BF16X4: return 8;                 // four planes (padded rows)
     default: return 0;
   }
 }
@@ -78,9 +79,30 @@ int gemm_tn(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_
 // of NOF_P_BF16X1/X3/X6/X10; x_t may be NOF_BF16 for the first transform stage.
 int gemm_bf16(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStream_t st);
 // Split a k-major FP64 matrix into np bf16 planes [np][ncol][ldk] (gemm_bf16.hip).
-// fixed: the four fixed-point planes of the x10 form (np = 4, ldk % 32 == 0).
+// Fixed-point (x10) transform stage on the matrix cores (gemm_fx.hip):
+//   Out_b[m][n] = sum_k X_b(k, m) Y_b(k, n)   (FP32 out, FP64 diagonal Dg if sym)
+// X: planes [4][..] at X + q*psx + b*sx + m*ldx + k, or FP32 at X + b*sx + k*ldx + m
+//    with row grid exponents ex[b*sex + m];  Y likewise (n for m, ey/sey).
+struct FxDesc {
+  int M, N, K, batch;
+  const void* X; long long ldx, sx, psx; const int* ex; long long sex;
+  const void* Y; long long ldy, sy, psy; const int* ey; long long sey;
+  float* Out; long long ldo, so;
+  double* Dg; long long sd;
+  bool sym;
+  int role;                        // 1 = transform stage 1, 2 = stage 2 (kernel symbol)
+};
+int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
+// Grid exponents (2^E above the largest |value|) of rows of A[nrow][K] (FP64/FP32)
+// and of the columns of A_b[K][N] (FP32, batch stride sa) -> e[b*N + n].
+int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st);
+int fx_col_exps(const float* A, int batch, int K, int N, long long sa, int* e, hipStream_t st);
+// Four fixed-point planes: of the columns of an FP64 k-major A[k][col] -> [4][ncol][ldk],
+// and of the rows of A[nrow][K] (FP64/FP32) -> [4][nrow][ldk]; zero for k >= K.
+int fx_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* out, hipStream_t st);
+int fx_split_rows(const void* A, int At, long long nrow, int K, int ldk, void* out, hipStream_t st);
 int presplit_bf16(const double* A, int K, int ncol, int lda, int ldk, int np, void* out,
-                  hipStream_t st, bool fixed = false);
+                  hipStream_t st);
 inline int bf16_pieces(int prec) {
   return prec == NOF_P_BF16X1 ? 1 : prec == NOF_P_BF16X3 ? 2 : prec == NOF_P_BF16X10 ? 4 : 3;
 }

@@ -20,7 +20,10 @@
 // is split once per call into bf16 planes (k_presplit) stored [piece][col][k],
 // so the loaders fill LDS with 16-byte copies.
 //
-// x10 (fixed-point split).  The matrix cores add the 32 products of one
+// x10 (fixed-point split; here for the exchange-type Fock term, whose
+// contraction runs over every (P, q) pair: the transform stages of x10, with
+// one grid per row over the whole contraction, are in gemm_fx.hip).  The
+// matrix cores add the 32 products of one
 // instruction with a datapath aligned to the largest term, so the sum of
 // element-wise split pieces is not correctly rounded and cancellation leaves
 // errors of many ulps of the result.  x10 therefore puts the pieces of a row
@@ -120,41 +123,6 @@ __global__ void k_presplit(const double* __restrict__ A, int K, int ncol, int ld
       const __bf16 p = (__bf16)(float)v;
       out[(long long)q * n + i] = p;
       v -= (double)(float)p;
-    }
-  }
-}
-
-// Fixed-point variant of k_presplit (x10): four planes, the grid of column col
-// in the 32-deep block kb set by the largest |A| of that block.  One thread per
-// (column, block).
-__global__ void k_presplit_fx(const double* __restrict__ A, int K, int ncol, int lda, int ldk,
-                              __bf16* __restrict__ out) {
-  const int nblk = ldk / KT;
-  const long long n = (long long)ncol * ldk;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)ncol * nblk;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int kb = (int)(i / ncol), col = (int)(i - (long long)kb * ncol);
-    double v[KT];
-    double m = 0.0;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      const int kk = kb * KT + k;
-      v[k] = kk < K ? A[(long long)kk * lda + col] : 0.0;
-      m = fmax(m, fabs(v[k]));
-    }
-    int E;
-    frexp(m, &E);                                   // m < 2^E
-    E = E < -90 ? -90 : (E > 128 ? 128 : E);
-    __bf16* o = out + (long long)col * ldk + kb * KT;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      double t = ldexp(v[k], 8 - E);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double nq = rint(t);
-        o[(long long)q * n + k] = (__bf16)(float)ldexp(nq, E - 8 * (q + 1));
-        t = (t - nq) * 256.0;
-      }
     }
   }
 }
@@ -463,7 +431,7 @@ int launch(const GemmDesc& d, hipStream_t st) {
   return launch_status();
 }
 
-// x6 and x10 accumulate in FP64 every stage; x1 and x3 keep FP32 within a batch.
+// x6 accumulates in FP64 every stage; x1 and x3 keep FP32 within a batch.
 template <int NX, int NY, int ORD, bool FX = false>
 int dispatch_types(const GemmDesc& d, int x_t, int y_t, int out_t, hipStream_t st) {
   constexpr bool A64 = ORD >= 2;
@@ -486,16 +454,7 @@ int dispatch_types(const GemmDesc& d, int x_t, int y_t, int out_t, hipStream_t s
 }  // namespace
 
 int presplit_bf16(const double* A, int K, int ncol, int lda, int ldk, int np, void* out,
-                  hipStream_t st, bool fixed) {
-  if (fixed) {
-    if (np != 4 || ldk % KT) return NOF_E_ARG;
-    const long long items = (long long)ncol * (ldk / KT);
-    long long g = (items + 255) / 256;
-    if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_presplit_fx, dim3((unsigned)g), dim3(256), 0, st, A, K, ncol, lda, ldk,
-                       (__bf16*)out);
-    return launch_status();
-  }
+                  hipStream_t st) {
   const long long n = (long long)ncol * ldk;
   long long g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -518,7 +477,11 @@ int gemm_bf16(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStrea
     case NOF_P_BF16X1: return dispatch_types<1, 1, 0>(d, x_t, y_t, out_t, st);
     case NOF_P_BF16X3: return dispatch_types<2, 2, 1>(d, x_t, y_t, out_t, st);
     case NOF_P_BF16X6: return dispatch_types<3, 3, 2>(d, x_t, y_t, out_t, st);
-    case NOF_P_BF16X10: return dispatch_types<4, 4, 3, true>(d, x_t, y_t, out_t, st);
+    case NOF_P_BF16X10:   // the transform stages of x10 run in gemm_fx.hip
+      if (d.role != GemmRole::ExchangeFock || x_t != NOF_F32 || y_t != NOF_F32 || out_t != NOF_F64 || !d.S)
+        return NOF_E_DTYPE;
+      return d.fold > 1 ? launch<4, 4, 3, float, float, double, true, false, false, true, 3, true>(d, st)
+                        : launch<4, 4, 3, float, float, double, false, false, false, true, 3, true>(d, st);
     default: return NOF_E_PREC;
   }
 }

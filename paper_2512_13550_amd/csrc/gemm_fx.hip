@@ -1,0 +1,445 @@
+// Fixed-point split-precision transform (the NOF_P_BF16X10 form of the two
+// stages of the orbital transformation, b^P = C^T B^P C).
+//
+//   Out_b[m][n] = sum_k X_b(k, m) * Y_b(k, n)
+//
+// The matrix cores add the 32 products of one BF16 instruction with a
+// datapath aligned to the largest term, so element-wise BF16 pieces (x6) do
+// not sum correctly rounded and cancellation leaves errors of many ulps of
+// the result.  Here every row m of X and every column n of Y gets one grid
+// over the whole contraction: with 2^E above its largest magnitude,
+//   x = sum_{q<4} n_q 2^(E-7-8q) + r,   n_q integers, |n_q| <= 128,
+//   |r| <= 2^(E-32)
+// (Ozaki, Ogita, Oishi and Rump, "Error-free transformations of matrix
+// multiplication by using fast routines of matrix multiplication", Numer.
+// Algorithms 2012, with BF16 pieces; each n_q 2^(...) is exact in BF16).  The
+// order-0 products n_0 n_0' are integers of at most 2^14 units of
+// 2^(Ex+Ey-14), so up to K = 1024 their running sum (<= 2^24 units) is exact
+// in FP32: it has its own accumulator.  Orders 1..3 (2^-8 and less of the
+// result) share a second FP32 accumulator.  The ten products of order <= 3
+// leave a truncation of order 2^-32 of |x||y|.  For K > 1024 the order-0 sum
+// is added to FP64 every 1024 terms (BIGK variant).
+//
+// Layout: 256 threads = 4 waves (2 x 2); the workgroup tile is 128 (m) x 64
+// (n), each wave 64 x 32 as 4 x 2 fragments of v_mfma_f32_16x16x32_bf16
+// (lane l holds 8 consecutive k of row l%16 at k offset 8*(l/16); output row
+// 4*(l/16)+r, column l%16).  Two workgroups share a compute unit, so one's
+// loads overlap the other's products.  LDS holds the four pieces as [row][k]
+// with rows padded to 40 elements (80 B).
+//
+// Operands are either pre-split planes (X: [4][..][m][ldk], k contiguous) or
+// FP32 values split in the loader against per-row / per-column grid
+// exponents computed by a pass before the product.
+#include "common.h"
+
+namespace nof {
+namespace {
+
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+constexpr int FM = 128;                 // tile rows
+constexpr int FN = 64;                  // tile columns
+constexpr int KT = 32;
+constexpr int NTHR = 256;
+constexpr int LROW = KT + 8;
+constexpr int EXACT_K = 1024;           // order-0 sums stay exact in FP32 up to this depth
+constexpr int EMIN = -90, EMAX = 128;   // grid exponent range (all scales normal FP32)
+
+__device__ __forceinline__ int xcd_logical(int w, int G) {
+  const int q = G >> 3, r = G & 7, x = w & 7, i = w >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ float pow2f(int e) { return __int_as_float((127 + e) << 23); }
+
+__device__ __forceinline__ int clamp_exp(int e) { return e < EMIN ? EMIN : (e > EMAX ? EMAX : e); }
+
+// Smallest E with 2^E > m, from the bits of a non-negative FP32 m.
+__device__ __forceinline__ int grid_exp_bits(unsigned mbits) {
+  return clamp_exp((int)(mbits >> 23) - 126);
+}
+
+// Four pieces of v on the grid of exponent E (|v| < 2^E).
+__device__ __forceinline__ void split_g(float v, int E, __bf16 (&p)[4]) {
+  float t = v * pow2f(7 - E);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float n = rintf(t);
+    p[q] = (__bf16)(n * pow2f(E - 7 - 8 * q));
+    t = (t - n) * 256.0f;
+  }
+}
+
+__device__ __forceinline__ void split_g64(double v, int E, __bf16 (&p)[4]) {
+  double t = ldexp(v, 7 - E);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double n = rint(t);
+    p[q] = (__bf16)(float)ldexp(n, E - 7 - 8 * q);
+    t = (t - n) * 256.0;
+  }
+}
+
+// Grid exponents of the rows of A[nrow][K] (rows contiguous): one wave per row.
+template <typename T>
+__global__ void k_row_exps(const T* __restrict__ A, long long nrow, int K, int* __restrict__ e) {
+  const int l = threadIdx.x & 63;
+  const long long wpb = blockDim.x >> 6;
+  for (long long row = blockIdx.x * wpb + (threadIdx.x >> 6); row < nrow; row += (long long)gridDim.x * wpb) {
+    const T* a = A + row * K;
+    double m = 0.0;
+    for (int k = l; k < K; k += 64) m = fmax(m, fabs((double)a[k]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (l == 0) {
+      int E;
+      frexp(m, &E);
+      e[row] = clamp_exp(E);
+    }
+  }
+}
+
+// Grid exponents of the columns of A_b[K][N] (FP32, batch stride sa):
+// e[b*N + n] from max_k |A_b[k][n]|; one thread per (b, n).
+__global__ void k_col_exps(const float* __restrict__ A, int batch, int K, int N, long long sa,
+                           int* __restrict__ e) {
+  const long long total = (long long)batch * N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / N;
+    const int n = (int)(i - b * N);
+    const float* a = A + b * sa + n;
+    unsigned m = 0;
+    for (int k = 0; k < K; ++k) m = max(m, __float_as_uint(a[(long long)k * N]) & 0x7fffffffu);
+    e[i] = grid_exp_bits(m);
+  }
+}
+
+// Planes of the columns of an FP64 k-major matrix A[k][col] (k < K):
+// out[q][col][ldk], one grid per column; one thread per column.
+__global__ void k_split_cols(const double* __restrict__ A, int K, int ncol, int lda, int ldk,
+                             __bf16* __restrict__ out) {
+  const long long plane = (long long)ncol * ldk;
+  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < ncol; col += gridDim.x * blockDim.x) {
+    double m = 0.0;
+    for (int k = 0; k < K; ++k) m = fmax(m, fabs(A[(long long)k * lda + col]));
+    int E;
+    frexp(m, &E);
+    E = clamp_exp(E);
+    __bf16* o = out + (long long)col * ldk;
+    for (int k = 0; k < ldk; ++k) {
+      __bf16 p[4];
+      split_g64(k < K ? A[(long long)k * lda + col] : 0.0, E, p);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q * plane + k] = p[q];
+    }
+  }
+}
+
+// Planes of the rows of A[nrow][K] (FP64 or FP32, rows contiguous):
+// out[q][row][ldk], one grid per row; one wave per row.
+template <typename T>
+__global__ void k_split_rows(const T* __restrict__ A, long long nrow, int K, int ldk,
+                             __bf16* __restrict__ out) {
+  const int l = threadIdx.x & 63;
+  const long long wpb = blockDim.x >> 6;
+  const long long plane = nrow * ldk;
+  for (long long row = blockIdx.x * wpb + (threadIdx.x >> 6); row < nrow; row += (long long)gridDim.x * wpb) {
+    const T* a = A + row * K;
+    double m = 0.0;
+    for (int k = l; k < K; k += 64) m = fmax(m, fabs((double)a[k]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    int E;
+    frexp(m, &E);
+    E = clamp_exp(E);
+    for (int k = l; k < ldk; k += 64) {
+      __bf16 p[4];
+      split_g64(k < K ? (double)a[k] : 0.0, E, p);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q * plane + row * ldk + k] = p[q];
+    }
+  }
+}
+
+// Linear tile index -> (tm, tn).  sym: tiles that meet the upper triangle,
+// i.e. tn >= 2 tm for 128 x 64 tiles.
+__device__ __forceinline__ void tile_of(int t, int tiles_m, int tiles_n, bool sym, int& tm, int& tn) {
+  if (!sym) {
+    tm = t / tiles_n;
+    tn = t - tm * tiles_n;
+    return;
+  }
+  int row = 0;
+  while (row < tiles_m && t >= tiles_n - 2 * row) { t -= tiles_n - 2 * row; ++row; }
+  tm = row;
+  tn = 2 * row + t;
+}
+
+template <bool XPS, bool YPS, bool BIGK>
+__device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_m, int tiles_n, int ntiles) {
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[4][FM][LROW];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[4][FN][LROW];
+
+  const int tid = threadIdx.x;
+  const int l = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  const int bb = logical / ntiles;
+  int tm, tn;
+  tile_of(logical - bb * ntiles, tiles_m, tiles_n, d.sym, tm, tn);
+  const int m0 = tm * FM, n0 = tn * FN;
+  const int nstage = (d.K + KT - 1) / KT;
+
+  // loaders: X row cx, k half kx (16 each); Y column cy, k quarter ky (8 each)
+  const int cx = tid & (FM - 1), kx = tid >> 7;
+  const int cy = tid & (FN - 1), ky = tid >> 6;
+  const bool xok = m0 + cx < d.M, yok = n0 + cy < d.N;
+  const int ex = (!XPS && xok) ? d.ex[(long long)bb * d.sex + m0 + cx] : 0;
+  const int ey = (!YPS && yok) ? d.ey[(long long)bb * d.sey + n0 + cy] : 0;
+
+  bf8v xp[XPS ? 4 : 1][2], yp[YPS ? 4 : 1];
+  float xr[XPS ? 1 : 16], yr[YPS ? 1 : 8];
+
+  auto load = [&](int s) {
+    const int k0 = s * KT;
+    if constexpr (XPS) {
+      const __bf16* p = (const __bf16*)d.X + (long long)bb * d.sx + (long long)(m0 + cx) * d.ldx + k0 + 16 * kx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          xp[q][h] = xok ? *(const bf8v*)(p + (long long)q * d.psx + 8 * h) : bf8v{};
+    } else {
+      const float* p = (const float*)d.X + (long long)bb * d.sx + (long long)(k0 + 16 * kx) * d.ldx + m0 + cx;
+      const int kl = d.K - k0 - 16 * kx;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[(long long)j * d.ldx] : 0.f;
+    }
+    if constexpr (YPS) {
+      const __bf16* p = (const __bf16*)d.Y + (long long)bb * d.sy + (long long)(n0 + cy) * d.ldy + k0 + 8 * ky;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yp[YPS ? q : 0] = yok ? *(const bf8v*)(p + (long long)q * d.psy) : bf8v{};
+    } else {
+      const float* p = (const float*)d.Y + (long long)bb * d.sy + (long long)(k0 + 8 * ky) * d.ldy + n0 + cy;
+      const int kl = d.K - k0 - 8 * ky;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) yr[YPS ? 0 : j] = (yok && j < kl) ? p[(long long)j * d.ldy] : 0.f;
+    }
+  };
+
+  auto store = [&]() {
+    if constexpr (XPS) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) *(bf8v*)&Xs[q][cx][16 * kx + 8 * h] = xp[q][h];
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        bf8v pk[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 p[4];
+          split_g(xr[XPS ? 0 : 8 * h + e], ex, p);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[q][cx][16 * kx + 8 * h] = pk[q];
+      }
+    }
+    if constexpr (YPS) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[q][cy][8 * ky] = yp[YPS ? q : 0];
+    } else {
+      bf8v pk[4];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 p[4];
+        split_g(yr[YPS ? 0 : e], ey, p);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[q][cy][8 * ky] = pk[q];
+    }
+  };
+
+  f4v acc0[4][2], acc1[4][2];
+  d4v acc64[BIGK ? 4 : 1][BIGK ? 2 : 1];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc0[i][j] = f4v{0, 0, 0, 0};
+      acc1[i][j] = f4v{0, 0, 0, 0};
+      if (BIGK) acc64[BIGK ? i : 0][BIGK ? j : 0] = d4v{0, 0, 0, 0};
+    }
+
+  if (nstage > 0) {
+    load(0);
+    store();
+  }
+  __syncthreads();
+  const int kl = 8 * (l >> 4);
+  for (int s = 0; s < nstage; ++s) {
+    if (s + 1 < nstage) load(s + 1);
+    bf8v a[4][4], b[2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[i][q] = *(const bf8v*)&Xs[q][wm * 64 + i * 16 + (l & 15)][kl];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const bf8v*)&Ys[q][wn * 32 + j * 16 + (l & 15)][kl];
+    // orders 3, 2, 1 into acc1 (smallest first), then the exact order 0
+#pragma unroll
+    for (int o = 3; o >= 1; --o)
+#pragma unroll
+      for (int px = 0; px <= o; ++px) {
+        const int py = o - px;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], b[j][py], acc1[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], acc0[i][j], 0, 0, 0);
+    if (BIGK && ((s + 1) % (EXACT_K / KT) == 0)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[BIGK ? i : 0][BIGK ? j : 0][r] += (double)acc0[i][j][r];
+          acc0[i][j] = f4v{0, 0, 0, 0};
+        }
+    }
+    __syncthreads();
+    if (s + 1 < nstage) store();
+    __syncthreads();
+  }
+
+  float* __restrict__ Out = d.Out + (long long)bb * d.so;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+        const int gn = n0 + wn * 32 + j * 16 + (l & 15);
+        double v = (double)acc0[i][j][r] + (double)acc1[i][j][r];
+        if (BIGK) v += acc64[BIGK ? i : 0][BIGK ? j : 0][r];
+        if (gm >= d.M || gn >= d.N) continue;
+        if (!d.sym) {
+          Out[(long long)gm * d.ldo + gn] = (float)v;
+        } else if (gm <= gn) {
+          Out[(long long)gm * d.ldo + gn] = (float)v;
+          Out[(long long)gn * d.ldo + gm] = (float)v;
+          if (gm == gn && d.Dg) d.Dg[(long long)bb * d.sd + gm] = v;
+        }
+      }
+}
+
+#define NOF_FX_KERNEL(NAME)                                                              \
+  template <bool XPS, bool YPS, bool BIGK>                                               \
+  __global__ __launch_bounds__(NTHR, BIGK ? 1 : 2) void NAME(FxDesc d, int tiles_m,      \
+                                                             int tiles_n, int ntiles) {  \
+    fx_body<XPS, YPS, BIGK>(d, tiles_m, tiles_n, ntiles);                                \
+  }
+NOF_FX_KERNEL(k_transform_stage1_fx)
+NOF_FX_KERNEL(k_transform_stage2_fx)
+#undef NOF_FX_KERNEL
+
+template <bool XPS, bool YPS, bool BIGK>
+int launch_fx(const FxDesc& d, hipStream_t st) {
+  const int tiles_m = (d.M + FM - 1) / FM;
+  const int tiles_n = (d.N + FN - 1) / FN;
+  int ntiles = 0;
+  if (d.sym) {
+    for (int tm = 0; tm < tiles_m; ++tm) ntiles += tiles_n - 2 * tm > 0 ? tiles_n - 2 * tm : 0;
+  } else {
+    ntiles = tiles_m * tiles_n;
+  }
+  const long long G = (long long)ntiles * d.batch;
+  if (G <= 0) return NOF_OK;
+  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  if (d.role == 1)
+    hipLaunchKernelGGL((k_transform_stage1_fx<XPS, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
+                       tiles_m, tiles_n, ntiles);
+  else
+    hipLaunchKernelGGL((k_transform_stage2_fx<XPS, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
+                       tiles_m, tiles_n, ntiles);
+  return launch_status();
+}
+
+long long grid_for(long long items, int per_block) {
+  long long g = (items + per_block - 1) / per_block;
+  return g < 1 ? 1 : (g > 65536 ? 65536 : g);
+}
+
+}  // namespace
+
+int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
+  if (d.M < 0 || d.N < 0 || d.K < 0 || d.batch < 0) return NOF_E_DIM;
+  if (d.sym && (d.M != d.N)) return NOF_E_DIM;
+  if ((!x_planes && !d.ex) || (!y_planes && !d.ey)) return NOF_E_NULL;
+  const bool big = d.K > EXACT_K;
+  if (x_planes && y_planes)
+    return big ? launch_fx<true, true, true>(d, st) : launch_fx<true, true, false>(d, st);
+  if (!x_planes && y_planes)
+    return big ? launch_fx<false, true, true>(d, st) : launch_fx<false, true, false>(d, st);
+  if (x_planes && !y_planes)
+    return big ? launch_fx<true, false, true>(d, st) : launch_fx<true, false, false>(d, st);
+  return NOF_E_DTYPE;
+}
+
+int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st) {
+  if (nrow <= 0 || K <= 0) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_for(nrow, 4);
+  if (At == NOF_F64)
+    hipLaunchKernelGGL(k_row_exps<double>, dim3(g), dim3(256), 0, st, (const double*)A, nrow, K, e);
+  else if (At == NOF_F32)
+    hipLaunchKernelGGL(k_row_exps<float>, dim3(g), dim3(256), 0, st, (const float*)A, nrow, K, e);
+  else
+    return NOF_E_DTYPE;
+  return launch_status();
+}
+
+int fx_col_exps(const float* A, int batch, int K, int N, long long sa, int* e, hipStream_t st) {
+  if (batch <= 0 || K <= 0 || N <= 0) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_for((long long)batch * N, 256);
+  hipLaunchKernelGGL(k_col_exps, dim3(g), dim3(256), 0, st, A, batch, K, N, sa, e);
+  return launch_status();
+}
+
+int fx_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* out, hipStream_t st) {
+  if (K <= 0 || ncol <= 0 || ldk < K || ldk % KT) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_for(ncol, 64);
+  hipLaunchKernelGGL(k_split_cols, dim3(g), dim3(64), 0, st, A, K, ncol, lda, ldk, (__bf16*)out);
+  return launch_status();
+}
+
+int fx_split_rows(const void* A, int At, long long nrow, int K, int ldk, void* out, hipStream_t st) {
+  if (nrow <= 0 || K <= 0 || ldk < K || ldk % KT) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_for(nrow, 4);
+  if (At == NOF_F64)
+    hipLaunchKernelGGL(k_split_rows<double>, dim3(g), dim3(256), 0, st, (const double*)A, nrow, K, ldk,
+                       (__bf16*)out);
+  else if (At == NOF_F32)
+    hipLaunchKernelGGL(k_split_rows<float>, dim3(g), dim3(256), 0, st, (const float*)A, nrow, K, ldk,
+                       (__bf16*)out);
+  else
+    return NOF_E_DTYPE;
+  return launch_status();
+}
+
+}  // namespace nof

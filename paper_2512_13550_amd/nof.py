@@ -20,7 +20,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 # status codes and enums (mirror include/nof.h)
 OK, E_NULL, E_DIM, E_DTYPE, E_PREC, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_ARG = 0, -1, -2, -3, -4, -5, -6, -7, -8
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, BF16X4 = 0, 1, 2, 3
 P_F64, P_F32, P_BF16X1, P_BF16X3, P_BF16X6, P_BF16X10 = 0, 1, 2, 3, 4, 5
 
 _vp, _i, _sz, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
@@ -36,7 +36,9 @@ def _sig(name, res, *args):
 _sig("nof_status_str", ctypes.c_char_p, _i)
 _sig("nof_mo_transform_ws", _sz, _i, _i, _i, _i, _i, _i)
 _sig("nof_mo_transform", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
-_sig("nof_mo_transform_stage_ws", _sz, _i, _i, _i)
+_sig("nof_mo_transform_stage_ws", _sz, _i, _i, _i, _i)
+_sig("nof_split_B_bytes", _sz, _i, _i)
+_sig("nof_split_B", _i, _i, _i, _vp, _i, _vp, _sz, _vp)
 _sig("nof_mo_transform_stage1", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _sz, _vp)
 _sig("nof_mo_transform_stage2", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
 _sig("nof_jk_diag_ws", _sz, _i, _i, _i)
@@ -82,7 +84,8 @@ FUNC_HF, FUNC_PNOF5 = 0, 1
 
 DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
-    "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_jk_diag_ws", "nof_jk_diag",
+    "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_split_B_bytes", "nof_split_B",
+    "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
@@ -134,6 +137,27 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------------------
+class SplitB:
+    """B as the four fixed-point BF16 planes written by nof_split_B, the input
+    of the P_BF16X10 transform (split once, reused by every iteration)."""
+
+    def __init__(self, B, stream=None):
+        naux, nbf, _ = B.shape
+        self.shape = tuple(B.shape)
+        self.device = B.device
+        nbytes = lib.nof_split_B_bytes(naux, nbf)
+        self.planes = workspace(nbytes, B.device)
+        check(lib.nof_split_B(naux, nbf, _p(B), _TDT[B.dtype], _p(self.planes), nbytes,
+                              stream_handle(stream)), "nof_split_B")
+
+
+def _b_arg(B):
+    """(storage code, device pointer) of a B argument: a tensor or a SplitB."""
+    if isinstance(B, SplitB):
+        return BF16X4, _p(B.planes)
+    return _TDT[B.dtype], _p(B)
+
+
 def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
     """b^P = C^T B^P C and D[P][p] = b^P_pp (nof_mo_transform).
 
@@ -142,8 +166,8 @@ def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
     produce b in FP32."""
     naux, nbf, _ = B.shape
     norb = C.shape[1]
-    Bt = _TDT[B.dtype]
-    prec = _PREC_OF.get(Bt, P_F64) if prec is None else prec
+    Bt, Bp = _b_arg(B)
+    prec = _PREC_OF.get(Bt, P_BF16X10 if Bt == BF16X4 else P_F64) if prec is None else prec
     bdtype = torch.float64 if prec == P_F64 else torch.float32
     if b is None:
         b = torch.empty((naux, norb, norb), dtype=bdtype, device=B.device)
@@ -155,13 +179,13 @@ def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
         raise NofError(E_DTYPE, "nof_mo_transform_ws")
     if ws is None or ws.numel() < need:
         ws = workspace(need, B.device)
-    check(lib.nof_mo_transform(naux, nbf, norb, _p(B), Bt, _f64(C, "C"), _p(b), bt, _p(D), prec,
+    check(lib.nof_mo_transform(naux, nbf, norb, Bp, Bt, _f64(C, "C"), _p(b), bt, _p(D), prec,
                                _p(ws), ws.numel(), stream_handle(stream)), "nof_mo_transform")
     return b, D
 
 
-def _stage_ws(nbf, norb, prec, device, ws):
-    need = lib.nof_mo_transform_stage_ws(nbf, norb, prec)
+def _stage_ws(naux, nbf, norb, prec, device, ws):
+    need = lib.nof_mo_transform_stage_ws(naux, nbf, norb, prec)
     if ws is None or ws.numel() < need:
         ws = workspace(need, device)
     return ws
@@ -171,10 +195,10 @@ def transform_stage1(B, C, T, prec=None, ws=None, stream=None):
     """T^P = B^P C (first half of nof_mo_transform) into caller-owned T."""
     naux, nbf, _ = B.shape
     norb = C.shape[1]
-    bt = _TDT[B.dtype]
-    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
-    ws = _stage_ws(nbf, norb, prec, B.device, ws)
-    check(lib.nof_mo_transform_stage1(naux, nbf, norb, _p(B), bt, _f64(C, "C"), _p(T), _TDT[T.dtype],
+    bt, Bp = _b_arg(B)
+    prec = _PREC_OF.get(bt, P_BF16X10 if bt == BF16X4 else P_F64) if prec is None else prec
+    ws = _stage_ws(naux, nbf, norb, prec, B.device, ws)
+    check(lib.nof_mo_transform_stage1(naux, nbf, norb, Bp, bt, _f64(C, "C"), _p(T), _TDT[T.dtype],
                                       prec, _p(ws), ws.numel(), stream_handle(stream)),
           "nof_mo_transform_stage1")
     return T
@@ -185,7 +209,7 @@ def transform_stage2(T, C, b, D, prec=None, ws=None, stream=None):
     naux, nbf, norb = T.shape
     bt = _TDT[b.dtype]
     prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
-    ws = _stage_ws(nbf, norb, prec, T.device, ws)
+    ws = _stage_ws(naux, nbf, norb, prec, T.device, ws)
     check(lib.nof_mo_transform_stage2(naux, nbf, norb, _p(T), _TDT[T.dtype], _f64(C, "C"), _p(b), bt,
                                       _p(D), prec, _p(ws), ws.numel(), stream_handle(stream)),
           "nof_mo_transform_stage2")

@@ -23,7 +23,7 @@ def declared_symbols():
         if fn.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", fn)).read()
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-            names += re.findall(r"\b(nof_[a-z0-9_]+)\s*\(", txt)
+            names += re.findall(r"\b(nof_[A-Za-z0-9_]+)\s*\(", txt)
     return sorted(set(names))
 
 

@@ -80,6 +80,25 @@ def test_bf16_x10_fixed_point(nbf, naux, norb, seed):
     assert errs["E"] <= 2e-8
 
 
+@pytest.mark.parametrize("src", ["f32", "f64"])
+@pytest.mark.parametrize("nbf,naux,norb,seed", [(48, 192, 48, 0), (300, 40, 260, 1), (130, 7, 97, 5)])
+def test_bf16_x10_split_B(src, nbf, naux, norb, seed):
+    """B split once into fixed-point planes (nof_split_B), from FP32 or FP64."""
+    nof = need_gpu()
+    print(f"case bf16 x10 split B from {src} nbf={nbf} naux={naux} norb={norb}", flush=True)
+    B, C, H, n, cJ, cK = case(nbf, naux, norb, seed)
+    Bin = B.astype(np.float32).astype(np.float64) if src == "f32" else B
+    ref = dfjk.iteration(Bin, C, H, n, cJ, cK)
+    planes = nof.SplitB(dev(Bin, torch.float32 if src == "f32" else torch.float64))
+    got = run_gpu(nof, planes, C, H, n, cJ, cK, nof.P_BF16X10)
+    errs = {k: normwise(got[k], ref[k]) for k in ("b", "J", "K", "lam", "g")}
+    errs["E"] = abs(got["E"] - ref["E"]) / abs(ref["E"])
+    print("x10 split B", src, errs, flush=True)
+    for k in ("b", "J", "K", "lam"):
+        assert errs[k] <= 3e-7, (k, errs[k])
+    assert errs["E"] <= 2e-8
+
+
 def paired(rng, nrow, ncol, sign):
     """Rows 2k and 2k+1 equal (sign=+1) or opposite (sign=-1), entries with
     magnitudes spread over 2^-12..1."""
@@ -108,6 +127,8 @@ def test_bf16_x10_cancellation():
     nof.transform_stage1(dev(B, torch.float32), dev(C), T, prec=nof.P_BF16X10)
     scale1 = np.einsum("Pab,bq->Paq", np.abs(B.astype(np.float64)), np.abs(C))
     r1 = float(np.max(np.abs(host(T)) / scale1))
+    nof.transform_stage1(nof.SplitB(dev(B, torch.float32)), dev(C), T, prec=nof.P_BF16X10)
+    r1 = max(r1, float(np.max(np.abs(host(T)) / scale1)))
     # stage 2: T with rows 2k+1 = -(rows 2k), C with rows 2k and 2k+1 equal: b = C^T T = 0
     T2 = np.stack([paired(rng, nbf, norb, -1.0) for _ in range(naux)]).astype(np.float32)
     b = torch.empty((naux, norb, norb), dtype=torch.float32, device="cuda")
