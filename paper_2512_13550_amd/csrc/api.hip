@@ -187,7 +187,7 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
         f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
       } else {
         NOF_TRY(fx_row_exps(B, Bt, (long long)naux * nbf, nbf, ex, stream));
-        f.ldx = nbf; f.sx = (long long)nbf * nbf; f.ex = ex; f.sex = nbf;
+        f.ldx = nbf; f.sx = (long long)nbf * nbf; f.ex = ex; f.sex = nbf; f.x_rows = true;
       }
       f.Y = w; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk;
       f.Out = (float*)T; f.ldo = norb; f.so = (long long)nbf * norb;

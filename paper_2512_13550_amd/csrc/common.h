@@ -91,6 +91,7 @@ struct FxDesc {
   double* Dg; long long sd;
   bool sym;
   int role;                        // 1 = transform stage 1, 2 = stage 2 (kernel symbol)
+  bool x_rows;                     // FP32 X symmetric per batch: may be read m-major (rows)
 };
 int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
 // Grid exponents (2^E above the largest |value|) of rows of A[nrow][K] (FP64/FP32)

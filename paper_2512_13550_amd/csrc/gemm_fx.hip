@@ -20,12 +20,13 @@
 // leave a truncation of order 2^-32 of |x||y|.  For K > 1024 the order-0 sum
 // is added to FP64 every 1024 terms (BIGK variant).
 //
-// Layout: 256 threads = 4 waves (2 x 2); the workgroup tile is 128 (m) x 64
-// (n), each wave 64 x 32 as 4 x 2 fragments of v_mfma_f32_16x16x32_bf16
-// (lane l holds 8 consecutive k of row l%16 at k offset 8*(l/16); output row
-// 4*(l/16)+r, column l%16).  Two workgroups share a compute unit, so one's
-// loads overlap the other's products.  LDS holds the four pieces as [row][k]
-// with rows padded to 40 elements (80 B).
+// Layout: 512 threads = 8 waves (2 x 4); the workgroup tile is 128 x 128,
+// each wave 64 x 32 as 4 x 2 fragments of v_mfma_f32_16x16x32_bf16 (lane l
+// holds 8 consecutive k of row l%16 at k offset 8*(l/16); output row
+// 4*(l/16)+r, column l%16).  LDS holds the four pieces as [row][k] (k in
+// swizzled 16-byte chunks, see swz), in two buffers: the next stage is stored
+// while the current one is multiplied.  The operand split in
+// a loader (a row of X or column of Y) is shared by 128 output columns/rows.
 //
 // Operands are either pre-split planes (X: [4][..][m][ldk], k contiguous) or
 // FP32 values split in the loader against per-row / per-column grid
@@ -37,11 +38,9 @@ namespace {
 
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-constexpr int FM = 128;                 // tile rows
-constexpr int FN = 64;                  // tile columns
+constexpr int FT = 128;                 // tile edge (rows and columns)
 constexpr int KT = 32;
-constexpr int NTHR = 256;
-constexpr int LROW = KT + 8;
+constexpr int NTHR = 512;
 constexpr int EXACT_K = 1024;           // order-0 sums stay exact in FP32 up to this depth
 constexpr int EMIN = -90, EMAX = 128;   // grid exponent range (all scales normal FP32)
 
@@ -162,97 +161,115 @@ __global__ void k_split_rows(const T* __restrict__ A, long long nrow, int K, int
   }
 }
 
-// Linear tile index -> (tm, tn).  sym: tiles that meet the upper triangle,
-// i.e. tn >= 2 tm for 128 x 64 tiles.
-__device__ __forceinline__ void tile_of(int t, int tiles_m, int tiles_n, bool sym, int& tm, int& tn) {
+// LDS rows hold the 32 k of one stage as four 16-byte chunks, chunk c of row
+// r at position c ^ ((r >> 2) & 3): the 16 rows of a fragment read (one
+// chunk each) and the 4 x 4 chunks written by 16 loader lanes both fall on
+// distinct banks.  Element offset of chunk c in row r:
+__device__ __forceinline__ int swz(int r, int c) { return (c ^ ((r >> 2) & 3)) << 3; }
+
+// Linear tile index -> (tm, tn); sym: the tiles with tm <= tn.
+__device__ __forceinline__ void tile_of(int t, int tiles_n, bool sym, int& tm, int& tn) {
   if (!sym) {
     tm = t / tiles_n;
     tn = t - tm * tiles_n;
     return;
   }
   int row = 0;
-  while (row < tiles_m && t >= tiles_n - 2 * row) { t -= tiles_n - 2 * row; ++row; }
+  while (t >= tiles_n - row) { t -= tiles_n - row; ++row; }
   tm = row;
-  tn = 2 * row + t;
+  tn = row + t;
 }
 
-template <bool XPS, bool YPS, bool BIGK>
-__device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_m, int tiles_n, int ntiles) {
-  __shared__ __attribute__((aligned(16))) __bf16 Xs[4][FM][LROW];
-  __shared__ __attribute__((aligned(16))) __bf16 Ys[4][FN][LROW];
+// XM: X operand as planes (0), FP32 k-major X + b*sx + k*ldx + m (1), or FP32
+// with rows contiguous X + b*sx + m*ldx + k, 16-byte aligned rows (2).
+template <int XM, bool YPS, bool BIGK>
+__device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles) {
+  constexpr bool XPS = XM == 0;
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][4][FT][KT];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][4][FT][KT];
 
   const int tid = threadIdx.x;
   const int l = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w >> 2, wn = w & 3;          // wave tile: rows 64*wm.., columns 32*wn..
 
   const int logical = xcd_logical(blockIdx.x, gridDim.x);
   const int bb = logical / ntiles;
   int tm, tn;
-  tile_of(logical - bb * ntiles, tiles_m, tiles_n, d.sym, tm, tn);
-  const int m0 = tm * FM, n0 = tn * FN;
+  tile_of(logical - bb * ntiles, tiles_n, d.sym, tm, tn);
+  const int m0 = tm * FT, n0 = tn * FT;
   const int nstage = (d.K + KT - 1) / KT;
 
-  // loaders: X row cx, k half kx (16 each); Y column cy, k quarter ky (8 each)
-  const int cx = tid & (FM - 1), kx = tid >> 7;
-  const int cy = tid & (FN - 1), ky = tid >> 6;
+  // loaders: thread owns row cx of the X tile (column cy of Y) and its 8 k of
+  // quarter kq.  Operands with k contiguous (planes, row-major X): the four
+  // quarters of a row are neighbouring lanes, so one wave reads 16 rows of
+  // 64-128 contiguous bytes; k-major FP32: lanes run along the row index.
+  constexpr bool XKC = XM != 1;                 // X with k contiguous
+  const int cx = XKC ? tid >> 2 : tid & (FT - 1), kqx = XKC ? tid & 3 : tid >> 7;
+  const int cy = YPS ? tid >> 2 : tid & (FT - 1), kqy = YPS ? tid & 3 : tid >> 7;
   const bool xok = m0 + cx < d.M, yok = n0 + cy < d.N;
   const int ex = (!XPS && xok) ? d.ex[(long long)bb * d.sex + m0 + cx] : 0;
   const int ey = (!YPS && yok) ? d.ey[(long long)bb * d.sey + n0 + cy] : 0;
 
-  bf8v xp[XPS ? 4 : 1][2], yp[YPS ? 4 : 1];
-  float xr[XPS ? 1 : 16], yr[YPS ? 1 : 8];
+  bf8v xp[XPS ? 4 : 1], yp[YPS ? 4 : 1];
+  float xr[XPS ? 1 : 8], yr[YPS ? 1 : 8];
 
   auto load = [&](int s) {
-    const int k0 = s * KT;
+    int k0 = s * KT + 8 * kqx;
+    int kl = d.K - k0;
     if constexpr (XPS) {
-      const __bf16* p = (const __bf16*)d.X + (long long)bb * d.sx + (long long)(m0 + cx) * d.ldx + k0 + 16 * kx;
+      const __bf16* p = (const __bf16*)d.X + (long long)bb * d.sx + (long long)(m0 + cx) * d.ldx + k0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q) xp[XPS ? q : 0] = xok ? *(const bf8v*)(p + (long long)q * d.psx) : bf8v{};
+    } else if constexpr (XM == 2) {
+      const float* p = (const float*)d.X + (long long)bb * d.sx + (long long)(m0 + cx) * d.ldx + k0;
+      if (xok && kl >= 8) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          xp[q][h] = xok ? *(const bf8v*)(p + (long long)q * d.psx + 8 * h) : bf8v{};
+        for (int v = 0; v < 2; ++v) {
+          const float4 f = *(const float4*)(p + 4 * v);
+          xr[XPS ? 0 : 4 * v] = f.x; xr[XPS ? 0 : 4 * v + 1] = f.y;
+          xr[XPS ? 0 : 4 * v + 2] = f.z; xr[XPS ? 0 : 4 * v + 3] = f.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[j] : 0.f;
+      }
     } else {
-      const float* p = (const float*)d.X + (long long)bb * d.sx + (long long)(k0 + 16 * kx) * d.ldx + m0 + cx;
-      const int kl = d.K - k0 - 16 * kx;
+      const float* p = (const float*)d.X + (long long)bb * d.sx + (long long)k0 * d.ldx + m0 + cx;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[(long long)j * d.ldx] : 0.f;
+      for (int j = 0; j < 8; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[(long long)j * d.ldx] : 0.f;
     }
+    k0 = s * KT + 8 * kqy;
+    kl = d.K - k0;
     if constexpr (YPS) {
-      const __bf16* p = (const __bf16*)d.Y + (long long)bb * d.sy + (long long)(n0 + cy) * d.ldy + k0 + 8 * ky;
+      const __bf16* p = (const __bf16*)d.Y + (long long)bb * d.sy + (long long)(n0 + cy) * d.ldy + k0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) yp[YPS ? q : 0] = yok ? *(const bf8v*)(p + (long long)q * d.psy) : bf8v{};
     } else {
-      const float* p = (const float*)d.Y + (long long)bb * d.sy + (long long)(k0 + 8 * ky) * d.ldy + n0 + cy;
-      const int kl = d.K - k0 - 8 * ky;
+      const float* p = (const float*)d.Y + (long long)bb * d.sy + (long long)k0 * d.ldy + n0 + cy;
 #pragma unroll
       for (int j = 0; j < 8; ++j) yr[YPS ? 0 : j] = (yok && j < kl) ? p[(long long)j * d.ldy] : 0.f;
     }
   };
 
-  auto store = [&]() {
+  auto store = [&](int buf) {
     if constexpr (XPS) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) *(bf8v*)&Xs[q][cx][16 * kx + 8 * h] = xp[q][h];
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[buf][q][cx][swz(cx, kqx)] = xp[XPS ? q : 0];
     } else {
+      bf8v pk[4];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        bf8v pk[4];
+      for (int e = 0; e < 8; ++e) {
+        __bf16 p[4];
+        split_g(xr[XPS ? 0 : e], ex, p);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 p[4];
-          split_g(xr[XPS ? 0 : 8 * h + e], ex, p);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[q][cx][16 * kx + 8 * h] = pk[q];
+        for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[buf][q][cx][swz(cx, kqx)] = pk[q];
     }
     if constexpr (YPS) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[q][cy][8 * ky] = yp[YPS ? q : 0];
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[buf][q][cy][swz(cy, kqy)] = yp[YPS ? q : 0];
     } else {
       bf8v pk[4];
 #pragma unroll
@@ -263,7 +280,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_m, int tiles_
         for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[q][cy][8 * ky] = pk[q];
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[buf][q][cy][swz(cy, kqy)] = pk[q];
     }
   };
 
@@ -278,40 +295,41 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_m, int tiles_
       if (BIGK) acc64[BIGK ? i : 0][BIGK ? j : 0] = d4v{0, 0, 0, 0};
     }
 
-  if (nstage > 0) {
-    load(0);
-    store();
-  }
-  __syncthreads();
-  const int kl = 8 * (l >> 4);
-  for (int s = 0; s < nstage; ++s) {
-    if (s + 1 < nstage) load(s + 1);
-    bf8v a[4][4], b[2][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[i][q] = *(const bf8v*)&Xs[q][wm * 64 + i * 16 + (l & 15)][kl];
+  // fragment rows start at multiples of 16, so the swizzle of row l%16 applies
+  const int kl = swz(l & 15, l >> 4);
+  auto compute = [&](int s, int buf) {
+    bf8v b[2][4];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) b[j][q] = *(const bf8v*)&Ys[q][wn * 32 + j * 16 + (l & 15)][kl];
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const bf8v*)&Ys[buf][q][wn * 32 + j * 16 + (l & 15)][kl];
+    // two row fragments at a time (four independent accumulators per step):
     // orders 3, 2, 1 into acc1 (smallest first), then the exact order 0
 #pragma unroll
-    for (int o = 3; o >= 1; --o)
+    for (int ip = 0; ip < 4; ip += 2) {
+      bf8v a[2][4];
 #pragma unroll
-      for (int px = 0; px <= o; ++px) {
-        const int py = o - px;
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int q = 0; q < 4; ++q) a[i][q] = *(const bf8v*)&Xs[buf][q][wm * 64 + (ip + i) * 16 + (l & 15)][kl];
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], b[j][py], acc1[i][j], 0, 0, 0);
-      }
+      for (int o = 3; o >= 1; --o)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int px = 0; px <= o; ++px) {
+          const int py = o - px;
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc0[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], acc0[i][j], 0, 0, 0);
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc1[ip + i][j] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], b[j][py], acc1[ip + i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc0[ip + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], acc0[ip + i][j], 0, 0, 0);
+    }
     if (BIGK && ((s + 1) % (EXACT_K / KT) == 0)) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -322,8 +340,20 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_m, int tiles_
           acc0[i][j] = f4v{0, 0, 0, 0};
         }
     }
-    __syncthreads();
-    if (s + 1 < nstage) store();
+  };
+
+  // two LDS buffers: stage s+1 is stored into the other buffer while stage s
+  // is multiplied, one barrier per stage
+  if (nstage > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstage) load(s + 1);
+    compute(s, buf);
+    if (s + 1 < nstage) store(buf ^ 1);
     __syncthreads();
   }
 
@@ -350,34 +380,28 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_m, int tiles_
 }
 
 #define NOF_FX_KERNEL(NAME)                                                              \
-  template <bool XPS, bool YPS, bool BIGK>                                               \
-  __global__ __launch_bounds__(NTHR, BIGK ? 1 : 2) void NAME(FxDesc d, int tiles_m,      \
-                                                             int tiles_n, int ntiles) {  \
-    fx_body<XPS, YPS, BIGK>(d, tiles_m, tiles_n, ntiles);                                \
+  template <int XM, bool YPS, bool BIGK>                                                 \
+  __global__ __launch_bounds__(NTHR, 1) void NAME(FxDesc d, int tiles_n, int ntiles) {   \
+    fx_body<XM, YPS, BIGK>(d, tiles_n, ntiles);                                          \
   }
 NOF_FX_KERNEL(k_transform_stage1_fx)
 NOF_FX_KERNEL(k_transform_stage2_fx)
 #undef NOF_FX_KERNEL
 
-template <bool XPS, bool YPS, bool BIGK>
+template <int XM, bool YPS, bool BIGK>
 int launch_fx(const FxDesc& d, hipStream_t st) {
-  const int tiles_m = (d.M + FM - 1) / FM;
-  const int tiles_n = (d.N + FN - 1) / FN;
-  int ntiles = 0;
-  if (d.sym) {
-    for (int tm = 0; tm < tiles_m; ++tm) ntiles += tiles_n - 2 * tm > 0 ? tiles_n - 2 * tm : 0;
-  } else {
-    ntiles = tiles_m * tiles_n;
-  }
+  const int tiles_m = (d.M + FT - 1) / FT;
+  const int tiles_n = (d.N + FT - 1) / FT;
+  const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
   const long long G = (long long)ntiles * d.batch;
   if (G <= 0) return NOF_OK;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
   if (d.role == 1)
-    hipLaunchKernelGGL((k_transform_stage1_fx<XPS, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
-                       tiles_m, tiles_n, ntiles);
+    hipLaunchKernelGGL((k_transform_stage1_fx<XM, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
+                       tiles_n, ntiles);
   else
-    hipLaunchKernelGGL((k_transform_stage2_fx<XPS, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
-                       tiles_m, tiles_n, ntiles);
+    hipLaunchKernelGGL((k_transform_stage2_fx<XM, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
+                       tiles_n, ntiles);
   return launch_status();
 }
 
@@ -394,12 +418,17 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
   if ((!x_planes && !d.ex) || (!y_planes && !d.ey)) return NOF_E_NULL;
   const bool big = d.K > EXACT_K;
   if (x_planes && y_planes)
-    return big ? launch_fx<true, true, true>(d, st) : launch_fx<true, true, false>(d, st);
-  if (!x_planes && y_planes)
-    return big ? launch_fx<false, true, true>(d, st) : launch_fx<false, true, false>(d, st);
+    return big ? launch_fx<0, true, true>(d, st) : launch_fx<0, true, false>(d, st);
   if (x_planes && !y_planes)
-    return big ? launch_fx<true, false, true>(d, st) : launch_fx<true, false, false>(d, st);
-  return NOF_E_DTYPE;
+    return big ? launch_fx<0, false, true>(d, st) : launch_fx<0, false, false>(d, st);
+  if (!y_planes) return NOF_E_DTYPE;
+  if (d.x_rows) {
+    // rows contiguous: float4 loads when every row start is 16-byte aligned
+    if (d.ldx % 4 == 0 && d.sx % 4 == 0 && ((uintptr_t)d.X & 15) == 0)
+      return big ? launch_fx<2, true, true>(d, st) : launch_fx<2, true, false>(d, st);
+    // otherwise the same values read k-major (the operand is symmetric)
+  }
+  return big ? launch_fx<1, true, true>(d, st) : launch_fx<1, true, false>(d, st);
 }
 
 int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st) {
