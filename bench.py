@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c500")
-    ap.add_argument("--forms", default="f32,bf16x3,bf16x6,bf16B",
-                    help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16x10, "
-                         "bf16B (B stored in BF16)")
+    ap.add_argument("--forms", default="f32,bf16x3,bf16x6,bf16x10,bf16x10f32,bf16B",
+                    help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16x10 (B split "
+                         "once into fixed-point planes from FP64), bf16x10f32 (FP32 B split in the "
+                         "loader), bf16B (B stored in BF16)")
     ap.add_argument("--cpu-slabs", type=int, default=160,
                     help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--batched", type=int, default=1,
@@ -121,7 +122,7 @@ def main():
     flops = algorithmic_flops(nbf, naux, norb)
 
     PRECS = {"f64": nof.P_F64, "f32": nof.P_F32, "bf16x1": nof.P_BF16X1, "bf16x3": nof.P_BF16X3,
-             "bf16x6": nof.P_BF16X6, "bf16x10": nof.P_BF16X10,
+             "bf16x6": nof.P_BF16X6, "bf16x10": nof.P_BF16X10, "bf16x10f32": nof.P_BF16X10,
              "bf16B": nof.P_BF16X6}
 
     def run(B, prec_name, steps, warmup):
@@ -198,6 +199,8 @@ def main():
         print(f"# timing {f}", file=sys.stderr, flush=True)
         if f == "bf16B":
             Bf = B64.to(torch.bfloat16)
+        elif f == "bf16x10":
+            Bf = nof.SplitB(B64)          # fixed-point planes of the FP64 B, split once
         else:
             if B32 is None:
                 B32 = B64.to(torch.float32)

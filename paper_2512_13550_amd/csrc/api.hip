@@ -38,7 +38,7 @@ JkLayout jk_layout(int naux, int norb) {
 // Workspace of nof_gen_fock: W, F1/K chunk partials, F2 partials, F1, F2.
 struct FockLayout {
   int kchunks, f2fold, f2groups;
-  size_t off_W, off_f1part, off_kpart, off_f2part, off_F1, off_F2, total;
+  size_t off_W, off_f1part, off_kpart, off_f2part, off_F1, off_F2, off_St, total;
 };
 FockLayout fock_layout(int naux, int norb) {
   FockLayout L;
@@ -57,7 +57,8 @@ FockLayout fock_layout(int naux, int norb) {
   L.off_f2part = align256(L.off_kpart + (size_t)L.kchunks * n2);
   L.off_F1 = align256(L.off_f2part + (size_t)L.f2groups * n2);
   L.off_F2 = align256(L.off_F1 + n2);
-  L.total = align256(L.off_F2 + n2);
+  L.off_St = align256(L.off_F2 + n2);
+  L.total = align256(L.off_St + (size_t)norb * norb * sizeof(float));
   return L;
 }
 
@@ -362,7 +363,12 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     g2.Out = f2part; g2.ldo = norb; g2.so = n2;
     g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
     g2.role = GemmRole::ExchangeFock;
-    NOF_TRY(gemm_any(g2, bt, bt, NOF_F64, prec, stream));
+    if (prec == NOF_P_BF16X10) {
+      ExDesc e{naux, norb, L.f2fold, (const float*)b, nullptr, f2part};
+      NOF_TRY(exchange_fock_fx(e, cK, (float*)(w + L.off_St), stream));
+    } else {
+      NOF_TRY(gemm_any(g2, bt, bt, NOF_F64, prec, stream));
+    }
     NOF_TRY(reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream));
     return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
   });

@@ -94,6 +94,17 @@ struct FxDesc {
   bool x_rows;                     // FP32 X symmetric per batch: may be read m-major (rows)
 };
 int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
+// Exchange-type Fock partials of the split forms (gemm_fx.hip):
+//   Out[g][r][s] = sum_{P in [g*fold, (g+1)*fold)} sum_q b^P[q][r] S[q][s] b^P[q][s]
+// b FP32 [naux][norb][norb] symmetric slabs; S FP64 [norb][norb]; St a
+// norb*norb FP32 scratch (S transposed); Out FP64 [groups][norb][norb].
+struct ExDesc {
+  int naux, norb, fold;
+  const float* b;
+  const float* St;
+  double* Out;
+};
+int exchange_fock_fx(const ExDesc& d, const double* S, float* St, hipStream_t st);
 // Grid exponents (2^E above the largest |value|) of rows of A[nrow][K] (FP64/FP32)
 // and of the columns of A_b[K][N] (FP32, batch stride sa) -> e[b*N + n].
 int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st);

@@ -12,33 +12,12 @@
 //   x1:  (0,0)                         NX = NY = 1, ORD = 0
 //   x3:  (0,0) (0,1) (1,0)             NX = NY = 2, ORD = 1
 //   x6:  (0,0) (0,1) (1,0) (0,2) (1,1) (2,0)   NX = NY = 3, ORD = 2
-//   x10: fixed-point pieces (below), all pairs with i + j <= 3
 //   X stored in BF16 (exact as one piece) with a 3-piece Y: (0,0) (0,1) (0,2).
 // x1/x3 accumulate products in FP32 inside one batch (one auxiliary slab) and,
 // when a workgroup folds several batches, in FP64 across them; x6 adds every
 // 32-deep stage's FP32 partial into FP64 accumulators.  The orbital matrix C
 // is split once per call into bf16 planes (k_presplit) stored [piece][col][k],
 // so the loaders fill LDS with 16-byte copies.
-//
-// x10 (fixed-point split; here for the exchange-type Fock term, whose
-// contraction runs over every (P, q) pair: the transform stages of x10, with
-// one grid per row over the whole contraction, are in gemm_fx.hip).  The
-// matrix cores add the 32 products of one
-// instruction with a datapath aligned to the largest term, so the sum of
-// element-wise split pieces is not correctly rounded and cancellation leaves
-// errors of many ulps of the result.  x10 therefore puts the pieces of a row
-// of X (and a column of Y) within one 32-deep stage on a common grid: with
-// 2^E > max |x| over the stage,
-//   x = sum_{i<4} n_i 2^(E-8(i+1)) + r,  n_i integers, |n_0| <= 256,
-//   |n_i| <= 128 (i > 0), |r| <= 2^(E-33)
-// (Ozaki, Ogita, Oishi and Rump, "Error-free transformations of matrix
-// multiplication by using fast routines of matrix multiplication", Numer.
-// Algorithms 2012, with BF16 pieces).  Each n_i 2^(...) is exact in BF16.  The
-// order-0 products of one stage are integers below 2^16 in units of
-// 2^(Ex+Ey-16), so their 32-term sum (< 2^21 units) is exact in FP32 whatever
-// the alignment; it goes into its own accumulator, added to FP64 every stage.
-// Orders 1..3 are 2^-9 and less of the result and share a second FP32
-// accumulator, added to FP64 at the end of every batch.
 //
 // Layout: 256 threads = 4 waves (2x2), each wave a 64x64 block as 4x4
 // fragments of v_mfma_f32_16x16x32_bf16 (lane l holds 8 consecutive k of row
@@ -87,27 +66,6 @@ __device__ __forceinline__ void split(float v, __bf16 (&p)[3]) {
   }
 }
 
-// Fixed-point split of v with 2^E > |v| (x10; see the header): four exact
-// BF16 pieces on the grids 2^(E-8), 2^(E-16), 2^(E-24), 2^(E-32).  E is kept
-// in [-90, 128] so every scale below is a normal FP32 power of two.
-__device__ __forceinline__ float pow2f(int e) { return __int_as_float((127 + e) << 23); }
-
-__device__ __forceinline__ void split_fx(float v, int E, __bf16 (&p)[4]) {
-  float t = v * pow2f(8 - E);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float n = rintf(t);
-    p[i] = (__bf16)(n * pow2f(E - 8 * (i + 1)));
-    t = (t - n) * 256.0f;
-  }
-}
-
-// Smallest E with 2^E > m for m >= 0 (FP32), clamped to [-90, 128].
-__device__ __forceinline__ int grid_exp(float m) {
-  const int e = (int)(__float_as_uint(m) >> 23) - 126;
-  return e < -90 ? -90 : (e > 128 ? 128 : e);
-}
-
 // Pre-split an FP64 k-major matrix A[k][col] (rows < K, cols < ncol) into NP
 // bf16 planes laid out col-major with k contiguous: out[q][col][k], row length
 // ldk (a multiple of 32), zero for k >= K.  The pieces are taken from the FP64
@@ -131,17 +89,12 @@ __global__ void k_presplit(const double* __restrict__ A, int K, int ncol, int ld
 // sx = plane stride in elements; see k_presplit).  NBUF: LDS stages (1 or 2).
 // A64: every stage's FP32 partial is added into FP64 accumulators (otherwise
 // FP32 accumulation spans one batch and FLUSH64 folds batches in FP64).
-// FX: fixed-point pieces (x10; NX = NY = 4, ORD = 3, A64).
 template <int NX, int NY, int ORD, typename TX, typename TY, typename TO, bool FLUSH64, bool HAS_S,
-          bool PSX, bool PSY, int NBUF, bool A64, bool FX>
+          bool PSX, bool PSY, int NBUF, bool A64>
 __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int ntiles) {
   __shared__ __attribute__((aligned(16))) __bf16 Xs[NBUF][NX][BM][LROW];
   __shared__ __attribute__((aligned(16))) __bf16 Ys[NBUF][NY][BM][LROW];
-  // per-thread grid exponents of the two 16-deep halves of a stage (FX loaders)
-  __shared__ int Ex[FX && !PSX ? 2 : 1][FX && !PSX ? BM : 1];
-  __shared__ int Ey[FX && !PSY ? 2 : 1][FX && !PSY ? BM : 1];
   constexpr bool ACC2 = FLUSH64 || A64;
-  static_assert(!FX || (NX == 4 && NY == 4 && ORD == 3 && A64), "x10 layout");
 
   if (d.pred && *d.pred <= d.pred_gt) return;
   const int tid = threadIdx.x;
@@ -172,15 +125,11 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
   const bool yn_ok = n0 + c_t < d.N;
 
   f4v acc[4][4];
-  f4v acc0[FX ? 4 : 1][FX ? 4 : 1];            // FX: exact order-0 sum of the stage
   d4v acc64[ACC2 ? 4 : 1][ACC2 ? 4 : 1];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc[i][j] = f4v{0, 0, 0, 0};
-      if (FX) acc0[FX ? i : 0][FX ? j : 0] = f4v{0, 0, 0, 0};
-    }
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0, 0, 0, 0};
   if (ACC2) {
 #pragma unroll
     for (int i = 0; i < (ACC2 ? 4 : 1); ++i)
@@ -233,33 +182,6 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
     }
   };
   auto store = [&](int buf) {
-    // FX: the stage's grid exponent per column, from both 16-deep halves
-    int ex = 0, ey = 0;
-    float yv[FX && HAS_S ? PER_T : 1];
-    if constexpr (FX) {
-      if constexpr (!PSX) {
-        float m = 0.f;
-#pragma unroll
-        for (int j = 0; j < PER_T; ++j) m = fmaxf(m, fabsf(as_float(xr[PSX ? 0 : j])));
-        Ex[FX && !PSX ? kg : 0][FX && !PSX ? c_t : 0] = grid_exp(m);
-      }
-      if constexpr (!PSY) {
-        float m = 0.f;
-#pragma unroll
-        for (int j = 0; j < PER_T; ++j) {
-          float v = as_float(yr[PSY ? 0 : j]);
-          if constexpr (HAS_S) {
-            v *= sr[HAS_S ? j : 0];
-            yv[FX && HAS_S ? j : 0] = v;
-          }
-          m = fmaxf(m, fabsf(v));
-        }
-        Ey[FX && !PSY ? kg : 0][FX && !PSY ? c_t : 0] = grid_exp(m);
-      }
-      __syncthreads();
-      if constexpr (!PSX) ex = max(Ex[0][FX && !PSX ? c_t : 0], Ex[FX && !PSX ? 1 : 0][FX && !PSX ? c_t : 0]);
-      if constexpr (!PSY) ey = max(Ey[0][FX && !PSY ? c_t : 0], Ey[FX && !PSY ? 1 : 0][FX && !PSY ? c_t : 0]);
-    }
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const int kofs = kg * 16 + half * 8;
@@ -267,17 +189,11 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
 #pragma unroll
         for (int q = 0; q < NX; ++q) *(bf8v*)&Xs[buf][q][c_t][kofs] = xp[PSX ? q : 0][half];
       } else {
-        bf8v px[NX];
+        bf8v px[3];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          __bf16 p[4];
-          if constexpr (FX) {
-            split_fx(as_float(xr[PSX ? 0 : half * 8 + e]), ex, p);
-          } else {
-            __bf16 p3[3];
-            split<NX>(as_float(xr[PSX ? 0 : half * 8 + e]), p3);
-            p[0] = p3[0]; p[1] = p3[1]; p[2] = p3[2];
-          }
+          __bf16 p[3];
+          split<NX>(as_float(xr[PSX ? 0 : half * 8 + e]), p);
 #pragma unroll
           for (int q = 0; q < NX; ++q) px[q][e] = p[q];
         }
@@ -288,20 +204,13 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
 #pragma unroll
         for (int q = 0; q < NY; ++q) *(bf8v*)&Ys[buf][q][c_t][kofs] = yp[PSY ? q : 0][half];
       } else {
-        bf8v py[NY];
+        bf8v py[3];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int j = half * 8 + e;
-          __bf16 p[4];
-          if constexpr (FX) {
-            const float v = HAS_S ? yv[FX && HAS_S ? j : 0] : as_float(yr[PSY ? 0 : j]);
-            split_fx(v, ey, p);
-          } else {
-            __bf16 p3[3];
-            const float v = HAS_S ? as_float(yr[PSY ? 0 : j]) * sr[HAS_S ? j : 0] : as_float(yr[PSY ? 0 : j]);
-            split<NY>(v, p3);
-            p[0] = p3[0]; p[1] = p3[1]; p[2] = p3[2];
-          }
+          __bf16 p[3];
+          const float v = HAS_S ? as_float(yr[PSY ? 0 : j]) * sr[HAS_S ? j : 0] : as_float(yr[PSY ? 0 : j]);
+          split<NY>(v, p);
 #pragma unroll
           for (int q = 0; q < NY; ++q) py[q][e] = p[q];
         }
@@ -339,25 +248,10 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (FX && o == 0)
-              acc0[FX ? i : 0][FX ? j : 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  a[i][px], bv[j][py], acc0[FX ? i : 0][FX ? j : 0], 0, 0, 0);
-            else
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], bv[j][py], acc[i][j], 0, 0, 0);
-          }
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], bv[j][py], acc[i][j], 0, 0, 0);
       }
-    if constexpr (FX) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc0[FX ? i : 0][FX ? j : 0][r];
-          acc0[FX ? i : 0][FX ? j : 0] = f4v{0, 0, 0, 0};
-        }
-    }
-    if ((A64 && !FX) || ((FLUSH64 || FX) && ((s + 1) % nkb == 0))) {
+    if (A64 || (FLUSH64 && ((s + 1) % nkb == 0))) {
 #pragma unroll
       for (int i = 0; i < (ACC2 ? 4 : 1); ++i)
 #pragma unroll
@@ -398,10 +292,10 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
 
 #define NOF_BF16_KERNEL(NAME)                                                                  \
   template <int NX, int NY, int ORD, typename TX, typename TY, typename TO, bool FLUSH64,      \
-            bool HAS_S, bool PSX, bool PSY, int NBUF, bool A64, bool FX>                       \
+            bool HAS_S, bool PSX, bool PSY, int NBUF, bool A64>                                \
   __global__ __launch_bounds__(NTHR, (FLUSH64 || A64) ? 1 : 2) void NAME(GemmDesc d, int tiles_n, \
                                                                        int ntiles) {            \
-    bf16_body<NX, NY, ORD, TX, TY, TO, FLUSH64, HAS_S, PSX, PSY, NBUF, A64, FX>(d, tiles_n, ntiles); \
+    bf16_body<NX, NY, ORD, TX, TY, TO, FLUSH64, HAS_S, PSX, PSY, NBUF, A64>(d, tiles_n, ntiles); \
   }
 NOF_BF16_KERNEL(k_transform_stage1_bf16)
 NOF_BF16_KERNEL(k_transform_stage2_bf16)
@@ -409,7 +303,7 @@ NOF_BF16_KERNEL(k_exchange_fock_bf16)
 #undef NOF_BF16_KERNEL
 
 template <int NX, int NY, int ORD, typename TX, typename TY, typename TO, bool FLUSH64, bool PSX,
-          bool PSY, bool A64, int ROLE, bool FX = false>
+          bool PSY, bool A64, int ROLE>
 int launch(const GemmDesc& d, hipStream_t st) {
   constexpr int NBUF = (NX + NY) >= 5 ? 1 : 2;
   const int tiles_m = (d.M + BM - 1) / BM;
@@ -420,34 +314,34 @@ int launch(const GemmDesc& d, hipStream_t st) {
   if (G <= 0) return NOF_OK;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
   if (ROLE == 1)
-    hipLaunchKernelGGL((k_transform_stage1_bf16<NX, NY, ORD, TX, TY, TO, FLUSH64, false, PSX, PSY, NBUF, A64, FX>),
+    hipLaunchKernelGGL((k_transform_stage1_bf16<NX, NY, ORD, TX, TY, TO, FLUSH64, false, PSX, PSY, NBUF, A64>),
                        dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
   else if (ROLE == 2)
-    hipLaunchKernelGGL((k_transform_stage2_bf16<NX, NY, ORD, TX, TY, TO, FLUSH64, false, PSX, PSY, NBUF, A64, FX>),
+    hipLaunchKernelGGL((k_transform_stage2_bf16<NX, NY, ORD, TX, TY, TO, FLUSH64, false, PSX, PSY, NBUF, A64>),
                        dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
   else
-    hipLaunchKernelGGL((k_exchange_fock_bf16<NX, NY, ORD, TX, TY, TO, FLUSH64, true, PSX, PSY, NBUF, A64, FX>),
+    hipLaunchKernelGGL((k_exchange_fock_bf16<NX, NY, ORD, TX, TY, TO, FLUSH64, true, PSX, PSY, NBUF, A64>),
                        dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
   return launch_status();
 }
 
 // x6 accumulates in FP64 every stage; x1 and x3 keep FP32 within a batch.
-template <int NX, int NY, int ORD, bool FX = false>
+template <int NX, int NY, int ORD>
 int dispatch_types(const GemmDesc& d, int x_t, int y_t, int out_t, hipStream_t st) {
   constexpr bool A64 = ORD >= 2;
   const bool flush = d.fold > 1;
   // transform stage 1: X = B (f32), Y = C pre-split planes, Out = T (f32)
   if (d.role == GemmRole::TransformStage1 && y_t == NOF_BF16 && out_t == NOF_F32 && !flush &&
       x_t == NOF_F32)
-    return launch<NX, NY, ORD, float, float, float, false, false, true, A64, 1, FX>(d, st);
+    return launch<NX, NY, ORD, float, float, float, false, false, true, A64, 1>(d, st);
   // transform stage 2: X = C pre-split planes, Y = T (f32), Out = b (f32)
   if (d.role == GemmRole::TransformStage2 && x_t == NOF_BF16 && y_t == NOF_F32 && out_t == NOF_F32 &&
       !flush)
-    return launch<NX, NY, ORD, float, float, float, false, true, false, A64, 2, FX>(d, st);
+    return launch<NX, NY, ORD, float, float, float, false, true, false, A64, 2>(d, st);
   // exchange-type Fock: X = Y = b (f32), S = cK, Out = FP64 partials
   if (d.role == GemmRole::ExchangeFock && x_t == NOF_F32 && y_t == NOF_F32 && out_t == NOF_F64 && d.S)
-    return flush ? launch<NX, NY, ORD, float, float, double, true, false, false, A64, 3, FX>(d, st)
-                 : launch<NX, NY, ORD, float, float, double, false, false, false, A64, 3, FX>(d, st);
+    return flush ? launch<NX, NY, ORD, float, float, double, true, false, false, A64, 3>(d, st)
+                 : launch<NX, NY, ORD, float, float, double, false, false, false, A64, 3>(d, st);
   return NOF_E_DTYPE;
 }
 
@@ -471,17 +365,13 @@ int gemm_bf16(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hipStrea
   if (x_t == NOF_BF16 && d.role == GemmRole::TransformStage1) {
     if (y_t != NOF_BF16 || out_t != NOF_F32 || d.fold > 1) return NOF_E_DTYPE;
     if (prec != NOF_P_BF16X6 && prec != NOF_P_BF16X3) return NOF_E_PREC;
-    return launch<1, 3, 2, __bf16, float, float, false, false, true, true, 1, false>(d, st);
+    return launch<1, 3, 2, __bf16, float, float, false, false, true, true, 1>(d, st);
   }
   switch (prec) {
     case NOF_P_BF16X1: return dispatch_types<1, 1, 0>(d, x_t, y_t, out_t, st);
     case NOF_P_BF16X3: return dispatch_types<2, 2, 1>(d, x_t, y_t, out_t, st);
     case NOF_P_BF16X6: return dispatch_types<3, 3, 2>(d, x_t, y_t, out_t, st);
-    case NOF_P_BF16X10:   // the transform stages of x10 run in gemm_fx.hip
-      if (d.role != GemmRole::ExchangeFock || x_t != NOF_F32 || y_t != NOF_F32 || out_t != NOF_F64 || !d.S)
-        return NOF_E_DTYPE;
-      return d.fold > 1 ? launch<4, 4, 3, float, float, double, true, false, false, true, 3, true>(d, st)
-                        : launch<4, 4, 3, float, float, double, false, false, false, true, 3, true>(d, st);
+    // NOF_P_BF16X10 runs in gemm_fx.hip
     default: return NOF_E_PREC;
   }
 }

@@ -379,6 +379,186 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
       }
 }
 
+// Exchange-type generalized-Fock term of the split forms, on the tiling of
+// the transform above:
+//   Out_g[r][s] = sum_{P in group g} sum_q b^P[q][r] (S[q][s] b^P[q][s])
+// b^P is symmetric, so both operands are read along rows (q contiguous); St
+// is S transposed in FP32 (St[s][q]).  Each FP32 operand value is split into
+// three BF16 pieces (x = hi + mid + lo exactly) and the six products of order
+// <= 2 are accumulated in FP32 within one auxiliary slab, then added to FP64.
+// The term enters lambda and the orbital gradient, not the energy.
+__device__ __forceinline__ void split3(float v, __bf16 (&p)[3]) {
+  const __bf16 h = (__bf16)v;
+  const float r1 = v - (float)h;
+  const __bf16 m = (__bf16)r1;
+  p[0] = h;
+  p[1] = m;
+  p[2] = (__bf16)(r1 - (float)m);
+}
+
+__device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntiles) {
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][3][FT][KT];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][3][FT][KT];
+
+  const int tid = threadIdx.x;
+  const int l = tid & 63, w = tid >> 6;
+  const int wm = w >> 2, wn = w & 3;
+
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  const int grp = logical / ntiles;
+  const int t = logical - grp * ntiles;
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int m0 = tm * FT, n0 = tn * FT;
+  const int n = d.norb;
+  const int nkb = (n + KT - 1) / KT;
+  const int p_lo = grp * d.fold;
+  const int p_hi = min(d.naux, p_lo + d.fold);
+  const int nstage = (p_hi - p_lo) * nkb;
+
+  const int c = tid >> 2, kq = tid & 3;       // row c of both tiles, k quarter kq
+  const bool xok = m0 + c < n, yok = n0 + c < n;
+  const int xrow = min(m0 + c, n - 1), yrow = min(n0 + c, n - 1);
+  const bool vec = (n % 4) == 0;              // rows 16-byte aligned
+
+  float xr[8], yr[8];
+  auto load = [&](int s) {
+    const int pb = p_lo + s / nkb;
+    const int k0 = (s - (pb - p_lo) * nkb) * KT + 8 * kq;
+    const int kl = n - k0;
+    const float* bp = d.b + (long long)pb * n * n;
+    const float* px = bp + (long long)xrow * n;
+    const float* py = bp + (long long)yrow * n;
+    const float* ps = d.St + (long long)yrow * n;
+    if (vec && kl >= 8) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const float4 fx = *(const float4*)(px + k0 + 4 * v);
+        const float4 fy = *(const float4*)(py + k0 + 4 * v);
+        const float4 fs = *(const float4*)(ps + k0 + 4 * v);
+        xr[4 * v] = fx.x; xr[4 * v + 1] = fx.y; xr[4 * v + 2] = fx.z; xr[4 * v + 3] = fx.w;
+        yr[4 * v] = fy.x * fs.x; yr[4 * v + 1] = fy.y * fs.y;
+        yr[4 * v + 2] = fy.z * fs.z; yr[4 * v + 3] = fy.w * fs.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = min(k0 + j, n - 1);
+        const bool in = j < kl;
+        xr[j] = in ? px[k] : 0.f;
+        yr[j] = in ? py[k] * ps[k] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      xr[j] = xok ? xr[j] : 0.f;
+      yr[j] = yok ? yr[j] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+    bf8v px[3], py[3];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 a[3], b[3];
+      split3(xr[e], a);
+      split3(yr[e], b);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) { px[q][e] = a[q]; py[q][e] = b[q]; }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      *(bf8v*)&Xs[buf][q][c][swz(c, kq)] = px[q];
+      *(bf8v*)&Ys[buf][q][c][swz(c, kq)] = py[q];
+    }
+  };
+
+  f4v acc[4][2];
+  d4v acc64[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = f4v{0, 0, 0, 0};
+      acc64[i][j] = d4v{0, 0, 0, 0};
+    }
+
+  const int kl = swz(l & 15, l >> 4);
+  auto compute = [&](int s, int buf) {
+    bf8v b[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) b[j][q] = *(const bf8v*)&Ys[buf][q][wn * 32 + j * 16 + (l & 15)][kl];
+#pragma unroll
+    for (int ip = 0; ip < 4; ip += 2) {
+      bf8v a[2][3];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[i][q] = *(const bf8v*)&Xs[buf][q][wm * 64 + (ip + i) * 16 + (l & 15)][kl];
+#pragma unroll
+      for (int o = 2; o >= 0; --o)
+#pragma unroll
+        for (int px = 0; px <= o; ++px) {
+          const int py = o - px;
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[ip + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], b[j][py], acc[ip + i][j], 0, 0, 0);
+        }
+    }
+    if ((s + 1) % nkb == 0) {                 // end of an auxiliary slab
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+          acc[i][j] = f4v{0, 0, 0, 0};
+        }
+    }
+  };
+
+  if (nstage > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstage) load(s + 1);
+    compute(s, buf);
+    if (s + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  double* __restrict__ Out = d.Out + (long long)grp * n * n;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+        const int gn = n0 + wn * 32 + j * 16 + (l & 15);
+        if (gm < n && gn < n) Out[(long long)gm * n + gn] = acc64[i][j][r];
+      }
+}
+
+__global__ __launch_bounds__(NTHR, 1) void k_exchange_fock_fx(ExDesc d, int tiles_n, int ntiles) {
+  exch_body(d, tiles_n, ntiles);
+}
+
+// St[s][q] = (float)S[q][s]
+__global__ void k_transpose_f32(const double* __restrict__ S, int n, float* __restrict__ St) {
+  const long long total = (long long)n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long s = i / n, q = i - s * n;
+    St[i] = (float)S[q * n + s];
+  }
+}
+
 #define NOF_FX_KERNEL(NAME)                                                              \
   template <int XM, bool YPS, bool BIGK>                                                 \
   __global__ __launch_bounds__(NTHR, 1) void NAME(FxDesc d, int tiles_n, int ntiles) {   \
@@ -429,6 +609,23 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
     // otherwise the same values read k-major (the operand is symmetric)
   }
   return big ? launch_fx<1, true, true>(d, st) : launch_fx<1, true, false>(d, st);
+}
+
+int exchange_fock_fx(const ExDesc& d0, const double* S, float* St, hipStream_t st) {
+  if (d0.naux <= 0 || d0.norb <= 0 || d0.fold <= 0) return NOF_E_DIM;
+  const long long nn = (long long)d0.norb * d0.norb;
+  hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)grid_for(nn, 256)), dim3(256), 0, st, S, d0.norb, St);
+  const int rc = launch_status();
+  if (rc != NOF_OK) return rc;
+  ExDesc d = d0;
+  d.St = St;
+  const int tiles_n = (d.norb + FT - 1) / FT;
+  const int ntiles = tiles_n * tiles_n;
+  const int groups = (d.naux + d.fold - 1) / d.fold;
+  const long long G = (long long)ntiles * groups;
+  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  hipLaunchKernelGGL(k_exchange_fock_fx, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
+  return launch_status();
 }
 
 int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st) {
