@@ -59,7 +59,7 @@ def parse():
                     help="bytes of a plain read+write kernel run 3 times after timing "
                          "(counter calibration under rocprofv3 --pmc)")
     ap.add_argument("--traffic-file", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                           "profiles", "traffic_transform_stage1_c500.json"))
+                                                           "profiles", "traffic_fp64_c500.json"))
     return ap.parse_args()
 
 
@@ -69,15 +69,18 @@ def kernel_source_digest():
     import hashlib
     root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2512_13550_amd", "csrc")
     h = hashlib.sha256()
-    for fn in ("gemm_tn.hip", "common.h"):
-        with open(os.path.join(root, fn), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(root, "gemm_tn.hip"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(root, "common.h"), "rb") as f:      # the descriptor it reads
+        txt = f.read()
+    i = txt.index(b"struct GemmDesc {")
+    h.update(txt[i:txt.index(b"};", i)])
     return h.hexdigest()[:16]
 
 
-def load_traffic(path):
-    """HBM bytes per launch of the dominant kernel from a committed counter
-    summary, or None when absent or taken on other kernel sources."""
+def load_traffic(path, kernel):
+    """HBM bytes per launch of a kernel from a committed counter summary, or
+    None when absent or taken on other kernel sources."""
     try:
         with open(path) as f:
             t = json.load(f)
@@ -85,7 +88,8 @@ def load_traffic(path):
         return None
     if t.get("source_digest") != kernel_source_digest():
         return None
-    return t.get("bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    return k.get("bytes_per_launch") if k else None
 
 
 def main():
@@ -180,7 +184,19 @@ def main():
         res = dict(ms_per_step=total_ms / steps, seg_ms=seg.mean(axis=0).tolist(),
                    E=[float(x) for x in Es], J=J.clone(), K=out["K"].clone(),
                    lam=out["lam"].clone(), g=out["g"].clone())
-        del T, b
+        # the exchange-type Fock kernel alone (inside nof_gen_fock above), same
+        # inputs and launch configuration, timed with events on its stream
+        ws_x = nof.workspace(nof.lib.nof_exchange_fock_ws(naux, norb, nof._TDT[dt], prec), dev)
+        F2 = torch.empty_like(Z)
+        nof.exchange_fock(b, cK, prec=prec, F2=F2, ws=ws_x)
+        ex = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ex[0].record()
+        for _ in range(steps):
+            nof.exchange_fock(b, cK, prec=prec, F2=F2, ws=ws_x)
+        ex[1].record()
+        torch.cuda.synchronize()
+        res["exchange_ms"] = ex[0].elapsed_time(ex[1]) / steps
+        del T, b, ws_x
         torch.cuda.empty_cache()
         return res
 
@@ -191,7 +207,15 @@ def main():
     ms = r64["ms_per_step"]
     value = flops["total"] / (ms * 1e-3) / 1e12
     a1_ms = r64["seg_ms"][1]
-    a1_tf = flops["a1"] / (a1_ms * 1e-3) / 1e12
+    a6_ms = r64["exchange_ms"]
+    # dominant kernel of the FP64 step: transform stage 1 or the exchange-type Fock term
+    if a6_ms > a1_ms:
+        dom = dict(key="k_exchange_fock", name="exchange-type Fock term F2 (sum_P b^P (cK o b^P)), FP64 MFMA",
+                   ms=a6_ms, flops=flops["a6"], bytes=8.0 * (naux * norb * norb + norb * norb))
+    else:
+        dom = dict(key="k_transform_stage1", name="transform stage 1 (T^P = B^P C), FP64 MFMA",
+                   ms=a1_ms, flops=flops["a1"], bytes=8.0 * (naux * nbf * nbf + naux * nbf * norb + nbf * norb))
+    dom_tf = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
 
     forms = {}
     B32 = None
@@ -258,11 +282,14 @@ def main():
         "E_last": r64["E"][-1],
         "algorithmic_flops_per_step": flops["total"],
         "stage_ms": dict(zip(seg_names, r64["seg_ms"])),
-        "roofline": {"bound": "mfma", "kernel": "transform stage 1 (T^P = B^P C), FP64 MFMA",
-                     "achieved": a1_tf, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                     "frac": a1_tf / PEAK["f64"], "traffic": load_traffic(args.traffic_file),
-                     "flops_per_launch": flops["a1"], "avg_launch_ms": a1_ms,
-                     "algorithmic_bytes_per_launch": 8.0 * (naux * nbf * nbf + naux * nbf * norb + nbf * norb)},
+        "roofline": {"bound": "mfma", "kernel": dom["name"],
+                     "achieved": dom_tf, "peak": PEAK["f64"], "unit": "TFLOP/s",
+                     "frac": dom_tf / PEAK["f64"], "traffic": load_traffic(args.traffic_file, dom["key"]),
+                     "flops_per_launch": dom["flops"], "avg_launch_ms": dom["ms"],
+                     "algorithmic_bytes_per_launch": dom["bytes"],
+                     "other": {"transform_stage1_ms": a1_ms, "exchange_fock_ms": a6_ms,
+                               "transform_stage1_frac": flops["a1"] / (a1_ms * 1e-3) / 1e12 / PEAK["f64"],
+                               "exchange_fock_frac": flops["a6"] / (a6_ms * 1e-3) / 1e12 / PEAK["f64"]}},
         "forms": forms,
         "batched": batched,
         "warmstart": warm,

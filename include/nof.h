@@ -184,8 +184,10 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  * lambda  out [norb][norb] FP64.          grad  out, may be NULL.
  * K_opt   if not NULL, also receives K (same definition as nof_jk_diag),
  *         formed in the same pass over b as the Coulomb-type term.
- * prec    NOF_P_F64 (bt = NOF_F64) or NOF_P_F32 (bt = NOF_F32) for the
- *         exchange-type contraction; the pass over b accumulates in FP64.
+ * prec    NOF_P_F64 (bt = NOF_F64), NOF_P_F32 or a split form (bt = NOF_F32)
+ *         for the exchange-type contraction (X10: three element-wise BF16
+ *         pieces, FP32 accumulation within a slab); the pass over b
+ *         accumulates in FP64.
  * ------------------------------------------------------------------------- */
 size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec);
 int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D,
@@ -193,6 +195,17 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D,
                  const double* cJ, const double* cK,
                  double* lambda, double* grad, double* K_opt,
                  int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * The exchange-type term of the generalized Fock build alone (the last sum
+ * of lambda above, NO Optimization), as nof_gen_fock computes it:
+ *   F2_rs = sum_P sum_q b^P_rq cK_sq b^P_qs
+ * b, bt, cK, prec as in nof_gen_fock.  F2 out [norb][norb] FP64 (not
+ * symmetric).  ws: at least nof_exchange_fock_ws(...) bytes.
+ * ------------------------------------------------------------------------- */
+size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec);
+int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* cK, double* F2,
+                      int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Energy of Eq. (PNOF):

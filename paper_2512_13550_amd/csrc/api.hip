@@ -314,6 +314,55 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, doub
   });
 }
 
+// F2 (exchange-type term) into F2 from the partials in f2part (groups of
+// L.f2fold slabs); St: norb*norb FP32 scratch of the split forms.
+int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, int prec,
+                  const FockLayout& L, double* f2part, float* St, double* F2, hipStream_t stream) {
+  const long long n2 = (long long)norb * norb;
+  if (prec == NOF_P_BF16X10) {
+    ExDesc e{naux, norb, L.f2fold, (const float*)b, nullptr, f2part};
+    NOF_TRY(exchange_fock_fx(e, cK, St, stream));
+  } else {
+    // F2_rs = sum_P sum_q b^P[q][r] (cK[q][s] b^P[q][s])
+    GemmDesc g2{};
+    g2.M = norb; g2.N = norb; g2.K = norb; g2.Ktot = 0;
+    g2.batch = naux; g2.fold = L.f2fold;
+    g2.X = b; g2.ldx = norb; g2.sx = n2; g2.x_kmajor = true;
+    g2.Y = b; g2.ldy = norb; g2.sy = n2;
+    g2.S = cK; g2.lds = norb;
+    g2.Out = f2part; g2.ldo = norb; g2.so = n2;
+    g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
+    g2.role = GemmRole::ExchangeFock;
+    NOF_TRY(gemm_any(g2, bt, bt, NOF_F64, prec, stream));
+  }
+  return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
+}
+
+size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
+  if (!dim_ok(naux) || !dim_ok(norb)) return 0;
+  if (!prec_matches(prec, bt)) return 0;
+  const FockLayout L = fock_layout(naux, norb);
+  return align256((size_t)L.f2groups * norb * norb * sizeof(double)) +
+         align256((size_t)norb * norb * sizeof(float));
+}
+
+int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* cK, double* F2,
+                      int prec, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!b || !cK || !F2) return NOF_E_NULL;
+    if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
+    if (!prec_ok(prec)) return NOF_E_PREC;
+    if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    if (!ws || ws_bytes < nof_exchange_fock_ws(naux, norb, bt, prec)) return NOF_E_WORKSPACE;
+    const FockLayout L = fock_layout(naux, norb);
+    char* w = (char*)ws;
+    double* part = (double*)w;
+    float* St = (float*)(w + align256((size_t)L.f2groups * norb * norb * sizeof(double)));
+    return exchange_term(naux, norb, b, bt, cK, prec, L, part, St, F2, stream);
+  });
+}
+
 size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
@@ -353,23 +402,8 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     NOF_TRY(kf1_pass(naux, norb, b, bt, W, K_opt ? kpart : nullptr, f1part, L.kchunks, stream));
     NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
     if (K_opt) NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K_opt, stream));
-    // Exchange-type term F2_rs = sum_P sum_q b^P[q][r] (cK[q][s] b^P[q][s])
-    GemmDesc g2{};
-    g2.M = norb; g2.N = norb; g2.K = norb; g2.Ktot = 0;
-    g2.batch = naux; g2.fold = L.f2fold;
-    g2.X = b; g2.ldx = norb; g2.sx = n2; g2.x_kmajor = true;
-    g2.Y = b; g2.ldy = norb; g2.sy = n2;
-    g2.S = cK; g2.lds = norb;
-    g2.Out = f2part; g2.ldo = norb; g2.so = n2;
-    g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
-    g2.role = GemmRole::ExchangeFock;
-    if (prec == NOF_P_BF16X10) {
-      ExDesc e{naux, norb, L.f2fold, (const float*)b, nullptr, f2part};
-      NOF_TRY(exchange_fock_fx(e, cK, (float*)(w + L.off_St), stream));
-    } else {
-      NOF_TRY(gemm_any(g2, bt, bt, NOF_F64, prec, stream));
-    }
-    NOF_TRY(reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream));
+    // Exchange-type term F2
+    NOF_TRY(exchange_term(naux, norb, b, bt, cK, prec, L, f2part, (float*)(w + L.off_St), F2, stream));
     return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
   });
 }

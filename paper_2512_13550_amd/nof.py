@@ -44,6 +44,8 @@ _sig("nof_mo_transform_stage2", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, 
 _sig("nof_jk_diag_ws", _sz, _i, _i, _i)
 _sig("nof_jk_diag", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
+_sig("nof_exchange_fock_ws", _sz, _i, _i, _i, _i)
+_sig("nof_exchange_fock", _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp)
 _sig("nof_gen_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp)
 _sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_coeffs_from_cumulant", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp)
@@ -86,7 +88,7 @@ DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
     "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_split_B_bytes", "nof_split_B",
     "nof_jk_diag_ws", "nof_jk_diag",
-    "nof_gen_fock_ws", "nof_gen_fock", "nof_energy", "nof_coeffs_from_cumulant",
+    "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
@@ -264,6 +266,21 @@ def gen_fock(b, D, n, h, cJ, cK, want_grad=True, want_K=False, prec=None, out=No
                            _f64(cJ, "cJ"), _f64(cK, "cK"), _p(lam), _p(g), _p(K), prec, _p(ws),
                            ws.numel(), stream_handle(stream)), "nof_gen_fock")
     return lam, g, K
+
+
+def exchange_fock(b, cK, prec=None, F2=None, ws=None, stream=None):
+    """F2_rs = sum_P sum_q b^P_rq cK_sq b^P_qs alone (nof_exchange_fock)."""
+    naux, norb, _ = b.shape
+    bt = _TDT[b.dtype]
+    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    if F2 is None:
+        F2 = torch.empty((norb, norb), dtype=torch.float64, device=b.device)
+    need = lib.nof_exchange_fock_ws(naux, norb, bt, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, b.device)
+    check(lib.nof_exchange_fock(naux, norb, _p(b), bt, _f64(cK, "cK"), _p(F2), prec, _p(ws), ws.numel(),
+                                stream_handle(stream)), "nof_exchange_fock")
+    return F2
 
 
 def energy(n, h, J, K, cJ, cK, E=None, stream=None):

@@ -74,3 +74,33 @@ def test_jk_and_fock_validation():
     assert L.nof_energy(0, *([FAKE] * 7), None) == nof.E_DIM
     assert L.nof_energy(4, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, None) == nof.E_NULL
     assert L.nof_coeffs_from_cumulant(4, FAKE, None, FAKE, FAKE, FAKE, None) == nof.E_NULL
+
+
+def test_exchange_split_and_stage_validation():
+    nof = _lib()
+    L = nof.lib
+    big = 1 << 30
+    assert L.nof_exchange_fock(0, 4, FAKE, 0, FAKE, FAKE, 0, FAKE, big, None) == nof.E_DIM
+    assert L.nof_exchange_fock(3, 4, None, 0, FAKE, FAKE, 0, FAKE, big, None) == nof.E_NULL
+    assert L.nof_exchange_fock(3, 4, FAKE, 0, None, FAKE, 0, FAKE, big, None) == nof.E_NULL
+    assert L.nof_exchange_fock(3, 4, FAKE, 2, FAKE, FAKE, 0, FAKE, big, None) == nof.E_DTYPE
+    assert L.nof_exchange_fock(3, 4, FAKE, 0, FAKE, FAKE, 1, FAKE, big, None) == nof.E_PREC
+    assert L.nof_exchange_fock(3, 4, FAKE, 1, FAKE, FAKE, 0, FAKE, big, None) == nof.E_PREC
+    assert L.nof_exchange_fock(3, 4, FAKE, 0, FAKE, FAKE, 0, FAKE, 8, None) == nof.E_WORKSPACE
+    assert L.nof_exchange_fock_ws(3, 4, 0, 1) == 0
+    assert L.nof_exchange_fock_ws(3, 4, 1, nof.P_BF16X10) >= 3 * 4 * 4 * 8 // 3
+    # fixed-point planes of B: [4][naux][nbf][ldk], ldk = nbf rounded up to 32
+    assert L.nof_split_B_bytes(2, 33) == 4 * 2 * 33 * 64 * 2
+    assert L.nof_split_B_bytes(0, 33) == 0
+    assert L.nof_split_B(2, 4, FAKE, nof.BF16, FAKE, big, None) == nof.E_DTYPE
+    assert L.nof_split_B(2, 4, None, nof.F32, FAKE, big, None) == nof.E_NULL
+    assert L.nof_split_B(2, 4, FAKE, nof.F32, FAKE, 8, None) == nof.E_WORKSPACE
+    # planes are accepted by the x10 transform only
+    assert L.nof_mo_transform(2, 4, 4, FAKE, nof.BF16X4, FAKE, FAKE, 1, None, nof.P_BF16X6, FAKE, big, None) == nof.E_DTYPE
+    # stage workspace: FP64/FP32 need none of substance; x10 holds C planes and grid exponents
+    assert L.nof_mo_transform_stage_ws(2, 40, 30, nof.P_F64) > 0
+    x10 = L.nof_mo_transform_stage_ws(2, 40, 30, nof.P_BF16X10)
+    assert x10 >= 4 * 30 * 64 * 2 + 2 * 40 * 4
+    assert L.nof_mo_transform_stage_ws(0, 40, 30, nof.P_BF16X10) == 0
+    assert L.nof_mo_transform_stage1(2, 40, 30, FAKE, nof.F32, FAKE, FAKE, nof.F32, nof.P_BF16X10,
+                                     FAKE, x10 - 1, None) == nof.E_WORKSPACE

@@ -78,6 +78,9 @@ def test_bf16_x10_fixed_point(nbf, naux, norb, seed):
     for k in ("b", "J", "K", "lam"):
         assert errs[k] <= 3e-7, (k, errs[k])
     assert errs["E"] <= 2e-8
+    b32 = dev(ref["b"], torch.float32)
+    F2 = nof.exchange_fock(b32, dev(cK), prec=nof.P_BF16X10)
+    assert normwise(host(F2), ref["F2"]) <= 3e-7
 
 
 @pytest.mark.parametrize("src", ["f32", "f64"])

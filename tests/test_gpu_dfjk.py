@@ -50,6 +50,8 @@ def test_transform_jk_fock_energy_fp64(nbf, naux, norb, seed):
     assert normwise(host(lam), ref["lam"]) <= FP64_TOL
     assert normwise(host(g), ref["g"]) <= FP64_TOL
     assert abs(float(E) - ref["E"]) <= FP64_TOL * abs(ref["E"])
+    F2 = nof.exchange_fock(b, dev(cK))
+    assert normwise(host(F2), ref["F2"]) <= FP64_TOL
 
 
 def test_structured_coefficients_hf_closed_form():
