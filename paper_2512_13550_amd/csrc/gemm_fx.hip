@@ -99,39 +99,66 @@ __global__ void k_row_exps(const T* __restrict__ A, long long nrow, int K, int* 
 }
 
 // Grid exponents of the columns of A_b[K][N] (FP32, batch stride sa):
-// e[b*N + n] from max_k |A_b[k][n]|; one thread per (b, n).
+// e[b*N + n] from max_k |A_b[k][n]|.  Block: 64 columns x 4 row groups (lanes
+// along n read contiguous rows), combined through LDS.
 __global__ void k_col_exps(const float* __restrict__ A, int batch, int K, int N, long long sa,
                            int* __restrict__ e) {
-  const long long total = (long long)batch * N;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long b = i / N;
-    const int n = (int)(i - b * N);
-    const float* a = A + b * sa + n;
+  __shared__ unsigned red[4][64];
+  const int cb = (N + 63) / 64;
+  const int c = threadIdx.x & 63, kg = threadIdx.x >> 6;
+  for (long long blk = blockIdx.x; blk < (long long)batch * cb; blk += gridDim.x) {
+    const long long b = blk / cb;
+    const int n = (int)(blk - b * cb) * 64 + c;
     unsigned m = 0;
-    for (int k = 0; k < K; ++k) m = max(m, __float_as_uint(a[(long long)k * N]) & 0x7fffffffu);
-    e[i] = grid_exp_bits(m);
+    if (n < N) {
+      const float* a = A + b * sa + n;
+#pragma unroll 4
+      for (int k = kg; k < K; k += 4) m = max(m, __float_as_uint(a[(long long)k * N]) & 0x7fffffffu);
+    }
+    red[kg][c] = m;
+    __syncthreads();
+    if (kg == 0 && n < N) e[b * N + n] = grid_exp_bits(max(max(red[0][c], red[1][c]), max(red[2][c], red[3][c])));
+    __syncthreads();
   }
 }
 
 // Planes of the columns of an FP64 k-major matrix A[k][col] (k < K):
-// out[q][col][ldk], one grid per column; one thread per column.
+// out[q][col][ldk], one grid per column.  Block: 16 columns; the column
+// maxima from 16 row groups, then each wave splits four columns with lanes
+// along k (contiguous plane writes).
 __global__ void k_split_cols(const double* __restrict__ A, int K, int ncol, int lda, int ldk,
                              __bf16* __restrict__ out) {
+  __shared__ double red[16][16];
+  __shared__ int ecol[16];
   const long long plane = (long long)ncol * ldk;
-  for (int col = blockIdx.x * blockDim.x + threadIdx.x; col < ncol; col += gridDim.x * blockDim.x) {
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int c = t & 15, kg = t >> 4;
+  for (int c0 = blockIdx.x * 16; c0 < ncol; c0 += gridDim.x * 16) {
     double m = 0.0;
-    for (int k = 0; k < K; ++k) m = fmax(m, fabs(A[(long long)k * lda + col]));
-    int E;
-    frexp(m, &E);
-    E = clamp_exp(E);
-    __bf16* o = out + (long long)col * ldk;
-    for (int k = 0; k < ldk; ++k) {
-      __bf16 p[4];
-      split_g64(k < K ? A[(long long)k * lda + col] : 0.0, E, p);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) o[q * plane + k] = p[q];
+    if (c0 + c < ncol)
+      for (int k = kg; k < K; k += 16) m = fmax(m, fabs(A[(long long)k * lda + c0 + c]));
+    red[kg][c] = m;
+    __syncthreads();
+    if (kg == 0) {
+      double mm = 0.0;
+      for (int i = 0; i < 16; ++i) mm = fmax(mm, red[i][c]);
+      int E;
+      frexp(mm, &E);
+      ecol[c] = clamp_exp(E);
     }
+    __syncthreads();
+    for (int cc = 4 * w; cc < 4 * w + 4; ++cc) {
+      const int col = c0 + cc;
+      if (col >= ncol) break;
+      __bf16* o = out + (long long)col * ldk;
+      for (int k = l; k < ldk; k += 64) {
+        __bf16 p[4];
+        split_g64(k < K ? A[(long long)k * lda + col] : 0.0, ecol[cc], p);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q * plane + k] = p[q];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -642,15 +669,15 @@ int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_
 
 int fx_col_exps(const float* A, int batch, int K, int N, long long sa, int* e, hipStream_t st) {
   if (batch <= 0 || K <= 0 || N <= 0) return NOF_E_DIM;
-  const unsigned g = (unsigned)grid_for((long long)batch * N, 256);
+  const unsigned g = (unsigned)grid_for((long long)batch * ((N + 63) / 64), 1);
   hipLaunchKernelGGL(k_col_exps, dim3(g), dim3(256), 0, st, A, batch, K, N, sa, e);
   return launch_status();
 }
 
 int fx_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* out, hipStream_t st) {
   if (K <= 0 || ncol <= 0 || ldk < K || ldk % KT) return NOF_E_DIM;
-  const unsigned g = (unsigned)grid_for(ncol, 64);
-  hipLaunchKernelGGL(k_split_cols, dim3(g), dim3(64), 0, st, A, K, ncol, lda, ldk, (__bf16*)out);
+  const unsigned g = (unsigned)grid_for(ncol, 16);
+  hipLaunchKernelGGL(k_split_cols, dim3(g), dim3(256), 0, st, A, K, ncol, lda, ldk, (__bf16*)out);
   return launch_status();
 }
 
