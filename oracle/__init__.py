@@ -24,4 +24,7 @@ Pin status (what each function is checked against, in tests/test_oracle_*.py):
   occupations.*               pinned: sum rule, bounds, finite differences
   rotation.*                  pinned: orthogonality, closed forms
   mlp.*                       pinned: finite differences, hand-checked tiny net
+  solver.solve                pinned: closed-shell HF minimum equal to a DIIS
+                              Roothaan SCF; stationarity (lambda symmetric, ON
+                              gradient zero) and variational checks at the end
 """

@@ -1,0 +1,105 @@
+"""Pins of the alternating NO + ON optimisation (oracle/solver.py).
+
+1. Closed-shell HF: with the HF-like coefficients and occupations frozen at
+   1 (ns orbitals) / 0, the NO optimisation must reach the minimum of the
+   closed-shell Hartree-Fock energy, which a textbook Roothaan SCF with DIIS
+   (Pulay, Chem. Phys. Lett. 73 (1980)) finds independently by
+   diagonalising the Fock matrix F = H + J[D] - K[D] of the AO density
+   D = C_occ C_occ^T (orthonormal AO basis, B = the fitted three-index tensor).
+2. PNOF5 on a kernel-on-grid tensor: at convergence lambda is symmetric,
+   re-optimising the occupations gains nothing, and no small rotation of the
+   orbitals or change of the occupation variables lowers the energy.  (With
+   the trigonometric map this instance alternates without settling within
+   200 outer iterations at the default learning rate; the softmax map, the
+   numerically more stable one, converges.)
+"""
+import numpy as np
+import pytest
+
+from oracle import dfjk, functionals, mlp, occupations, rotation, solver
+from paper_2512_13550_amd import inputs
+
+
+def scf_energy(B, H, nocc, iters=300):
+    e, V = np.linalg.eigh(H)
+    Cocc = V[:, :nocc]
+    Fs, errs = [], []
+    E_old = None
+    for _ in range(iters):
+        D = Cocc @ Cocc.T
+        Jm = np.einsum("Pmn,P->mn", B, 2.0 * np.einsum("Pab,ab->P", B, D))
+        Km = np.einsum("Pma,ab,Pbn->mn", B, D, B)
+        F = H + Jm - Km
+        E = float(np.sum(D * (2.0 * H + Jm - Km)))
+        err = F @ D - D @ F
+        Fs, errs = (Fs + [F])[-8:], (errs + [err])[-8:]
+        k = len(Fs)
+        A = -np.ones((k + 1, k + 1))
+        A[k, k] = 0.0
+        for i in range(k):
+            for j in range(k):
+                A[i, j] = np.sum(errs[i] * errs[j])
+        rhs = np.zeros(k + 1)
+        rhs[k] = -1.0
+        c = np.linalg.solve(A, rhs)[:k]
+        _, V = np.linalg.eigh(sum(ci * Fi for ci, Fi in zip(c, Fs)))
+        Cocc = V[:, :nocc]
+        if E_old is not None and abs(E - E_old) < 1e-13 and np.max(np.abs(err)) < 1e-10:
+            return E
+        E_old = E
+    raise AssertionError("SCF did not converge")
+
+
+def test_hf_minimum_equals_roothaan_scf():
+    nbf, naux, nocc = 24, 96, 6
+    B = inputs.make_B_grid(nbf, naux, seed=3)
+    H = inputs.make_H(3, nbf)
+    C0 = inputs.make_C(3, nbf, nbf)
+    members = np.array(inputs.pairing(nbf, nocc, 1), dtype=np.int64)
+    gamma = np.zeros((nocc, 1))                       # trig: n = 1 strong, 0 weak
+    n = occupations.occupations(gamma, members, nbf, "trig")
+    assert np.allclose(np.sort(n)[::-1][:nocc], 1.0) and np.isclose(n.sum(), nocc)
+    r = solver.solve(B, C0, H, members, "trig", "hf", gamma, max_outer=3, no_steps=4000,
+                     tol_lambda=1e-9, on_maxit=0)
+    assert r["converged"]
+    E_scf = scf_energy(B, H, nocc)
+    assert abs(r["E"] - E_scf) <= 1e-10 * abs(E_scf), (r["E"], E_scf)
+
+
+@pytest.mark.parametrize("mapping", ["softmax"])
+def test_pnof5_converged_point_is_stationary(mapping):
+    nbf, naux, ns, ng = 24, 96, 6, 2
+    B = inputs.make_B_grid(nbf, naux, seed=5)
+    H = inputs.make_H(5, nbf)
+    C0 = inputs.make_C(5, nbf, nbf)
+    members = np.array(inputs.pairing(nbf, ns, ng), dtype=np.int64)
+    gamma0 = mlp.cold_gamma(members, mapping)
+    hist = []
+    r = solver.solve(B, C0, H, members, mapping, "pnof5", gamma0, max_outer=200, tol_lambda=1e-6,
+                     tol_energy=1e-10, history=hist)
+    assert r["converged"], (r["outer"], r["asym"])
+    C, gamma, E = r["C"], r["gamma"], r["E"]
+    # the energy of the returned point
+    b, _ = dfjk.mo_transform(B, C)
+    h = dfjk.one_electron(H, C)
+    J, K = dfjk.jk(b)
+    n = occupations.occupations(gamma, members, nbf, mapping)
+    cJ, cK = functionals.coefficients(n, members, "pnof5")
+    assert abs(dfjk.energy(n, h, J, K, cJ, cK) - E) <= 1e-12 * abs(E)
+    assert E < hist[0][0]
+    # re-optimising the occupations at the final orbitals gains nothing (the
+    # last NO sweep follows the ON step, so the ON gradient is not exactly 0)
+    _, _, E_on, _, _ = occupations.optimize_lbfgs(gamma, members, nbf, mapping, np.diag(h), J, K, "pnof5")
+    assert E_on >= E - 1e-9
+    # no small rotation or occupation change lowers E
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        Y = rng.standard_normal((nbf, nbf))
+        y = 1e-3 * (Y - Y.T)
+        b2, _ = dfjk.mo_transform(B, rotation.rotate(C, y))
+        h2 = dfjk.one_electron(H, rotation.rotate(C, y))
+        J2, K2 = dfjk.jk(b2)
+        assert dfjk.energy(n, h2, J2, K2, cJ, cK) >= E - 1e-9
+        gp = gamma + 1e-3 * rng.standard_normal(gamma.shape)
+        Ep, _, _ = occupations.energy_and_grad(gp, members, nbf, mapping, np.diag(h), J, K, "pnof5")
+        assert Ep >= E - 1e-10
