@@ -393,6 +393,58 @@ int nof_mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map,
                        const float* theta, double nfloor, double* gamma, int* info,
                        hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * The alternating NO + ON optimisation to convergence (Theory: the energy is
+ * minimised separately over occupations and orbitals; Occupation Number
+ * Optimization; Natural Orbital Optimization: lambda symmetric at the
+ * minimum, g = 4(lambda - lambda^T), ADAM on the generator y, U = exp(y)).
+ *
+ * Outer iteration: the ON step at fixed orbitals (nof_occ_optimize on gamma
+ * with h, J, K of the current C; skipped when on_maxit = 0, the occupations
+ * then stay those of gamma), then a sweep of up to no_steps ADAM steps
+ * C <- C exp(y) at fixed occupations.  A sweep ends once
+ * max|lambda - lambda^T| <= tol_lambda (NTHRESHL's criterion); the run ends
+ * when a sweep ended so and E changed by at most tol_energy since the
+ * previous outer iteration (NTHRESHE's), or after max_outer iterations.  The
+ * ADAM moments persist over the run (one step counter for the bias
+ * correction).  The host reads E and max|lambda - lambda^T| once per step.
+ *
+ * B, Bt, prec   as nof_mo_transform (NOF_P_F64, NOF_P_F32 or NOF_P_BF16X10;
+ *               for X10, B in FP32 or as nof_split_B planes).
+ * H             [nbf][nbf] FP64 AO one-electron matrix.
+ * C             [nbf][norb] FP64, in: start orbitals, out: final orbitals.
+ * members, map, func, ns, ng   as nof_occ_optimize (device).
+ * gamma         [ns][ng] FP64, in/out.   n_out  [norb] FP64, may be NULL.
+ * p             host parameters (typical: 100 outer, 30 steps, lr 0.01,
+ *               0.9, 0.999, 1e-8, tol_lambda 1e-5, tol_energy 1e-9,
+ *               on_maxit 2000, on_tol 1e-8).
+ * res           host result.  Errors: NOF_E_NULL, NOF_E_ARG, NOF_E_DIM,
+ *               NOF_E_WORKSPACE, the status of a failing step (also in
+ *               res->status), NOF_E_NOT_CONVERGED if E or the asymmetry
+ *               stops being finite.  Not convergence within max_outer is
+ *               not an error: res->converged = 0.
+ * ws            at least nof_solve_ws(...) bytes.  Not capturable in a HIP
+ *               graph (it synchronises the stream every step).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int max_outer, no_steps;
+  double lr, beta1, beta2, eps;
+  double tol_lambda, tol_energy;
+  int on_maxit;
+  double on_tol;
+} nof_solve_params;
+
+typedef struct {
+  double E, asym;
+  int outer, no_steps, on_iters, converged, status;
+} nof_solve_result;
+
+size_t nof_solve_ws(int naux, int nbf, int norb, int ns, int ng, int Bt, int prec);
+int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* H, double* C,
+              int ns, int ng, const int* members, int map, int func, double* gamma,
+              double* n_out, int prec, const nof_solve_params* p, nof_solve_result* res,
+              void* ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

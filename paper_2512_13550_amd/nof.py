@@ -81,6 +81,19 @@ _sig("nof_mlp_adam", _i, _i, _vp, _vp, _vp, _vp, _i, ctypes.c_float, ctypes.c_fl
      ctypes.c_float, _vp)
 _sig("nof_mlp_warm_gamma", _i, _i, _i, _i, _vp, _i, _vp, _d, _vp, _vp, _vp)
 
+class SolveParams(ctypes.Structure):
+    _fields_ = [("max_outer", _i), ("no_steps", _i), ("lr", _d), ("beta1", _d), ("beta2", _d),
+                ("eps", _d), ("tol_lambda", _d), ("tol_energy", _d), ("on_maxit", _i), ("on_tol", _d)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("E", _d), ("asym", _d), ("outer", _i), ("no_steps", _i), ("on_iters", _i),
+                ("converged", _i), ("status", _i)]
+
+
+_sig("nof_solve_ws", _sz, _i, _i, _i, _i, _i, _i, _i)
+_sig("nof_solve", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _i, _i, _vp, _vp, _i,
+     ctypes.POINTER(SolveParams), ctypes.POINTER(SolveResult), _vp, _sz, _vp)
 MAP_TRIG, MAP_SOFTMAX = 0, 1
 FUNC_HF, FUNC_PNOF5 = 0, 1
 
@@ -94,7 +107,7 @@ DECLARED = [
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
     "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
-    "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
+    "nof_solve_ws", "nof_solve", "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
 ]
 
 
@@ -528,3 +541,28 @@ def mlp_warm_gamma(theta, members, mapping, norb, nfloor=1e-12, info=None, strea
                                  stream_handle(stream)),
           "nof_mlp_warm_gamma")
     return gamma
+
+
+def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=None, stream=None,
+          max_outer=100, no_steps=30, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, tol_lambda=1e-5,
+          tol_energy=1e-9, on_maxit=2000, on_tol=1e-8):
+    """Alternating NO + ON optimisation to convergence (nof_solve).  C and gamma
+    are updated in place; returns the result as a dict."""
+    naux, nbf, _ = B.shape
+    norb = C.shape[1]
+    ns, ng = gamma.shape
+    Bt, Bp = _b_arg(B)
+    prec = _PREC_OF.get(Bt, P_BF16X10 if Bt == BF16X4 else P_F64) if prec is None else prec
+    if members.dtype != torch.int32:
+        raise TypeError("members must be int32")
+    need = lib.nof_solve_ws(naux, nbf, norb, ns, ng, Bt, prec)
+    if need == 0:
+        raise NofError(E_DIM, "nof_solve_ws")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, C.device)
+    prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit, on_tol)
+    res = SolveResult()
+    check(lib.nof_solve(naux, nbf, norb, Bp, Bt, _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
+                        mapping, functional, _f64(gamma, "gamma"), _p(n), prec, ctypes.byref(prm),
+                        ctypes.byref(res), _p(ws), ws.numel(), stream_handle(stream)), "nof_solve")
+    return {f: getattr(res, f) for f, _ in SolveResult._fields_}

@@ -104,3 +104,21 @@ def test_exchange_split_and_stage_validation():
     assert L.nof_mo_transform_stage_ws(0, 40, 30, nof.P_BF16X10) == 0
     assert L.nof_mo_transform_stage1(2, 40, 30, FAKE, nof.F32, FAKE, FAKE, nof.F32, nof.P_BF16X10,
                                      FAKE, x10 - 1, None) == nof.E_WORKSPACE
+
+
+def test_solve_validation():
+    import ctypes
+    nof = _lib()
+    L = nof.lib
+    prm = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+    res = nof.SolveResult()
+    args = lambda B, p, ws_bytes: (2, 4, 4, B, 0, FAKE, FAKE, 1, 1, FAKE, 1, 1, FAKE, None, 0,
+                                   ctypes.byref(p), ctypes.byref(res), FAKE, ws_bytes, None)
+    assert L.nof_solve(*args(None, prm, 1 << 30)) == nof.E_NULL
+    bad = nof.SolveParams(0, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+    assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
+    bad = nof.SolveParams(10, 30, 0.0, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+    assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
+    assert L.nof_solve(*args(FAKE, prm, 8)) == nof.E_WORKSPACE
+    assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_BF16X1) == 0
+    assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_F64) > 2 * 4 * 4 * 8
