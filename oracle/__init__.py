@@ -24,6 +24,10 @@ Pin status (what each function is checked against, in tests/test_oracle_*.py):
   occupations.*               pinned: sum rule, bounds, finite differences
   rotation.*                  pinned: orthogonality, closed forms
   mlp.*                       pinned: finite differences, hand-checked tiny net
+  nlop.*                      pinned: exact on polynomial dipoles, analytic
+                              derivatives of a smooth dipole, hand-made
+                              selection cases, Hellmann-Feynman (dipole equals
+                              minus the field derivative of SCF energies)
   solver.solve                pinned: closed-shell HF minimum equal to a DIIS
                               Roothaan SCF; stationarity (lambda symmetric, ON
                               gradient zero) and variational checks at the end

@@ -1,0 +1,110 @@
+"""Pins of the finite-field NLOP step (oracle/nlop.py).
+
+- Polynomial dipoles: for mu(F) a polynomial of degree 5 the centred
+  differences carry errors in h^2 and h^4 only, so the third Romberg column is
+  exact and the selected values equal alpha = mu'(0), beta = mu''(0) and
+  gamma = mu'''(0) to rounding.
+- A smooth non-polynomial mu(F) = a sin(wF) + b F^2 e^F: the selected values
+  approach the analytic derivatives far below the first-column error.
+- The selection rule on a hand-made triangle (smallest vertical difference,
+  value from the next column, ties to the smallest magnitude).
+- The dipole formula against Hellmann-Feynman: at the closed-shell SCF
+  minimum mu(F) = -dE/dF, checked by a centred difference of SCF energies.
+- Isotropic average and anisotropy closed forms.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import nlop
+from paper_2512_13550_amd import inputs
+from _scf import scf_energy
+
+
+def ladder(f, step, npoint):
+    mu_p = [f(step * 2.0 ** k) for k in range(npoint + 1)]
+    mu_m = [f(-step * 2.0 ** k) for k in range(npoint + 1)]
+    return f(0.0), mu_p, mu_m
+
+
+def test_polynomial_dipole_is_exact():
+    c = [0.3, 4.2, -1.7, 35.0, 11.0, -80.0]          # mu = sum c_i F^i
+    f = lambda F: sum(ci * F ** i for i, ci in enumerate(c))
+    mu0, mp, mm = ladder(f, 1e-3, 5)
+    res = nlop.nlop(mu0, mp, mm, 1e-3, 5)
+    exact = [c[1], 2.0 * c[2], 6.0 * c[3]]
+    for r, e in zip(res, exact):
+        assert abs(r["value"] - e) <= 1e-6 * max(1.0, abs(e)), (r["value"], e)
+        assert abs(r["table"][0, 2] - e) <= 1e-6 * max(1.0, abs(e))
+
+
+def test_smooth_dipole_converges():
+    a, w, b = 1.3, 2.0, 0.7
+    f = lambda F: a * math.sin(w * F) + b * F * F * math.exp(F)
+    exact = [a * w, 2.0 * b, -a * w ** 3 + 6.0 * b]   # derivatives at 0
+    mu0, mp, mm = ladder(f, 1e-2, 6)
+    res = nlop.nlop(mu0, mp, mm, 1e-2, 6)
+    for r, e in zip(res, exact):
+        first_col_err = abs(r["table"][0, 0] - e)
+        assert abs(r["value"] - e) <= max(1e-3 * first_col_err, 1e-7 * abs(e)), (r["value"], e)
+
+
+def test_selection_rule():
+    R = np.full((3, 3), np.nan)
+    R[:, 0] = [1.0, 1.5, 3.0]          # vertical differences 0.5, 1.5
+    R[:2, 1] = [0.75, 1.0]             # difference 0.25 (smallest)
+    R[0, 2] = 0.875
+    v, d, k, j = nlop.select(R)
+    assert (v, d, k, j) == (0.875, 0.25, 0, 1)
+    # a tie between two pairs: the smaller candidate value wins
+    R = np.full((3, 3), np.nan)
+    R[:, 0] = [1.0, 1.25, 1.5]         # two pairs, both 0.25
+    R[:2, 1] = [2.0, -0.5]             # candidates of column 0: 2.0 (k=0), -0.5 (k=1); difference 2.5
+    R[0, 2] = 7.0
+    v, d, k, j = nlop.select(R)
+    assert (v, d, k, j) == (-0.5, 0.25, 1, 0)
+    # the Romberg recursion itself: a first column D(h) = A + c h^2 with
+    # h doubling down the column extrapolates to A in the second column
+    A, c = 2.5, 3.0
+    D = np.array([A + c * (0.1 * 2 ** k) ** 2 for k in range(4)])
+    assert np.allclose(nlop.romberg(D)[:3, 1], A, rtol=0, atol=1e-14)
+
+
+def test_dipole_is_minus_energy_derivative_at_scf_minimum():
+    nbf, nocc = 16, 4
+    B = inputs.make_B_grid(nbf, 64, seed=2)
+    H = inputs.make_H(2, nbf)
+    d = inputs.make_dipoles(2, nbf)[2]
+    h = 1e-4
+    Ep = scf_energy(B, H + h * d, nocc)
+    Em = scf_energy(B, H - h * d, nocc)
+    # orbitals of the field-free SCF minimum (the occupied eigenvectors of F)
+    C, n = scf_orbitals(B, H, nocc)
+    mu = nlop.dipole(C, n, d)
+    assert abs(mu - (-(Ep - Em) / (2.0 * h))) <= 1e-7 * max(1.0, abs(mu))
+
+
+def scf_orbitals(B, H, nocc, iters=300):
+    e, V = np.linalg.eigh(H)
+    Cocc = V[:, :nocc]
+    for _ in range(iters):
+        D = Cocc @ Cocc.T
+        Jm = np.einsum("Pmn,P->mn", B, 2.0 * np.einsum("Pab,ab->P", B, D))
+        Km = np.einsum("Pma,ab,Pbn->mn", B, D, B)
+        F = H + Jm - Km
+        e, V = np.linalg.eigh(F)
+        new = V[:, :nocc]
+        if np.max(np.abs(new @ new.T - D)) < 1e-13:
+            break
+        Cocc = new
+    n = np.zeros(V.shape[1])
+    n[:nocc] = 1.0
+    return V, n
+
+
+def test_isotropic_closed_forms():
+    mean, aniso = nlop.isotropic(4.58, 4.58, 6.40)
+    assert abs(mean - (4.58 * 2 + 6.40) / 3) < 1e-15
+    assert abs(aniso - abs(6.40 - 4.58)) < 1e-14          # axial: |a_par - a_perp|
+    assert nlop.isotropic(3.0, 3.0, 3.0) == (3.0, 0.0)
