@@ -445,6 +445,42 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
               double* n_out, int prec, const nof_solve_params* p, nof_solve_result* res,
               void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Finite-field NLOPs (NLOPs: Polarizabilities and Hyperpolarizabilities).
+ *
+ * nof_dipole: electronic dipole of a NOF state along one axis,
+ *   mu = -2 sum_p n_p (C^T d C)_pp,
+ * for a field entering as H(F) = H + F d (d: AO matrix of the coupling, minus
+ * the dipole operator; at a converged state mu = -dE/dF).  C [nbf][norb],
+ * n [norb], d [nbf][nbf] FP64 device; mu out, one FP64 device scalar.
+ * ws: nof_dipole_ws() bytes.
+ *
+ * nof_nlop_romberg: alpha = dmu/dF, beta = d^2mu/dF^2, gamma = d^3mu/dF^3
+ * at F = 0 from the dipoles on the dyadic ladder h_k = step 2^(k-1):
+ *   alpha(h) = (mu(h) - mu(-h)) / 2h,  beta(h) = (mu(h) - 2mu(0) + mu(-h)) / h^2,
+ *   gamma(h) = (mu(2h) - 2mu(h) + 2mu(-h) - mu(-2h)) / 2h^3,
+ *   R(k,1) = D(h_k),  R(k,j) = R(k,j-1) + (R(k,j-1) - R(k+1,j-1)) / (4^(j-1) - 1);
+ * the value is R(k,j+1) of the vertical pair (k,k+1) of column j with the
+ * smallest |R(k+1,j) - R(k,j)| (its uncertainty); equal differences go to the
+ * candidate of smallest magnitude.
+ * mu0       device scalar mu(0).
+ * mu_p, mu_m [npoint+1] device: mu(+h_k), mu(-h_k), k = 1..npoint+1.
+ * table     out [3][npoint][npoint] (alpha, beta, gamma; NaN outside the
+ *           triangle, row k = step index, column j = extrapolation order).
+ * result    out [3][4]: value, uncertainty, k, j (0-based; npoint = 1: the
+ *           first estimate, uncertainty NaN).
+ * Errors: NOF_E_DIM (npoint outside 1..16), NOF_E_ARG (step <= 0), NOF_E_NULL.
+ * ------------------------------------------------------------------------- */
+size_t nof_dipole_ws(int nbf, int norb);
+int nof_dipole(int nbf, int norb, const double* C, const double* n, const double* d, double* mu,
+               void* ws, size_t ws_bytes, hipStream_t stream);
+int nof_nlop_romberg(int npoint, double step, const double* mu0, const double* mu_p,
+                     const double* mu_m, double* table, double* result, hipStream_t stream);
+/* Isotropic polarizability and anisotropy (Raman convention, ISOALPHA) of the
+ * diagonal components alpha[3] (xx, yy, zz; device): out[0] = mean,
+ * out[1] = sqrt(((a_xx - a_yy)^2 + (a_yy - a_zz)^2 + (a_zz - a_xx)^2) / 2). */
+int nof_nlop_isotropic(const double* alpha, double* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

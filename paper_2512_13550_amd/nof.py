@@ -92,6 +92,10 @@ class SolveResult(ctypes.Structure):
 
 
 _sig("nof_solve_ws", _sz, _i, _i, _i, _i, _i, _i, _i)
+_sig("nof_dipole_ws", _sz, _i, _i)
+_sig("nof_dipole", _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("nof_nlop_romberg", _i, _i, _d, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nof_nlop_isotropic", _i, _vp, _vp, _vp)
 _sig("nof_solve", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _i, _i, _vp, _vp, _i,
      ctypes.POINTER(SolveParams), ctypes.POINTER(SolveResult), _vp, _sz, _vp)
 MAP_TRIG, MAP_SOFTMAX = 0, 1
@@ -107,7 +111,8 @@ DECLARED = [
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
     "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
-    "nof_solve_ws", "nof_solve", "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
+    "nof_solve_ws", "nof_solve", "nof_dipole_ws", "nof_dipole", "nof_nlop_romberg",
+    "nof_nlop_isotropic", "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
 ]
 
 
@@ -566,3 +571,34 @@ def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=No
                         mapping, functional, _f64(gamma, "gamma"), _p(n), prec, ctypes.byref(prm),
                         ctypes.byref(res), _p(ws), ws.numel(), stream_handle(stream)), "nof_solve")
     return {f: getattr(res, f) for f, _ in SolveResult._fields_}
+
+
+def dipole(C, n, d, mu=None, ws=None, stream=None):
+    """mu = -2 sum_p n_p (C^T d C)_pp (nof_dipole), a device scalar."""
+    nbf, norb = C.shape
+    if mu is None:
+        mu = torch.empty((), dtype=torch.float64, device=C.device)
+    need = lib.nof_dipole_ws(nbf, norb)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, C.device)
+    check(lib.nof_dipole(nbf, norb, _f64(C, "C"), _f64(n, "n"), _f64(d, "d"), _p(mu), _p(ws), ws.numel(),
+                         stream_handle(stream)), "nof_dipole")
+    return mu
+
+
+def nlop_romberg(mu0, mu_p, mu_m, step, stream=None):
+    """alpha, beta, gamma tables and selections (nof_nlop_romberg); mu_p, mu_m
+    hold mu(+-h_k) for k = 1 .. npoint+1."""
+    npoint = mu_p.shape[0] - 1
+    table = torch.empty((3, npoint, npoint), dtype=torch.float64, device=mu_p.device)
+    result = torch.empty((3, 4), dtype=torch.float64, device=mu_p.device)
+    check(lib.nof_nlop_romberg(npoint, step, _f64(mu0, "mu0"), _f64(mu_p, "mu_p"), _f64(mu_m, "mu_m"),
+                               _p(table), _p(result), stream_handle(stream)), "nof_nlop_romberg")
+    return table, result
+
+
+def nlop_isotropic(alpha, stream=None):
+    """(mean, anisotropy) of the diagonal polarizabilities alpha[3] (nof_nlop_isotropic)."""
+    out = torch.empty(2, dtype=torch.float64, device=alpha.device)
+    check(lib.nof_nlop_isotropic(_f64(alpha, "alpha"), _p(out), stream_handle(stream)), "nof_nlop_isotropic")
+    return out

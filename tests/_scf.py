@@ -32,3 +32,23 @@ def scf_energy(B, H, nocc, iters=300):
             return E
         E_old = E
     raise AssertionError("SCF did not converge")
+
+
+def scf_orbitals(B, H, nocc, iters=300):
+    """All orbitals of the closed-shell SCF minimum (eigenvectors of the
+    converged Fock matrix, ascending) and the 0/1 occupations."""
+    e, V = np.linalg.eigh(H)
+    Cocc = V[:, :nocc]
+    for _ in range(iters):
+        D = Cocc @ Cocc.T
+        Jm = np.einsum("Pmn,P->mn", B, 2.0 * np.einsum("Pab,ab->P", B, D))
+        Km = np.einsum("Pma,ab,Pbn->mn", B, D, B)
+        F = H + Jm - Km
+        e, V = np.linalg.eigh(F)
+        new = V[:, :nocc]
+        if np.max(np.abs(new @ new.T - D)) < 1e-13:
+            break
+        Cocc = new
+    n = np.zeros(V.shape[1])
+    n[:nocc] = 1.0
+    return V, n

@@ -122,3 +122,17 @@ def test_solve_validation():
     assert L.nof_solve(*args(FAKE, prm, 8)) == nof.E_WORKSPACE
     assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_BF16X1) == 0
     assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_F64) > 2 * 4 * 4 * 8
+
+
+def test_nlop_validation():
+    nof = _lib()
+    L = nof.lib
+    assert L.nof_dipole(0, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == nof.E_DIM
+    assert L.nof_dipole(4, 4, None, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == nof.E_NULL
+    assert L.nof_dipole(4, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 8, None) == nof.E_WORKSPACE
+    assert L.nof_dipole_ws(4, 4) > 4 * 4 * 8
+    assert L.nof_nlop_romberg(0, 1e-3, FAKE, FAKE, FAKE, FAKE, FAKE, None) == nof.E_DIM
+    assert L.nof_nlop_romberg(17, 1e-3, FAKE, FAKE, FAKE, FAKE, FAKE, None) == nof.E_DIM
+    assert L.nof_nlop_romberg(3, 0.0, FAKE, FAKE, FAKE, FAKE, FAKE, None) == nof.E_ARG
+    assert L.nof_nlop_romberg(3, 1e-3, None, FAKE, FAKE, FAKE, FAKE, None) == nof.E_NULL
+    assert L.nof_nlop_isotropic(None, FAKE, None) == nof.E_NULL

@@ -19,7 +19,7 @@ import pytest
 
 from oracle import nlop
 from paper_2512_13550_amd import inputs
-from _scf import scf_energy
+from _scf import scf_energy, scf_orbitals
 
 
 def ladder(f, step, npoint):
@@ -83,24 +83,6 @@ def test_dipole_is_minus_energy_derivative_at_scf_minimum():
     C, n = scf_orbitals(B, H, nocc)
     mu = nlop.dipole(C, n, d)
     assert abs(mu - (-(Ep - Em) / (2.0 * h))) <= 1e-7 * max(1.0, abs(mu))
-
-
-def scf_orbitals(B, H, nocc, iters=300):
-    e, V = np.linalg.eigh(H)
-    Cocc = V[:, :nocc]
-    for _ in range(iters):
-        D = Cocc @ Cocc.T
-        Jm = np.einsum("Pmn,P->mn", B, 2.0 * np.einsum("Pab,ab->P", B, D))
-        Km = np.einsum("Pma,ab,Pbn->mn", B, D, B)
-        F = H + Jm - Km
-        e, V = np.linalg.eigh(F)
-        new = V[:, :nocc]
-        if np.max(np.abs(new @ new.T - D)) < 1e-13:
-            break
-        Cocc = new
-    n = np.zeros(V.shape[1])
-    n[:nocc] = 1.0
-    return V, n
 
 
 def test_isotropic_closed_forms():
