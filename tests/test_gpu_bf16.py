@@ -28,6 +28,7 @@ import torch
 
 from oracle import dfjk
 from gpu_util import case, dev, host, need_gpu, normwise
+from paper_2512_13550_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -100,6 +101,23 @@ def test_bf16_x10_split_B(src, nbf, naux, norb, seed):
     for k in ("b", "J", "K", "lam"):
         assert errs[k] <= 3e-7, (k, errs[k])
     assert errs["E"] <= 2e-8
+
+
+def test_bf16_x10_long_contraction():
+    """Nbf > 1024: the order-0 sums are added to FP64 every 1024 terms."""
+    nof = need_gpu()
+    nbf, naux, norb = 1100, 3, 150
+    print(f"case bf16 x10 long contraction nbf={nbf} naux={naux} norb={norb}", flush=True)
+    B = inputs.make_B(9, nbf, naux, 25.0)
+    C = inputs.make_C(9, nbf, norb)
+    B32 = B.astype(np.float32)
+    b_ref, D_ref = dfjk.mo_transform(B32.astype(np.float64), C)
+    for Bd in (dev(B32, torch.float32), nof.SplitB(dev(B32, torch.float32))):
+        b, D = nof.mo_transform(Bd, dev(C), prec=nof.P_BF16X10)
+        torch.cuda.synchronize()
+        eb, eD = normwise(host(b), b_ref), normwise(host(D), D_ref)
+        print("x10 long", eb, eD, flush=True)
+        assert eb <= 3e-7 and eD <= 3e-7
 
 
 def paired(rng, nrow, ncol, sign):
