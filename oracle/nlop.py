@@ -56,6 +56,8 @@ def select(R):
     differences: the candidate of smallest absolute value.
     Returns (value, uncertainty, k, j) with 0-based k, j of the pair."""
     m = R.shape[0]
+    if m == 1:
+        return R[0, 0], float("nan"), 0, 0
     best = None
     for j in range(m - 1):
         for k in range(m - j - 1):

@@ -90,3 +90,13 @@ def test_isotropic_closed_forms():
     assert abs(mean - (4.58 * 2 + 6.40) / 3) < 1e-15
     assert abs(aniso - abs(6.40 - 4.58)) < 1e-14          # axial: |a_par - a_perp|
     assert nlop.isotropic(3.0, 3.0, 3.0) == (3.0, 0.0)
+
+
+def test_single_point_ladder_is_the_centred_difference():
+    """With one step there is no vertical pair to select from: the value is
+    the centred difference itself (mu quadratic in F: alpha and beta exact)."""
+    f = lambda F: 0.25 + 3.0 * F - 0.5 * F * F      # dyadic: every step exact
+    mu0, mp, mm = ladder(f, 0.25, 1)
+    res = nlop.nlop(mu0, mp, mm, 0.25, 1)
+    assert res[0]["value"] == 3.0 and res[1]["value"] == -1.0 and res[2]["value"] == 0.0
+    assert all(math.isnan(r["uncertainty"]) and (r["k"], r["j"]) == (0, 0) for r in res)
