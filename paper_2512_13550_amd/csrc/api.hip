@@ -18,7 +18,7 @@ struct JkLayout {
   int jsplit, jk, kchunks;
   size_t off_jpart, off_kpart, total;
 };
-JkLayout jk_layout(int naux, int norb) {
+JkLayout jk_layout(int naux, int norb, int bt) {
   JkLayout L;
   const int tn = (norb + 127) / 128;
   const int tiles = tn * (tn + 1) / 2;
@@ -27,7 +27,7 @@ JkLayout jk_layout(int naux, int norb) {
   if (js > naux) js = naux;
   L.jk = (naux + js - 1) / js;
   L.jsplit = (naux + L.jk - 1) / L.jk;
-  L.kchunks = kf1_chunks(naux, norb);
+  L.kchunks = kf1_parts(naux, norb, 1, bt);
   const size_t n2 = (size_t)norb * norb * sizeof(double);
   L.off_jpart = 0;
   L.off_kpart = align256(L.off_jpart + (size_t)L.jsplit * n2);
@@ -40,9 +40,9 @@ struct FockLayout {
   int kchunks, f2fold, f2groups;
   size_t off_W, off_f1part, off_kpart, off_f2part, off_F1, off_F2, off_St, total;
 };
-FockLayout fock_layout(int naux, int norb) {
+FockLayout fock_layout(int naux, int norb, int bt) {
   FockLayout L;
-  L.kchunks = kf1_chunks(naux, norb);
+  L.kchunks = kf1_parts(naux, norb, 1, bt);
   const int tn = (norb + 127) / 128;
   const int tiles = tn * tn;
   int groups = (512 + tiles - 1) / tiles;
@@ -279,7 +279,7 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
 size_t nof_jk_diag_ws(int naux, int norb, int bt) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (bt != NOF_F64 && bt != NOF_F32) return 0;
-  return jk_layout(naux, norb).total;
+  return jk_layout(naux, norb, bt).total;
 }
 
 int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, double* J, double* K,
@@ -288,7 +288,7 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, doub
     if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
     if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
     if ((K && !b) || (J && !D)) return NOF_E_NULL;
-    const JkLayout L = jk_layout(naux, norb);
+    const JkLayout L = jk_layout(naux, norb, bt);
     if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
     char* w = (char*)ws;
     const long long n2 = (long long)norb * norb;
@@ -341,7 +341,7 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, i
 size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
-  const FockLayout L = fock_layout(naux, norb);
+  const FockLayout L = fock_layout(naux, norb, bt);
   return align256((size_t)L.f2groups * norb * norb * sizeof(double)) +
          align256((size_t)norb * norb * sizeof(float));
 }
@@ -355,7 +355,7 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     if (!ws || ws_bytes < nof_exchange_fock_ws(naux, norb, bt, prec)) return NOF_E_WORKSPACE;
-    const FockLayout L = fock_layout(naux, norb);
+    const FockLayout L = fock_layout(naux, norb, bt);
     char* w = (char*)ws;
     double* part = (double*)w;
     float* St = (float*)(w + align256((size_t)L.f2groups * norb * norb * sizeof(double)));
@@ -366,7 +366,7 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
 size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
-  return fock_layout(naux, norb).total;
+  return fock_layout(naux, norb, bt).total;
 }
 
 int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, const double* n,
@@ -378,7 +378,7 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
-    const FockLayout L = fock_layout(naux, norb);
+    const FockLayout L = fock_layout(naux, norb, bt);
     if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
     char* w = (char*)ws;
     const long long n2 = (long long)norb * norb;

@@ -129,14 +129,17 @@ inline int gemm_any(const GemmDesc& d, int x_t, int y_t, int out_t, int prec, hi
                             : gemm_tn(d, x_t, y_t, out_t, prec, st);
 }
 
-// Pass over the upper triangle of b (HBM bound):
-//   Kpart[c][r][s] = sum_{P in chunk c} b_rs^2              (r <= s)
-//   F1part[c][r][s] += b_rs W[P][s],  F1part[c][s][r] += b_rs W[P][r]
-// Either output may be NULL.
+// Pass over the upper triangle of b (HBM bound), written as nparts partial
+// planes whose in-order sum is
+//   K[r][s] = sum_P b_rs^2                                     (r <= s)
+//   F1[r][s] = sum_P b_rs W[P][s],  F1[s][r] = sum_P b_rs W[P][r]
+// Either output may be NULL.  nparts must equal kf1_parts(naux, norb, ninst,
+// bt); every element of every plane that the sum reads is written (no
+// clearing).
 int kf1_pass(int naux, int norb, const void* b, int bt, const double* W,
-             double* Kpart, double* F1part, int nchunk, hipStream_t st, int ninst = 1,
+             double* Kpart, double* F1part, int nparts, hipStream_t st, int ninst = 1,
              long long bstride = 0, long long wstride = 0, long long pstride = 0);
-int kf1_chunks(int naux, int norb);
+int kf1_parts(int naux, int norb, int ninst, int bt);
 
 // out[i] = sum_c part[c*stride + i] in fixed order; if sym_upper, element
 // (r,s) is read from (min,max) and written to both (r,s) and (s,r).

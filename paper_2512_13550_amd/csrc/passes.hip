@@ -9,12 +9,22 @@ namespace {
 //
 // Tile = 16 rows (r) x 128 columns (s) of the norb x norb plane; one
 // workgroup walks one tile through a contiguous chunk of auxiliary slabs P.
-// Thread (ty, tx) owns columns s = tile_col*128 + 2*tx + {0,1} and rows
-// r = tile_row*16 + 4*ty + {0..3}; each row is fetched as one 2-element vector
-// (16 B in FP64), so a wave reads 1 KiB contiguous per row and slab.  Four
-// slabs are in flight per iteration.  W (naux x norb, FP64) is L2 resident.
+// Wave w owns rows r = tile_row*16 + 4w + {0..3} (wave-uniform) and lane l
+// the columns s = tile_col*128 + 2l + {0,1}; each row is fetched as one
+// 2-element vector per lane, so a wave reads 1 KiB contiguous per row and
+// slab.  KF_U slabs are in flight per iteration.
+//
+// The loop is branch-free: a lane whose pair lies outside r <= s (or outside
+// the plane) loads a clamped address inside the same row near the diagonal,
+// whose cache line the active lanes fetch anyway, and the value is zeroed by
+// a select.  W[P][r] is wave-uniform (scalar loads); W[P][s] is one vector
+// load per lane.  Tiles strictly inside the upper triangle skip the selects.
 // ---------------------------------------------------------------------------
-constexpr int KF_R = 16, KF_C = 128, KF_THR = 256, KF_U = 4;
+constexpr int KF_R = 16, KF_C = 128, KF_THR = 256, KF_U = 4, KF_RW = 4;
+constexpr int KF_GRID64 = 256;   // workgroups of a pass over FP64 b: one per CU
+constexpr int KF_MAXCHUNK = 64;  // partial planes at most
+constexpr int KF_MINSLABS = 16;  // slabs per chunk at least (small naux)
+constexpr int KF_PIPE = 1;       // slab loop: 0 groups of KF_U, 1 double-buffered
 
 __device__ __forceinline__ void kf_tile(int t, int ntc, int ntr, int& tr, int& tc) {
   // tiles are listed column-block by column-block; column block tc holds the
@@ -32,110 +42,212 @@ template <typename TB> struct Vec2;
 template <> struct Vec2<double> { typedef double2 t; };
 template <> struct Vec2<float> { typedef float2 t; };
 
-// VEC: norb even, so every row segment starting at an even column is aligned.
-// Instance i (blockIdx.y) reads b + i*bstride, W + i*wstride and writes its
-// partials at + i*pstride.
-template <typename TB, bool VEC>
-__global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __restrict__ b,
-                                                const double* __restrict__ W,
-                                                double* __restrict__ Kpart,
-                                                double* __restrict__ F1part, int pchunk,
-                                                int ntiles, int ntr, int ntc, long long bstride,
-                                                long long wstride, long long pstride) {
+// Per-lane state of one tile: the clamped (wave-uniform) row offsets and
+// per-lane columns of the loads, the select masks and the clamped W indices.
+struct KfLane {
+  long long roff[KF_RW];  // rr * norb, rr = clamped row (wave-uniform)
+  int col[KF_RW][2];      // clamped columns of the pair
+  bool act[KF_RW][2];
+  int wl;                 // clamped row r0 + (lane mod KF_RW), read into wl
+  int ws;                 // clamped column index of the pair's first column
+};
+
+// One slab's operands of a lane: the pair of every row, and for the
+// Coulomb-type term W[P][s], W[P][s+1] and wl = W[P][row (lane mod KF_RW)] of
+// the wave's rows (lanes 0 .. KF_RW-1 hold the KF_RW row values, which every
+// lane reads back with readlane: one vector load instead of one per row).
+template <typename TB> struct KfSlab {
+  TB v[KF_RW][2];
+  double ws0, ws1, wl;
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <typename TB, bool VEC, bool FULL, bool wantF, int PIPE>
+__device__ __forceinline__ void kf_run(const TB* __restrict__ b, const double* __restrict__ W,
+                                       int norb, long long plane, int p_lo, int p_hi,
+                                       const KfLane& L, double (&k)[KF_RW][2],
+                                       double (&frs)[KF_RW][2], double (&fsr)[KF_RW][2]) {
   typedef typename Vec2<TB>::t V2;
-  const int tile = blockIdx.x % ntiles;
-  const int chunk = blockIdx.x / ntiles;
-  b += (long long)blockIdx.y * bstride;
-  if (W) W += (long long)blockIdx.y * wstride;
-  if (Kpart) Kpart += (long long)blockIdx.y * pstride;
-  if (F1part) F1part += (long long)blockIdx.y * pstride;
-  int tr, tc;
-  kf_tile(tile, ntc, ntr, tr, tc);
-  if (tr < 0) return;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int s0 = tc * KF_C + 2 * tx;
-  const int r0 = tr * KF_R + ty * 4;
-  const int p_lo = chunk * pchunk;
-  const int p_hi = min(naux, p_lo + pchunk);
-  const long long plane = (long long)norb * norb;
-  const bool wantF = F1part != nullptr;
-
-  bool act[4][2];
+  // every load of a slab (b and W) is issued before any of its values is used
+  auto fetch = [&](int P, KfSlab<TB>& x) {
+    const TB* pl = b + (long long)P * plane;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-      act[i][c] = (s0 + c < norb) && (r0 + i < norb) && (r0 + i <= s0 + c);
-  bool rowany[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) rowany[i] = act[i][0] || act[i][1];
-
-  double k[4][2] = {}, frs[4][2] = {}, fsr[4][2] = {};
-
-  auto fetch = [&](int P, int i, TB& v0, TB& v1) {
-    const TB* row = b + (long long)P * plane + (long long)(r0 + i) * norb + s0;
-    if (VEC) {
-      V2 v = rowany[i] ? *(const V2*)row : V2{0, 0};
-      v0 = act[i][0] ? v.x : (TB)0;
-      v1 = act[i][1] ? v.y : (TB)0;
-    } else {
-      v0 = act[i][0] ? row[0] : (TB)0;
-      v1 = act[i][1] ? row[1] : (TB)0;
+    for (int i = 0; i < KF_RW; ++i) {
+      const TB* row = pl + L.roff[i];
+      if (VEC) {
+        const V2 t = *(const V2*)(row + L.col[i][0]);
+        x.v[i][0] = t.x;
+        x.v[i][1] = t.y;
+      } else {
+        x.v[i][0] = row[L.col[i][0]];
+        x.v[i][1] = row[L.col[i][1]];
+      }
     }
-  };
-  auto accum = [&](int P, const TB (&v)[4][2]) {
-    double ws0 = 0.0, ws1 = 0.0, wr[4] = {0, 0, 0, 0};
     if (wantF) {
       const double* wp = W + (long long)P * norb;
-      ws0 = s0 < norb ? wp[s0] : 0.0;
-      ws1 = s0 + 1 < norb ? wp[s0 + 1] : 0.0;
+      if (VEC) {
+        const double2 t = *(const double2*)(wp + L.ws);
+        x.ws0 = t.x;
+        x.ws1 = t.y;
+      } else {
+        x.ws0 = wp[L.ws];
+        x.ws1 = wp[L.ws + 1 < norb ? L.ws + 1 : L.ws];
+      }
+      x.wl = wp[L.wl];
+    }
+  };
+  auto accum = [&](KfSlab<TB>& x) {
+    double wr[KF_RW];
+    if (wantF) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) wr[i] = (r0 + i < norb) ? wp[r0 + i] : 0.0;
+      for (int i = 0; i < KF_RW; ++i) wr[i] = readlane_f64(x.wl, i);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double a0 = (double)v[i][0], a1 = (double)v[i][1];
+    for (int i = 0; i < KF_RW; ++i) {
+      double a0 = (double)x.v[i][0], a1 = (double)x.v[i][1];
+      if (!FULL) {
+        a0 = L.act[i][0] ? a0 : 0.0;
+        a1 = L.act[i][1] ? a1 : 0.0;
+      }
       k[i][0] = fma(a0, a0, k[i][0]);
       k[i][1] = fma(a1, a1, k[i][1]);
       if (wantF) {
-        frs[i][0] = fma(a0, ws0, frs[i][0]);
-        frs[i][1] = fma(a1, ws1, frs[i][1]);
+        frs[i][0] = fma(a0, x.ws0, frs[i][0]);
+        frs[i][1] = fma(a1, x.ws1, frs[i][1]);
         fsr[i][0] = fma(a0, wr[i], fsr[i][0]);
         fsr[i][1] = fma(a1, wr[i], fsr[i][1]);
       }
     }
   };
-
-  int P = p_lo;
-  for (; P + KF_U <= p_hi; P += KF_U) {
-    TB v[KF_U][4][2];
+  if (PIPE == 0) {
+    // groups of KF_U slabs: all loads of a group issued, then all used
+    int P = p_lo;
+    for (; P + KF_U <= p_hi; P += KF_U) {
+      KfSlab<TB> x[KF_U];
 #pragma unroll
-    for (int u = 0; u < KF_U; ++u)
+      for (int u = 0; u < KF_U; ++u) fetch(P + u, x[u]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fetch(P + u, i, v[u][i][0], v[u][i][1]);
-#pragma unroll
-    for (int u = 0; u < KF_U; ++u) accum(P + u, v[u]);
+      for (int u = 0; u < KF_U; ++u) accum(x[u]);
+    }
+    for (; P < p_hi; ++P) {
+      KfSlab<TB> x;
+      fetch(P, x);
+      accum(x);
+    }
+  } else {
+    // double-buffered: slab P+1 in flight while slab P is used
+    if (p_lo >= p_hi) return;
+    KfSlab<TB> x, y;
+    fetch(p_lo, x);
+    int P = p_lo;
+    for (; P + 2 <= p_hi; P += 2) {
+      fetch(P + 1, y);
+      __builtin_amdgcn_sched_barrier(0);
+      accum(x);
+      if (P + 2 < p_hi) fetch(P + 2, x);
+      __builtin_amdgcn_sched_barrier(0);
+      accum(y);
+    }
+    if (P < p_hi) accum(x);
   }
-  for (; P < p_hi; ++P) {
-    TB v[4][2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) fetch(P, i, v[i][0], v[i][1]);
-    accum(P, v);
-  }
+}
 
-  const long long cb = (long long)chunk * plane;
+// Work units: (instance, chunk of slabs, tile), tile fastest.  The grid
+// sweeps the units in order, unit u on workgroup u mod G, so the workgroups
+// of one sweep read all tiles of the same few slabs at the same time (whole
+// planes read densely) and each workgroup gets the same number of units.
+// Unit (i, c, t) writes plane c of instance i's partials; a chunk past the
+// last slab writes zeros, so summing the nchunk planes in order gives the
+// sums over all slabs (fixed order, no atomics).
+//
+// VEC: norb even and b 16-byte aligned, so every pair starting at an even
+// column is one aligned vector.  Instance i reads b + i*bstride, W + i*wstride
+// and writes its partials at + i*pstride.
+template <typename TB, bool VEC, int PIPE>
+__global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __restrict__ b,
+                                                const double* __restrict__ W,
+                                                double* __restrict__ Kpart,
+                                                double* __restrict__ F1part, int pchunk,
+                                                int nchunk, int ntiles, int ntr, int ntc,
+                                                int ninst, long long bstride, long long wstride,
+                                                long long pstride) {
+  const long long units = (long long)ninst * nchunk * ntiles;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const long long plane = (long long)norb * norb;
+  const bool wantF = F1part != nullptr;
+  for (long long u = blockIdx.x; u < units; u += gridDim.x) {
+    const int tile = (int)(u % ntiles);
+    const long long ic = u / ntiles;
+    const int chunk = (int)(ic % nchunk);
+    const int inst = (int)(ic / nchunk);
+    const int p_lo = min(naux, chunk * pchunk);
+    const int p_hi = min(naux, p_lo + pchunk);
+    const TB* bi = b + (long long)inst * bstride;
+    const double* Wi = W ? W + (long long)inst * wstride : nullptr;
+    int tr, tc;
+    kf_tile(tile, ntc, ntr, tr, tc);
+    const int s0 = tc * KF_C + 2 * lane;
+    const int r0 = tr * KF_R + wv * KF_RW;
+
+    KfLane L;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < KF_RW; ++i) {
+      const int r = r0 + i;
+      const int rr = min(r, norb - 1);
+      L.roff[i] = (long long)rr * norb;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      if (!act[i][c]) continue;
-      const int r = r0 + i, s = s0 + c;
-      if (Kpart) Kpart[cb + (long long)r * norb + s] = k[i][c];
-      if (wantF) {
-        F1part[cb + (long long)r * norb + s] = frs[i][c];
-        if (r != s) F1part[cb + (long long)s * norb + r] = fsr[i][c];
+      for (int c = 0; c < 2; ++c) L.act[i][c] = (s0 + c < norb) && (r < norb) && (r <= s0 + c);
+      if (VEC) {
+        // the pair (cc, cc+1), cc even, cc <= norb-2, never left of the
+        // diagonal pair of row rr
+        L.col[i][0] = min(max(s0, rr & ~1), norb - 2);
+        L.col[i][1] = L.col[i][0] + 1;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) L.col[i][c] = min(max(s0 + c, rr), norb - 1);
       }
     }
+    L.ws = VEC ? min(s0, norb - 2) : min(s0, norb - 1);
+    L.wl = min(r0 + (lane & (KF_RW - 1)), norb - 1);
+    // tile strictly inside r <= s and inside the plane: no lane is masked
+    const bool full = (tr * KF_R + KF_R - 1 <= tc * KF_C) && (tc * KF_C + KF_C <= norb) &&
+                      (tr * KF_R + KF_R <= norb);
+
+    double k[KF_RW][2] = {}, frs[KF_RW][2] = {}, fsr[KF_RW][2] = {};
+    if (wantF) {
+      if (full)
+        kf_run<TB, VEC, true, true, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
+      else
+        kf_run<TB, VEC, false, true, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
+    } else {
+      if (full)
+        kf_run<TB, VEC, true, false, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
+      else
+        kf_run<TB, VEC, false, false, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
+    }
+
+    const long long cb = (long long)inst * pstride + (long long)chunk * plane;
+#pragma unroll
+    for (int i = 0; i < KF_RW; ++i)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (!L.act[i][c]) continue;
+        const int r = r0 + i, s = s0 + c;
+        if (Kpart) Kpart[cb + (long long)r * norb + s] = k[i][c];
+        if (wantF) {
+          F1part[cb + (long long)r * norb + s] = frs[i][c];
+          if (r != s) F1part[cb + (long long)s * norb + r] = fsr[i][c];
+        }
+      }
+  }
 }
 
 __global__ void k_reduce(const double* __restrict__ part, int nparts, long long stride, int norb,
@@ -244,52 +356,70 @@ void kf_geometry(int norb, int& ntr, int& ntc, int& ntiles) {
   }
 }
 
-}  // namespace
 
-int kf1_chunks(int naux, int norb) {
+// Plan of one pass: nchunk chunks of pchunk slabs, G workgroups.  With few
+// units per CU the slowest CU sets the time, so the chunk count is the
+// smallest whose units fill the grid (KF_GRID64 workgroups for FP64 b, twice
+// that for FP32 b, whose waves hold half the bytes in flight) to within 7 %;
+// with at least 8 units per workgroup the grid is one workgroup per unit and
+// the hardware balances it.
+struct KfPlan {
+  int nchunk, pchunk, G;
+};
+
+KfPlan kf_plan(int naux, int norb, int ninst, int bt) {
   int ntr, ntc, ntiles;
   kf_geometry(norb, ntr, ntc, ntiles);
-  int nc = (2048 + ntiles - 1) / ntiles;
-  if (nc > naux) nc = naux;
-  if (nc < 1) nc = 1;
-  return nc;
+  const long long grid = bt == NOF_F64 ? KF_GRID64 : 2 * KF_GRID64;
+  const long long per = (long long)ninst * ntiles;
+  int ncmax = naux / KF_MINSLABS < KF_MAXCHUNK ? naux / KF_MINSLABS : KF_MAXCHUNK;
+  if (ncmax < 1) ncmax = 1;
+  int nc = ncmax;
+  for (int c = 1; c <= ncmax; ++c) {
+    const long long units = per * c;
+    if (units >= 8 * grid) { nc = c; break; }
+    const long long rounds = (units + grid - 1) / grid;
+    if (units * 10 >= grid * 9 && rounds * grid * 100 <= units * 107) { nc = c; break; }
+  }
+  KfPlan pl;
+  pl.pchunk = (naux + nc - 1) / nc;
+  pl.nchunk = (naux + pl.pchunk - 1) / pl.pchunk;
+  const long long units = per * pl.nchunk;
+  long long G = units >= 8 * grid || units < grid ? units : grid;
+  if (G > (1 << 24)) G = 1 << 24;  // the workgroups sweep the units in any case
+  pl.G = (int)G;
+  return pl;
 }
 
+}  // namespace
+
+int kf1_parts(int naux, int norb, int ninst, int bt) { return kf_plan(naux, norb, ninst, bt).nchunk; }
+
 int kf1_pass(int naux, int norb, const void* b, int bt, const double* W, double* Kpart,
-             double* F1part, int nchunk, hipStream_t st, int ninst, long long bstride,
+             double* F1part, int nparts, hipStream_t st, int ninst, long long bstride,
              long long wstride, long long pstride) {
+  if (ninst < 1 || ninst > 65535) return NOF_E_DIM;
   int ntr, ntc, ntiles;
   kf_geometry(norb, ntr, ntc, ntiles);
-  const int pchunk = (naux + nchunk - 1) / nchunk;
-  const int nc = (naux + pchunk - 1) / pchunk;
-  if (nc > nchunk) return NOF_E_INTERNAL;
-  const long long G = (long long)ntiles * nchunk;
-  if (G > 0x7fffffffLL || ninst < 1 || ninst > 65535) return NOF_E_DIM;
-  // chunks beyond nc (when pchunk rounding leaves them empty) write zeros
-  const dim3 grid((unsigned)G, (unsigned)ninst);
+  const KfPlan pl = kf_plan(naux, norb, ninst, bt);
+  if (nparts != pl.nchunk) return NOF_E_INTERNAL;
+  if (ninst > 1 && pstride < (long long)nparts * norb * norb) return NOF_E_INTERNAL;
+  const dim3 grid((unsigned)pl.G);
   const size_t esz = bt == NOF_F64 ? 8 : 4;
-  const bool vec = (norb % 2) == 0 && ((uintptr_t)b % 16) == 0 && ((bstride * esz) % 16) == 0;
+  const bool vec = (norb % 2) == 0 && ((uintptr_t)b % 16) == 0 && ((bstride * esz) % 16) == 0 &&
+                   (!W || (((uintptr_t)W % 16) == 0 && (wstride % 2) == 0));
+#define NOF_KF1(TB, V)                                                                          \
+  hipLaunchKernelGGL((k_kf1<TB, V, KF_PIPE>), grid, dim3(KF_THR), 0, st, naux, norb,            \
+                     (const TB*)b, W, Kpart, F1part, pl.pchunk, pl.nchunk, ntiles, ntr, ntc,     \
+                     ninst, bstride, wstride, pstride)
   if (bt == NOF_F64) {
-    if (vec)
-      hipLaunchKernelGGL((k_kf1<double, true>), grid, dim3(KF_THR), 0, st, naux, norb,
-                         (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
-                         wstride, pstride);
-    else
-      hipLaunchKernelGGL((k_kf1<double, false>), grid, dim3(KF_THR), 0, st, naux, norb,
-                         (const double*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
-                         wstride, pstride);
+    if (vec) NOF_KF1(double, true); else NOF_KF1(double, false);
   } else if (bt == NOF_F32) {
-    if (vec)
-      hipLaunchKernelGGL((k_kf1<float, true>), grid, dim3(KF_THR), 0, st, naux, norb,
-                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
-                         wstride, pstride);
-    else
-      hipLaunchKernelGGL((k_kf1<float, false>), grid, dim3(KF_THR), 0, st, naux, norb,
-                         (const float*)b, W, Kpart, F1part, pchunk, ntiles, ntr, ntc, bstride,
-                         wstride, pstride);
+    if (vec) NOF_KF1(float, true); else NOF_KF1(float, false);
   } else {
     return NOF_E_DTYPE;
   }
+#undef NOF_KF1
   return launch_status();
 }
 
