@@ -351,6 +351,7 @@ int nof_plan_capture(nof_plan plan, const void* B, const double* C, const double
 int nof_plan_launch(nof_plan plan, hipStream_t stream);
 int nof_plan_destroy(nof_plan plan);
 
+
 /* ---------------------------------------------------------------------------
  * Learned warm start of the occupation update (not part of the paper's method:
  * its prediction is always refined by nof_occ_optimize).
@@ -444,6 +445,42 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
               int ns, int ng, const int* members, int map, int func, double* gamma,
               double* n_out, int prec, const nof_solve_params* p, nof_solve_result* res,
               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched solve (NLOPs: Polarizabilities and Hyperpolarizabilities: the
+ * finite-field instances share B and differ in H): the alternating NO + ON
+ * optimisation of nof_solve, run for every instance of a plan at once.
+ *
+ * Per outer iteration: one batched iteration gives h_i, J_i, K_i of the
+ * current orbitals; each instance still running takes its ON step
+ * (nof_occ_optimize, or the occupations of gamma_i when on_maxit = 0) and its
+ * coefficients; then NO steps until every instance's sweep has ended.  A NO
+ * step of all instances is the batched iteration, max|lambda_i - lambda_i^T|
+ * per instance, ADAM on the instances whose sweep runs and whose asymmetry is
+ * above tol_lambda, U_i = exp(y_i) and C_i <- C_i U_i; the other instances get
+ * y_i = 0 and keep C_i bit for bit.  With a non-null stream the NO step is
+ * captured once into a HIP graph and each step is one hipGraphLaunch; the
+ * host reads E_i and the asymmetries after every step.  Every instance
+ * follows the same sequence of states as nof_solve would give it alone
+ * (sweep and convergence rules, ADAM moments and step counter per instance).
+ *
+ * plan     from nof_plan_create (prec NOF_P_F64 or NOF_P_F32; B as for
+ *          nof_plan_iteration).  Uses the plan's tuned configuration; the
+ *          plan's own captured graph, if any, is left alone.
+ * H        [ninst][nbf][nbf] FP64; C [ninst][nbf][norb] FP64 in/out.
+ * members, map, func, ns, ng   as nof_occ_optimize, shared by all instances.
+ * gamma    [ninst][ns][ng] FP64 in/out.  n_out [ninst][norb] or NULL.
+ * p        host parameters as nof_solve.  res [ninst] host results.
+ * ws       nof_plan_solve_ws(plan, ns, ng) bytes (includes the plan's).
+ * Returns NOF_E_NOT_CONVERGED when an instance's E or asymmetry stopped being
+ * finite (that instance stops, res[i].status says so, the others run on),
+ * the status of a failing step otherwise, else NOF_OK.  Synchronises stream.
+ * ------------------------------------------------------------------------- */
+size_t nof_plan_solve_ws(nof_plan plan, int ns, int ng);
+int nof_plan_solve(nof_plan plan, const void* B, const double* H, double* C, int ns, int ng,
+                   const int* members, int map, int func, double* gamma, double* n_out,
+                   const nof_solve_params* p, nof_solve_result* res, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Finite-field NLOPs (NLOPs: Polarizabilities and Hyperpolarizabilities).

@@ -15,6 +15,8 @@
 // hipGraphLaunch.  The workgroup tile of each matrix product (128 or 64) and
 // the P-split of the exchange term are chosen by timing the candidates
 // (nof_plan_autotune).
+#include <algorithm>
+#include <cmath>
 #include <new>
 #include <vector>
 
@@ -238,6 +240,302 @@ float time_stage(F&& f, hipStream_t st, int reps) {
   return ms;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched solve: the alternating NO + ON optimisation (the same iteration as
+// the single-instance solver) for every instance of a plan at once.  A NO step
+// of all instances is one launch sequence (one graph replay when the stream
+// can be captured): the batched iteration, max|lambda_i - lambda_i^T|, ADAM on
+// the instances still stepping, U_i = exp(y_i), C_i <- C_i U_i.  An instance
+// that does not step gets y_i = 0, so U_i = I exactly and C_i is unchanged.
+// ---------------------------------------------------------------------------
+
+// max_pq |L_pq - L_qp| of instance blockIdx.x's n x n matrix.
+__global__ void k_asym_inst(int n, const double* __restrict__ L, double* __restrict__ out) {
+  __shared__ double red[256];
+  const long long nn = (long long)n * n;
+  L += (long long)blockIdx.x * nn;
+  double m = 0.0;
+  for (long long i = threadIdx.x; i < nn; i += blockDim.x) {
+    const long long p = i / n, q = i - p * n;
+    if (q > p) m = fmax(m, fabs(L[p * n + q] - L[q * n + p]));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// ADAM step of instance blockIdx.y when ctl[3i] != 0 (its sweep runs) and its
+// lambda is not yet symmetric (asym[i] > tol); ctl[3i+1], ctl[3i+2] are the
+// bias corrections 1 - b1^t, 1 - b2^t of the step it would take.  Other
+// instances: y_i = 0, moments unchanged.
+__global__ void k_adam_inst(long long n2, const double* __restrict__ g, double* __restrict__ m,
+                            double* __restrict__ v, const double* __restrict__ ctl,
+                            const double* __restrict__ asym, double tol, double b1, double b2,
+                            double lr, double eps, double* __restrict__ y) {
+  const int i = blockIdx.y;
+  const long long off = (long long)i * n2;
+  const bool step = ctl[3 * i] != 0.0 && asym[i] > tol;
+  const double c1 = ctl[3 * i + 1], c2 = ctl[3 * i + 2];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n2;
+       e += (long long)gridDim.x * blockDim.x) {
+    if (!step) {
+      y[off + e] = 0.0;
+      continue;
+    }
+    const double gi = g[off + e];
+    const double mi = b1 * m[off + e] + (1.0 - b1) * gi;
+    const double vi = b2 * v[off + e] + (1.0 - b2) * gi * gi;
+    m[off + e] = mi;
+    v[off + e] = vi;
+    const double mh = mi / c1, vh = vi / c2;
+    y[off + e] = -lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+__global__ void k_copy_f64(long long n, const double* __restrict__ src, double* __restrict__ dst) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+__global__ void k_zero_f64(long long n, double* __restrict__ dst) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = 0.0;
+}
+
+unsigned grid_of(long long n) {
+  long long g = (n + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : g > 4096 ? 4096 : g);
+}
+
+// Workspace of the batched solve, after the plan's own.
+struct SolveLay {
+  size_t n, cJ, cK, lam, grad, m, v, y, U, Cn, E, Eon, asym, ctl, info, scr, scr_bytes, total;
+};
+
+SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
+  SolveLay L{};
+  const size_t ni = p->ninst, no = p->norb, nb = p->nbf;
+  const size_t n2 = no * no * 8;
+  size_t o = p->total;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  L.n = take(ni * no * 8);
+  L.cJ = take(ni * n2);
+  L.cK = take(ni * n2);
+  L.lam = take(ni * n2);
+  L.grad = take(ni * n2);
+  L.m = take(ni * n2);
+  L.v = take(ni * n2);
+  L.y = take(ni * n2);
+  L.U = take(ni * n2);
+  L.Cn = take(ni * nb * no * 8);
+  L.E = take(ni * 8);
+  L.Eon = take(ni * 8);
+  L.asym = take(ni * 8);
+  L.ctl = take(ni * 3 * 8);
+  L.info = take(ni * 3 * sizeof(int));
+  size_t s = nof_expm_antisym_ws(p->norb);
+  s = std::max(s, nof_rotate_orbitals_ws(p->nbf, p->norb));
+  s = std::max(s, nof_occ_ws(p->norb, ns, ng));
+  L.scr_bytes = s;
+  L.scr = take(s);
+  L.total = o;
+  return L;
+}
+
+struct SolveBufs {
+  double *n, *cJ, *cK, *lam, *grad, *m, *v, *y, *U, *Cn, *E, *Eon, *asym, *ctl;
+  int* info;
+  void* scr;
+  size_t scr_bytes;
+};
+
+// One NO step of every instance (see above); ctl must be on the device.
+int no_step(nof_plan_s* p, const Args& a, const SolveBufs& w, double* C, const nof_solve_params* prm,
+            hipStream_t st) {
+  const long long n2 = (long long)p->norb * p->norb;
+  const long long cs = (long long)p->nbf * p->norb;
+  int rc = run_iteration(p, a, st);
+  if (rc != NOF_OK) return rc;
+  hipLaunchKernelGGL(k_asym_inst, dim3(p->ninst), dim3(256), 0, st, p->norb, w.lam, w.asym);
+  if ((rc = launch_status()) != NOF_OK) return rc;
+  hipLaunchKernelGGL(k_adam_inst, dim3(grid_of(n2), p->ninst), dim3(256), 0, st, n2, w.grad, w.m,
+                     w.v, w.ctl, w.asym, prm->tol_lambda, prm->beta1, prm->beta2, prm->lr, prm->eps,
+                     w.y);
+  if ((rc = launch_status()) != NOF_OK) return rc;
+  for (int i = 0; i < p->ninst; ++i) {
+    rc = nof_expm_antisym(p->norb, w.y + i * n2, w.U + i * n2, w.scr, w.scr_bytes, st);
+    if (rc != NOF_OK) return rc;
+    rc = nof_rotate_orbitals(p->nbf, p->norb, C + i * cs, w.U + i * n2, w.Cn + i * cs, w.scr,
+                             w.scr_bytes, st);
+    if (rc != NOF_OK) return rc;
+  }
+  hipLaunchKernelGGL(k_copy_f64, dim3(grid_of(cs * p->ninst)), dim3(256), 0, st, cs * p->ninst, w.Cn,
+                     C);
+  return launch_status();
+}
+
+int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns, int ng,
+               const int* members, int map, int func, double* gamma, double* n_out,
+               const nof_solve_params* prm, nof_solve_result* res, char* ws, hipStream_t st) {
+  const int ni = p->ninst;
+  const long long n2 = (long long)p->norb * p->norb;
+  const SolveLay L = solve_lay(p, ns, ng);
+  SolveBufs w;
+  w.n = (double*)(ws + L.n); w.cJ = (double*)(ws + L.cJ); w.cK = (double*)(ws + L.cK);
+  w.lam = (double*)(ws + L.lam); w.grad = (double*)(ws + L.grad);
+  w.m = (double*)(ws + L.m); w.v = (double*)(ws + L.v); w.y = (double*)(ws + L.y);
+  w.U = (double*)(ws + L.U); w.Cn = (double*)(ws + L.Cn);
+  w.E = (double*)(ws + L.E); w.Eon = (double*)(ws + L.Eon); w.asym = (double*)(ws + L.asym);
+  w.ctl = (double*)(ws + L.ctl); w.info = (int*)(ws + L.info);
+  w.scr = ws + L.scr; w.scr_bytes = L.scr_bytes;
+  const Args a{B, C, H, w.n, w.cJ, w.cK, w.E, w.lam, w.grad, ws};
+  const double* h = (const double*)(ws + p->off[O_H]);
+  const double* J = (const double*)(ws + p->off[O_J]);
+  const double* K = (const double*)(ws + p->off[O_K]);
+  const int nv = ns * ng;
+
+  for (int i = 0; i < ni; ++i) {
+    res[i] = nof_solve_result{};
+    res[i].status = NOF_OK;
+  }
+  // ADAM moments start at zero; n, cJ, cK are set before their first use but
+  // are cleared so that the first integrals pass reads defined values
+  int rc = NOF_OK;
+  for (double* z : {w.m, w.v, w.cJ, w.cK}) {
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(n2 * ni)), dim3(256), 0, st, n2 * ni, z);
+    if ((rc = launch_status()) != NOF_OK) return rc;
+  }
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid_of((long long)ni * p->norb)), dim3(256), 0, st,
+                     (long long)ni * p->norb, w.n);
+  if ((rc = launch_status()) != NOF_OK) return rc;
+
+  // the NO step as a graph when the stream can be captured
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct GraphGuard {
+    hipGraph_t& g;
+    hipGraphExec_t& e;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } guard{graph, exec};
+  if (st != nullptr) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return NOF_E_HIP;
+    rc = no_step(p, a, w, C, prm, st);
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rc != NOF_OK) return rc;
+    if (ec != hipSuccess || !graph) return NOF_E_HIP;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) return NOF_E_HIP;
+  }
+
+  std::vector<int> live(ni), sweep(ni), tstep(ni, 0), have_prev(ni, 0), hinfo(3 * ni);
+  std::vector<double> E_prev(ni, 0.0), hE(ni), hA(ni), ctl(3 * ni);
+  int failed_status = NOF_OK;
+  for (int i = 0; i < ni; ++i) live[i] = 1;
+  auto sync = [&]() { return hipStreamSynchronize(st) == hipSuccess ? NOF_OK : NOF_E_HIP; };
+
+  for (int outer = 0; outer < prm->max_outer; ++outer) {
+    bool any = false;
+    for (int i = 0; i < ni; ++i) any = any || live[i];
+    if (!any) break;
+    // ON step at fixed orbitals: h_i, J_i, K_i of the current C_i
+    if ((rc = run_iteration(p, a, st)) != NOF_OK) return rc;
+    for (int i = 0; i < ni; ++i) {
+      if (!live[i]) continue;
+      if (prm->on_maxit > 0)
+        rc = nof_occ_optimize(p->norb, ns, ng, members, map, func, h + i * n2, p->norb + 1, J + i * n2,
+                              K + i * n2, gamma + (long long)i * nv, w.n + (long long)i * p->norb,
+                              w.Eon + i, w.info + 3 * i, prm->on_maxit, prm->on_tol, w.scr,
+                              w.scr_bytes, st);
+      else
+        rc = nof_occ_energy_grad(p->norb, ns, ng, members, map, func, gamma + (long long)i * nv,
+                                 h + i * n2, p->norb + 1, J + i * n2, K + i * n2,
+                                 w.n + (long long)i * p->norb, w.Eon + i, nullptr, w.info + 3 * i,
+                                 w.scr, w.scr_bytes, st);
+      if (rc != NOF_OK) return rc;
+    }
+    if (hipMemcpyAsync(hinfo.data(), w.info, 3 * ni * sizeof(int), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
+      return NOF_E_HIP;
+    if ((rc = sync()) != NOF_OK) return rc;
+    for (int i = 0; i < ni; ++i) {
+      if (!live[i]) continue;
+      if (hinfo[3 * i + 2] != NOF_OK) return hinfo[3 * i + 2];
+      if (prm->on_maxit > 0) res[i].on_iters += hinfo[3 * i];
+      rc = nof_functional_coeffs(p->norb, ns, ng, members, func, w.n + (long long)i * p->norb,
+                                 w.cJ + i * n2, w.cK + i * n2, nullptr, w.scr, w.scr_bytes, st);
+      if (rc != NOF_OK) return rc;
+      sweep[i] = 1;
+    }
+    // NO sweep at fixed occupations
+    for (int t = 0; t < prm->no_steps; ++t) {
+      bool stepping = false;
+      for (int i = 0; i < ni; ++i) stepping = stepping || sweep[i];
+      if (!stepping) break;
+      for (int i = 0; i < ni; ++i) {
+        const double tt = (double)(tstep[i] + 1);
+        ctl[3 * i] = sweep[i] ? 1.0 : 0.0;
+        ctl[3 * i + 1] = 1.0 - pow(prm->beta1, tt);
+        ctl[3 * i + 2] = 1.0 - pow(prm->beta2, tt);
+      }
+      if (hipMemcpyAsync(w.ctl, ctl.data(), 3 * ni * sizeof(double), hipMemcpyHostToDevice, st) !=
+          hipSuccess)
+        return NOF_E_HIP;
+      if (exec) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) return NOF_E_HIP;
+      } else if ((rc = no_step(p, a, w, C, prm, st)) != NOF_OK) {
+        return rc;
+      }
+      if (hipMemcpyAsync(hE.data(), w.E, ni * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(hA.data(), w.asym, ni * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return NOF_E_HIP;
+      if ((rc = sync()) != NOF_OK) return rc;
+      for (int i = 0; i < ni; ++i) {
+        if (!sweep[i]) continue;
+        res[i].E = hE[i];
+        res[i].asym = hA[i];
+        if (!std::isfinite(hE[i]) || !std::isfinite(hA[i])) {
+          // the step was not taken (asym not > tol); the instance stops here
+          res[i].status = NOF_E_NOT_CONVERGED;
+          failed_status = NOF_E_NOT_CONVERGED;
+          sweep[i] = 0;
+          live[i] = 0;
+        } else if (hA[i] <= prm->tol_lambda) {
+          sweep[i] = 0;
+        } else {
+          ++tstep[i];
+          ++res[i].no_steps;
+        }
+      }
+    }
+    for (int i = 0; i < ni; ++i) {
+      if (!live[i]) continue;
+      res[i].outer = outer + 1;
+      if (res[i].asym <= prm->tol_lambda && have_prev[i] &&
+          std::fabs(res[i].E - E_prev[i]) <= prm->tol_energy) {
+        res[i].converged = 1;
+        live[i] = 0;
+        continue;
+      }
+      E_prev[i] = res[i].E;
+      have_prev[i] = 1;
+    }
+  }
+  if (n_out) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_of((long long)ni * p->norb)), dim3(256), 0, st,
+                       (long long)ni * p->norb, w.n, n_out);
+    if ((rc = launch_status()) != NOF_OK) return rc;
+  }
+  return failed_status;
+}
 }  // namespace
 }  // namespace nof
 
@@ -279,7 +577,7 @@ int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int 
     p->tile_s1 = 128; p->tile_s2 = 128; p->tile_f2 = 128;
     p->f2gpi = 1;
     // the exchange partial buffer is sized for the largest split the tuner may pick
-    p->kchunks = kf1_chunks(naux, norb);
+    p->kchunks = kf1_parts(naux, norb, ninst, p->bt);
     const int gmax = f2_target_gpi(p, 64) * 4 > naux ? naux : f2_target_gpi(p, 64) * 4;
     p->f2gpi = gmax;
     plan_layout(p);
@@ -412,6 +710,34 @@ int nof_plan_launch(nof_plan plan, hipStream_t stream) {
   if (!plan_ok(plan)) return NOF_E_NULL;
   if (!plan->captured) return NOF_E_ARG;
   return hipGraphLaunch(plan->exec, stream) == hipSuccess ? NOF_OK : NOF_E_HIP;
+}
+
+size_t nof_plan_solve_ws(nof_plan plan, int ns, int ng) {
+  if (!plan_ok(plan) || ns < 1 || ng < 1 || (long long)ns * (ng + 1) > plan->norb) return 0;
+  try {
+    return solve_lay(plan, ns, ng).total;
+  } catch (...) {
+    return 0;
+  }
+}
+
+int nof_plan_solve(nof_plan plan, const void* B, const double* H, double* C, int ns, int ng,
+                   const int* members, int map, int func, double* gamma, double* n_out,
+                   const nof_solve_params* p, nof_solve_result* res, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+  return guarded_b([&]() -> int {
+    if (!plan_ok(plan)) return NOF_E_NULL;
+    if (!B || !H || !C || !members || !gamma || !p || !res) return NOF_E_NULL;
+    if (p->max_outer < 1 || p->no_steps < 1 || p->on_maxit < 0 || !(p->lr > 0.0) ||
+        !(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
+        !(p->eps >= 0.0))
+      return NOF_E_ARG;
+    const size_t need = nof_plan_solve_ws(plan, ns, ng);
+    if (need == 0) return NOF_E_DIM;
+    if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
+    return plan_solve(plan, B, H, C, ns, ng, members, map, func, gamma, n_out, p, res, (char*)ws,
+                      stream);
+  });
 }
 
 int nof_plan_destroy(nof_plan plan) {

@@ -98,6 +98,9 @@ _sig("nof_nlop_romberg", _i, _i, _d, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_nlop_isotropic", _i, _vp, _vp, _vp)
 _sig("nof_solve", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _i, _i, _vp, _vp, _i,
      ctypes.POINTER(SolveParams), ctypes.POINTER(SolveResult), _vp, _sz, _vp)
+_sig("nof_plan_solve_ws", _sz, _vp, _i, _i)
+_sig("nof_plan_solve", _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _i, _i, _vp, _vp,
+     ctypes.POINTER(SolveParams), ctypes.POINTER(SolveResult), _vp, _sz, _vp)
 MAP_TRIG, MAP_SOFTMAX = 0, 1
 FUNC_HF, FUNC_PNOF5 = 0, 1
 
@@ -111,7 +114,7 @@ DECLARED = [
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
     "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
-    "nof_solve_ws", "nof_solve", "nof_dipole_ws", "nof_dipole", "nof_nlop_romberg",
+    "nof_solve_ws", "nof_solve", "nof_plan_solve_ws", "nof_plan_solve", "nof_dipole_ws", "nof_dipole", "nof_nlop_romberg",
     "nof_nlop_isotropic", "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
 ]
 
@@ -444,6 +447,7 @@ class BatchPlan:
         for t, name in zip(self.inputs[1:], ("C", "H", "n", "cJ", "cK")):
             _f64(t, name)
         self.E = torch.empty(self.ninst, dtype=torch.float64, device=dev)
+        self.solve_ws = None
         self.lam = torch.empty((self.ninst, norb, norb), dtype=torch.float64, device=dev)
         self.g = torch.empty_like(self.lam)
 
@@ -466,6 +470,33 @@ class BatchPlan:
     def launch(self, stream):
         check(lib.nof_plan_launch(self.handle, stream_handle(stream)), "nof_plan_launch")
         return self.E, self.lam, self.g
+
+    def solve(self, members, mapping, functional, gamma, n_out=None, stream=None, max_outer=100,
+              no_steps=30, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, tol_lambda=1e-5,
+              tol_energy=1e-9, on_maxit=2000, on_tol=1e-8):
+        """Alternating NO + ON optimisation of every instance (nof_plan_solve).
+        The bound C [ninst][nbf][norb] and gamma [ninst][ns][ng] are updated in
+        place; returns one result dict per instance."""
+        B, C, H = self.inputs[:3]
+        _, ns, ng = gamma.shape
+        if members.dtype != torch.int32:
+            raise TypeError("members must be int32")
+        need = lib.nof_plan_solve_ws(self.handle, ns, ng)
+        if need == 0:
+            raise NofError(E_DIM, "nof_plan_solve_ws")
+        if self.solve_ws is None or self.solve_ws.numel() < need:
+            self.solve_ws = workspace(need, C.device)
+        prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit,
+                          on_tol)
+        res = (SolveResult * self.ninst)()
+        rc = lib.nof_plan_solve(self.handle, _p(B), _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
+                                int(mapping), int(functional), _f64(gamma, "gamma"), _p(n_out),
+                                ctypes.byref(prm), res, _p(self.solve_ws), self.solve_ws.numel(),
+                                stream_handle(stream))
+        out = [{f: getattr(r, f) for f, _ in SolveResult._fields_} for r in res]
+        if rc != E_NOT_CONVERGED:
+            check(rc, "nof_plan_solve")
+        return out
 
     @property
     def config(self):

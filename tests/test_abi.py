@@ -136,3 +136,29 @@ def test_nlop_validation():
     assert L.nof_nlop_romberg(3, 0.0, FAKE, FAKE, FAKE, FAKE, FAKE, None) == nof.E_ARG
     assert L.nof_nlop_romberg(3, 1e-3, None, FAKE, FAKE, FAKE, FAKE, None) == nof.E_NULL
     assert L.nof_nlop_isotropic(None, FAKE, None) == nof.E_NULL
+
+
+def test_plan_solve_validation():
+    import ctypes
+    nof = _lib()
+    L = nof.lib
+    plan = ctypes.c_void_p()
+    assert L.nof_plan_create(ctypes.byref(plan), 3, 16, 8, 8, nof.P_F64) == nof.OK
+    try:
+        need = L.nof_plan_solve_ws(plan, 2, 1)
+        assert need > L.nof_plan_ws(plan) + 3 * 9 * 8 * 8 * 8   # plan + nine norb^2 arrays per instance
+        assert L.nof_plan_solve_ws(plan, 3, 2) == 0                # 3 x (2+1) > norb
+        assert L.nof_plan_solve_ws(None, 2, 1) == 0
+        prm = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+        res = (nof.SolveResult * 3)()
+        args = lambda pl, B, p, ws_bytes: (pl, B, FAKE, FAKE, 2, 1, FAKE, 1, 1, FAKE, None,
+                                           ctypes.byref(p), res, FAKE, ws_bytes, None)
+        assert L.nof_plan_solve(*args(None, FAKE, prm, need)) == nof.E_NULL
+        assert L.nof_plan_solve(*args(plan, None, prm, need)) == nof.E_NULL
+        bad = nof.SolveParams(10, 0, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+        assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
+        bad = nof.SolveParams(10, 30, 0.01, 1.0, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+        assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
+        assert L.nof_plan_solve(*args(plan, FAKE, prm, need - 1)) == nof.E_WORKSPACE
+    finally:
+        L.nof_plan_destroy(plan)
