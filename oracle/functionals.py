@@ -14,6 +14,14 @@ cK = nn^T - Delta - Pi:
   Pi_pp = n_p), zero between subspaces.  The formulas follow the cited
   literature (parity unpinned as a functional; its energy is pinned against
   the exact two-electron two-orbital result and the spin-orbital 2RDM).
+* "pnof7": PNOF5 inside each subspace plus the interpair static term of the
+  cited literature: between orbitals of different subspaces Delta_pq = 0 and
+  Pi_pq = -Phi_p Phi_q with Phi_p = sqrt(n_p (1 - n_p)), so the pair adds
+  -Phi_p Phi_q K_pq (L = K for real orbitals) to the HF-like n_p n_q (2J - K).
+  Parity unpinned as a functional (formulas outside the paper); pinned: it
+  reduces to PNOF5 for one subspace and for 0/1 occupations, the interpair
+  term only lowers E where K >= 0, and its gradient matches finite
+  differences.
 
 ``members`` is an (ns, ng+1) integer array: row g lists the strong orbital of
 subspace g first, then its weak orbitals.
@@ -36,7 +44,7 @@ def delta_pi(n, members, functional):
     m = len(n)
     if functional == "hf":
         return np.zeros((m, m)), np.zeros((m, m))
-    if functional != "pnof5":
+    if functional not in ("pnof5", "pnof7"):
         raise ValueError(functional)
     grp, strong = group_of(m, members)
     Delta = np.zeros((m, m))
@@ -50,6 +58,12 @@ def delta_pi(n, members, functional):
                 else:
                     sgn = -1.0 if (strong[p] or strong[q]) else 1.0
                     Pi[p, q] = sgn * np.sqrt(n[p] * n[q])
+    if functional == "pnof7":
+        phi = np.sqrt(n * (1.0 - n))
+        for p in range(m):
+            for q in range(m):
+                if grp[p] >= 0 and grp[q] >= 0 and grp[p] != grp[q]:
+                    Pi[p, q] = -phi[p] * phi[q]
     return Delta, Pi
 
 
@@ -86,4 +100,14 @@ def denergy_dn(n, hdiag, J, K, members, functional, nfloor=1e-300):
                     continue
                 sgn = -1.0 if (strong[r] or strong[q]) else 1.0
                 g[r] += sgn * 0.5 * np.sqrt(n[q] / max(n[r], nfloor)) * K[r, q] * 2.0
+    if functional == "pnof7":
+        # interpair: -sum over ordered pairs of different subspaces of
+        # Phi_p Phi_q K_pq; d/dn_r = -2 Phi_r' sum_{q not in r's subspace} Phi_q K_rq,
+        # Phi_r' = (1 - 2 n_r) / (2 Phi_r)
+        phi = np.sqrt(n * (1.0 - n))
+        for r in range(len(n)):
+            if grp[r] < 0:
+                continue
+            S = sum(phi[q] * K[r, q] for q in range(len(n)) if grp[q] >= 0 and grp[q] != grp[r])
+            g[r] -= 2.0 * (1.0 - 2.0 * n[r]) / (2.0 * max(phi[r], nfloor)) * S
     return g

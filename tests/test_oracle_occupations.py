@@ -48,7 +48,7 @@ def _jk(norb, seed):
     return np.diag(dfjk.one_electron(H, C)).copy(), J, K
 
 
-@pytest.mark.parametrize("functional", ["hf", "pnof5"])
+@pytest.mark.parametrize("functional", ["hf", "pnof5", "pnof7"])
 def test_dEdn_against_finite_differences(functional):
     ns, ng = 3, 2
     members, norb = members_of(ns, ng)
@@ -65,7 +65,7 @@ def test_dEdn_against_finite_differences(functional):
 
 
 @pytest.mark.parametrize("mapping", ["trig", "softmax"])
-@pytest.mark.parametrize("functional", ["hf", "pnof5"])
+@pytest.mark.parametrize("functional", ["hf", "pnof5", "pnof7"])
 def test_dEdgamma_against_finite_differences(mapping, functional):
     ns, ng = 3, 3
     members, norb = members_of(ns, ng)
@@ -120,3 +120,86 @@ def test_optimizer_reaches_a_stationary_minimum(mapping):
     # and the gradient vanishes at the returned point
     assert E <= res.fun + 1e-9 * max(1.0, abs(E))
     assert np.max(np.abs(jac(x.ravel()))) < 1e-6
+
+
+def _grid_jk(norb, seed):
+    """h_pp, J, K on the kernel-on-grid tensor (K >= 0 there)."""
+    B = inputs.make_B_grid(norb, 4 * norb, seed=seed)
+    C = inputs.make_C(seed, norb, norb)
+    b, _ = dfjk.mo_transform(B, C)
+    J, K = dfjk.jk(b)
+    return np.diag(dfjk.one_electron(inputs.make_H(seed, norb), C)).copy(), J, K
+
+
+def test_pnof7_reduces_to_pnof5():
+    """One subspace: no interpair term.  Occupations 0 or 1: Phi = 0, so the
+    interpair term vanishes for any number of subspaces."""
+    members = np.array([[0, 1, 2]])
+    hd, J, K = _jk(3, 4)
+    n = np.array([0.9, 0.07, 0.03])
+    for f in (functionals.coefficients, ):
+        c5, c7 = f(n, members, "pnof5"), f(n, members, "pnof7")
+        assert np.array_equal(c5[0], c7[0]) and np.array_equal(c5[1], c7[1])
+    ns, ng = 3, 2
+    members, norb = members_of(ns, ng)
+    hd, J, K = _jk(norb, 5)
+    n = np.zeros(norb)
+    n[members[:, 0]] = 1.0
+    assert functionals.energy_of_n(n, hd, J, K, members, "pnof7") == \
+        functionals.energy_of_n(n, hd, J, K, members, "pnof5")
+
+
+def test_pnof7_interpair_term_lowers_the_energy():
+    """With K >= 0 (kernel-on-grid tensor) the interpair term -Phi_p Phi_q K_pq
+    only lowers E, by exactly sum over ordered pairs of different subspaces;
+    a sign or factor slip in Pi fails this."""
+    ns, ng = 3, 2
+    members, norb = members_of(ns, ng)
+    hd, J, K = _grid_jk(norb, 6)
+    assert np.all(K >= 0)
+    rng = np.random.default_rng(6)
+    n = occupations.occupations(rng.uniform(0.3, 1.2, (ns, ng)), members, norb, "trig")
+    E5 = functionals.energy_of_n(n, hd, J, K, members, "pnof5")
+    E7 = functionals.energy_of_n(n, hd, J, K, members, "pnof7")
+    phi = np.sqrt(n * (1 - n))
+    grp, _ = functionals.group_of(norb, members)
+    inter = sum(phi[p] * phi[q] * K[p, q] for p in range(norb) for q in range(norb)
+                if grp[p] != grp[q])
+    assert inter > 0
+    assert abs((E5 - E7) - inter) <= 1e-12 * max(1.0, abs(E7))
+
+
+def test_pnof7_two_electron_exact():
+    """One pair: PNOF7 has no interpair term and keeps PNOF5's exact
+    two-electron two-orbital minimum."""
+    members = np.array([[0, 1]])
+    hd, J, K = _jk(2, 12)
+    a, b = 2 * hd[0] + J[0, 0], 2 * hd[1] + J[1, 1]
+    if a > b:
+        hd = hd[::-1].copy(); J = J[::-1, ::-1].copy(); K = K[::-1, ::-1].copy()
+        a, b = b, a
+    exact = 0.5 * (a + b) - np.sqrt(0.25 * (a - b) ** 2 + K[0, 1] ** 2)
+    x, n, E, it, ok = occupations.optimize_lbfgs(np.array([[0.3]]), members, 2, "trig", hd, J, K,
+                                                 "pnof7", tol=1e-10, maxit=2000)
+    assert ok and abs(E - exact) < 1e-12 * max(1.0, abs(exact))
+
+
+def test_pnof7_cumulant_against_spin_orbital_2rdm():
+    """The PNOF7 (Delta, Pi) through Eq. (PNOF)'s coefficients gives the energy
+    of the spin-orbital 2RDM built from the same cumulant."""
+    import _bruteforce as bf
+    ns, ng = 2, 1
+    members, norb = members_of(ns, ng)
+    B = inputs.make_B(8, norb, 3 * norb, 4.0, threads=1)
+    C = inputs.make_C(8, norb, norb)
+    H = inputs.make_H(8, norb)
+    n = occupations.occupations(np.array([[0.4], [0.7]]), members, norb, "trig")
+    Delta, Pi = functionals.delta_pi(n, members, "pnof7")
+    assert np.any(Pi[members[0][:, None], members[1][None, :]] != 0)
+    b, _ = dfjk.mo_transform(B, C)
+    h = dfjk.one_electron(H, C)
+    J, K = dfjk.jk(b)
+    cJ, cK = dfjk.coeffs_from_cumulant(n, Delta, Pi)
+    E = dfjk.energy(n, h, J, K, cJ, cK)
+    Ebf = bf.spin_orbital_energy(n, h, bf.mo_eri(B, C), Delta, Pi)
+    assert abs(E - Ebf) <= 1e-12 * max(1.0, abs(Ebf))
