@@ -183,7 +183,9 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
   g.x_kmajor = true;
   g.Y = a.ws + p->off[O_B]; g.ldy = p->norb; g.sy = n2; g.sy2 = (long long)p->naux * n2;
   g.S = a.cK; g.lds = p->norb; g.ss2 = n2;
-  g.Out = f2p; g.ldo = p->norb; g.so = n2;
+  // partial (instance i, group c) at f2p + (i*gpi + c)*n2: with fold > 1 the
+  // epilogue indexes it by group, with fold = 1 by inner*so + outer*so2
+  g.Out = f2p; g.ldo = p->norb; g.so = n2; g.so2 = (long long)gpi * n2;
   g.role = GemmRole::ExchangeFock;
   g.tile = p->tile_f2;
   int rc = gemm_tn(g, p->bt, p->bt, NOF_F64, p->prec, st);

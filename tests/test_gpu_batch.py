@@ -45,7 +45,10 @@ def test_batch_matches_single_instance_every_config(prec_name):
     plan = nof.BatchPlan(Bd, dev(C), dev(H), dev(n), dev(cJ), dev(cK), prec=prec)
     ref = [single(nof, Bd, C[i], H[i], n[i], cJ[i], cK[i], prec) for i in range(ninst)]
     tol = 1e-12 if prec_name == "f64" else 2e-6
-    for cfg in ([128, 128, 128, 1], [64, 64, 64, 2], [64, 128, 64, 1], [128, 64, 128, 3]):
+    # the last two: one P per exchange group (fold 1, the default split of small
+    # plans), where the partials of instance i must not land on instance 0's
+    for cfg in ([128, 128, 128, 1], [64, 64, 64, 2], [64, 128, 64, 1], [128, 64, 128, 3],
+                [128, 128, 128, naux], [64, 64, 64, naux]):
         plan.config = cfg
         E, lam, g = plan.iteration()
         torch.cuda.synchronize()
