@@ -267,9 +267,12 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
  *          cos^2 x_j sin^2 x_i, the last weak orbital takes the rest;
  *          NOF_MAP_SOFTMAX: n_g = 1/(1 + sum_k e^{x_k}), n_{p_i} = n_g e^{x_i}.
  * gamma    [ns][ng] variables (trig: x_g then x_1..x_{ng-1}; softmax x_1..x_ng).
- * func     NOF_FUNC_HF (Delta = Pi = 0) or NOF_FUNC_PNOF5 (independent pairs:
+ * func     NOF_FUNC_HF (Delta = Pi = 0), NOF_FUNC_PNOF5 (independent pairs:
  *          Delta_pq = n_p n_q and Pi_pq = -+sqrt(n_p n_q) within a subspace,
- *          Pi_pp = n_p; see nof_functional_coeffs).
+ *          Pi_pp = n_p; see nof_functional_coeffs) or NOF_FUNC_PNOF7 (PNOF5
+ *          within each subspace; between orbitals of different subspaces
+ *          Delta_pq = 0 and Pi_pq = -Phi_p Phi_q, Phi_p = sqrt(n_p (1 - n_p)):
+ *          the interpair static term of Table 1's PNOF7, cited by the paper).
  * hdiag    h_pp = hdiag[p * hstride] (hstride = norb + 1 reads the diagonal of
  *          a full h).  J, K [norb][norb] FP64.
  * E = 2 sum_p n_p h_pp + sum_pq cJ(n)_pq J_pq - sum_pq cK(n)_pq K_pq.
@@ -287,7 +290,7 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
  * ws: nof_occ_ws() bytes (all three calls).
  * ------------------------------------------------------------------------- */
 typedef enum { NOF_MAP_TRIG = 0, NOF_MAP_SOFTMAX = 1 } nof_map;
-typedef enum { NOF_FUNC_HF = 0, NOF_FUNC_PNOF5 = 1 } nof_functional;
+typedef enum { NOF_FUNC_HF = 0, NOF_FUNC_PNOF5 = 1, NOF_FUNC_PNOF7 = 2 } nof_functional;
 size_t nof_occ_ws(int norb, int ns, int ng);
 int nof_occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int func,
                         const double* gamma, const double* hdiag, int hstride,

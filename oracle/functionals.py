@@ -60,11 +60,14 @@ def delta_pi(n, members, functional):
                     Pi[p, q] = sgn * np.sqrt(n[p] * n[q])
     if functional == "pnof7":
         phi = np.sqrt(n * (1.0 - n))
-        for p in range(m):
-            for q in range(m):
-                if grp[p] >= 0 and grp[q] >= 0 and grp[p] != grp[q]:
-                    Pi[p, q] = -phi[p] * phi[q]
+        inter = interpair_mask(grp)
+        Pi[inter] = -np.outer(phi, phi)[inter]
     return Delta, Pi
+
+
+def interpair_mask(grp):
+    """[p, q] True when p and q belong to different subspaces."""
+    return (grp[:, None] >= 0) & (grp[None, :] >= 0) & (grp[:, None] != grp[None, :])
 
 
 def coefficients(n, members, functional):
@@ -105,9 +108,8 @@ def denergy_dn(n, hdiag, J, K, members, functional, nfloor=1e-300):
         # Phi_p Phi_q K_pq; d/dn_r = -2 Phi_r' sum_{q not in r's subspace} Phi_q K_rq,
         # Phi_r' = (1 - 2 n_r) / (2 Phi_r)
         phi = np.sqrt(n * (1.0 - n))
+        S = np.where(interpair_mask(grp), K, 0.0) @ phi
         for r in range(len(n)):
-            if grp[r] < 0:
-                continue
-            S = sum(phi[q] * K[r, q] for q in range(len(n)) if grp[q] >= 0 and grp[q] != grp[r])
-            g[r] -= 2.0 * (1.0 - 2.0 * n[r]) / (2.0 * max(phi[r], nfloor)) * S
+            if grp[r] >= 0:
+                g[r] -= 2.0 * (1.0 - 2.0 * n[r]) / (2.0 * max(phi[r], nfloor)) * S[r]
     return g

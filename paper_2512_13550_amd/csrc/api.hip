@@ -473,7 +473,7 @@ namespace {
 bool occ_args_ok(int norb, int ns, int ng, int map, int func) {
   if (!dim_ok(norb) || ns < 1 || ng < 1 || (long long)ns * (ng + 1) > norb) return false;
   if (map != NOF_MAP_TRIG && map != NOF_MAP_SOFTMAX) return false;
-  if (func != NOF_FUNC_HF && func != NOF_FUNC_PNOF5) return false;
+  if (func != NOF_FUNC_HF && func != NOF_FUNC_PNOF5 && func != NOF_FUNC_PNOF7) return false;
   return true;
 }
 }  // namespace

@@ -29,30 +29,32 @@ struct OccProblem {
   const double* hdiag; int hstride;
   const double* J; const double* K;
   const double* M;             // 2J - K (workspace)
+  double* phi;                 // PNOF7: Phi_r = sqrt(n_r (1 - n_r)) (workspace)
+  double* u;                   // PNOF7: u = K Phi (workspace)
   int* grp;                    // [norb] subspace of each orbital, -1 if none
   int* pos;                    // [norb] position inside the subspace (0 = strong)
 };
 
 struct OccWs {
-  double *x, *g, *d, *xt, *gt, *S, *Y, *n, *nt, *dn, *v, *sy, *yy;
+  double *x, *g, *d, *xt, *gt, *S, *Y, *n, *nt, *dn, *v, *sy, *yy, *phi, *u;
   int *grp, *pos;
   double* M;
 };
 
 // Workspace layout (all sub-buffers 256-byte aligned).
 struct OccLayout {
-  size_t off[16];
+  size_t off[18];
   size_t total;
 };
 OccLayout occ_layout(int norb, int ns, int ng) {
   OccLayout L;
   const size_t nv = (size_t)ns * ng;
-  const size_t sz[16] = {(size_t)norb * norb * 8, nv * 8, nv * 8, nv * 8, nv * 8, nv * 8,
+  const size_t sz[18] = {(size_t)norb * norb * 8, nv * 8, nv * 8, nv * 8, nv * 8, nv * 8,
                          LM * nv * 8, LM * nv * 8, (size_t)norb * 8, (size_t)norb * 8,
                          (size_t)norb * 8, (size_t)norb * 8, LM * 8, LM * 8,
-                         (size_t)norb * 4, (size_t)norb * 4};
+                         (size_t)norb * 4, (size_t)norb * 4, (size_t)norb * 8, (size_t)norb * 8};
   size_t o = 0;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < 18; ++i) {
     L.off[i] = o;
     o = align256(o + sz[i]);
   }
@@ -79,6 +81,8 @@ OccWs occ_ws_ptrs(void* ws, int norb, int ns, int ng) {
   w.yy = (double*)(b + L.off[13]);
   w.grp = (int*)(b + L.off[14]);
   w.pos = (int*)(b + L.off[15]);
+  w.phi = (double*)(b + L.off[16]);
+  w.u = (double*)(b + L.off[17]);
   return w;
 }
 
@@ -180,7 +184,12 @@ __device__ double evaluate(const OccProblem& P, const double* x, double* n, doub
   __syncthreads();
   for (int g = tid; g < P.ns; g += OT) map_group(P, x, n, g);
   __syncthreads();
-  // v = M n, one wave per row
+  const bool p7 = P.func == NOF_FUNC_PNOF7;
+  if (p7) {
+    for (int r = tid; r < P.norb; r += OT) P.phi[r] = sqrt(n[r] * (1.0 - n[r]));
+    __syncthreads();
+  }
+  // v = M n (PNOF7 also u = K Phi), one wave per row
   const int lane = tid & 63, wv = tid >> 6;
   for (int r = wv; r < P.norb; r += OW) {
     const double* Mr = P.M + (long long)r * P.norb;
@@ -188,6 +197,13 @@ __device__ double evaluate(const OccProblem& P, const double* x, double* n, doub
     for (int q = lane; q < P.norb; q += 64) s = fma(Mr[q], n[q], s);
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) v[r] = s;
+    if (p7) {
+      const double* Kr = P.K + (long long)r * P.norb;
+      double t = 0.0;
+      for (int q = lane; q < P.norb; q += 64) t = fma(Kr[q], P.phi[q], t);
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      if (lane == 0) P.u[r] = t;
+    }
   }
   __syncthreads();
   double e = 0.0;
@@ -197,7 +213,7 @@ __device__ double evaluate(const OccProblem& P, const double* x, double* n, doub
     double d = 2.0 * hr + 2.0 * v[r];
     e += 2.0 * nr * hr + nr * v[r];
     const int g = P.grp[r];
-    if (P.func == NOF_FUNC_PNOF5 && g >= 0) {
+    if (P.func != NOF_FUNC_HF && g >= 0) {
       const int* row = P.members + (long long)g * (P.ng + 1);
       const bool rstrong = P.pos[r] == 0;
       const double Jrr = P.J[(long long)r * P.norb + r];
@@ -215,6 +231,15 @@ __device__ double evaluate(const OccProblem& P, const double* x, double* n, doub
           d += sgn * sqrt(nq / fmax(nr, 1e-300)) * Krq;
           e += sgn * sqrt(nr * nq) * Krq;
         }
+      }
+      if (p7) {
+        // interpair: S_r = sum over q outside r's subspace of K_rq Phi_q;
+        // E gains -Phi_r S_r per r, dE/dn_r = -2 Phi_r' S_r
+        double S = P.u[r];
+        for (int i = 0; i <= P.ng; ++i) S -= P.K[(long long)r * P.norb + row[i]] * P.phi[row[i]];
+        const double ph = P.phi[r];
+        e -= ph * S;
+        d -= 2.0 * (1.0 - 2.0 * nr) / (2.0 * fmax(ph, 1e-300)) * S;
       }
     }
     dn[r] = d;
@@ -374,7 +399,9 @@ __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsPa
   }
 }
 
-// cJ = 2(nn^T - Delta), cK = nn^T - Delta - Pi for the HF-like or PNOF5 functional
+// cJ = 2(nn^T - Delta), cK = nn^T - Delta - Pi for the HF-like, PNOF5 or PNOF7
+// functional (PNOF7: PNOF5 inside a subspace, Pi_pq = -Phi_p Phi_q between
+// subspaces, Phi = sqrt(n (1 - n)))
 __global__ void k_func_coeffs(int norb, int ng, int func, const double* __restrict__ n,
                               const int* __restrict__ grp, const int* __restrict__ pos,
                               double* __restrict__ cJ, double* __restrict__ cK) {
@@ -384,10 +411,12 @@ __global__ void k_func_coeffs(int norb, int ng, int func, const double* __restri
     const int p = (int)(i / norb), q = (int)(i - (long long)p * norb);
     const double nn = n[p] * n[q];
     double dl = 0.0, pi = 0.0;
-    if (func == NOF_FUNC_PNOF5 && grp[p] >= 0 && grp[p] == grp[q]) {
+    if (func != NOF_FUNC_HF && grp[p] >= 0 && grp[p] == grp[q]) {
       dl = nn;
       if (p == q) pi = n[p];
       else pi = ((pos[p] == 0 || pos[q] == 0) ? -1.0 : 1.0) * sqrt(nn);
+    } else if (func == NOF_FUNC_PNOF7 && grp[p] >= 0 && grp[q] >= 0) {
+      pi = -(sqrt(n[p] * (1.0 - n[p])) * sqrt(n[q] * (1.0 - n[q])));
     }
     cJ[i] = 2.0 * (nn - dl);
     cK[i] = nn - dl - pi;
@@ -417,7 +446,7 @@ OccProblem make_problem(int norb, int ns, int ng, const int* members, int map, i
   OccProblem P;
   P.norb = norb; P.ns = ns; P.ng = ng; P.map = map; P.func = func;
   P.members = members; P.hdiag = hdiag; P.hstride = hstride; P.J = J; P.K = K;
-  P.M = w.M; P.grp = w.grp; P.pos = w.pos;
+  P.M = w.M; P.grp = w.grp; P.pos = w.pos; P.phi = w.phi; P.u = w.u;
   return P;
 }
 

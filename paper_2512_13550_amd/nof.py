@@ -102,7 +102,7 @@ _sig("nof_plan_solve_ws", _sz, _vp, _i, _i)
 _sig("nof_plan_solve", _i, _vp, _vp, _vp, _vp, _i, _i, _vp, _i, _i, _vp, _vp,
      ctypes.POINTER(SolveParams), ctypes.POINTER(SolveResult), _vp, _sz, _vp)
 MAP_TRIG, MAP_SOFTMAX = 0, 1
-FUNC_HF, FUNC_PNOF5 = 0, 1
+FUNC_HF, FUNC_PNOF5, FUNC_PNOF7 = 0, 1, 2
 
 DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",

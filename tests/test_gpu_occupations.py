@@ -1,5 +1,5 @@
 """Parity of the FP64 occupation update (mappings, functional energy and
-gradient, PNOF5 coefficients, L-BFGS) against the oracle.
+gradient, PNOF5 and PNOF7 coefficients, L-BFGS) against the oracle.
 
 Bars: E relative 1e-12, dE/dgamma and n normwise 1e-10 (FP64, different
 summation order); a few L-BFGS iterations reproduce the oracle's iterates to
@@ -30,12 +30,12 @@ def on_instance(ns, ng, seed, gap=1.0, extra=0):
 
 def gpu_occ(nof, norb, members, mapping, functional):
     m = {"trig": nof.MAP_TRIG, "softmax": nof.MAP_SOFTMAX}[mapping]
-    f = {"hf": nof.FUNC_HF, "pnof5": nof.FUNC_PNOF5}[functional]
+    f = {"hf": nof.FUNC_HF, "pnof5": nof.FUNC_PNOF5, "pnof7": nof.FUNC_PNOF7}[functional]
     return nof.Occupations(norb, torch.from_numpy(members.astype(np.int32)).cuda(), m, f)
 
 
 @pytest.mark.parametrize("mapping", ["trig", "softmax"])
-@pytest.mark.parametrize("functional", ["hf", "pnof5"])
+@pytest.mark.parametrize("functional", ["hf", "pnof5", "pnof7"])
 @pytest.mark.parametrize("ns,ng,extra", [(4, 3, 0), (125, 3, 0), (9, 1, 5)])
 def test_energy_grad(mapping, functional, ns, ng, extra):
     nof = need_gpu()
@@ -52,7 +52,7 @@ def test_energy_grad(mapping, functional, ns, ng, extra):
     assert normwise(host(ngpu), n) <= 1e-14
 
 
-@pytest.mark.parametrize("functional", ["hf", "pnof5"])
+@pytest.mark.parametrize("functional", ["hf", "pnof5", "pnof7"])
 def test_functional_coefficients(functional):
     nof = need_gpu()
     norb, members, hd, J, K = on_instance(12, 3, 4, extra=3)
@@ -82,15 +82,16 @@ def test_lbfgs_first_iterates_match(mapping):
 
 
 @pytest.mark.parametrize("mapping", ["trig", "softmax"])
-@pytest.mark.parametrize("ns,ng", [(10, 3), (125, 3)])
-def test_lbfgs_converges_to_oracle_minimum(mapping, ns, ng):
+@pytest.mark.parametrize("ns,ng,functional", [(10, 3, "pnof5"), (125, 3, "pnof5"), (10, 3, "pnof7"),
+                                              (125, 3, "pnof7")])
+def test_lbfgs_converges_to_oracle_minimum(mapping, ns, ng, functional):
     nof = need_gpu()
     norb, members, hd, J, K = on_instance(ns, ng, 6)
     x0 = np.full((ns, ng), 0.3 if mapping == "trig" else -3.0)
-    x, n, E, it, ok = occupations.optimize_lbfgs(x0, members, norb, mapping, hd, J, K, "pnof5",
+    x, n, E, it, ok = occupations.optimize_lbfgs(x0, members, norb, mapping, hd, J, K, functional,
                                                  maxit=3000, tol=1e-8)
     assert ok
-    occ = gpu_occ(nof, norb, members, mapping, "pnof5")
+    occ = gpu_occ(nof, norb, members, mapping, functional)
     g = dev(x0)
     Eg, ng_, info = occ.optimize(g, dev(hd), dev(J), dev(K), maxit=3000, tol=1e-8)
     torch.cuda.synchronize()

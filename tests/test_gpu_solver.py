@@ -51,25 +51,26 @@ def gapped_system(seed, nbf, naux, ns, gap=1.0):
     return B, (V * e) @ V.T, V
 
 
-@pytest.mark.parametrize("prec", ["f64", "x10"])
-def test_solve_pnof5_trajectory_matches_oracle(prec):
+@pytest.mark.parametrize("prec,functional", [("f64", "pnof5"), ("x10", "pnof5"), ("f64", "pnof7")])
+def test_solve_trajectory_matches_oracle(prec, functional):
     """Four outer iterations (ON step + 30 ADAM steps each) from the same start:
     the two loops take the same steps, so the iterates agree (the early
     iterations, with large gradients, do not amplify rounding differences)."""
     nof = need_gpu()
-    print(f"case solve pnof5 trajectory nbf=24 {prec}", flush=True)
+    print(f"case solve {functional} trajectory nbf=24 {prec}", flush=True)
     nbf, ns, ng = 24, 6, 2
     B, H, C0 = gapped_system(5, nbf, 96, ns)
     members = np.array(inputs.pairing(nbf, ns, ng), dtype=np.int64)
     gamma0 = mlp.cold_gamma(members, "softmax")
     kw = dict(max_outer=4, no_steps=30, tol_lambda=1e-12, tol_energy=0.0)
-    ref = solver.solve(B, C0, H, members, "softmax", "pnof5", gamma0, **kw)
+    ref = solver.solve(B, C0, H, members, "softmax", functional, gamma0, **kw)
     C = dev(C0)
     gamma = dev(gamma0)
     n = torch.empty(nbf, dtype=torch.float64, device="cuda")
     Bd = dev(B) if prec == "f64" else nof.SplitB(dev(B))
+    func = {"pnof5": nof.FUNC_PNOF5, "pnof7": nof.FUNC_PNOF7}[functional]
     r = nof.solve(Bd, C, dev(H), torch.from_numpy(members.astype(np.int32)).cuda(), nof.MAP_SOFTMAX,
-                  nof.FUNC_PNOF5, gamma, n=n, prec=nof.P_F64 if prec == "f64" else nof.P_BF16X10, **kw)
+                  func, gamma, n=n, prec=nof.P_F64 if prec == "f64" else nof.P_BF16X10, **kw)
     print("gpu", r, "oracle E", ref["E"], "asym", ref["asym"], "steps", ref["no_steps"], flush=True)
     dE = abs(r["E"] - ref["E"]) / abs(ref["E"])
     dC = float(np.max(np.abs(C.cpu().numpy() - ref["C"])))
