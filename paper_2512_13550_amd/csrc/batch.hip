@@ -318,7 +318,7 @@ unsigned grid_of(long long n) {
 
 // Workspace of the batched solve, after the plan's own.
 struct SolveLay {
-  size_t n, cJ, cK, lam, grad, m, v, y, U, Cn, E, Eon, asym, ctl, info, scr, scr_bytes, total;
+  size_t n, cJ, cK, lam, grad, m, v, y, U, Cn, E, Eon, asym, ctl, info, act, scr, scr_bytes, total;
 };
 
 SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
@@ -342,9 +342,10 @@ SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
   L.asym = take(ni * 8);
   L.ctl = take(ni * 3 * 8);
   L.info = take(ni * 3 * sizeof(int));
-  size_t s = nof_expm_antisym_ws(p->norb);
-  s = std::max(s, nof_rotate_orbitals_ws(p->nbf, p->norb));
-  s = std::max(s, nof_occ_ws(p->norb, ns, ng));
+  L.act = take(ni * sizeof(int));
+  size_t s = expm_ws(p->norb, p->ninst);
+  s = std::max(s, rotate_ws(p->nbf, p->norb, p->ninst));
+  s = std::max(s, ni * occ_ws_stride(p->norb, ns, ng));   // all instances' ON steps at once
   L.scr_bytes = s;
   L.scr = take(s);
   L.total = o;
@@ -353,7 +354,7 @@ SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
 
 struct SolveBufs {
   double *n, *cJ, *cK, *lam, *grad, *m, *v, *y, *U, *Cn, *E, *Eon, *asym, *ctl;
-  int* info;
+  int *info, *act;
   void* scr;
   size_t scr_bytes;
 };
@@ -371,13 +372,9 @@ int no_step(nof_plan_s* p, const Args& a, const SolveBufs& w, double* C, const n
                      w.v, w.ctl, w.asym, prm->tol_lambda, prm->beta1, prm->beta2, prm->lr, prm->eps,
                      w.y);
   if ((rc = launch_status()) != NOF_OK) return rc;
-  for (int i = 0; i < p->ninst; ++i) {
-    rc = nof_expm_antisym(p->norb, w.y + i * n2, w.U + i * n2, w.scr, w.scr_bytes, st);
-    if (rc != NOF_OK) return rc;
-    rc = nof_rotate_orbitals(p->nbf, p->norb, C + i * cs, w.U + i * n2, w.Cn + i * cs, w.scr,
-                             w.scr_bytes, st);
-    if (rc != NOF_OK) return rc;
-  }
+  // every instance's exp(y_i) and C_i U_i in the same launches
+  if ((rc = expm_antisym(p->norb, w.y, w.U, w.scr, st, p->ninst)) != NOF_OK) return rc;
+  if ((rc = rotate_orbitals(p->nbf, p->norb, C, w.U, w.Cn, w.scr, st, p->ninst)) != NOF_OK) return rc;
   hipLaunchKernelGGL(k_copy_f64, dim3(grid_of(cs * p->ninst)), dim3(256), 0, st, cs * p->ninst, w.Cn,
                      C);
   return launch_status();
@@ -395,13 +392,12 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
   w.m = (double*)(ws + L.m); w.v = (double*)(ws + L.v); w.y = (double*)(ws + L.y);
   w.U = (double*)(ws + L.U); w.Cn = (double*)(ws + L.Cn);
   w.E = (double*)(ws + L.E); w.Eon = (double*)(ws + L.Eon); w.asym = (double*)(ws + L.asym);
-  w.ctl = (double*)(ws + L.ctl); w.info = (int*)(ws + L.info);
+  w.ctl = (double*)(ws + L.ctl); w.info = (int*)(ws + L.info); w.act = (int*)(ws + L.act);
   w.scr = ws + L.scr; w.scr_bytes = L.scr_bytes;
   const Args a{B, C, H, w.n, w.cJ, w.cK, w.E, w.lam, w.grad, ws};
   const double* h = (const double*)(ws + p->off[O_H]);
   const double* J = (const double*)(ws + p->off[O_J]);
   const double* K = (const double*)(ws + p->off[O_K]);
-  const int nv = ns * ng;
 
   for (int i = 0; i < ni; ++i) {
     res[i] = nof_solve_result{};
@@ -448,22 +444,14 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
     bool any = false;
     for (int i = 0; i < ni; ++i) any = any || live[i];
     if (!any) break;
-    // ON step at fixed orbitals: h_i, J_i, K_i of the current C_i
+    // ON step at fixed orbitals: h_i, J_i, K_i of the current C_i; every
+    // running instance in one launch (one workgroup each)
     if ((rc = run_iteration(p, a, st)) != NOF_OK) return rc;
-    for (int i = 0; i < ni; ++i) {
-      if (!live[i]) continue;
-      if (prm->on_maxit > 0)
-        rc = nof_occ_optimize(p->norb, ns, ng, members, map, func, h + i * n2, p->norb + 1, J + i * n2,
-                              K + i * n2, gamma + (long long)i * nv, w.n + (long long)i * p->norb,
-                              w.Eon + i, w.info + 3 * i, prm->on_maxit, prm->on_tol, w.scr,
-                              w.scr_bytes, st);
-      else
-        rc = nof_occ_energy_grad(p->norb, ns, ng, members, map, func, gamma + (long long)i * nv,
-                                 h + i * n2, p->norb + 1, J + i * n2, K + i * n2,
-                                 w.n + (long long)i * p->norb, w.Eon + i, nullptr, w.info + 3 * i,
-                                 w.scr, w.scr_bytes, st);
-      if (rc != NOF_OK) return rc;
-    }
+    if (hipMemcpyAsync(w.act, live.data(), ni * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
+      return NOF_E_HIP;
+    rc = occ_batched(ni, w.act, p->norb, ns, ng, members, map, func, h, p->norb + 1, n2, J, K, n2,
+                     gamma, w.n, w.Eon, w.info, prm->on_maxit, prm->on_tol, w.scr, st);
+    if (rc != NOF_OK) return rc;
     if (hipMemcpyAsync(hinfo.data(), w.info, 3 * ni * sizeof(int), hipMemcpyDeviceToHost, st) !=
         hipSuccess)
       return NOF_E_HIP;

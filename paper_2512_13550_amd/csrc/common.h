@@ -59,7 +59,8 @@ struct GemmDesc {
   void* Out; long long ldo, so;
   double* Dg; long long sd;
   bool sym;
-  const int* pred; int pred_gt;   // if pred: run only when *pred > pred_gt (else write nothing)
+  const int* pred; int pred_gt;   // if pred: run only when *pred > pred_gt (else write nothing);
+  long long pred_so;               // with two-level batching, outer index o reads pred[o * pred_so]
   GemmRole role;                   // selects the kernel symbol (profiling attribution only)
   long long psx, psy;              // plane strides of pre-split bf16 operands (gemm_bf16)
   // Two-level batching (binner > 0): batch b = outer * binner + inner; operand
@@ -158,11 +159,13 @@ int energy(int norb, const double* n, const double* h, const double* J,
            long long jstride = 0);
 
 // FP64 orbital-rotation helpers (rotation.hip).
-size_t expm_ws(int norb);
-size_t rotate_ws(int nbf, int norb);
+size_t expm_ws(int norb, int ninst = 1);
+size_t rotate_ws(int nbf, int norb, int ninst = 1);
+// ninst instances at once: C, Cout stride nbf*norb, U and y stride norb^2;
+// ws of rotate_ws / expm_ws(.., ninst) bytes.
 int rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout, void* ws,
-                    hipStream_t st);
-int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st);
+                    hipStream_t st, int ninst = 1);
+int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st, int ninst = 1);
 int adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
               double beta2, double eps, double* y, hipStream_t st);
 
@@ -178,6 +181,16 @@ int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func
                  hipStream_t st);
 int functional_coeffs(int norb, int ns, int ng, const int* members, int func, const double* n,
                       double* cJ, double* cK, void* ws, int* bad, hipStream_t st);
+// ON steps of ninst independent problems in one launch (one workgroup each):
+// instance i reads hdiag + i*hinst, J, K + i*jkinst, updates gamma + i*ns*ng,
+// writes n + i*norb, E[i], info[3i..3i+2] and uses workspace
+// ws + i*occ_ws_stride(); skipped when active[i] == 0 (active may be NULL).
+// maxit > 0: L-BFGS as occ_optimize; maxit == 0: evaluation only.
+size_t occ_ws_stride(int norb, int ns, int ng);
+int occ_batched(int ninst, const int* active, int norb, int ns, int ng, const int* members, int map,
+                int func, const double* hdiag, int hstride, long long hinst, const double* J,
+                const double* K, long long jkinst, double* gamma, double* n, double* E, int* info,
+                int maxit, double tol, void* ws, hipStream_t st);
 
 // Learned warm start (mlp.hip).
 int mlp_nparams();

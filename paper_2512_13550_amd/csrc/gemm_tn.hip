@@ -68,7 +68,6 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   __shared__ TC Xs[2][KT][BMt + 16];
   __shared__ TC Ys[2][KT][BNt + 16];
 
-  if (d.pred && *d.pred <= d.pred_gt) return;
   const int tid = threadIdx.x;
   const int l = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
@@ -92,6 +91,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     b_lo = group * d.fold;
     b_hi = min(d.batch, b_lo + d.fold);
   }
+  if (d.pred && d.pred[(long long)outer * d.pred_so] <= d.pred_gt) return;
   const long long xo = (long long)outer * d.sx2, yo = (long long)outer * d.sy2;
   const double* __restrict__ Sg = d.S ? d.S + (long long)outer * d.ss2 : nullptr;
   const int nkb = (d.K + KT - 1) / KT;

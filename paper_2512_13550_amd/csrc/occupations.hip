@@ -272,8 +272,44 @@ __device__ bool setup(OccProblem& P, OccWs& w, int* info, double* red) {
   return true;
 }
 
+// Several independent problems in one launch, one workgroup each (blockIdx.x
+// = instance): element strides of h (diagonal base), J and K, gamma and n,
+// the byte stride of the per-instance workspace, and an optional mask
+// (instance skipped when active[i] == 0).  All zero: one problem.
+struct OccBatch {
+  long long h, jk, gamma, n, ws;
+  const int* active;
+};
+
+template <class T> __device__ __forceinline__ T* shift(T* p, long long bytes) {
+  return p ? (T*)((char*)p + bytes) : p;
+}
+
+// Moves P and w (and its views in P) to instance blockIdx.x; false if masked.
+__device__ bool to_instance(OccProblem& P, OccWs& w, const OccBatch& ib) {
+  const long long i = blockIdx.x;
+  if (ib.active && !ib.active[i]) return false;
+  if (i == 0) return true;
+  const long long wb = i * ib.ws;
+  w.x = shift(w.x, wb); w.g = shift(w.g, wb); w.d = shift(w.d, wb); w.xt = shift(w.xt, wb);
+  w.gt = shift(w.gt, wb); w.S = shift(w.S, wb); w.Y = shift(w.Y, wb); w.n = shift(w.n, wb);
+  w.nt = shift(w.nt, wb); w.dn = shift(w.dn, wb); w.v = shift(w.v, wb); w.sy = shift(w.sy, wb);
+  w.yy = shift(w.yy, wb); w.phi = shift(w.phi, wb); w.u = shift(w.u, wb);
+  w.grp = shift(w.grp, wb); w.pos = shift(w.pos, wb); w.M = shift(w.M, wb);
+  P.M = w.M; P.grp = w.grp; P.pos = w.pos; P.phi = w.phi; P.u = w.u;
+  P.hdiag += i * ib.h;
+  P.J += i * ib.jk;
+  P.K += i * ib.jk;
+  return true;
+}
+
+// M = 2J - K of instance blockIdx.y (J, K stride jk; M at byte stride wsb).
 __global__ void k_build_M(long long n2, const double* __restrict__ J, const double* __restrict__ K,
-                          double* __restrict__ M) {
+                          double* __restrict__ M, long long jk, long long wsb) {
+  const long long y = blockIdx.y;
+  J += y * jk;
+  K += y * jk;
+  M = shift(M, y * wsb);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x)
     M[i] = 2.0 * J[i] - K[i];
@@ -281,8 +317,17 @@ __global__ void k_build_M(long long n2, const double* __restrict__ J, const doub
 
 __global__ __launch_bounds__(OT) void k_occ_eval(OccProblem P, OccWs w, const double* gamma,
                                                  double* n_out, double* E_out, double* g_out,
-                                                 int* info) {
+                                                 int* info, OccBatch ib) {
   __shared__ double red[OT];
+  if (!to_instance(P, w, ib)) return;
+  {
+    const long long i = blockIdx.x;
+    gamma += i * ib.gamma;
+    if (n_out) n_out += i * ib.n;
+    if (E_out) E_out += i;
+    if (g_out) g_out += i * ib.gamma;
+    if (info) info += 3 * i;
+  }
   if (!setup(P, w, info, red)) return;
   const double E = evaluate(P, gamma, w.n, w.dn, w.v, w.g, red);
   const int nv = P.ns * P.ng;
@@ -301,8 +346,16 @@ struct LbfgsParams {
 
 __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsParams L,
                                                   double* gamma, double* n_out, double* E_out,
-                                                  int* info) {
+                                                  int* info, OccBatch ib) {
   __shared__ double red[OT];
+  if (!to_instance(P, w, ib)) return;
+  {
+    const long long i = blockIdx.x;
+    gamma += i * ib.gamma;
+    if (n_out) n_out += i * ib.n;
+    if (E_out) E_out += i;
+    if (info) info += 3 * i;
+  }
   if (!setup(P, w, info, red)) return;
   const int tid = threadIdx.x;
   const int nv = P.ns * P.ng;
@@ -450,11 +503,12 @@ OccProblem make_problem(int norb, int ns, int ng, const int* members, int map, i
   return P;
 }
 
-int build_M(int norb, const double* J, const double* K, double* M, hipStream_t st) {
+int build_M(int norb, const double* J, const double* K, double* M, hipStream_t st, int ninst = 1,
+            long long jk = 0, long long wsb = 0) {
   const long long n2 = (long long)norb * norb;
   long long g = (n2 + 255) / 256;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_build_M, dim3((unsigned)g), dim3(256), 0, st, n2, J, K, M);
+  hipLaunchKernelGGL(k_build_M, dim3((unsigned)g, ninst), dim3(256), 0, st, n2, J, K, M, jk, wsb);
   return launch_status();
 }
 
@@ -470,7 +524,8 @@ int occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int f
   int rc = build_M(norb, J, K, w.M, st);
   if (rc != NOF_OK) return rc;
   OccProblem P = make_problem(norb, ns, ng, members, map, func, hdiag, hstride, J, K, w);
-  hipLaunchKernelGGL(k_occ_eval, dim3(1), dim3(OT), 0, st, P, w, gamma, n, E, dEdgamma, info);
+  hipLaunchKernelGGL(k_occ_eval, dim3(1), dim3(OT), 0, st, P, w, gamma, n, E, dEdgamma, info,
+                     OccBatch{});
   return launch_status();
 }
 
@@ -485,7 +540,32 @@ int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func
   LbfgsParams L;
   L.maxit = maxit; L.maxbt = 50; L.tol = tol; L.etol = 1e-14; L.loose = 1e-5; L.c1 = 1e-4;
   L.step0 = 0.1;
-  hipLaunchKernelGGL(k_occ_lbfgs, dim3(1), dim3(OT), 0, st, P, w, L, gamma, n, E, info);
+  hipLaunchKernelGGL(k_occ_lbfgs, dim3(1), dim3(OT), 0, st, P, w, L, gamma, n, E, info,
+                     OccBatch{});
+  return launch_status();
+}
+
+size_t occ_ws_stride(int norb, int ns, int ng) { return align256(occ_layout(norb, ns, ng).total); }
+
+int occ_batched(int ninst, const int* active, int norb, int ns, int ng, const int* members, int map,
+                int func, const double* hdiag, int hstride, long long hinst, const double* J,
+                const double* K, long long jkinst, double* gamma, double* n, double* E, int* info,
+                int maxit, double tol, void* ws, hipStream_t st) {
+  const size_t wsb = occ_ws_stride(norb, ns, ng);
+  OccWs w = occ_ws_ptrs(ws, norb, ns, ng);
+  int rc = build_M(norb, J, K, w.M, st, ninst, jkinst, (long long)wsb);
+  if (rc != NOF_OK) return rc;
+  OccProblem P = make_problem(norb, ns, ng, members, map, func, hdiag, hstride, J, K, w);
+  const OccBatch ib{hinst, jkinst, (long long)ns * ng, norb, (long long)wsb, active};
+  if (maxit > 0) {
+    LbfgsParams L;
+    L.maxit = maxit; L.maxbt = 50; L.tol = tol; L.etol = 1e-14; L.loose = 1e-5; L.c1 = 1e-4;
+    L.step0 = 0.1;
+    hipLaunchKernelGGL(k_occ_lbfgs, dim3(ninst), dim3(OT), 0, st, P, w, L, gamma, n, E, info, ib);
+  } else {
+    hipLaunchKernelGGL(k_occ_eval, dim3(ninst), dim3(OT), 0, st, P, w, gamma, n, E,
+                       (double*)nullptr, info, ib);
+  }
   return launch_status();
 }
 

@@ -30,10 +30,13 @@ struct ExpmScratch {
 
 // ||y||_F (a sub-multiplicative norm, so the Taylor truncation bound holds for
 // it) -> scaling power s with ||y||_F / 2^s <= 1/4.
+// Instance blockIdx.x: y + i*n2 -> sc[i].
 __global__ __launch_bounds__(1024) void k_norm_scale(int norb, const double* __restrict__ y,
                                                      ExpmScratch* __restrict__ sc) {
   __shared__ double red[1024];
   const long long n2 = (long long)norb * norb;
+  y += blockIdx.x * n2;
+  sc += blockIdx.x;
   double a = 0.0;
   for (long long i = threadIdx.x; i < n2; i += 1024) a = fma(y[i], y[i], a);
   red[threadIdx.x] = a;
@@ -52,15 +55,19 @@ __global__ __launch_bounds__(1024) void k_norm_scale(int norb, const double* __r
   }
 }
 
-// out = diag_c * I + coef * sum_c part[c]   (fixed summation order);
-// coef = coef_mul * sc->scale when sc is given.  If pred is given the kernel
-// runs only when *pred > pred_gt.
+// Instance i = blockIdx.y: out_i = diag_c * I + coef * sum_c part_i[c] (fixed
+// summation order), part_i = part + i*pinst, out_i = out + i*oinst;
+// coef = coef_mul * sc[i].scale when sc is given.  With pred_sc the kernel
+// runs only when pred_sc[i].s > pred_gt.
 __global__ void k_combine(int rows, int cols, const double* __restrict__ part, int nparts,
                           long long stride, double diag_c, double coef_mul,
-                          const ExpmScratch* __restrict__ sc, const int* __restrict__ pred,
-                          int pred_gt, double* __restrict__ out) {
-  if (pred && *pred <= pred_gt) return;
-  const double coef = sc ? coef_mul * sc->scale : coef_mul;
+                          const ExpmScratch* __restrict__ sc, const ExpmScratch* __restrict__ pred_sc,
+                          int pred_gt, double* __restrict__ out, long long pinst, long long oinst) {
+  const int y = blockIdx.y;
+  if (pred_sc && pred_sc[y].s <= pred_gt) return;
+  part += y * pinst;
+  out += y * oinst;
+  const double coef = sc ? coef_mul * sc[y].scale : coef_mul;
   const long long n = (long long)rows * cols;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -71,11 +78,14 @@ __global__ void k_combine(int rows, int cols, const double* __restrict__ part, i
   }
 }
 
-// U = buffer holding the result after s squarings (ping-pong parity)
+// U_i = buffer holding instance i's result after s_i squarings (ping-pong
+// parity); A and B at instance stride ab, U at norb^2.
 __global__ void k_select(int norb, const double* __restrict__ A, const double* __restrict__ B,
-                         const ExpmScratch* __restrict__ sc, double* __restrict__ U) {
-  const double* src = (sc->s & 1) ? B : A;
+                         long long ab, const ExpmScratch* __restrict__ sc, double* __restrict__ U) {
   const long long n2 = (long long)norb * norb;
+  const long long y = blockIdx.y;
+  const double* src = ((sc[y].s & 1) ? B : A) + y * ab;
+  U += y * n2;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x)
     U[i] = src[i];
@@ -114,89 +124,108 @@ int split_for(int rows, int cols, int K) {
   return ns;
 }
 
-// part[c] = sum over k in split c of X(k, m) Y(k, n); X given k-major or m-major.
-int gemm_split(int M, int N, int K, const double* X, bool x_kmajor, long long ldx, const double* Y,
-               long long ldy, double* part, int nsplit, const int* pred, int pred_gt,
-               hipStream_t st) {
+// part_i[c] = sum over k in split c of X_i(k, m) Y_i(k, n) for instances
+// i < ninst (X_i = X + i*xinst, Y_i = Y + i*yinst, part_i = part + i*nsplit*M*N);
+// X given k-major or m-major.  With pred_sc, instance i runs only when
+// pred_sc[i].s > pred_gt.
+int gemm_split(int ninst, int M, int N, int K, const double* X, bool x_kmajor, long long ldx,
+               long long xinst, const double* Y, long long ldy, long long yinst, double* part,
+               int nsplit, const ExpmScratch* pred_sc, int pred_gt, hipStream_t st) {
   const int kc = (K + nsplit - 1) / nsplit;
   GemmDesc g{};
   g.M = M; g.N = N; g.K = kc; g.Ktot = K;
-  g.batch = nsplit; g.fold = 1;
+  g.batch = ninst * nsplit; g.binner = nsplit; g.fold = 1;
   g.X = X; g.ldx = ldx; g.sx = x_kmajor ? (long long)kc * ldx : (long long)kc; g.x_kmajor = x_kmajor;
-  g.Y = Y; g.ldy = ldy; g.sy = (long long)kc * ldy;
-  g.Out = part; g.ldo = N; g.so = (long long)M * N;
-  g.pred = pred; g.pred_gt = pred_gt;
+  g.sx2 = xinst;
+  g.Y = Y; g.ldy = ldy; g.sy = (long long)kc * ldy; g.sy2 = yinst;
+  g.Out = part; g.ldo = N; g.so = (long long)M * N; g.so2 = (long long)nsplit * M * N;
+  if (pred_sc) {
+    g.pred = &pred_sc->s;
+    g.pred_so = (long long)(sizeof(ExpmScratch) / sizeof(int));
+    g.pred_gt = pred_gt;
+  }
   return gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
 }
 
-int combine(int rows, int cols, const double* part, int nparts, double diag_c, double coef_mul,
-            const ExpmScratch* sc, const int* pred, int pred_gt, double* out, hipStream_t st) {
+int combine(int ninst, int rows, int cols, const double* part, int nparts, double diag_c,
+            double coef_mul, const ExpmScratch* sc, const ExpmScratch* pred_sc, int pred_gt,
+            double* out, long long oinst, hipStream_t st) {
   const long long n = (long long)rows * cols;
-  hipLaunchKernelGGL(k_combine, dim3(grid_for(n, 256)), dim3(256), 0, st, rows, cols, part, nparts,
-                     n, diag_c, coef_mul, sc, pred, pred_gt, out);
+  hipLaunchKernelGGL(k_combine, dim3(grid_for(n, 256), ninst), dim3(256), 0, st, rows, cols, part,
+                     nparts, n, diag_c, coef_mul, sc, pred_sc, pred_gt, out, (long long)nparts * n,
+                     oinst);
   return launch_status();
 }
 
 }  // namespace
 
-size_t expm_ws(int norb) {
+// Workspace of ninst simultaneous exponentials: scaling records, A and B
+// ping-pong buffers and split partials per instance.
+size_t expm_ws(int norb, int ninst) {
   const size_t n2 = align256((size_t)norb * norb * sizeof(double));
   const int ns = split_for(norb, norb, norb);
-  return align256(sizeof(ExpmScratch)) + 2 * n2 + (size_t)ns * n2;
+  return align256((size_t)ninst * sizeof(ExpmScratch)) + (size_t)ninst * (2 * n2 + (size_t)ns * n2);
 }
 
-size_t rotate_ws(int nbf, int norb) {
+size_t rotate_ws(int nbf, int norb, int ninst) {
   const int ns = split_for(nbf, norb, norb);
-  return (size_t)ns * align256((size_t)nbf * norb * sizeof(double));
+  return (size_t)ninst * ns * align256((size_t)nbf * norb * sizeof(double));
 }
 
+// Cout_i = C_i U_i for i < ninst (C, Cout stride nbf*norb, U stride norb^2).
 int rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout, void* ws,
-                    hipStream_t st) {
+                    hipStream_t st, int ninst) {
   const int ns = split_for(nbf, norb, norb);
   double* part = (double*)ws;
+  const long long cs = (long long)nbf * norb, n2 = (long long)norb * norb;
   // Cout[mu][p] = sum_q C[mu][q] U[q][p]: X(k=q, m=mu) = C[mu][q] (m-major)
-  int rc = gemm_split(nbf, norb, norb, C, false, norb, U, norb, part, ns, nullptr, 0, st);
+  int rc = gemm_split(ninst, nbf, norb, norb, C, false, norb, cs, U, norb, n2, part, ns, nullptr, 0,
+                      st);
   if (rc != NOF_OK) return rc;
-  return combine(nbf, norb, part, ns, 0.0, 1.0, nullptr, nullptr, 0, Cout, st);
+  return combine(ninst, nbf, norb, part, ns, 0.0, 1.0, nullptr, nullptr, 0, Cout, cs, st);
 }
 
-int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st) {
+// U_i = exp(y_i) for i < ninst (y, U stride norb^2); each instance takes its
+// own scaling power, so its result does not depend on the other instances.
+int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st, int ninst) {
   char* w = (char*)ws;
   ExpmScratch* sc = (ExpmScratch*)w;
   const size_t n2b = align256((size_t)norb * norb * sizeof(double));
-  double* A = (double*)(w + align256(sizeof(ExpmScratch)));
-  double* Bm = (double*)((char*)A + n2b);
-  double* part = (double*)((char*)Bm + n2b);
+  const long long n2 = (long long)norb * norb;
+  const long long ab = (long long)(n2b / sizeof(double));   // instance stride of A and B
+  double* A = (double*)(w + align256((size_t)ninst * sizeof(ExpmScratch)));
+  double* Bm = A + (long long)ninst * ab;
+  double* part = Bm + (long long)ninst * ab;
   const int ns = split_for(norb, norb, norb);
-  hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(1024), 0, st, norb, y, sc);
+  hipLaunchKernelGGL(k_norm_scale, dim3(ninst), dim3(1024), 0, st, norb, y, sc);
   int rc = launch_status();
   if (rc != NOF_OK) return rc;
   // Horner with x = y / 2^s:  R_12 = I + x/12,  R_k = I + (x/k) R_{k+1}.
   // y^T = -y, so x R = -(2^-s) y^T R and y^T R is a k-major product.
-  // First step: R_12 = I - (2^-s/12) y^T I = I + x/12 computed as a product too.
-  hipLaunchKernelGGL(k_combine, dim3(grid_for((long long)norb * norb, 256)), dim3(256), 0, st, norb,
-                     norb, y, 1, 0LL, 1.0, 1.0 / kTaylor, sc, nullptr, 0, A);
+  // First step: R_12 = I + (2^-s/12) y (a combine of y itself).
+  hipLaunchKernelGGL(k_combine, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, norb, y, 1,
+                     0LL, 1.0, 1.0 / kTaylor, sc, nullptr, 0, A, n2, ab);
   rc = launch_status();
   if (rc != NOF_OK) return rc;
   for (int k = kTaylor - 1; k >= 1; --k) {
-    rc = gemm_split(norb, norb, norb, y, true, norb, A, norb, part, ns, nullptr, 0, st);
+    rc = gemm_split(ninst, norb, norb, norb, y, true, norb, n2, A, norb, ab, part, ns, nullptr, 0, st);
     if (rc != NOF_OK) return rc;
-    rc = combine(norb, norb, part, ns, 1.0, -1.0 / k, sc, nullptr, 0, A, st);
+    rc = combine(ninst, norb, norb, part, ns, 1.0, -1.0 / k, sc, nullptr, 0, A, ab, st);
     if (rc != NOF_OK) return rc;
   }
-  // squarings i = 0 .. s-1, ping-pong A -> B -> A ...
+  // squarings i = 0 .. s-1, ping-pong A -> B -> A ... (instances with s <= i skip)
   double* cur = A;
   double* nxt = Bm;
   for (int i = 0; i < kMaxSquare; ++i) {
     // nxt = cur cur: X(k, m) = cur[m][k] (m-major)
-    rc = gemm_split(norb, norb, norb, cur, false, norb, cur, norb, part, ns, &sc->s, i, st);
+    rc = gemm_split(ninst, norb, norb, norb, cur, false, norb, ab, cur, norb, ab, part, ns, sc, i, st);
     if (rc != NOF_OK) return rc;
-    rc = combine(norb, norb, part, ns, 0.0, 1.0, nullptr, &sc->s, i, nxt, st);
+    rc = combine(ninst, norb, norb, part, ns, 0.0, 1.0, nullptr, sc, i, nxt, ab, st);
     if (rc != NOF_OK) return rc;
     double* t = cur; cur = nxt; nxt = t;
   }
-  hipLaunchKernelGGL(k_select, dim3(grid_for((long long)norb * norb, 256)), dim3(256), 0, st, norb,
-                     A, Bm, sc, U);
+  hipLaunchKernelGGL(k_select, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, A, Bm, ab, sc,
+                     U);
   return launch_status();
 }
 
