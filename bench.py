@@ -53,6 +53,9 @@ def parse():
                     help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--batched", type=int, default=1,
                     help="1: also time the 25-instance finite-field batch (graph launch)")
+    ap.add_argument("--precision-workload", default="chain1000",
+                    help="also time FP64 against the x10 forms on this workload in a child run "
+                         "('' = skip)")
     ap.add_argument("--warmstart", type=int, default=0,
                     help="train the warm-start network on this many instances and evaluate it")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -262,6 +265,12 @@ def main():
     if args.cpu_slabs > 0:
         cpu = cpu_baseline(B_h, C0, H_h, n_h, w, args.cpu_slabs)
 
+    precision = None
+    if args.precision_workload and args.precision_workload != args.workload:
+        del B64
+        torch.cuda.empty_cache()
+        precision = run_precision_workload(args.precision_workload)
+
     line = {
         "metric": "JK+gen-Fock build ms/iter and TFLOP/s; BF16 vs FP64 on one GPU at |dE|<=1e-6 Eh",
         "value": value,
@@ -292,10 +301,31 @@ def main():
                                "exchange_fock_frac": flops["a6"] / (a6_ms * 1e-3) / 1e12 / PEAK["f64"]}},
         "forms": forms,
         "batched": batched,
+        "precision_workload": precision,
         "warmstart": warm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_precision_workload(name, steps=3, warmup=1):
+    """FP64 against the x10 forms (B as fixed-point planes of the FP64 B, and
+    FP32 B split in the loader) on another workload, in a child process of
+    this script (its inputs do not fit beside this run's)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", name, "--forms", "bf16x10,bf16x10f32",
+           "--batched", "0", "--cpu-slabs", "0", "--precision-workload", "", "--steps", str(steps),
+           "--warmup", str(warmup), "--traffic-file", ""]
+    print(f"# precision workload {name}: child run", file=sys.stderr, flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"workload": name, "error": f"child exited {r.returncode}", "stderr_tail": r.stderr[-400:]}
+    d = json.loads(lines[-1])
+    keep = ("ms_per_step", "speedup_vs_f64", "max_abs_dE_Eh", "max_abs_dJ", "max_abs_dK", "meets_dE_1e6")
+    return {"workload": d["config"]["workload"], "fp64_ms_per_step": d["ms_per_step"],
+            "E_fp64": d["E_last"], "steps": steps,
+            "forms": {k: {q: v[q] for q in keep} for k, v in d["forms"].items()}}
 
 
 def run_batched(nof, inputs, dev, steps=5):
