@@ -36,7 +36,8 @@ def algorithmic_flops(nbf, naux, norb):
     a2 = 1.0 * naux * nbf * norb * (norb + 1)          # b^P = C^T T^P, symmetric half
     a6 = 2.0 * naux * norb ** 3                        # exchange-type Fock contraction
     small = 6.0 * naux * norb * norb                   # J, K, W, F1
-    return dict(a1=a1, a2=a2, a6=a6, small=small, total=a1 + a2 + a6 + small)
+    dense = a1 + 2.0 * naux * nbf * norb * norb + a6   # the three products as dense GEMMs
+    return dict(a1=a1, a2=a2, a6=a6, small=small, total=a1 + a2 + a6 + small, dense=dense)
 
 
 def parse():
@@ -184,7 +185,9 @@ def main():
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(stop)
         seg = np.array([[ev[i].elapsed_time(ev[i + 1]) for i in range(nev - 1)] for ev in evs])
+        per_step = [ev[0].elapsed_time(ev[nev - 1]) for ev in evs]
         res = dict(ms_per_step=total_ms / steps, seg_ms=seg.mean(axis=0).tolist(),
+                   step_median_ms=float(np.median(per_step)), step_min_ms=float(np.min(per_step)),
                    E=[float(x) for x in Es], J=J.clone(), K=out["K"].clone(),
                    lam=out["lam"].clone(), g=out["g"].clone())
         # the exchange-type Fock kernel alone (inside nof_gen_fock above), same
@@ -199,6 +202,16 @@ def main():
         ex[1].record()
         torch.cuda.synchronize()
         res["exchange_ms"] = ex[0].elapsed_time(ex[1]) / steps
+        # the K pass alone (A4: one HBM pass over the unique half of b + the
+        # fixed-order reduction of its chunk partials)
+        Kk = torch.empty_like(Z)
+        nof.jk_diag(b, D, want_J=False, want_K=True, K=Kk, ws=ws_j)
+        ex[0].record()
+        for _ in range(steps):
+            nof.jk_diag(b, D, want_J=False, want_K=True, K=Kk, ws=ws_j)
+        ex[1].record()
+        torch.cuda.synchronize()
+        res["k_pass_ms"] = ex[0].elapsed_time(ex[1]) / steps
         del T, b, ws_x
         torch.cuda.empty_cache()
         return res
@@ -289,7 +302,15 @@ def main():
                                f"{w.nstrong} strong orbitals x {w.ng} weak partners",
                    "nbf": nbf, "naux": naux, "norb": norb, "seed": w.seed},
         "E_last": r64["E"][-1],
+        "ms_per_step_median": r64["step_median_ms"],
+        "ms_per_step_min": r64["step_min_ms"],
         "algorithmic_flops_per_step": flops["total"],
+        "tflops_dense_equivalent": flops["dense"] / (ms * 1e-3) / 1e12,
+        "k_pass": {"ms": r64["k_pass_ms"],
+                   "bytes": 8.0 * naux * norb * (norb + 1) / 2,
+                   "gbs": 8.0 * naux * norb * (norb + 1) / 2 / (r64["k_pass_ms"] * 1e-3) / 1e9,
+                   "frac_of_8tbs": 8.0 * naux * norb * (norb + 1) / 2 / (r64["k_pass_ms"] * 1e-3) / 1e9
+                   / HBM_PEAK_GBS},
         "stage_ms": dict(zip(seg_names, r64["seg_ms"])),
         "roofline": {"bound": "mfma", "kernel": dom["name"],
                      "achieved": dom_tf, "peak": PEAK["f64"], "unit": "TFLOP/s",
@@ -465,9 +486,22 @@ def cpu_baseline(B_h, C0, H_h, n_h, w, slabs):
     dfjk.iteration(Bs, C0, H_h, n_h, cJ, cK)
     dt = time.perf_counter() - t0
     f = algorithmic_flops(w.nbf, slabs, w.norb)["total"]
+    one = None
+    try:                                   # the same sample on one host core
+        from threadpoolctl import threadpool_limits
+        s1 = max(1, slabs // 8)
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            dfjk.iteration(B_h[:s1], C0, H_h, n_h, cJ, cK)
+            d1 = time.perf_counter() - t1
+        one = {"value": algorithmic_flops(w.nbf, s1, w.norb)["total"] / d1 / 1e12, "unit": "TFLOP/s",
+               "sample": f"{s1} slabs, {d1:.2f} s"}
+    except Exception:  # pragma: no cover
+        pass
     return {"value": f / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{slabs} of {w.naux} auxiliary slabs of {w.name}, one iteration, "
-                      f"{dt:.2f} s; full-iteration estimate {dt * w.naux / slabs:.1f} s"}
+                      f"{dt:.2f} s; full-iteration estimate {dt * w.naux / slabs:.1f} s",
+            "one_core": one}
 
 
 if __name__ == "__main__":
