@@ -113,3 +113,27 @@ def test_field_workload_fp32_against_oracle():
         print("field instance", i, "dE", float(E[i]) - o["E"], flush=True)
         assert abs(float(E[i]) - o["E"]) <= 1e-7 * abs(o["E"])
         assert normwise(host(lam[i]), o["lam"]) <= 2e-6
+
+
+@pytest.mark.parametrize("prec_name", ["f64", "f32"])
+def test_batch_odd_norb_default_and_fold1(prec_name):
+    """Odd Norb (the pass takes its unaligned-pair path), three instances, the
+    plan's default split and one P per exchange group, against the
+    single-instance entry points."""
+    nof = need_gpu()
+    ninst, nbf, naux, norb = 3, 40, 20, 37
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3003, 9)
+    tdt = torch.float64 if prec_name == "f64" else torch.float32
+    prec = nof.P_F64 if prec_name == "f64" else nof.P_F32
+    Bd = dev(B, tdt)
+    plan = nof.BatchPlan(Bd, dev(C), dev(H), dev(n), dev(cJ), dev(cK), prec=prec)
+    ref = [single(nof, Bd, C[i], H[i], n[i], cJ[i], cK[i], prec) for i in range(ninst)]
+    tol = 1e-12 if prec_name == "f64" else 2e-6
+    for cfg in (None, [64, 64, 64, naux]):
+        if cfg is not None:
+            plan.config = cfg
+        E, lam, g = plan.iteration()
+        torch.cuda.synchronize()
+        for i in range(ninst):
+            assert abs(float(E[i]) - ref[i][0]) <= tol * abs(ref[i][0]), (cfg, i)
+            assert normwise(host(lam[i]), ref[i][1]) <= tol, (cfg, i)

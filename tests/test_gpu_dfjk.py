@@ -128,3 +128,38 @@ def test_fp32_form(nbf, naux, norb, seed):
     for k in ("b", "J", "K", "lam"):
         assert errs[k] <= 2e-6, (k, errs[k])
     assert errs["E"] <= 1e-6
+
+
+PASS_SHAPES = [(1, 1), (2, 3), (17, 5), (33, 127), (40, 130), (64, 257), (300, 64)]
+
+
+@pytest.mark.parametrize("naux,norb", PASS_SHAPES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_k_and_coulomb_pass_shapes(naux, norb, dt):
+    """The pass over the unique half of b (K and the Coulomb-type term F1) on
+    degenerate, odd (unaligned pairs) and ragged shapes, FP64 and FP32 b, fed
+    directly with symmetric slabs: K = sum_P b^2 and lambda = n h + F1 (cK = 0,
+    so F2 = 0) against the oracle on the same values, FP64 accumulation: 1e-13."""
+    nof = need_gpu()
+    print(f"case pass naux={naux} norb={norb} {dt}", flush=True)
+    rng = np.random.default_rng(naux * 1000 + norb)
+    b = rng.standard_normal((naux, norb, norb))
+    b = b + np.swapaxes(b, 1, 2)
+    if dt == "f32":
+        b = b.astype(np.float32).astype(np.float64)
+    D = np.ascontiguousarray(np.diagonal(b, axis1=1, axis2=2))
+    n = rng.uniform(0.0, 1.0, norb)
+    h = rng.standard_normal((norb, norb)); h = h + h.T
+    cJ = rng.standard_normal((norb, norb)); cJ = cJ + cJ.T
+    cK = np.zeros((norb, norb))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    prec = nof.P_F64 if dt == "f64" else nof.P_F32
+    bd = dev(b, tdt)
+    _, K = nof.jk_diag(bd, dev(D), want_J=False)
+    lam, g, K2 = nof.gen_fock(bd, dev(D), dev(n), dev(h), dev(cJ), dev(cK), want_K=True, prec=prec)
+    torch.cuda.synchronize()
+    Kref = np.einsum("Ppq,Ppq->pq", b, b)
+    lam_ref, _, _, _ = dfjk.gen_fock(b, n, h, cJ, cK)
+    assert normwise(host(K), Kref) <= 1e-13
+    assert np.array_equal(host(K), host(K2))
+    assert normwise(host(lam), lam_ref) <= 1e-13
