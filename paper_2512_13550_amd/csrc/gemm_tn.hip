@@ -110,6 +110,9 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   const bool xm_ok = XK ? (m0 + cx_t < d.M) : true;
   const bool yn_ok = n0 + cy_t < d.N;
   const int xk_t = tid & (KT - 1), xm_t = tid >> 4;
+  // on a diagonal tile of a symmetric product, a wave whose block lies wholly
+  // below the diagonal computes nothing that is written: it only loads
+  const bool lower_wave = d.sym && tm == tn && wm > wn;
 
   acc_t acc[FM][FN];
   d4v acc64[FLUSH64 ? FM : 1][FLUSH64 ? FN : 1];
@@ -178,6 +181,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   for (int s = 0; s < nstage; ++s) {
     const int buf = s & 1;
     if (s + 1 < nstage) load(s + 1);
+    if (!lower_wave)
 #pragma unroll
     for (int kk = 0; kk < KT / 4; ++kk) {
       TC a[FM], bv[FN];
