@@ -18,9 +18,12 @@ Pin status (what each function is checked against, in tests/test_oracle_*.py):
   dfjk.energy                 pinned: spin-orbital 2RDM brute force, closed-shell HF
   dfjk.gen_fock               pinned: finite-difference orbital gradient,
                               textbook AO closed-shell Fock matrix
-  functionals.pnof5_*         parity unpinned as a functional (its formulas are
+  functionals (pnof5, pnof7)  parity unpinned as functionals (their formulas are
                               cited out of the paper); the Delta/Pi -> cJ/cK
-                              mapping it feeds is pinned by the 2RDM brute force
+                              mapping they feed is pinned by the 2RDM brute force;
+                              PNOF7 also: equal to PNOF5 for one subspace and for
+                              0/1 occupations, exact interpair energy drop, finite
+                              differences of dE/dn
   occupations.*               pinned: sum rule, bounds, finite differences
   rotation.*                  pinned: orthogonality, closed forms
   mlp.*                       pinned: finite differences, hand-checked tiny net
