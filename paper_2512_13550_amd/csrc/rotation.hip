@@ -37,8 +37,21 @@ __global__ __launch_bounds__(1024) void k_norm_scale(int norb, const double* __r
   const long long n2 = (long long)norb * norb;
   y += blockIdx.x * n2;
   sc += blockIdx.x;
+  // eight independent partial sums keep eight loads in flight per thread
+  double acc[8] = {};
+  long long i = threadIdx.x;
+  for (; i + 7 * 1024 < n2; i += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = y[i + u * 1024];
+    __builtin_amdgcn_sched_barrier(0);    // every load issued before any is used
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = fma(v[u], v[u], acc[u]);
+  }
+  for (; i < n2; i += 1024) acc[0] = fma(y[i], y[i], acc[0]);
   double a = 0.0;
-  for (long long i = threadIdx.x; i < n2; i += 1024) a = fma(y[i], y[i], a);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a += acc[u];
   red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
