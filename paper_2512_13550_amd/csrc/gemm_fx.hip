@@ -423,6 +423,19 @@ __device__ __forceinline__ void split3(float v, __bf16 (&p)[3]) {
   p[2] = (__bf16)(r1 - (float)m);
 }
 
+// Raw operands of one stage of a lane: eight consecutive q of its X row, Y
+// row and St row, loaded as they are; the masks, the S scaling and the split
+// are applied when they are stored to LDS, so no instruction consumes a load
+// in the stage that issues it (the wait for it falls after that stage's
+// products).
+struct ExRaw {
+  float x[8], y[8], s[8];
+};
+
+// VEC: norb % 4 == 0 (rows 16-byte aligned): two float4 per row and stage, at
+// addresses clamped into the row (a column block past the end re-reads the
+// last four values, masked at the store).
+template <bool VEC>
 __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntiles) {
   __shared__ __attribute__((aligned(16))) __bf16 Xs[2][3][FT][KT];
   __shared__ __attribute__((aligned(16))) __bf16 Ys[2][3][FT][KT];
@@ -445,49 +458,47 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   const int c = tid >> 2, kq = tid & 3;       // row c of both tiles, k quarter kq
   const bool xok = m0 + c < n, yok = n0 + c < n;
   const int xrow = min(m0 + c, n - 1), yrow = min(n0 + c, n - 1);
-  const bool vec = (n % 4) == 0;              // rows 16-byte aligned
 
-  float xr[8], yr[8];
-  auto load = [&](int s) {
+  // first q of this lane's eight in stage s
+  auto qbase = [&](int s) { return (s % nkb) * KT + 8 * kq; };
+  auto load = [&](int s, ExRaw& r) {
     const int pb = p_lo + s / nkb;
-    const int k0 = (s - (pb - p_lo) * nkb) * KT + 8 * kq;
-    const int kl = n - k0;
+    const int k0 = qbase(s);
     const float* bp = d.b + (long long)pb * n * n;
     const float* px = bp + (long long)xrow * n;
     const float* py = bp + (long long)yrow * n;
     const float* ps = d.St + (long long)yrow * n;
-    if (vec && kl >= 8) {
+    if constexpr (VEC) {
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
-        const float4 fx = *(const float4*)(px + k0 + 4 * v);
-        const float4 fy = *(const float4*)(py + k0 + 4 * v);
-        const float4 fs = *(const float4*)(ps + k0 + 4 * v);
-        xr[4 * v] = fx.x; xr[4 * v + 1] = fx.y; xr[4 * v + 2] = fx.z; xr[4 * v + 3] = fx.w;
-        yr[4 * v] = fy.x * fs.x; yr[4 * v + 1] = fy.y * fs.y;
-        yr[4 * v + 2] = fy.z * fs.z; yr[4 * v + 3] = fy.w * fs.w;
+        const int k = min(k0 + 4 * v, n - 4);
+        const float4 fx = *(const float4*)(px + k);
+        const float4 fy = *(const float4*)(py + k);
+        const float4 fs = *(const float4*)(ps + k);
+        r.x[4 * v] = fx.x; r.x[4 * v + 1] = fx.y; r.x[4 * v + 2] = fx.z; r.x[4 * v + 3] = fx.w;
+        r.y[4 * v] = fy.x; r.y[4 * v + 1] = fy.y; r.y[4 * v + 2] = fy.z; r.y[4 * v + 3] = fy.w;
+        r.s[4 * v] = fs.x; r.s[4 * v + 1] = fs.y; r.s[4 * v + 2] = fs.z; r.s[4 * v + 3] = fs.w;
       }
     } else {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int k = min(k0 + j, n - 1);
-        const bool in = j < kl;
-        xr[j] = in ? px[k] : 0.f;
-        yr[j] = in ? py[k] * ps[k] : 0.f;
+        r.x[j] = px[k];
+        r.y[j] = py[k];
+        r.s[j] = ps[k];
       }
     }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      xr[j] = xok ? xr[j] : 0.f;
-      yr[j] = yok ? yr[j] : 0.f;
-    }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int s, const ExRaw& r, int buf) {
+    const int kl = n - qbase(s);
     bf8v px[3], py[3];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
+      const float xv = (xok && e < kl) ? r.x[e] : 0.f;
+      const float yv = (yok && e < kl) ? r.y[e] * r.s[e] : 0.f;
       __bf16 a[3], b[3];
-      split3(xr[e], a);
-      split3(yr[e], b);
+      split3(xv, a);
+      split3(yv, b);
 #pragma unroll
       for (int q = 0; q < 3; ++q) { px[q][e] = a[q]; py[q][e] = b[q]; }
     }
@@ -546,18 +557,29 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
     }
   };
 
+  // two stages in flight in registers: at stage s the registers of s (stored
+  // to LDS already) are refilled with stage s + 2, clamped to the last stage
+  // (the final loads repeat it and are stored to a buffer nobody reads)
+  const int last = nstage - 1;
+  ExRaw r0, r1;
   if (nstage > 0) {
-    load(0);
-    store(0);
+    load(0, r0);
+    load(min(1, last), r1);
+    store(0, r0, 0);
   }
   __syncthreads();
-  for (int s = 0; s < nstage; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nstage) load(s + 1);
-    compute(s, buf);
-    if (s + 1 < nstage) store(buf ^ 1);
+  int s = 0;
+  for (; s + 2 <= nstage; s += 2) {
+    load(min(s + 2, last), r0);
+    compute(s, 0);
+    store(s + 1, r1, 1);
+    __syncthreads();
+    load(min(s + 3, last), r1);
+    compute(s + 1, 1);
+    store(min(s + 2, last), r0, 0);
     __syncthreads();
   }
+  if (s < nstage) compute(s, 0);
 
   double* __restrict__ Out = d.Out + (long long)grp * n * n;
 #pragma unroll
@@ -572,8 +594,9 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
       }
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(NTHR, 1) void k_exchange_fock_fx(ExDesc d, int tiles_n, int ntiles) {
-  exch_body(d, tiles_n, ntiles);
+  exch_body<VEC>(d, tiles_n, ntiles);
 }
 
 // St[s][q] = (float)S[q][s]
@@ -651,7 +674,10 @@ int exchange_fock_fx(const ExDesc& d0, const double* S, float* St, hipStream_t s
   const int groups = (d.naux + d.fold - 1) / d.fold;
   const long long G = (long long)ntiles * groups;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
-  hipLaunchKernelGGL(k_exchange_fock_fx, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
+  if (d.norb % 4 == 0)
+    hipLaunchKernelGGL(k_exchange_fock_fx<true>, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
+  else
+    hipLaunchKernelGGL(k_exchange_fock_fx<false>, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
   return launch_status();
 }
 
