@@ -126,15 +126,26 @@ inline int grid_for(long long n, int thr) {
   return (int)g;
 }
 
-// Split-K plan for the small square products of this file.
-int split_for(int rows, int cols, int K) {
-  const int tiles = ((rows + 127) / 128) * ((cols + 127) / 128);
-  int ns = (384 + tiles - 1) / tiles;
+// Split-K plan for the small products of this file: 128-wide tiles once
+// there are 64 of them (Norb >= ~1000), else 64-wide tiles, and enough splits
+// of K for about 384 (128-wide) or 256 (64-wide) workgroups.  At Norb = 500
+// the 64-wide plan (4 splits) takes exp(y) from 0.56 to 0.35 ms against 128-wide
+// tiles with 24 splits, whose partials (2 MB each) dominate; at Norb = 1000 the
+// 128-wide plan is faster (1.14 vs 1.28 ms).
+struct SplitPlan {
+  int tile, ns;
+};
+SplitPlan split_for(int rows, int cols, int K) {
+  const int t128 = ((rows + 127) / 128) * ((cols + 127) / 128);
+  const int tile = t128 >= 64 ? 128 : 64;
+  const int tiles = tile == 128 ? t128 : ((rows + 63) / 64) * ((cols + 63) / 64);
+  const int target = tile == 128 ? 384 : 256;
+  int ns = (target + tiles - 1) / tiles;
   const int maxs = (K + 15) / 16;          // at least one 16-deep stage per split
   if (ns > maxs) ns = maxs;
   if (ns > 32) ns = 32;
   if (ns < 1) ns = 1;
-  return ns;
+  return {tile, ns};
 }
 
 // part_i[c] = sum over k in split c of X_i(k, m) Y_i(k, n) for instances
@@ -143,10 +154,12 @@ int split_for(int rows, int cols, int K) {
 // pred_sc[i].s > pred_gt.
 int gemm_split(int ninst, int M, int N, int K, const double* X, bool x_kmajor, long long ldx,
                long long xinst, const double* Y, long long ldy, long long yinst, double* part,
-               int nsplit, const ExpmScratch* pred_sc, int pred_gt, hipStream_t st) {
+               SplitPlan plan, const ExpmScratch* pred_sc, int pred_gt, hipStream_t st) {
+  const int nsplit = plan.ns;
   const int kc = (K + nsplit - 1) / nsplit;
   GemmDesc g{};
   g.M = M; g.N = N; g.K = kc; g.Ktot = K;
+  g.tile = plan.tile;
   g.batch = ninst * nsplit; g.binner = nsplit; g.fold = 1;
   g.X = X; g.ldx = ldx; g.sx = x_kmajor ? (long long)kc * ldx : (long long)kc; g.x_kmajor = x_kmajor;
   g.sx2 = xinst;
@@ -176,26 +189,26 @@ int combine(int ninst, int rows, int cols, const double* part, int nparts, doubl
 // ping-pong buffers and split partials per instance.
 size_t expm_ws(int norb, int ninst) {
   const size_t n2 = align256((size_t)norb * norb * sizeof(double));
-  const int ns = split_for(norb, norb, norb);
+  const int ns = split_for(norb, norb, norb).ns;
   return align256((size_t)ninst * sizeof(ExpmScratch)) + (size_t)ninst * (2 * n2 + (size_t)ns * n2);
 }
 
 size_t rotate_ws(int nbf, int norb, int ninst) {
-  const int ns = split_for(nbf, norb, norb);
+  const int ns = split_for(nbf, norb, norb).ns;
   return (size_t)ninst * ns * align256((size_t)nbf * norb * sizeof(double));
 }
 
 // Cout_i = C_i U_i for i < ninst (C, Cout stride nbf*norb, U stride norb^2).
 int rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout, void* ws,
                     hipStream_t st, int ninst) {
-  const int ns = split_for(nbf, norb, norb);
+  const SplitPlan plan = split_for(nbf, norb, norb);
   double* part = (double*)ws;
   const long long cs = (long long)nbf * norb, n2 = (long long)norb * norb;
   // Cout[mu][p] = sum_q C[mu][q] U[q][p]: X(k=q, m=mu) = C[mu][q] (m-major)
-  int rc = gemm_split(ninst, nbf, norb, norb, C, false, norb, cs, U, norb, n2, part, ns, nullptr, 0,
+  int rc = gemm_split(ninst, nbf, norb, norb, C, false, norb, cs, U, norb, n2, part, plan, nullptr, 0,
                       st);
   if (rc != NOF_OK) return rc;
-  return combine(ninst, nbf, norb, part, ns, 0.0, 1.0, nullptr, nullptr, 0, Cout, cs, st);
+  return combine(ninst, nbf, norb, part, plan.ns, 0.0, 1.0, nullptr, nullptr, 0, Cout, cs, st);
 }
 
 // U_i = exp(y_i) for i < ninst (y, U stride norb^2); each instance takes its
@@ -209,7 +222,8 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st,
   double* A = (double*)(w + align256((size_t)ninst * sizeof(ExpmScratch)));
   double* Bm = A + (long long)ninst * ab;
   double* part = Bm + (long long)ninst * ab;
-  const int ns = split_for(norb, norb, norb);
+  const SplitPlan plan = split_for(norb, norb, norb);
+  const int ns = plan.ns;
   hipLaunchKernelGGL(k_norm_scale, dim3(ninst), dim3(1024), 0, st, norb, y, sc);
   int rc = launch_status();
   if (rc != NOF_OK) return rc;
@@ -221,7 +235,7 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st,
   rc = launch_status();
   if (rc != NOF_OK) return rc;
   for (int k = kTaylor - 1; k >= 1; --k) {
-    rc = gemm_split(ninst, norb, norb, norb, y, true, norb, n2, A, norb, ab, part, ns, nullptr, 0, st);
+    rc = gemm_split(ninst, norb, norb, norb, y, true, norb, n2, A, norb, ab, part, plan, nullptr, 0, st);
     if (rc != NOF_OK) return rc;
     rc = combine(ninst, norb, norb, part, ns, 1.0, -1.0 / k, sc, nullptr, 0, A, ab, st);
     if (rc != NOF_OK) return rc;
@@ -231,7 +245,7 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st,
   double* nxt = Bm;
   for (int i = 0; i < kMaxSquare; ++i) {
     // nxt = cur cur: X(k, m) = cur[m][k] (m-major)
-    rc = gemm_split(ninst, norb, norb, norb, cur, false, norb, ab, cur, norb, ab, part, ns, sc, i, st);
+    rc = gemm_split(ninst, norb, norb, norb, cur, false, norb, ab, cur, norb, ab, part, plan, sc, i, st);
     if (rc != NOF_OK) return rc;
     rc = combine(ninst, norb, norb, part, ns, 0.0, 1.0, nullptr, sc, i, nxt, ab, st);
     if (rc != NOF_OK) return rc;
