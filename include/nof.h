@@ -124,7 +124,9 @@ int nof_split_B(int naux, int nbf, const void* B, int Bt, void* planes, size_t p
  *                          C once per call (three pieces for a BF16-stored B,
  *                          four with X10).
  * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C and
- *     the BF16 pieces of C).
+ *     the BF16 pieces of C; with X10 also the column maxima of B^P C that the
+ *     first stage writes as it stores them, which give the second stage the
+ *     grids of its split without another pass over B^P C).
  *
  * With naux = 1 and B = H (the AO one-electron matrix) this yields
  * h = C^T H C, the one-electron integrals of Eq. (Energy) in the NO basis.

@@ -116,6 +116,10 @@ const char* nof_status_str(int status) {
   }
 }
 
+}  // extern "C"
+
+namespace {
+
 // Bytes of the per-call scratch of one transform stage: the BF16 planes of C
 // and, for x10, the grid exponents of the operand split in the loader.
 size_t fx_planes_bytes(int nbf, int norb) { return align256((size_t)4 * norb * presplit_ldk(nbf) * 2); }
@@ -133,6 +137,60 @@ int split_C(int nbf, int norb, const double* C, int prec, int Bt, void* ws, hipS
   return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream);
 }
 
+// x10 stage 1 (T^P = B^P C) with the workspace w of one stage: C planes (one
+// grid per column), B planes or FP32 B with one grid per row (B^P symmetric:
+// row mu = column mu).  With cmax the epilogue also writes the column maxima
+// of T per row tile (the grids of the next stage's split).
+int fx_stage1(int naux, int nbf, int norb, const void* B, int Bt, const double* C, float* T, char* w,
+              unsigned* cmax, hipStream_t stream) {
+  const long long ldk = presplit_ldk(nbf);
+  int* ex = (int*)(w + fx_planes_bytes(nbf, norb));
+  NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
+  FxDesc f{};
+  f.M = nbf; f.N = norb; f.K = nbf; f.batch = naux;
+  const bool planes = Bt == NOF_BF16X4;
+  f.X = B;
+  if (planes) {
+    f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
+  } else {
+    NOF_TRY(fx_row_exps(B, Bt, (long long)naux * nbf, nbf, ex, stream));
+    f.ldx = nbf; f.sx = (long long)nbf * nbf; f.ex = ex; f.sex = nbf; f.x_rows = true;
+  }
+  f.Y = w; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk;
+  f.Out = T; f.ldo = norb; f.so = (long long)nbf * norb;
+  f.sym = false; f.role = 1;
+  f.cmax = cmax; f.scm = (long long)fx_tiles(nbf) * norb;
+  return gemm_fx(f, planes, true, stream);
+}
+
+// x10 stage 2 (b^P = C^T T^P and D): C planes, T split in the loader on one
+// grid per column q of T^P.  grids_ready: the grid exponents are already in
+// their slot of w (from the stage-1 column maxima); otherwise a pass over T
+// finds them.
+int fx_stage2(int naux, int nbf, int norb, const float* T, const double* C, float* b, double* D,
+              char* w, bool grids_ready, hipStream_t stream) {
+  const long long ldk = presplit_ldk(nbf);
+  int* ey = (int*)(w + fx_planes_bytes(nbf, norb));
+  NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
+  if (!grids_ready) NOF_TRY(fx_col_exps(T, naux, nbf, norb, (long long)nbf * norb, ey, stream));
+  FxDesc f{};
+  f.M = norb; f.N = norb; f.K = nbf; f.batch = naux;
+  f.X = w; f.ldx = ldk; f.sx = 0; f.psx = (long long)norb * ldk;
+  f.Y = T; f.ldy = norb; f.sy = (long long)nbf * norb; f.ey = ey; f.sey = norb;
+  f.Out = b; f.ldo = norb; f.so = (long long)norb * norb;
+  f.Dg = D; f.sd = norb; f.sym = true; f.role = 2;
+  return gemm_fx(f, true, false, stream);
+}
+
+// Column maxima of T per row tile (x10, nof_mo_transform only).
+size_t fx_cmax_bytes(int naux, int nbf, int norb) {
+  return align256((size_t)naux * fx_tiles(nbf) * norb * sizeof(unsigned));
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t nof_mo_transform_stage_ws(int naux, int nbf, int norb, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb) || !prec_ok(prec)) return 0;
   // B may be given in FP32 or BF16: size for the larger of the two splits of C
@@ -142,7 +200,8 @@ size_t nof_mo_transform_stage_ws(int naux, int nbf, int norb, int prec) {
 size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt) || !b_input_ok(prec, Bt)) return 0;
-  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(naux, nbf, norb, prec, Bt);
+  return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(naux, nbf, norb, prec, Bt) +
+         (prec == NOF_P_BF16X10 ? fx_cmax_bytes(naux, nbf, norb) : 0);
 }
 
 size_t nof_split_B_bytes(int naux, int nbf) {
@@ -173,28 +232,8 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
     const bool bf = is_bf16_prec(prec);
     if (bf && (!ws || ws_bytes < stage_ws(naux, nbf, norb, prec, Bt))) return NOF_E_WORKSPACE;
-    if (prec == NOF_P_BF16X10) {
-      // fixed-point form: C planes (one grid per column), B planes or FP32 B
-      // with one grid per row (B^P symmetric: row mu = column mu)
-      const long long ldk = presplit_ldk(nbf);
-      char* w = (char*)ws;
-      int* ex = (int*)(w + fx_planes_bytes(nbf, norb));
-      NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
-      FxDesc f{};
-      f.M = nbf; f.N = norb; f.K = nbf; f.batch = naux;
-      const bool planes = Bt == NOF_BF16X4;
-      f.X = B;
-      if (planes) {
-        f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
-      } else {
-        NOF_TRY(fx_row_exps(B, Bt, (long long)naux * nbf, nbf, ex, stream));
-        f.ldx = nbf; f.sx = (long long)nbf * nbf; f.ex = ex; f.sex = nbf; f.x_rows = true;
-      }
-      f.Y = w; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk;
-      f.Out = (float*)T; f.ldo = norb; f.so = (long long)nbf * norb;
-      f.sym = false; f.role = 1;
-      return gemm_fx(f, planes, true, stream);
-    }
+    if (prec == NOF_P_BF16X10)
+      return fx_stage1(naux, nbf, norb, B, Bt, C, (float*)T, (char*)ws, nullptr, stream);
     // T^P[mu][q] = sum_nu B^P[nu][mu] C[nu][q]   (B^P symmetric)
     GemmDesc g1{};
     g1.M = nbf; g1.N = norb; g1.K = nbf; g1.Ktot = 0;
@@ -224,22 +263,8 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     const bool bf = is_bf16_prec(prec);
     if (bf && (!ws || ws_bytes < stage_ws(naux, nbf, norb, prec, NOF_F32))) return NOF_E_WORKSPACE;
-    if (prec == NOF_P_BF16X10) {
-      // fixed-point form: C planes, T split in the loader on one grid per
-      // column q of T^P (a pass over T finds them)
-      const long long ldk = presplit_ldk(nbf);
-      char* w = (char*)ws;
-      int* ey = (int*)(w + fx_planes_bytes(nbf, norb));
-      NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
-      NOF_TRY(fx_col_exps((const float*)T, naux, nbf, norb, (long long)nbf * norb, ey, stream));
-      FxDesc f{};
-      f.M = norb; f.N = norb; f.K = nbf; f.batch = naux;
-      f.X = w; f.ldx = ldk; f.sx = 0; f.psx = (long long)norb * ldk;
-      f.Y = T; f.ldy = norb; f.sy = (long long)nbf * norb; f.ey = ey; f.sey = norb;
-      f.Out = (float*)b; f.ldo = norb; f.so = (long long)norb * norb;
-      f.Dg = D; f.sd = norb; f.sym = true; f.role = 2;
-      return gemm_fx(f, true, false, stream);
-    }
+    if (prec == NOF_P_BF16X10)
+      return fx_stage2(naux, nbf, norb, (const float*)T, C, (float*)b, D, (char*)ws, false, stream);
     // b^P[p][q] = sum_mu C[mu][p] T^P[mu][q], upper tiles + mirror, D
     GemmDesc g2{};
     g2.M = norb; g2.N = norb; g2.K = nbf; g2.Ktot = 0;
@@ -270,6 +295,16 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
     const size_t tbytes = align256((size_t)naux * nbf * norb * dtype_size(bt));
     char* sws = (char*)ws + tbytes;
+    if (prec == NOF_P_BF16X10) {
+      // T, the stage scratch, then the column maxima of T that the stage-1
+      // epilogue writes: they give stage 2 its grids without a pass over T
+      unsigned* cmax = (unsigned*)(sws + stage_ws(naux, nbf, norb, prec, Bt));
+      float* T = (float*)ws;
+      NOF_TRY(fx_stage1(naux, nbf, norb, B, Bt, C, T, sws, cmax, stream));
+      NOF_TRY(fx_cmax_exps(cmax, naux, fx_tiles(nbf), norb, (int*)(sws + fx_planes_bytes(nbf, norb)),
+                           stream));
+      return fx_stage2(naux, nbf, norb, T, C, (float*)b, D, sws, true, stream);
+    }
     const size_t sbytes = ws_bytes - tbytes;
     NOF_TRY(nof_mo_transform_stage1(naux, nbf, norb, B, Bt, C, ws, bt, prec, sws, sbytes, stream));
     return nof_mo_transform_stage2(naux, nbf, norb, ws, bt, C, b, bt, D, prec, sws, sbytes, stream);
@@ -314,6 +349,10 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, doub
   });
 }
 
+}  // extern "C"
+
+namespace {
+
 // F2 (exchange-type term) into F2 from the partials in f2part (groups of
 // L.f2fold slabs); St: norb*norb FP32 scratch of the split forms.
 int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, int prec,
@@ -337,6 +376,10 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, i
   }
   return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
 }
+
+}  // namespace
+
+extern "C" {
 
 size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
@@ -469,6 +512,8 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
   });
 }
 
+}  // extern "C"
+
 namespace {
 bool occ_args_ok(int norb, int ns, int ng, int map, int func) {
   if (!dim_ok(norb) || ns < 1 || ng < 1 || (long long)ns * (ng + 1) > norb) return false;
@@ -477,6 +522,8 @@ bool occ_args_ok(int norb, int ns, int ng, int map, int func) {
   return true;
 }
 }  // namespace
+
+extern "C" {
 
 size_t nof_occ_ws(int norb, int ns, int ng) {
   if (!dim_ok(norb) || ns < 1 || ng < 1 || (long long)ns * (ng + 1) > norb) return 0;

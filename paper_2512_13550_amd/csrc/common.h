@@ -93,8 +93,13 @@ struct FxDesc {
   bool sym;
   int role;                        // 1 = transform stage 1, 2 = stage 2 (kernel symbol)
   bool x_rows;                     // FP32 X symmetric per batch: may be read m-major (rows)
+  unsigned* cmax; long long scm;   // optional: per row tile t the FP32 bits of max_m |Out_b[m][n]|
+                                   // over the tile's rows -> cmax[b*scm + t*N + n] (not sym)
 };
 int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
+// Column grid exponents e[b*N + n] from the row-tile maxima above.
+int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st);
+inline int fx_tiles(int n) { return (n + 127) / 128; }
 // Exchange-type Fock partials of the split forms (gemm_fx.hip):
 //   Out[g][r][s] = sum_{P in [g*fold, (g+1)*fold)} sum_q b^P[q][r] S[q][s] b^P[q][s]
 // b FP32 [naux][norb][norb] symmetric slabs; S FP64 [norb][norb]; St a

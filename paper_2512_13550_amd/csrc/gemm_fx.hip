@@ -122,6 +122,22 @@ __global__ void k_col_exps(const float* __restrict__ A, int batch, int K, int N,
   }
 }
 
+// Grid exponents of the columns of T_b from the per-row-tile column maxima
+// that the stage-1 epilogue wrote: e[b*N + n] from max_t cmax[b][t][n].
+__global__ void k_cmax_exps(const unsigned* __restrict__ cmax, long long batch, int tiles, int N,
+                            int* __restrict__ e) {
+  const long long total = batch * N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / N;
+    const int n = (int)(i - b * N);
+    const unsigned* c = cmax + b * tiles * N + n;
+    unsigned m = 0;
+    for (int t = 0; t < tiles; ++t) m = max(m, c[(long long)t * N]);
+    e[i] = grid_exp_bits(m);
+  }
+}
+
 // Planes of the columns of an FP64 k-major matrix A[k][col] (k < K):
 // out[q][col][ldk], one grid per column.  Block: 16 columns; the column
 // maxima from 16 row groups, then each wave splits four columns with lanes
@@ -385,6 +401,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   }
 
   float* __restrict__ Out = d.Out + (long long)bb * d.so;
+  int cm[2] = {0, 0};      // bits of the largest |stored value| per column fragment
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -396,14 +413,30 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
         double v = (double)acc0[i][j][r] + (double)acc1[i][j][r];
         if (BIGK) v += acc64[BIGK ? i : 0][BIGK ? j : 0][r];
         if (gm >= d.M || gn >= d.N) continue;
+        const float fv = (float)v;
+        cm[j] = max(cm[j], (int)(__float_as_uint(fv) & 0x7fffffffu));
         if (!d.sym) {
-          Out[(long long)gm * d.ldo + gn] = (float)v;
+          Out[(long long)gm * d.ldo + gn] = fv;
         } else if (gm <= gn) {
-          Out[(long long)gm * d.ldo + gn] = (float)v;
-          Out[(long long)gn * d.ldo + gm] = (float)v;
+          Out[(long long)gm * d.ldo + gn] = fv;
+          Out[(long long)gn * d.ldo + gm] = fv;
           if (gm == gn && d.Dg) d.Dg[(long long)bb * d.sd + gm] = v;
         }
       }
+  if (d.cmax) {
+    // column maxima of this tile's stored values (its rows only): over the
+    // lane's rows, the four lane groups of a column, then the two row waves
+    __shared__ int cms[2][FT];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cm[j] = max(cm[j], __shfl_xor(cm[j], 16, 64));
+      cm[j] = max(cm[j], __shfl_xor(cm[j], 32, 64));
+      if (l < 16) cms[wm][wn * 32 + j * 16 + l] = cm[j];
+    }
+    __syncthreads();
+    if (tid < FT && n0 + tid < d.N)
+      d.cmax[(long long)bb * d.scm + (long long)tm * d.N + n0 + tid] = (unsigned)max(cms[0][tid], cms[1][tid]);
+  }
 }
 
 // Exchange-type generalized-Fock term of the split forms, on the tiling of
@@ -697,6 +730,13 @@ int fx_col_exps(const float* A, int batch, int K, int N, long long sa, int* e, h
   if (batch <= 0 || K <= 0 || N <= 0) return NOF_E_DIM;
   const unsigned g = (unsigned)grid_for((long long)batch * ((N + 63) / 64), 1);
   hipLaunchKernelGGL(k_col_exps, dim3(g), dim3(256), 0, st, A, batch, K, N, sa, e);
+  return launch_status();
+}
+
+int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st) {
+  if (batch <= 0 || tiles <= 0 || N <= 0) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_for((long long)batch * N, 256);
+  hipLaunchKernelGGL(k_cmax_exps, dim3(g), dim3(256), 0, st, cmax, (long long)batch, tiles, N, e);
   return launch_status();
 }
 

@@ -120,6 +120,28 @@ def test_bf16_x10_long_contraction():
         assert eb <= 3e-7 and eD <= 3e-7
 
 
+@pytest.mark.parametrize("nbf,naux,norb,seed", [(48, 192, 48, 0), (300, 40, 260, 1), (130, 7, 97, 5),
+                                               (1100, 3, 150, 9)])
+def test_bf16_x10_fused_grids_equal_two_stage(nbf, naux, norb, seed):
+    """nof_mo_transform (x10) takes the column grids of T from the maxima that
+    the first stage's epilogue writes per row tile; the two separate stage
+    calls find them with a pass over T.  Same grids, so b and D agree bit for
+    bit (row tiles: 1, 3, 2 and 9; ragged columns; K > 1024 in the last)."""
+    nof = need_gpu()
+    print(f"case bf16 x10 fused grids nbf={nbf} naux={naux} norb={norb}", flush=True)
+    B = inputs.make_B(seed, nbf, naux, 25.0).astype(np.float32)
+    Cd = dev(inputs.make_C(seed, nbf, norb))
+    for Bd in (dev(B, torch.float32), nof.SplitB(dev(B, torch.float32))):
+        b1, D1 = nof.mo_transform(Bd, Cd, prec=nof.P_BF16X10)
+        T = torch.empty((naux, nbf, norb), dtype=torch.float32, device="cuda")
+        nof.transform_stage1(Bd, Cd, T, prec=nof.P_BF16X10)
+        b2 = torch.empty_like(b1)
+        D2 = torch.empty_like(D1)
+        nof.transform_stage2(T, Cd, b2, D2, prec=nof.P_BF16X10)
+        torch.cuda.synchronize()
+        assert torch.equal(b1, b2) and torch.equal(D1, D2)
+
+
 def paired(rng, nrow, ncol, sign):
     """Rows 2k and 2k+1 equal (sign=+1) or opposite (sign=-1), entries with
     magnitudes spread over 2^-12..1."""
