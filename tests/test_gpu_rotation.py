@@ -11,7 +11,10 @@ from gpu_util import dev, host, need_gpu, normwise
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("norb,scale", [(48, 1e-2), (260, 0.3), (131, 30.0), (3, 2.0), (500, 1e-2)])
+# Norb below ~1000 runs the products on 64-wide tiles with a few K splits,
+# 1024 (64 tiles of 128) on 128-wide tiles with more splits: both plans here
+@pytest.mark.parametrize("norb,scale", [(48, 1e-2), (260, 0.3), (131, 30.0), (3, 2.0), (500, 1e-2),
+                                        (1024, 0.05)])
 def test_expm_and_rotate(norb, scale):
     nof = need_gpu()
     print(f"case expm norb={norb} scale={scale}", flush=True)
