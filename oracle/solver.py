@@ -14,6 +14,8 @@ One outer iteration:
      The sweep stops early once max|lambda - lambda^T| <= tol_lambda (the
      symmetry of the Lagrange multipliers at the minimum, monitored by
      NTHRESHL).
+  3. Orthonormality check of the orbitals after the sweep: max|C^T C - I|,
+     and one Newton-Schulz repair step when it exceeds tol_orth.
 The loop ends when a sweep ends on the symmetry criterion and the energy
 changed by at most tol_energy since the previous outer iteration (NTHRESHE),
 or after ``max_outer`` iterations.
@@ -32,8 +34,9 @@ from oracle import dfjk, functionals, occupations, rotation
 
 def solve(B, C, H, members, mapping, functional, gamma, max_outer=100, no_steps=30, lr=0.01,
           beta1=0.9, beta2=0.999, eps=1e-8, tol_lambda=1e-5, tol_energy=1e-9, on_maxit=2000,
-          on_tol=1e-8, history=None):
-    """Returns dict(C, gamma, n, E, asym, outer, no_steps, converged)."""
+          on_tol=1e-8, tol_orth=1e-10, history=None):
+    """Returns dict(C, gamma, n, E, asym, outer, no_steps, converged, orth);
+    orth is the largest max|C^T C - I| the checks found."""
     C = np.array(C, dtype=np.float64)
     gamma = np.array(gamma, dtype=np.float64)
     norb = C.shape[1]
@@ -44,6 +47,7 @@ def solve(B, C, H, members, mapping, functional, gamma, max_outer=100, no_steps=
     E_prev = None
     converged = False
     E = asym = None
+    orth = 0.0
     n = occupations.occupations(gamma, members, norb, mapping)
     for outer in range(max_outer):
         b, _ = dfjk.mo_transform(B, C)
@@ -67,6 +71,8 @@ def solve(B, C, H, members, mapping, functional, gamma, max_outer=100, no_steps=
             steps += 1
             y, m, v = rotation.adam_step(g, m, v, t_global, lr=lr, beta1=beta1, beta2=beta2, eps=eps)
             C = rotation.rotate(C, y)
+        C, err = rotation.orthonormalize(C, tol=tol_orth)
+        orth = max(orth, err)
         if history is not None:
             history.append((E, asym))
         if asym <= tol_lambda and E_prev is not None and abs(E - E_prev) <= tol_energy:
@@ -74,4 +80,4 @@ def solve(B, C, H, members, mapping, functional, gamma, max_outer=100, no_steps=
             break
         E_prev = E
     return dict(C=C, gamma=gamma, n=n, E=E, asym=asym, outer=outer + 1, no_steps=steps,
-                converged=converged)
+                converged=converged, orth=orth)

@@ -51,3 +51,47 @@ def test_adam_first_step_is_signed_lr():
     assert np.all(y.diagonal() == 0)
     assert np.array_equal(y, -y.T)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def spd(rng, n):
+    A = rng.standard_normal((n, n))
+    return A @ A.T / n + np.eye(n)
+
+
+def test_orthonormality_error_brute_force():
+    # E_pq = sum_mu,nu C_mu,p S_mu,nu C_nu,q - delta_pq, written out on a tiny case
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal((5, 3))
+    S = spd(rng, 5)
+    E = rotation.orthonormality_error(C, S)
+    for p in range(3):
+        for q in range(3):
+            ref = sum(C[mu, p] * S[mu, nu] * C[nu, q] for mu in range(5) for nu in range(5))
+            assert abs(E[p, q] - (ref - (p == q))) < 1e-13
+    assert np.array_equal(rotation.orthonormality_error(C), C.T @ C - np.eye(3))
+
+
+@pytest.mark.parametrize("with_S", [False, True])
+def test_newton_schulz_step_leaves_the_closed_form_error(with_S):
+    # C^T S C = I + E0 (E0 symmetric): after C (I - E0/2) the error is
+    # (I - E0/2)(I + E0)(I - E0/2) - I = -3/4 E0^2 + 1/4 E0^3
+    rng = np.random.default_rng(4)
+    nbf, norb = 9, 6
+    S = spd(rng, nbf) if with_S else None
+    L = np.linalg.cholesky(S) if with_S else np.eye(nbf)
+    Q = np.linalg.solve(L.T, np.linalg.qr(rng.standard_normal((nbf, norb)))[0])   # Q^T S Q = I
+    A = rng.standard_normal((norb, norb)) * 1e-3
+    C = Q @ (np.eye(norb) + A)
+    E0 = rotation.orthonormality_error(C, S)
+    C1, err = rotation.orthonormalize(C, S, tol=0.0)
+    assert err == float(np.max(np.abs(E0))) and err > 1e-4
+    E1 = rotation.orthonormality_error(C1, S)
+    assert np.max(np.abs(E1 - (-0.75 * E0 @ E0 + 0.25 * E0 @ E0 @ E0))) < 1e-14
+    assert np.max(np.abs(E1)) < 2 * err ** 2
+
+
+def test_orthonormalize_within_tolerance_returns_the_input():
+    rng = np.random.default_rng(5)
+    C = np.linalg.qr(rng.standard_normal((8, 5)))[0]
+    C2, err = rotation.orthonormalize(C, tol=1e-12)
+    assert err < 1e-15 and np.array_equal(C2, C)

@@ -58,6 +58,10 @@ def test_pnof5_converged_point_is_stationary(mapping):
     cJ, cK = functionals.coefficients(n, members, "pnof5")
     assert abs(dfjk.energy(n, h, J, K, cJ, cK) - E) <= 1e-12 * abs(E)
     assert E < hist[0][0]
+    # the orbitals stayed orthonormal to rounding over the whole run (the
+    # checks after each sweep saw no drift worth a repair)
+    assert r["orth"] <= 1e-13
+    assert np.max(np.abs(C.T @ C - np.eye(nbf))) <= 1e-13
     # re-optimising the occupations at the final orbitals gains nothing (the
     # last NO sweep follows the ON step, so the ON gradient is not exactly 0)
     _, _, E_on, _, _ = occupations.optimize_lbfgs(gamma, members, nbf, mapping, np.diag(h), J, K, "pnof5")
