@@ -253,6 +253,25 @@ int nof_expm_antisym(int norb, const double* y, double* U, void* ws, size_t ws_b
 size_t nof_rotate_orbitals_ws(int nbf, int norb);
 int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout,
                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Orthonormality check and repair of the NOs (Natural Orbital Optimization:
+ * the orbitals are orthonormal, the constraint whose multipliers are lambda;
+ * products of rotations keep it only up to rounding).
+ *   E = C^T S C - I,  err = max_pq |E_pq|  (a non-finite entry counts as +inf)
+ *   if err > tol:  C <- C (I - E/2)
+ * one Newton-Schulz step of the polar decomposition, after which the error is
+ * -3/4 E^2 + 1/4 E^3 (of order err^2).
+ * C    [nbf][norb] FP64, device, in/out (unchanged when err <= tol).
+ * S    [nbf][nbf] FP64 AO overlap, device, or NULL for an orthonormal AO basis.
+ * tol  >= 0 (else NOF_E_ARG).
+ * err  device FP64 scalar, out, may be NULL.
+ * ws   at least nof_orthonormalize_ws(nbf, norb) bytes.  Nothing is read back:
+ *      the repair runs predicated on the device-side check.
+ * Errors: NOF_E_DIM, NOF_E_NULL (C), NOF_E_ARG, NOF_E_WORKSPACE, NOF_E_HIP. */
+size_t nof_orthonormalize_ws(int nbf, int norb);
+int nof_orthonormalize(int nbf, int norb, double* C, const double* S, double tol, double* err,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
 int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double lr,
                   double beta1, double beta2, double eps, double* y, hipStream_t stream);
 
@@ -413,7 +432,9 @@ int nof_mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map,
  * when a sweep ended so and E changed by at most tol_energy since the
  * previous outer iteration (NTHRESHE's), or after max_outer iterations.  The
  * ADAM moments persist over the run (one step counter for the bias
- * correction).  The host reads E and max|lambda - lambda^T| once per step.
+ * correction).  After every sweep nof_orthonormalize checks C^T C = I and
+ * repairs C when max|C^T C - I| > tol_orth.  The host reads E and
+ * max|lambda - lambda^T| once per step and the check once per sweep.
  *
  * B, Bt, prec   as nof_mo_transform (NOF_P_F64, NOF_P_F32 or NOF_P_BF16X10;
  *               for X10, B in FP32 or as nof_split_B planes).
@@ -423,7 +444,7 @@ int nof_mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map,
  * gamma         [ns][ng] FP64, in/out.   n_out  [norb] FP64, may be NULL.
  * p             host parameters (typical: 100 outer, 30 steps, lr 0.01,
  *               0.9, 0.999, 1e-8, tol_lambda 1e-5, tol_energy 1e-9,
- *               on_maxit 2000, on_tol 1e-8).
+ *               on_maxit 2000, on_tol 1e-8, tol_orth 1e-10; tol_orth >= 0).
  * res           host result.  Errors: NOF_E_NULL, NOF_E_ARG, NOF_E_DIM,
  *               NOF_E_WORKSPACE, the status of a failing step (also in
  *               res->status), NOF_E_NOT_CONVERGED if E or the asymmetry
@@ -438,11 +459,14 @@ typedef struct {
   double tol_lambda, tol_energy;
   int on_maxit;
   double on_tol;
+  double tol_orth;
 } nof_solve_params;
 
+/* orth: the largest max|C^T C - I| that the checks after the sweeps found. */
 typedef struct {
   double E, asym;
   int outer, no_steps, on_iters, converged, status;
+  double orth;
 } nof_solve_result;
 
 size_t nof_solve_ws(int naux, int nbf, int norb, int ns, int ng, int Bt, int prec);

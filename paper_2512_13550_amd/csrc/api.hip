@@ -500,6 +500,22 @@ int nof_rotate_orbitals(int nbf, int norb, const double* C, const double* U, dou
   });
 }
 
+size_t nof_orthonormalize_ws(int nbf, int norb) {
+  if (!dim_ok(nbf) || !dim_ok(norb)) return 0;
+  return orth_ws(nbf, norb);
+}
+
+int nof_orthonormalize(int nbf, int norb, double* C, const double* S, double tol, double* err,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!C) return NOF_E_NULL;
+    if (!(tol >= 0.0)) return NOF_E_ARG;
+    if (!ws || ws_bytes < orth_ws(nbf, norb)) return NOF_E_WORKSPACE;
+    return orthonormalize(nbf, norb, C, S, tol, err, ws, stream);
+  });
+}
+
 int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
                   double beta2, double eps, double* y, hipStream_t stream) {
   return guarded([&]() -> int {

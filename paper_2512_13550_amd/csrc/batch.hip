@@ -318,7 +318,7 @@ unsigned grid_of(long long n) {
 
 // Workspace of the batched solve, after the plan's own.
 struct SolveLay {
-  size_t n, cJ, cK, lam, grad, m, v, y, U, Cn, E, Eon, asym, ctl, info, act, scr, scr_bytes, total;
+  size_t n, cJ, cK, lam, grad, m, v, y, U, Cn, E, Eon, asym, orth, ctl, info, act, scr, scr_bytes, total;
 };
 
 SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
@@ -340,12 +340,14 @@ SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
   L.E = take(ni * 8);
   L.Eon = take(ni * 8);
   L.asym = take(ni * 8);
+  L.orth = take(ni * 8);
   L.ctl = take(ni * 3 * 8);
   L.info = take(ni * 3 * sizeof(int));
   L.act = take(ni * sizeof(int));
   size_t s = expm_ws(p->norb, p->ninst);
   s = std::max(s, rotate_ws(p->nbf, p->norb, p->ninst));
   s = std::max(s, ni * occ_ws_stride(p->norb, ns, ng));   // all instances' ON steps at once
+  s = std::max(s, orth_ws(p->nbf, p->norb));
   L.scr_bytes = s;
   L.scr = take(s);
   L.total = o;
@@ -353,7 +355,7 @@ SolveLay solve_lay(const nof_plan_s* p, int ns, int ng) {
 }
 
 struct SolveBufs {
-  double *n, *cJ, *cK, *lam, *grad, *m, *v, *y, *U, *Cn, *E, *Eon, *asym, *ctl;
+  double *n, *cJ, *cK, *lam, *grad, *m, *v, *y, *U, *Cn, *E, *Eon, *asym, *orth, *ctl;
   int *info, *act;
   void* scr;
   size_t scr_bytes;
@@ -392,6 +394,7 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
   w.m = (double*)(ws + L.m); w.v = (double*)(ws + L.v); w.y = (double*)(ws + L.y);
   w.U = (double*)(ws + L.U); w.Cn = (double*)(ws + L.Cn);
   w.E = (double*)(ws + L.E); w.Eon = (double*)(ws + L.Eon); w.asym = (double*)(ws + L.asym);
+  w.orth = (double*)(ws + L.orth);
   w.ctl = (double*)(ws + L.ctl); w.info = (int*)(ws + L.info); w.act = (int*)(ws + L.act);
   w.scr = ws + L.scr; w.scr_bytes = L.scr_bytes;
   const Args a{B, C, H, w.n, w.cJ, w.cK, w.E, w.lam, w.grad, ws};
@@ -435,7 +438,7 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
   }
 
   std::vector<int> live(ni), sweep(ni), tstep(ni, 0), have_prev(ni, 0), hinfo(3 * ni);
-  std::vector<double> E_prev(ni, 0.0), hE(ni), hA(ni), ctl(3 * ni);
+  std::vector<double> E_prev(ni, 0.0), hE(ni), hA(ni), ctl(3 * ni), hO(ni);
   int failed_status = NOF_OK;
   for (int i = 0; i < ni; ++i) live[i] = 1;
   auto sync = [&]() { return hipStreamSynchronize(st) == hipSuccess ? NOF_OK : NOF_E_HIP; };
@@ -506,8 +509,20 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
         }
       }
     }
+    // orthonormality of each running instance's orbitals after the sweep,
+    // repaired past tol_orth
+    const long long cs = (long long)p->nbf * p->norb;
     for (int i = 0; i < ni; ++i) {
       if (!live[i]) continue;
+      rc = orthonormalize(p->nbf, p->norb, C + i * cs, nullptr, prm->tol_orth, w.orth + i, w.scr, st);
+      if (rc != NOF_OK) return rc;
+    }
+    if (hipMemcpyAsync(hO.data(), w.orth, ni * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return NOF_E_HIP;
+    if ((rc = sync()) != NOF_OK) return rc;
+    for (int i = 0; i < ni; ++i) {
+      if (!live[i]) continue;
+      res[i].orth = std::max(res[i].orth, hO[i]);
       res[i].outer = outer + 1;
       if (res[i].asym <= prm->tol_lambda && have_prev[i] &&
           std::fabs(res[i].E - E_prev[i]) <= prm->tol_energy) {
@@ -720,7 +735,7 @@ int nof_plan_solve(nof_plan plan, const void* B, const double* H, double* C, int
     if (!B || !H || !C || !members || !gamma || !p || !res) return NOF_E_NULL;
     if (p->max_outer < 1 || p->no_steps < 1 || p->on_maxit < 0 || !(p->lr > 0.0) ||
         !(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
-        !(p->eps >= 0.0))
+        !(p->eps >= 0.0) || !(p->tol_orth >= 0.0))
       return NOF_E_ARG;
     const size_t need = nof_plan_solve_ws(plan, ns, ng);
     if (need == 0) return NOF_E_DIM;

@@ -171,6 +171,11 @@ size_t rotate_ws(int nbf, int norb, int ninst = 1);
 int rotate_orbitals(int nbf, int norb, const double* C, const double* U, double* Cout, void* ws,
                     hipStream_t st, int ninst = 1);
 int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st, int ninst = 1);
+// Orthonormality check and repair of C [nbf][norb] (S [nbf][nbf] or NULL):
+// err = max|C^T S C - I| (device, may be NULL); C <- C (I - E/2) when err > tol.
+size_t orth_ws(int nbf, int norb);
+int orthonormalize(int nbf, int norb, double* C, const double* S, double tol, double* err, void* ws,
+                   hipStream_t st);
 int adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,
               double beta2, double eps, double* y, hipStream_t st);
 

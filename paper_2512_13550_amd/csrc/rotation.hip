@@ -13,6 +13,8 @@
 // launches beyond s exit immediately.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace nof {
@@ -116,6 +118,37 @@ __global__ void k_adam(long long n2, const double* __restrict__ g, double* __res
     v[i] = vi;
     const double mh = mi / c1, vh = vi / c2;
     y[i] = -lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+// Orthonormality check of the orbitals: err = max|E| of E = C^T S C - I
+// (a non-finite entry counts as +inf), sc->s = (err > tol), sc->scale = err,
+// *err_out = err when given, and M = I - E/2 for the repair step.
+__global__ __launch_bounds__(1024) void k_orth_check(int norb, const double* __restrict__ E,
+                                                     double tol, double* __restrict__ M,
+                                                     ExpmScratch* __restrict__ sc,
+                                                     double* __restrict__ err_out) {
+  __shared__ double red[1024];
+  const long long n2 = (long long)norb * norb;
+  double m = 0.0;
+  for (long long i = threadIdx.x; i < n2; i += 1024) {
+    const double e = E[i];
+    const double a = fabs(e);
+    m = a <= 1.7976931348623157e308 ? fmax(m, a) : INFINITY;
+    const long long p = i / norb, q = i - p * norb;
+    M[i] = (p == q ? 1.0 : 0.0) - 0.5 * e;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sc->s = red[0] > tol ? 1 : 0;
+    sc->pad = 0;
+    sc->scale = red[0];
+    if (err_out) *err_out = red[0];
   }
 }
 
@@ -254,6 +287,56 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st,
   hipLaunchKernelGGL(k_select, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, A, Bm, ab, sc,
                      U);
   return launch_status();
+}
+
+// Workspace of orthonormalize: check record, E, M, S C, split partials.
+size_t orth_ws(int nbf, int norb) {
+  const size_t n2b = align256((size_t)norb * norb * sizeof(double));
+  const size_t cb = align256((size_t)nbf * norb * sizeof(double));
+  const size_t ng = (size_t)split_for(norb, norb, nbf).ns * n2b;
+  const size_t nc = (size_t)std::max(split_for(nbf, norb, norb).ns, split_for(nbf, norb, nbf).ns) * cb;
+  return 256 + 2 * n2b + cb + std::max(ng, nc);
+}
+
+// C <- C (I - E/2) when max|E| > tol, E = C^T S C - I (S NULL: identity);
+// *err (device, may be NULL) = max|E| before the repair.  Nothing is read
+// back: the repair launches are predicated on the check record.
+int orthonormalize(int nbf, int norb, double* C, const double* S, double tol, double* err, void* ws,
+                   hipStream_t st) {
+  char* w = (char*)ws;
+  const size_t n2b = align256((size_t)norb * norb * sizeof(double));
+  const size_t cb = align256((size_t)nbf * norb * sizeof(double));
+  ExpmScratch* sc = (ExpmScratch*)w;
+  double* E = (double*)(w + 256);
+  double* M = (double*)(w + 256 + n2b);
+  double* SC = (double*)(w + 256 + 2 * n2b);
+  double* part = (double*)(w + 256 + 2 * n2b + cb);
+  int rc;
+  const double* Y = C;
+  if (S) {
+    // SC[mu][p] = sum_nu S[mu][nu] C[nu][p]: X(k=nu, m=mu) = S[mu][nu] (m-major)
+    const SplitPlan ps = split_for(nbf, norb, nbf);
+    if ((rc = gemm_split(1, nbf, norb, nbf, S, false, nbf, 0, C, norb, 0, part, ps, nullptr, 0, st)) !=
+        NOF_OK)
+      return rc;
+    if ((rc = combine(1, nbf, norb, part, ps.ns, 0.0, 1.0, nullptr, nullptr, 0, SC, 0, st)) != NOF_OK)
+      return rc;
+    Y = SC;
+  }
+  // E[p][q] = sum_mu C[mu][p] Y[mu][q] - delta_pq: X(k=mu, m=p) = C[mu][p] (k-major)
+  const SplitPlan pg = split_for(norb, norb, nbf);
+  if ((rc = gemm_split(1, norb, norb, nbf, C, true, norb, 0, Y, norb, 0, part, pg, nullptr, 0, st)) !=
+      NOF_OK)
+    return rc;
+  if ((rc = combine(1, norb, norb, part, pg.ns, -1.0, 1.0, nullptr, nullptr, 0, E, 0, st)) != NOF_OK)
+    return rc;
+  hipLaunchKernelGGL(k_orth_check, dim3(1), dim3(1024), 0, st, norb, E, tol, M, sc, err);
+  if ((rc = launch_status()) != NOF_OK) return rc;
+  // C <- C M, both launches predicated on sc->s: X(k=q, m=mu) = C[mu][q] (m-major)
+  const SplitPlan pc = split_for(nbf, norb, norb);
+  if ((rc = gemm_split(1, nbf, norb, norb, C, false, norb, 0, M, norb, 0, part, pc, sc, 0, st)) != NOF_OK)
+    return rc;
+  return combine(1, nbf, norb, part, pc.ns, 0.0, 1.0, nullptr, sc, 0, C, 0, st);
 }
 
 int adam_step(int norb, const double* g, double* m, double* v, int t, double lr, double beta1,

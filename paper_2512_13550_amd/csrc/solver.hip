@@ -66,7 +66,7 @@ SolveLayout solve_layout(int naux, int nbf, int norb, int ns, int ng, int Bt, in
   L.U = o;   o += a256(n2);
   L.Cn = o;  o += a256((size_t)nbf * norb * sizeof(double));
   L.n = o;   o += a256((size_t)norb * sizeof(double));
-  L.scal = o; o += 256;                      // E, E_on, asym
+  L.scal = o; o += 256;                      // E, E_on, asym, orthonormality error
   L.info = o; o += 256;                      // ON info
   L.scratch = o;
   size_t s = 0;
@@ -77,6 +77,7 @@ SolveLayout solve_layout(int naux, int nbf, int norb, int ns, int ng, int Bt, in
   s = std::max(s, nof_expm_antisym_ws(norb));
   s = std::max(s, nof_rotate_orbitals_ws(nbf, norb));
   s = std::max(s, nof_occ_ws(norb, ns, ng));
+  s = std::max(s, nof_orthonormalize_ws(nbf, norb));
   L.total = L.scratch + a256(s);
   return L;
 }
@@ -101,7 +102,9 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
               size_t ws_bytes, hipStream_t stream) {
   try {
     if (!B || !H || !C || !members || !gamma || !p || !res) return NOF_E_NULL;
-    if (p->max_outer < 1 || p->no_steps < 1 || p->on_maxit < 0 || !(p->lr > 0.0)) return NOF_E_ARG;
+    if (p->max_outer < 1 || p->no_steps < 1 || p->on_maxit < 0 || !(p->lr > 0.0) ||
+        !(p->tol_orth >= 0.0))
+      return NOF_E_ARG;
     const size_t need = nof_solve_ws(naux, nbf, norb, ns, ng, Bt, prec);
     if (need == 0) return NOF_E_DIM;
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
@@ -191,6 +194,13 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
         NOF_STEP(hipMemcpyAsync(C, Cn, (size_t)nbf * norb * sizeof(double), hipMemcpyDeviceToDevice,
                                 stream) == hipSuccess ? NOF_OK : NOF_E_HIP);
       }
+      // orthonormality of the orbitals after the sweep, repaired past tol_orth
+      NOF_STEP(nof_orthonormalize(nbf, norb, C, nullptr, p->tol_orth, scal + 3, scr, sbytes, stream));
+      double orth = 0.0;
+      NOF_STEP(hipMemcpyAsync(&orth, scal + 3, sizeof(double), hipMemcpyDeviceToHost, stream) == hipSuccess
+                   ? NOF_OK : NOF_E_HIP);
+      NOF_STEP(hipStreamSynchronize(stream) == hipSuccess ? NOF_OK : NOF_E_HIP);
+      res->orth = std::max(res->orth, orth);
       res->outer = outer + 1;
       if (res->asym <= p->tol_lambda && have_prev && std::fabs(res->E - E_prev) <= p->tol_energy) {
         res->converged = 1;

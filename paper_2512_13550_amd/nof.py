@@ -83,15 +83,18 @@ _sig("nof_mlp_warm_gamma", _i, _i, _i, _i, _vp, _i, _vp, _d, _vp, _vp, _vp)
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("max_outer", _i), ("no_steps", _i), ("lr", _d), ("beta1", _d), ("beta2", _d),
-                ("eps", _d), ("tol_lambda", _d), ("tol_energy", _d), ("on_maxit", _i), ("on_tol", _d)]
+                ("eps", _d), ("tol_lambda", _d), ("tol_energy", _d), ("on_maxit", _i), ("on_tol", _d),
+                ("tol_orth", _d)]
 
 
 class SolveResult(ctypes.Structure):
     _fields_ = [("E", _d), ("asym", _d), ("outer", _i), ("no_steps", _i), ("on_iters", _i),
-                ("converged", _i), ("status", _i)]
+                ("converged", _i), ("status", _i), ("orth", _d)]
 
 
 _sig("nof_solve_ws", _sz, _i, _i, _i, _i, _i, _i, _i)
+_sig("nof_orthonormalize_ws", _sz, _i, _i)
+_sig("nof_orthonormalize", _i, _i, _i, _vp, _vp, _d, _vp, _vp, _sz, _vp)
 _sig("nof_dipole_ws", _sz, _i, _i)
 _sig("nof_dipole", _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_nlop_romberg", _i, _i, _d, _vp, _vp, _vp, _vp, _vp, _vp)
@@ -110,6 +113,7 @@ DECLARED = [
     "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
+    "nof_orthonormalize_ws", "nof_orthonormalize",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
@@ -348,6 +352,21 @@ def rotate_orbitals(C, U, Cout=None, ws=None, stream=None):
     return Cout
 
 
+def orthonormalize(C, S=None, tol=1e-10, err=None, ws=None, stream=None):
+    """Check max|C^T S C - I| and repair C in place past tol (nof_orthonormalize);
+    returns the device scalar err."""
+    nbf, norb = C.shape
+    if err is None:
+        err = torch.empty((), dtype=torch.float64, device=C.device)
+    need = lib.nof_orthonormalize_ws(nbf, norb)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, C.device)
+    check(lib.nof_orthonormalize(nbf, norb, _f64(C, "C"), _f64(S, "S") if S is not None else None,
+                                 float(tol), _p(err), _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_orthonormalize")
+    return err
+
+
 def adam_step(g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, y=None, stream=None):
     """One ADAM step on the orbital gradient; returns the rotation generator y."""
     norb = g.shape[0]
@@ -473,7 +492,7 @@ class BatchPlan:
 
     def solve(self, members, mapping, functional, gamma, n_out=None, stream=None, max_outer=100,
               no_steps=30, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, tol_lambda=1e-5,
-              tol_energy=1e-9, on_maxit=2000, on_tol=1e-8):
+              tol_energy=1e-9, on_maxit=2000, on_tol=1e-8, tol_orth=1e-10):
         """Alternating NO + ON optimisation of every instance (nof_plan_solve).
         The bound C [ninst][nbf][norb] and gamma [ninst][ns][ng] are updated in
         place; returns one result dict per instance."""
@@ -487,7 +506,7 @@ class BatchPlan:
         if self.solve_ws is None or self.solve_ws.numel() < need:
             self.solve_ws = workspace(need, C.device)
         prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit,
-                          on_tol)
+                          on_tol, tol_orth)
         res = (SolveResult * self.ninst)()
         rc = lib.nof_plan_solve(self.handle, _p(B), _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
                                 int(mapping), int(functional), _f64(gamma, "gamma"), _p(n_out),
@@ -581,7 +600,7 @@ def mlp_warm_gamma(theta, members, mapping, norb, nfloor=1e-12, info=None, strea
 
 def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=None, stream=None,
           max_outer=100, no_steps=30, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, tol_lambda=1e-5,
-          tol_energy=1e-9, on_maxit=2000, on_tol=1e-8):
+          tol_energy=1e-9, on_maxit=2000, on_tol=1e-8, tol_orth=1e-10):
     """Alternating NO + ON optimisation to convergence (nof_solve).  C and gamma
     are updated in place; returns the result as a dict."""
     naux, nbf, _ = B.shape
@@ -596,7 +615,8 @@ def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=No
         raise NofError(E_DIM, "nof_solve_ws")
     if ws is None or ws.numel() < need:
         ws = workspace(need, C.device)
-    prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit, on_tol)
+    prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit, on_tol,
+                      tol_orth)
     res = SolveResult()
     check(lib.nof_solve(naux, nbf, norb, Bp, Bt, _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
                         mapping, functional, _f64(gamma, "gamma"), _p(n), prec, ctypes.byref(prm),

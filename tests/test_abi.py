@@ -110,14 +110,16 @@ def test_solve_validation():
     import ctypes
     nof = _lib()
     L = nof.lib
-    prm = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+    prm = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
     res = nof.SolveResult()
     args = lambda B, p, ws_bytes: (2, 4, 4, B, 0, FAKE, FAKE, 1, 1, FAKE, 1, 1, FAKE, None, 0,
                                    ctypes.byref(p), ctypes.byref(res), FAKE, ws_bytes, None)
     assert L.nof_solve(*args(None, prm, 1 << 30)) == nof.E_NULL
-    bad = nof.SolveParams(0, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+    bad = nof.SolveParams(0, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
     assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
-    bad = nof.SolveParams(10, 30, 0.0, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+    bad = nof.SolveParams(10, 30, 0.0, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
+    assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
+    bad = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, -1.0)
     assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
     assert L.nof_solve(*args(FAKE, prm, 8)) == nof.E_WORKSPACE
     assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_BF16X1) == 0
@@ -149,16 +151,31 @@ def test_plan_solve_validation():
         assert need > L.nof_plan_ws(plan) + 3 * 9 * 8 * 8 * 8   # plan + nine norb^2 arrays per instance
         assert L.nof_plan_solve_ws(plan, 3, 2) == 0                # 3 x (2+1) > norb
         assert L.nof_plan_solve_ws(None, 2, 1) == 0
-        prm = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+        prm = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
         res = (nof.SolveResult * 3)()
         args = lambda pl, B, p, ws_bytes: (pl, B, FAKE, FAKE, 2, 1, FAKE, 1, 1, FAKE, None,
                                            ctypes.byref(p), res, FAKE, ws_bytes, None)
         assert L.nof_plan_solve(*args(None, FAKE, prm, need)) == nof.E_NULL
         assert L.nof_plan_solve(*args(plan, None, prm, need)) == nof.E_NULL
-        bad = nof.SolveParams(10, 0, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+        bad = nof.SolveParams(10, 0, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
         assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
-        bad = nof.SolveParams(10, 30, 0.01, 1.0, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8)
+        bad = nof.SolveParams(10, 30, 0.01, 1.0, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
+        assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
+        bad = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, float("nan"))
         assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
         assert L.nof_plan_solve(*args(plan, FAKE, prm, need - 1)) == nof.E_WORKSPACE
     finally:
         L.nof_plan_destroy(plan)
+
+
+def test_orthonormalize_validation():
+    nof = _lib()
+    L = nof.lib
+    need = L.nof_orthonormalize_ws(40, 30)
+    assert need > 2 * 30 * 30 * 8 + 40 * 30 * 8
+    assert L.nof_orthonormalize_ws(0, 30) == 0
+    assert L.nof_orthonormalize(0, 30, FAKE, None, 1e-10, None, FAKE, need, None) == nof.E_DIM
+    assert L.nof_orthonormalize(40, 30, None, None, 1e-10, None, FAKE, need, None) == nof.E_NULL
+    assert L.nof_orthonormalize(40, 30, FAKE, None, -1.0, None, FAKE, need, None) == nof.E_ARG
+    assert L.nof_orthonormalize(40, 30, FAKE, None, float("nan"), None, FAKE, need, None) == nof.E_ARG
+    assert L.nof_orthonormalize(40, 30, FAKE, None, 1e-10, None, FAKE, need - 1, None) == nof.E_WORKSPACE

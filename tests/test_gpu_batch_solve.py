@@ -70,6 +70,7 @@ def test_batched_trajectory_matches_oracle():
         print(f"instance {i} F={fields[i]}: gpu {r} oracle E {ref['E']} steps {ref['no_steps']}  "
               f"dE {dE:.2e} dC {dC:.2e} dgamma {dg:.2e}", flush=True)
         assert r["status"] == 0 and r["outer"] == 4 and r["no_steps"] == ref["no_steps"] == 120
+        assert r["orth"] <= 1e-13
         assert dE <= 1e-8 and dC <= 1e-5 and dg <= 1e-4
         assert abs(float(n[i].sum()) - ns) <= 1e-12 * ns
     # the instances really differ (the field moved the energies apart), and

@@ -46,3 +46,36 @@ def test_adam_steps():
         assert normwise(host(yd), y) <= 1e-14
         assert normwise(host(md), m) <= 1e-15
         assert np.array_equal(host(yd), -host(yd).T)
+
+
+def spd(rng, n):
+    A = rng.standard_normal((n, n))
+    return A @ A.T / n + np.eye(n)
+
+
+@pytest.mark.parametrize("nbf,norb,with_S", [(40, 30, False), (130, 97, True), (520, 500, False),
+                                              (1041, 1024, True)])
+def test_orthonormalize(nbf, norb, with_S):
+    """max|C^T S C - I| and the Newton-Schulz repair against the oracle: C
+    untouched (bit for bit) within the tolerance, repaired past it."""
+    nof = need_gpu()
+    print(f"case orthonormalize nbf={nbf} norb={norb} S={with_S}", flush=True)
+    rng = np.random.default_rng(nbf)
+    S = spd(rng, nbf) if with_S else None
+    L = np.linalg.cholesky(S) if with_S else np.eye(nbf)
+    Q = np.linalg.solve(L.T, np.linalg.qr(rng.standard_normal((nbf, norb)))[0])   # Q^T S Q = I
+    C = Q @ (np.eye(norb) + 1e-4 * rng.standard_normal((norb, norb)))
+    Sd = dev(S) if with_S else None
+    C1_ref, err_ref = rotation.orthonormalize(C, S, tol=0.0)
+    Cd = dev(C)
+    err = float(nof.orthonormalize(Cd, Sd, tol=1.0))
+    assert abs(err - err_ref) <= 1e-13 and torch.equal(Cd, dev(C))
+    err = float(nof.orthonormalize(Cd, Sd, tol=0.0))
+    assert abs(err - err_ref) <= 1e-13
+    C1 = host(Cd)
+    assert normwise(C1, C1_ref) <= 1e-13
+    # the error left is the closed form of one step, -3/4 E0^2 + 1/4 E0^3
+    E0 = rotation.orthonormality_error(C, S)
+    E1 = rotation.orthonormality_error(C1, S)
+    print("err", err, "after", float(np.max(np.abs(E1))), flush=True)
+    assert np.max(np.abs(E1 - (-0.75 * E0 @ E0 + 0.25 * E0 @ E0 @ E0))) <= 1e-13

@@ -51,18 +51,20 @@ def gapped_system(seed, nbf, naux, ns, gap=1.0):
     return B, (V * e) @ V.T, V
 
 
-@pytest.mark.parametrize("prec,functional", [("f64", "pnof5"), ("x10", "pnof5"), ("f64", "pnof7")])
-def test_solve_trajectory_matches_oracle(prec, functional):
+@pytest.mark.parametrize("prec,functional,tol_orth", [("f64", "pnof5", 1e-10), ("x10", "pnof5", 1e-10),
+                                                      ("f64", "pnof7", 1e-10), ("f64", "pnof5", 0.0)])
+def test_solve_trajectory_matches_oracle(prec, functional, tol_orth):
     """Four outer iterations (ON step + 30 ADAM steps each) from the same start:
     the two loops take the same steps, so the iterates agree (the early
-    iterations, with large gradients, do not amplify rounding differences)."""
+    iterations, with large gradients, do not amplify rounding differences).
+    With tol_orth = 0 both loops repair the orbitals after every sweep."""
     nof = need_gpu()
-    print(f"case solve {functional} trajectory nbf=24 {prec}", flush=True)
+    print(f"case solve {functional} trajectory nbf=24 {prec} tol_orth={tol_orth}", flush=True)
     nbf, ns, ng = 24, 6, 2
     B, H, C0 = gapped_system(5, nbf, 96, ns)
     members = np.array(inputs.pairing(nbf, ns, ng), dtype=np.int64)
     gamma0 = mlp.cold_gamma(members, "softmax")
-    kw = dict(max_outer=4, no_steps=30, tol_lambda=1e-12, tol_energy=0.0)
+    kw = dict(max_outer=4, no_steps=30, tol_lambda=1e-12, tol_energy=0.0, tol_orth=tol_orth)
     ref = solver.solve(B, C0, H, members, "softmax", functional, gamma0, **kw)
     C = dev(C0)
     gamma = dev(gamma0)
@@ -77,6 +79,8 @@ def test_solve_trajectory_matches_oracle(prec, functional):
     dg = float(np.max(np.abs(gamma.cpu().numpy() - ref["gamma"])))
     print(f"relative dE {dE:.2e}  max dC {dC:.2e}  max dgamma {dg:.2e}", flush=True)
     assert r["status"] == 0 and r["outer"] == 4 and r["no_steps"] == ref["no_steps"] == 120
+    # the orbitals stay orthonormal to rounding (the checks after the sweeps)
+    assert r["orth"] <= 1e-13 and ref["orth"] <= 1e-13
     if prec == "f64":
         # each ON step stops at max|dE/dgamma| <= 1e-8, so the occupations of the
         # two loops agree to that order and the later iterates inherit it
