@@ -242,6 +242,7 @@ def main():
     ms = r64["ms_per_step"]
     value = flops["total"] / (ms * 1e-3) / 1e12
     a1_ms = r64["seg_ms"][1]
+    a2_ms = r64["seg_ms"][2]
     a6_ms = r64["exchange_ms"]
     # dominant kernel of the FP64 step: transform stage 1 or the exchange-type Fock term
     if a6_ms > a1_ms:
@@ -338,7 +339,11 @@ def main():
                      "algorithmic_bytes_per_launch": dom["bytes"],
                      "other": {"transform_stage1_ms": a1_ms, "exchange_fock_ms": a6_ms,
                                "transform_stage1_frac": flops["a1"] / (a1_ms * 1e-3) / 1e12 / PEAK["f64"],
-                               "exchange_fock_frac": flops["a6"] / (a6_ms * 1e-3) / 1e12 / PEAK["f64"]}},
+                               "exchange_fock_frac": flops["a6"] / (a6_ms * 1e-3) / 1e12 / PEAK["f64"],
+                               # both transform stages (A1 + A2, symmetric half of A2 counted)
+                               "transform_ms": a1_ms + a2_ms,
+                               "transform_frac": (flops["a1"] + flops["a2"]) / ((a1_ms + a2_ms) * 1e-3) / 1e12
+                               / PEAK["f64"]}},
         "forms": forms,
         "batched": batched,
         "precision_workload": precision,
