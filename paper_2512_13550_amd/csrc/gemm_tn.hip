@@ -15,6 +15,8 @@
 // s+1 are in flight while stage s is multiplied.  The batch index (auxiliary
 // function P) is the outer grid dimension, remapped so that all tiles of one
 // batch run on the same XCD and share its L2.
+#include <type_traits>
+
 #include "common.h"
 
 namespace nof {
@@ -111,8 +113,10 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   const bool yn_ok = n0 + cy_t < d.N;
   const int xk_t = tid & (KT - 1), xm_t = tid >> 4;
   // on a diagonal tile of a symmetric product, a wave whose block lies wholly
-  // below the diagonal computes nothing that is written: it only loads
+  // below the diagonal computes nothing that is written: it only loads; a
+  // wave on the diagonal skips its fragments below it (i > j)
   const bool lower_wave = d.sym && tm == tn && wm > wn;
+  const bool diag_wave = d.sym && tm == tn && wm == wn && FM == FN;
 
   acc_t acc[FM][FN];
   d4v acc64[FLUSH64 ? FM : 1][FLUSH64 ? FN : 1];
@@ -181,20 +185,24 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   for (int s = 0; s < nstage; ++s) {
     const int buf = s & 1;
     if (s + 1 < nstage) load(s + 1);
-    if (!lower_wave)
+    auto products = [&](auto upper_only) {
 #pragma unroll
-    for (int kk = 0; kk < KT / 4; ++kk) {
-      TC a[FM], bv[FN];
-      const int kr = kk * 4 + (l >> 4);
+      for (int kk = 0; kk < KT / 4; ++kk) {
+        TC a[FM], bv[FN];
+        const int kr = kk * 4 + (l >> 4);
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kr][wm * 16 * FM + i * 16 + (l & 15)];
+        for (int i = 0; i < FM; ++i) a[i] = Xs[buf][kr][wm * 16 * FM + i * 16 + (l & 15)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bv[j] = Ys[buf][kr][wn * 16 * FN + j * 16 + (l & 15)];
+        for (int j = 0; j < FN; ++j) bv[j] = Ys[buf][kr][wn * 16 * FN + j * 16 + (l & 15)];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = MF::op(a[i], bv[j], acc[i][j]);
-    }
+          for (int j = 0; j < FN; ++j)
+            if (!decltype(upper_only)::value || i <= j) acc[i][j] = MF::op(a[i], bv[j], acc[i][j]);
+      }
+    };
+    if (diag_wave) products(std::true_type{});
+    else if (!lower_wave) products(std::false_type{});
     if (FLUSH64 && ((s + 1) % nkb == 0)) {
       // end of one batch: fold the FP32 partial into FP64
 #pragma unroll
