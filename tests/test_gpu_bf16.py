@@ -16,7 +16,8 @@ oracle on the FP32-rounded B, so that only the arithmetic remains: the
 representation error of four pieces is 2^-33 of a stage's largest element and
 the dropped products are of order 2^-32, so what is left is the FP32 storage of
 T and b (unit roundoff u = 2^-24, twice: normwise <= 2u = 1.2e-7), bound 3e-7;
-the energy, a sum over those stored values, |dE|/|E| <= 2e-8 (observed <= 4.3e-9).
+the energy, a sum over those stored values, |dE|/|E| <= 2e-8 (observed <= 4.3e-9) where many
+orbitals average the roundings, and |dE| <= 4u sum|terms| (the worst case) for one or two.
 A cancellation case pins the exactness itself: with paired rows whose products
 cancel, the exact result is zero and x10 must return it to 2^-30 of the sum of
 the |products| (element-wise split pieces with the matrix cores' alignment
@@ -65,7 +66,8 @@ def test_bf16_split_forms(mode, nbf, naux, norb, seed):
     assert errs["E"] <= tolE
 
 
-@pytest.mark.parametrize("nbf,naux,norb,seed", [(48, 192, 48, 0), (300, 40, 260, 1), (130, 7, 97, 5)])
+@pytest.mark.parametrize("nbf,naux,norb,seed", [(48, 192, 48, 0), (300, 40, 260, 1), (130, 7, 97, 5),
+                                               (1, 3, 1, 6), (2, 5, 2, 7)])
 def test_bf16_x10_fixed_point(nbf, naux, norb, seed):
     nof = need_gpu()
     print(f"case bf16 x10 nbf={nbf} naux={naux} norb={norb}", flush=True)
@@ -78,7 +80,15 @@ def test_bf16_x10_fixed_point(nbf, naux, norb, seed):
     print("x10", errs, flush=True)
     for k in ("b", "J", "K", "lam"):
         assert errs[k] <= 3e-7, (k, errs[k])
-    assert errs["E"] <= 2e-8
+    # E sums products of the stored T and b values: with many orbitals the
+    # roundings average (2e-8 of |E|); with one or two nothing averages and
+    # the bound is the worst case, 4u of the sum of the terms' magnitudes
+    if norb >= 48:
+        assert errs["E"] <= 2e-8
+    else:
+        terms = (2 * np.sum(np.abs(n * np.diag(ref["h"]))) + np.sum(np.abs(cJ * ref["J"]))
+                 + np.sum(np.abs(cK * ref["K"])))
+        assert abs(got["E"] - ref["E"]) <= 4 * 2.0 ** -24 * terms
     b32 = dev(ref["b"], torch.float32)
     F2 = nof.exchange_fock(b32, dev(cK), prec=nof.P_BF16X10)
     assert normwise(host(F2), ref["F2"]) <= 3e-7

@@ -23,6 +23,7 @@ SHAPES = [
     (257, 9, 129, 2),
     (5, 2, 3, 3),
     (130, 1, 130, 4),
+    (1, 3, 1, 5),
 ]
 
 
