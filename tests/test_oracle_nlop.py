@@ -100,3 +100,38 @@ def test_single_point_ladder_is_the_centred_difference():
     res = nlop.nlop(mu0, mp, mm, 0.25, 1)
     assert res[0]["value"] == 3.0 and res[1]["value"] == -1.0 and res[2]["value"] == 0.0
     assert all(math.isnan(r["uncertainty"]) and (r["k"], r["j"]) == (0, 0) for r in res)
+
+
+def test_printed_stencils_and_romberg_constants():
+    """The oracle's finite differences and Romberg recursion against the
+    constants the paper prints (tests/golden/nlop_formulas.json): each
+    stencil's weights are read off the oracle by feeding it unit dipoles, the
+    Romberg denominators by a first column with one unit entry."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "nlop_formulas.json")))
+    h = 0.5                       # a power of two: the weights come back exact
+    offsets_all = [0, 1, -1, 2, -2]
+    for prop, name in enumerate(("alpha", "beta", "gamma")):
+        st = g["stencils"][name]
+        got = {}
+        for off in offsets_all:
+            mu = {o: 0.0 for o in offsets_all}
+            mu[off] = 1.0
+            val = nlop.estimates(prop, mu[0], (mu[1], mu[-1]), (mu[2], mu[-2]), h)
+            got[off] = val * st["divisor"] * h ** st["power"]
+        ref = {o: 0.0 for o in offsets_all}
+        for o, w in zip(st["offsets"], st["weights"]):
+            ref[o] = float(w)
+        assert got == ref, (name, got, ref)
+    # R(1, j) from a first column that is 1 at k = 1 and 0 elsewhere: column j
+    # (1-based) scales the previous one by 1 + 1/(4^(j-1) - 1)
+    D = np.zeros(9)
+    D[0] = 1.0
+    R = nlop.romberg(D)
+    for j, den in enumerate(g["romberg"]["denominators_j2_to_j9"], start=1):
+        assert abs(R[0, j] / R[0, j - 1] - (1.0 + 1.0 / den)) <= 4e-16
+    # ladder
+    lad = g["ladder"]
+    hk = [lad["default_STEP"] * 2.0 ** k for k in range(lad["default_NPOINT"])]
+    assert np.allclose(hk, lad["h_default"], rtol=0, atol=1e-18)
