@@ -132,6 +132,15 @@ size_t stage_ws(int naux, int nbf, int norb, int prec, int Bt) {
   return align256((size_t)np * norb * presplit_ldk(nbf) * 2);
 }
 
+// Workgroup tile of a batched transform product: 64-wide when 128-wide tiles
+// would give fewer than 512 workgroups (the one-electron transform, naux = 1,
+// has 16 at Norb = 500), else 128-wide.
+int small_grid_tile(int batch, int M, int N, bool sym) {
+  const long long tm = (M + 127) / 128, tn = (N + 127) / 128;
+  const long long tiles = sym ? tn * (tn + 1) / 2 : tm * tn;
+  return tiles * batch < 512 ? 64 : 128;
+}
+
 int split_C(int nbf, int norb, const double* C, int prec, int Bt, void* ws, hipStream_t stream) {
   const int np = Bt == NOF_BF16 ? 3 : bf16_pieces(prec);
   return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream);
@@ -245,6 +254,7 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     g1.Dg = nullptr; g1.sd = 0; g1.sym = false;
     // the one-electron transform (naux = 1) is attributed to the small products
     g1.role = naux > 1 ? GemmRole::TransformStage1 : GemmRole::Small;
+    g1.tile = small_grid_tile(naux, nbf, norb, false);
     if (!bf) return gemm_tn(g1, Bt, NOF_F64, Tt, prec, stream);
     NOF_TRY(split_C(nbf, norb, C, prec, Bt, ws, stream));
     g1.Y = ws; g1.ldy = presplit_ldk(nbf); g1.psy = (long long)norb * presplit_ldk(nbf);
@@ -275,6 +285,7 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     g2.Out = b; g2.ldo = norb; g2.so = (long long)norb * norb;
     g2.Dg = D; g2.sd = norb; g2.sym = true;
     g2.role = naux > 1 ? GemmRole::TransformStage2 : GemmRole::Small;
+    g2.tile = small_grid_tile(naux, norb, norb, true);
     if (!bf) return gemm_tn(g2, NOF_F64, Tt, bt, prec, stream);
     NOF_TRY(split_C(nbf, norb, C, prec, NOF_F32, ws, stream));
     g2.X = ws; g2.ldx = presplit_ldk(nbf); g2.psx = (long long)norb * presplit_ldk(nbf);
