@@ -158,6 +158,7 @@ def main():
         rot = nof.Rotation(norb, nbf, dev)
         ws_f = nof.workspace(nof.lib.nof_gen_fock_ws(naux, norb, nof._TDT[dt], prec), dev)
         ws_j = nof.workspace(nof.lib.nof_jk_diag_ws(naux, norb, nof._TDT[dt]), dev)
+        ws_e = nof.workspace(nof.lib.nof_energy_ws(norb), dev)
         Es = []
         nev = len(names) + 1
         evs = []
@@ -187,7 +188,7 @@ def main():
             nof.gen_fock(b, D, n, h, cJ, cK, want_grad=True, want_K=True, prec=prec,
                          out=out, ws=ws_f)                            # A4-A7
             tick()
-            nof.energy(n, h, J, out["K"], cJ, cK, E=E)                # A8
+            nof.energy(n, h, J, out["K"], cJ, cK, E=E, ws=ws_e)      # A8
             tick()
             return e
 

@@ -213,11 +213,16 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
  * Energy of Eq. (PNOF):
  *   E = 2 sum_p n_p h_pp + sum_pq cJ_pq J_pq - sum_pq cK_pq K_pq
  * All inputs [norb] or [norb][norb] FP64; E is one FP64 device scalar.
- * Deterministic fixed-order FP64 reduction.
+ * Deterministic fixed-order FP64 reduction: fixed chunks summed by many
+ * workgroups into ws, then the partials in a fixed tree.
+ * ws  at least nof_energy_ws(norb) bytes (the partial sums).
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_WORKSPACE, NOF_E_HIP.
  * ------------------------------------------------------------------------- */
+size_t nof_energy_ws(int norb);
 int nof_energy(int norb, const double* n, const double* h,
                const double* J, const double* K,
-               const double* cJ, const double* cK, double* E, hipStream_t stream);
+               const double* cJ, const double* cK, double* E, void* ws, size_t ws_bytes,
+               hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Coefficients of Eq. (PNOF) from the cumulant matrices of the (2,2)-positivity

@@ -462,12 +462,19 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
   });
 }
 
+size_t nof_energy_ws(int norb) {
+  if (!dim_ok(norb)) return 0;
+  return energy_ws(1);
+}
+
 int nof_energy(int norb, const double* n, const double* h, const double* J, const double* K,
-               const double* cJ, const double* cK, double* E, hipStream_t stream) {
+               const double* cJ, const double* cK, double* E, void* ws, size_t ws_bytes,
+               hipStream_t stream) {
   return guarded([&]() -> int {
     if (!dim_ok(norb)) return NOF_E_DIM;
     if (!n || !h || !J || !K || !cJ || !cK || !E) return NOF_E_NULL;
-    return energy(norb, n, h, J, K, cJ, cK, E, stream);
+    if (!ws || ws_bytes < energy_ws(1)) return NOF_E_WORKSPACE;
+    return energy(norb, n, h, J, K, cJ, cK, E, (double*)ws, stream);
   });
 }
 

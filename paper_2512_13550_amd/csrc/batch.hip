@@ -37,7 +37,7 @@ namespace nof {
 namespace {
 
 enum {
-  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_N
+  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_EP, O_N
 };
 
 void plan_layout(nof_plan_s* p) {
@@ -60,6 +60,7 @@ void plan_layout(nof_plan_s* p) {
   sz[O_F2P] = (size_t)f2groups * n2;
   sz[O_F1] = ni * n2;
   sz[O_F2] = ni * n2;
+  sz[O_EP] = energy_ws((int)ni);
   size_t o = 0;
   for (int i = 0; i < O_N; ++i) {
     p->off[i] = o;
@@ -203,7 +204,7 @@ int run_tail(nof_plan_s* p, const Args& a, hipStream_t st) {
   if (rc != NOF_OK) return rc;
   // energy: h, cJ, cK stride n2 per instance; J, K stride n2
   return energy(p->norb, a.n, h, (double*)(a.ws + p->off[O_J]), (double*)(a.ws + p->off[O_K]),
-                a.cJ, a.cK, a.E, st, p->ninst, p->norb, n2, n2);
+                a.cJ, a.cK, a.E, (double*)(a.ws + p->off[O_EP]), st, p->ninst, p->norb, n2, n2);
 }
 
 int run_iteration(nof_plan_s* p, const Args& a, hipStream_t st) {

@@ -158,8 +158,10 @@ int lambda_grad(int norb, const double* n, const double* h, const double* F1,
                 const double* F2, double* lam, double* grad, hipStream_t st, int ninst = 1,
                 long long nstride = 0, long long mstride = 0, long long fstride = 0);
 
+// E of ninst instances; part: energy_ws(ninst) bytes of partial sums.
+size_t energy_ws(int ninst);
 int energy(int norb, const double* n, const double* h, const double* J,
-           const double* K, const double* cJ, const double* cK, double* E,
+           const double* K, const double* cJ, const double* cK, double* E, double* part,
            hipStream_t st, int ninst = 1, long long nstride = 0, long long mstride = 0,
            long long jstride = 0);
 

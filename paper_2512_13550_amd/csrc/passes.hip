@@ -293,35 +293,56 @@ __global__ void k_lambda(int norb, const double* __restrict__ n, const double* _
   }
 }
 
-constexpr int E_THR = 1024;
-__global__ __launch_bounds__(E_THR) void k_energy(int norb, const double* __restrict__ n,
-                                                  const double* __restrict__ h,
-                                                  const double* __restrict__ J,
-                                                  const double* __restrict__ K,
-                                                  const double* __restrict__ cJ,
-                                                  const double* __restrict__ cK,
-                                                  double* __restrict__ E, long long nstride,
-                                                  long long mstride, long long jstride) {
+// Energy in two fixed-order steps (bitwise repeatable): workgroup c of
+// instance y sums elements [c*chunk, (c+1)*chunk) of cJ o J - cK o K and the
+// diagonal terms 2 n_p h_pp of its share of p into part[y*E_PARTS + c]; one
+// workgroup per instance then adds the E_PARTS partials in a fixed tree.
+constexpr int E_PARTS = 128, E_THR = 256;
+__global__ __launch_bounds__(E_THR) void k_energy_part(int norb, const double* __restrict__ n,
+                                                       const double* __restrict__ h,
+                                                       const double* __restrict__ J,
+                                                       const double* __restrict__ K,
+                                                       const double* __restrict__ cJ,
+                                                       const double* __restrict__ cK,
+                                                       double* __restrict__ part, long long nstride,
+                                                       long long mstride, long long jstride) {
   __shared__ double red[E_THR];
   const long long n2 = (long long)norb * norb;
-  const long long y = blockIdx.x;
+  const long long y = blockIdx.y;
+  const int c = blockIdx.x;
   n += y * nstride;
   h += y * mstride;
   cJ += y * mstride;
   cK += y * mstride;
   J += y * jstride;
   K += y * jstride;
-  E += y;
+  const long long chunk = (n2 + E_PARTS - 1) / E_PARTS;
+  const long long lo = c * chunk, hi = min(n2, lo + chunk);
   double a = 0.0;
-  for (long long i = threadIdx.x; i < n2; i += E_THR) a += cJ[i] * J[i] - cK[i] * K[i];
-  for (int p = threadIdx.x; p < norb; p += E_THR) a += 2.0 * n[p] * h[(long long)p * norb + p];
+  for (long long i = lo + threadIdx.x; i < hi; i += E_THR) a += cJ[i] * J[i] - cK[i] * K[i];
+  const int pc = (norb + E_PARTS - 1) / E_PARTS;
+  const int p_hi = min(norb, (c + 1) * pc);
+  for (int p = c * pc + threadIdx.x; p < p_hi; p += E_THR) a += 2.0 * n[p] * h[(long long)p * norb + p];
   red[threadIdx.x] = a;
   __syncthreads();
   for (int w = E_THR / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *E = red[0];
+  if (threadIdx.x == 0) part[y * E_PARTS + c] = red[0];
+}
+
+__global__ __launch_bounds__(E_PARTS) void k_energy_sum(const double* __restrict__ part,
+                                                        double* __restrict__ E) {
+  __shared__ double red[E_PARTS];
+  const long long y = blockIdx.x;
+  red[threadIdx.x] = part[y * E_PARTS + threadIdx.x];
+  __syncthreads();
+  for (int w = E_PARTS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E[y] = red[0];
 }
 
 __global__ void k_coeffs(int norb, const double* __restrict__ n, const double* __restrict__ Delta,
@@ -440,11 +461,16 @@ int lambda_grad(int norb, const double* n, const double* h, const double* F1, co
   return launch_status();
 }
 
+size_t energy_ws(int ninst) { return align256((size_t)ninst * E_PARTS * sizeof(double)); }
+
 int energy(int norb, const double* n, const double* h, const double* J, const double* K,
-           const double* cJ, const double* cK, double* E, hipStream_t st, int ninst,
+           const double* cJ, const double* cK, double* E, double* part, hipStream_t st, int ninst,
            long long nstride, long long mstride, long long jstride) {
-  hipLaunchKernelGGL(k_energy, dim3(ninst), dim3(E_THR), 0, st, norb, n, h, J, K, cJ, cK, E,
-                     nstride, mstride, jstride);
+  hipLaunchKernelGGL(k_energy_part, dim3(E_PARTS, ninst), dim3(E_THR), 0, st, norb, n, h, J, K, cJ,
+                     cK, part, nstride, mstride, jstride);
+  int rc = launch_status();
+  if (rc != NOF_OK) return rc;
+  hipLaunchKernelGGL(k_energy_sum, dim3(ninst), dim3(E_PARTS), 0, st, part, E);
   return launch_status();
 }
 

@@ -78,6 +78,7 @@ SolveLayout solve_layout(int naux, int nbf, int norb, int ns, int ng, int Bt, in
   s = std::max(s, nof_rotate_orbitals_ws(nbf, norb));
   s = std::max(s, nof_occ_ws(norb, ns, ng));
   s = std::max(s, nof_orthonormalize_ws(nbf, norb));
+  s = std::max(s, nof_energy_ws(norb));
   L.total = L.scratch + a256(s);
   return L;
 }
@@ -176,7 +177,7 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
         NOF_STEP(nof_jk_diag(naux, norb, b, bt, D, J, nullptr, scr, sbytes, stream));
         NOF_STEP(nof_gen_fock(naux, norb, b, bt, D, n, h, cJ, cK, lam, g, K, prec, scr, sbytes,
                               stream));
-        NOF_STEP(nof_energy(norb, n, h, J, K, cJ, cK, scal, stream));
+        NOF_STEP(nof_energy(norb, n, h, J, K, cJ, cK, scal, scr, sbytes, stream));
         hipLaunchKernelGGL(k_asym, dim3(1), dim3(256), 0, stream, norb, lam, scal + 2);
         NOF_STEP(launch_status());
         NOF_STEP(hipMemcpyAsync(host, scal, sizeof(host), hipMemcpyDeviceToHost, stream) == hipSuccess

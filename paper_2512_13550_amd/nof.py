@@ -47,7 +47,8 @@ _sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_exchange_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_exchange_fock", _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp)
 _sig("nof_gen_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp)
-_sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nof_energy_ws", _sz, _i)
+_sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_coeffs_from_cumulant", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_expm_antisym_ws", _sz, _i)
 _sig("nof_expm_antisym", _i, _i, _vp, _vp, _vp, _sz, _vp)
@@ -111,7 +112,7 @@ DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
     "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_split_B_bytes", "nof_split_B",
     "nof_jk_diag_ws", "nof_jk_diag",
-    "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock", "nof_energy", "nof_coeffs_from_cumulant",
+    "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock", "nof_energy_ws", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_orthonormalize_ws", "nof_orthonormalize",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
@@ -308,12 +309,16 @@ def exchange_fock(b, cK, prec=None, F2=None, ws=None, stream=None):
     return F2
 
 
-def energy(n, h, J, K, cJ, cK, E=None, stream=None):
+def energy(n, h, J, K, cJ, cK, E=None, ws=None, stream=None):
     norb = n.shape[0]
     if E is None:
         E = torch.empty((), dtype=torch.float64, device=n.device)
+    need = lib.nof_energy_ws(norb)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, n.device)
     check(lib.nof_energy(norb, _f64(n, "n"), _f64(h, "h"), _f64(J, "J"), _f64(K, "K"),
-                         _f64(cJ, "cJ"), _f64(cK, "cK"), _p(E), stream_handle(stream)), "nof_energy")
+                         _f64(cJ, "cJ"), _f64(cK, "cK"), _p(E), _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_energy")
     return E
 
 

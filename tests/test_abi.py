@@ -71,8 +71,10 @@ def test_jk_and_fock_validation():
     assert L.nof_gen_fock(3, 4, FAKE, 0, *args, None, None, 0, FAKE, 8, None) == nof.E_WORKSPACE
     assert L.nof_gen_fock(3, 4, FAKE, 0, FAKE, FAKE, FAKE, FAKE, None, FAKE, None, None, 0, FAKE, 1 << 30, None) == nof.E_NULL
     assert L.nof_gen_fock(3, 4, FAKE, 0, *args, None, None, 1, FAKE, 1 << 30, None) == nof.E_PREC
-    assert L.nof_energy(0, *([FAKE] * 7), None) == nof.E_DIM
-    assert L.nof_energy(4, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, None) == nof.E_NULL
+    assert L.nof_energy(0, *([FAKE] * 7), FAKE, 1 << 20, None) == nof.E_DIM
+    assert L.nof_energy(4, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == nof.E_NULL
+    assert L.nof_energy_ws(4) > 0 and L.nof_energy_ws(0) == 0
+    assert L.nof_energy(4, *([FAKE] * 7), FAKE, L.nof_energy_ws(4) - 1, None) == nof.E_WORKSPACE
     assert L.nof_coeffs_from_cumulant(4, FAKE, None, FAKE, FAKE, FAKE, None) == nof.E_NULL
 
 
