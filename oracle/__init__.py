@@ -25,13 +25,18 @@ Pin status (what each function is checked against, in tests/test_oracle_*.py):
                               0/1 occupations, exact interpair energy drop, finite
                               differences of dE/dn
   occupations.*               pinned: sum rule, bounds, finite differences
-  rotation.*                  pinned: orthogonality, closed forms
+  rotation.*                  pinned: orthogonality, closed forms; the orthonormality
+                              check written out as a double loop, the closed-form
+                              error -3/4 E^2 + 1/4 E^3 left by one repair step
   mlp.*                       pinned: finite differences, hand-checked tiny net
   nlop.*                      pinned: exact on polynomial dipoles, analytic
                               derivatives of a smooth dipole, hand-made
                               selection cases, Hellmann-Feynman (dipole equals
-                              minus the field derivative of SCF energies)
+                              minus the field derivative of SCF energies), the
+                              stencil weights and Romberg denominators the paper
+                              prints (tests/golden/nlop_formulas.json)
   solver.solve                pinned: closed-shell HF minimum equal to a DIIS
                               Roothaan SCF; stationarity (lambda symmetric, ON
-                              gradient zero) and variational checks at the end
+                              gradient zero) and variational checks at the end;
+                              the orbitals stay orthonormal over the run
 """
