@@ -6,7 +6,11 @@
 // exponential revisited", SIAM J. Matrix Anal. Appl. 26 (2005)): the scaling
 // power s is chosen on the device from the Frobenius norm so that
 // ||y / 2^s||_F <= 1/4, where the truncation error is below 3e-18; the
-// polynomial is applied in Horner form and then squared s times.  Every
+// polynomial is evaluated by the Paterson-Stockmeyer scheme (Paterson and
+// Stockmeyer, SIAM J. Comput. 2 (1973)) in blocks of four powers,
+//   p(x) = B0 + x^4 (B1 + x^4 B2),  B_j = sum_i x^i / (4j + i)!,
+// which takes five products (y^2, y^3, y^4 and two by x^4) where Horner's rule
+// takes eleven, and the result is then squared s times.  Every
 // product is a split-K matrix-core GEMM (the matrices are small, so the K
 // dimension is spread over workgroups) followed by a fixed-order combine.  Nothing is read back to the host,
 // so the whole step stays asynchronous (and graph capturable): the squaring
@@ -90,6 +94,54 @@ __global__ void k_combine(int rows, int cols, const double* __restrict__ part, i
     for (int c = 0; c < nparts; ++c) a += part[(long long)c * stride + i];
     const int r = (int)(i / cols), q = (int)(i - (long long)r * cols);
     out[i] = (r == q ? diag_c : 0.0) + coef * a;
+  }
+}
+
+// Instance i = blockIdx.y: out_i = add_i + sc[i].scale^4 * sum_c part_i[c]
+// (fixed summation order); the Horner step in x^4 = (2^-s y)^4.
+__global__ void k_combine_x4(long long n2, const double* __restrict__ part, int nparts, long long stride,
+                             const ExpmScratch* __restrict__ sc, const double* __restrict__ add,
+                             double* __restrict__ out, long long pinst, long long oinst) {
+  const int y = blockIdx.y;
+  part += y * pinst;
+  add += y * oinst;
+  out += y * oinst;
+  const double s = sc[y].scale, coef = (s * s) * (s * s);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int c = 0; c < nparts; ++c) a += part[(long long)c * stride + i];
+    out[i] = add[i] + coef * a;
+  }
+}
+
+// One block of the Taylor polynomial in x = sc[i].scale * y for instance
+// i = blockIdx.y: out = sum_{j<np} c[j] x^j with x^0 = I, x^1 from y and x^2,
+// x^3, x^4 from the unscaled powers P2, P3, P4 (np <= 5).
+struct TaylorBlock {
+  double c[5];
+  int np;
+};
+__global__ void k_taylor_block(int norb, const double* __restrict__ y, const double* __restrict__ P2,
+                               const double* __restrict__ P3, const double* __restrict__ P4,
+                               TaylorBlock tb, const ExpmScratch* __restrict__ sc,
+                               double* __restrict__ out, long long yinst, long long ab) {
+  const long long inst = blockIdx.y;
+  const long long n2 = (long long)norb * norb;
+  const double s = sc[inst].scale;
+  const double w1 = tb.c[1] * s, w2 = tb.c[2] * (s * s), w3 = tb.c[3] * (s * s * s);
+  const double w4 = tb.np > 4 ? tb.c[4] * ((s * s) * (s * s)) : 0.0;
+  y += inst * yinst;
+  P2 += inst * ab;
+  P3 += inst * ab;
+  P4 += inst * ab;
+  out += inst * ab;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / norb), q = (int)(i - (long long)r * norb);
+    double v = (r == q ? tb.c[0] : 0.0) + w1 * y[i] + w2 * P2[i] + w3 * P3[i];
+    if (tb.np > 4) v += w4 * P4[i];
+    out[i] = v;
   }
 }
 
@@ -223,7 +275,8 @@ int combine(int ninst, int rows, int cols, const double* part, int nparts, doubl
 size_t expm_ws(int norb, int ninst) {
   const size_t n2 = align256((size_t)norb * norb * sizeof(double));
   const int ns = split_for(norb, norb, norb).ns;
-  return align256((size_t)ninst * sizeof(ExpmScratch)) + (size_t)ninst * (2 * n2 + (size_t)ns * n2);
+  // A, B (ping-pong), the powers y^2, y^3, y^4, split partials
+  return align256((size_t)ninst * sizeof(ExpmScratch)) + (size_t)ninst * (5 * n2 + (size_t)ns * n2);
 }
 
 size_t rotate_ws(int nbf, int norb, int ninst) {
@@ -254,24 +307,46 @@ int expm_antisym(int norb, const double* y, double* U, void* ws, hipStream_t st,
   const long long ab = (long long)(n2b / sizeof(double));   // instance stride of A and B
   double* A = (double*)(w + align256((size_t)ninst * sizeof(ExpmScratch)));
   double* Bm = A + (long long)ninst * ab;
-  double* part = Bm + (long long)ninst * ab;
+  double* P2 = Bm + (long long)ninst * ab;
+  double* P3 = P2 + (long long)ninst * ab;
+  double* P4 = P3 + (long long)ninst * ab;
+  double* part = P4 + (long long)ninst * ab;
   const SplitPlan plan = split_for(norb, norb, norb);
   const int ns = plan.ns;
+  const dim3 eg(grid_for(n2, 256), ninst);
   hipLaunchKernelGGL(k_norm_scale, dim3(ninst), dim3(1024), 0, st, norb, y, sc);
   int rc = launch_status();
   if (rc != NOF_OK) return rc;
-  // Horner with x = y / 2^s:  R_12 = I + x/12,  R_k = I + (x/k) R_{k+1}.
-  // y^T = -y, so x R = -(2^-s) y^T R and y^T R is a k-major product.
-  // First step: R_12 = I + (2^-s/12) y (a combine of y itself).
-  hipLaunchKernelGGL(k_combine, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, norb, y, 1,
-                     0LL, 1.0, 1.0 / kTaylor, sc, nullptr, 0, A, n2, ab);
-  rc = launch_status();
-  if (rc != NOF_OK) return rc;
-  for (int k = kTaylor - 1; k >= 1; --k) {
-    rc = gemm_split(ninst, norb, norb, norb, y, true, norb, n2, A, norb, ab, part, plan, nullptr, 0, st);
+  // unscaled powers: P = X Y with X(k, m) = X[m][k] (m-major)
+  auto power = [&](const double* X, long long xinst, const double* Y, long long yinst, double* out) {
+    int r = gemm_split(ninst, norb, norb, norb, X, false, norb, xinst, Y, norb, yinst, part, plan,
+                       nullptr, 0, st);
+    if (r != NOF_OK) return r;
+    return combine(ninst, norb, norb, part, ns, 0.0, 1.0, nullptr, nullptr, 0, out, ab, st);
+  };
+  if ((rc = power(y, n2, y, n2, P2)) != NOF_OK) return rc;      // y^2
+  if ((rc = power(P2, ab, y, n2, P3)) != NOF_OK) return rc;     // y^3
+  if ((rc = power(P2, ab, P2, ab, P4)) != NOF_OK) return rc;    // y^4
+  // Taylor coefficients 1/k!, k = 0 .. 12, in blocks of four (the last holds five)
+  double f[kTaylor + 1];
+  f[0] = 1.0;
+  for (int k = 1; k <= kTaylor; ++k) f[k] = f[k - 1] / k;
+  auto block = [&](int j, double* out) {
+    TaylorBlock tb{};
+    tb.np = j == 2 ? 5 : 4;
+    for (int i = 0; i < tb.np; ++i) tb.c[i] = f[4 * j + i];
+    hipLaunchKernelGGL(k_taylor_block, eg, dim3(256), 0, st, norb, y, P2, P3, P4, tb, sc, out, n2, ab);
+    return launch_status();
+  };
+  // A = B2;  A = B1 + x^4 A;  A = B0 + x^4 A
+  if ((rc = block(2, A)) != NOF_OK) return rc;
+  for (int j = 1; j >= 0; --j) {
+    if ((rc = block(j, Bm)) != NOF_OK) return rc;
+    rc = gemm_split(ninst, norb, norb, norb, P4, false, norb, ab, A, norb, ab, part, plan, nullptr, 0, st);
     if (rc != NOF_OK) return rc;
-    rc = combine(ninst, norb, norb, part, ns, 1.0, -1.0 / k, sc, nullptr, 0, A, ab, st);
-    if (rc != NOF_OK) return rc;
+    hipLaunchKernelGGL(k_combine_x4, eg, dim3(256), 0, st, n2, part, ns, n2, sc, Bm, A,
+                       (long long)ns * n2, ab);
+    if ((rc = launch_status()) != NOF_OK) return rc;
   }
   // squarings i = 0 .. s-1, ping-pong A -> B -> A ... (instances with s <= i skip)
   double* cur = A;
