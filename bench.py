@@ -281,6 +281,13 @@ def main():
             stage_ms=dict(zip(r["seg_names"], r["seg_ms"])),
             meets_dE_1e6=bool(dE <= 1e-6),
         )
+        if "a1_a2_transform" in r["seg_names"]:
+            # the fused x10 transform as BF16 matrix-core work: ten products of
+            # pieces per algorithmic flop of either stage
+            t = r["seg_ms"][r["seg_names"].index("a1_a2_transform")]
+            tf = 10.0 * (flops["a1"] + flops["a2"]) / (t * 1e-3) / 1e12
+            forms[f]["transform_matrix_core"] = dict(products_per_flop=10, tflops_bf16=tf,
+                                                     peak=PEAK["bf16"], frac=tf / PEAK["bf16"])
     del B32
     torch.cuda.empty_cache()
 
