@@ -341,7 +341,11 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
  * later step is a single instance-batched launch.
  *
  *   B      [naux][nbf][nbf], storage NOF_F64 (prec NOF_P_F64) or NOF_F32
- *          (prec NOF_P_F32: FP32 matrix-core products, FP64 reductions)
+ *          (prec NOF_P_F32: FP32 matrix-core products, FP64 reductions), or
+ *          the fixed-point planes of nof_split_B (prec NOF_P_BF16X10: the x10
+ *          transform and exchange-type term of nof_mo_transform and
+ *          nof_gen_fock, instance by instance after the shared first stage;
+ *          ninst * norb <= 2^20)
  *   C      [ninst][nbf][norb]     H  [ninst][nbf][nbf]    n  [ninst][norb]
  *   cJ, cK [ninst][norb][norb] (symmetric)
  *   E      out [ninst]      lambda, grad  out [ninst][norb][norb] (grad may be NULL)
@@ -351,7 +355,8 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
  *   configuration and, once captured, a HIP graph of one iteration.
  * nof_plan_autotune: runs one iteration, then times each candidate workgroup
  *   tile (128 or 64) of the two transform stages and the exchange-type
- *   contraction, and its split over P, keeping the fastest; finishes with one
+ *   contraction, and its split over P, keeping the fastest (NOF_P_BF16X10:
+ *   the split only, its kernels have one tile shape); finishes with one
  *   iteration in the chosen configuration.  Synchronises `stream`.
  * nof_plan_get_config / nof_plan_set_config: int[4] = {tile stage 1, tile
  *   stage 2, tile exchange, P-split count of the exchange term}, so a caller
@@ -498,7 +503,7 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
  * follows the same sequence of states as nof_solve would give it alone
  * (sweep and convergence rules, ADAM moments and step counter per instance).
  *
- * plan     from nof_plan_create (prec NOF_P_F64 or NOF_P_F32; B as for
+ * plan     from nof_plan_create (any of its precisions; B as for
  *          nof_plan_iteration).  Uses the plan's tuned configuration; the
  *          plan's own captured graph, if any, is left alone.
  * H        [ninst][nbf][nbf] FP64; C [ninst][nbf][norb] FP64 in/out.

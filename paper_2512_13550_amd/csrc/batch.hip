@@ -37,7 +37,8 @@ namespace nof {
 namespace {
 
 enum {
-  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_EP, O_N
+  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_EP,
+  O_CPL, O_CMX, O_EY, O_ST, O_N      // the last four: the fixed-point (x10) form only
 };
 
 void plan_layout(nof_plan_s* p) {
@@ -61,6 +62,14 @@ void plan_layout(nof_plan_s* p) {
   sz[O_F1] = ni * n2;
   sz[O_F2] = ni * n2;
   sz[O_EP] = energy_ws((int)ni);
+  // x10: planes of the packed C, column maxima of T per row tile, the grid
+  // exponents of T's columns, cK transposed in FP32 (one instance at a time)
+  const bool fx = p->prec == NOF_P_BF16X10;
+  const size_t ldk = (size_t)presplit_ldk(p->nbf), ldc = ni * no;
+  sz[O_CPL] = fx ? 4 * ldc * ldk * 2 : 0;
+  sz[O_CMX] = fx ? na * (size_t)fx_tiles(p->nbf) * ldc * 4 : 0;
+  sz[O_EY] = fx ? na * ldc * 4 : 0;
+  sz[O_ST] = fx ? no * no * 4 : 0;
   size_t o = 0;
   for (int i = 0; i < O_N; ++i) {
     p->off[i] = o;
@@ -91,6 +100,25 @@ struct Args {
 // Stage kernels of one iteration.  Each returns a status.
 int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long ldc = (long long)p->ninst * p->norb;
+  if (p->prec == NOF_P_BF16X10) {
+    // B as fixed-point planes [4][naux][nbf][ldk]; the packed C split once
+    // into planes of its ninst*norb columns; the epilogue's column maxima of
+    // T give stage 2 its grids
+    const long long ldk = presplit_ldk(p->nbf);
+    void* cpl = a.ws + p->off[O_CPL];
+    int rc = fx_split_cols((const double*)(a.ws + p->off[O_CALL]), p->nbf, (int)ldc, (int)ldc, (int)ldk,
+                           cpl, st);
+    if (rc != NOF_OK) return rc;
+    FxDesc f{};
+    f.M = p->nbf; f.N = (int)ldc; f.K = p->nbf; f.batch = p->naux;
+    f.X = a.B; f.ldx = ldk; f.sx = (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
+    f.Y = cpl; f.ldy = ldk; f.sy = 0; f.psy = ldc * ldk;
+    f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = (long long)p->nbf * ldc;
+    f.sym = false; f.role = 1;
+    f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)fx_tiles(p->nbf) * ldc;
+    if ((rc = gemm_fx(f, true, true, st)) != NOF_OK) return rc;
+    return fx_cmax_exps(f.cmax, p->naux, fx_tiles(p->nbf), (int)ldc, (int*)(a.ws + p->off[O_EY]), st);
+  }
   GemmDesc g{};
   g.M = p->nbf; g.N = p->ninst * p->norb; g.K = p->nbf;
   g.batch = p->naux; g.fold = 1;
@@ -105,6 +133,27 @@ int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
 int run_stage2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long ldc = (long long)p->ninst * p->norb;
   const long long n2 = (long long)p->norb * p->norb;
+  if (p->prec == NOF_P_BF16X10) {
+    // instance i: its C planes are columns i*norb.. of the packed planes, its
+    // T^P columns i*norb.. of T, with their grid exponents
+    const long long ldk = presplit_ldk(p->nbf);
+    const char* cpl = a.ws + p->off[O_CPL];
+    const int* ey = (const int*)(a.ws + p->off[O_EY]);
+    for (int i = 0; i < p->ninst; ++i) {
+      FxDesc f{};
+      f.M = p->norb; f.N = p->norb; f.K = p->nbf; f.batch = p->naux;
+      f.X = cpl + (long long)i * p->norb * ldk * 2; f.ldx = ldk; f.sx = 0; f.psx = ldc * ldk;
+      f.Y = (const float*)(a.ws + p->off[O_T]) + (long long)i * p->norb; f.ldy = ldc;
+      f.sy = (long long)p->nbf * ldc;
+      f.ey = ey + (long long)i * p->norb; f.sey = ldc;
+      f.Out = (float*)(a.ws + p->off[O_B]) + (long long)i * p->naux * n2; f.ldo = p->norb; f.so = n2;
+      f.Dg = (double*)(a.ws + p->off[O_D]) + (long long)i * p->naux * p->norb; f.sd = p->norb;
+      f.sym = true; f.role = 2;
+      const int rc = gemm_fx(f, true, false, st);
+      if (rc != NOF_OK) return rc;
+    }
+    return NOF_OK;
+  }
   GemmDesc g{};
   g.M = p->norb; g.N = p->norb; g.K = p->nbf;
   g.batch = p->ninst * p->naux; g.fold = 1; g.binner = p->naux;
@@ -177,6 +226,17 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const int fold = (p->naux + p->f2gpi - 1) / p->f2gpi;
   const int gpi = (p->naux + fold - 1) / fold;
   double* f2p = (double*)(a.ws + p->off[O_F2P]);
+  if (p->prec == NOF_P_BF16X10) {
+    // instance by instance (the FP32 copy of cK_i^T is rebuilt for each)
+    for (int i = 0; i < p->ninst; ++i) {
+      ExDesc e{p->naux, p->norb, fold, (const float*)(a.ws + p->off[O_B]) + (long long)i * p->naux * n2,
+               nullptr, f2p + (long long)i * gpi * n2};
+      const int rc = exchange_fock_fx(e, a.cK + (long long)i * n2, (float*)(a.ws + p->off[O_ST]), st);
+      if (rc != NOF_OK) return rc;
+    }
+    return reduce_parts(f2p, gpi, n2, p->norb, false, (double*)(a.ws + p->off[O_F2]), st, p->ninst,
+                        (long long)gpi * n2, n2);
+  }
   GemmDesc g{};
   g.M = p->norb; g.N = p->norb; g.K = p->norb;
   g.batch = p->ninst * p->naux; g.fold = fold; g.binner = p->naux;
@@ -576,7 +636,8 @@ int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int 
     if (ninst < 1 || ninst > 4096 || naux < 1 || nbf < 1 || norb < 1 || naux > (1 << 20) ||
         nbf > (1 << 16) || norb > (1 << 16))
       return NOF_E_DIM;
-    if (prec != NOF_P_F64 && prec != NOF_P_F32) return NOF_E_PREC;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32 && prec != NOF_P_BF16X10) return NOF_E_PREC;
+    if (prec == NOF_P_BF16X10 && (long long)ninst * norb > (1 << 20)) return NOF_E_DIM;
     nof_plan_s* p = new nof_plan_s();
     p->ninst = ninst; p->naux = naux; p->nbf = nbf; p->norb = norb; p->prec = prec;
     p->bt = prec == NOF_P_F64 ? NOF_F64 : NOF_F32;
@@ -640,10 +701,15 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     int rc = run_iteration(plan, a, stream);        // fills T, b, W with valid data
     if (rc != NOF_OK) return rc;
     const int reps = 3;
-    const int tiles[2] = {128, 64};
+    // the x10 kernels have one tile shape: only the exchange split is tuned
+    const bool fx = plan->prec == NOF_P_BF16X10;
+    const int tiles_all[2] = {128, 64};
+    const int ntiles = fx ? 1 : 2;
+    const int* tiles = tiles_all;
     float best = -1.f;
     int bt1 = plan->tile_s1;
-    for (int t : tiles) {
+    for (int it = 0; it < ntiles && !fx; ++it) {
+      const int t = tiles[it];
       plan->tile_s1 = t;
       const float ms = time_stage([&]() { return run_stage1(plan, a, stream); }, stream, reps);
       if (ms > 0.f && (best < 0.f || ms < best)) { best = ms; bt1 = t; }
@@ -651,7 +717,8 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     plan->tile_s1 = bt1;
     best = -1.f;
     int bt2 = plan->tile_s2;
-    for (int t : tiles) {
+    for (int it = 0; it < ntiles && !fx; ++it) {
+      const int t = tiles[it];
       plan->tile_s2 = t;
       const float ms = time_stage([&]() { return run_stage2(plan, a, stream); }, stream, reps);
       if (ms > 0.f && (best < 0.f || ms < best)) { best = ms; bt2 = t; }
@@ -660,7 +727,8 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     best = -1.f;
     int btf = plan->tile_f2, bg = plan->f2gpi;
     const int gmax = f2_target_gpi(plan, 64) * 4 > plan->naux ? plan->naux : f2_target_gpi(plan, 64) * 4;
-    for (int t : tiles) {
+    for (int it = 0; it < ntiles; ++it) {
+      const int t = tiles[it];
       const int g0 = f2_target_gpi(plan, t);
       const int cands[3] = {g0 / 2 > 0 ? g0 / 2 : 1, g0, 2 * g0};
       for (int g : cands) {

@@ -458,10 +458,11 @@ class BatchPlan:
     call, so update them in place between iterations)."""
 
     def __init__(self, B, C, H, n, cJ, cK, prec=None):
+        """B: FP64 (P_F64), FP32 (P_F32) or a SplitB (P_BF16X10)."""
         self.ninst, nbf, norb = C.shape
         naux = B.shape[0]
-        bt = _TDT[B.dtype]
-        self.prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+        bt = _b_arg(B)[0]
+        self.prec = (P_BF16X10 if bt == BF16X4 else _PREC_OF.get(bt, P_F64)) if prec is None else prec
         self.handle = _vp()
         check(lib.nof_plan_create(ctypes.byref(self.handle), self.ninst, naux, nbf, norb, self.prec),
               "nof_plan_create")
@@ -477,7 +478,7 @@ class BatchPlan:
 
     def _args(self):
         B, C, H, n, cJ, cK = self.inputs
-        return (self.handle, _p(B), _p(C), _p(H), _p(n), _p(cJ), _p(cK), _p(self.E), _p(self.lam),
+        return (self.handle, _b_arg(B)[1], _p(C), _p(H), _p(n), _p(cJ), _p(cK), _p(self.E), _p(self.lam),
                 _p(self.g), _p(self.ws), self.ws.numel())
 
     def iteration(self, stream=None):
@@ -513,7 +514,7 @@ class BatchPlan:
         prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit,
                           on_tol, tol_orth)
         res = (SolveResult * self.ninst)()
-        rc = lib.nof_plan_solve(self.handle, _p(B), _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
+        rc = lib.nof_plan_solve(self.handle, _b_arg(B)[1], _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
                                 int(mapping), int(functional), _f64(gamma, "gamma"), _p(n_out),
                                 ctypes.byref(prm), res, _p(self.solve_ws), self.solve_ws.numel(),
                                 stream_handle(stream))

@@ -63,6 +63,38 @@ def test_batch_matches_single_instance_every_config(prec_name):
             assert normwise(host(lam[i]), o["lam"]) <= 1e-10
 
 
+@pytest.mark.parametrize("src", ["f32", "f64"])
+def test_batch_x10_matches_single_instance(src):
+    """The fixed-point (x10) plan: B as planes, the packed C split once, stage
+    2 and the exchange-type term instance by instance; every instance equals
+    the single-instance x10 path (same grids and products; only the grouping
+    of FP64 partial sums differs), for several exchange splits and after the
+    autotuner, and one instance against the oracle on the FP32-rounded B."""
+    nof = need_gpu()
+    print(f"case batched x10 from {src}", flush=True)
+    ninst, nbf, naux, norb = 5, 130, 90, 110
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3002, 27)
+    Bin = B.astype(np.float32).astype(np.float64) if src == "f32" else B
+    Bs = nof.SplitB(dev(Bin, torch.float32 if src == "f32" else torch.float64))
+    plan = nof.BatchPlan(Bs, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
+    assert plan.prec == nof.P_BF16X10
+    ref = [single(nof, Bs, C[i], H[i], n[i], cJ[i], cK[i], nof.P_BF16X10) for i in range(ninst)]
+    for cfg in ([128, 128, 128, 1], [128, 128, 128, 3], [128, 128, 128, naux], None):
+        if cfg is None:
+            plan.autotune()
+        else:
+            plan.config = cfg
+        E, lam, g = plan.iteration()
+        torch.cuda.synchronize()
+        for i in range(ninst):
+            assert abs(float(E[i]) - ref[i][0]) <= 1e-12 * abs(ref[i][0]), (cfg, i)
+            assert normwise(host(lam[i]), ref[i][1]) <= 1e-12, (cfg, i)
+            assert normwise(host(g[i]), ref[i][2]) <= 1e-10, (cfg, i)
+    o = dfjk.iteration(Bin, C[1], H[1], n[1], cJ[1], cK[1])
+    assert abs(float(E[1]) - o["E"]) <= 2e-8 * abs(o["E"])
+    assert normwise(host(lam[1]), o["lam"]) <= 3e-7
+
+
 def test_autotune_and_graph_replays():
     nof = need_gpu()
     ninst, nbf, naux, norb = 9, 100, 70, 96
