@@ -22,11 +22,19 @@
 
 #include "common.h"
 
+namespace nof {
+// Regions of a plan's workspace (byte offsets in nof_plan_s::off).
+enum PlanRegion : int {
+  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_EP,
+  O_CPL, O_CMX, O_EY, O_ST, O_N      // the last four: the fixed-point (x10) form only
+};
+}  // namespace nof
+
 struct nof_plan_s {
   int ninst, naux, nbf, norb, prec, bt;
   int tile_s1, tile_s2, tile_f2, f2gpi;    // tuned choices
   int kchunks;
-  size_t off[16];
+  size_t off[nof::O_N];                    // one offset per region
   size_t total;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -35,11 +43,6 @@ struct nof_plan_s {
 
 namespace nof {
 namespace {
-
-enum {
-  O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_EP,
-  O_CPL, O_CMX, O_EY, O_ST, O_N      // the last four: the fixed-point (x10) form only
-};
 
 void plan_layout(nof_plan_s* p) {
   const size_t ni = p->ninst, na = p->naux, nb = p->nbf, no = p->norb;

@@ -95,6 +95,44 @@ def test_batch_x10_matches_single_instance(src):
     assert normwise(host(lam[1]), o["lam"]) <= 3e-7
 
 
+@pytest.mark.parametrize("prec_name", ["f64", "f32", "x10"])
+def test_plan_writes_stay_inside_workspace(prec_name):
+    """Every region of a plan's workspace lies inside the nof_plan_ws bytes it
+    reports: the workspace is a view into a larger buffer whose tail holds a
+    sentinel, and after iterations, the autotuner, a capture and graph replays
+    the tail is unchanged and the replayed energies equal the eager ones."""
+    nof = need_gpu()
+    print(f"case plan workspace bounds {prec_name}", flush=True)
+    ninst, nbf, naux, norb = 4, 100, 70, 96
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3002, 24)
+    if prec_name == "x10":
+        Bp = nof.SplitB(dev(B))
+    else:
+        Bp = dev(B, torch.float32 if prec_name == "f32" else torch.float64)
+    plan = nof.BatchPlan(Bp, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
+    need = plan.ws.numel()
+    tail = 64 << 20
+    big = torch.empty(need + tail, dtype=torch.uint8, device=plan.ws.device)
+    big[need:] = 0xA5
+    plan.ws = big[:need]
+    E0 = plan.iteration()[0].clone()
+    plan.autotune()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(s)
+        for _ in range(2):
+            plan.launch(s)
+    s.synchronize()
+    Eg = plan.E.clone()
+    E1 = plan.iteration()[0].clone()
+    torch.cuda.synchronize()
+    assert bool((big[need:] == 0xA5).all())
+    assert torch.equal(Eg, E1)
+    # the tuner may change the FP32 tiles (summation order of the products)
+    tol = 1e-6 if prec_name == "f32" else 1e-10
+    assert float((E0 - E1).abs().max()) <= tol * float(E1.abs().max())
+
+
 def test_autotune_and_graph_replays():
     nof = need_gpu()
     ninst, nbf, naux, norb = 9, 100, 70, 96
