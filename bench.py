@@ -434,12 +434,45 @@ def run_batched(nof, inputs, dev, steps=5):
     torch.cuda.synchronize()
     ms_single = e0.elapsed_time(e1)
     f = algorithmic_flops(nbf, naux, norb)["total"] * 25
+    E32 = plan.E.clone()
+    C_start = Cd.clone()
     solve = run_batched_solve(nof, plan, Bd, Cd, Hd, members, w, dev, s)
+    Cd.copy_(C_start)                     # the solve leaves its orbitals in C
+    # the same batch in the fixed-point x10 form (B split once into planes from
+    # FP64) and in FP64, both autotuned and replayed from a graph; energies
+    # of the three against the FP64 batch
+    del T, b, D
+    torch.cuda.empty_cache()
+    B64 = d(B)
+    out = {}
+    for name, Bp in (("x10", nof.SplitB(B64)), ("f64", B64)):
+        pl = nof.BatchPlan(Bp, Cd, Hd, nd, cJd, cKd)
+        pl.autotune()
+        with torch.cuda.stream(s):
+            pl.capture(s)
+            pl.launch(s)
+        s.synchronize()
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for _ in range(steps):
+                pl.launch(s)
+            e1.record(s)
+        s.synchronize()
+        out[name] = (e0.elapsed_time(e1) / steps, pl.E.clone())
+        del pl, Bp
+        torch.cuda.empty_cache()
+    ms_x10, Ex10 = out["x10"]
+    ms_64, E64 = out["f64"]
     return {"workload": "field300: 25 finite-field instances, Nbf=300 Naux=1200 Norb=300, FP32 products",
             "ms_per_iteration_batched_graph": ms_batch, "ms_per_iteration_25_single": ms_single,
             "speedup": ms_single / ms_batch, "tflops_batched": f / (ms_batch * 1e-3) / 1e12,
             "tuned_config": {"tile_stage1": cfg[0], "tile_stage2": cfg[1], "tile_exchange": cfg[2],
                              "exchange_p_split": cfg[3]},
+            "max_abs_dE_Eh_vs_f64": float((E32 - E64).abs().max()),
+            "x10": {"ms_per_iteration_batched_graph": ms_x10, "tflops": f / (ms_x10 * 1e-3) / 1e12,
+                    "speedup_vs_fp32_batch": ms_batch / ms_x10, "speedup_vs_f64_batch": ms_64 / ms_x10,
+                    "max_abs_dE_Eh_vs_f64": float((Ex10 - E64).abs().max())},
+            "f64": {"ms_per_iteration_batched_graph": ms_64},
             "solve": solve}
 
 
