@@ -66,13 +66,13 @@ void plan_layout(nof_plan_s* p) {
   sz[O_F2] = ni * n2;
   sz[O_EP] = energy_ws((int)ni);
   // x10: planes of the packed C, column maxima of T per row tile, the grid
-  // exponents of T's columns, cK transposed in FP32 (one instance at a time)
+  // exponents of T's columns, every instance's cK transposed in FP32
   const bool fx = p->prec == NOF_P_BF16X10;
   const size_t ldk = (size_t)presplit_ldk(p->nbf), ldc = ni * no;
   sz[O_CPL] = fx ? 4 * ldc * ldk * 2 : 0;
   sz[O_CMX] = fx ? na * (size_t)fx_tiles(p->nbf) * ldc * 4 : 0;
   sz[O_EY] = fx ? na * ldc * 4 : 0;
-  sz[O_ST] = fx ? no * no * 4 : 0;
+  sz[O_ST] = fx ? ni * no * no * 4 : 0;
   size_t o = 0;
   for (int i = 0; i < O_N; ++i) {
     p->off[i] = o;
@@ -230,13 +230,13 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const int gpi = (p->naux + fold - 1) / fold;
   double* f2p = (double*)(a.ws + p->off[O_F2P]);
   if (p->prec == NOF_P_BF16X10) {
-    // instance by instance (the FP32 copy of cK_i^T is rebuilt for each)
-    for (int i = 0; i < p->ninst; ++i) {
-      ExDesc e{p->naux, p->norb, fold, (const float*)(a.ws + p->off[O_B]) + (long long)i * p->naux * n2,
-               nullptr, f2p + (long long)i * gpi * n2};
-      const int rc = exchange_fock_fx(e, a.cK + (long long)i * n2, (float*)(a.ws + p->off[O_ST]), st);
-      if (rc != NOF_OK) return rc;
-    }
+    // every instance in one launch (cK_i^T in FP32 for each)
+    ExDesc e{p->naux, p->norb, fold, (const float*)(a.ws + p->off[O_B]), nullptr, f2p};
+    e.ninst = p->ninst;
+    e.sb = (long long)p->naux * n2;
+    e.so = (long long)gpi * n2;
+    const int rc = exchange_fock_fx(e, a.cK, (float*)(a.ws + p->off[O_ST]), st);
+    if (rc != NOF_OK) return rc;
     return reduce_parts(f2p, gpi, n2, p->norb, false, (double*)(a.ws + p->off[O_F2]), st, p->ninst,
                         (long long)gpi * n2, n2);
   }

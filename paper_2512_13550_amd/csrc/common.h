@@ -104,11 +104,15 @@ inline int fx_tiles(int n) { return (n + 127) / 128; }
 //   Out[g][r][s] = sum_{P in [g*fold, (g+1)*fold)} sum_q b^P[q][r] S[q][s] b^P[q][s]
 // b FP32 [naux][norb][norb] symmetric slabs; S FP64 [norb][norb]; St a
 // norb*norb FP32 scratch (S transposed); Out FP64 [groups][norb][norb].
+// ninst > 1: instance i reads b + i*sb, S + i*norb^2 and writes Out + i*so;
+// St then holds ninst transposed copies (norb^2 apart).
 struct ExDesc {
   int naux, norb, fold;
   const float* b;
   const float* St;
   double* Out;
+  int ninst = 1;
+  long long sb = 0, so = 0;
 };
 int exchange_fock_fx(const ExDesc& d, const double* S, float* St, hipStream_t st);
 // Grid exponents (2^E above the largest |value|) of rows of A[nrow][K] (FP64/FP32)

@@ -478,11 +478,16 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   const int wm = w >> 2, wn = w & 3;
 
   const int logical = xcd_logical(blockIdx.x, gridDim.x);
-  const int grp = logical / ntiles;
-  const int t = logical - grp * ntiles;
+  const int ngrp = (d.naux + d.fold - 1) / d.fold;
+  const int inst = logical / (ngrp * ntiles);
+  const int r = logical - inst * (ngrp * ntiles);
+  const int grp = r / ntiles;
+  const int t = r - grp * ntiles;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
   const int m0 = tm * FT, n0 = tn * FT;
   const int n = d.norb;
+  const float* __restrict__ bI = d.b + (long long)inst * d.sb;
+  const float* __restrict__ StI = d.St + (long long)inst * n * n;
   const int nkb = (n + KT - 1) / KT;
   const int p_lo = grp * d.fold;
   const int p_hi = min(d.naux, p_lo + d.fold);
@@ -497,10 +502,10 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   auto load = [&](int s, ExRaw& r) {
     const int pb = p_lo + s / nkb;
     const int k0 = qbase(s);
-    const float* bp = d.b + (long long)pb * n * n;
+    const float* bp = bI + (long long)pb * n * n;
     const float* px = bp + (long long)xrow * n;
     const float* py = bp + (long long)yrow * n;
-    const float* ps = d.St + (long long)yrow * n;
+    const float* ps = StI + (long long)yrow * n;
     if constexpr (VEC) {
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
@@ -614,7 +619,7 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   }
   if (s < nstage) compute(s, 0);
 
-  double* __restrict__ Out = d.Out + (long long)grp * n * n;
+  double* __restrict__ Out = d.Out + (long long)inst * d.so + (long long)grp * n * n;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -632,13 +637,14 @@ __global__ __launch_bounds__(NTHR, 1) void k_exchange_fock_fx(ExDesc d, int tile
   exch_body<VEC>(d, tiles_n, ntiles);
 }
 
-// St[s][q] = (float)S[q][s]
-__global__ void k_transpose_f32(const double* __restrict__ S, int n, float* __restrict__ St) {
-  const long long total = (long long)n * n;
+// St_i[s][q] = (float)S_i[q][s] for ninst matrices n^2 apart
+__global__ void k_transpose_f32(const double* __restrict__ S, int n, int ninst, float* __restrict__ St) {
+  const long long nn = (long long)n * n, total = nn * ninst;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
-    const long long s = i / n, q = i - s * n;
-    St[i] = (float)S[q * n + s];
+    const long long y = i / nn, e = i - y * nn;
+    const long long s = e / n, q = e - s * n;
+    St[i] = (float)S[y * nn + q * n + s];
   }
 }
 
@@ -695,9 +701,10 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
 }
 
 int exchange_fock_fx(const ExDesc& d0, const double* S, float* St, hipStream_t st) {
-  if (d0.naux <= 0 || d0.norb <= 0 || d0.fold <= 0) return NOF_E_DIM;
+  if (d0.naux <= 0 || d0.norb <= 0 || d0.fold <= 0 || d0.ninst <= 0) return NOF_E_DIM;
   const long long nn = (long long)d0.norb * d0.norb;
-  hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)grid_for(nn, 256)), dim3(256), 0, st, S, d0.norb, St);
+  hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)grid_for(nn * d0.ninst, 256)), dim3(256), 0, st, S,
+                     d0.norb, d0.ninst, St);
   const int rc = launch_status();
   if (rc != NOF_OK) return rc;
   ExDesc d = d0;
@@ -705,7 +712,7 @@ int exchange_fock_fx(const ExDesc& d0, const double* S, float* St, hipStream_t s
   const int tiles_n = (d.norb + FT - 1) / FT;
   const int ntiles = tiles_n * tiles_n;
   const int groups = (d.naux + d.fold - 1) / d.fold;
-  const long long G = (long long)ntiles * groups;
+  const long long G = (long long)ntiles * groups * d.ninst;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
   if (d.norb % 4 == 0)
     hipLaunchKernelGGL(k_exchange_fock_fx<true>, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
