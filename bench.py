@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--cpu-slabs", type=int, default=160,
                     help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--batched", type=int, default=1,
-                    help="1: also time the 25-instance finite-field batch (graph launch)")
+                    help="1: also time the 25-instance finite-field batch (graph launch); "
+                         "2: time only that batch and print its record (for kernel profiles)")
     ap.add_argument("--precision-workload", default="chain1000",
                     help="also time FP64 against the x10 forms on this workload in a child run "
                          "('' = skip)")
@@ -106,6 +107,10 @@ def main():
     import paper_2512_13550_amd.nof as nof
     from paper_2512_13550_amd import inputs
 
+    if args.batched == 2:
+        rec = run_batched(nof, inputs, torch.device("cuda:0"), steps=args.steps)
+        print(json.dumps({"batched": rec}))
+        return
     w = inputs.WORKLOADS[args.workload]
     nbf, naux, norb = w.nbf, w.naux, w.norb
     t0 = time.time()
