@@ -152,3 +152,61 @@ def test_batched_hf_finite_field_end_to_end():
     for p, scale in enumerate((1.0 / step, 1.0 / step ** 2, 1.0 / step ** 3)):
         print(p, Rs[p, 0], ref[p]["value"], flush=True)
         assert abs(Rs[p, 0] - ref[p]["value"]) <= 4.0 * e * scale
+
+
+def test_batched_solve_x10_plan_matches_fp64():
+    """The batched NO loop on an x10 plan (B as fixed-point planes of the FP64
+    B), NO steps replayed from a graph on a side stream, converges like the
+    same loop on the FP64 plan (HF finite fields), and the two converged
+    energies agree within the 1e-6 Eh bar, as do the two plans' energies at
+    the FP64 solution (the x10 evaluation error).  The loops stop at
+    |lambda - lambda^T| <= 1e-6, which leaves each run ~1e-8 - 1e-7 Eh above
+    its minimum, so the two differences are not compared with each other.  (Unconverged
+    trajectories are not compared: ADAM normalises every gradient component,
+    so rounding noise in components near zero changes whole steps.)"""
+    nof = need_gpu()
+    print("case batched solve x10 plan vs fp64 hf nbf=16 x3", flush=True)
+    nbf, naux, nocc = 16, 64, 4
+    B = inputs.make_B_grid(nbf, naux, seed=2)
+    H0 = inputs.make_H(2, nbf)
+    d = inputs.make_dipoles(2, nbf)[2]
+    Hs = field_instances(H0, d, [-0.004, 0.0, 0.004])
+    C0, _ = scf_orbitals(B, H0, nocc)
+    members = torch.from_numpy(np.array(inputs.pairing(nbf, nocc, 1), dtype=np.int32)).cuda()
+    Bd = dev(B)
+    Z = torch.zeros((nbf, nbf), dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+
+    def plan_of(name, C, n):
+        cJ = torch.empty((3, nbf, nbf), dtype=torch.float64, device="cuda")
+        cK = torch.empty_like(cJ)
+        for i in range(3):
+            cJ[i], cK[i] = nof.coeffs_from_cumulant(n[i], Z, Z)
+        return nof.BatchPlan(nof.SplitB(Bd) if name == "x10" else Bd, C, dev(Hs), n, cJ, cK)
+
+    out = {}
+    for name in ("f64", "x10"):
+        C = dev(np.stack([C0] * 3))
+        n = torch.zeros((3, nbf), dtype=torch.float64, device="cuda")
+        plan = plan_of(name, C, n)
+        assert plan.prec == (nof.P_BF16X10 if name == "x10" else nof.P_F64)
+        gamma = dev(np.zeros((3, nocc, 1)))
+        nout = torch.empty((3, nbf), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            res = plan.solve(members, nof.MAP_TRIG, nof.FUNC_HF, gamma, n_out=nout, stream=side,
+                             max_outer=3, no_steps=4000, tol_lambda=1e-6, on_maxit=0, lr=1e-3)
+        torch.cuda.synchronize()
+        out[name] = (res, C, nout)
+    (r64, C64, n64), (r10, _, _) = out["f64"], out["x10"]
+    # both plans' energies at the FP64 solution
+    e_at = {name: host(plan_of(name, C64.clone(), n64).iteration()[0]).copy() for name in ("f64", "x10")}
+    for i in range(3):
+        ev = abs(e_at["x10"][i] - e_at["f64"][i])
+        dE = abs(r10[i]["E"] - r64[i]["E"])
+        print(f"instance {i}: f64 {r64[i]['E']:.12f} x10 {r10[i]['E']:.12f} dE {dE:.2e} "
+              f"x10 evaluation error {ev:.2e} steps {r64[i]['no_steps']} {r10[i]['no_steps']}", flush=True)
+        assert r64[i]["converged"] == 1 and r10[i]["converged"] == 1, (r64[i], r10[i])
+        assert r10[i]["status"] == 0 and r10[i]["orth"] <= 1e-12
+        assert abs(e_at["f64"][i] - r64[i]["E"]) <= 1e-10 * abs(r64[i]["E"])
+        assert dE <= 1e-6 and ev <= 1e-6
