@@ -137,25 +137,19 @@ int run_stage2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long ldc = (long long)p->ninst * p->norb;
   const long long n2 = (long long)p->norb * p->norb;
   if (p->prec == NOF_P_BF16X10) {
-    // instance i: its C planes are columns i*norb.. of the packed planes, its
-    // T^P columns i*norb.. of T, with their grid exponents
+    // instance i (outer index): its C planes are columns i*norb.. of the
+    // packed planes, its T^P columns i*norb.. of T, with their grid exponents
     const long long ldk = presplit_ldk(p->nbf);
-    const char* cpl = a.ws + p->off[O_CPL];
-    const int* ey = (const int*)(a.ws + p->off[O_EY]);
-    for (int i = 0; i < p->ninst; ++i) {
-      FxDesc f{};
-      f.M = p->norb; f.N = p->norb; f.K = p->nbf; f.batch = p->naux;
-      f.X = cpl + (long long)i * p->norb * ldk * 2; f.ldx = ldk; f.sx = 0; f.psx = ldc * ldk;
-      f.Y = (const float*)(a.ws + p->off[O_T]) + (long long)i * p->norb; f.ldy = ldc;
-      f.sy = (long long)p->nbf * ldc;
-      f.ey = ey + (long long)i * p->norb; f.sey = ldc;
-      f.Out = (float*)(a.ws + p->off[O_B]) + (long long)i * p->naux * n2; f.ldo = p->norb; f.so = n2;
-      f.Dg = (double*)(a.ws + p->off[O_D]) + (long long)i * p->naux * p->norb; f.sd = p->norb;
-      f.sym = true; f.role = 2;
-      const int rc = gemm_fx(f, true, false, st);
-      if (rc != NOF_OK) return rc;
-    }
-    return NOF_OK;
+    FxDesc f{};
+    f.M = p->norb; f.N = p->norb; f.K = p->nbf;
+    f.batch = p->ninst * p->naux; f.binner = p->naux;
+    f.X = a.ws + p->off[O_CPL]; f.ldx = ldk; f.sx = 0; f.sx2 = (long long)p->norb * ldk; f.psx = ldc * ldk;
+    f.Y = a.ws + p->off[O_T]; f.ldy = ldc; f.sy = (long long)p->nbf * ldc; f.sy2 = p->norb;
+    f.ey = (const int*)(a.ws + p->off[O_EY]); f.sey = ldc; f.sey2 = p->norb;
+    f.Out = (float*)(a.ws + p->off[O_B]); f.ldo = p->norb; f.so = n2; f.so2 = (long long)p->naux * n2;
+    f.Dg = (double*)(a.ws + p->off[O_D]); f.sd = p->norb; f.sd2 = (long long)p->naux * p->norb;
+    f.sym = true; f.role = 2;
+    return gemm_fx(f, true, false, st);
   }
   GemmDesc g{};
   g.M = p->norb; g.N = p->norb; g.K = p->nbf;

@@ -95,6 +95,10 @@ struct FxDesc {
   bool x_rows;                     // FP32 X symmetric per batch: may be read m-major (rows)
   unsigned* cmax; long long scm;   // optional: per row tile t the FP32 bits of max_m |Out_b[m][n]|
                                    // over the tile's rows -> cmax[b*scm + t*N + n] (not sym)
+  // Two-level batching (binner > 0, not with cmax): batch b = outer * binner +
+  // inner; X, Y, ey, Out, Dg at inner * s? + outer * s?2
+  int binner = 0;
+  long long sx2 = 0, sy2 = 0, sey2 = 0, so2 = 0, sd2 = 0;
 };
 int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
 // Column grid exponents e[b*N + n] from the row-tile maxima above.

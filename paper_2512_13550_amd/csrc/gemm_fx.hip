@@ -239,6 +239,12 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   const int bb = logical / ntiles;
   int tm, tn;
   tile_of(logical - bb * ntiles, tiles_n, d.sym, tm, tn);
+  long long ob = 0, ib = bb;                  // outer and inner batch index
+  if (d.binner > 0) {
+    ob = bb / d.binner;
+    ib = bb - ob * d.binner;
+  }
+  const long long offx = ib * d.sx + ob * d.sx2, offy = ib * d.sy + ob * d.sy2;
   const int m0 = tm * FT, n0 = tn * FT;
   const int nstage = (d.K + KT - 1) / KT;
 
@@ -251,7 +257,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   const int cy = YPS ? tid >> 2 : tid & (FT - 1), kqy = YPS ? tid & 3 : tid >> 7;
   const bool xok = m0 + cx < d.M, yok = n0 + cy < d.N;
   const int ex = (!XPS && xok) ? d.ex[(long long)bb * d.sex + m0 + cx] : 0;
-  const int ey = (!YPS && yok) ? d.ey[(long long)bb * d.sey + n0 + cy] : 0;
+  const int ey = (!YPS && yok) ? d.ey[ib * d.sey + ob * d.sey2 + n0 + cy] : 0;
 
   bf8v xp[XPS ? 4 : 1], yp[YPS ? 4 : 1];
   float xr[XPS ? 1 : 8], yr[YPS ? 1 : 8];
@@ -260,11 +266,11 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     int k0 = s * KT + 8 * kqx;
     int kl = d.K - k0;
     if constexpr (XPS) {
-      const __bf16* p = (const __bf16*)d.X + (long long)bb * d.sx + (long long)(m0 + cx) * d.ldx + k0;
+      const __bf16* p = (const __bf16*)d.X + offx + (long long)(m0 + cx) * d.ldx + k0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) xp[XPS ? q : 0] = xok ? *(const bf8v*)(p + (long long)q * d.psx) : bf8v{};
     } else if constexpr (XM == 2) {
-      const float* p = (const float*)d.X + (long long)bb * d.sx + (long long)(m0 + cx) * d.ldx + k0;
+      const float* p = (const float*)d.X + offx + (long long)(m0 + cx) * d.ldx + k0;
       if (xok && kl >= 8) {
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
@@ -277,18 +283,18 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
         for (int j = 0; j < 8; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[j] : 0.f;
       }
     } else {
-      const float* p = (const float*)d.X + (long long)bb * d.sx + (long long)k0 * d.ldx + m0 + cx;
+      const float* p = (const float*)d.X + offx + (long long)k0 * d.ldx + m0 + cx;
 #pragma unroll
       for (int j = 0; j < 8; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[(long long)j * d.ldx] : 0.f;
     }
     k0 = s * KT + 8 * kqy;
     kl = d.K - k0;
     if constexpr (YPS) {
-      const __bf16* p = (const __bf16*)d.Y + (long long)bb * d.sy + (long long)(n0 + cy) * d.ldy + k0;
+      const __bf16* p = (const __bf16*)d.Y + offy + (long long)(n0 + cy) * d.ldy + k0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) yp[YPS ? q : 0] = yok ? *(const bf8v*)(p + (long long)q * d.psy) : bf8v{};
     } else {
-      const float* p = (const float*)d.Y + (long long)bb * d.sy + (long long)k0 * d.ldy + n0 + cy;
+      const float* p = (const float*)d.Y + offy + (long long)k0 * d.ldy + n0 + cy;
 #pragma unroll
       for (int j = 0; j < 8; ++j) yr[YPS ? 0 : j] = (yok && j < kl) ? p[(long long)j * d.ldy] : 0.f;
     }
@@ -400,7 +406,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     __syncthreads();
   }
 
-  float* __restrict__ Out = d.Out + (long long)bb * d.so;
+  float* __restrict__ Out = d.Out + ib * d.so + ob * d.so2;
   int cm[2] = {0, 0};      // bits of the largest |stored value| per column fragment
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -420,7 +426,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
         } else if (gm <= gn) {
           Out[(long long)gm * d.ldo + gn] = fv;
           Out[(long long)gn * d.ldo + gm] = fv;
-          if (gm == gn && d.Dg) d.Dg[(long long)bb * d.sd + gm] = v;
+          if (gm == gn && d.Dg) d.Dg[ib * d.sd + ob * d.sd2 + gm] = v;
         }
       }
   if (d.cmax) {
@@ -685,6 +691,7 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
   if (d.M < 0 || d.N < 0 || d.K < 0 || d.batch < 0) return NOF_E_DIM;
   if (d.sym && (d.M != d.N)) return NOF_E_DIM;
   if ((!x_planes && !d.ex) || (!y_planes && !d.ey)) return NOF_E_NULL;
+  if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
   const bool big = d.K > EXACT_K;
   if (x_planes && y_planes)
     return big ? launch_fx<0, true, true>(d, st) : launch_fx<0, true, false>(d, st);
