@@ -344,8 +344,9 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
  *          (prec NOF_P_F32: FP32 matrix-core products, FP64 reductions), or
  *          the fixed-point planes of nof_split_B (prec NOF_P_BF16X10: the x10
  *          transform and exchange-type term of nof_mo_transform and
- *          nof_gen_fock, instance by instance after the shared first stage;
- *          ninst * norb <= 2^20)
+ *          nof_gen_fock: one first-stage launch over the packed columns, the
+ *          second stage and the exchange-type term of all instances in one
+ *          launch each; ninst * norb <= 2^20)
  *   C      [ninst][nbf][norb]     H  [ninst][nbf][nbf]    n  [ninst][norb]
  *   cJ, cK [ninst][norb][norb] (symmetric)
  *   E      out [ninst]      lambda, grad  out [ninst][norb][norb] (grad may be NULL)
