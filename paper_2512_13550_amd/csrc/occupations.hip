@@ -87,25 +87,24 @@ OccWs occ_ws_ptrs(void* ws, int norb, int ns, int ng) {
 }
 
 // ---- block-wide deterministic reductions -----------------------------------
+// Each wave reduces its 64 values with a butterfly (lane 0's value is kept),
+// then every thread adds the OW wave results in wave order: two barriers, the
+// same order on every call, the same result in every thread.
 __device__ double block_sum(double a, double* red) {
-  red[threadIdx.x] = a;
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
   __syncthreads();
-  for (int w = OT / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int i = 1; i < OW; ++i) r += red[i];
   __syncthreads();
   return r;
 }
 __device__ double block_max(double a, double* red) {
-  red[threadIdx.x] = a;
+  for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
   __syncthreads();
-  for (int w = OT / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+  for (int i = 1; i < OW; ++i) r = fmax(r, red[i]);
   __syncthreads();
   return r;
 }
@@ -189,20 +188,43 @@ __device__ double evaluate(const OccProblem& P, const double* x, double* n, doub
     for (int r = tid; r < P.norb; r += OT) P.phi[r] = sqrt(n[r] * (1.0 - n[r]));
     __syncthreads();
   }
-  // v = M n (PNOF7 also u = K Phi), one wave per row
+  // v = M n (PNOF7 also u = K Phi): a wave takes RW rows at a time (their
+  // loads in flight together), each row summed lane-wise over q and then
+  // across the wave, the same order for any RW
+  constexpr int RW = 4;
   const int lane = tid & 63, wv = tid >> 6;
-  for (int r = wv; r < P.norb; r += OW) {
-    const double* Mr = P.M + (long long)r * P.norb;
-    double s = 0.0;
-    for (int q = lane; q < P.norb; q += 64) s = fma(Mr[q], n[q], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) v[r] = s;
-    if (p7) {
-      const double* Kr = P.K + (long long)r * P.norb;
-      double t = 0.0;
-      for (int q = lane; q < P.norb; q += 64) t = fma(Kr[q], P.phi[q], t);
-      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-      if (lane == 0) P.u[r] = t;
+  for (int r0 = wv; r0 < P.norb; r0 += RW * OW) {
+    double s[RW], t[RW];
+    const double* Mr[RW];
+    const double* Kr[RW];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int r = min(r0 + j * OW, P.norb - 1);
+      Mr[j] = P.M + (long long)r * P.norb;
+      Kr[j] = p7 ? P.K + (long long)r * P.norb : nullptr;
+      s[j] = 0.0;
+      t[j] = 0.0;
+    }
+    for (int q = lane; q < P.norb; q += 64) {
+      const double nq = n[q];
+#pragma unroll
+      for (int j = 0; j < RW; ++j) s[j] = fma(Mr[j][q], nq, s[j]);
+      if (p7) {
+        const double pq = P.phi[q];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) t[j] = fma(Kr[j][q], pq, t[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      for (int o = 32; o > 0; o >>= 1) s[j] += __shfl_xor(s[j], o, 64);
+      if (p7)
+        for (int o = 32; o > 0; o >>= 1) t[j] += __shfl_xor(t[j], o, 64);
+      const int r = r0 + j * OW;
+      if (lane == 0 && r < P.norb) {
+        v[r] = s[j];
+        if (p7) P.u[r] = t[j];
+      }
     }
   }
   __syncthreads();
