@@ -364,7 +364,31 @@ __global__ __launch_bounds__(OT) void k_occ_eval(OccProblem P, OccWs w, const do
 struct LbfgsParams {
   int maxit, maxbt;
   double tol, etol, loose, c1, step0;
+  int lds;          // > 0: the iteration vectors live in that many doubles of dynamic LDS
 };
+
+// Doubles of LDS for the iteration vectors of one problem: x, g, d, xt, gt
+// (nv each), the LM pairs S, Y, then n, nt, dn, v, phi, u (norb each) and
+// sy, yy (LM each); 0 when they do not fit beside the reduction buffer.
+constexpr size_t kOccLdsMax = 144 * 1024;
+int occ_lds_doubles(int norb, int ns, int ng) {
+  const size_t nv = (size_t)ns * ng;
+  const size_t d = 5 * nv + 2 * (size_t)LM * nv + 6 * (size_t)norb + 2 * LM;
+  return d * sizeof(double) <= kOccLdsMax ? (int)d : 0;
+}
+
+// Point the iteration vectors of w (and P's phi, u) at LDS (layout above).
+__device__ void vectors_to_lds(OccProblem& P, OccWs& w, double* sm, int nv) {
+  const int no = P.norb;
+  double* p = sm;
+  auto take = [&](long long k) { double* q = p; p += k; return q; };
+  w.x = take(nv); w.g = take(nv); w.d = take(nv); w.xt = take(nv); w.gt = take(nv);
+  w.S = take((long long)LM * nv); w.Y = take((long long)LM * nv);
+  w.n = take(no); w.nt = take(no); w.dn = take(no); w.v = take(no); w.phi = take(no); w.u = take(no);
+  w.sy = take(LM); w.yy = take(LM);
+  P.phi = w.phi;
+  P.u = w.u;
+}
 
 __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsParams L,
                                                   double* gamma, double* n_out, double* E_out,
@@ -381,6 +405,8 @@ __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsPa
   if (!setup(P, w, info, red)) return;
   const int tid = threadIdx.x;
   const int nv = P.ns * P.ng;
+  extern __shared__ double occ_sm[];
+  if (L.lds > 0) vectors_to_lds(P, w, occ_sm, nv);
   for (int i = tid; i < nv; i += OT) w.x[i] = gamma[i];
   __syncthreads();
   double E = evaluate(P, w.x, w.n, w.dn, w.v, w.g, red);
@@ -551,6 +577,22 @@ int occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int f
   return launch_status();
 }
 
+
+// LDS doubles for k_occ_lbfgs's vectors (0: they stay in the workspace); the
+// kernel's dynamic-LDS limit is raised to that size first.
+int lbfgs_lds(int norb, int ns, int ng) {
+  const int d = occ_lds_doubles(norb, ns, ng);
+  if (d == 0) return 0;
+  const size_t bytes = (size_t)d * sizeof(double);
+  if (bytes > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_occ_lbfgs),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return d;
+}
+
 int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func,
                  const double* hdiag, int hstride, const double* J, const double* K,
                  double* gamma, double* n, double* E, int* info, int maxit, double tol, void* ws,
@@ -562,8 +604,9 @@ int occ_optimize(int norb, int ns, int ng, const int* members, int map, int func
   LbfgsParams L;
   L.maxit = maxit; L.maxbt = 50; L.tol = tol; L.etol = 1e-14; L.loose = 1e-5; L.c1 = 1e-4;
   L.step0 = 0.1;
-  hipLaunchKernelGGL(k_occ_lbfgs, dim3(1), dim3(OT), 0, st, P, w, L, gamma, n, E, info,
-                     OccBatch{});
+  L.lds = lbfgs_lds(norb, ns, ng);
+  hipLaunchKernelGGL(k_occ_lbfgs, dim3(1), dim3(OT), (size_t)L.lds * sizeof(double), st, P, w, L, gamma,
+                     n, E, info, OccBatch{});
   return launch_status();
 }
 
@@ -583,7 +626,9 @@ int occ_batched(int ninst, const int* active, int norb, int ns, int ng, const in
     LbfgsParams L;
     L.maxit = maxit; L.maxbt = 50; L.tol = tol; L.etol = 1e-14; L.loose = 1e-5; L.c1 = 1e-4;
     L.step0 = 0.1;
-    hipLaunchKernelGGL(k_occ_lbfgs, dim3(ninst), dim3(OT), 0, st, P, w, L, gamma, n, E, info, ib);
+    L.lds = lbfgs_lds(norb, ns, ng);
+    hipLaunchKernelGGL(k_occ_lbfgs, dim3(ninst), dim3(OT), (size_t)L.lds * sizeof(double), st, P, w, L,
+                       gamma, n, E, info, ib);
   } else {
     hipLaunchKernelGGL(k_occ_eval, dim3(ninst), dim3(OT), 0, st, P, w, gamma, n, E,
                        (double*)nullptr, info, ib);
