@@ -511,7 +511,8 @@ def run_batched_solve(nof, plan, Bd, Cd, Hd, members, w, dev, stream, outer=2, s
     ms_s = (time.perf_counter() - t0) * 1e3
     return {"outer": outer, "no_steps_per_outer": steps, "on_maxit": kw["on_maxit"],
             "ms_batched": ms_b, "ms_25_single": ms_s, "speedup": ms_s / ms_b,
-            "statuses_ok": all(r["status"] == 0 for r in res)}
+            "statuses_ok": all(r["status"] == 0 for r in res),
+            "on_iters_per_instance_mean": float(np.mean([r["on_iters"] for r in res]))}
 
 
 def run_warmstart(nof, ntrain, nheld=20):
