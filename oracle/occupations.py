@@ -10,7 +10,11 @@ trigonometric:  n_g = (1 + cos^2 gamma_g) / 2, hole h_g = 1 - n_g,
                 n_{p_Ng} = h_g cos^2 theta_1 ... cos^2 theta_{Ng-1};
                 variables per subspace: (gamma_g, theta_1 .. theta_{Ng-1}).
 softmax:        n_g = 1 / (1 + sum_k exp(gamma_k)), n_{p_i} = n_g exp(gamma_i);
-                variables per subspace: (gamma_1 .. gamma_Ng).
+                variables per subspace: (gamma_1 .. gamma_Ng).  Evaluated with
+                numerator and denominator scaled by exp(-m), m = max(0, max_k
+                gamma_k), so that no exponential overflows: the same values for
+                every gamma, finite and summing to one also where exp(gamma_k)
+                alone would overflow (gamma_k > 709).
 
 gamma is stored (ns, ng).  The optimiser (parity reference for the GPU) is a
 limited-memory BFGS with a backtracking Armijo line search.
@@ -30,7 +34,7 @@ def occupations(gamma, members, norb, mapping):
         row = members[g]
         if mapping == "trig":
             ng_ = 0.5 * (1.0 + np.cos(gamma[g, 0]) ** 2)
-            hole = 1.0 - ng_
+            hole = 0.5 * np.sin(gamma[g, 0]) ** 2      # = 1 - n_g, without cancellation
             n[row[0]] = ng_
             P = 1.0
             for i in range(1, ng):
@@ -39,10 +43,11 @@ def occupations(gamma, members, norb, mapping):
                 P *= np.cos(th) ** 2
             n[row[ng]] = hole * P
         elif mapping == "softmax":
-            e = np.exp(gamma[g])
-            ng_ = 1.0 / (1.0 + e.sum())
-            n[row[0]] = ng_
-            n[row[1:]] = ng_ * e
+            m = max(0.0, float(np.max(gamma[g])))
+            e = np.exp(gamma[g] - m)                  # every factor <= 1
+            den = np.exp(-m) + e.sum()                # >= 1 term equal to 1
+            n[row[0]] = np.exp(-m) / den
+            n[row[1:]] = e / den
         else:
             raise ValueError(mapping)
     return n
@@ -63,7 +68,7 @@ def chain_rule(gamma, members, norb, mapping, dEdn):
             out[g] = nn_[1:] * (gn[1:] - gbar)
             continue
         cg, sg = np.cos(gamma[g, 0]), np.sin(gamma[g, 0])
-        hole = 1.0 - 0.5 * (1.0 + cg * cg)
+        hole = 0.5 * sg * sg
         # weak part: n_{p_i} = hole * Pprev_i * t_i
         c = np.cos(gamma[g, 1:]); s = np.sin(gamma[g, 1:])
         t = np.append(s * s, 1.0)                     # t_i, i = 1..ng
@@ -88,21 +93,65 @@ def energy_and_grad(gamma, members, norb, mapping, hdiag, J, K, functional):
     return E, chain_rule(gamma, members, norb, mapping, dn), n
 
 
+# The trigonometric variables live on a box (see optimize_lbfgs); the
+# softmax variables are unbounded.
+TRIG_EDGE = 1e-12          # faces of the weak-orbital angles, and pi/2 for all
+TRIG_STRONG_EDGE = 1e-6    # lower face of the strong-orbital angle gamma_g
+
+
+def variable_bounds(mapping, shape=None):
+    """Box of the optimiser's variables: the trigonometric map is even and
+    pi-periodic in every angle, so [0, pi/2]^n reaches every occupation vector
+    once, and the only points where E is not differentiable in the angles
+    (a weak amplitude sqrt(n_p) = |sqrt(h_g) cos.. sin..| crossing zero, which
+    PNOF5's sqrt(n_p n_q) terms turn into a kink) lie on its faces.  The faces
+    are held TRIG_EDGE inside, where E and its gradient are finite and equal
+    the one-sided limits to O(TRIG_EDGE).  The strong angle's lower face
+    (h_g -> 0, n_g -> 1) is held TRIG_STRONG_EDGE inside: E falls linearly
+    moving away from it (every K_gp >= 0), so no minimum lies there, and at
+    1e-12 the hole 1 - n_g would be lost to rounding in n_g (PNOF7's
+    sqrt(n_g (1 - n_g))).  Returns scalars without `shape`, else arrays of
+    that (ns, ng) shape."""
+    if mapping != "trig":
+        return -np.inf, np.inf
+    if shape is None:
+        return TRIG_EDGE, 0.5 * np.pi - TRIG_EDGE
+    lo = np.full(shape, TRIG_EDGE)
+    lo[:, 0] = TRIG_STRONG_EDGE
+    return lo, np.full(shape, 0.5 * np.pi - TRIG_EDGE)
+
+
+def projected_gradient(x, g, lo, hi):
+    """g with the components that push a variable out through a face it sits
+    on set to zero (the first-order optimality measure of a box problem)."""
+    pg = g.copy()
+    pg[(x <= lo) & (g > 0.0)] = 0.0
+    pg[(x >= hi) & (g < 0.0)] = 0.0
+    return pg
+
+
 def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxit=2000,
                    tol=1e-8, etol=1e-14, loose=1e-5, memory=8, c1=1e-4, max_backtrack=50,
                    step0=0.1):
-    """Limited-memory BFGS (Nocedal, Math. Comp. 35 (1980)): two-loop recursion
-    over the last `memory` (s, y) pairs with initial scaling s.y / y.y, then a
-    backtracking Armijo line search from step 1 (from `step0` / max|g| on the
-    first iteration or after a reset).  Pairs with s.y <= 0 are skipped; a
-    non-descent direction, or a line search that needed half of its halvings,
-    resets the memory.  Converged when max|dE/dgamma| <= tol, or when
-    max|dE/dgamma| <= loose and two consecutive steps change E by at most
+    """Limited-memory BFGS (Nocedal, Math. Comp. 35 (1980)) on the box of
+    ``variable_bounds``: the two-loop recursion over the last `memory` (s, y)
+    pairs with initial scaling s.y / y.y acts on the projected gradient, the
+    direction is zeroed on the variables held at a face, and a backtracking
+    Armijo line search from step 1 (from `step0` / max|pg| on the first
+    iteration or after a reset) projects every trial point onto the box and
+    tests E_t <= E + c1 g.(x_t - x) (Bertsekas, projected quasi-Newton).  With
+    no bounds (softmax) this is plain L-BFGS.  Pairs with s.y <= 0 are skipped;
+    a non-descent direction, or a line search that needed half of its
+    halvings, resets the memory.  Converged when max|pg| <= tol, or when
+    max|pg| <= loose and two consecutive steps change E by at most
     etol * max(1, |E|) (the FP64 floor of the energy).
 
     Returns (gamma, n, E, iterations, converged)."""
     shape = np.shape(gamma0)
-    x = np.array(gamma0, dtype=np.float64).ravel()
+    lo, hi = variable_bounds(mapping, shape)
+    if np.ndim(lo):
+        lo, hi = lo.ravel(), hi.ravel()
+    x = np.clip(np.array(gamma0, dtype=np.float64).ravel(), lo, hi)
 
     def f(v):
         E, g, n = energy_and_grad(v.reshape(shape), members, norb, mapping, hdiag, J, K, functional)
@@ -112,8 +161,10 @@ def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxi
     S, Y = [], []
     it = 0
     flat = 0
-    while it < maxit and np.max(np.abs(g)) > tol and flat < 2:
-        q = g.copy()
+    pg = projected_gradient(x, g, lo, hi)
+    while it < maxit and np.max(np.abs(pg)) > tol and flat < 2:
+        held = pg != g                          # at a face, pushed outwards
+        q = pg.copy()
         al = []
         for s_, y_ in zip(reversed(S), reversed(Y)):
             a = np.dot(s_, q) / np.dot(s_, y_)
@@ -122,22 +173,22 @@ def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxi
         if S:
             r = q * (np.dot(S[-1], Y[-1]) / np.dot(Y[-1], Y[-1]))
         else:
-            r = q * (step0 / np.max(np.abs(g)))
+            r = q * (step0 / np.max(np.abs(pg)))
         for (s_, y_), a in zip(zip(S, Y), reversed(al)):
             bcoef = np.dot(y_, r) / np.dot(s_, y_)
             r = r + s_ * (a - bcoef)
         d = -r
+        d[held] = 0.0
         gd = float(np.dot(g, d))
         if not gd < 0.0:
             S, Y = [], []
-            d = -g * (step0 / np.max(np.abs(g)))
-            gd = float(np.dot(g, d))
+            d = -pg * (step0 / np.max(np.abs(pg)))
         t = 1.0
         nb = 0
         for nb in range(max_backtrack):
-            xt = x + t * d
+            xt = np.clip(x + t * d, lo, hi)
             Et, gt, nt = f(xt)
-            if Et <= E + c1 * t * gd:
+            if Et <= E + c1 * float(np.dot(g, xt - x)):
                 break
             t *= 0.5
         s_ = xt - x
@@ -148,11 +199,12 @@ def optimize_lbfgs(gamma0, members, norb, mapping, hdiag, J, K, functional, maxi
             S.append(s_); Y.append(y_)
             if len(S) > memory:
                 S.pop(0); Y.pop(0)
-        small = np.max(np.abs(gt)) <= loose
+        pgt = projected_gradient(xt, gt, lo, hi)
+        small = np.max(np.abs(pgt)) <= loose
         flat = flat + 1 if (small and abs(Et - E) <= etol * max(1.0, abs(E))) else 0
-        x, E, g, n = xt, Et, gt, nt
+        x, E, g, n, pg = xt, Et, gt, nt, pgt
         it += 1
-    return x.reshape(shape), n, E, it, bool(np.max(np.abs(g)) <= tol or flat >= 2)
+    return x.reshape(shape), n, E, it, bool(np.max(np.abs(pg)) <= tol or flat >= 2)
 
 
 def aufbau_members(hdiag, ns, ng):

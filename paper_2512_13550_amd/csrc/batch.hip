@@ -495,7 +495,7 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
     if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) return NOF_E_HIP;
   }
 
-  std::vector<int> live(ni), sweep(ni), tstep(ni, 0), have_prev(ni, 0), hinfo(3 * ni);
+  std::vector<int> live(ni), sweep(ni), tstep(ni, 0), have_prev(ni, 0), hinfo(3 * ni), on_ok(ni, 1);
   std::vector<double> E_prev(ni, 0.0), hE(ni), hA(ni), ctl(3 * ni), hO(ni);
   int failed_status = NOF_OK;
   for (int i = 0; i < ni; ++i) live[i] = 1;
@@ -520,7 +520,11 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
     for (int i = 0; i < ni; ++i) {
       if (!live[i]) continue;
       if (hinfo[3 * i + 2] != NOF_OK) return hinfo[3 * i + 2];
-      if (prm->on_maxit > 0) res[i].on_iters += hinfo[3 * i];
+      if (prm->on_maxit > 0) {
+        res[i].on_iters += hinfo[3 * i];
+        on_ok[i] = hinfo[3 * i + 1] != 0;
+        if (!on_ok[i]) ++res[i].on_unconverged;
+      }
       rc = nof_functional_coeffs(p->norb, ns, ng, members, func, w.n + (long long)i * p->norb,
                                  w.cJ + i * n2, w.cK + i * n2, nullptr, w.scr, w.scr_bytes, st);
       if (rc != NOF_OK) return rc;
@@ -582,7 +586,7 @@ int plan_solve(nof_plan_s* p, const void* B, const double* H, double* C, int ns,
       if (!live[i]) continue;
       res[i].orth = std::max(res[i].orth, hO[i]);
       res[i].outer = outer + 1;
-      if (res[i].asym <= prm->tol_lambda && have_prev[i] &&
+      if (on_ok[i] && res[i].asym <= prm->tol_lambda && have_prev[i] &&
           std::fabs(res[i].E - E_prev[i]) <= prm->tol_energy) {
         res[i].converged = 1;
         live[i] = 0;
@@ -801,7 +805,7 @@ int nof_plan_solve(nof_plan plan, const void* B, const double* H, double* C, int
     if (!B || !H || !C || !members || !gamma || !p || !res) return NOF_E_NULL;
     if (p->max_outer < 1 || p->no_steps < 1 || p->on_maxit < 0 || !(p->lr > 0.0) ||
         !(p->beta1 >= 0.0 && p->beta1 < 1.0) || !(p->beta2 >= 0.0 && p->beta2 < 1.0) ||
-        !(p->eps >= 0.0) || !(p->tol_orth >= 0.0))
+        !(p->eps >= 0.0) || !(p->tol_orth >= 0.0) || p->orbopt == 1)
       return NOF_E_ARG;
     const size_t need = nof_plan_solve_ws(plan, ns, ng);
     if (need == 0) return NOF_E_DIM;

@@ -14,6 +14,8 @@
 // loop needs no host round trip.
 #include <math.h>
 
+#include <cstdlib>
+
 #include "common.h"
 
 namespace nof {
@@ -120,9 +122,9 @@ __device__ void map_group(const OccProblem& P, const double* x, double* n, int g
   const int* row = P.members + (long long)g * (P.ng + 1);
   const double* xg = x + (long long)g * P.ng;
   if (P.map == NOF_MAP_TRIG) {
-    const double c = cos(xg[0]);
+    const double c = cos(xg[0]), s0 = sin(xg[0]);
     const double ngv = 0.5 * (1.0 + c * c);
-    const double hole = 1.0 - ngv;
+    const double hole = 0.5 * s0 * s0;          // = 1 - n_g, without cancellation
     n[row[0]] = ngv;
     double Pp = 1.0;
     for (int i = 1; i < P.ng; ++i) {
@@ -132,11 +134,15 @@ __device__ void map_group(const OccProblem& P, const double* x, double* n, int g
     }
     n[row[P.ng]] = hole * Pp;
   } else {
-    double sum = 0.0;
-    for (int i = 0; i < P.ng; ++i) sum += exp(xg[i]);
-    const double ngv = 1.0 / (1.0 + sum);
-    n[row[0]] = ngv;
-    for (int i = 0; i < P.ng; ++i) n[row[1 + i]] = ngv * exp(xg[i]);
+    // numerator and denominator scaled by exp(-m), m = max(0, max_i x_i): no
+    // exponential overflows, the denominator holds a term equal to one
+    double m = 0.0;
+    for (int i = 0; i < P.ng; ++i) m = fmax(m, xg[i]);
+    const double e0 = exp(-m);
+    double den = e0;
+    for (int i = 0; i < P.ng; ++i) den += exp(xg[i] - m);
+    n[row[0]] = e0 / den;
+    for (int i = 0; i < P.ng; ++i) n[row[1 + i]] = exp(xg[i] - m) / den;
   }
 }
 
@@ -154,7 +160,7 @@ __device__ void chain_group(const OccProblem& P, const double* x, const double* 
     return;
   }
   const double cg = cos(xg[0]), sg = sin(xg[0]);
-  const double hole = 1.0 - 0.5 * (1.0 + cg * cg);
+  const double hole = 0.5 * sg * sg;
   // n_{p_i} = hole * Pprev_i * t_i,  i = 1..ng (Pprev_1 = 1, t_ng = 1)
   double dE_dhole = 0.0;
   double Pp = 1.0;
@@ -390,6 +396,44 @@ __device__ void vectors_to_lds(OccProblem& P, OccWs& w, double* sm, int nv) {
   P.u = w.u;
 }
 
+// Box of the variables: the trigonometric map is even and pi-periodic in every
+// angle, so [0, pi/2]^n reaches every occupation vector once, and the points
+// where E is not differentiable in the angles (a weak amplitude sqrt(n_p)
+// crossing zero, a kink through PNOF5's sqrt(n_p n_q) terms) lie on its faces,
+// held kTrigEdge inside.  The strong angle's lower face (n_g -> 1) is held
+// kTrigStrongEdge inside: no minimum lies there (E falls linearly away from
+// it, every K_gp >= 0), and closer to 0 the hole 1 - n_g is lost to rounding
+// in n_g.  The softmax variables are unbounded.
+constexpr double kTrigEdge = 1e-12;
+constexpr double kTrigStrongEdge = 1e-6;
+// bounds of variable i (row-major [ns][ng]: column 0 is the strong angle)
+__device__ __forceinline__ void var_bounds(int map, int ng, int i, double& lo, double& hi) {
+  if (map == NOF_MAP_TRIG) {
+    lo = (i % ng) == 0 ? kTrigStrongEdge : kTrigEdge;
+    hi = 0.5 * M_PI - kTrigEdge;
+  } else {
+    lo = -HUGE_VAL;
+    hi = HUGE_VAL;
+  }
+}
+// projection of x onto the bounds of variable i, and the projected gradient
+struct VarBox {
+  int map, ng;
+  __device__ __forceinline__ double lo(int i) const {
+    double l, h; var_bounds(map, ng, i, l, h); return l;
+  }
+  __device__ __forceinline__ double hi(int i) const {
+    double l, h; var_bounds(map, ng, i, l, h); return h;
+  }
+};
+// a component that pushes a variable out through a face it sits on
+__device__ __forceinline__ bool held_at_face(double x, double g, double lo, double hi) {
+  return (x <= lo && g > 0.0) || (x >= hi && g < 0.0);
+}
+__device__ __forceinline__ double proj_grad(double x, double g, double lo, double hi) {
+  return held_at_face(x, g, lo, hi) ? 0.0 : g;
+}
+
 __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsParams L,
                                                   double* gamma, double* n_out, double* E_out,
                                                   int* info, OccBatch ib) {
@@ -407,18 +451,20 @@ __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsPa
   const int nv = P.ns * P.ng;
   extern __shared__ double occ_sm[];
   if (L.lds > 0) vectors_to_lds(P, w, occ_sm, nv);
-  for (int i = tid; i < nv; i += OT) w.x[i] = gamma[i];
+  const VarBox bx{P.map, P.ng};
+  for (int i = tid; i < nv; i += OT) w.x[i] = fmin(fmax(gamma[i], bx.lo(i)), bx.hi(i));
   __syncthreads();
   double E = evaluate(P, w.x, w.n, w.dn, w.v, w.g, red);
   int it = 0, flat = 0, mcount = 0, head = 0;
   double gmax = 0.0;
   while (true) {
+    // projected gradient: the first-order optimality measure on the box
     double gl = 0.0;
-    for (int i = tid; i < nv; i += OT) gl = fmax(gl, fabs(w.g[i]));
+    for (int i = tid; i < nv; i += OT) gl = fmax(gl, fabs(proj_grad(w.x[i], w.g[i], bx.lo(i), bx.hi(i))));
     gmax = block_max(gl, red);
     if (it >= L.maxit || gmax <= L.tol || flat >= 2) break;
-    // two-loop recursion: d = H g
-    for (int i = tid; i < nv; i += OT) w.d[i] = w.g[i];
+    // two-loop recursion on the projected gradient: d = H pg
+    for (int i = tid; i < nv; i += OT) w.d[i] = proj_grad(w.x[i], w.g[i], bx.lo(i), bx.hi(i));
     __syncthreads();
     double alph[LM];
     for (int k = 0; k < mcount; ++k) {
@@ -438,23 +484,30 @@ __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsPa
       for (int i = tid; i < nv; i += OT) w.d[i] += w.S[(long long)idx * nv + i] * (alph[k] - bcoef);
       __syncthreads();
     }
-    for (int i = tid; i < nv; i += OT) w.d[i] = -w.d[i];
+    // descent direction, zero on the variables held at a face
+    for (int i = tid; i < nv; i += OT)
+      w.d[i] = held_at_face(w.x[i], w.g[i], bx.lo(i), bx.hi(i)) ? 0.0 : -w.d[i];
     __syncthreads();
-    double gd = dot(w.g, w.d, nv, red);
+    const double gd = dot(w.g, w.d, nv, red);
     if (!(gd < 0.0)) {
       mcount = 0;
-      for (int i = tid; i < nv; i += OT) w.d[i] = -w.g[i] * (L.step0 / gmax);
+      for (int i = tid; i < nv; i += OT) w.d[i] = -proj_grad(w.x[i], w.g[i], bx.lo(i), bx.hi(i)) * (L.step0 / gmax);
       __syncthreads();
-      gd = dot(w.g, w.d, nv, red);
     }
-    // backtracking Armijo line search
+    // backtracking Armijo line search, every trial point projected onto the
+    // box: E_t <= E + c1 g.(x_t - x)
     double t = 1.0, Et = 0.0;
     int nb = 0;
     for (nb = 0; nb < L.maxbt; ++nb) {
-      for (int i = tid; i < nv; i += OT) w.xt[i] = w.x[i] + t * w.d[i];
-      __syncthreads();
+      double gs = 0.0;
+      for (int i = tid; i < nv; i += OT) {
+        const double xt = fmin(fmax(w.x[i] + t * w.d[i], bx.lo(i)), bx.hi(i));
+        w.xt[i] = xt;
+        gs = fma(w.g[i], xt - w.x[i], gs);
+      }
+      const double gdx = block_sum(gs, red);
       Et = evaluate(P, w.xt, w.nt, w.dn, w.v, w.gt, red);
-      if (Et <= E + L.c1 * t * gd) break;
+      if (Et <= E + L.c1 * gdx) break;
       t *= 0.5;
     }
     if (nb == L.maxbt) nb = L.maxbt - 1;
@@ -478,7 +531,7 @@ __global__ __launch_bounds__(OT) void k_occ_lbfgs(OccProblem P, OccWs w, LbfgsPa
       }
     }
     double gl2 = 0.0;
-    for (int i = tid; i < nv; i += OT) gl2 = fmax(gl2, fabs(w.gt[i]));
+    for (int i = tid; i < nv; i += OT) gl2 = fmax(gl2, fabs(proj_grad(w.xt[i], w.gt[i], bx.lo(i), bx.hi(i))));
     const double gtmax = block_max(gl2, red);
     const bool small = gtmax <= L.loose;
     flat = (small && fabs(Et - E) <= L.etol * fmax(1.0, fabs(E))) ? flat + 1 : 0;
@@ -579,8 +632,13 @@ int occ_energy_grad(int norb, int ns, int ng, const int* members, int map, int f
 
 
 // LDS doubles for k_occ_lbfgs's vectors (0: they stay in the workspace); the
-// kernel's dynamic-LDS limit is raised to that size first.
+// kernel's dynamic-LDS limit is raised to that size first.  The environment
+// variable NOF_OCC_VECTORS_IN_WORKSPACE=1 keeps them in the workspace at any
+// size (the two placements give bit-identical results; the switch lets both
+// be tested on small problems).
 int lbfgs_lds(int norb, int ns, int ng) {
+  const char* force_ws = std::getenv("NOF_OCC_VECTORS_IN_WORKSPACE");
+  if (force_ws && force_ws[0] == '1') return 0;
   const int d = occ_lds_doubles(norb, ns, ng);
   if (d == 0) return 0;
   const size_t bytes = (size_t)d * sizeof(double);

@@ -5,7 +5,9 @@
 //
 // Outer iteration: ON step at fixed orbitals (transform, h, J, K, L-BFGS on
 // gamma, coefficients), then a NO sweep of up to no_steps ADAM steps on the
-// orbital gradient g = 4(lambda - lambda^T) with U = exp(y), C <- C U.  A sweep
+// orbital gradient g = 4(lambda - lambda^T) with U = exp(y), C <- C U (or,
+// with orbopt = 1, steps of the iterative diagonalization of the generalized
+// pseudo-Fockian: U = its eigenvectors).  A sweep
 // stops once max|lambda - lambda^T| <= tol_lambda; the run stops when a sweep
 // ended that way and E moved by at most tol_energy since the previous outer
 // iteration.  ADAM moments persist over the whole run (one step counter).
@@ -38,7 +40,7 @@ __global__ void k_asym(int n, const double* __restrict__ L, double* __restrict__
 }
 
 struct SolveLayout {
-  size_t b, D, h, J, K, lam, g, cJ, cK, m, v, y, U, Cn, n, scal, info, scratch, total;
+  size_t b, D, h, J, K, lam, g, cJ, cK, m, v, y, U, Cn, n, dg, scal, info, scratch, total;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -66,6 +68,7 @@ SolveLayout solve_layout(int naux, int nbf, int norb, int ns, int ng, int Bt, in
   L.U = o;   o += a256(n2);
   L.Cn = o;  o += a256((size_t)nbf * norb * sizeof(double));
   L.n = o;   o += a256((size_t)norb * sizeof(double));
+  L.dg = o;  o += a256((size_t)norb * sizeof(double));   // pseudo-Fockian diagonal (orbopt 1)
   L.scal = o; o += 256;                      // E, E_on, asym, orthonormality error
   L.info = o; o += 256;                      // ON info
   L.scratch = o;
@@ -79,6 +82,7 @@ SolveLayout solve_layout(int naux, int nbf, int norb, int ns, int ng, int Bt, in
   s = std::max(s, nof_occ_ws(norb, ns, ng));
   s = std::max(s, nof_orthonormalize_ws(nbf, norb));
   s = std::max(s, nof_energy_ws(norb));
+  s = std::max(s, nof_pseudo_fock_diag_ws(norb));
   L.total = L.scratch + a256(s);
   return L;
 }
@@ -104,8 +108,9 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
   try {
     if (!B || !H || !C || !members || !gamma || !p || !res) return NOF_E_NULL;
     if (p->max_outer < 1 || p->no_steps < 1 || p->on_maxit < 0 || !(p->lr > 0.0) ||
-        !(p->tol_orth >= 0.0))
+        !(p->tol_orth >= 0.0) || (p->orbopt == 1 && !(p->maxoff > 0.0)))
       return NOF_E_ARG;
+    if (p->orbopt == 1 && nof_pseudo_fock_diag_ws(norb) == 0) return NOF_E_DIM;
     const size_t need = nof_solve_ws(naux, nbf, norb, ns, ng, Bt, prec);
     if (need == 0) return NOF_E_DIM;
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
@@ -120,6 +125,8 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
     double *m = (double*)(w + L.m), *v = (double*)(w + L.v), *y = (double*)(w + L.y);
     double *U = (double*)(w + L.U), *Cn = (double*)(w + L.Cn);
     double* n = (double*)(w + L.n);
+    double* dg = (double*)(w + L.dg);
+    bool have_dg = false;
     double* scal = (double*)(w + L.scal);            // [0] E, [1] E of the ON step, [2] asym
     int* info = (int*)(w + L.info);
     void* scr = w + L.scratch;
@@ -168,7 +175,12 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
       }
       NOF_STEP(hipStreamSynchronize(stream) == hipSuccess ? NOF_OK : NOF_E_HIP);
       if (hinfo[2] != NOF_OK) NOF_STEP(hinfo[2]);
-      if (p->on_maxit > 0) res->on_iters += hinfo[0];
+      bool on_ok = true;
+      if (p->on_maxit > 0) {
+        res->on_iters += hinfo[0];
+        on_ok = hinfo[1] != 0;
+        if (!on_ok) ++res->on_unconverged;
+      }
       NOF_STEP(nof_functional_coeffs(norb, ns, ng, members, func, n, cJ, cK, nullptr, scr, sbytes,
                                      stream));
       // NO sweep at fixed occupations
@@ -189,8 +201,16 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
         if (host[2] <= p->tol_lambda) break;
         ++t_global;
         ++res->no_steps;
-        NOF_STEP(nof_adam_step(norb, g, m, v, t_global, p->lr, p->beta1, p->beta2, p->eps, y, stream));
-        NOF_STEP(nof_expm_antisym(norb, y, U, scr, sbytes, stream));
+        if (p->orbopt == 1) {
+          // iterative diagonalization: U = eigenvectors of the pseudo-Fockian,
+          // whose eigenvalues are the next step's diagonal
+          NOF_STEP(nof_pseudo_fock_diag(norb, lam, have_dg ? dg : nullptr, p->maxoff, U, dg, nullptr, scr,
+                                        sbytes, stream));
+          have_dg = true;
+        } else {
+          NOF_STEP(nof_adam_step(norb, g, m, v, t_global, p->lr, p->beta1, p->beta2, p->eps, y, stream));
+          NOF_STEP(nof_expm_antisym(norb, y, U, scr, sbytes, stream));
+        }
         NOF_STEP(nof_rotate_orbitals(nbf, norb, C, U, Cn, scr, sbytes, stream));
         NOF_STEP(hipMemcpyAsync(C, Cn, (size_t)nbf * norb * sizeof(double), hipMemcpyDeviceToDevice,
                                 stream) == hipSuccess ? NOF_OK : NOF_E_HIP);
@@ -203,7 +223,7 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
       NOF_STEP(hipStreamSynchronize(stream) == hipSuccess ? NOF_OK : NOF_E_HIP);
       res->orth = std::max(res->orth, orth);
       res->outer = outer + 1;
-      if (res->asym <= p->tol_lambda && have_prev && std::fabs(res->E - E_prev) <= p->tol_energy) {
+      if (on_ok && res->asym <= p->tol_lambda && have_prev && std::fabs(res->E - E_prev) <= p->tol_energy) {
         res->converged = 1;
         break;
       }

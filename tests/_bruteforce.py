@@ -87,3 +87,73 @@ def ao_closed_shell_fock(H, B, C_occ):
     for BP in B:
         F += 2.0 * BP * np.sum(BP * Pd) - BP @ Pd @ BP
     return F
+
+
+# ---- Fock-space brute force (occupation-number vectors, Jordan-Wigner signs) ----
+# A state is a dict {bitmask: amplitude}; spin-orbital index 2*p + s (s = 0
+# alpha, 1 beta).  Nothing here knows about cumulants or coefficient matrices.
+
+def _annihilate(i, state):
+    out = {}
+    for det, a in state.items():
+        if det >> i & 1:
+            sign = -1.0 if bin(det & ((1 << i) - 1)).count("1") & 1 else 1.0
+            d2 = det ^ (1 << i)
+            out[d2] = out.get(d2, 0.0) + sign * a
+    return out
+
+
+def _create(i, state):
+    out = {}
+    for det, a in state.items():
+        if not det >> i & 1:
+            sign = -1.0 if bin(det & ((1 << i) - 1)).count("1") & 1 else 1.0
+            d2 = det | (1 << i)
+            out[d2] = out.get(d2, 0.0) + sign * a
+    return out
+
+
+def _inner(x, y):
+    return sum(a * y.get(d, 0.0) for d, a in x.items())
+
+
+def geminal_product_state(groups, coeffs):
+    """Psi = prod_g (sum_{p in group g} c_p a+_{p alpha} a+_{p beta}) |0>:
+    an antisymmetrized product of strongly orthogonal singlet geminals, each in
+    its natural-orbital (Lowdin-Shull) form."""
+    psi = {0: 1.0}
+    for grp in groups:
+        new = {}
+        for p in grp:
+            t = _create(2 * p, _create(2 * p + 1, psi))
+            for d, a in t.items():
+                new[d] = new.get(d, 0.0) + coeffs[p] * a
+        psi = new
+    return psi
+
+
+def expectation_energy(psi, h, eri):
+    """<Psi|H|Psi> with H = sum h_pq a+_p,s a_q,s + 1/2 sum (pq|rs) a+_p,s a+_r,t a_s,t a_q,s
+    (chemists' notation (pq|rs)), by applying the operators to the state."""
+    m = h.shape[0]
+    M = 2 * m
+    one = {i: _annihilate(i, psi) for i in range(M)}
+    two = {(i, j): _annihilate(i, one[j]) for i in range(M) for j in range(M)}   # a_i a_j Psi
+    E = 0.0
+    for i in range(M):
+        for j in range(M):
+            if i % 2 == j % 2:
+                E += h[i // 2, j // 2] * _inner(one[i], one[j])
+    for p in range(M):
+        for q in range(M):
+            if p % 2 != q % 2:
+                continue
+            for r in range(M):
+                for s in range(M):
+                    if r % 2 != s % 2:
+                        continue
+                    v = eri[p // 2, q // 2, r // 2, s // 2]
+                    if v != 0.0:
+                        # <Psi| a+_p a+_r a_s a_q |Psi> = <a_r a_p Psi | a_s a_q Psi>
+                        E += 0.5 * v * _inner(two[(r, p)], two[(s, q)])
+    return E, _inner(psi, psi)

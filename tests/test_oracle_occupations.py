@@ -203,3 +203,136 @@ def test_pnof7_cumulant_against_spin_orbital_2rdm():
     E = dfjk.energy(n, h, J, K, cJ, cK)
     Ebf = bf.spin_orbital_energy(n, h, bf.mo_eri(B, C), Delta, Pi)
     assert abs(E - Ebf) <= 1e-12 * max(1.0, abs(Ebf))
+
+
+# ---- closed-form values of the two ON maps (Occupation Number Optimization) ----
+# Hand-evaluated from the printed equations at angles / exponentials whose
+# squares are exact rationals; a sin^2 <-> cos^2 swap, a shifted index or a
+# wrong subspace assignment changes at least one value.
+
+def _member_orders():
+    # natural order and a scrambled assignment of the four orbitals
+    return [np.array([[0, 1, 2, 3]]), np.array([[2, 0, 3, 1]])]
+
+
+def test_trig_map_hand_values():
+    """Eq. trigo-n_sdono_gamma and the weak-orbital chain, N_g = 3:
+    gamma_g = pi/3 (cos^2 = 1/4): n_g = (1 + 1/4)/2 = 5/8, h_g = 3/8;
+    gamma_p1 = pi/6 (sin^2 = 1/4): n_p1 = 3/8 * 1/4 = 3/32;
+    gamma_p2 = pi/3 (sin^2 = 3/4, cos^2 = 1/4): n_p2 = 3/8 * 3/4 * 3/4 = 27/128,
+    n_p3 = 3/8 * 3/4 * 1/4 = 9/128."""
+    gamma = np.array([[np.pi / 3, np.pi / 6, np.pi / 3]])
+    expect = [5 / 8, 3 / 32, 27 / 128, 9 / 128]
+    for members in _member_orders():
+        n = occupations.occupations(gamma, members, 4, "trig")
+        for k, p in enumerate(members[0]):
+            assert abs(n[p] - expect[k]) < 4e-16, (members, k)
+
+
+@pytest.mark.parametrize("g,ng_expect", [(0.0, 1.0), (np.pi / 4, 0.75), (np.pi / 2, 0.5),
+                                          (2 * np.pi / 3, 0.625)])
+def test_trig_map_strong_orbital_hand_values(g, ng_expect):
+    """N_g = 1: n_g = (1 + cos^2 gamma)/2 and the single weak orbital takes the hole."""
+    n = occupations.occupations(np.array([[g]]), np.array([[1, 0]]), 2, "trig")
+    assert abs(n[1] - ng_expect) < 4e-16 and abs(n[0] - (1 - ng_expect)) < 4e-16
+
+
+def test_softmax_map_hand_values():
+    """Eqs. softmax-n_sdono_gamma and n_wdono_gamma1: exp(gamma) = (1, 2, 3)
+    gives n_g = 1/7 and n_p = (1/7, 2/7, 3/7); exp(gamma) = (1/2, 1/4) gives
+    n_g = 4/7, n_p = (2/7, 1/7)."""
+    for members in _member_orders():
+        n = occupations.occupations(np.log([[1.0, 2.0, 3.0]]), members, 4, "softmax")
+        for k, p in enumerate(members[0]):
+            assert abs(n[p] - [1 / 7, 1 / 7, 2 / 7, 3 / 7][k]) < 4e-16
+    n = occupations.occupations(np.log([[0.5, 0.25]]), np.array([[2, 0, 1]]), 3, "softmax")
+    assert np.allclose(n, [2 / 7, 1 / 7, 4 / 7], rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("gamma", [[710.0, 0.0, -5.0], [800.0, 800.0, 1000.0], [1000.0, 1000.0, -1000.0],
+                                   [-1000.0, -800.0, -750.0], [709.0, 709.5, 0.5]])
+def test_softmax_map_large_arguments(gamma):
+    """The softmax map is defined for every gamma: occupations stay finite,
+    non-negative and on the sum rule where exp(gamma) alone overflows, and
+    equal the map evaluated in 60-digit decimal arithmetic."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    members = np.array([[0, 1, 2, 3]])
+    with np.errstate(over="raise", invalid="raise"):
+        n = occupations.occupations(np.array([gamma]), members, 4, "softmax")
+        gr = occupations.chain_rule(np.array([gamma]), members, 4, "softmax", np.array([1.0, -2.0, 0.5, 3.0]))
+    assert np.all(np.isfinite(n)) and np.all(n >= 0) and abs(n.sum() - 1.0) < 1e-15
+    assert np.all(np.isfinite(gr))
+    e = [Decimal(x).exp() for x in gamma]
+    den = 1 + sum(e)
+    ref = [float(1 / den)] + [float(x / den) for x in e]
+    assert np.allclose(n, ref, rtol=1e-14, atol=1e-300)
+
+
+def test_pnof5_equals_geminal_product_expectation():
+    """PNOF5 is the energy of an antisymmetrized product of strongly
+    orthogonal geminals, each in natural-orbital form with coefficient
+    +sqrt(n_g) on its strong orbital and -sqrt(n_p) on every weak one (the
+    sign choice behind Pi = -sqrt(n n) with the strong orbital and
+    +sqrt(n n) between weak orbitals; Pernal, Comput. Theor. Chem. 1003 (2013)
+    127).  <Psi|H|Psi> is evaluated here by brute force in Fock space from h and
+    the four-index integrals, with no cumulant or coefficient matrix: a wrong
+    weak-weak sign, a missing interpair exchange term or a factor slip fails."""
+    import _bruteforce as bf
+    for ns, ng, seed in ((1, 2, 21), (1, 3, 22), (2, 2, 23), (3, 1, 24)):
+        members, norb = members_of(ns, ng)
+        B = inputs.make_B(seed, norb, 3 * norb, 4.0, threads=1)
+        C = inputs.make_C(seed, norb, norb)
+        h = dfjk.one_electron(inputs.make_H(seed, norb), C)
+        eri = bf.mo_eri(B, C)
+        b, _ = dfjk.mo_transform(B, C)
+        J, K = dfjk.jk(b)
+        rng = np.random.default_rng(seed)
+        n = occupations.occupations(rng.uniform(0.2, 1.3, (ns, ng)), members, norb, "trig")
+        c = -np.sqrt(n)
+        c[members[:, 0]] = np.sqrt(n[members[:, 0]])
+        psi = bf.geminal_product_state([list(r) for r in members], c)
+        Ebf, norm = bf.expectation_energy(psi, h, eri)
+        assert abs(norm - 1.0) < 1e-14
+        E5 = functionals.energy_of_n(n, np.diag(h).copy(), J, K, members, "pnof5")
+        assert abs(E5 - Ebf) < 1e-12 * max(1.0, abs(Ebf)), (ns, ng, E5, Ebf)
+        # the opposite weak-weak sign is a different (non-geminal) energy
+        if ng >= 2:
+            c2 = c.copy()
+            c2[members[:, 1]] *= -1.0
+            Ebad, _ = bf.expectation_energy(bf.geminal_product_state([list(r) for r in members], c2), h, eri)
+            assert abs(E5 - Ebad) > 1e-8
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_box_optimizer_reaches_kink_minima(seed):
+    """Roles that the one-electron energies contradict (the first orbitals
+    strong, no gap) push weak occupations to zero, where PNOF5's
+    sqrt(n_p n_q) terms make E a kink in the angles: no gradient vanishes
+    there.  The optimiser on the box of the trigonometric variables stops with
+    a vanishing projected gradient, and the point is a local minimum checked
+    without the gradient code: E rises (central one-sided differences of E)
+    when any variable held at a face moves inwards, and the free components
+    are stationary.  (A variable can also be flat there: once an earlier
+    factor cos^2 theta_l is zero, the later angles move no occupation.)"""
+    ns, ng = 6, 3
+    members, norb = members_of(ns, ng)
+    hd, J, K = _jk(norb, seed)
+    x0 = np.full((ns, ng), 0.6)
+    x, n, E, it, ok = occupations.optimize_lbfgs(x0, members, norb, "trig", hd, J, K, "pnof5",
+                                                 maxit=5000, tol=1e-9)
+    assert ok, it
+    lo, hi = occupations.variable_bounds("trig", (ns, ng))
+    assert np.all(x >= lo) and np.all(x <= hi)
+    f = lambda v: occupations.energy_and_grad(v, members, norb, "trig", hd, J, K, "pnof5")[0]
+    at_face = (x <= lo) | (x >= hi)
+    assert at_face.any()            # the instance does have kink minima
+    for idx in zip(*np.nonzero(at_face)):
+        for step in (1e-6, 1e-4):
+            v = x.copy()
+            v[idx] += step if x[idx] <= lo[idx] else -step
+            assert f(v) >= E - 1e-13 * abs(E), (idx, step)
+    for idx in zip(*np.nonzero(~at_face)):
+        v1 = x.copy(); v1[idx] += 1e-6
+        v2 = x.copy(); v2[idx] -= 1e-6
+        assert abs(f(v1) - f(v2)) / 2e-6 < 1e-6
