@@ -70,11 +70,17 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3 } nof_dtyp
  *   NOF_P_BF16X6  operands split into BF16 hi+mid+lo, the six products whose
  *                 combined order of magnitude is at most two splits down;
  *                 every 32-deep stage is added into FP64 accumulators.
- *   NOF_P_BF16X10 fixed-point split: per row of an operand and 32-deep
- *                 stage, four BF16 pieces on the grids 2^(E-8)..2^(E-32)
- *                 below the stage's largest magnitude 2^E; the ten products
- *                 of order <= 3.  The leading products of a stage sum
- *                 exactly in FP32 and are added to FP64 every stage.
+ *   NOF_P_BF16X10 fixed-point split (Ozaki-type error-free split on BF16):
+ *                 every row of X and column of Y gets one grid over the whole
+ *                 contraction, 2^E above its largest magnitude, and four BF16
+ *                 pieces x = sum_{q<4} n_q 2^(E-7-8q) + r, integers
+ *                 |n_q| <= 128, |r| <= 2^(E-32); the ten products of order
+ *                 <= 3.  The order-0 products are integers of at most 2^14
+ *                 units, so their FP32 running sum is exact for up to 1024
+ *                 terms; longer contractions add it to FP64 every 1024 terms.
+ *                 Orders 1..3 share a second FP32 accumulator.  T and b are
+ *                 stored in FP32.  The exchange-type Fock term uses three
+ *                 element-wise pieces (six products) instead.
  * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
 typedef enum {
   NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4,
@@ -87,10 +93,10 @@ const char* nof_status_str(int status);
 /* ---------------------------------------------------------------------------
  * Fixed-point split of the three-index tensor for NOF_P_BF16X10, done once
  * per B (every orbital iteration reuses B; Single Point Energy Calculations,
- * ERITYP='RI').  Row (P, mu) of B^P is cut into 32-deep blocks of nu; with
- * 2^E above the largest |value| of a block, each value becomes
- *   v = sum_{q<4} n_q 2^(E-8(q+1)) + r,  n_q integers (exact in BF16),
- *   |n_0| <= 256, |n_q| <= 128 (q > 0), |r| <= 2^(E-33).
+ * ERITYP='RI').  Row (P, mu) of B^P gets one grid over its whole length:
+ * with 2^E above the row's largest |value|, each value becomes
+ *   v = sum_{q<4} n_q 2^(E-7-8q) + r,  n_q integers (exact in BF16),
+ *   |n_q| <= 128, |r| <= 2^(E-32).
  * B       [naux][nbf][nbf] FP64 or FP32 (Bt), symmetric, device.
  * planes  out, at least nof_split_B_bytes(naux, nbf) bytes, device (caller
  *         owned); layout [4][naux][nbf][ldk], ldk = nbf rounded up to a
@@ -210,6 +216,30 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
                       int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * The Coulomb-type term of the generalized Fock build alone (the middle sum
+ * of lambda above, NO Optimization), with K from the same pass over the
+ * upper half of b, as nof_gen_fock computes them:
+ *   W = D cJ,   F1_rs = sum_P b^P_rs W[P][s],   K_pq = sum_P (b^P_pq)^2
+ * b, bt, D, cJ as in nof_gen_fock.  F1 out [norb][norb] FP64 (not symmetric);
+ * K_opt out [norb][norb] FP64 or NULL.  FP64 accumulation in a fixed order.
+ * ws: at least nof_coulomb_fock_ws(naux, norb, bt) bytes.
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_DTYPE, NOF_E_WORKSPACE, NOF_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t nof_coulomb_fock_ws(int naux, int norb, int bt);
+int nof_coulomb_fock(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
+                     double* F1, double* K_opt, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Lagrange multipliers and orbital gradient from the two Fock terms (NO
+ * Optimization): lambda_rs = n_s h_rs + F1_rs - F2_rs, grad = 4(lambda -
+ * lambda^T), as nof_gen_fock forms them.  n [norb], h, F1, F2 [norb][norb]
+ * FP64 device; lambda out [norb][norb]; grad out or NULL.  No workspace.
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_HIP.
+ * ------------------------------------------------------------------------- */
+int nof_lambda_grad(int norb, const double* n, const double* h, const double* F1, const double* F2,
+                    double* lambda, double* grad, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Energy of Eq. (PNOF):
  *   E = 2 sum_p n_p h_pp + sum_pq cJ_pq J_pq - sum_pq cK_pq K_pq
  * All inputs [norb] or [norb][norb] FP64; E is one FP64 device scalar.
@@ -281,6 +311,40 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
                   double beta1, double beta2, double eps, double* y, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * One step of the iterative diagonalization of the generalized pseudo-
+ * Fockian (NO Optimization: the alternative to orbital rotations selected by
+ * IORBOPT = 1; lambda is symmetric at the minimum, so a symmetric matrix
+ * whose off-diagonal elements are lambda's asymmetry is diagonal there).
+ *
+ *   F_pq = F_qp = clamp(s_pq (lambda_qp - lambda_pq), -maxoff, maxoff),
+ *   s_pq = +1 if diag_p <= diag_q else -1 (p < q),   F_pp = diag_p,
+ *
+ * (the orientation makes the first-order rotation a descent step for every
+ * pair; the paper leaves the diagonal open).  F is diagonalized (cyclic
+ * Jacobi, rotations of at most pi/4); eigenvector k is assigned to the
+ * orbital on which it has the largest weight, with a non-negative component
+ * there: V[:, r] is that eigenvector and eig[r] its eigenvalue.  The caller
+ * then forms C <- C V (nof_rotate_orbitals) and passes eig as the next
+ * step's diag.
+ *
+ * lambda  [norb][norb] FP64 device.   diag  [norb] FP64 device, or NULL for
+ *         lambda_pp (the first step of a run).   maxoff > 0.
+ * V       out [norb][norb] FP64.      eig   out [norb] FP64 or NULL.
+ * info    device int[2] or NULL: [0] Jacobi sweeps (-1: not converged),
+ *         [1] 1 if the largest-weight assignment was a permutation (else the
+ *         eigenvectors stay in the solver's order).
+ * ws      nof_pseudo_fock_diag_ws(norb) bytes.  norb <= 65536.
+ * Synchronises the stream once per Jacobi sweep (not capturable).
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_ARG (maxoff, or lambda not finite),
+ * NOF_E_WORKSPACE, NOF_E_HIP, NOF_E_NOT_CONVERGED (40 sweeps; outputs are
+ * written from the last sweep).
+ * ------------------------------------------------------------------------- */
+size_t nof_pseudo_fock_diag_ws(int norb);
+int nof_pseudo_fock_diag(int norb, const double* lambda, const double* diag, double maxoff,
+                         double* V, double* eig, int* info, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Occupation-number update at fixed orbitals, FP64 (Occupation Number
  * Optimization; orbital-pairing structure of Eq. OmegaG and sum rule Eq. sum1).
  *
@@ -291,7 +355,9 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
  *          written.
  * map      NOF_MAP_TRIG: n_g = (1 + cos^2 x_g)/2, n_{p_i} = h_g prod_{j<i}
  *          cos^2 x_j sin^2 x_i, the last weak orbital takes the rest;
- *          NOF_MAP_SOFTMAX: n_g = 1/(1 + sum_k e^{x_k}), n_{p_i} = n_g e^{x_i}.
+ *          NOF_MAP_SOFTMAX: n_g = 1/(1 + sum_k e^{x_k}), n_{p_i} = n_g e^{x_i},
+ *          evaluated with numerator and denominator scaled by e^{-m},
+ *          m = max(0, max_k x_k), so it is finite for every x.
  * gamma    [ns][ng] variables (trig: x_g then x_1..x_{ng-1}; softmax x_1..x_ng).
  * func     NOF_FUNC_HF (Delta = Pi = 0), NOF_FUNC_PNOF5 (independent pairs:
  *          Delta_pq = n_p n_q and Pi_pq = -+sqrt(n_p n_q) within a subspace,
@@ -306,11 +372,19 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
  * nof_occ_energy_grad: n [norb], E (scalar), dEdgamma [ns][ng]; any output may
  *   be NULL.
  * nof_occ_optimize: L-BFGS (memory 8, two-loop recursion, Armijo backtracking
- *   from step 1, initial step 0.1/max|g|) on gamma in place, in one
- *   workgroup with no host round trip.  Stops when max|dE/dgamma| <= tol, or
- *   when max|dE/dgamma| <= 1e-5 and two consecutive steps change E by at
- *   most 1e-14 max(1,|E|), or after maxit iterations.  info[0] = iterations,
- *   info[1] = 1 if converged, info[2] = 0 or a device-detected status.
+ *   from step 1, initial step 0.1/max|pg|) on gamma in place, in one
+ *   workgroup with no host round trip.  Trig variables are kept in the box
+ *   [1e-12, pi/2 - 1e-12]: the map is even and pi-periodic in every angle,
+ *   so the box reaches every occupation vector, and E's kinks in the angles
+ *   (a weak occupation reaching 0, where PNOF5's sqrt(n_p n_q) terms are not
+ *   differentiable) lie on its faces.  The start is projected onto the box,
+ *   trial points are projected, the direction is zero on variables held at a
+ *   face, and pg is the projected gradient (components pushing out through a
+ *   face a variable sits on are 0).  Softmax variables are unbounded (pg = g).
+ *   Stops when max|pg| <= tol, or when max|pg| <= 1e-5 and two consecutive
+ *   steps change E by at most 1e-14 max(1,|E|), or after maxit iterations.
+ *   info[0] = iterations, info[1] = 1 if converged, info[2] = 0 or a
+ *   device-detected status.
  * nof_functional_coeffs: cJ = 2(nn^T - Delta), cK = nn^T - Delta - Pi for
  *   the functional (Eq. PNOF coefficients for the NO step); info may be NULL.
  * ws: nof_occ_ws() bytes (all three calls).
@@ -464,6 +538,10 @@ int nof_mlp_warm_gamma(int norb, int ns, int ng, const int* members, int map,
  * ws            at least nof_solve_ws(...) bytes.  Not capturable in a HIP
  *               graph (it synchronises the stream every step).
  * ------------------------------------------------------------------------- */
+/* orbopt: 1 = each NO step is one step of nof_pseudo_fock_diag (iterative
+ * diagonalization, IORBOPT = 1; its diagonal persists over the run, lambda_pp
+ * at the first step) with off-diagonal bound maxoff; any other value = ADAM
+ * rotation steps (IORBOPT = 2). */
 typedef struct {
   int max_outer, no_steps;
   double lr, beta1, beta2, eps;
@@ -471,13 +549,19 @@ typedef struct {
   int on_maxit;
   double on_tol;
   double tol_orth;
+  int orbopt;
+  double maxoff;
 } nof_solve_params;
 
-/* orth: the largest max|C^T C - I| that the checks after the sweeps found. */
+/* orth: the largest max|C^T C - I| that the checks after the sweeps found.
+ * on_unconverged: ON steps (nof_occ_optimize calls) that stopped at on_maxit
+ * without meeting their stopping test.  converged = 1 needs the run's
+ * criteria and a converged ON step in the last outer iteration. */
 typedef struct {
   double E, asym;
   int outer, no_steps, on_iters, converged, status;
   double orth;
+  int on_unconverged;
 } nof_solve_result;
 
 size_t nof_solve_ws(int naux, int nbf, int norb, int ns, int ng, int Bt, int prec);
@@ -510,7 +594,8 @@ int nof_solve(int naux, int nbf, int norb, const void* B, int Bt, const double* 
  * H        [ninst][nbf][nbf] FP64; C [ninst][nbf][norb] FP64 in/out.
  * members, map, func, ns, ng   as nof_occ_optimize, shared by all instances.
  * gamma    [ninst][ns][ng] FP64 in/out.  n_out [ninst][norb] or NULL.
- * p        host parameters as nof_solve.  res [ninst] host results.
+ * p        host parameters as nof_solve (ADAM steps only: orbopt = 1 is
+ *          NOF_E_ARG).  res [ninst] host results.
  * ws       nof_plan_solve_ws(plan, ns, ng) bytes (includes the plan's).
  * Returns NOF_E_NOT_CONVERGED when an instance's E or asymmetry stopped being
  * finite (that instance stops, res[i].status says so, the others run on),

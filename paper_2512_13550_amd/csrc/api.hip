@@ -462,6 +462,51 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
   });
 }
 
+size_t nof_coulomb_fock_ws(int naux, int norb, int bt) {
+  if (!dim_ok(naux) || !dim_ok(norb)) return 0;
+  if (bt != NOF_F64 && bt != NOF_F32) return 0;
+  const FockLayout L = fock_layout(naux, norb, bt);
+  return L.off_f2part;          // W and the F1 / K chunk partials
+}
+
+int nof_coulomb_fock(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
+                     double* F1, double* K_opt, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!b || !D || !cJ || !F1) return NOF_E_NULL;
+    if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
+    const FockLayout L = fock_layout(naux, norb, bt);
+    if (!ws || ws_bytes < L.off_f2part) return NOF_E_WORKSPACE;
+    char* w = (char*)ws;
+    const long long n2 = (long long)norb * norb;
+    double* W = (double*)(w + L.off_W);
+    double* f1part = (double*)(w + L.off_f1part);
+    double* kpart = (double*)(w + L.off_kpart);
+    GemmDesc gw{};
+    gw.M = naux; gw.N = norb; gw.K = norb; gw.Ktot = 0;
+    gw.batch = 1; gw.fold = 1;
+    gw.X = D; gw.ldx = norb; gw.sx = 0; gw.x_kmajor = false;
+    gw.Y = cJ; gw.ldy = norb; gw.sy = 0;
+    gw.S = nullptr; gw.lds = 0;
+    gw.Out = W; gw.ldo = norb; gw.so = 0;
+    gw.Dg = nullptr; gw.sd = 0; gw.sym = false;
+    NOF_TRY(gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
+    NOF_TRY(kf1_pass(naux, norb, b, bt, W, K_opt ? kpart : nullptr, f1part, L.kchunks, stream));
+    NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
+    if (K_opt) NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K_opt, stream));
+    return NOF_OK;
+  });
+}
+
+int nof_lambda_grad(int norb, const double* n, const double* h, const double* F1, const double* F2,
+                    double* lambda, double* grad, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(norb)) return NOF_E_DIM;
+    if (!n || !h || !F1 || !F2 || !lambda) return NOF_E_NULL;
+    return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
+  });
+}
+
 size_t nof_energy_ws(int norb) {
   if (!dim_ok(norb)) return 0;
   return energy_ws(1);

@@ -46,6 +46,9 @@ _sig("nof_jk_diag", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_exchange_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_exchange_fock", _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp)
+_sig("nof_coulomb_fock_ws", _sz, _i, _i, _i)
+_sig("nof_coulomb_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("nof_lambda_grad", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nof_gen_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp)
 _sig("nof_energy_ws", _sz, _i)
 _sig("nof_energy", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
@@ -85,15 +88,17 @@ _sig("nof_mlp_warm_gamma", _i, _i, _i, _i, _vp, _i, _vp, _d, _vp, _vp, _vp)
 class SolveParams(ctypes.Structure):
     _fields_ = [("max_outer", _i), ("no_steps", _i), ("lr", _d), ("beta1", _d), ("beta2", _d),
                 ("eps", _d), ("tol_lambda", _d), ("tol_energy", _d), ("on_maxit", _i), ("on_tol", _d),
-                ("tol_orth", _d)]
+                ("tol_orth", _d), ("orbopt", _i), ("maxoff", _d)]
 
 
 class SolveResult(ctypes.Structure):
     _fields_ = [("E", _d), ("asym", _d), ("outer", _i), ("no_steps", _i), ("on_iters", _i),
-                ("converged", _i), ("status", _i), ("orth", _d)]
+                ("converged", _i), ("status", _i), ("orth", _d), ("on_unconverged", _i)]
 
 
 _sig("nof_solve_ws", _sz, _i, _i, _i, _i, _i, _i, _i)
+_sig("nof_pseudo_fock_diag_ws", _sz, _i)
+_sig("nof_pseudo_fock_diag", _i, _i, _vp, _vp, _d, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_orthonormalize_ws", _sz, _i, _i)
 _sig("nof_orthonormalize", _i, _i, _i, _vp, _vp, _d, _vp, _vp, _sz, _vp)
 _sig("nof_dipole_ws", _sz, _i, _i)
@@ -112,14 +117,15 @@ DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
     "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_split_B_bytes", "nof_split_B",
     "nof_jk_diag_ws", "nof_jk_diag",
-    "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock", "nof_energy_ws", "nof_energy", "nof_coeffs_from_cumulant",
+    "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock",
+    "nof_coulomb_fock_ws", "nof_coulomb_fock", "nof_lambda_grad", "nof_energy_ws", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_orthonormalize_ws", "nof_orthonormalize",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
     "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
-    "nof_solve_ws", "nof_solve", "nof_plan_solve_ws", "nof_plan_solve", "nof_dipole_ws", "nof_dipole", "nof_nlop_romberg",
+    "nof_solve_ws", "nof_solve", "nof_pseudo_fock_diag_ws", "nof_pseudo_fock_diag", "nof_plan_solve_ws", "nof_plan_solve", "nof_dipole_ws", "nof_dipole", "nof_nlop_romberg",
     "nof_nlop_isotropic", "nof_mlp_features", "nof_mlp_forward", "nof_mlp_targets", "nof_mlp_loss_grad", "nof_mlp_adam", "nof_mlp_warm_gamma",
 ]
 
@@ -307,6 +313,36 @@ def exchange_fock(b, cK, prec=None, F2=None, ws=None, stream=None):
     check(lib.nof_exchange_fock(naux, norb, _p(b), bt, _f64(cK, "cK"), _p(F2), prec, _p(ws), ws.numel(),
                                 stream_handle(stream)), "nof_exchange_fock")
     return F2
+
+
+def coulomb_fock(b, D, cJ, F1=None, K=None, want_K=True, ws=None, stream=None):
+    """F1_rs = sum_P b^P_rs (D cJ)[P][s] and K from the same pass (nof_coulomb_fock)."""
+    naux, norb, _ = b.shape
+    bt = _TDT[b.dtype]
+    dev = b.device
+    if F1 is None:
+        F1 = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    if want_K and K is None:
+        K = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    need = lib.nof_coulomb_fock_ws(naux, norb, bt)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    check(lib.nof_coulomb_fock(naux, norb, _p(b), bt, _f64(D, "D"), _f64(cJ, "cJ"), _p(F1),
+                               _p(K) if want_K else None, _p(ws), ws.numel(), stream_handle(stream)),
+          "nof_coulomb_fock")
+    return F1, (K if want_K else None)
+
+
+def lambda_grad(n, h, F1, F2, lam=None, g=None, want_grad=True, stream=None):
+    """lambda = n_s h_rs + F1 - F2 and grad = 4(lambda - lambda^T) (nof_lambda_grad)."""
+    norb = n.shape[0]
+    if lam is None:
+        lam = torch.empty((norb, norb), dtype=torch.float64, device=n.device)
+    if want_grad and g is None:
+        g = torch.empty_like(lam)
+    check(lib.nof_lambda_grad(norb, _f64(n, "n"), _f64(h, "h"), _f64(F1, "F1"), _f64(F2, "F2"), _p(lam),
+                              _p(g) if want_grad else None, stream_handle(stream)), "nof_lambda_grad")
+    return lam, (g if want_grad else None)
 
 
 def energy(n, h, J, K, cJ, cK, E=None, ws=None, stream=None):
@@ -512,7 +548,7 @@ class BatchPlan:
         if self.solve_ws is None or self.solve_ws.numel() < need:
             self.solve_ws = workspace(need, C.device)
         prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit,
-                          on_tol, tol_orth)
+                          on_tol, tol_orth, 2, 1.0)
         res = (SolveResult * self.ninst)()
         rc = lib.nof_plan_solve(self.handle, _b_arg(B)[1], _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
                                 int(mapping), int(functional), _f64(gamma, "gamma"), _p(n_out),
@@ -606,7 +642,7 @@ def mlp_warm_gamma(theta, members, mapping, norb, nfloor=1e-12, info=None, strea
 
 def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=None, stream=None,
           max_outer=100, no_steps=30, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8, tol_lambda=1e-5,
-          tol_energy=1e-9, on_maxit=2000, on_tol=1e-8, tol_orth=1e-10):
+          tol_energy=1e-9, on_maxit=2000, on_tol=1e-8, tol_orth=1e-10, orbopt=2, maxoff=1.0):
     """Alternating NO + ON optimisation to convergence (nof_solve).  C and gamma
     are updated in place; returns the result as a dict."""
     naux, nbf, _ = B.shape
@@ -622,12 +658,33 @@ def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=No
     if ws is None or ws.numel() < need:
         ws = workspace(need, C.device)
     prm = SolveParams(max_outer, no_steps, lr, beta1, beta2, eps, tol_lambda, tol_energy, on_maxit, on_tol,
-                      tol_orth)
+                      tol_orth, orbopt, maxoff)
     res = SolveResult()
     check(lib.nof_solve(naux, nbf, norb, Bp, Bt, _f64(H, "H"), _f64(C, "C"), ns, ng, _p(members),
                         mapping, functional, _f64(gamma, "gamma"), _p(n), prec, ctypes.byref(prm),
                         ctypes.byref(res), _p(ws), ws.numel(), stream_handle(stream)), "nof_solve")
     return {f: getattr(res, f) for f, _ in SolveResult._fields_}
+
+
+def pseudo_fock_diag(lam, diag=None, maxoff=1.0, V=None, eig=None, ws=None, stream=None):
+    """One iterative-diagonalization step (nof_pseudo_fock_diag): returns
+    (V, eig, info) with info = [sweeps, assignment ok] (device)."""
+    norb = lam.shape[0]
+    dev = lam.device
+    if V is None:
+        V = torch.empty((norb, norb), dtype=torch.float64, device=dev)
+    if eig is None:
+        eig = torch.empty(norb, dtype=torch.float64, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    need = lib.nof_pseudo_fock_diag_ws(norb)
+    if need == 0:
+        raise NofError(E_DIM, "nof_pseudo_fock_diag_ws")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    check(lib.nof_pseudo_fock_diag(norb, _f64(lam, "lambda"), _p(diag) if diag is not None else None,
+                                   float(maxoff), _p(V), _p(eig), _p(info), _p(ws), ws.numel(),
+                                   stream_handle(stream)), "nof_pseudo_fock_diag")
+    return V, eig, info
 
 
 def dipole(C, n, d, mu=None, ws=None, stream=None):

@@ -7,7 +7,8 @@ generators, J, K, h from the library's transform; orbital roles by ascending
 h_pp (aufbau): the ns lowest orbitals are strong, paired with N_g =
 (norb - ns) // ns weak ones in the mirrored order; the strong orbitals' h_pp is
 lowered by `gap` (the occupied-virtual gap a molecule has and random matrices
-lack).  The optimiser is the library's L-BFGS with the softmax map.
+lack).  The optimiser is the library's L-BFGS (softmax map for the training
+data; either map in the evaluation).
 """
 from __future__ import annotations
 
@@ -59,16 +60,22 @@ class InstanceFactory:
         shift[torch.from_numpy(members[:, 0].astype(np.int64)).to(self.dev)] = -self.gap
         hd = hd + shift
         occ = nof.Occupations(norb, torch.from_numpy(members).to(self.dev), mapping, nof.FUNC_PNOF5)
-        return dict(norb=norb, ns=ns, ng=ng, h=hd, J=J, K=K, members=members, occ=occ, mapping=mapping)
+        return dict(norb=norb, ns=ns, ng=ng, h=hd, J=J, K=K, members=members, occ=occ, mapping=mapping,
+                    nof=nof)
 
 
 def cold_gamma(inst, nstrong=0.98):
-    """n_g = 0.98 with the hole shared equally among the weak orbitals."""
-    ng, ns = inst["ng"], inst["ns"]
-    if inst["mapping"] == 1:
-        val = math.log((1.0 - nstrong) / ng / nstrong)
-        return torch.full((ns, ng), val, dtype=torch.float64, device=inst["h"].device)
-    raise NotImplementedError("cold start is defined here for the softmax map")
+    """n_g = 0.98 with the hole shared equally among the weak orbitals, for
+    either map: the occupations are handed to the device-side map inversion
+    (nof_mlp_warm_gamma) as the angles theta with cos^2 theta = n."""
+    nof = inst["nof"]
+    ng, norb = inst["ng"], inst["norb"]
+    dev = inst["h"].device
+    members = torch.from_numpy(inst["members"]).to(dev)
+    theta = torch.full((norb,), 0.5 * math.pi, dtype=torch.float32, device=dev)      # n = 0
+    theta[members[:, 1:].reshape(-1).long()] = math.acos(math.sqrt((1.0 - nstrong) / ng))
+    theta[members[:, 0].long()] = math.acos(math.sqrt(nstrong))
+    return nof.mlp_warm_gamma(theta, members, inst["mapping"], norb, 0.0)
 
 
 def solve(inst, gamma0, maxit=3000, tol=1e-8):
@@ -153,13 +160,14 @@ def warm_gamma(nof, inst, params, nfloor=WARM_FLOOR):
     return nof.mlp_warm_gamma(theta, members, inst["mapping"], inst["norb"], nfloor)
 
 
-def evaluate(nof, factory, params, seeds, nbf, ns):
+def evaluate(nof, factory, params, seeds, nbf, ns, mapping=1):
     """Iterations and converged energies from the cold start, the network's
     warm start, and (as the ideal reference) a restart from the converged
-    variables themselves."""
+    variables themselves, with the optimiser on the given map (1 softmax,
+    0 trigonometric)."""
     rows = []
     for s in seeds:
-        inst = factory.make(int(s), nbf, ns)
+        inst = factory.make(int(s), nbf, ns, mapping=mapping)
         Ec, _, ic, okc, gc = solve(inst, cold_gamma(inst))
         Ew, _, iw, okw, _ = solve(inst, warm_gamma(nof, inst, params))
         _, _, ir, _, _ = solve(inst, gc)

@@ -76,6 +76,14 @@ def test_jk_and_fock_validation():
     assert L.nof_energy_ws(4) > 0 and L.nof_energy_ws(0) == 0
     assert L.nof_energy(4, *([FAKE] * 7), FAKE, L.nof_energy_ws(4) - 1, None) == nof.E_WORKSPACE
     assert L.nof_coeffs_from_cumulant(4, FAKE, None, FAKE, FAKE, FAKE, None) == nof.E_NULL
+    need = L.nof_coulomb_fock_ws(3, 4, 0)
+    assert need > 0 and L.nof_coulomb_fock_ws(3, 4, 2) == 0 and L.nof_coulomb_fock_ws(0, 4, 0) == 0
+    assert L.nof_coulomb_fock(3, 4, FAKE, 0, FAKE, FAKE, FAKE, None, FAKE, need - 1, None) == nof.E_WORKSPACE
+    assert L.nof_coulomb_fock(3, 4, FAKE, 0, None, FAKE, FAKE, None, FAKE, need, None) == nof.E_NULL
+    assert L.nof_coulomb_fock(3, 4, FAKE, 2, FAKE, FAKE, FAKE, None, FAKE, need, None) == nof.E_DTYPE
+    assert L.nof_coulomb_fock(0, 4, FAKE, 0, FAKE, FAKE, FAKE, None, FAKE, need, None) == nof.E_DIM
+    assert L.nof_lambda_grad(4, FAKE, FAKE, FAKE, None, FAKE, None, None) == nof.E_NULL
+    assert L.nof_lambda_grad(0, FAKE, FAKE, FAKE, FAKE, FAKE, None, None) == nof.E_DIM
 
 
 def test_exchange_split_and_stage_validation():
@@ -125,6 +133,22 @@ def test_solve_validation():
     assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
     assert L.nof_solve(*args(FAKE, prm, 8)) == nof.E_WORKSPACE
     assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_BF16X1) == 0
+    # iterative diagonalization needs a positive off-diagonal bound
+    bad = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10, 1, 0.0)
+    assert L.nof_solve(*args(FAKE, bad, 1 << 30)) == nof.E_ARG
+
+
+def test_pseudo_fock_diag_validation():
+    nof = _lib()
+    L = nof.lib
+    need = L.nof_pseudo_fock_diag_ws(5)
+    assert need >= 3 * 6 * 6 * 8 and L.nof_pseudo_fock_diag_ws(0) == 0 and L.nof_pseudo_fock_diag_ws(70000) == 0
+    assert L.nof_pseudo_fock_diag(0, FAKE, None, 1.0, FAKE, None, None, FAKE, need, None) == nof.E_DIM
+    assert L.nof_pseudo_fock_diag(5, None, None, 1.0, FAKE, None, None, FAKE, need, None) == nof.E_NULL
+    assert L.nof_pseudo_fock_diag(5, FAKE, None, 1.0, None, None, None, FAKE, need, None) == nof.E_NULL
+    assert L.nof_pseudo_fock_diag(5, FAKE, None, 0.0, FAKE, None, None, FAKE, need, None) == nof.E_ARG
+    assert L.nof_pseudo_fock_diag(5, FAKE, None, float("nan"), FAKE, None, None, FAKE, need, None) == nof.E_ARG
+    assert L.nof_pseudo_fock_diag(5, FAKE, None, 1.0, FAKE, None, None, FAKE, need - 1, None) == nof.E_WORKSPACE
     assert L.nof_solve_ws(2, 4, 4, 1, 1, 0, nof.P_F64) > 2 * 4 * 4 * 8
 
 
@@ -164,6 +188,8 @@ def test_plan_solve_validation():
         bad = nof.SolveParams(10, 30, 0.01, 1.0, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10)
         assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
         bad = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, float("nan"))
+        assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
+        bad = nof.SolveParams(10, 30, 0.01, 0.9, 0.999, 1e-8, 1e-5, 1e-9, 100, 1e-8, 1e-10, 1, 1.0)
         assert L.nof_plan_solve(*args(plan, FAKE, bad, need)) == nof.E_ARG
         assert L.nof_plan_solve(*args(plan, FAKE, prm, need - 1)) == nof.E_WORKSPACE
     finally:

@@ -211,3 +211,33 @@ def test_bf16_stored_B(nbf, naux, norb, seed):
     for k in ("b", "J", "K", "lam"):
         assert errs[k] <= tol, (k, errs[k])
     assert errs["E"] <= tolE
+
+
+def test_split_B_pieces_meet_documented_bounds():
+    """nof_split_B's planes read back: per row (P, mu), with 2^E the smallest
+    power of two above the row's largest |value|, piece q is an integer
+    n_q times 2^(E-7-8q) with |n_q| <= 128, the four pieces leave
+    |v - sum| <= 2^(E-32), and the padding columns are zero."""
+    nof = need_gpu()
+    nbf, naux = 50, 3
+    B = inputs.make_B(11, nbf, naux, 8.0)
+    B[1, 7, :] *= 1e-9            # rows far below the others keep their own grid
+    B[1, :, 7] *= 1e-9
+    B[2, 3, :] = 0.0              # an all-zero row
+    B[2, :, 3] = 0.0
+    planes = nof.SplitB(dev(B))
+    torch.cuda.synchronize()
+    ldk = (nbf + 31) // 32 * 32
+    pl = planes.planes.view(torch.bfloat16)[: 4 * naux * nbf * ldk].view(4, naux, nbf, ldk)
+    P = pl.to(torch.float64).cpu().numpy()
+    assert np.all(P[:, :, :, nbf:] == 0.0)
+    P = P[:, :, :, :nbf]
+    m = np.max(np.abs(B), axis=2)                       # [naux][nbf]
+    E = np.where(m > 0, np.frexp(m)[1], 0)
+    for q in range(4):
+        unit = np.ldexp(1.0, E - 7 - 8 * q)[:, :, None]
+        nq = P[q] / unit
+        assert np.array_equal(nq, np.rint(nq)), q
+        assert np.max(np.abs(nq)) <= 128, q
+    resid = np.abs(B - P.sum(axis=0))
+    assert np.all(resid <= np.ldexp(1.0, E - 32)[:, :, None])

@@ -53,6 +53,14 @@ def test_transform_jk_fock_energy_fp64(nbf, naux, norb, seed):
     assert abs(float(E) - ref["E"]) <= FP64_TOL * abs(ref["E"])
     F2 = nof.exchange_fock(b, dev(cK))
     assert normwise(host(F2), ref["F2"]) <= FP64_TOL
+    # the same build as its three steps (Coulomb-type pass with K, exchange-type
+    # term, lambda and g): identical to the fused call bit for bit
+    F1, K3 = nof.coulomb_fock(b, D, dev(cJ))
+    lam3, g3 = nof.lambda_grad(dev(n), h, F1, F2)
+    torch.cuda.synchronize()
+    assert normwise(host(F1), ref["F1"]) <= FP64_TOL
+    assert np.array_equal(host(K3), host(K2))
+    assert np.array_equal(host(lam3), host(lam)) and np.array_equal(host(g3), host(g))
 
 
 def test_structured_coefficients_hf_closed_form():

@@ -1,17 +1,17 @@
 """Parity at the benchmark's full sizes, in its launch configuration.
 
-c500 (Nbf=500, Naux=2000, Norb=500): the whole iteration as bench.py runs it
-(stage 1, stage 2, h, J, generalized Fock with fused K, energy) against the
-complete FP64 oracle, element by element, for the FP64, FP32, BF16 x6 and
-BF16 x10 (B split once into fixed-point planes) forms.
+c500 (Nbf=500, Naux=2000, Norb=500): the whole iteration (stage 1, stage 2,
+h, J, generalized Fock with fused K, energy) against the complete FP64
+oracle, element by element, for the FP64, FP32, BF16 x6 and BF16 x10 (B
+split once into fixed-point planes) forms.
 
-chain1000 (Nbf=1000, Naux=4000, Norb=1000): FP64 against the oracle on
-sampled outputs it computes slab by slab (b elements, J and K on a sample of
-orbitals), the orthogonal sum rules that hold at any size, and the split
-forms' energy errors against the FP64 GPU result: x10 within 1e-6 Eh with B
-given as planes of the FP64 B and with B stored in FP32 (whose rounding alone
-moves E by about 6e-7 Eh here); x6 to 2e-9 |E| (its matrix-core accumulation
-leaves about 6e-6 Eh).
+chain1000 (Nbf=1000, Naux=4000, Norb=1000): one whole iteration in the
+benchmark's call sequence (stages, h, J, Coulomb-type pass with K,
+exchange-type term, lambda and g, energy) against the oracle run slab by slab
+over all 4000 slabs: E, J, K, lambda and g to 1e-10 normwise in FP64; the x10
+forms (B as planes of the FP64 B; B stored in FP32, whose rounding alone
+moves E by about 6e-7 Eh here) within 1e-6 Eh of the oracle's E; also the
+orthogonal sum rules, which hold at any size.
 """
 import numpy as np
 import pytest
@@ -55,6 +55,8 @@ def test_c500_full_iteration_all_forms():
     print("oracle E", ref["E"], flush=True)
     Cd, Hd, nd, cJd, cKd = dev(C), dev(H), dev(n), dev(cJ), dev(cK)
     bounds = {"f64": (1e-10, 1e-10), "f32": (2e-6, 1e-8), "bf16x6": (5e-7, 2e-9), "bf16x10": (3e-7, 1e-9)}
+    # g = 4 (lambda - lambda^T) is normed by its own (smaller) maximum
+    gbounds = {"f64": 1e-10, "f32": 5e-5, "bf16x6": 2e-6, "bf16x10": 2e-6}
     for form, prec, dt in (("f64", nof.P_F64, torch.float64), ("f32", nof.P_F32, torch.float32),
                            ("bf16x6", nof.P_BF16X6, torch.float32), ("bf16x10", nof.P_BF16X10, torch.float32)):
         Bd = dev(B, torch.float64 if form in ("f64", "bf16x10") else torch.float32)
@@ -72,10 +74,38 @@ def test_c500_full_iteration_all_forms():
         tol, tolE = bounds[form]
         for k in ("b", "D", "J", "K", "lam"):
             assert errs[k] <= tol, (form, k, errs[k])
+        assert errs["g"] <= gbounds[form], (form, errs["g"])
         assert errs["E"] <= tolE, (form, errs["E"])
 
 
-def test_chain1000_sampled_and_precision_form():
+def bench_step(nof, B, C, H, n, cJ, cK, prec, dt):
+    """One iteration in bench.py's call sequence: the stages (one
+    nof_mo_transform call for x10), h, J, the Coulomb-type pass with K, the
+    exchange-type term, lambda and g, E."""
+    naux, nbf, _ = B.shape
+    norb = C.shape[1]
+    b = torch.empty((naux, norb, norb), dtype=dt, device="cuda")
+    D = torch.empty((naux, norb), dtype=torch.float64, device="cuda")
+    if prec == nof.P_BF16X10:
+        nof.mo_transform(B, C, prec=prec, b=b, D=D)
+    else:
+        T = torch.empty((naux, nbf, norb), dtype=dt, device="cuda")
+        nof.transform_stage1(B, C, T, prec=prec)
+        nof.transform_stage2(T, C, b, D, prec=prec)
+        del T
+    h = nof.one_electron(H, C)
+    J, _ = nof.jk_diag(b, D, want_K=False)
+    F1, K = nof.coulomb_fock(b, D, cJ)
+    F2 = nof.exchange_fock(b, cK, prec=prec)
+    lam, g = nof.lambda_grad(n, h, F1, F2)
+    E = nof.energy(n, h, J, K, cJ, cK)
+    torch.cuda.synchronize()
+    del b, D
+    torch.cuda.empty_cache()
+    return dict(h=host(h), J=host(J), K=host(K), lam=host(lam), g=host(g), E=float(E))
+
+
+def test_chain1000_against_oracle_all_forms():
     nof = need_gpu()
     w = inputs.WORKLOADS["chain1000"]
     print("case chain1000", flush=True)
@@ -84,43 +114,35 @@ def test_chain1000_sampled_and_precision_form():
     H = inputs.make_H(w.seed, w.nbf)
     n = inputs.make_occupations(w.seed, w.norb, w.nstrong)
     nn = np.outer(n, n)
-    Cd, Hd, nd, cJd, cKd = dev(C), dev(H), dev(n), dev(2.0 * nn), dev(nn)
+    cJ, cK = 2.0 * nn, nn
+    Cd, Hd, nd, cJd, cKd = dev(C), dev(H), dev(n), dev(cJ), dev(cK)
     Bd = dev(B)
-    b, D, got64 = gpu_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_F64, torch.float64)
-    # sampled oracle values, slab by slab
-    rng = np.random.default_rng(0)
-    S = np.sort(rng.choice(w.norb, 6, replace=False))
-    CS = C[:, S]
-    bSS = np.einsum("mp,Pmn,nq->Ppq", CS, B, CS, optimize=True)      # b^P on the sample, all P
-    DS = np.diagonal(bSS, axis1=1, axis2=2)
-    J_ref = DS.T @ DS
-    K_ref = np.einsum("Ppq,Ppq->pq", bSS, bSS)
-    bh = host(b[:, S][:, :, S])
-    assert normwise(bh, bSS) <= 1e-10
-    assert normwise(got64["J"][np.ix_(S, S)], J_ref) <= 1e-10
-    assert normwise(got64["K"][np.ix_(S, S)], K_ref) <= 1e-10
+    got64 = bench_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_F64, torch.float64)
+    planes = nof.SplitB(Bd)
+    del Bd
+    torch.cuda.empty_cache()
+    gotx = bench_step(nof, planes, Cd, Hd, nd, cJd, cKd, nof.P_BF16X10, torch.float32)
+    del planes
+    torch.cuda.empty_cache()
+    Bd = dev(B, torch.float32)
+    gotx32 = bench_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_BF16X10, torch.float32)
+    del Bd
+    torch.cuda.empty_cache()
+    print("gpu done; oracle over all slabs", flush=True)
+    ref = dfjk.streamed_iteration(lambda lo, hi: B[lo:hi], w.naux, C, H, n, cJ, cK, pblock=100)
+    errs = {k: normwise(got64[k], ref[k]) for k in ("h", "J", "K", "lam", "g")}
+    errs["E"] = abs(got64["E"] - ref["E"]) / abs(ref["E"])
+    print("chain1000 FP64 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, "E", ref["E"], flush=True)
+    for k, v in errs.items():
+        assert v <= 1e-10, (k, v)
+    for name, got in (("x10 planes of FP64 B", gotx), ("x10 FP32 B", gotx32)):
+        dE = got["E"] - ref["E"]
+        print("chain1000", name, "dE (Eh)", dE, "max dJ", np.abs(got["J"] - ref["J"]).max(),
+              "max dK", np.abs(got["K"] - ref["K"]).max(), "lambda normwise", normwise(got["lam"], ref["lam"]),
+              flush=True)
+        assert abs(dE) <= 1e-6, (name, dE)
     # orthogonal sum rules (Norb = Nbf): sum K = sum_P ||B^P||_F^2, sum J = sum_P (tr B^P)^2
     sK = float(np.einsum("Pmn,Pmn->", B, B))
     sJ = float(np.sum(np.trace(B, axis1=1, axis2=2) ** 2))
     assert abs(got64["K"].sum() - sK) <= 1e-10 * sK
     assert abs(got64["J"].sum() - sJ) <= 1e-10 * sJ
-    del b, D, Bd
-    torch.cuda.empty_cache()
-    Bd = dev(B, torch.float32)
-    b, D, got = gpu_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_BF16X6, torch.float32)
-    dE = got["E"] - got64["E"]
-    print("chain1000 E64", got64["E"], "bf16x6 dE (Eh)", dE, "max dJ", np.abs(got["J"] - got64["J"]).max(),
-          "max dK", np.abs(got["K"] - got64["K"]).max(), flush=True)
-    assert abs(dE) <= 2e-9 * abs(got64["E"])
-    del b, D
-    torch.cuda.empty_cache()
-    b, D, got = gpu_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_BF16X10, torch.float32)
-    dE32 = got["E"] - got64["E"]
-    del b, D, Bd
-    torch.cuda.empty_cache()
-    planes = nof.SplitB(dev(B))
-    b, D, got = gpu_step(nof, planes, Cd, Hd, nd, cJd, cKd, nof.P_BF16X10, torch.float32)
-    dE64 = got["E"] - got64["E"]
-    print("chain1000 bf16x10 dE (Eh): FP32 B", dE32, "planes of FP64 B", dE64,
-          "max dJ", np.abs(got["J"] - got64["J"]).max(), "max dK", np.abs(got["K"] - got64["K"]).max(), flush=True)
-    assert abs(dE64) <= 1e-6 and abs(dE32) <= 1e-6

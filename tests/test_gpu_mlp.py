@@ -77,8 +77,9 @@ def test_trained_network_against_cold_start():
     larger instances, the optimiser's iterations from the cold start, from the
     network's warm start and from the converged point itself (the ideal warm
     start).  Checks that training reduces the loss, that every start converges
-    to the same energy, and that the warm start costs at most twice the cold
-    start; the gain itself is measured, not asserted."""
+    to the same energy, and that the warm start needs fewer iterations than
+    the cold start on average (the runs are bitwise repeatable: fixed-order
+    reductions everywhere)."""
     nof = need_gpu()
     from paper_2512_13550_amd import warmstart
     fac = warmstart.InstanceFactory(nof, gap=0.5)
@@ -96,4 +97,21 @@ def test_trained_network_against_cold_start():
     assert all(r["converged"] for r in rows)
     assert dE.max() <= 1e-7
     assert ideal.max() <= 5
-    assert warm.mean() <= 2.0 * cold.mean()
+    assert warm.mean() < cold.mean()
+
+
+@pytest.mark.parametrize("mapping", [0, 1])
+def test_cold_start_through_device_map(mapping):
+    """The cold start (n_g = 0.98, the hole shared equally) built by the
+    device-side map inversion equals the closed form of either map (to the
+    FP32 rounding of the angles handed over)."""
+    nof = need_gpu()
+    from paper_2512_13550_amd import warmstart
+    fac = warmstart.InstanceFactory(nof, gap=0.5)
+    inst = fac.make(77, 60, 12, mapping=mapping)
+    g = host(warmstart.cold_gamma(inst))
+    ng = inst["ng"]
+    n = occupations.occupations(g, inst["members"], inst["norb"], "trig" if mapping == 0 else "softmax")
+    for row in inst["members"]:
+        assert abs(n[row[0]] - 0.98) < 1e-6
+        assert np.all(np.abs(n[row[1:]] - 0.02 / ng) < 1e-6)

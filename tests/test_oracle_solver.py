@@ -78,3 +78,60 @@ def test_pnof5_converged_point_is_stationary(mapping):
         gp = gamma + 1e-3 * rng.standard_normal(gamma.shape)
         Ep, _, _ = occupations.energy_and_grad(gp, members, nbf, mapping, np.diag(h), J, K, "pnof5")
         assert Ep >= E - 1e-10
+
+
+# ---- iterative diagonalization of the generalized pseudo-Fockian (orbopt = 1) ----
+
+def test_pseudo_fock_diagonal_at_symmetric_lambda():
+    """A symmetric lambda (the minimum) gives a diagonal pseudo-Fockian, whose
+    eigenvectors are the current orbitals: the step leaves C unchanged."""
+    from oracle import diagonalization
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((9, 9))
+    lam = A + A.T
+    F = diagonalization.pseudo_fock(lam, np.diag(lam), 1.0)
+    assert np.array_equal(F, np.diag(np.diag(lam)))
+    C = inputs.make_C(1, 12, 9)
+    C2, e, V = diagonalization.step(C, lam, None, 1.0)
+    assert np.array_equal(V, np.eye(9)) and np.array_equal(C2, C)
+
+
+def test_pseudo_fock_step_descends_to_first_order():
+    """Small asymmetry: the diagonalization rotates the orbitals by
+    y_pq = -g_pq / (4 |d_q - d_p|) to first order (a descent step for every
+    pair, whatever the index order of the diagonal), so the energy change
+    predicted by the gradient, sum_{p<q} g_pq y_pq, is negative."""
+    from oracle import diagonalization
+    rng = np.random.default_rng(2)
+    m = 8
+    d = rng.permutation(np.linspace(-3.0, 2.0, m))          # diagonal not sorted by index
+    S = rng.standard_normal((m, m)); S = S + S.T
+    Aa = rng.standard_normal((m, m)); Aa = Aa - Aa.T
+    eps = 1e-6
+    lam = np.diag(d) + 0.1 * (S - np.diag(np.diag(S))) + eps * Aa
+    g = 4.0 * (lam - lam.T)
+    _, _, V = diagonalization.step(np.eye(m), lam, d, 1.0)
+    y = (V - V.T) / 2.0                                     # first-order generator
+    for p in range(m):
+        for q in range(p + 1, m):
+            expect = -g[p, q] / (4.0 * abs(d[q] - d[p]))
+            assert abs(y[p, q] - expect) <= 1e-3 * abs(expect) + 1e-12
+    dE = sum(g[p, q] * y[p, q] for p in range(m) for q in range(p + 1, m))
+    assert dE < 0.0
+
+
+def test_iterative_diagonalization_hf_equals_roothaan_scf():
+    """0/1 occupations, HF-like coefficients: the iterative diagonalization
+    converges to the minimum that the textbook Roothaan SCF with DIIS finds
+    independently, with lambda symmetric."""
+    nbf, naux, nocc = 24, 96, 6
+    B = inputs.make_B_grid(nbf, naux, seed=3)
+    H = inputs.make_H(3, nbf)
+    C0 = inputs.make_C(3, nbf, nbf)
+    members = np.array(inputs.pairing(nbf, nocc, 1), dtype=np.int64)
+    gamma = np.zeros((nocc, 1))
+    r = solver.solve(B, C0, H, members, "trig", "hf", gamma, max_outer=3, no_steps=2000,
+                     tol_lambda=1e-8, on_maxit=0, orbopt=1, maxoff=1.0)
+    assert r["converged"], (r["asym"], r["no_steps"])
+    E_scf = scf_energy(B, H, nocc)
+    assert abs(r["E"] - E_scf) <= 1e-10 * abs(E_scf), (r["E"], E_scf)
