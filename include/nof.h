@@ -401,6 +401,21 @@ int nof_occ_optimize(int norb, int ns, int ng, const int* members, int map, int 
                      const double* hdiag, int hstride, const double* J, const double* K,
                      double* gamma, double* n, double* E, int* info, int maxit, double tol,
                      void* ws, size_t ws_bytes, hipStream_t stream);
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): nof_occ_optimize with its scratch in a static device array of
+ * 32 MiB per GPU (allocated with the library's code object on each GPU it
+ * runs on, held until the process ends).  Same arguments and results as
+ * nof_occ_optimize without ws/ws_bytes; problems whose nof_occ_ws(norb, ns,
+ * ng) exceeds 32 MiB (about norb > 2000) return NOF_E_DIM.  Uses the scratch
+ * of the current device: stream must belong to it.  Every call on a GPU
+ * shares that GPU's scratch, so calls that overlap on one GPU (other streams
+ * or threads) race; every call writes all scratch it reads, so nothing must
+ * start at zero.  Allocates nothing. */
+int nof_occ_optimize_noalloc(int norb, int ns, int ng, const int* members, int map, int func,
+                             const double* hdiag, int hstride, const double* J, const double* K,
+                             double* gamma, double* n, double* E, int* info, int maxit,
+                             double tol, hipStream_t stream);
 int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func,
                           const double* n, double* cJ, double* cK, int* info, void* ws,
                           size_t ws_bytes, hipStream_t stream);

@@ -1,6 +1,7 @@
 // extern "C" entry points declared in include/nof.h: host-side validation,
 // workspace layout and the launch sequence of each call.
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -632,6 +633,54 @@ int nof_occ_optimize(int norb, int ns, int ng, const int* members, int map, int 
     if (hstride < 1 || maxit < 0 || !(tol >= 0.0)) return NOF_E_ARG;
     if (!members || !gamma || !hdiag || !J || !K) return NOF_E_NULL;
     if (!ws || ws_bytes < occ_ws(norb, ns, ng)) return NOF_E_WORKSPACE;
+    return occ_optimize(norb, ns, ng, members, map, func, hdiag, hstride, J, K, gamma, n, E, info,
+                        maxit, tol, ws, stream);
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of nof_occ_optimize_noalloc: one array per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel: its
+// device address is taken per device with hipGetSymbolAddress on the first
+// call made with that device current, and kept.
+constexpr size_t kOccScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kOccScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+int occ_scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return NOF_E_HIP;
+  if (dev < 0 || dev >= kScratchDevices) return NOF_E_INTERNAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NOF_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nof_occ_optimize_noalloc(int norb, int ns, int ng, const int* members, int map, int func,
+                             const double* hdiag, int hstride, const double* J, const double* K,
+                             double* gamma, double* n, double* E, int* info, int maxit, double tol,
+                             hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!occ_args_ok(norb, ns, ng, map, func)) return NOF_E_DIM;
+    if (hstride < 1 || maxit < 0 || !(tol >= 0.0)) return NOF_E_ARG;
+    if (!members || !gamma || !hdiag || !J || !K) return NOF_E_NULL;
+    if (occ_ws(norb, ns, ng) > kOccScratchBytes) return NOF_E_DIM;
+    void* ws = nullptr;
+    NOF_TRY(occ_scratch_of_current_device(&ws));
     return occ_optimize(norb, ns, ng, members, map, func, hdiag, hstride, J, K, gamma, n, E, info,
                         maxit, tol, ws, stream);
   });

@@ -63,6 +63,8 @@ _sig("nof_occ_energy_grad", _i, _i, _i, _i, _vp, _i, _i, _vp, _vp, _i, _vp, _vp,
      _sz, _vp)
 _sig("nof_occ_optimize", _i, _i, _i, _i, _vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i, _d, _vp,
      _sz, _vp)
+_sig("nof_occ_optimize_noalloc", _i, _i, _i, _i, _vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i, _d,
+     _vp)
 _sig("nof_functional_coeffs", _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
 _PLAN_ARGS = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _sig("nof_plan_create", _i, ctypes.POINTER(_vp), _i, _i, _i, _i, _i)
@@ -121,7 +123,7 @@ DECLARED = [
     "nof_coulomb_fock_ws", "nof_coulomb_fock", "nof_lambda_grad", "nof_energy_ws", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_orthonormalize_ws", "nof_orthonormalize",
-    "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize",
+    "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize", "nof_occ_optimize_noalloc",
     "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
     "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
