@@ -74,30 +74,37 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_digest():
-    """Digest of the sources that decide the timed kernels' code and launch
-    configuration (the counter traffic figure is stale once they change)."""
+# the sources that decide each timed kernel's code and launch configuration
+KERNEL_SOURCES = {"k_exchange_fock": ("gemm_tn.hip", "api.hip", "common.h"),
+                  "k_transform_stage1": ("gemm_tn.hip", "api.hip", "common.h"),
+                  "k_transform_stage2": ("gemm_tn.hip", "api.hip", "common.h"),
+                  "k_kf1": ("passes.hip", "api.hip", "common.h")}
+
+
+def kernel_source_digest(kernel):
+    """Digest of a kernel's sources (its counter traffic is stale once they change)."""
     import hashlib
     root = os.path.join(ROOT, "paper_2512_13550_amd", "csrc")
     h = hashlib.sha256()
-    for fn in ("gemm_tn.hip", "passes.hip", "api.hip", "common.h"):
+    for fn in KERNEL_SOURCES[kernel]:
         with open(os.path.join(root, fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(path, kernel):
-    """HBM bytes per launch of a kernel from a committed counter summary, or
-    None when absent or taken on other kernel sources."""
+    """HBM-side bytes per launch of a kernel from a committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel's readings), or None when
+    absent or taken on other sources of that kernel."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_digest") != kernel_source_digest():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return k.get("bytes_per_launch") if k else None
+    if not k or k.get("source_digest") != kernel_source_digest(kernel):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_model():

@@ -321,9 +321,11 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
  *
  * (the orientation makes the first-order rotation a descent step for every
  * pair; the paper leaves the diagonal open).  F is diagonalized (cyclic
- * Jacobi, rotations of at most pi/4); eigenvector k is assigned to the
- * orbital on which it has the largest weight, with a non-negative component
- * there: V[:, r] is that eigenvector and eig[r] its eigenvalue.  The caller
+ * Jacobi, rotations of at most pi/4); eigenvectors are matched to orbitals
+ * greedily by overlap (the largest |U_rk| of a still-free orbital r and
+ * eigenvector k first; ties to the smaller r, then k), each with a
+ * non-negative component on its orbital: V[:, r] is that eigenvector and
+ * eig[r] its eigenvalue.  The caller
  * then forms C <- C V (nof_rotate_orbitals) and passes eig as the next
  * step's diag.
  *
@@ -331,8 +333,7 @@ int nof_adam_step(int norb, const double* g, double* m, double* v, int t, double
  *         lambda_pp (the first step of a run).   maxoff > 0.
  * V       out [norb][norb] FP64.      eig   out [norb] FP64 or NULL.
  * info    device int[2] or NULL: [0] Jacobi sweeps (-1: not converged),
- *         [1] 1 if the largest-weight assignment was a permutation (else the
- *         eigenvectors stay in the solver's order).
+ *         [1] rounds of the matching (each takes at least one pair).
  * ws      nof_pseudo_fock_diag_ws(norb) bytes.  norb <= 65536.
  * Synchronises the stream once per Jacobi sweep (not capturable).
  * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_ARG (maxoff, or lambda not finite),

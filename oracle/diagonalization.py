@@ -20,9 +20,11 @@ expression exists).  Readings taken here:
   large early steps);
 * diagonal: lambda_pp at the first step of a run, afterwards the
   eigenvalues of the previous step, each kept with its orbital;
-* each eigenvector is assigned to the orbital it overlaps most (the
-  assignment maximising the summed squared overlaps), with a non-negative
-  component on that orbital, so orbital roles survive the step;
+* eigenvectors are matched to orbitals greedily by overlap: the largest
+  |V_rk| among pairs whose orbital r and eigenvector k are both still free
+  is taken first (ties to the smaller r, then the smaller k); each
+  eigenvector gets a non-negative component on its orbital, so orbital roles
+  survive the step;
 * new orbitals C <- C V (orbitals as columns).
 
 For 0/1 occupations with Delta = Pi = 0, lambda_rs = n_s F_rs with F the
@@ -32,7 +34,6 @@ this F is the Fock matrix's and the fixed point is the Roothaan SCF minimum.
 from __future__ import annotations
 
 import numpy as np
-from scipy.optimize import linear_sum_assignment
 
 
 def pseudo_fock(lam, diag, maxoff):
@@ -49,16 +50,32 @@ def pseudo_fock(lam, diag, maxoff):
     return F
 
 
+def greedy_overlap_match(U):
+    """orbital_of[k] for every eigenvector k (column of U): pairs (r, k) in
+    decreasing |U_rk| (ties: smaller r, then smaller k), each taken when both
+    r and k are still free."""
+    m = U.shape[0]
+    a = np.abs(U)
+    order = sorted(((-a[r, k], r, k) for r in range(m) for k in range(m)))
+    orbital_of = -np.ones(m, dtype=np.int64)
+    row_used = np.zeros(m, dtype=bool)
+    for _, r, k in order:
+        if orbital_of[k] < 0 and not row_used[r]:
+            orbital_of[k] = r
+            row_used[r] = True
+    return orbital_of
+
+
 def diagonalize(F):
     """Eigenvalues and eigenvectors of the symmetric F, eigenvector k placed
-    in column assign(k) by the maximum-overlap assignment, signs fixed so that
-    V_pp >= 0.  Returns (eigenvalues per orbital, V)."""
+    in column orbital_of[k] of the greedy overlap matching, signs fixed so
+    that V_pp >= 0.  Returns (eigenvalues per orbital, V)."""
     w, U = np.linalg.eigh(F)
-    rows, cols = linear_sum_assignment(-(U * U))      # orbital rows[i] <- eigenvector cols[i]
+    orbital_of = greedy_overlap_match(U)
     V = np.empty_like(U)
     e = np.empty_like(w)
-    V[:, rows] = U[:, cols]
-    e[rows] = w[cols]
+    V[:, orbital_of] = U
+    e[orbital_of] = w
     sgn = np.where(np.diag(V) < 0.0, -1.0, 1.0)
     return e, V * sgn[None, :]
 

@@ -20,10 +20,9 @@
 // padded with a decoupled zero row and column.  Sweeps stop when
 // max|A_pq| (p != q) <= 1e-14 max|A_pp| (checked on the host between sweeps).
 //
-// Afterwards eigenvector k goes to the orbital r(k) on which it has the
-// largest weight (V column r(k) = +-eigenvector k with V_rr >= 0, eig_r =
-// its eigenvalue); when r is not a permutation the Jacobi order is kept and
-// info[1] = 0.
+// Afterwards the eigenvectors are matched to the orbitals greedily by
+// overlap (k_assign): V column r(k) = +-eigenvector k with V_rr >= 0, eig_r =
+// its eigenvalue.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -179,37 +178,76 @@ __global__ __launch_bounds__(1024) void k_offdiag(int norb, int np, const double
   }
 }
 
-// r(k) = argmax_r |W_rk| (smallest r on ties) for every eigenvector k; info[1]
-// = 1 when r is a permutation (then perm = r), else perm = identity.
+// Greedy overlap matching of eigenvectors (columns k of W) to orbitals (rows
+// r): pairs in decreasing |W_rk| (ties: smaller r, then smaller k), each
+// taken while both are free.  Computed as rounds of mutual best choices
+// (every free column's best free row, every free row's best free column; a
+// pair that chose each other is the largest of all pairs touching either, so
+// the greedy rule takes it too); each round takes at least the largest free
+// pair, so at most norb rounds.  perm[k] = orbital of eigenvector k;
+// info[0] = sweeps, info[1] = rounds.  One workgroup.
 __global__ __launch_bounds__(1024) void k_assign(int norb, int np, const double* __restrict__ W,
-                                                 int* __restrict__ perm, int* __restrict__ cnt,
+                                                 int* __restrict__ perm, int* __restrict__ used,
+                                                 int* __restrict__ best_row, int* __restrict__ best_col,
                                                  int* __restrict__ info, int sweeps) {
-  __shared__ int ok;
-  for (int r = threadIdx.x; r < norb; r += 1024) cnt[r] = 0;
-  if (threadIdx.x == 0) ok = 1;
-  __syncthreads();
-  for (int k = threadIdx.x; k < norb; k += 1024) {
-    int best = 0;
-    double bv = -1.0;
-    for (int r = 0; r < norb; ++r) {
-      const double a = fabs(W[(long long)r * np + k]);
-      if (a > bv) {
-        bv = a;
-        best = r;
-      }
-    }
-    perm[k] = best;
-    atomicAdd(&cnt[best], 1);
+  __shared__ int more;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < norb; i += 1024) {
+    perm[i] = -1;
+    used[i] = 0;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < norb; r += 1024)
-    if (cnt[r] != 1) ok = 0;          // every writer stores the same value
-  __syncthreads();
-  if (!ok)
-    for (int k = threadIdx.x; k < norb; k += 1024) perm[k] = k;
-  if (threadIdx.x == 0 && info) {
+  int rounds = 0;
+  for (;;) {
+    ++rounds;
+    for (int k = tid; k < norb; k += 1024) {
+      if (perm[k] >= 0) continue;
+      int br = -1;
+      double bv = -1.0;
+      for (int r = 0; r < norb; ++r) {
+        if (used[r]) continue;
+        const double a = fabs(W[(long long)r * np + k]);
+        if (a > bv) {
+          bv = a;
+          br = r;
+        }
+      }
+      best_row[k] = br;
+    }
+    for (int r = tid; r < norb; r += 1024) {
+      if (used[r]) continue;
+      int bc = -1;
+      double bv = -1.0;
+      const double* row = W + (long long)r * np;
+      for (int k = 0; k < norb; ++k) {
+        if (perm[k] >= 0) continue;
+        const double a = fabs(row[k]);
+        if (a > bv) {
+          bv = a;
+          bc = k;
+        }
+      }
+      best_col[r] = bc;
+    }
+    __syncthreads();
+    for (int k = tid; k < norb; k += 1024) {
+      if (perm[k] >= 0) continue;
+      const int r = best_row[k];
+      if (best_col[r] == k) {
+        perm[k] = r;
+        used[r] = 1;
+      }
+    }
+    if (tid == 0) more = 0;
+    __syncthreads();
+    for (int k = tid; k < norb; k += 1024)
+      if (perm[k] < 0) more = 1;          // every writer stores the same value
+    __syncthreads();
+    if (!more || rounds >= norb) break;
+  }
+  if (tid == 0 && info) {
     info[0] = sweeps;
-    info[1] = ok;
+    info[1] = rounds;
   }
 }
 
@@ -230,7 +268,7 @@ __global__ void k_permute(int norb, int np, const double* __restrict__ W, const 
 
 struct DiagLayout {
   int np;
-  size_t a0, a1, w, perm, cnt, scal, total;
+  size_t a0, a1, w, perm, used, brow, bcol, scal, total;
 };
 DiagLayout diag_layout(int norb) {
   DiagLayout L;
@@ -241,7 +279,9 @@ DiagLayout diag_layout(int norb) {
   L.a1 = o;   o += align256(m);
   L.w = o;    o += align256(m);
   L.perm = o; o += align256((size_t)norb * sizeof(int));
-  L.cnt = o;  o += align256((size_t)norb * sizeof(int));
+  L.used = o; o += align256((size_t)norb * sizeof(int));
+  L.brow = o; o += align256((size_t)norb * sizeof(int));
+  L.bcol = o; o += align256((size_t)norb * sizeof(int));
   L.scal = o; o += 256;
   L.total = o;
   return L;
@@ -272,7 +312,9 @@ int nof_pseudo_fock_diag(int norb, const double* lambda, const double* diag, dou
     double* B = (double*)(w + L.a1);
     double* W = (double*)(w + L.w);
     int* perm = (int*)(w + L.perm);
-    int* cnt = (int*)(w + L.cnt);
+    int* used = (int*)(w + L.used);
+    int* brow = (int*)(w + L.brow);
+    int* bcol = (int*)(w + L.bcol);
     double* scal = (double*)(w + L.scal);
     const int np = L.np;
     const long long nn = (long long)np * np;
@@ -306,7 +348,7 @@ int nof_pseudo_fock_diag(int norb, const double* lambda, const double* diag, dou
       }
       ++sweeps;
     }
-    hipLaunchKernelGGL(k_assign, dim3(1), dim3(1024), 0, stream, norb, np, W, perm, cnt, info,
+    hipLaunchKernelGGL(k_assign, dim3(1), dim3(1024), 0, stream, norb, np, W, perm, used, brow, bcol, info,
                        converged ? sweeps : -1);
     if ((rc = launch_status()) != NOF_OK) return rc;
     hipLaunchKernelGGL(k_permute, dim3(dg_grid((long long)norb * norb)), dim3(DG_THR), 0, stream, norb, np,

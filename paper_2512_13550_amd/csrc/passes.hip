@@ -170,7 +170,7 @@ __device__ __forceinline__ void kf_run(const TB* __restrict__ b, const double* _
 // VEC: norb even and b 16-byte aligned, so every pair starting at an even
 // column is one aligned vector.  Instance i reads b + i*bstride, W + i*wstride
 // and writes its partials at + i*pstride.
-template <typename TB, bool VEC, int PIPE>
+template <typename TB, bool VEC, int PIPE, bool WANTF>
 __global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __restrict__ b,
                                                 const double* __restrict__ W,
                                                 double* __restrict__ Kpart,
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const long long plane = (long long)norb * norb;
-  const bool wantF = F1part != nullptr;
+  constexpr bool wantF = WANTF;
   for (long long u = blockIdx.x; u < units; u += gridDim.x) {
     const int tile = (int)(u % ntiles);
     const long long ic = u / ntiles;
@@ -222,17 +222,10 @@ __global__ __launch_bounds__(KF_THR) void k_kf1(int naux, int norb, const TB* __
                       (tr * KF_R + KF_R <= norb);
 
     double k[KF_RW][2] = {}, frs[KF_RW][2] = {}, fsr[KF_RW][2] = {};
-    if (wantF) {
-      if (full)
-        kf_run<TB, VEC, true, true, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
-      else
-        kf_run<TB, VEC, false, true, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
-    } else {
-      if (full)
-        kf_run<TB, VEC, true, false, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
-      else
-        kf_run<TB, VEC, false, false, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
-    }
+    if (full)
+      kf_run<TB, VEC, true, WANTF, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
+    else
+      kf_run<TB, VEC, false, WANTF, PIPE>(bi, Wi, norb, plane, p_lo, p_hi, L, k, frs, fsr);
 
     const long long cb = (long long)inst * pstride + (long long)chunk * plane;
 #pragma unroll
@@ -430,9 +423,16 @@ int kf1_pass(int naux, int norb, const void* b, int bt, const double* W, double*
   const bool vec = (norb % 2) == 0 && ((uintptr_t)b % 16) == 0 && ((bstride * esz) % 16) == 0 &&
                    (!W || (((uintptr_t)W % 16) == 0 && (wstride % 2) == 0));
 #define NOF_KF1(TB, V)                                                                          \
-  hipLaunchKernelGGL((k_kf1<TB, V, KF_PIPE>), grid, dim3(KF_THR), 0, st, naux, norb,            \
-                     (const TB*)b, W, Kpart, F1part, pl.pchunk, pl.nchunk, ntiles, ntr, ntc,     \
-                     ninst, bstride, wstride, pstride)
+  do {                                                                                          \
+    if (F1part)                                                                                 \
+      hipLaunchKernelGGL((k_kf1<TB, V, KF_PIPE, true>), grid, dim3(KF_THR), 0, st, naux, norb,  \
+                         (const TB*)b, W, Kpart, F1part, pl.pchunk, pl.nchunk, ntiles, ntr, ntc, \
+                         ninst, bstride, wstride, pstride);                                     \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_kf1<TB, V, KF_PIPE, false>), grid, dim3(KF_THR), 0, st, naux, norb, \
+                         (const TB*)b, W, Kpart, F1part, pl.pchunk, pl.nchunk, ntiles, ntr, ntc, \
+                         ninst, bstride, wstride, pstride);                                     \
+  } while (0)
   if (bt == NOF_F64) {
     if (vec) NOF_KF1(double, true); else NOF_KF1(double, false);
   } else if (bt == NOF_F32) {

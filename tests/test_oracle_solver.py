@@ -135,3 +135,17 @@ def test_iterative_diagonalization_hf_equals_roothaan_scf():
     assert r["converged"], (r["asym"], r["no_steps"])
     E_scf = scf_energy(B, H, nocc)
     assert abs(r["E"] - E_scf) <= 1e-10 * abs(E_scf), (r["E"], E_scf)
+
+
+def test_greedy_overlap_match_hand_cases():
+    """The greedy overlap matching on hand-made overlap matrices: a
+    permutation matrix is read back; a case where the optimal sum assignment
+    and the greedy rule differ takes the single largest overlap first."""
+    from oracle import diagonalization
+    P = np.eye(4)[[2, 0, 3, 1]]           # eigenvector k lives on orbital P[:, k].argmax()
+    assert list(diagonalization.greedy_overlap_match(P)) == [1, 3, 0, 2]
+    U = np.array([[0.9, 0.8], [0.8, 0.0]])
+    # greedy: (r0, k0) = 0.9 first, then (r1, k1) = 0.0;  the sum-optimal would pick 0.8 + 0.8
+    assert list(diagonalization.greedy_overlap_match(U)) == [0, 1]
+    T = np.array([[0.5, 0.5], [0.5, 0.5]])  # ties: smaller r, then smaller k
+    assert list(diagonalization.greedy_overlap_match(T)) == [0, 1]
