@@ -458,6 +458,16 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
  * ------------------------------------------------------------------------- */
 typedef struct nof_plan_s* nof_plan;
 int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int prec);
+/* Workspace layout of a plan (host only, no GPU work): the byte offset and
+ * size of each of its regions, in order (first min(count, max_regions)
+ * entries; offsets or bytes may be NULL).  Returns the region count, or
+ * NOF_E_NULL / NOF_E_ARG.  Regions are 256-byte aligned, disjoint and end
+ * within nof_plan_ws(plan); the order is: packed C, T, b, D, the one-electron
+ * half transform, h, J, K, W, K partials, F1 partials, F2 partials, F1, F2,
+ * energy partials, and for NOF_P_BF16X10 the planes of the packed C, the
+ * column maxima of T per row tile, the grid exponents of T's columns and
+ * every instance's cK transposed in FP32 (size 0 otherwise). */
+int nof_plan_layout(nof_plan plan, size_t* offsets, size_t* bytes, int max_regions);
 size_t nof_plan_ws(nof_plan plan);
 int nof_plan_get_config(nof_plan plan, int* cfg);
 int nof_plan_set_config(nof_plan plan, const int* cfg);

@@ -35,6 +35,7 @@ struct nof_plan_s {
   int tile_s1, tile_s2, tile_f2, f2gpi;    // tuned choices
   int kchunks;
   size_t off[nof::O_N];                    // one offset per region
+  size_t bytes[nof::O_N];                  // and its size
   size_t total;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -76,6 +77,7 @@ void plan_layout(nof_plan_s* p) {
   size_t o = 0;
   for (int i = 0; i < O_N; ++i) {
     p->off[i] = o;
+    p->bytes[i] = sz[i];
     o = align256(o + sz[i]);
   }
   p->total = o;
@@ -657,6 +659,17 @@ int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int 
 }
 
 size_t nof_plan_ws(nof_plan plan) { return plan_ok(plan) ? plan->total : 0; }
+
+int nof_plan_layout(nof_plan plan, size_t* offsets, size_t* bytes, int max_regions) {
+  if (!plan_ok(plan)) return NOF_E_NULL;
+  if (max_regions < 0) return NOF_E_ARG;
+  const int n = nof::O_N < max_regions ? nof::O_N : max_regions;
+  for (int i = 0; i < n; ++i) {
+    if (offsets) offsets[i] = plan->off[i];
+    if (bytes) bytes[i] = plan->bytes[i];
+  }
+  return nof::O_N;
+}
 
 int nof_plan_get_config(nof_plan plan, int* cfg) {
   if (!plan_ok(plan) || !cfg) return NOF_E_NULL;

@@ -69,6 +69,7 @@ _sig("nof_functional_coeffs", _i, _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, 
 _PLAN_ARGS = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _sig("nof_plan_create", _i, ctypes.POINTER(_vp), _i, _i, _i, _i, _i)
 _sig("nof_plan_ws", _sz, _vp)
+_sig("nof_plan_layout", _i, _vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz), _i)
 _sig("nof_plan_get_config", _i, _vp, ctypes.POINTER(_i))
 _sig("nof_plan_set_config", _i, _vp, ctypes.POINTER(_i))
 _sig("nof_plan_iteration", _i, *_PLAN_ARGS)
@@ -124,7 +125,7 @@ DECLARED = [
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_orthonormalize_ws", "nof_orthonormalize",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize", "nof_occ_optimize_noalloc",
-    "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_get_config",
+    "nof_functional_coeffs", "nof_plan_create", "nof_plan_ws", "nof_plan_layout", "nof_plan_get_config",
     "nof_plan_set_config", "nof_plan_iteration", "nof_plan_autotune", "nof_plan_capture",
     "nof_plan_launch", "nof_plan_destroy", "nof_mlp_nparams", "nof_mlp_ws", "nof_mlp_features_ws",
     "nof_solve_ws", "nof_solve", "nof_pseudo_fock_diag_ws", "nof_pseudo_fock_diag", "nof_plan_solve_ws", "nof_plan_solve", "nof_dipole_ws", "nof_dipole", "nof_nlop_romberg",

@@ -207,3 +207,61 @@ def test_orthonormalize_validation():
     assert L.nof_orthonormalize(40, 30, FAKE, None, -1.0, None, FAKE, need, None) == nof.E_ARG
     assert L.nof_orthonormalize(40, 30, FAKE, None, float("nan"), None, FAKE, need, None) == nof.E_ARG
     assert L.nof_orthonormalize(40, 30, FAKE, None, 1e-10, None, FAKE, need - 1, None) == nof.E_WORKSPACE
+
+
+# ---- host-side bounds check of the batched plans' workspace layouts ----
+PLAN_REGIONS = ["Call", "T", "b", "D", "TH", "h", "J", "K", "W", "Kpart", "F1part", "F2part", "F1", "F2",
+                "Epart", "Cplanes", "Tcolmax", "Texp", "cKT"]
+
+
+@pytest.mark.parametrize("ninst,naux,nbf,norb", [(25, 1200, 300, 300), (3, 7, 33, 17), (1, 1, 1, 1),
+                                                 (4, 40, 130, 97), (2, 300, 1100, 150)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "x10"])
+def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
+    """Every region of every plan layout (field300 x10 included) is 256-byte
+    aligned, disjoint from the others, ends inside nof_plan_ws, and is at least
+    as large as what the iteration writes there (computed here from the
+    documented layout), also for the largest exchange split the tuner may set."""
+    import ctypes
+    nof = _lib()
+    L = nof.lib
+    p = {"f64": nof.P_F64, "f32": nof.P_F32, "x10": nof.P_BF16X10}[prec]
+    plan = ctypes.c_void_p()
+    assert L.nof_plan_create(ctypes.byref(plan), ninst, naux, nbf, norb, p) == 0
+    try:
+        total = L.nof_plan_ws(plan)
+        off = (ctypes.c_size_t * 32)()
+        size = (ctypes.c_size_t * 32)()
+        n = L.nof_plan_layout(plan, off, size, 32)
+        assert n == len(PLAN_REGIONS)
+        regions = [(PLAN_REGIONS[i], off[i], size[i]) for i in range(n)]
+        for name, o, sz in regions:
+            assert o % 256 == 0, name
+            assert o + sz <= total, (name, o, sz, total)
+        spans = sorted((o, o + sz, name) for name, o, sz in regions if sz > 0)
+        for (a0, a1, na), (b0, b1, nb) in zip(spans, spans[1:]):
+            assert a1 <= b0, (na, nb)
+        # the largest exchange-term split the tuner may set (host-only calls)
+        cfg = (ctypes.c_int * 4)()
+        assert L.nof_plan_get_config(plan, cfg) == 0
+        gmax = 1
+        while True:
+            cfg[3] = gmax + 1
+            if L.nof_plan_set_config(plan, cfg) != 0:
+                break
+            gmax += 1
+        es = 8 if prec == "f64" else 4
+        n2 = norb * norb * 8
+        ldc = ninst * norb
+        need = {"Call": nbf * ldc * 8, "T": naux * nbf * ldc * es, "b": ninst * naux * norb * norb * es,
+                "D": ninst * naux * norb * 8, "TH": ninst * nbf * norb * 8, "h": ninst * n2, "J": ninst * n2,
+                "K": ninst * n2, "W": ninst * naux * norb * 8, "Kpart": ninst * n2, "F1part": ninst * n2,
+                "F2part": ninst * gmax * n2, "F1": ninst * n2, "F2": ninst * n2, "Epart": ninst * 8}
+        if prec == "x10":
+            ldk = (nbf + 31) // 32 * 32
+            need.update({"Cplanes": 4 * ldc * ldk * 2, "Tcolmax": naux * ((nbf + 127) // 128) * ldc * 4,
+                         "Texp": naux * ldc * 4, "cKT": ninst * norb * norb * 4})
+        for name, o, sz in regions:
+            assert sz >= need.get(name, 0), (name, sz, need.get(name))
+    finally:
+        L.nof_plan_destroy(plan)
