@@ -53,7 +53,8 @@ def test_pseudo_fock_diag_matches_oracle(m, seed, given_diag):
     assert normwise(host(V), V_ref) <= tolV
     assert normwise(host(e), e_ref) <= 1e-12
     Vh = host(V)
-    assert np.max(np.abs(Vh.T @ Vh - np.eye(m))) <= 1e-13
+    # accumulated rotations keep V orthogonal to a few m eps
+    assert np.max(np.abs(Vh.T @ Vh - np.eye(m))) <= 4 * m * 2.2e-16 + 1e-15
 
 
 def test_symmetric_lambda_is_a_fixed_point():
