@@ -28,7 +28,7 @@ import time
 
 import numpy as np
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s (MI355X datasheet)
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "i8": 5000.0}   # dense MFMA TFLOP/s / TOP/s (MI355X datasheet)
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
@@ -42,9 +42,9 @@ def algorithmic_flops(nbf, naux, norb):
     return dict(a1=a1, a2=a2, a6=a6, small=small, total=a1 + a2 + a6 + small, dense=dense)
 
 
-def kf_bytes(naux, norb, esz):
-    """Algorithmic bytes of the K + Coulomb-type pass: the upper half of b and W."""
-    return esz * naux * norb * (norb + 1) / 2 + 8.0 * naux * norb
+def k_bytes(naux, norb, esz):
+    """Algorithmic bytes of the K pass: the upper half of b."""
+    return esz * naux * norb * (norb + 1) / 2
 
 
 def parse():
@@ -56,8 +56,8 @@ def parse():
     ap.add_argument("--forms", default="bf16x10,bf16x10f32,f32,bf16B",
                     help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16x10 (B split "
                          "once into fixed-point planes from FP64), bf16x10f32 (FP32 B split in the "
-                         "loader), bf16B (B stored in BF16; also compared with FP64 on the "
-                         "BF16-rounded B)")
+                         "loader), i8x10 (B split once into INT8 fixed-point planes from FP64), "
+                         "bf16B (B stored in BF16; also compared with FP64 on the BF16-rounded B)")
     ap.add_argument("--cpu-slabs", type=int, default=800,
                     help="auxiliary slabs in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--batched", type=int, default=1,
@@ -160,7 +160,7 @@ def main():
 
     PRECS = {"f64": nof.P_F64, "f32": nof.P_F32, "bf16x1": nof.P_BF16X1, "bf16x3": nof.P_BF16X3,
              "bf16x6": nof.P_BF16X6, "bf16x10": nof.P_BF16X10, "bf16x10f32": nof.P_BF16X10,
-             "bf16B": nof.P_BF16X6}
+             "bf16B": nof.P_BF16X6, "i8x10": nof.P_I8X10}
 
     def run(B, prec_name, steps, warmup):
         dt = torch.float64 if prec_name == "f64" else torch.float32
@@ -170,9 +170,16 @@ def main():
         # x10: both stages in one nof_mo_transform call (the first stage's
         # epilogue gives the second its column grids); the others call the
         # stages separately, so that each is timed on its own
-        fused = prec == nof.P_BF16X10
+        fused = prec in (nof.P_BF16X10, nof.P_I8X10)
+        # F64, F32 and the element-wise split forms fold the Coulomb-type term
+        # into the exchange-type product (the pass over b forms K alone); the
+        # x10 exchange-type product does not take it, so there the pass forms
+        # K and the Coulomb-type term together
+        folded = not fused
         names = (["rotate"] + (["a1_a2_transform"] if fused else ["a1_transform_stage1", "a2_transform_stage2"])
-                 + ["h_and_J", "a4_a5_coulomb_pass", "a6_exchange", "a7_lambda_grad", "a8_energy"])
+                 + ["h_and_J"]
+                 + (["a4_k_pass", "a5_a6_fock_terms"] if folded else ["a4_a5_coulomb_pass", "a6_exchange"])
+                 + ["a7_lambda_grad", "a8_energy"])
         if fused:
             T = None
             ws_t = nof.workspace(nof.lib.nof_mo_transform_ws(naux, nbf, norb, nof._b_arg(B)[0], nof._TDT[dt], prec),
@@ -181,11 +188,14 @@ def main():
             T = torch.empty((naux, nbf, norb), dtype=dt, device=dev)
         b = torch.empty((naux, norb, norb), dtype=dt, device=dev)
         D = torch.empty((naux, norb), dtype=torch.float64, device=dev)
-        lam, g, K, J, F1, F2 = (torch.empty_like(Z) for _ in range(6))
+        lam, g, K, J, F, F1 = (torch.empty_like(Z) for _ in range(6))
         E = torch.empty((), dtype=torch.float64, device=dev)
         rot = nof.Rotation(norb, nbf, dev)
-        ws_c = nof.workspace(nof.lib.nof_coulomb_fock_ws(naux, norb, nof._TDT[dt]), dev)
-        ws_x = nof.workspace(nof.lib.nof_exchange_fock_ws(naux, norb, nof._TDT[dt], prec), dev)
+        if folded:
+            ws_f = nof.workspace(nof.lib.nof_fock_terms_ws(naux, norb, nof._TDT[dt], prec), dev)
+        else:
+            ws_c = nof.workspace(nof.lib.nof_coulomb_fock_ws(naux, norb, nof._TDT[dt]), dev)
+            ws_x = nof.workspace(nof.lib.nof_exchange_fock_ws(naux, norb, nof._TDT[dt], prec), dev)
         ws_j = nof.workspace(nof.lib.nof_jk_diag_ws(naux, norb, nof._TDT[dt]), dev)
         ws_e = nof.workspace(nof.lib.nof_energy_ws(norb), dev)
         Es = []
@@ -214,11 +224,18 @@ def main():
             h = nof.one_electron(H, C)
             nof.jk_diag(b, D, want_J=True, want_K=False, J=J, ws=ws_j)   # A3
             tick()
-            nof.coulomb_fock(b, D, cJ, F1=F1, K=K, ws=ws_c)          # A4 + A5
-            tick()
-            nof.exchange_fock(b, cK, prec=prec, F2=F2, ws=ws_x)      # A6
-            tick()
-            nof.lambda_grad(n, h, F1, F2, lam=lam, g=g)              # A7
+            if folded:
+                nof.jk_diag(b, D, want_J=False, want_K=True, K=K, ws=ws_j)   # A4
+                tick()
+                nof.fock_terms(b, D, cJ, cK, prec=prec, F=F, ws=ws_f)    # A5 + A6: F2 - F1
+                tick()
+                nof.lambda_grad(n, h, None, F, lam=lam, g=g)             # A7
+            else:
+                nof.coulomb_fock(b, D, cJ, F1=F1, K=K, ws=ws_c)          # A4 + A5
+                tick()
+                nof.exchange_fock(b, cK, prec=prec, F2=F, ws=ws_x)       # A6
+                tick()
+                nof.lambda_grad(n, h, F1, F, lam=lam, g=g)               # A7
             tick()
             nof.energy(n, h, J, K, cJ, cK, E=E, ws=ws_e)             # A8
             tick()
@@ -252,12 +269,14 @@ def main():
     seg64 = dict(zip(r64["seg_names"], r64["seg_ms"]))
     ms = r64["ms_per_step"]
     value = flops["total"] / (ms * 1e-3) / 1e12
-    a1_ms, a2_ms, a6_ms = seg64["a1_transform_stage1"], seg64["a2_transform_stage2"], seg64["a6_exchange"]
-    kf_ms = seg64["a4_a5_coulomb_pass"]
-    # dominant kernel of the FP64 step: transform stage 1 or the exchange-type Fock term
+    a1_ms, a2_ms, a6_ms = seg64["a1_transform_stage1"], seg64["a2_transform_stage2"], seg64["a5_a6_fock_terms"]
+    kf_ms = seg64["a4_k_pass"]
+    # dominant kernel of the FP64 step: transform stage 1 or the Fock-term contraction
     if a6_ms > a1_ms:
-        dom = dict(key="k_exchange_fock", name="exchange-type Fock term F2 (sum_P b^P (cK o b^P)), FP64 MFMA",
-                   ms=a6_ms, flops=flops["a6"], bytes=8.0 * (naux * norb * norb + norb * norb))
+        dom = dict(key="k_exchange_fock", name="Fock terms F2 - F1 in one contraction (sum_P b^P (cK o b^P "
+                   "- diag W_P)), FP64 MFMA; the segment includes the W = D cJ product and the reduction",
+                   ms=a6_ms, flops=flops["a6"],
+                   bytes=8.0 * (naux * norb * norb + norb * norb + naux * norb))
     else:
         dom = dict(key="k_transform_stage1", name="transform stage 1 (T^P = B^P C), FP64 MFMA",
                    ms=a1_ms, flops=flops["a1"], bytes=8.0 * (naux * nbf * nbf + naux * nbf * norb + nbf * norb))
@@ -271,6 +290,8 @@ def main():
             Bf = B64.to(torch.bfloat16)
         elif f == "bf16x10":
             Bf = nof.SplitB(B64)          # fixed-point planes of the FP64 B, split once
+        elif f == "i8x10":
+            Bf = nof.SplitBI8(B64)        # INT8 fixed-point planes of the FP64 B, split once
         else:
             if B32 is None:
                 B32 = B64.to(torch.float32)
@@ -290,12 +311,13 @@ def main():
             forms[f]["vs_fp64_on_bf16_rounded_B"] = errors(r, rr)
             Bf = None
         if "a1_a2_transform" in r["seg_names"]:
-            # the fused x10 transform as BF16 matrix-core work: ten products of
-            # pieces per algorithmic flop of either stage
+            # the fused fixed-point transform as matrix-core work: ten products
+            # of pieces per algorithmic operation of either stage (BF16 or INT8)
             t = r["seg_ms"][r["seg_names"].index("a1_a2_transform")]
+            unit = "i8" if f == "i8x10" else "bf16"
             tf = 10.0 * (flops["a1"] + flops["a2"]) / (t * 1e-3) / 1e12
-            forms[f]["transform_matrix_core"] = dict(products_per_flop=10, tflops_bf16=tf,
-                                                     peak=PEAK["bf16"], frac=tf / PEAK["bf16"])
+            forms[f]["transform_matrix_core"] = dict(products_per_flop=10, unit=unit, tops=tf,
+                                                     peak=PEAK[unit], frac=tf / PEAK[unit])
         del Bf
         torch.cuda.empty_cache()
     del B32
@@ -322,7 +344,7 @@ def main():
     batched = run_batched(nof, inputs, dev) if args.batched else None
     warm = run_warmstart(nof, args.warmstart) if args.warmstart > 0 else None
 
-    kfb = kf_bytes(naux, norb, 8.0)
+    kfb = k_bytes(naux, norb, 8.0)
     line = {
         "metric": "JK+gen-Fock build ms/iter and TFLOP/s; BF16 vs FP64 on one GPU at |dE|<=1e-6 Eh",
         "value": value,
@@ -346,9 +368,9 @@ def main():
         "algorithmic_flops_per_step": flops["total"],
         "tflops_dense_equivalent": flops["dense"] / (ms * 1e-3) / 1e12,
         "stage_ms": seg64,
-        "k_pass": {"what": "W = D cJ, then K and the Coulomb-type term F1 in one pass over the upper "
-                           "half of b, and the fixed-order reductions of their partials (the "
-                           "a4_a5_coulomb_pass segment of the step)",
+        "k_pass": {"what": "K in one pass over the upper half of b and the fixed-order reduction of "
+                           "its partials (the a4_k_pass segment of the step; the Coulomb-type Fock "
+                           "term rides in the Fock-term contraction)",
                    "ms": kf_ms, "bytes": kfb, "gbs": kfb / (kf_ms * 1e-3) / 1e9,
                    "frac_of_8tbs": kfb / (kf_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {"bound": "mfma", "kernel": dom["name"],

@@ -58,8 +58,10 @@ typedef enum {
 
 /* Storage type of a large tensor argument (B, b).
  *   NOF_BF16X4  B as the four fixed-point BF16 planes written by nof_split_B
- *               (NOF_P_BF16X10 only). */
-typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3 } nof_dtype;
+ *               (NOF_P_BF16X10 only).
+ *   NOF_I8X4    B as the four fixed-point INT8 planes and row exponents
+ *               written by nof_split_B_i8 (NOF_P_I8X10 only). */
+typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3, NOF_I8X4 = 4 } nof_dtype;
 
 /* Arithmetic used by the matrix-core (MFMA) contractions.
  *   NOF_P_F64     FP64 MFMA, FP64 accumulation.
@@ -81,10 +83,20 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3 } nof_dtyp
  *                 Orders 1..3 share a second FP32 accumulator.  T and b are
  *                 stored in FP32.  The exchange-type Fock term uses three
  *                 element-wise pieces (six products) instead.
+ *   NOF_P_I8X10   the fixed-point split with INT8 pieces on the INT8 matrix
+ *                 cores (transform only; nof_mo_transform with B from
+ *                 nof_split_B_i8): one grid per row / column, 2^E the
+ *                 smallest power of two with max|x| 2^(7-E) < 127.5,
+ *                 x = n_0 2^(E-7) + sum_{q=1..3} n_q 2^(E-7-7q) + r,
+ *                 |n_0| <= 127, |n_q| <= 64, |r| <= 2^(E-29); the ten
+ *                 products of order <= 3 in four int32 accumulators (one per
+ *                 order; exact for contractions shorter than 65536), combined
+ *                 exactly in FP64.  T and b stored in FP32; the exchange-type
+ *                 term as in NOF_P_BF16X10.
  * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
 typedef enum {
   NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4,
-  NOF_P_BF16X10 = 5
+  NOF_P_BF16X10 = 5, NOF_P_I8X10 = 6
 } nof_prec;
 
 /* Human-readable text for a status code (static storage, never NULL). */
@@ -105,6 +117,22 @@ const char* nof_status_str(int status);
  * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_DTYPE (Bt not F64/F32),
  *         NOF_E_WORKSPACE (planes_bytes too small), NOF_E_HIP.
  * ------------------------------------------------------------------------- */
+/* ---------------------------------------------------------------------------
+ * The same once-per-B split with INT8 pieces for NOF_P_I8X10: row (P, mu)
+ * of B^P gets the grid exponent E of NOF_P_I8X10 above and four INT8 pieces.
+ * B       [naux][nbf][nbf] FP64 or FP32 (Bt), symmetric, device.
+ * out     at least nof_split_B_i8_bytes(naux, nbf) bytes, device (caller
+ *         owned): planes [4][naux][nbf][ldk] (int8, ldk = nbf rounded up to
+ *         a multiple of 64, zero for nu >= nbf), then at the next 256-byte
+ *         boundary the exponents [naux][nbf] (int32).  Pass it as B with
+ *         Bt = NOF_I8X4 to nof_mo_transform.
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_DTYPE (Bt not F64/F32),
+ *         NOF_E_WORKSPACE (out_bytes too small), NOF_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t nof_split_B_i8_bytes(int naux, int nbf);
+int nof_split_B_i8(int naux, int nbf, const void* B, int Bt, void* out, size_t out_bytes,
+                   hipStream_t stream);
+
 size_t nof_split_B_bytes(int naux, int nbf);
 int nof_split_B(int naux, int nbf, const void* B, int Bt, void* planes, size_t planes_bytes,
                 hipStream_t stream);
@@ -129,10 +157,14 @@ int nof_split_B(int naux, int nbf, const void* B, int Bt, void* planes, size_t p
  *                          (B not at all when given as NOF_BF16X4 planes),
  *                          C once per call (three pieces for a BF16-stored B,
  *                          four with X10).
+ *     NOF_P_I8X10          Bt = NOF_I8X4 (nof_split_B_i8), bt = NOF_F32; C
+ *                          split once per call, B^P C split by a pass (one
+ *                          grid per column of each B^P C) between the stages.
  * ws  workspace of at least nof_mo_transform_ws(...) bytes (holds B^P C and
  *     the BF16 pieces of C; with X10 also the column maxima of B^P C that the
  *     first stage writes as it stores them, which give the second stage the
- *     grids of its split without another pass over B^P C).
+ *     grids of its split without another pass over B^P C; with I8X10 the
+ *     INT8 planes of C, those maxima and the INT8 planes of B^P C).
  *
  * With naux = 1 and B = H (the AO one-electron matrix) this yields
  * h = C^T H C, the one-electron integrals of Eq. (Energy) in the NO basis.
@@ -144,7 +176,9 @@ int nof_mo_transform(int naux, int nbf, int norb,
                      int prec, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* The two stages of nof_mo_transform as separate calls (same arguments and
- * rules), for callers that keep the half-transformed tensor or time the stages:
+ * rules; not for NOF_P_I8X10, whose second stage takes the first stage's
+ * column maxima: NOF_E_PREC), for callers that keep the half-transformed
+ * tensor or time the stages:
  *   stage 1:  T[P][mu][q] = (B^P C)_{mu q}        T: [naux][nbf][norb], storage Tt
  *   stage 2:  b^P = C^T T^P, D[P][p] = b^P_pp     (exactly symmetric b)
  * Tt is the storage of b for the precision mode.  ws (at least
@@ -191,11 +225,14 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  * cJ, cK  [norb][norb] FP64, must be symmetric (Eq. PNOF coefficients).
  * lambda  out [norb][norb] FP64.          grad  out, may be NULL.
  * K_opt   if not NULL, also receives K (same definition as nof_jk_diag),
- *         formed in the same pass over b as the Coulomb-type term.
+ *         from one pass over the upper half of b.
  * prec    NOF_P_F64 (bt = NOF_F64), NOF_P_F32 or a split form (bt = NOF_F32)
- *         for the exchange-type contraction (X10: three element-wise BF16
- *         pieces, FP32 accumulation within a slab); the pass over b
- *         accumulates in FP64.
+ *         for the matrix-core contraction (X10: three element-wise BF16
+ *         pieces, FP32 accumulation within a slab, FP64 across slabs).
+ * The two sums over P are one contraction (nof_fock_terms): the Coulomb-type
+ * sum is the exchange-type one with cK_sq b^P_qs replaced by -W[P][s] on
+ * q = s, so it is applied to the right operand as it is staged, at no cost
+ * beyond the exchange-type product.
  * ------------------------------------------------------------------------- */
 size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec);
 int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D,
@@ -203,6 +240,22 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D,
                  const double* cJ, const double* cK,
                  double* lambda, double* grad, double* K_opt,
                  int prec, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Both Fock terms of lambda (NO Optimization) in one matrix-core contraction,
+ * as nof_gen_fock computes them:
+ *   W = D cJ,
+ *   F_rs = F2_rs - F1_rs = sum_P sum_q b^P_rq (cK_sq b^P_qs - [q = s] W[P][s])
+ * so that lambda_rs = n_s h_rs - F_rs (nof_lambda_grad with F1 = NULL).
+ * b, bt, D, cJ, cK, prec as in nof_gen_fock.  F out [norb][norb] FP64 (not
+ * symmetric).  ws: at least nof_fock_terms_ws(naux, norb, bt, prec) bytes.
+ * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_DTYPE, NOF_E_PREC, NOF_E_WORKSPACE,
+ * NOF_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t nof_fock_terms_ws(int naux, int norb, int bt, int prec);
+int nof_fock_terms(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
+                   const double* cK, double* F, int prec, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * The exchange-type term of the generalized Fock build alone (the last sum
@@ -218,7 +271,8 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
 /* ---------------------------------------------------------------------------
  * The Coulomb-type term of the generalized Fock build alone (the middle sum
  * of lambda above, NO Optimization), with K from the same pass over the
- * upper half of b, as nof_gen_fock computes them:
+ * upper half of b (an HBM-bound pass; nof_gen_fock folds this term into the
+ * exchange-type contraction instead):
  *   W = D cJ,   F1_rs = sum_P b^P_rs W[P][s],   K_pq = sum_P (b^P_pq)^2
  * b, bt, D, cJ as in nof_gen_fock.  F1 out [norb][norb] FP64 (not symmetric);
  * K_opt out [norb][norb] FP64 or NULL.  FP64 accumulation in a fixed order.
@@ -233,7 +287,8 @@ int nof_coulomb_fock(int naux, int norb, const void* b, int bt, const double* D,
  * Lagrange multipliers and orbital gradient from the two Fock terms (NO
  * Optimization): lambda_rs = n_s h_rs + F1_rs - F2_rs, grad = 4(lambda -
  * lambda^T), as nof_gen_fock forms them.  n [norb], h, F1, F2 [norb][norb]
- * FP64 device; lambda out [norb][norb]; grad out or NULL.  No workspace.
+ * FP64 device; F1 may be NULL, then F2 is the combined F2 - F1 of
+ * nof_fock_terms; lambda out [norb][norb]; grad out or NULL.  No workspace.
  * Errors: NOF_E_DIM, NOF_E_NULL, NOF_E_HIP.
  * ------------------------------------------------------------------------- */
 int nof_lambda_grad(int norb, const double* n, const double* h, const double* F1, const double* F2,

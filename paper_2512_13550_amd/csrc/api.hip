@@ -14,6 +14,11 @@ constexpr int kMaxDim = 1 << 20;
 
 bool dim_ok(int x) { return x >= 1 && x <= kMaxDim; }
 
+// The fixed-point forms (BF16 or INT8 pieces): b in FP32, the exchange-type
+// term in three element-wise BF16 pieces, the Coulomb-type term from the pass.
+bool fixed_point(int prec) { return prec == NOF_P_BF16X10 || prec == NOF_P_I8X10; }
+
+
 // Workspace of nof_jk_diag: J split partials, K chunk partials.
 struct JkLayout {
   int jsplit, jk, kchunks;
@@ -36,12 +41,15 @@ JkLayout jk_layout(int naux, int norb, int bt) {
   return L;
 }
 
-// Workspace of nof_gen_fock: W, F1/K chunk partials, F2 partials, F1, F2.
+// Workspace of nof_gen_fock and nof_fock_terms: W, the partials of the
+// Fock-term product and their sum F, the FP32 cK^T of the x10 form, and (x10,
+// whose exchange-type product does not take the Coulomb-type term) the F1
+// chunk partials and F1; then (nof_gen_fock) the K chunk partials.
 struct FockLayout {
   int kchunks, f2fold, f2groups;
-  size_t off_W, off_f1part, off_kpart, off_f2part, off_F1, off_F2, off_St, total;
+  size_t off_W, off_f2part, off_F, off_St, off_f1part, off_F1, terms, off_kpart, total;
 };
-FockLayout fock_layout(int naux, int norb, int bt) {
+FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   FockLayout L;
   L.kchunks = kf1_parts(naux, norb, 1, bt);
   const int tn = (norb + 127) / 128;
@@ -52,30 +60,51 @@ FockLayout fock_layout(int naux, int norb, int bt) {
   L.f2fold = (naux + groups - 1) / groups;
   L.f2groups = (naux + L.f2fold - 1) / L.f2fold;
   const size_t n2 = (size_t)norb * norb * sizeof(double);
+  const bool fx = fixed_point(prec);
+  L.off_W = 0;
+  L.off_f2part = align256((size_t)naux * norb * sizeof(double));
+  L.off_F = align256(L.off_f2part + (size_t)L.f2groups * n2);
+  L.off_St = align256(L.off_F + n2);
+  L.off_f1part = align256(L.off_St + (size_t)norb * norb * sizeof(float));
+  L.off_F1 = align256(L.off_f1part + (fx ? (size_t)L.kchunks * n2 : 0));
+  L.terms = align256(L.off_F1 + (fx ? n2 : 0));
+  L.off_kpart = L.terms;
+  L.total = align256(L.off_kpart + (size_t)L.kchunks * n2);
+  return L;
+}
+
+// Workspace of nof_coulomb_fock: W, the F1 and K chunk partials.
+struct CoulombLayout {
+  int kchunks;
+  size_t off_W, off_f1part, off_kpart, total;
+};
+CoulombLayout coulomb_layout(int naux, int norb, int bt) {
+  CoulombLayout L;
+  L.kchunks = kf1_parts(naux, norb, 1, bt);
+  const size_t n2 = (size_t)norb * norb * sizeof(double);
   L.off_W = 0;
   L.off_f1part = align256((size_t)naux * norb * sizeof(double));
   L.off_kpart = align256(L.off_f1part + (size_t)L.kchunks * n2);
-  L.off_f2part = align256(L.off_kpart + (size_t)L.kchunks * n2);
-  L.off_F1 = align256(L.off_f2part + (size_t)L.f2groups * n2);
-  L.off_F2 = align256(L.off_F1 + n2);
-  L.off_St = align256(L.off_F2 + n2);
-  L.total = align256(L.off_St + (size_t)norb * norb * sizeof(float));
+  L.total = align256(L.off_kpart + (size_t)L.kchunks * n2);
   return L;
 }
 
 bool prec_ok(int prec) {
-  return prec == NOF_P_F64 || prec == NOF_P_F32 || is_bf16_prec(prec);
+  return prec == NOF_P_F64 || prec == NOF_P_F32 || is_bf16_prec(prec) || prec == NOF_P_I8X10;
 }
 
 // Storage of b (and of the half-transformed T) for a precision mode.
 bool prec_matches(int prec, int t) {
   return (prec == NOF_P_F64 && t == NOF_F64) || (prec == NOF_P_F32 && t == NOF_F32) ||
-         (is_bf16_prec(prec) && t == NOF_F32);
+         ((is_bf16_prec(prec) || prec == NOF_P_I8X10) && t == NOF_F32);
 }
 
-// Storage of B for a precision mode: as b, or BF16 for the 3-piece split forms.
+// Storage of B for a precision mode: as b, BF16 for the 3-piece split forms,
+// fixed-point planes for the two fixed-point forms (the INT8 one only so).
 bool b_input_ok(int prec, int Bt) {
   if (Bt == NOF_BF16X4) return prec == NOF_P_BF16X10;
+  if (Bt == NOF_I8X4) return prec == NOF_P_I8X10;
+  if (prec == NOF_P_I8X10) return false;
   if (prec_matches(prec, Bt)) return true;
   return Bt == NOF_BF16 && (prec == NOF_P_BF16X3 || prec == NOF_P_BF16X6);
 }
@@ -197,12 +226,68 @@ size_t fx_cmax_bytes(int naux, int nbf, int norb) {
   return align256((size_t)naux * fx_tiles(nbf) * norb * sizeof(unsigned));
 }
 
+// INT8 fixed-point transform.  B as written by nof_split_B_i8: planes
+// [4][naux*nbf][ldk] and, after them, one grid exponent per row (P, mu).
+size_t i8_planes_bytes(long long rows, int K) { return align256((size_t)4 * rows * i8_ldk(K)); }
+
+// Scratch after T: C planes and exponents, the stage-1 column maxima of T,
+// the grid exponents of T's columns and T's planes.
+struct I8Layout {
+  size_t off_Ce, off_cmax, off_Te, off_Tp, total;
+};
+I8Layout i8_layout(int naux, int nbf, int norb) {
+  I8Layout L;
+  L.off_Ce = i8_planes_bytes(norb, nbf);
+  L.off_cmax = L.off_Ce + align256((size_t)norb * sizeof(int));
+  L.off_Te = L.off_cmax + fx_cmax_bytes(naux, nbf, norb);
+  L.off_Tp = L.off_Te + align256((size_t)naux * norb * sizeof(int));
+  L.total = L.off_Tp + i8_planes_bytes((long long)naux * norb, nbf);
+  return L;
+}
+
+// b^P = C^T B^P C on the INT8 matrix cores: C split per column; stage 1
+// T^P = B^P C (its epilogue gives the column maxima of T); T split per
+// column of each T^P on those grids; stage 2 b^P = C^T T^P with D.
+int i8_transform(int naux, int nbf, int norb, const void* B, const double* C, float* T, float* b,
+                 double* D, char* w, hipStream_t stream) {
+  const I8Layout L = i8_layout(naux, nbf, norb);
+  const long long ldk = i8_ldk(nbf);
+  const unsigned char* Bp = (const unsigned char*)B;
+  const int* Be = (const int*)(Bp + i8_planes_bytes((long long)naux * nbf, nbf));
+  unsigned char* Cp = (unsigned char*)w;
+  int* Ce = (int*)(w + L.off_Ce);
+  unsigned* cmax = (unsigned*)(w + L.off_cmax);
+  int* Te = (int*)(w + L.off_Te);
+  unsigned char* Tp = (unsigned char*)(w + L.off_Tp);
+  NOF_TRY(i8_split_cols(C, nbf, norb, norb, (int)ldk, Cp, Ce, stream));
+  I8Desc f{};
+  f.M = nbf; f.N = norb; f.K = nbf; f.batch = naux;
+  f.X = Bp; f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
+  f.ex = Be; f.sex = nbf;
+  f.Y = Cp; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk; f.ey = Ce; f.sey = 0;
+  f.Out = T; f.ldo = norb; f.so = (long long)nbf * norb;
+  f.sym = false; f.role = 1;
+  f.cmax = cmax; f.scm = (long long)fx_tiles(nbf) * norb;
+  NOF_TRY(gemm_i8(f, stream));
+  NOF_TRY(i8_cmax_exps(cmax, naux, fx_tiles(nbf), norb, Te, stream));
+  NOF_TRY(i8_split_T(T, naux, nbf, norb, (long long)nbf * norb, (int)ldk, Te, Tp, stream));
+  I8Desc g{};
+  g.M = norb; g.N = norb; g.K = nbf; g.batch = naux;
+  g.X = Cp; g.ldx = ldk; g.sx = 0; g.psx = (long long)norb * ldk; g.ex = Ce; g.sex = 0;
+  g.Y = Tp; g.ldy = ldk; g.sy = (long long)norb * ldk; g.psy = (long long)naux * norb * ldk;
+  g.ey = Te; g.sey = norb;
+  g.Out = b; g.ldo = norb; g.so = (long long)norb * norb;
+  g.Dg = D; g.sd = norb; g.sym = true; g.role = 2;
+  return gemm_i8(g, stream);
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t nof_mo_transform_stage_ws(int naux, int nbf, int norb, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb) || !prec_ok(prec)) return 0;
+  if (prec == NOF_P_I8X10) return 0;             // nof_mo_transform only
   // B may be given in FP32 or BF16: size for the larger of the two splits of C
   return std::max(stage_ws(naux, nbf, norb, prec, NOF_F32), stage_ws(naux, nbf, norb, prec, NOF_BF16));
 }
@@ -210,8 +295,29 @@ size_t nof_mo_transform_stage_ws(int naux, int nbf, int norb, int prec) {
 size_t nof_mo_transform_ws(int naux, int nbf, int norb, int Bt, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt) || !b_input_ok(prec, Bt)) return 0;
+  if (prec == NOF_P_I8X10)
+    return align256((size_t)naux * nbf * norb * sizeof(float)) + i8_layout(naux, nbf, norb).total;
   return align256((size_t)naux * nbf * norb * dtype_size(bt)) + stage_ws(naux, nbf, norb, prec, Bt) +
          (prec == NOF_P_BF16X10 ? fx_cmax_bytes(naux, nbf, norb) : 0);
+}
+
+size_t nof_split_B_i8_bytes(int naux, int nbf) {
+  if (!dim_ok(naux) || !dim_ok(nbf)) return 0;
+  const long long rows = (long long)naux * nbf;
+  return i8_planes_bytes(rows, nbf) + align256((size_t)rows * sizeof(int));
+}
+
+int nof_split_B_i8(int naux, int nbf, const void* B, int Bt, void* out, size_t out_bytes,
+                   hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(nbf)) return NOF_E_DIM;
+    if (!B || !out) return NOF_E_NULL;
+    if (Bt != NOF_F64 && Bt != NOF_F32) return NOF_E_DTYPE;
+    if (out_bytes < nof_split_B_i8_bytes(naux, nbf)) return NOF_E_WORKSPACE;
+    const long long rows = (long long)naux * nbf;
+    int* e = (int*)((char*)out + i8_planes_bytes(rows, nbf));
+    return i8_split_rows(B, Bt, rows, nbf, (int)i8_ldk(nbf), out, e, stream);
+  });
 }
 
 size_t nof_split_B_bytes(int naux, int nbf) {
@@ -237,7 +343,7 @@ int nof_mo_transform_stage1(int naux, int nbf, int norb, const void* B, int Bt, 
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!B || !C || !T) return NOF_E_NULL;
     if (dtype_size(Bt) == 0 || dtype_size(Tt) == 0) return NOF_E_DTYPE;
-    if (!prec_ok(prec)) return NOF_E_PREC;
+    if (!prec_ok(prec) || prec == NOF_P_I8X10) return NOF_E_PREC;
     if (!prec_matches(prec, Tt)) return NOF_E_PREC;
     if (!b_input_ok(prec, Bt)) return NOF_E_DTYPE;
     const bool bf = is_bf16_prec(prec);
@@ -270,7 +376,7 @@ int nof_mo_transform_stage2(int naux, int nbf, int norb, const void* T, int Tt, 
     if (!dim_ok(naux) || !dim_ok(nbf) || !dim_ok(norb)) return NOF_E_DIM;
     if (!T || !C || !b) return NOF_E_NULL;
     if (Tt != bt || dtype_size(bt) == 0 || bt == NOF_BF16) return NOF_E_DTYPE;
-    if (!prec_ok(prec)) return NOF_E_PREC;
+    if (!prec_ok(prec) || prec == NOF_P_I8X10) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     const bool bf = is_bf16_prec(prec);
     if (bf && (!ws || ws_bytes < stage_ws(naux, nbf, norb, prec, NOF_F32))) return NOF_E_WORKSPACE;
@@ -307,6 +413,7 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
     if (!ws || ws_bytes < need) return NOF_E_WORKSPACE;
     const size_t tbytes = align256((size_t)naux * nbf * norb * dtype_size(bt));
     char* sws = (char*)ws + tbytes;
+    if (prec == NOF_P_I8X10) return i8_transform(naux, nbf, norb, B, C, (float*)ws, (float*)b, D, sws, stream);
     if (prec == NOF_P_BF16X10) {
       // T, the stage scratch, then the column maxima of T that the stage-1
       // epilogue writes: they give stage 2 its grids without a pass over T
@@ -367,10 +474,12 @@ namespace {
 
 // F2 (exchange-type term) into F2 from the partials in f2part (groups of
 // L.f2fold slabs); St: norb*norb FP32 scratch of the split forms.
-int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, int prec,
-                  const FockLayout& L, double* f2part, float* St, double* F2, hipStream_t stream) {
+int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, const double* W,
+                  int prec, const FockLayout& L, double* f2part, float* St, double* F2,
+                  hipStream_t stream) {
   const long long n2 = (long long)norb * norb;
-  if (prec == NOF_P_BF16X10) {
+  if (fixed_point(prec)) {
+    if (W) return NOF_E_INTERNAL;               // this product takes no W (fock_terms)
     ExDesc e{naux, norb, L.f2fold, (const float*)b, nullptr, f2part};
     NOF_TRY(exchange_fock_fx(e, cK, St, stream));
   } else {
@@ -384,9 +493,48 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, i
     g2.Out = f2part; g2.ldo = norb; g2.so = n2;
     g2.Dg = nullptr; g2.sd = 0; g2.sym = false;
     g2.role = GemmRole::ExchangeFock;
+    g2.W = W; g2.ldw = norb;
     NOF_TRY(gemm_any(g2, bt, bt, NOF_F64, prec, stream));
   }
   return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
+}
+
+// W = D cJ (W[P][s] = sum_q D[P][q] cJ[q][s]), FP64.
+int coulomb_weights(int naux, int norb, const double* D, const double* cJ, double* W,
+                    hipStream_t stream) {
+  GemmDesc gw{};
+  gw.M = naux; gw.N = norb; gw.K = norb; gw.Ktot = 0;
+  gw.batch = 1; gw.fold = 1;
+  gw.X = D; gw.ldx = norb; gw.sx = 0; gw.x_kmajor = false;
+  gw.Y = cJ; gw.ldy = norb; gw.sy = 0;
+  gw.S = nullptr; gw.lds = 0;
+  gw.Out = W; gw.ldo = norb; gw.so = 0;
+  gw.Dg = nullptr; gw.sd = 0; gw.sym = false;
+  return gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream);
+}
+
+// F = F2 - F1 = sum_P sum_q b^P[r][q] (cK[q][s] b^P[q][s] - [q == s] W[P][s]):
+// the Coulomb-type term rides in the exchange-type product's operand loader.
+// The x10 exchange-type product stages element-wise pieces of FP32 values
+// and does not take it: there F1 comes from the pass over the upper half of
+// b (with K when Kpart is given: both from one read of b) and is subtracted.
+int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
+               const double* cK, int prec, const FockLayout& L, char* w, double* F,
+               double* Kpart, double* K, hipStream_t stream) {
+  double* W = (double*)(w + L.off_W);
+  NOF_TRY(coulomb_weights(naux, norb, D, cJ, W, stream));
+  if (!fixed_point(prec))
+    return exchange_term(naux, norb, b, bt, cK, W, prec, L, (double*)(w + L.off_f2part),
+                         (float*)(w + L.off_St), F, stream);
+  const long long n2 = (long long)norb * norb;
+  double* f1part = (double*)(w + L.off_f1part);
+  double* F1 = (double*)(w + L.off_F1);
+  NOF_TRY(kf1_pass(naux, norb, b, bt, W, Kpart, f1part, L.kchunks, stream));
+  NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
+  if (Kpart) NOF_TRY(reduce_parts(Kpart, L.kchunks, n2, norb, true, K, stream));
+  NOF_TRY(exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, (double*)(w + L.off_f2part),
+                        (float*)(w + L.off_St), F, stream));
+  return subtract(n2, F1, F, stream);
 }
 
 }  // namespace
@@ -396,7 +544,7 @@ extern "C" {
 size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
-  const FockLayout L = fock_layout(naux, norb, bt);
+  const FockLayout L = fock_layout(naux, norb, bt, prec);
   return align256((size_t)L.f2groups * norb * norb * sizeof(double)) +
          align256((size_t)norb * norb * sizeof(float));
 }
@@ -410,18 +558,18 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
     if (!ws || ws_bytes < nof_exchange_fock_ws(naux, norb, bt, prec)) return NOF_E_WORKSPACE;
-    const FockLayout L = fock_layout(naux, norb, bt);
+    const FockLayout L = fock_layout(naux, norb, bt, prec);
     char* w = (char*)ws;
     double* part = (double*)w;
     float* St = (float*)(w + align256((size_t)L.f2groups * norb * norb * sizeof(double)));
-    return exchange_term(naux, norb, b, bt, cK, prec, L, part, St, F2, stream);
+    return exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, part, St, F2, stream);
   });
 }
 
 size_t nof_gen_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
-  return fock_layout(naux, norb, bt).total;
+  return fock_layout(naux, norb, bt, prec).total;
 }
 
 int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, const double* n,
@@ -433,41 +581,48 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
     if (!prec_ok(prec)) return NOF_E_PREC;
     if (!prec_matches(prec, bt)) return NOF_E_PREC;
-    const FockLayout L = fock_layout(naux, norb, bt);
+    const FockLayout L = fock_layout(naux, norb, bt, prec);
     if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
     char* w = (char*)ws;
     const long long n2 = (long long)norb * norb;
-    double* W = (double*)(w + L.off_W);
-    double* f1part = (double*)(w + L.off_f1part);
-    double* kpart = (double*)(w + L.off_kpart);
-    double* f2part = (double*)(w + L.off_f2part);
-    double* F1 = (double*)(w + L.off_F1);
-    double* F2 = (double*)(w + L.off_F2);
-    // W[P][s] = sum_q D[P][q] cJ[q][s]
-    GemmDesc gw{};
-    gw.M = naux; gw.N = norb; gw.K = norb; gw.Ktot = 0;
-    gw.batch = 1; gw.fold = 1;
-    gw.X = D; gw.ldx = norb; gw.sx = 0; gw.x_kmajor = false;
-    gw.Y = cJ; gw.ldy = norb; gw.sy = 0;
-    gw.S = nullptr; gw.lds = 0;
-    gw.Out = W; gw.ldo = norb; gw.so = 0;
-    gw.Dg = nullptr; gw.sd = 0; gw.sym = false;
-    NOF_TRY(gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
-    // Coulomb-type term F1 (and K) in one pass over the upper half of b
-    NOF_TRY(kf1_pass(naux, norb, b, bt, W, K_opt ? kpart : nullptr, f1part, L.kchunks, stream));
-    NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
-    if (K_opt) NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K_opt, stream));
-    // Exchange-type term F2
-    NOF_TRY(exchange_term(naux, norb, b, bt, cK, prec, L, f2part, (float*)(w + L.off_St), F2, stream));
-    return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
+    double* F = (double*)(w + L.off_F);
+    double* kpart = K_opt ? (double*)(w + L.off_kpart) : nullptr;
+    const bool fx = fixed_point(prec);           // K then comes with F1 from one pass
+    NOF_TRY(fock_terms(naux, norb, b, bt, D, cJ, cK, prec, L, w, F, fx ? kpart : nullptr, K_opt,
+                       stream));
+    if (K_opt && !fx) {
+      NOF_TRY(kf1_pass(naux, norb, b, bt, nullptr, kpart, nullptr, L.kchunks, stream));
+      NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K_opt, stream));
+    }
+    return lambda_grad(norb, n, h, nullptr, F, lambda, grad, stream);
+  });
+}
+
+size_t nof_fock_terms_ws(int naux, int norb, int bt, int prec) {
+  if (!dim_ok(naux) || !dim_ok(norb)) return 0;
+  if (!prec_matches(prec, bt)) return 0;
+  return fock_layout(naux, norb, bt, prec).terms;
+}
+
+int nof_fock_terms(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
+                   const double* cK, double* F, int prec, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
+    if (!b || !D || !cJ || !cK || !F) return NOF_E_NULL;
+    if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
+    if (!prec_ok(prec)) return NOF_E_PREC;
+    if (!prec_matches(prec, bt)) return NOF_E_PREC;
+    const FockLayout L = fock_layout(naux, norb, bt, prec);
+    if (!ws || ws_bytes < L.terms) return NOF_E_WORKSPACE;
+    return fock_terms(naux, norb, b, bt, D, cJ, cK, prec, L, (char*)ws, F, nullptr, nullptr, stream);
   });
 }
 
 size_t nof_coulomb_fock_ws(int naux, int norb, int bt) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (bt != NOF_F64 && bt != NOF_F32) return 0;
-  const FockLayout L = fock_layout(naux, norb, bt);
-  return L.off_f2part;          // W and the F1 / K chunk partials
+  return coulomb_layout(naux, norb, bt).total;
 }
 
 int nof_coulomb_fock(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
@@ -476,22 +631,14 @@ int nof_coulomb_fock(int naux, int norb, const void* b, int bt, const double* D,
     if (!dim_ok(naux) || !dim_ok(norb)) return NOF_E_DIM;
     if (!b || !D || !cJ || !F1) return NOF_E_NULL;
     if (bt != NOF_F64 && bt != NOF_F32) return NOF_E_DTYPE;
-    const FockLayout L = fock_layout(naux, norb, bt);
-    if (!ws || ws_bytes < L.off_f2part) return NOF_E_WORKSPACE;
+    const CoulombLayout L = coulomb_layout(naux, norb, bt);
+    if (!ws || ws_bytes < L.total) return NOF_E_WORKSPACE;
     char* w = (char*)ws;
     const long long n2 = (long long)norb * norb;
     double* W = (double*)(w + L.off_W);
     double* f1part = (double*)(w + L.off_f1part);
     double* kpart = (double*)(w + L.off_kpart);
-    GemmDesc gw{};
-    gw.M = naux; gw.N = norb; gw.K = norb; gw.Ktot = 0;
-    gw.batch = 1; gw.fold = 1;
-    gw.X = D; gw.ldx = norb; gw.sx = 0; gw.x_kmajor = false;
-    gw.Y = cJ; gw.ldy = norb; gw.sy = 0;
-    gw.S = nullptr; gw.lds = 0;
-    gw.Out = W; gw.ldo = norb; gw.so = 0;
-    gw.Dg = nullptr; gw.sd = 0; gw.sym = false;
-    NOF_TRY(gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
+    NOF_TRY(coulomb_weights(naux, norb, D, cJ, W, stream));
     NOF_TRY(kf1_pass(naux, norb, b, bt, W, K_opt ? kpart : nullptr, f1part, L.kchunks, stream));
     NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
     if (K_opt) NOF_TRY(reduce_parts(kpart, L.kchunks, n2, norb, true, K_opt, stream));
@@ -503,7 +650,7 @@ int nof_lambda_grad(int norb, const double* n, const double* h, const double* F1
                     double* lambda, double* grad, hipStream_t stream) {
   return guarded([&]() -> int {
     if (!dim_ok(norb)) return NOF_E_DIM;
-    if (!n || !h || !F1 || !F2 || !lambda) return NOF_E_NULL;
+    if (!n || !h || !F2 || !lambda) return NOF_E_NULL;    // F1 == NULL: F2 is F2 - F1
     return lambda_grad(norb, n, h, F1, F2, lambda, grad, stream);
   });
 }

@@ -61,9 +61,13 @@ void plan_layout(nof_plan_s* p) {
   sz[O_K] = ni * n2;
   sz[O_W] = ni * na * no * 8;
   sz[O_KP] = ni * p->kchunks * n2;
-  sz[O_F1P] = ni * p->kchunks * n2;
+  // F64 / F32: the Coulomb-type term is folded into the exchange-type
+  // product (O_F2 holds F2 - F1), so its partials and sum take no space; the
+  // x10 exchange-type product does not take it (F1 from the pass with K)
+  const bool fx1 = p->prec == NOF_P_BF16X10;
+  sz[O_F1P] = fx1 ? ni * p->kchunks * n2 : 0;
   sz[O_F2P] = (size_t)f2groups * n2;
-  sz[O_F1] = ni * n2;
+  sz[O_F1] = fx1 ? ni * n2 : 0;
   sz[O_F2] = ni * n2;
   sz[O_EP] = energy_ws((int)ni);
   // x10: planes of the packed C, column maxima of T per row tile, the grid
@@ -205,17 +209,22 @@ int run_small(nof_plan_s* p, const Args& a, hipStream_t st) {
   return gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
 }
 
+// K of every instance in one pass over the upper halves of the b_i; in the
+// x10 form also the Coulomb-type term F1 (same pass).
 int run_pass(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long n2 = (long long)p->norb * p->norb;
+  const bool fx = p->prec == NOF_P_BF16X10;
   double* kp = (double*)(a.ws + p->off[O_KP]);
-  double* f1p = (double*)(a.ws + p->off[O_F1P]);
-  int rc = kf1_pass(p->naux, p->norb, a.ws + p->off[O_B], p->bt, (double*)(a.ws + p->off[O_W]), kp,
-                    f1p, p->kchunks, st, p->ninst, (long long)p->naux * n2,
-                    (long long)p->naux * p->norb, (long long)p->kchunks * n2);
+  double* f1p = fx ? (double*)(a.ws + p->off[O_F1P]) : nullptr;
+  int rc = kf1_pass(p->naux, p->norb, a.ws + p->off[O_B], p->bt,
+                    fx ? (double*)(a.ws + p->off[O_W]) : nullptr, kp, f1p, p->kchunks, st, p->ninst,
+                    (long long)p->naux * n2, (long long)p->naux * p->norb, (long long)p->kchunks * n2);
   if (rc != NOF_OK) return rc;
-  rc = reduce_parts(f1p, p->kchunks, n2, p->norb, false, (double*)(a.ws + p->off[O_F1]), st,
-                    p->ninst, (long long)p->kchunks * n2, n2);
-  if (rc != NOF_OK) return rc;
+  if (fx) {
+    rc = reduce_parts(f1p, p->kchunks, n2, p->norb, false, (double*)(a.ws + p->off[O_F1]), st,
+                      p->ninst, (long long)p->kchunks * n2, n2);
+    if (rc != NOF_OK) return rc;
+  }
   return reduce_parts(kp, p->kchunks, n2, p->norb, true, (double*)(a.ws + p->off[O_K]), st,
                       p->ninst, (long long)p->kchunks * n2, n2);
 }
@@ -248,6 +257,8 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
   g.Out = f2p; g.ldo = p->norb; g.so = n2; g.so2 = (long long)gpi * n2;
   g.role = GemmRole::ExchangeFock;
   g.tile = p->tile_f2;
+  // the Coulomb-type term in the operand loader: the product is F2 - F1
+  g.W = (const double*)(a.ws + p->off[O_W]); g.ldw = p->norb; g.sw2 = (long long)p->naux * p->norb;
   int rc = gemm_tn(g, p->bt, p->bt, NOF_F64, p->prec, st);
   if (rc != NOF_OK) return rc;
   return reduce_parts(f2p, gpi, n2, p->norb, false, (double*)(a.ws + p->off[O_F2]), st, p->ninst,
@@ -257,9 +268,9 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
 int run_tail(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long n2 = (long long)p->norb * p->norb;
   const double* h = (const double*)(a.ws + p->off[O_H]);
-  int rc = lambda_grad(p->norb, a.n, h, (double*)(a.ws + p->off[O_F1]),
-                       (double*)(a.ws + p->off[O_F2]), a.lam, a.grad, st, p->ninst, p->norb, n2,
-                       n2);
+  const double* F1 = p->prec == NOF_P_BF16X10 ? (const double*)(a.ws + p->off[O_F1]) : nullptr;
+  int rc = lambda_grad(p->norb, a.n, h, F1, (double*)(a.ws + p->off[O_F2]), a.lam, a.grad, st,
+                       p->ninst, p->norb, n2, n2);
   if (rc != NOF_OK) return rc;
   // energy: h, cJ, cK stride n2 per instance; J, K stride n2
   return energy(p->norb, a.n, h, (double*)(a.ws + p->off[O_J]), (double*)(a.ws + p->off[O_K]),

@@ -29,6 +29,7 @@ inline size_t dtype_size(int t) {
     case NOF_F32: return 4;
     case NOF_BF16: return 2;
     case NOF_BF16X4: return 8;                 // four planes (padded rows)
+    case NOF_I8X4: return 4;                   // four INT8 planes (and row exponents)
     default: return 0;
   }
 }
@@ -69,6 +70,10 @@ struct GemmDesc {
   int binner;
   long long sx2, sy2, so2, sd2, ss2;
   int tile;                        // workgroup tile edge of gemm_tn: 128 (default) or 64
+  // Exchange-type role with S only: if W, the right operand becomes
+  // Y_b(k,n) S(k,n) - [k == n] W[outer*sw2 + b*ldw + n], so that the product
+  // is the exchange-type term minus the Coulomb-type term (F2 - F1).
+  const double* W; long long ldw, sw2;
 };
 
 // Element types: 0 = f64, 1 = f32.  prec: NOF_P_F64 or NOF_P_F32.
@@ -104,6 +109,37 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
 // Column grid exponents e[b*N + n] from the row-tile maxima above.
 int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st);
 inline int fx_tiles(int n) { return (n + 127) / 128; }
+// INT8 fixed-point transform stage (gemm_i8.hip, NOF_P_I8X10):
+//   Out_b[m][n] = sum_k X_b(k, m) Y_b(k, n)   (FP32 out, FP64 diagonal Dg if sym)
+// X: INT8 planes at X + q*psx + b*sx + m*ldx + k (ldx a multiple of 64, zero
+// for k >= K) with grid exponents ex[b*sex + m]; Y likewise (n, ey, sey).
+// cmax as in FxDesc.
+constexpr int I8_MAX_K = 65536;          // int32 sums of the pieces stay exact below this depth
+struct I8Desc {
+  int M, N, K, batch;
+  const unsigned char* X; long long ldx, sx, psx; const int* ex; long long sex;
+  const unsigned char* Y; long long ldy, sy, psy; const int* ey; long long sey;
+  float* Out; long long ldo, so;
+  double* Dg; long long sd;
+  bool sym;
+  int role;                        // 1 = transform stage 1, 2 = stage 2 (kernel symbol)
+  unsigned* cmax; long long scm;
+};
+int gemm_i8(const I8Desc& d, hipStream_t st);
+inline long long i8_ldk(int K) { return ((long long)K + 63) / 64 * 64; }
+// INT8 planes [4][nrow][ldk] and grid exponents e[nrow] of the rows of
+// A[nrow][K] (FP64/FP32); of the columns of an FP64 k-major A[k][col]
+// ([4][ncol][ldk], e[ncol]); grid exponents of T_b's columns from the stage-1
+// column maxima; planes [4][batch][N][ldk] of the columns of the k-major FP32
+// T_b[K][N] on those grids.
+int i8_split_rows(const void* A, int At, long long nrow, int K, int ldk, void* planes, int* e,
+                  hipStream_t st);
+int i8_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* planes, int* e,
+                  hipStream_t st);
+int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st);
+int i8_split_T(const float* T, int batch, int K, int N, long long sT, int ldk, const int* e, void* planes,
+               hipStream_t st);
+
 // Exchange-type Fock partials of the split forms (gemm_fx.hip):
 //   Out[g][r][s] = sum_{P in [g*fold, (g+1)*fold)} sum_q b^P[q][r] S[q][s] b^P[q][s]
 // b FP32 [naux][norb][norb] symmetric slabs; S FP64 [norb][norb]; St a
@@ -160,6 +196,10 @@ int kf1_parts(int naux, int norb, int ninst, int bt);
 int reduce_parts(const double* part, int nparts, long long stride, int norb,
                  bool sym_upper, double* out, hipStream_t st, int ninst = 1,
                  long long pinst = 0, long long oinst = 0);
+
+// y -= x (n elements; ninst instances at the given strides).
+int subtract(long long n, const double* x, double* y, hipStream_t st, int ninst = 1,
+             long long xstride = 0, long long ystride = 0);
 
 // Instance-batched forms (grid dimension over instances with the given strides).
 int lambda_grad(int norb, const double* n, const double* h, const double* F1,

@@ -141,6 +141,13 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
   TY yr[PSY ? 1 : PER_T];
   bf8v xp[PSX ? NX : 1][2], yp[PSY ? NY : 1][2];
   float sr[HAS_S ? PER_T : 1];
+  // Coulomb-type term folded in (W given): the element with k == n of the
+  // staged rows loses W[b][n] (sk0: first k of the staged rows; sdiag: this
+  // lane stages that element)
+  const double* __restrict__ Wg = HAS_S ? d.W : nullptr;
+  float wv = 0.f;
+  int sk0 = 0;
+  bool sdiag = false;
 
   auto load = [&](int s) {
     const int bb = b_lo + s / nkb;
@@ -180,6 +187,12 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
         if (HAS_S) sr[HAS_S ? j : 0] = ok ? (float)S[(long long)(k0 + kb + j) * d.lds + (n0 + c_t)] : 0.f;
       }
     }
+    if (HAS_S) {
+      sk0 = k0;
+      const int dk = n0 + c_t - k0 - kb;
+      sdiag = Wg && yn_ok && dk >= 0 && dk < PER_T;
+      if (sdiag) wv = (float)Wg[(long long)bb * d.ldw + n0 + c_t];
+    }
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -209,7 +222,8 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
         for (int e = 0; e < 8; ++e) {
           const int j = half * 8 + e;
           __bf16 p[3];
-          const float v = HAS_S ? as_float(yr[PSY ? 0 : j]) * sr[HAS_S ? j : 0] : as_float(yr[PSY ? 0 : j]);
+          float v = HAS_S ? as_float(yr[PSY ? 0 : j]) * sr[HAS_S ? j : 0] : as_float(yr[PSY ? 0 : j]);
+          if (HAS_S && sdiag && sk0 + kg * 16 + j == n0 + c_t) v -= wv;
           split<NY>(v, p);
 #pragma unroll
           for (int q = 0; q < NY; ++q) py[q][e] = p[q];

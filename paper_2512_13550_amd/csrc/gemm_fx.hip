@@ -259,57 +259,61 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   const int ex = (!XPS && xok) ? d.ex[(long long)bb * d.sex + m0 + cx] : 0;
   const int ey = (!YPS && yok) ? d.ey[ib * d.sey + ob * d.sey2 + n0 + cy] : 0;
 
-  bf8v xp[XPS ? 4 : 1], yp[YPS ? 4 : 1];
-  float xr[XPS ? 1 : 8], yr[YPS ? 1 : 8];
+  // raw operands of one stage of this thread (planes as loaded, FP32 values
+  // split when they are stored to LDS)
+  struct Raw {
+    bf8v xp[XPS ? 4 : 1], yp[YPS ? 4 : 1];
+    float xr[XPS ? 1 : 8], yr[YPS ? 1 : 8];
+  };
 
-  auto load = [&](int s) {
+  auto load = [&](int s, Raw& R) {
     int k0 = s * KT + 8 * kqx;
     int kl = d.K - k0;
     if constexpr (XPS) {
       const __bf16* p = (const __bf16*)d.X + offx + (long long)(m0 + cx) * d.ldx + k0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xp[XPS ? q : 0] = xok ? *(const bf8v*)(p + (long long)q * d.psx) : bf8v{};
+      for (int q = 0; q < 4; ++q) R.xp[XPS ? q : 0] = xok ? *(const bf8v*)(p + (long long)q * d.psx) : bf8v{};
     } else if constexpr (XM == 2) {
       const float* p = (const float*)d.X + offx + (long long)(m0 + cx) * d.ldx + k0;
       if (xok && kl >= 8) {
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const float4 f = *(const float4*)(p + 4 * v);
-          xr[XPS ? 0 : 4 * v] = f.x; xr[XPS ? 0 : 4 * v + 1] = f.y;
-          xr[XPS ? 0 : 4 * v + 2] = f.z; xr[XPS ? 0 : 4 * v + 3] = f.w;
+          R.xr[XPS ? 0 : 4 * v] = f.x; R.xr[XPS ? 0 : 4 * v + 1] = f.y;
+          R.xr[XPS ? 0 : 4 * v + 2] = f.z; R.xr[XPS ? 0 : 4 * v + 3] = f.w;
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[j] : 0.f;
+        for (int j = 0; j < 8; ++j) R.xr[XPS ? 0 : j] = (xok && j < kl) ? p[j] : 0.f;
       }
     } else {
       const float* p = (const float*)d.X + offx + (long long)k0 * d.ldx + m0 + cx;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) xr[XPS ? 0 : j] = (xok && j < kl) ? p[(long long)j * d.ldx] : 0.f;
+      for (int j = 0; j < 8; ++j) R.xr[XPS ? 0 : j] = (xok && j < kl) ? p[(long long)j * d.ldx] : 0.f;
     }
     k0 = s * KT + 8 * kqy;
     kl = d.K - k0;
     if constexpr (YPS) {
       const __bf16* p = (const __bf16*)d.Y + offy + (long long)(n0 + cy) * d.ldy + k0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) yp[YPS ? q : 0] = yok ? *(const bf8v*)(p + (long long)q * d.psy) : bf8v{};
+      for (int q = 0; q < 4; ++q) R.yp[YPS ? q : 0] = yok ? *(const bf8v*)(p + (long long)q * d.psy) : bf8v{};
     } else {
       const float* p = (const float*)d.Y + offy + (long long)k0 * d.ldy + n0 + cy;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) yr[YPS ? 0 : j] = (yok && j < kl) ? p[(long long)j * d.ldy] : 0.f;
+      for (int j = 0; j < 8; ++j) R.yr[YPS ? 0 : j] = (yok && j < kl) ? p[(long long)j * d.ldy] : 0.f;
     }
   };
 
-  auto store = [&](int buf) {
+  auto store = [&](const Raw& R, int buf) {
     if constexpr (XPS) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[buf][q][cx][swz(cx, kqx)] = xp[XPS ? q : 0];
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[buf][q][cx][swz(cx, kqx)] = R.xp[XPS ? q : 0];
     } else {
       bf8v pk[4];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         __bf16 p[4];
-        split_g(xr[XPS ? 0 : e], ex, p);
+        split_g(R.xr[XPS ? 0 : e], ex, p);
 #pragma unroll
         for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
       }
@@ -318,13 +322,13 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     }
     if constexpr (YPS) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[buf][q][cy][swz(cy, kqy)] = yp[YPS ? q : 0];
+      for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[buf][q][cy][swz(cy, kqy)] = R.yp[YPS ? q : 0];
     } else {
       bf8v pk[4];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         __bf16 p[4];
-        split_g(yr[YPS ? 0 : e], ey, p);
+        split_g(R.yr[YPS ? 0 : e], ey, p);
 #pragma unroll
         for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
       }
@@ -391,19 +395,47 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     }
   };
 
-  // two LDS buffers: stage s+1 is stored into the other buffer while stage s
-  // is multiplied, one barrier per stage
-  if (nstage > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  for (int s = 0; s < nstage; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nstage) load(s + 1);
-    compute(s, buf);
-    if (s + 1 < nstage) store(buf ^ 1);
+  // two LDS buffers, one barrier per stage.  Without the FP64 flush (K <=
+  // 1024) two stages are in flight in registers: while stage s is multiplied
+  // out of one buffer, stage s + 1 (loaded a stage earlier) is stored into
+  // the other and stage s + 2 is being loaded; loads past the last stage
+  // repeat it (in bounds) and go to a buffer nobody reads.  The flushing
+  // variant has no registers to spare for that and keeps one stage in flight.
+  if constexpr (!BIGK) {
+    const int last = nstage - 1;
+    Raw r0, r1;
+    if (nstage > 0) {
+      load(0, r0);
+      load(min(1, last), r1);
+      store(r0, 0);
+    }
     __syncthreads();
+    int s = 0;
+    for (; s + 2 <= nstage; s += 2) {
+      load(min(s + 2, last), r0);
+      compute(s, 0);
+      store(r1, 1);
+      __syncthreads();
+      load(min(s + 3, last), r1);
+      compute(s + 1, 1);
+      store(r0, 0);
+      __syncthreads();
+    }
+    if (s < nstage) compute(s, 0);
+  } else {
+    Raw r0;
+    if (nstage > 0) {
+      load(0, r0);
+      store(r0, 0);
+    }
+    __syncthreads();
+    for (int s = 0; s < nstage; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nstage) load(s + 1, r0);
+      compute(s, buf);
+      if (s + 1 < nstage) store(r0, buf ^ 1);
+      __syncthreads();
+    }
   }
 
   float* __restrict__ Out = d.Out + ib * d.so + ob * d.so2;

@@ -1,0 +1,455 @@
+// INT8 form of the fixed-point split transform (NOF_P_I8X10): the two
+// stages of the orbital transformation, b^P = C^T B^P C, on the INT8 matrix
+// cores.
+//
+//   Out_b[m][n] = sum_k X_b(k, m) * Y_b(k, n)
+//
+// As in the BF16 fixed-point form, every row m of X and every column n of Y
+// gets one grid over the whole contraction (Ozaki, Ogita, Oishi and Rump,
+// Numer. Algorithms 2012: error-free splitting against a per-vector grid), here
+// with INT8 pieces: with 2^E the smallest power of two for which
+// max|x| 2^(7-E) < 127.5,
+//   x = n_0 2^(E-7) + n_1 2^(E-14) + n_2 2^(E-21) + n_3 2^(E-28) + r,
+//   |n_0| <= 127, |n_1|, |n_2|, |n_3| <= 64, |r| <= 2^(E-29)
+// (each piece rounds what the previous ones left, at most half a unit of
+// their grid, on a grid 2^7 finer).  A product of pieces of order
+// o = qx + qy counts units of 2^(Ex+Ey-14-7o); v_mfma_i32_16x16x64_i8 sums 64
+// of them per instruction exactly in int32, and the ten products of order
+// <= 3 go to four accumulators, one per order.  Per k an order adds at most
+// 2*127*64 + 2*64^2 = 24448 units, so the sums are exact for K < 87,000.  The
+// epilogue forms
+//   v = 2^(Ex+Ey-14) (acc0 + 2^-7 (acc1 + 2^-7 (acc2 + 2^-7 acc3)))
+// in FP64, where every step is exact (at most 52 significant bits).  What
+// remains is the representation residual r (2^-29 of a vector's largest
+// element) and the dropped products of order 4..6 (below 2^-28 of
+// |x|max |y|max per term).
+//
+// Against the BF16 form: the pieces are half the bytes, an instruction does
+// twice the multiply-adds at the same issue rate, and the accumulators never
+// round, so no FP64 flush is needed at any depth.
+//
+// Operands are planes [4][rows][ldk] of INT8 (k contiguous, ldk a multiple
+// of 64, zero past K) with one int32 grid exponent per row.
+//
+// Layout: 512 threads = 8 waves (2 x 4); the workgroup tile is 128 x 128,
+// each wave 64 x 32 as 4 x 2 fragments of v_mfma_i32_16x16x64_i8 (lane l
+// holds 16 consecutive k of row l%16 at k offset 16*(l/16), the same 16-byte
+// operand layout as the BF16 16x16x32 instruction; output row 4*(l/16)+r,
+// column l%16).  LDS holds the four planes as [row][64 k] (16-byte chunks
+// swizzled by row), double-buffered; the next stage's loads are in flight
+// while the current one is multiplied.
+#include "common.h"
+
+namespace nof {
+namespace {
+
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+constexpr int IT = 128;                 // tile edge
+constexpr int IK = 64;                  // k per stage (bytes per LDS row)
+constexpr int INTHR = 512;
+constexpr int IEMIN = -90, IEMAX = 128; // grid exponent range (FP32 scales stay normal)
+
+__device__ __forceinline__ int xcd_logical(int w, int G) {
+  const int q = G >> 3, r = G & 7, x = w & 7, i = w >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int clamp_e(int e) { return e < IEMIN ? IEMIN : (e > IEMAX ? IEMAX : e); }
+
+// Grid exponent of a vector whose largest magnitude is m (FP64).
+__device__ __forceinline__ int grid_exp_i8(double m) {
+  if (!(m > 0.0)) return IEMIN;
+  int E;
+  frexp(m, &E);                          // m < 2^E
+  if (ldexp(m, 7 - E) >= 127.5) ++E;
+  return clamp_e(E);
+}
+
+// The same from the bits of a non-negative FP32 maximum.
+__device__ __forceinline__ int grid_exp_i8_bits(unsigned mbits) {
+  if (mbits == 0) return IEMIN;
+  int E = (int)(mbits >> 23) - 126;      // 2^E > m, m 2^(7-E) in [64, 128)
+  if ((mbits & 0x7fffffu) >= 0x7f0000u) ++E;   // m 2^(7-E) >= 127.5
+  return clamp_e(E);
+}
+
+// Pieces of v on the grid of exponent E, packed: byte q of the result is n_q.
+__device__ __forceinline__ void split_i8(double v, int E, unsigned (&p)[4], int byte) {
+  double t = ldexp(v, 7 - E);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double n = rint(t);
+    p[q] |= ((unsigned)(int)n & 0xffu) << (8 * byte);
+    t = (t - n) * 128.0;
+  }
+}
+
+__device__ __forceinline__ void split_i8f(float v, int E, unsigned (&p)[4], int byte) {
+  float t = v * __int_as_float((127 + 7 - E) << 23);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float n = rintf(t);
+    p[q] |= ((unsigned)(int)n & 0xffu) << (8 * byte);
+    t = (t - n) * 128.0f;
+  }
+}
+
+// Planes and grid exponents of the rows of A[nrow][K] (FP64 or FP32, rows
+// contiguous): out[q][row][ldk], e[row]; one wave per row, lane l splits
+// four consecutive k per step (one 32-bit store per plane).
+template <typename T>
+__global__ void k_split_rows_i8(const T* __restrict__ A, long long nrow, int K, int ldk,
+                                unsigned char* __restrict__ out, int* __restrict__ e) {
+  const int l = threadIdx.x & 63;
+  const long long wpb = blockDim.x >> 6;
+  const long long plane = nrow * ldk;
+  for (long long row = blockIdx.x * wpb + (threadIdx.x >> 6); row < nrow; row += (long long)gridDim.x * wpb) {
+    const T* a = A + row * K;
+    double m = 0.0;
+    for (int k = l; k < K; k += 64) m = fmax(m, fabs((double)a[k]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    const int E = grid_exp_i8(m);
+    if (l == 0) e[row] = E;
+    for (int k4 = 4 * l; k4 < ldk; k4 += 256) {
+      unsigned p[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) split_i8(k4 + i < K ? (double)a[k4 + i] : 0.0, E, p, i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *(unsigned*)(out + q * plane + row * ldk + k4) = p[q];
+    }
+  }
+}
+
+// Planes and grid exponents of the columns of an FP64 k-major A[k][col]
+// (k < K): out[q][col][ldk], e[col].  Block: 16 columns; their maxima from 16
+// row groups, then each wave splits four columns with lanes along k.
+__global__ void k_split_cols_i8(const double* __restrict__ A, int K, int ncol, int lda, int ldk,
+                                unsigned char* __restrict__ out, int* __restrict__ e) {
+  __shared__ double red[16][16];
+  __shared__ int ecol[16];
+  const long long plane = (long long)ncol * ldk;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int c = t & 15, kg = t >> 4;
+  for (int c0 = blockIdx.x * 16; c0 < ncol; c0 += gridDim.x * 16) {
+    double m = 0.0;
+    if (c0 + c < ncol)
+      for (int k = kg; k < K; k += 16) m = fmax(m, fabs(A[(long long)k * lda + c0 + c]));
+    red[kg][c] = m;
+    __syncthreads();
+    if (kg == 0) {
+      double mm = 0.0;
+      for (int i = 0; i < 16; ++i) mm = fmax(mm, red[i][c]);
+      ecol[c] = grid_exp_i8(mm);
+      if (c0 + c < ncol) e[c0 + c] = ecol[c];
+    }
+    __syncthreads();
+    for (int cc = 4 * w; cc < 4 * w + 4; ++cc) {
+      const int col = c0 + cc;
+      if (col >= ncol) break;
+      for (int k4 = 4 * l; k4 < ldk; k4 += 256) {
+        unsigned p[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          split_i8(k4 + i < K ? A[(long long)(k4 + i) * lda + col] : 0.0, ecol[cc], p, i);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(unsigned*)(out + q * plane + (long long)col * ldk + k4) = p[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Grid exponents of the columns of T_b (FP32) from the per-row-tile column
+// maxima of the stage-1 epilogue: e[b*N + n] from max_t cmax[b][t][n].
+__global__ void k_cmax_exps_i8(const unsigned* __restrict__ cmax, long long batch, int tiles, int N,
+                               int* __restrict__ e) {
+  const long long total = batch * N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long b = i / N;
+    const int n = (int)(i - b * N);
+    const unsigned* c = cmax + b * tiles * N + n;
+    unsigned m = 0;
+    for (int t = 0; t < tiles; ++t) m = max(m, c[(long long)t * N]);
+    e[i] = grid_exp_i8_bits(m);
+  }
+}
+
+// Planes of the columns of the k-major FP32 T_b[K][N] (batch stride sT) on
+// the grids e[b*N + n]: out[q][b][n][ldk].  Block: 64 columns (lanes along n,
+// coalesced reads) x 4 chunks of 16 k; each thread splits 16 consecutive k of
+// its column into one 16-byte store per plane.  Consecutive blocks take
+// consecutive k ranges of the same columns, so the partial lines they write
+// meet in the L2.
+__global__ void k_split_T_i8(const float* __restrict__ T, long long batch, int K, int N, long long sT,
+                             int ldk, const int* __restrict__ e, unsigned char* __restrict__ out) {
+  const int nkb = ldk / IK;
+  const int ncb = (N + 63) / 64;
+  const long long blocks = batch * ncb * nkb;
+  const long long plane = batch * (long long)N * ldk;
+  const int nl = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  for (long long blk = blockIdx.x; blk < blocks; blk += gridDim.x) {
+    const int kb = (int)(blk % nkb);
+    const long long r = blk / nkb;
+    const int cb = (int)(r % ncb);
+    const long long b = r / ncb;
+    const int n = cb * 64 + nl;
+    if (n >= N) continue;
+    const int k0 = kb * IK + 16 * kc;
+    const int E = e[b * N + n];
+    const float* t = T + b * sT + n;
+    unsigned p[4][4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      unsigned pw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = k0 + 4 * w + i;
+        split_i8f(k < K ? t[(long long)k * N] : 0.f, E, pw, i);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) p[q][w] = pw[q];
+    }
+    unsigned char* o = out + (b * N + n) * (long long)ldk + k0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *(i4v*)(o + q * plane) = i4v{(int)p[q][0], (int)p[q][1], (int)p[q][2], (int)p[q][3]};
+  }
+}
+
+// Byte offset of 16-byte chunk c in LDS row r: chunk c of row r sits at
+// position c ^ ((r >> 2) & 3), so the 16 rows of a fragment read (one chunk
+// each) and the chunks written by neighbouring loader lanes spread over the
+// banks.
+__device__ __forceinline__ int swz16(int r, int c) { return (c ^ ((r >> 2) & 3)) << 4; }
+
+__device__ __forceinline__ void tile_of(int t, int tiles_n, bool sym, int& tm, int& tn) {
+  if (!sym) {
+    tm = t / tiles_n;
+    tn = t - tm * tiles_n;
+    return;
+  }
+  int row = 0;
+  while (t >= tiles_n - row) { t -= tiles_n - row; ++row; }
+  tm = row;
+  tn = row + t;
+}
+
+__device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles) {
+  __shared__ __attribute__((aligned(16))) unsigned char Xs[2][4][IT][IK];
+  __shared__ __attribute__((aligned(16))) unsigned char Ys[2][4][IT][IK];
+
+  const int tid = threadIdx.x;
+  const int l = tid & 63, w = tid >> 6;
+  const int wm = w >> 2, wn = w & 3;          // wave tile: rows 64*wm.., columns 32*wn..
+
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  const int bb = logical / ntiles;
+  int tm, tn;
+  tile_of(logical - bb * ntiles, tiles_n, d.sym, tm, tn);
+  const int m0 = tm * IT, n0 = tn * IT;
+  const int nstage = (d.K + IK - 1) / IK;
+
+  // loader: thread owns row c of both tiles and the 16-byte chunk kq of it
+  const int c = tid >> 2, kq = tid & 3;
+  const bool xok = m0 + c < d.M, yok = n0 + c < d.N;
+  const unsigned char* __restrict__ xrow = d.X + bb * d.sx + (long long)(m0 + c) * d.ldx + 16 * kq;
+  const unsigned char* __restrict__ yrow = d.Y + bb * d.sy + (long long)(n0 + c) * d.ldy + 16 * kq;
+
+  struct Raw {
+    i4v x[4], y[4];
+  };
+  auto load = [&](int s, Raw& R) {
+    const long long k0 = (long long)s * IK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      R.x[q] = xok ? *(const i4v*)(xrow + q * d.psx + k0) : i4v{0, 0, 0, 0};
+      R.y[q] = yok ? *(const i4v*)(yrow + q * d.psy + k0) : i4v{0, 0, 0, 0};
+    }
+  };
+  auto store = [&](const Raw& R, int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *(i4v*)&Xs[buf][q][c][swz16(c, kq)] = R.x[q];
+      *(i4v*)&Ys[buf][q][c][swz16(c, kq)] = R.y[q];
+    }
+  };
+
+  i4v acc[4][4][2];                           // [order][row fragment][column fragment]
+#pragma unroll
+  for (int o = 0; o < 4; ++o)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[o][i][j] = i4v{0, 0, 0, 0};
+
+  const int kl = swz16(l & 15, l >> 4);
+  auto compute = [&](int buf) {
+    i4v b[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const i4v*)&Ys[buf][q][wn * 32 + j * 16 + (l & 15)][kl];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      i4v a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = *(const i4v*)&Xs[buf][q][wm * 64 + i * 16 + (l & 15)][kl];
+      // consecutive instructions go to different accumulators
+#pragma unroll
+      for (int px = 0; px < 4; ++px)
+#pragma unroll
+        for (int py = 0; py + px < 4; ++py)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[px + py][i][j] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(a[px], b[j][py], acc[px + py][i][j], 0, 0, 0);
+    }
+  };
+
+  // two LDS buffers, one barrier per stage; stage s + 1 is loaded while
+  // stage s is multiplied and stored into the other buffer afterwards
+  Raw r0;
+  if (nstage > 0) {
+    load(0, r0);
+    store(r0, 0);
+  }
+  __syncthreads();
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstage) load(s + 1, r0);
+    compute(buf);
+    if (s + 1 < nstage) store(r0, buf ^ 1);
+    __syncthreads();
+  }
+
+  float* __restrict__ Out = d.Out + bb * d.so;
+  const int* __restrict__ ex = d.ex + bb * d.sex;
+  const int* __restrict__ ey = d.ey + bb * d.sey;
+  int eyc[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gn = n0 + wn * 32 + j * 16 + (l & 15);
+    eyc[j] = gn < d.N ? ey[gn] : 0;
+  }
+  int cm[2] = {0, 0};      // bits of the largest |stored value| per column fragment
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+      if (gm >= d.M) continue;
+      const int exr = ex[gm];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gn = n0 + wn * 32 + j * 16 + (l & 15);
+        if (gn >= d.N) continue;
+        double v = (double)acc[3][i][j][r];
+        v = (double)acc[2][i][j][r] + v * 0.0078125;
+        v = (double)acc[1][i][j][r] + v * 0.0078125;
+        v = (double)acc[0][i][j][r] + v * 0.0078125;
+        v = ldexp(v, exr + eyc[j] - 14);
+        const float fv = (float)v;
+        cm[j] = max(cm[j], (int)(__float_as_uint(fv) & 0x7fffffffu));
+        if (!d.sym) {
+          Out[(long long)gm * d.ldo + gn] = fv;
+        } else if (gm <= gn) {
+          Out[(long long)gm * d.ldo + gn] = fv;
+          Out[(long long)gn * d.ldo + gm] = fv;
+          if (gm == gn && d.Dg) d.Dg[bb * d.sd + gm] = v;
+        }
+      }
+    }
+  if (d.cmax) {
+    // column maxima of this tile's stored values over its rows: the lane's
+    // rows, the four lane groups of a column, then the two row waves
+    __shared__ int cms[2][IT];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cm[j] = max(cm[j], __shfl_xor(cm[j], 16, 64));
+      cm[j] = max(cm[j], __shfl_xor(cm[j], 32, 64));
+      if (l < 16) cms[wm][wn * 32 + j * 16 + l] = cm[j];
+    }
+    __syncthreads();
+    if (tid < IT && n0 + tid < d.N)
+      d.cmax[bb * d.scm + (long long)tm * d.N + n0 + tid] = (unsigned)max(cms[0][tid], cms[1][tid]);
+  }
+}
+
+__global__ __launch_bounds__(INTHR, 1) void k_transform_stage1_i8(I8Desc d, int tiles_n, int ntiles) {
+  i8_body(d, tiles_n, ntiles);
+}
+__global__ __launch_bounds__(INTHR, 1) void k_transform_stage2_i8(I8Desc d, int tiles_n, int ntiles) {
+  i8_body(d, tiles_n, ntiles);
+}
+
+long long grid_of(long long items, int per_block) {
+  long long g = (items + per_block - 1) / per_block;
+  return g < 1 ? 1 : (g > 65536 ? 65536 : g);
+}
+
+}  // namespace
+
+int gemm_i8(const I8Desc& d, hipStream_t st) {
+  if (d.M < 0 || d.N < 0 || d.K < 0 || d.batch < 0) return NOF_E_DIM;
+  if (d.sym && d.M != d.N) return NOF_E_DIM;
+  if (d.K > I8_MAX_K) return NOF_E_DIM;
+  if (!d.X || !d.Y || !d.ex || !d.ey || !d.Out) return NOF_E_NULL;
+  if (d.ldx % IK || d.ldy % IK || d.ldx < d.K || d.ldy < d.K) return NOF_E_DIM;
+  const int tiles_m = (d.M + IT - 1) / IT;
+  const int tiles_n = (d.N + IT - 1) / IT;
+  const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
+  const long long G = (long long)ntiles * d.batch;
+  if (G <= 0) return NOF_OK;
+  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  if (d.role == 1)
+    hipLaunchKernelGGL(k_transform_stage1_i8, dim3((unsigned)G), dim3(INTHR), 0, st, d, tiles_n, ntiles);
+  else
+    hipLaunchKernelGGL(k_transform_stage2_i8, dim3((unsigned)G), dim3(INTHR), 0, st, d, tiles_n, ntiles);
+  return launch_status();
+}
+
+int i8_split_rows(const void* A, int At, long long nrow, int K, int ldk, void* planes, int* e,
+                  hipStream_t st) {
+  if (nrow <= 0 || K <= 0 || ldk < K || ldk % IK) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_of(nrow, 4);
+  if (At == NOF_F64)
+    hipLaunchKernelGGL(k_split_rows_i8<double>, dim3(g), dim3(256), 0, st, (const double*)A, nrow, K, ldk,
+                       (unsigned char*)planes, e);
+  else if (At == NOF_F32)
+    hipLaunchKernelGGL(k_split_rows_i8<float>, dim3(g), dim3(256), 0, st, (const float*)A, nrow, K, ldk,
+                       (unsigned char*)planes, e);
+  else
+    return NOF_E_DTYPE;
+  return launch_status();
+}
+
+int i8_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* planes, int* e,
+                  hipStream_t st) {
+  if (K <= 0 || ncol <= 0 || ldk < K || ldk % IK) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_of(ncol, 16);
+  hipLaunchKernelGGL(k_split_cols_i8, dim3(g), dim3(256), 0, st, A, K, ncol, lda, ldk,
+                     (unsigned char*)planes, e);
+  return launch_status();
+}
+
+int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st) {
+  if (batch <= 0 || tiles <= 0 || N <= 0) return NOF_E_DIM;
+  const unsigned g = (unsigned)grid_of((long long)batch * N, 256);
+  hipLaunchKernelGGL(k_cmax_exps_i8, dim3(g), dim3(256), 0, st, cmax, (long long)batch, tiles, N, e);
+  return launch_status();
+}
+
+int i8_split_T(const float* T, int batch, int K, int N, long long sT, int ldk, const int* e, void* planes,
+               hipStream_t st) {
+  if (batch <= 0 || K <= 0 || N <= 0 || ldk < K || ldk % IK) return NOF_E_DIM;
+  const long long blocks = (long long)batch * ((N + 63) / 64) * (ldk / IK);
+  const unsigned g = (unsigned)(blocks < 1 ? 1 : (blocks > (1 << 20) ? (1 << 20) : blocks));
+  hipLaunchKernelGGL(k_split_T_i8, dim3(g), dim3(256), 0, st, T, (long long)batch, K, N, sT, ldk, e,
+                     (unsigned char*)planes);
+  return launch_status();
+}
+
+}  // namespace nof

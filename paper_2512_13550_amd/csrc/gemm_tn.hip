@@ -133,7 +133,18 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
 
   TX xr[PX];
   TY yr[PY];
-  double sr[HAS_S ? PY : 1];
+  // S values as staged: FP64 for the FP64 product, rounded to FP32 for the
+  // FP32 one (whose staged operand is FP32 anyway)
+  typedef TC TS;
+  TS sr[HAS_S ? PY : 1];
+  // Coulomb-type term folded into the exchange-type product: in the stage
+  // whose k rows hold this thread's column n = n0 + cy_t (the lane stages row
+  // wk = n - k0 itself), W[b][n] is subtracted from that element after the
+  // stores (wdiag: this lane patches in the stage being staged)
+  const double* __restrict__ Wg = HAS_S && d.W ? d.W + (long long)outer * d.sw2 : nullptr;
+  TS wv = 0;
+  int wk = 0;
+  bool wdiag = false;
 
   auto load = [&](int s) {
     const int bb = b_lo + s / nkb;
@@ -161,7 +172,12 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     for (int j = 0; j < PY; ++j) {
       const bool ok = yn_ok && ky_t + RY * j < klim;
       yr[j] = ok ? py[(long long)(RY * j) * d.ldy] : (TY)0;
-      if (HAS_S) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : 0.0;
+      if (HAS_S) sr[HAS_S ? j : 0] = ok ? (TS)S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : (TS)0;
+    }
+    if (HAS_S) {
+      wk = n0 + cy_t - k0;
+      wdiag = Wg && yn_ok && wk >= 0 && wk < KT && (wk - ky_t) % RY == 0;
+      if (wdiag) wv = (TS)Wg[(long long)bb * d.ldw + n0 + cy_t];
     }
   };
   auto store = [&](int buf) {
@@ -172,9 +188,12 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     }
 #pragma unroll
     for (int j = 0; j < PY; ++j) {
-      if (HAS_S) Ys[buf][ky_t + RY * j][cy_t] = (TC)((double)yr[j] * sr[HAS_S ? j : 0]);
+      if (HAS_S) Ys[buf][ky_t + RY * j][cy_t] = (TC)yr[j] * sr[HAS_S ? j : 0];
       else Ys[buf][ky_t + RY * j][cy_t] = (TC)yr[j];
     }
+    // the lane's own diagonal element, written just above (LDS accesses of a
+    // wave are ordered)
+    if (HAS_S && wdiag) Ys[buf][wk][cy_t] -= wv;
   };
 
   if (nstage > 0) {

@@ -261,6 +261,13 @@ __global__ void k_reduce(const double* __restrict__ part, int nparts, long long 
   }
 }
 
+// y -= x over n elements.
+__global__ void k_subtract(long long n, const double* __restrict__ x, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] -= x[i];
+}
+
 __global__ void k_lambda(int norb, const double* __restrict__ n, const double* __restrict__ h,
                          const double* __restrict__ F1, const double* __restrict__ F2,
                          double* __restrict__ lam, double* __restrict__ grad, long long nstride,
@@ -271,16 +278,17 @@ __global__ void k_lambda(int norb, const double* __restrict__ n, const double* _
   h += y * mstride;
   lam += y * mstride;
   if (grad) grad += y * mstride;
-  F1 += y * fstride;
+  // F1 == NULL: F2 already holds the exchange-type minus the Coulomb-type term
+  if (F1) F1 += y * fstride;
   F2 += y * fstride;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x) {
     const int r = (int)(i / norb), s = (int)(i - (long long)r * norb);
     const long long t = (long long)s * norb + r;
-    const double l_rs = n[s] * h[i] + F1[i] - F2[i];
+    const double l_rs = F1 ? n[s] * h[i] + F1[i] - F2[i] : n[s] * h[i] - F2[i];
     lam[i] = l_rs;
     if (grad) {
-      const double l_sr = n[r] * h[t] + F1[t] - F2[t];
+      const double l_sr = F1 ? n[r] * h[t] + F1[t] - F2[t] : n[r] * h[t] - F2[t];
       grad[i] = 4.0 * (l_rs - l_sr);
     }
   }
@@ -459,6 +467,17 @@ int lambda_grad(int norb, const double* n, const double* h, const double* F1, co
   hipLaunchKernelGGL(k_lambda, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, n, h, F1,
                      F2, lam, grad, nstride, mstride, fstride);
   return launch_status();
+}
+
+int subtract(long long n, const double* x, double* y, hipStream_t st, int ninst, long long xstride,
+             long long ystride) {
+  for (int i = 0; i < ninst; ++i) {
+    hipLaunchKernelGGL(k_subtract, dim3(grid_for(n, 256)), dim3(256), 0, st, n, x + i * xstride,
+                       y + i * ystride);
+    const int rc = launch_status();
+    if (rc != NOF_OK) return rc;
+  }
+  return NOF_OK;
 }
 
 size_t energy_ws(int ninst) { return align256((size_t)ninst * E_PARTS * sizeof(double)); }

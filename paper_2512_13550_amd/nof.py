@@ -20,8 +20,8 @@ lib = ctypes.CDLL(LIB_PATH)
 
 # status codes and enums (mirror include/nof.h)
 OK, E_NULL, E_DIM, E_DTYPE, E_PREC, E_WORKSPACE, E_HIP, E_NOT_CONVERGED, E_ARG = 0, -1, -2, -3, -4, -5, -6, -7, -8
-F64, F32, BF16, BF16X4 = 0, 1, 2, 3
-P_F64, P_F32, P_BF16X1, P_BF16X3, P_BF16X6, P_BF16X10 = 0, 1, 2, 3, 4, 5
+F64, F32, BF16, BF16X4, I8X4 = 0, 1, 2, 3, 4
+P_F64, P_F32, P_BF16X1, P_BF16X3, P_BF16X6, P_BF16X10, P_I8X10 = 0, 1, 2, 3, 4, 5, 6
 
 _vp, _i, _sz, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
 
@@ -37,6 +37,8 @@ _sig("nof_status_str", ctypes.c_char_p, _i)
 _sig("nof_mo_transform_ws", _sz, _i, _i, _i, _i, _i, _i)
 _sig("nof_mo_transform", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _i, _vp, _sz, _vp)
 _sig("nof_mo_transform_stage_ws", _sz, _i, _i, _i, _i)
+_sig("nof_split_B_i8_bytes", _sz, _i, _i)
+_sig("nof_split_B_i8", _i, _i, _i, _vp, _i, _vp, _sz, _vp)
 _sig("nof_split_B_bytes", _sz, _i, _i)
 _sig("nof_split_B", _i, _i, _i, _vp, _i, _vp, _sz, _vp)
 _sig("nof_mo_transform_stage1", _i, _i, _i, _i, _vp, _i, _vp, _vp, _i, _i, _vp, _sz, _vp)
@@ -46,6 +48,8 @@ _sig("nof_jk_diag", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_gen_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_exchange_fock_ws", _sz, _i, _i, _i, _i)
 _sig("nof_exchange_fock", _i, _i, _i, _vp, _i, _vp, _vp, _i, _vp, _sz, _vp)
+_sig("nof_fock_terms_ws", _sz, _i, _i, _i, _i)
+_sig("nof_fock_terms", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp)
 _sig("nof_coulomb_fock_ws", _sz, _i, _i, _i)
 _sig("nof_coulomb_fock", _i, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp)
 _sig("nof_lambda_grad", _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
@@ -119,9 +123,10 @@ FUNC_HF, FUNC_PNOF5, FUNC_PNOF7 = 0, 1, 2
 DECLARED = [
     "nof_status_str", "nof_mo_transform_ws", "nof_mo_transform", "nof_mo_transform_stage1",
     "nof_mo_transform_stage2", "nof_mo_transform_stage_ws", "nof_split_B_bytes", "nof_split_B",
+    "nof_split_B_i8_bytes", "nof_split_B_i8",
     "nof_jk_diag_ws", "nof_jk_diag",
     "nof_gen_fock_ws", "nof_gen_fock", "nof_exchange_fock_ws", "nof_exchange_fock",
-    "nof_coulomb_fock_ws", "nof_coulomb_fock", "nof_lambda_grad", "nof_energy_ws", "nof_energy", "nof_coeffs_from_cumulant",
+    "nof_fock_terms_ws", "nof_fock_terms", "nof_coulomb_fock_ws", "nof_coulomb_fock", "nof_lambda_grad", "nof_energy_ws", "nof_energy", "nof_coeffs_from_cumulant",
     "nof_expm_antisym_ws", "nof_expm_antisym", "nof_rotate_orbitals_ws", "nof_rotate_orbitals",
     "nof_orthonormalize_ws", "nof_orthonormalize",
     "nof_adam_step", "nof_occ_ws", "nof_occ_energy_grad", "nof_occ_optimize", "nof_occ_optimize_noalloc",
@@ -188,11 +193,32 @@ class SplitB:
                               stream_handle(stream)), "nof_split_B")
 
 
+class SplitBI8:
+    """B as the four fixed-point INT8 planes and row exponents written by
+    nof_split_B_i8, the input of the P_I8X10 transform (split once)."""
+
+    def __init__(self, B, stream=None):
+        naux, nbf, _ = B.shape
+        self.shape = tuple(B.shape)
+        self.device = B.device
+        nbytes = lib.nof_split_B_i8_bytes(naux, nbf)
+        self.planes = workspace(nbytes, B.device)
+        check(lib.nof_split_B_i8(naux, nbf, _p(B), _TDT[B.dtype], _p(self.planes), nbytes,
+                                 stream_handle(stream)), "nof_split_B_i8")
+
+
 def _b_arg(B):
-    """(storage code, device pointer) of a B argument: a tensor or a SplitB."""
+    """(storage code, device pointer) of a B argument: a tensor, a SplitB or a
+    SplitBI8."""
     if isinstance(B, SplitB):
         return BF16X4, _p(B.planes)
+    if isinstance(B, SplitBI8):
+        return I8X4, _p(B.planes)
     return _TDT[B.dtype], _p(B)
+
+
+def _default_prec(Bt):
+    return {F64: P_F64, F32: P_F32, BF16X4: P_BF16X10, I8X4: P_I8X10}.get(Bt, P_F64)
 
 
 def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
@@ -204,7 +230,7 @@ def mo_transform(B, C, prec=None, b=None, D=None, ws=None, stream=None):
     naux, nbf, _ = B.shape
     norb = C.shape[1]
     Bt, Bp = _b_arg(B)
-    prec = _PREC_OF.get(Bt, P_BF16X10 if Bt == BF16X4 else P_F64) if prec is None else prec
+    prec = _default_prec(Bt) if prec is None else prec
     bdtype = torch.float64 if prec == P_F64 else torch.float32
     if b is None:
         b = torch.empty((naux, norb, norb), dtype=bdtype, device=B.device)
@@ -233,7 +259,7 @@ def transform_stage1(B, C, T, prec=None, ws=None, stream=None):
     naux, nbf, _ = B.shape
     norb = C.shape[1]
     bt, Bp = _b_arg(B)
-    prec = _PREC_OF.get(bt, P_BF16X10 if bt == BF16X4 else P_F64) if prec is None else prec
+    prec = _default_prec(bt) if prec is None else prec
     ws = _stage_ws(naux, nbf, norb, prec, B.device, ws)
     check(lib.nof_mo_transform_stage1(naux, nbf, norb, Bp, bt, _f64(C, "C"), _p(T), _TDT[T.dtype],
                                       prec, _p(ws), ws.numel(), stream_handle(stream)),
@@ -318,6 +344,22 @@ def exchange_fock(b, cK, prec=None, F2=None, ws=None, stream=None):
     return F2
 
 
+def fock_terms(b, D, cJ, cK, prec=None, F=None, ws=None, stream=None):
+    """F = F2 - F1 in one contraction, the Coulomb-type term folded into the
+    exchange-type product's right operand (nof_fock_terms)."""
+    naux, norb, _ = b.shape
+    bt = _TDT[b.dtype]
+    prec = _PREC_OF.get(bt, P_F64) if prec is None else prec
+    if F is None:
+        F = torch.empty((norb, norb), dtype=torch.float64, device=b.device)
+    need = lib.nof_fock_terms_ws(naux, norb, bt, prec)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, b.device)
+    check(lib.nof_fock_terms(naux, norb, _p(b), bt, _f64(D, "D"), _f64(cJ, "cJ"), _f64(cK, "cK"), _p(F),
+                             prec, _p(ws), ws.numel(), stream_handle(stream)), "nof_fock_terms")
+    return F
+
+
 def coulomb_fock(b, D, cJ, F1=None, K=None, want_K=True, ws=None, stream=None):
     """F1_rs = sum_P b^P_rs (D cJ)[P][s] and K from the same pass (nof_coulomb_fock)."""
     naux, norb, _ = b.shape
@@ -337,13 +379,15 @@ def coulomb_fock(b, D, cJ, F1=None, K=None, want_K=True, ws=None, stream=None):
 
 
 def lambda_grad(n, h, F1, F2, lam=None, g=None, want_grad=True, stream=None):
-    """lambda = n_s h_rs + F1 - F2 and grad = 4(lambda - lambda^T) (nof_lambda_grad)."""
+    """lambda = n_s h_rs + F1 - F2 and grad = 4(lambda - lambda^T) (nof_lambda_grad);
+    F1 = None: F2 is the combined F2 - F1 of fock_terms."""
     norb = n.shape[0]
     if lam is None:
         lam = torch.empty((norb, norb), dtype=torch.float64, device=n.device)
     if want_grad and g is None:
         g = torch.empty_like(lam)
-    check(lib.nof_lambda_grad(norb, _f64(n, "n"), _f64(h, "h"), _f64(F1, "F1"), _f64(F2, "F2"), _p(lam),
+    f1 = None if F1 is None else _f64(F1, "F1")
+    check(lib.nof_lambda_grad(norb, _f64(n, "n"), _f64(h, "h"), f1, _f64(F2, "F2"), _p(lam),
                               _p(g) if want_grad else None, stream_handle(stream)), "nof_lambda_grad")
     return lam, (g if want_grad else None)
 
@@ -501,7 +545,7 @@ class BatchPlan:
         self.ninst, nbf, norb = C.shape
         naux = B.shape[0]
         bt = _b_arg(B)[0]
-        self.prec = (P_BF16X10 if bt == BF16X4 else _PREC_OF.get(bt, P_F64)) if prec is None else prec
+        self.prec = _default_prec(bt) if prec is None else prec
         self.handle = _vp()
         check(lib.nof_plan_create(ctypes.byref(self.handle), self.ninst, naux, nbf, norb, self.prec),
               "nof_plan_create")
@@ -652,7 +696,7 @@ def solve(B, C, H, members, mapping, functional, gamma, prec=None, n=None, ws=No
     norb = C.shape[1]
     ns, ng = gamma.shape
     Bt, Bp = _b_arg(B)
-    prec = _PREC_OF.get(Bt, P_BF16X10 if Bt == BF16X4 else P_F64) if prec is None else prec
+    prec = _default_prec(Bt) if prec is None else prec
     if members.dtype != torch.int32:
         raise TypeError("members must be int32")
     need = lib.nof_solve_ws(naux, nbf, norb, ns, ng, Bt, prec)

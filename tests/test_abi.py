@@ -255,8 +255,14 @@ def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
         ldc = ninst * norb
         need = {"Call": nbf * ldc * 8, "T": naux * nbf * ldc * es, "b": ninst * naux * norb * norb * es,
                 "D": ninst * naux * norb * 8, "TH": ninst * nbf * norb * 8, "h": ninst * n2, "J": ninst * n2,
-                "K": ninst * n2, "W": ninst * naux * norb * 8, "Kpart": ninst * n2, "F1part": ninst * n2,
-                "F2part": ninst * gmax * n2, "F1": ninst * n2, "F2": ninst * n2, "Epart": ninst * 8}
+                "K": ninst * n2, "W": ninst * naux * norb * 8, "Kpart": ninst * n2,
+                "F2part": ninst * gmax * n2, "F2": ninst * n2, "Epart": ninst * 8}
+        if prec == "x10":
+            need.update({"F1part": ninst * n2, "F1": ninst * n2})
+        else:
+            # the Coulomb-type term rides in the exchange-type product (F2
+            # holds F2 - F1): its partials and sum need no space
+            assert size[PLAN_REGIONS.index("F1part")] == 0 and size[PLAN_REGIONS.index("F1")] == 0
         if prec == "x10":
             ldk = (nbf + 31) // 32 * 32
             need.update({"Cplanes": 4 * ldc * ldk * 2, "Tcolmax": naux * ((nbf + 127) // 128) * ldc * 4,

@@ -241,3 +241,31 @@ def test_split_B_pieces_meet_documented_bounds():
         assert np.max(np.abs(nq)) <= 128, q
     resid = np.abs(B - P.sum(axis=0))
     assert np.all(resid <= np.ldexp(1.0, E - 32)[:, :, None])
+
+
+@pytest.mark.parametrize("mode", ["f32", "x1", "x3", "x6", "x10"])
+def test_fock_terms_reduced_precision(mode):
+    """Both Fock terms in one call (nof_fock_terms: F = F2 - F1) on FP32 b
+    against the oracle on the same FP32 values.  F32 and the element-wise
+    split forms take the Coulomb-type term into the exchange-type product's
+    right operand (each b_rs W_Ps then rounded once in that product's
+    arithmetic); x10 takes F1 from the FP64 pass over b.  Bounds, relative to
+    the larger of max|F1| and max|F2|: the forms' normwise bounds above (f32:
+    the FP32 form's 2e-6, x10: 3e-7)."""
+    nof = need_gpu()
+    prec = {"f32": nof.P_F32, "x1": nof.P_BF16X1, "x3": nof.P_BF16X3, "x6": nof.P_BF16X6,
+            "x10": nof.P_BF16X10}[mode]
+    tol = {"f32": 2e-6, "x10": 3e-7}.get(mode, BOUNDS.get(mode, (0, 0))[0])
+    nbf, naux, norb, seed = 150, 11, 133, 8
+    print(f"case fock terms {mode} naux={naux} norb={norb}", flush=True)
+    B, C, H, n, cJ, cK = case(nbf, naux, norb, seed)
+    b64 = dfjk.iteration(B, C, H, n, cJ, cK)["b"]
+    b32 = b64.astype(np.float32).astype(np.float64)
+    _, _, F1, F2 = dfjk.gen_fock(b32, n, np.zeros((norb, norb)), cJ, cK)
+    D = np.ascontiguousarray(np.diagonal(b32, axis1=1, axis2=2))
+    F = nof.fock_terms(dev(b32, torch.float32), dev(D), dev(cJ), dev(cK), prec=prec)
+    torch.cuda.synchronize()
+    scale = max(np.max(np.abs(F1)), np.max(np.abs(F2)))
+    err = float(np.max(np.abs(host(F) - (F2 - F1)))) / scale
+    print(mode, "fock terms error", err, flush=True)
+    assert err <= tol, (mode, err)

@@ -53,14 +53,21 @@ def test_transform_jk_fock_energy_fp64(nbf, naux, norb, seed):
     assert abs(float(E) - ref["E"]) <= FP64_TOL * abs(ref["E"])
     F2 = nof.exchange_fock(b, dev(cK))
     assert normwise(host(F2), ref["F2"]) <= FP64_TOL
-    # the same build as its three steps (Coulomb-type pass with K, exchange-type
-    # term, lambda and g): identical to the fused call bit for bit
+    # the same build as its steps (both Fock terms in one contraction, then
+    # lambda and g): identical to the fused call bit for bit
+    F = nof.fock_terms(b, D, dev(cJ), dev(cK))
+    lam3, g3 = nof.lambda_grad(dev(n), h, None, F)
+    torch.cuda.synchronize()
+    assert normwise(host(F), ref["F2"] - ref["F1"]) <= FP64_TOL
+    assert np.array_equal(host(lam3), host(lam)) and np.array_equal(host(g3), host(g))
+    # the Coulomb-type term alone (HBM pass with K) with the exchange-type term
+    # alone give the same lambda and g
     F1, K3 = nof.coulomb_fock(b, D, dev(cJ))
-    lam3, g3 = nof.lambda_grad(dev(n), h, F1, F2)
+    lam4, g4 = nof.lambda_grad(dev(n), h, F1, F2)
     torch.cuda.synchronize()
     assert normwise(host(F1), ref["F1"]) <= FP64_TOL
     assert np.array_equal(host(K3), host(K2))
-    assert np.array_equal(host(lam3), host(lam)) and np.array_equal(host(g3), host(g))
+    assert normwise(host(lam4), ref["lam"]) <= FP64_TOL and normwise(host(g4), ref["g"]) <= FP64_TOL
 
 
 def test_structured_coefficients_hf_closed_form():
@@ -147,8 +154,12 @@ PASS_SHAPES = [(1, 1), (2, 3), (17, 5), (33, 127), (40, 130), (64, 257), (300, 6
 def test_k_and_coulomb_pass_shapes(naux, norb, dt):
     """The pass over the unique half of b (K and the Coulomb-type term F1) on
     degenerate, odd (unaligned pairs) and ragged shapes, FP64 and FP32 b, fed
-    directly with symmetric slabs: K = sum_P b^2 and lambda = n h + F1 (cK = 0,
-    so F2 = 0) against the oracle on the same values, FP64 accumulation: 1e-13."""
+    directly with symmetric slabs: K = sum_P b^2 and F1 against the oracle on
+    the same values, FP64 accumulation: 1e-13.  With cK = 0 lambda = n h + F1,
+    where nof_gen_fock forms F1 inside the exchange-type product: 1e-13 in
+    FP64; with FP32 b that product runs in FP32 (W rounded to FP32, each
+    product b_rs W_Ps rounded once, slab partials added in FP64), so the
+    bound is 2 * 2^-24 * max_rs sum_P |b_rs W_Ps| beside 1e-13 of max|lambda|."""
     nof = need_gpu()
     print(f"case pass naux={naux} norb={norb} {dt}", flush=True)
     rng = np.random.default_rng(naux * 1000 + norb)
@@ -166,9 +177,17 @@ def test_k_and_coulomb_pass_shapes(naux, norb, dt):
     bd = dev(b, tdt)
     _, K = nof.jk_diag(bd, dev(D), want_J=False)
     lam, g, K2 = nof.gen_fock(bd, dev(D), dev(n), dev(h), dev(cJ), dev(cK), want_K=True, prec=prec)
+    F1, K3 = nof.coulomb_fock(bd, dev(D), dev(cJ))
     torch.cuda.synchronize()
     Kref = np.einsum("Ppq,Ppq->pq", b, b)
-    lam_ref, _, _, _ = dfjk.gen_fock(b, n, h, cJ, cK)
+    lam_ref, _, F1_ref, _ = dfjk.gen_fock(b, n, h, cJ, cK)
     assert normwise(host(K), Kref) <= 1e-13
-    assert np.array_equal(host(K), host(K2))
-    assert normwise(host(lam), lam_ref) <= 1e-13
+    assert np.array_equal(host(K), host(K2)) and np.array_equal(host(K), host(K3))
+    assert normwise(host(F1), F1_ref) <= 1e-13
+    if dt == "f64":
+        assert normwise(host(lam), lam_ref) <= 1e-13
+    else:
+        W = D @ cJ
+        mag = np.max(np.einsum("Prs,Ps->rs", np.abs(b), np.abs(W)))
+        err = np.max(np.abs(host(lam) - lam_ref))
+        assert err <= 2 * 2.0 ** -24 * mag + 1e-13 * np.max(np.abs(lam_ref)), (err, mag)

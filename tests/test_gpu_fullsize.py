@@ -80,8 +80,9 @@ def test_c500_full_iteration_all_forms():
 
 def bench_step(nof, B, C, H, n, cJ, cK, prec, dt):
     """One iteration in bench.py's call sequence: the stages (one
-    nof_mo_transform call for x10), h, J, the Coulomb-type pass with K, the
-    exchange-type term, lambda and g, E."""
+    nof_mo_transform call for x10), h, J; then K alone and both Fock terms in
+    one contraction (FP64), or K with the Coulomb-type term in one pass and
+    the exchange-type term (x10); lambda and g, E."""
     naux, nbf, _ = B.shape
     norb = C.shape[1]
     b = torch.empty((naux, norb, norb), dtype=dt, device="cuda")
@@ -94,10 +95,15 @@ def bench_step(nof, B, C, H, n, cJ, cK, prec, dt):
         nof.transform_stage2(T, C, b, D, prec=prec)
         del T
     h = nof.one_electron(H, C)
-    J, _ = nof.jk_diag(b, D, want_K=False)
-    F1, K = nof.coulomb_fock(b, D, cJ)
-    F2 = nof.exchange_fock(b, cK, prec=prec)
-    lam, g = nof.lambda_grad(n, h, F1, F2)
+    if prec == nof.P_BF16X10:
+        J, _ = nof.jk_diag(b, D, want_K=False)
+        F1, K = nof.coulomb_fock(b, D, cJ)
+        F2 = nof.exchange_fock(b, cK, prec=prec)
+        lam, g = nof.lambda_grad(n, h, F1, F2)
+    else:
+        J, K = nof.jk_diag(b, D)
+        F = nof.fock_terms(b, D, cJ, cK, prec=prec)
+        lam, g = nof.lambda_grad(n, h, None, F)
     E = nof.energy(n, h, J, K, cJ, cK)
     torch.cuda.synchronize()
     del b, D
