@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="chain1000")
-    ap.add_argument("--forms", default="bf16x10,bf16x10f32,f32,bf16B",
+    ap.add_argument("--forms", default="i8x10,bf16x10,bf16x10f32,f32,bf16B",
                     help="comma list of extra forms: f32, bf16x1, bf16x3, bf16x6, bf16x10 (B split "
                          "once into fixed-point planes from FP64), bf16x10f32 (FP32 B split in the "
                          "loader), i8x10 (B split once into INT8 fixed-point planes from FP64), "
