@@ -205,10 +205,13 @@ __global__ void k_split_rows(const T* __restrict__ A, long long nrow, int K, int
 }
 
 // LDS rows hold the 32 k of one stage as four 16-byte chunks, chunk c of row
-// r at position c ^ ((r >> 2) & 3): the 16 rows of a fragment read (one
-// chunk each) and the 4 x 4 chunks written by 16 loader lanes both fall on
-// distinct banks.  Element offset of chunk c in row r:
-__device__ __forceinline__ int swz(int r, int c) { return (c ^ ((r >> 2) & 3)) << 3; }
+// r at position c ^ f(r), f(r) = ((r >> 2) & 3) ^ (r & 2): a fragment read
+// (16 consecutive rows, one chunk each) falls on 16 distinct 16-byte slots of
+// every 256 bytes and on 8 distinct slots of every 128 bytes for any 8
+// consecutive rows, and loader lanes write whole rows, so there are no bank
+// conflicts whether the banks span 128 or 256 bytes.  Element offset of
+// chunk c in row r:
+__device__ __forceinline__ int swz(int r, int c) { return (c ^ (((r >> 2) & 3) ^ (r & 2))) << 3; }
 
 // Linear tile index -> (tm, tn); sym: the tiles with tm <= tn.
 __device__ __forceinline__ void tile_of(int t, int tiles_n, bool sym, int& tm, int& tn) {

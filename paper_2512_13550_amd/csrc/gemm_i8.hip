@@ -178,52 +178,71 @@ __global__ void k_cmax_exps_i8(const unsigned* __restrict__ cmax, long long batc
 }
 
 // Planes of the columns of the k-major FP32 T_b[K][N] (batch stride sT) on
-// the grids e[b*N + n]: out[q][b][n][ldk].  Block: 64 columns (lanes along n,
-// coalesced reads) x 4 chunks of 16 k; each thread splits 16 consecutive k of
-// its column into one 16-byte store per plane.  Consecutive blocks take
-// consecutive k ranges of the same columns, so the partial lines they write
-// meet in the L2.
+// the grids e[b*N + n]: out[q][b][n][ldk].  Block: 64 columns x 128 k.  The
+// split runs with lanes along n (coalesced reads of T's rows), 32 k per
+// thread, into an LDS tile [q][n][k]; the tile is then written with lanes
+// along k, so a wave stores eight whole 128-byte rows.
+constexpr int TS_N = 64, TS_K = 128, TS_ROW = TS_K + 16;   // LDS row: 144 bytes (no conflicts)
 __global__ void k_split_T_i8(const float* __restrict__ T, long long batch, int K, int N, long long sT,
                              int ldk, const int* __restrict__ e, unsigned char* __restrict__ out) {
-  const int nkb = ldk / IK;
-  const int ncb = (N + 63) / 64;
+  __shared__ __attribute__((aligned(16))) unsigned char L[4][TS_N][TS_ROW];
+  const int nkb = (ldk + TS_K - 1) / TS_K;
+  const int ncb = (N + TS_N - 1) / TS_N;
   const long long blocks = batch * ncb * nkb;
   const long long plane = batch * (long long)N * ldk;
-  const int nl = threadIdx.x & 63, kc = threadIdx.x >> 6;
+  const int t = threadIdx.x;
+  const int nl = t & 63, kc = t >> 6;
   for (long long blk = blockIdx.x; blk < blocks; blk += gridDim.x) {
     const int kb = (int)(blk % nkb);
     const long long r = blk / nkb;
     const int cb = (int)(r % ncb);
     const long long b = r / ncb;
-    const int n = cb * 64 + nl;
-    if (n >= N) continue;
-    const int k0 = kb * IK + 16 * kc;
-    const int E = e[b * N + n];
-    const float* t = T + b * sT + n;
-    unsigned p[4][4];
+    const int n0 = cb * TS_N, k0 = kb * TS_K;
+    // split: column n0 + nl, k = k0 + 32 kc .. + 32
+    {
+      const int n = min(n0 + nl, N - 1);
+      const int E = e[b * N + n];
+      const float* tp = T + b * sT + n;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      unsigned pw[4] = {0u, 0u, 0u, 0u};
+      for (int h = 0; h < 2; ++h) {
+        unsigned p[4][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = k0 + 4 * w + i;
-        split_i8f(k < K ? t[(long long)k * N] : 0.f, E, pw, i);
+        for (int w = 0; w < 4; ++w) {
+          unsigned pw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = k0 + 32 * kc + 16 * h + 4 * w + i;
+            split_i8f(k < K ? tp[(long long)k * N] : 0.f, E, pw, i);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) p[q][w] = pw[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *(i4v*)&L[q][nl][32 * kc + 16 * h] = i4v{(int)p[q][0], (int)p[q][1], (int)p[q][2], (int)p[q][3]};
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) p[q][w] = pw[q];
     }
-    unsigned char* o = out + (b * N + n) * (long long)ldk + k0;
+    __syncthreads();
+    // store: chunk c of row (q, nr), 16 bytes; eight lanes per 128-byte row
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *(i4v*)(o + q * plane) = i4v{(int)p[q][0], (int)p[q][1], (int)p[q][2], (int)p[q][3]};
+    for (int j = 0; j < 8; ++j) {
+      const int idx = t + 256 * j;
+      const int c = idx & 7, nr = (idx >> 3) & 63, q = idx >> 9;
+      const int k = k0 + 16 * c;
+      if (n0 + nr < N && k < ldk)
+        *(i4v*)(out + q * plane + (b * N + n0 + nr) * (long long)ldk + k) = *(const i4v*)&L[q][nr][16 * c];
+    }
+    __syncthreads();
   }
 }
 
-// Byte offset of 16-byte chunk c in LDS row r: chunk c of row r sits at
-// position c ^ ((r >> 2) & 3), so the 16 rows of a fragment read (one chunk
-// each) and the chunks written by neighbouring loader lanes spread over the
-// banks.
-__device__ __forceinline__ int swz16(int r, int c) { return (c ^ ((r >> 2) & 3)) << 4; }
+// Byte offset of 16-byte chunk c in LDS row r (64-byte rows): chunk c sits
+// at position c ^ f(r), f(r) = ((r >> 2) & 3) ^ (r & 2).  A fragment read
+// (16 consecutive rows, one chunk each) then falls on 16 distinct 16-byte
+// slots of every 256 bytes and on 8 distinct slots of every 128 bytes for
+// any 8 consecutive rows, and the loader lanes (four per row) write whole
+// 64-byte rows: no bank conflicts whether the banks span 128 or 256 bytes.
+__device__ __forceinline__ int swz16(int r, int c) { return (c ^ (((r >> 2) & 3) ^ (r & 2))) << 4; }
 
 __device__ __forceinline__ void tile_of(int t, int tiles_n, bool sym, int& tm, int& tn) {
   if (!sym) {
@@ -252,11 +271,14 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
   const int m0 = tm * IT, n0 = tn * IT;
   const int nstage = (d.K + IK - 1) / IK;
 
-  // loader: thread owns row c of both tiles and the 16-byte chunk kq of it
+  // loader: thread owns row c of both tiles and the 16-byte chunk kq of it;
+  // rows past the edge load the last row (in bounds, unconditional) and only
+  // feed outputs that are never written
   const int c = tid >> 2, kq = tid & 3;
-  const bool xok = m0 + c < d.M, yok = n0 + c < d.N;
-  const unsigned char* __restrict__ xrow = d.X + bb * d.sx + (long long)(m0 + c) * d.ldx + 16 * kq;
-  const unsigned char* __restrict__ yrow = d.Y + bb * d.sy + (long long)(n0 + c) * d.ldy + 16 * kq;
+  const unsigned char* __restrict__ xrow =
+      d.X + bb * d.sx + (long long)min(m0 + c, d.M - 1) * d.ldx + 16 * kq;
+  const unsigned char* __restrict__ yrow =
+      d.Y + bb * d.sy + (long long)min(n0 + c, d.N - 1) * d.ldy + 16 * kq;
 
   struct Raw {
     i4v x[4], y[4];
@@ -265,8 +287,8 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
     const long long k0 = (long long)s * IK;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      R.x[q] = xok ? *(const i4v*)(xrow + q * d.psx + k0) : i4v{0, 0, 0, 0};
-      R.y[q] = yok ? *(const i4v*)(yrow + q * d.psy + k0) : i4v{0, 0, 0, 0};
+      R.x[q] = *(const i4v*)(xrow + q * d.psx + k0);
+      R.y[q] = *(const i4v*)(yrow + q * d.psy + k0);
     }
   };
   auto store = [&](const Raw& R, int buf) {
@@ -445,7 +467,7 @@ int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipS
 int i8_split_T(const float* T, int batch, int K, int N, long long sT, int ldk, const int* e, void* planes,
                hipStream_t st) {
   if (batch <= 0 || K <= 0 || N <= 0 || ldk < K || ldk % IK) return NOF_E_DIM;
-  const long long blocks = (long long)batch * ((N + 63) / 64) * (ldk / IK);
+  const long long blocks = (long long)batch * ((N + 63) / 64) * ((ldk + 127) / 128);
   const unsigned g = (unsigned)(blocks < 1 ? 1 : (blocks > (1 << 20) ? (1 << 20) : blocks));
   hipLaunchKernelGGL(k_split_T_i8, dim3(g), dim3(256), 0, st, T, (long long)batch, K, N, sT, ldk, e,
                      (unsigned char*)planes);
