@@ -314,25 +314,25 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) b[j][q] = *(const i4v*)&Ys[buf][q][wn * 32 + j * 16 + (l & 15)][kl];
+    // one piece of the row fragment at a time (piece px meets pieces
+    // py <= 3 - px of the columns); consecutive instructions go to
+    // different accumulators
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      i4v a[4];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = *(const i4v*)&Xs[buf][q][wm * 64 + i * 16 + (l & 15)][kl];
-      // consecutive instructions go to different accumulators
-#pragma unroll
-      for (int px = 0; px < 4; ++px)
+      for (int px = 0; px < 4; ++px) {
+        const i4v a = *(const i4v*)&Xs[buf][px][wm * 64 + i * 16 + (l & 15)][kl];
 #pragma unroll
         for (int py = 0; py + px < 4; ++py)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[px + py][i][j] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(a[px], b[j][py], acc[px + py][i][j], 0, 0, 0);
-    }
+            acc[px + py][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[j][py], acc[px + py][i][j], 0, 0, 0);
+      }
   };
 
   // two LDS buffers, one barrier per stage; stage s + 1 is loaded while
-  // stage s is multiplied and stored into the other buffer afterwards
+  // stage s is multiplied and stored into the other buffer afterwards (a
+  // second stage in flight does not fit beside the four accumulators)
   Raw r0;
   if (nstage > 0) {
     load(0, r0);

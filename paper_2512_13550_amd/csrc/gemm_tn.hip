@@ -175,9 +175,14 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
       if (HAS_S) sr[HAS_S ? j : 0] = ok ? (TS)S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : (TS)0;
     }
     if (HAS_S) {
-      wk = n0 + cy_t - k0;
-      wdiag = Wg && yn_ok && wk >= 0 && wk < KT && (wk - ky_t) % RY == 0;
-      if (wdiag) wv = (TS)Wg[(long long)bb * d.ldw + n0 + cy_t];
+      // only stages whose rows [k0, k0 + KT) meet the tile's columns (a
+      // workgroup-uniform test) hold diagonal elements
+      wdiag = false;
+      if (Wg && k0 < n0 + BNt && n0 < k0 + KT) {
+        wk = n0 + cy_t - k0;
+        wdiag = yn_ok && wk >= 0 && wk < KT && (wk - ky_t) % RY == 0;
+        if (wdiag) wv = (TS)Wg[(long long)bb * d.ldw + n0 + cy_t];
+      }
     }
   };
   auto store = [&](int buf) {
