@@ -472,7 +472,9 @@ def run_batched(nof, inputs, dev, steps=5, solve=True):
 
     out = {}
     Bx = nof.SplitB(B64)
-    for name, Bp, prec in (("x10", Bx, None), ("f32", None, nof.P_F32), ("f64", B64, None)):
+    Bi = nof.SplitBI8(B64)
+    for name, Bp, prec in (("x10", Bx, None), ("i8x10", Bi, None), ("f32", None, nof.P_F32),
+                           ("f64", B64, None)):
         if name == "f32":
             Bp = B64.to(torch.float32)
         pl = nof.BatchPlan(Bp, Cd, Hd, nd, cJd, cKd, prec=prec) if prec is not None else \
@@ -483,6 +485,9 @@ def run_batched(nof, inputs, dev, steps=5, solve=True):
             del Bp
         torch.cuda.empty_cache()
     ms_x10, Ex10, cfg = out["x10"]
+    ms_i8, Ei8, _ = out["i8x10"]
+    del Bi
+    torch.cuda.empty_cache()
     ms_32, E32, _ = out["f32"]
     ms_64, E64, _ = out["f64"]
     # the same work as 25 separate single-instance x10 iterations
@@ -514,6 +519,8 @@ def run_batched(nof, inputs, dev, steps=5, solve=True):
            "tuned_config": {"tile_stage1": cfg[0], "tile_stage2": cfg[1], "tile_exchange": cfg[2],
                             "exchange_p_split": cfg[3]},
            "max_abs_dE_Eh_vs_f64": float((Ex10 - E64).abs().max()),
+           "i8x10": {"ms_per_iteration_batched_graph": ms_i8, "tflops": f / (ms_i8 * 1e-3) / 1e12,
+                     "max_abs_dE_Eh_vs_f64": float((Ei8 - E64).abs().max())},
            "f32": {"ms_per_iteration_batched_graph": ms_32, "tflops": f / (ms_32 * 1e-3) / 1e12,
                    "max_abs_dE_Eh_vs_f64": float((E32 - E64).abs().max())},
            "f64": {"ms_per_iteration_batched_graph": ms_64, "tflops": f / (ms_64 * 1e-3) / 1e12}}
@@ -561,6 +568,10 @@ def run_batched_solve(nof, Bx, B64, Cd, Hd, w, dev, stream, outer=2, steps=10, o
     ms_s = (time.perf_counter() - t0) * 1e3
     del plan
     torch.cuda.empty_cache()
+    # the two runs take the same steps in exact arithmetic; their roundings
+    # differ (packed first stage, one launch for all ON steps), and the ON line
+    # searches can turn such differences into different discrete choices
+    dEs = [abs(a["E"] - b_["E"]) for a, b_ in zip(res, single)]
     return {"outer": outer, "no_steps_per_outer": steps, "on_maxit": on_maxit, "map": "softmax",
             "roles": "aufbau at the shared start orbitals", "form": "x10",
             "ms_batched": ms_b, "ms_25_single": ms_s, "speedup": ms_s / ms_b,
@@ -568,7 +579,9 @@ def run_batched_solve(nof, Bx, B64, Cd, Hd, w, dev, stream, outer=2, steps=10, o
             "on_unconverged_calls": int(sum(r["on_unconverged"] for r in res)),
             "on_iters_per_call_mean": float(np.mean([r["on_iters"] for r in res])) / outer,
             "on_iters_per_call_max_instance": float(max(r["on_iters"] for r in res)) / outer,
-            "max_abs_dE_Eh_batched_vs_single": float(max(abs(a["E"] - b_["E"]) for a, b_ in zip(res, single)))}
+            "max_abs_dE_Eh_batched_vs_single": float(max(dEs)),
+            "median_abs_dE_Eh_batched_vs_single": float(np.median(dEs)),
+            "instances_dE_above_1e-6": int(sum(x > 1e-6 for x in dEs))}
 
 
 def run_warmstart(nof, ntrain, nheld=20):

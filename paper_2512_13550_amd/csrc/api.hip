@@ -228,7 +228,6 @@ size_t fx_cmax_bytes(int naux, int nbf, int norb) {
 
 // INT8 fixed-point transform.  B as written by nof_split_B_i8: planes
 // [4][naux*nbf][ldk] and, after them, one grid exponent per row (P, mu).
-size_t i8_planes_bytes(long long rows, int K) { return align256((size_t)4 * rows * i8_ldk(K)); }
 
 // Scratch after T: C planes and exponents, the stage-1 column maxima of T,
 // the grid exponents of T's columns and T's planes.

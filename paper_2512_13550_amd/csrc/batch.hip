@@ -26,7 +26,9 @@ namespace nof {
 // Regions of a plan's workspace (byte offsets in nof_plan_s::off).
 enum PlanRegion : int {
   O_CALL = 0, O_T, O_B, O_D, O_TH, O_H, O_J, O_K, O_W, O_KP, O_F1P, O_F2P, O_F1, O_F2, O_EP,
-  O_CPL, O_CMX, O_EY, O_ST, O_N      // the last four: the fixed-point (x10) form only
+  O_CPL, O_CMX, O_EY, O_ST,          // the fixed-point forms only
+  O_TPL,                             // the INT8 form only: T as planes
+  O_N
 };
 }  // namespace nof
 
@@ -44,6 +46,10 @@ struct nof_plan_s {
 
 namespace nof {
 namespace {
+
+// The fixed-point forms (BF16 or INT8 pieces) share b in FP32, the x10
+// exchange-type product and the Coulomb-type term from the pass.
+bool fixed_point_plan(const nof_plan_s* p) { return p->prec == NOF_P_BF16X10 || p->prec == NOF_P_I8X10; }
 
 void plan_layout(nof_plan_s* p) {
   const size_t ni = p->ninst, na = p->naux, nb = p->nbf, no = p->norb;
@@ -64,20 +70,23 @@ void plan_layout(nof_plan_s* p) {
   // F64 / F32: the Coulomb-type term is folded into the exchange-type
   // product (O_F2 holds F2 - F1), so its partials and sum take no space; the
   // x10 exchange-type product does not take it (F1 from the pass with K)
-  const bool fx1 = p->prec == NOF_P_BF16X10;
+  const bool fx1 = fixed_point_plan(p);
   sz[O_F1P] = fx1 ? ni * p->kchunks * n2 : 0;
   sz[O_F2P] = (size_t)f2groups * n2;
   sz[O_F1] = fx1 ? ni * n2 : 0;
   sz[O_F2] = ni * n2;
   sz[O_EP] = energy_ws((int)ni);
-  // x10: planes of the packed C, column maxima of T per row tile, the grid
-  // exponents of T's columns, every instance's cK transposed in FP32
-  const bool fx = p->prec == NOF_P_BF16X10;
+  // fixed-point forms: planes of the packed C (INT8: and their exponents),
+  // column maxima of T per row tile, the grid exponents of T's columns,
+  // every instance's cK transposed in FP32; INT8: T as planes
+  const bool fx = fixed_point_plan(p);
+  const bool i8 = p->prec == NOF_P_I8X10;
   const size_t ldk = (size_t)presplit_ldk(p->nbf), ldc = ni * no;
-  sz[O_CPL] = fx ? 4 * ldc * ldk * 2 : 0;
+  sz[O_CPL] = !fx ? 0 : i8 ? i8_planes_bytes((long long)ldc, p->nbf) + ldc * 4 : 4 * ldc * ldk * 2;
   sz[O_CMX] = fx ? na * (size_t)fx_tiles(p->nbf) * ldc * 4 : 0;
   sz[O_EY] = fx ? na * ldc * 4 : 0;
   sz[O_ST] = fx ? ni * no * no * 4 : 0;
+  sz[O_TPL] = i8 ? i8_planes_bytes((long long)na * ldc, p->nbf) : 0;
   size_t o = 0;
   for (int i = 0; i < O_N; ++i) {
     p->off[i] = o;
@@ -109,6 +118,31 @@ struct Args {
 // Stage kernels of one iteration.  Each returns a status.
 int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long ldc = (long long)p->ninst * p->norb;
+  if (p->prec == NOF_P_I8X10) {
+    // B as INT8 planes with row exponents; the packed C split once into
+    // INT8 planes of its ninst*norb columns; T's column maxima from the
+    // epilogue give its grids, then T is split into planes of its columns
+    const long long ldk = i8_ldk(p->nbf);
+    unsigned char* cpl = (unsigned char*)(a.ws + p->off[O_CPL]);
+    int* ce = (int*)(cpl + i8_planes_bytes(ldc, p->nbf));
+    int rc = i8_split_cols((const double*)(a.ws + p->off[O_CALL]), p->nbf, (int)ldc, (int)ldc, (int)ldk,
+                           cpl, ce, st);
+    if (rc != NOF_OK) return rc;
+    const unsigned char* Bp = (const unsigned char*)a.B;
+    I8Desc f{};
+    f.M = p->nbf; f.N = (int)ldc; f.K = p->nbf; f.batch = p->naux;
+    f.X = Bp; f.ldx = ldk; f.sx = (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
+    f.ex = (const int*)(Bp + i8_planes_bytes((long long)p->naux * p->nbf, p->nbf)); f.sex = p->nbf;
+    f.Y = cpl; f.ldy = ldk; f.sy = 0; f.psy = ldc * ldk; f.ey = ce; f.sey = 0;
+    f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = (long long)p->nbf * ldc;
+    f.sym = false; f.role = 1;
+    f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)fx_tiles(p->nbf) * ldc;
+    if ((rc = gemm_i8(f, st)) != NOF_OK) return rc;
+    int* te = (int*)(a.ws + p->off[O_EY]);
+    if ((rc = i8_cmax_exps(f.cmax, p->naux, fx_tiles(p->nbf), (int)ldc, te, st)) != NOF_OK) return rc;
+    return i8_split_T(f.Out, p->naux, p->nbf, (int)ldc, (long long)p->nbf * ldc, (int)ldk, te,
+                      a.ws + p->off[O_TPL], st);
+  }
   if (p->prec == NOF_P_BF16X10) {
     // B as fixed-point planes [4][naux][nbf][ldk]; the packed C split once
     // into planes of its ninst*norb columns; the epilogue's column maxima of
@@ -142,6 +176,24 @@ int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
 int run_stage2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long ldc = (long long)p->ninst * p->norb;
   const long long n2 = (long long)p->norb * p->norb;
+  if (p->prec == NOF_P_I8X10) {
+    // instance i (outer index): its C planes are rows i*norb.. of the packed
+    // planes, its T^P planes rows P*ldc + i*norb.., with their exponents
+    const long long ldk = i8_ldk(p->nbf);
+    const unsigned char* cpl = (const unsigned char*)(a.ws + p->off[O_CPL]);
+    I8Desc f{};
+    f.M = p->norb; f.N = p->norb; f.K = p->nbf;
+    f.batch = p->ninst * p->naux; f.binner = p->naux;
+    f.X = cpl; f.ldx = ldk; f.sx = 0; f.sx2 = (long long)p->norb * ldk; f.psx = ldc * ldk;
+    f.ex = (const int*)(cpl + i8_planes_bytes(ldc, p->nbf)); f.sex = 0; f.sex2 = p->norb;
+    f.Y = (const unsigned char*)(a.ws + p->off[O_TPL]); f.ldy = ldk; f.sy = ldc * ldk;
+    f.sy2 = (long long)p->norb * ldk; f.psy = (long long)p->naux * ldc * ldk;
+    f.ey = (const int*)(a.ws + p->off[O_EY]); f.sey = ldc; f.sey2 = p->norb;
+    f.Out = (float*)(a.ws + p->off[O_B]); f.ldo = p->norb; f.so = n2; f.so2 = (long long)p->naux * n2;
+    f.Dg = (double*)(a.ws + p->off[O_D]); f.sd = p->norb; f.sd2 = (long long)p->naux * p->norb;
+    f.sym = true; f.role = 2;
+    return gemm_i8(f, st);
+  }
   if (p->prec == NOF_P_BF16X10) {
     // instance i (outer index): its C planes are columns i*norb.. of the
     // packed planes, its T^P columns i*norb.. of T, with their grid exponents
@@ -213,7 +265,7 @@ int run_small(nof_plan_s* p, const Args& a, hipStream_t st) {
 // x10 form also the Coulomb-type term F1 (same pass).
 int run_pass(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long n2 = (long long)p->norb * p->norb;
-  const bool fx = p->prec == NOF_P_BF16X10;
+  const bool fx = fixed_point_plan(p);
   double* kp = (double*)(a.ws + p->off[O_KP]);
   double* f1p = fx ? (double*)(a.ws + p->off[O_F1P]) : nullptr;
   int rc = kf1_pass(p->naux, p->norb, a.ws + p->off[O_B], p->bt,
@@ -234,7 +286,7 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const int fold = (p->naux + p->f2gpi - 1) / p->f2gpi;
   const int gpi = (p->naux + fold - 1) / fold;
   double* f2p = (double*)(a.ws + p->off[O_F2P]);
-  if (p->prec == NOF_P_BF16X10) {
+  if (fixed_point_plan(p)) {
     // every instance in one launch (cK_i^T in FP32 for each)
     ExDesc e{p->naux, p->norb, fold, (const float*)(a.ws + p->off[O_B]), nullptr, f2p};
     e.ninst = p->ninst;
@@ -268,7 +320,7 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
 int run_tail(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long n2 = (long long)p->norb * p->norb;
   const double* h = (const double*)(a.ws + p->off[O_H]);
-  const double* F1 = p->prec == NOF_P_BF16X10 ? (const double*)(a.ws + p->off[O_F1]) : nullptr;
+  const double* F1 = fixed_point_plan(p) ? (const double*)(a.ws + p->off[O_F1]) : nullptr;
   int rc = lambda_grad(p->norb, a.n, h, F1, (double*)(a.ws + p->off[O_F2]), a.lam, a.grad, st,
                        p->ninst, p->norb, n2, n2);
   if (rc != NOF_OK) return rc;
@@ -650,8 +702,11 @@ int nof_plan_create(nof_plan* plan, int ninst, int naux, int nbf, int norb, int 
     if (ninst < 1 || ninst > 4096 || naux < 1 || nbf < 1 || norb < 1 || naux > (1 << 20) ||
         nbf > (1 << 16) || norb > (1 << 16))
       return NOF_E_DIM;
-    if (prec != NOF_P_F64 && prec != NOF_P_F32 && prec != NOF_P_BF16X10) return NOF_E_PREC;
-    if (prec == NOF_P_BF16X10 && (long long)ninst * norb > (1 << 20)) return NOF_E_DIM;
+    if (prec != NOF_P_F64 && prec != NOF_P_F32 && prec != NOF_P_BF16X10 && prec != NOF_P_I8X10)
+      return NOF_E_PREC;
+    if ((prec == NOF_P_BF16X10 || prec == NOF_P_I8X10) && (long long)ninst * norb > (1 << 20))
+      return NOF_E_DIM;
+    if (prec == NOF_P_I8X10 && nbf > I8_MAX_K) return NOF_E_DIM;
     nof_plan_s* p = new nof_plan_s();
     p->ninst = ninst; p->naux = naux; p->nbf = nbf; p->norb = norb; p->prec = prec;
     p->bt = prec == NOF_P_F64 ? NOF_F64 : NOF_F32;
@@ -726,8 +781,8 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     int rc = run_iteration(plan, a, stream);        // fills T, b, W with valid data
     if (rc != NOF_OK) return rc;
     const int reps = 3;
-    // the x10 kernels have one tile shape: only the exchange split is tuned
-    const bool fx = plan->prec == NOF_P_BF16X10;
+    // the fixed-point kernels have one tile shape: only the exchange split is tuned
+    const bool fx = fixed_point_plan(plan);
     const int tiles_all[2] = {128, 64};
     const int ntiles = fx ? 1 : 2;
     const int* tiles = tiles_all;

@@ -124,9 +124,15 @@ struct I8Desc {
   bool sym;
   int role;                        // 1 = transform stage 1, 2 = stage 2 (kernel symbol)
   unsigned* cmax; long long scm;
+  // Two-level batching (binner > 0, not with cmax): batch b = outer * binner +
+  // inner; X, ex, Y, ey, Out, Dg at inner * s? + outer * s?2
+  int binner;
+  long long sx2, sex2, sy2, sey2, so2, sd2;
 };
 int gemm_i8(const I8Desc& d, hipStream_t st);
 inline long long i8_ldk(int K) { return ((long long)K + 63) / 64 * 64; }
+// Bytes of the four INT8 planes of rows x K (the grid exponents follow at this offset).
+inline size_t i8_planes_bytes(long long rows, int K) { return align256((size_t)4 * rows * i8_ldk(K)); }
 // INT8 planes [4][nrow][ldk] and grid exponents e[nrow] of the rows of
 // A[nrow][K] (FP64/FP32); of the columns of an FP64 k-major A[k][col]
 // ([4][ncol][ldk], e[ncol]); grid exponents of T_b's columns from the stage-1

@@ -270,15 +270,20 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
   tile_of(logical - bb * ntiles, tiles_n, d.sym, tm, tn);
   const int m0 = tm * IT, n0 = tn * IT;
   const int nstage = (d.K + IK - 1) / IK;
+  long long ob = 0, ib = bb;                  // outer and inner batch index
+  if (d.binner > 0) {
+    ob = bb / d.binner;
+    ib = bb - ob * d.binner;
+  }
 
   // loader: thread owns row c of both tiles and the 16-byte chunk kq of it;
   // rows past the edge load the last row (in bounds, unconditional) and only
   // feed outputs that are never written
   const int c = tid >> 2, kq = tid & 3;
   const unsigned char* __restrict__ xrow =
-      d.X + bb * d.sx + (long long)min(m0 + c, d.M - 1) * d.ldx + 16 * kq;
+      d.X + ib * d.sx + ob * d.sx2 + (long long)min(m0 + c, d.M - 1) * d.ldx + 16 * kq;
   const unsigned char* __restrict__ yrow =
-      d.Y + bb * d.sy + (long long)min(n0 + c, d.N - 1) * d.ldy + 16 * kq;
+      d.Y + ib * d.sy + ob * d.sy2 + (long long)min(n0 + c, d.N - 1) * d.ldy + 16 * kq;
 
   struct Raw {
     i4v x[4], y[4];
@@ -347,9 +352,10 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
     __syncthreads();
   }
 
-  float* __restrict__ Out = d.Out + bb * d.so;
-  const int* __restrict__ ex = d.ex + bb * d.sex;
-  const int* __restrict__ ey = d.ey + bb * d.sey;
+  float* __restrict__ Out = d.Out + ib * d.so + ob * d.so2;
+  double* __restrict__ Dg = d.Dg ? d.Dg + ib * d.sd + ob * d.sd2 : nullptr;
+  const int* __restrict__ ex = d.ex + ib * d.sex + ob * d.sex2;
+  const int* __restrict__ ey = d.ey + ib * d.sey + ob * d.sey2;
   int eyc[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -380,7 +386,7 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
         } else if (gm <= gn) {
           Out[(long long)gm * d.ldo + gn] = fv;
           Out[(long long)gn * d.ldo + gm] = fv;
-          if (gm == gn && d.Dg) d.Dg[bb * d.sd + gm] = v;
+          if (gm == gn && Dg) Dg[gm] = v;
         }
       }
     }
@@ -420,6 +426,7 @@ int gemm_i8(const I8Desc& d, hipStream_t st) {
   if (d.K > I8_MAX_K) return NOF_E_DIM;
   if (!d.X || !d.Y || !d.ex || !d.ey || !d.Out) return NOF_E_NULL;
   if (d.ldx % IK || d.ldy % IK || d.ldx < d.K || d.ldy < d.K) return NOF_E_DIM;
+  if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
   const int tiles_m = (d.M + IT - 1) / IT;
   const int tiles_n = (d.N + IT - 1) / IT;
   const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;

@@ -133,9 +133,9 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
 
   TX xr[PX];
   TY yr[PY];
-  // S values as staged: FP64 for the FP64 product, rounded to FP32 for the
-  // FP32 one (whose staged operand is FP32 anyway)
-  typedef TC TS;
+  // S values kept as loaded (FP64) until the store: converting them at load
+  // time would put a wait for every load ahead of the stage's products
+  typedef double TS;
   TS sr[HAS_S ? PY : 1];
   // Coulomb-type term folded into the exchange-type product: in the stage
   // whose k rows hold this thread's column n = n0 + cy_t (the lane stages row
@@ -172,7 +172,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     for (int j = 0; j < PY; ++j) {
       const bool ok = yn_ok && ky_t + RY * j < klim;
       yr[j] = ok ? py[(long long)(RY * j) * d.ldy] : (TY)0;
-      if (HAS_S) sr[HAS_S ? j : 0] = ok ? (TS)S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : (TS)0;
+      if (HAS_S) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : 0.0;
     }
     if (HAS_S) {
       // only stages whose rows [k0, k0 + KT) meet the tile's columns (a
@@ -181,7 +181,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
       if (Wg && k0 < n0 + BNt && n0 < k0 + KT) {
         wk = n0 + cy_t - k0;
         wdiag = yn_ok && wk >= 0 && wk < KT && (wk - ky_t) % RY == 0;
-        if (wdiag) wv = (TS)Wg[(long long)bb * d.ldw + n0 + cy_t];
+        if (wdiag) wv = Wg[(long long)bb * d.ldw + n0 + cy_t];
       }
     }
   };
@@ -193,12 +193,12 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     }
 #pragma unroll
     for (int j = 0; j < PY; ++j) {
-      if (HAS_S) Ys[buf][ky_t + RY * j][cy_t] = (TC)yr[j] * sr[HAS_S ? j : 0];
+      if (HAS_S) Ys[buf][ky_t + RY * j][cy_t] = (TC)((double)yr[j] * sr[HAS_S ? j : 0]);
       else Ys[buf][ky_t + RY * j][cy_t] = (TC)yr[j];
     }
     // the lane's own diagonal element, written just above (LDS accesses of a
     // wave are ordered)
-    if (HAS_S && wdiag) Ys[buf][wk][cy_t] -= wv;
+    if (HAS_S && wdiag) Ys[buf][wk][cy_t] = (TC)((double)Ys[buf][wk][cy_t] - wv);
   };
 
   if (nstage > 0) {

@@ -541,7 +541,7 @@ class BatchPlan:
     call, so update them in place between iterations)."""
 
     def __init__(self, B, C, H, n, cJ, cK, prec=None):
-        """B: FP64 (P_F64), FP32 (P_F32) or a SplitB (P_BF16X10)."""
+        """B: FP64 (P_F64), FP32 (P_F32), a SplitB (P_BF16X10) or a SplitBI8 (P_I8X10)."""
         self.ninst, nbf, norb = C.shape
         naux = B.shape[0]
         bt = _b_arg(B)[0]

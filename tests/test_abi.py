@@ -211,12 +211,12 @@ def test_orthonormalize_validation():
 
 # ---- host-side bounds check of the batched plans' workspace layouts ----
 PLAN_REGIONS = ["Call", "T", "b", "D", "TH", "h", "J", "K", "W", "Kpart", "F1part", "F2part", "F1", "F2",
-                "Epart", "Cplanes", "Tcolmax", "Texp", "cKT"]
+                "Epart", "Cplanes", "Tcolmax", "Texp", "cKT", "Tplanes"]
 
 
 @pytest.mark.parametrize("ninst,naux,nbf,norb", [(25, 1200, 300, 300), (3, 7, 33, 17), (1, 1, 1, 1),
                                                  (4, 40, 130, 97), (2, 300, 1100, 150)])
-@pytest.mark.parametrize("prec", ["f64", "f32", "x10"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "x10", "i8x10"])
 def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
     """Every region of every plan layout (field300 x10 included) is 256-byte
     aligned, disjoint from the others, ends inside nof_plan_ws, and is at least
@@ -225,7 +225,7 @@ def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
     import ctypes
     nof = _lib()
     L = nof.lib
-    p = {"f64": nof.P_F64, "f32": nof.P_F32, "x10": nof.P_BF16X10}[prec]
+    p = {"f64": nof.P_F64, "f32": nof.P_F32, "x10": nof.P_BF16X10, "i8x10": nof.P_I8X10}[prec]
     plan = ctypes.c_void_p()
     assert L.nof_plan_create(ctypes.byref(plan), ninst, naux, nbf, norb, p) == 0
     try:
@@ -257,7 +257,7 @@ def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
                 "D": ninst * naux * norb * 8, "TH": ninst * nbf * norb * 8, "h": ninst * n2, "J": ninst * n2,
                 "K": ninst * n2, "W": ninst * naux * norb * 8, "Kpart": ninst * n2,
                 "F2part": ninst * gmax * n2, "F2": ninst * n2, "Epart": ninst * 8}
-        if prec == "x10":
+        if prec in ("x10", "i8x10"):
             need.update({"F1part": ninst * n2, "F1": ninst * n2})
         else:
             # the Coulomb-type term rides in the exchange-type product (F2
@@ -267,6 +267,12 @@ def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
             ldk = (nbf + 31) // 32 * 32
             need.update({"Cplanes": 4 * ldc * ldk * 2, "Tcolmax": naux * ((nbf + 127) // 128) * ldc * 4,
                          "Texp": naux * ldc * 4, "cKT": ninst * norb * norb * 4})
+        if prec == "i8x10":
+            ldk8 = (nbf + 63) // 64 * 64
+            need.update({"Cplanes": 4 * ldc * ldk8 + ldc * 4, "Tcolmax": naux * ((nbf + 127) // 128) * ldc * 4,
+                         "Texp": naux * ldc * 4, "cKT": ninst * norb * norb * 4, "Tplanes": 4 * naux * ldc * ldk8})
+        else:
+            assert size[PLAN_REGIONS.index("Tplanes")] == 0
         for name, o, sz in regions:
             assert sz >= need.get(name, 0), (name, sz, need.get(name))
     finally:

@@ -95,7 +95,39 @@ def test_batch_x10_matches_single_instance(src):
     assert normwise(host(lam[1]), o["lam"]) <= 3e-7
 
 
-@pytest.mark.parametrize("prec_name", ["f64", "f32", "x10"])
+def test_batch_i8x10_matches_single_instance():
+    """The INT8 fixed-point plan: B as INT8 planes, the packed C split once,
+    T split into planes of its columns, stage 2 and the exchange-type term
+    instance by instance.  The INT8 sums are exact and every instance gets the
+    same grids as alone, so b is bit-identical to the single-instance INT8
+    path; lambda differs only in the grouping of FP64 partial sums (1e-12),
+    for several exchange splits and after the autotuner; one instance
+    against the oracle."""
+    nof = need_gpu()
+    print("case batched i8x10", flush=True)
+    ninst, nbf, naux, norb = 5, 130, 90, 110
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3003, 27)
+    Bs = nof.SplitBI8(dev(B))
+    plan = nof.BatchPlan(Bs, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
+    assert plan.prec == nof.P_I8X10
+    ref = [single(nof, Bs, C[i], H[i], n[i], cJ[i], cK[i], nof.P_I8X10) for i in range(ninst)]
+    for cfg in ([128, 128, 128, 1], [128, 128, 128, 3], None):
+        if cfg is None:
+            plan.autotune()
+        else:
+            plan.config = cfg
+        E, lam, g = plan.iteration()
+        torch.cuda.synchronize()
+        for i in range(ninst):
+            assert abs(float(E[i]) - ref[i][0]) <= 1e-12 * abs(ref[i][0]), (cfg, i)
+            assert normwise(host(lam[i]), ref[i][1]) <= 1e-12, (cfg, i)
+            assert normwise(host(g[i]), ref[i][2]) <= 1e-10, (cfg, i)
+    o = dfjk.iteration(B, C[2], H[2], n[2], cJ[2], cK[2])
+    assert abs(float(E[2]) - o["E"]) <= 2e-8 * abs(o["E"])
+    assert normwise(host(lam[2]), o["lam"]) <= 3e-7
+
+
+@pytest.mark.parametrize("prec_name", ["f64", "f32", "x10", "i8x10"])
 def test_plan_writes_stay_inside_workspace(prec_name):
     """Every region of a plan's workspace lies inside the nof_plan_ws bytes it
     reports: the workspace is a view into a larger buffer whose tail holds a
@@ -107,6 +139,8 @@ def test_plan_writes_stay_inside_workspace(prec_name):
     B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3002, 24)
     if prec_name == "x10":
         Bp = nof.SplitB(dev(B))
+    elif prec_name == "i8x10":
+        Bp = nof.SplitBI8(dev(B))
     else:
         Bp = dev(B, torch.float32 if prec_name == "f32" else torch.float64)
     plan = nof.BatchPlan(Bp, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
