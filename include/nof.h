@@ -84,15 +84,20 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3, NOF_I8X4 
  *                 stored in FP32.  The exchange-type Fock term uses three
  *                 element-wise pieces (six products) instead.
  *   NOF_P_I8X10   the fixed-point split with INT8 pieces on the INT8 matrix
- *                 cores (transform only; nof_mo_transform with B from
- *                 nof_split_B_i8): one grid per row / column, 2^E the
+ *                 cores (nof_mo_transform with B from nof_split_B_i8, and the
+ *                 exchange-type Fock term): one grid per row / column, 2^E the
  *                 smallest power of two with max|x| 2^(7-E) < 127.5,
  *                 x = n_0 2^(E-7) + sum_{q=1..3} n_q 2^(E-7-7q) + r,
  *                 |n_0| <= 127, |n_q| <= 64, |r| <= 2^(E-29); the ten
  *                 products of order <= 3 in four int32 accumulators (one per
  *                 order; exact for contractions shorter than 65536), combined
- *                 exactly in FP64.  T and b stored in FP32; the exchange-type
- *                 term as in NOF_P_BF16X10.
+ *                 exactly in FP64.  T and b stored in FP32.  The exchange-type
+ *                 term sums groups of auxiliary slabs as one INT8 contraction
+ *                 each (as many slabs as keep slabs x 64-padded rows within
+ *                 65536), one grid per row of b^P and of cK o b^P over the
+ *                 group, an FP64 partial per group; its workspace holds those
+ *                 planes (twice the bytes of b in FP32).  The batched plan
+ *                 takes that term as in NOF_P_BF16X10.
  * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
 typedef enum {
   NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4,
@@ -228,7 +233,9 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  *         from one pass over the upper half of b.
  * prec    NOF_P_F64 (bt = NOF_F64), NOF_P_F32 or a split form (bt = NOF_F32)
  *         for the matrix-core contraction (X10: three element-wise BF16
- *         pieces, FP32 accumulation within a slab, FP64 across slabs).
+ *         pieces, FP32 accumulation within a slab, FP64 across slabs; I8X10:
+ *         INT8 fixed-point pieces over groups of slabs, exact int32 sums,
+ *         FP64 across groups).
  * The two sums over P are one contraction (nof_fock_terms): the Coulomb-type
  * sum is the exchange-type one with cK_sq b^P_qs replaced by -W[P][s] on
  * q = s, so it is applied to the right operand as it is staged, at no cost

@@ -47,7 +47,7 @@ JkLayout jk_layout(int naux, int norb, int bt) {
 // chunk partials and F1; then (nof_gen_fock) the K chunk partials.
 struct FockLayout {
   int kchunks, f2fold, f2groups;
-  size_t off_W, off_f2part, off_F, off_St, off_f1part, off_F1, terms, off_kpart, total;
+  size_t off_W, off_f2part, off_F, off_St, off_f1part, off_F1, off_i8, terms, off_kpart, total;
 };
 FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   FockLayout L;
@@ -58,6 +58,7 @@ FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   if (groups > naux) groups = naux;
   if (groups < 1) groups = 1;
   L.f2fold = (naux + groups - 1) / groups;
+  if (prec == NOF_P_I8X10) L.f2fold = i8_exchange_fold(naux, norb);   // exact int32 depth
   L.f2groups = (naux + L.f2fold - 1) / L.f2fold;
   const size_t n2 = (size_t)norb * norb * sizeof(double);
   const bool fx = fixed_point(prec);
@@ -67,7 +68,8 @@ FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   L.off_St = align256(L.off_F + n2);
   L.off_f1part = align256(L.off_St + (size_t)norb * norb * sizeof(float));
   L.off_F1 = align256(L.off_f1part + (fx ? (size_t)L.kchunks * n2 : 0));
-  L.terms = align256(L.off_F1 + (fx ? n2 : 0));
+  L.off_i8 = align256(L.off_F1 + (fx ? n2 : 0));
+  L.terms = align256(L.off_i8 + (prec == NOF_P_I8X10 ? i8_exchange_ws(1, naux, norb) : 0));
   L.off_kpart = L.terms;
   L.total = align256(L.off_kpart + (size_t)L.kchunks * n2);
   return L;
@@ -474,9 +476,16 @@ namespace {
 // F2 (exchange-type term) into F2 from the partials in f2part (groups of
 // L.f2fold slabs); St: norb*norb FP32 scratch of the split forms.
 int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, const double* W,
-                  int prec, const FockLayout& L, double* f2part, float* St, double* F2,
+                  int prec, const FockLayout& L, double* f2part, float* St, char* i8ws, double* F2,
                   hipStream_t stream) {
   const long long n2 = (long long)norb * norb;
+  if (prec == NOF_P_I8X10) {
+    // one INT8 product per group of slabs on cK^T in FP32, FP64 partials
+    if (W) return NOF_E_INTERNAL;
+    NOF_TRY(fx_transpose(cK, norb, 1, St, stream));
+    NOF_TRY(i8_exchange(1, naux, norb, (const float*)b, 0, St, f2part, i8ws, stream));
+    return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
+  }
   if (fixed_point(prec)) {
     if (W) return NOF_E_INTERNAL;               // this product takes no W (fock_terms)
     ExDesc e{naux, norb, L.f2fold, (const float*)b, nullptr, f2part};
@@ -524,7 +533,7 @@ int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const
   NOF_TRY(coulomb_weights(naux, norb, D, cJ, W, stream));
   if (!fixed_point(prec))
     return exchange_term(naux, norb, b, bt, cK, W, prec, L, (double*)(w + L.off_f2part),
-                         (float*)(w + L.off_St), F, stream);
+                         (float*)(w + L.off_St), w + L.off_i8, F, stream);
   const long long n2 = (long long)norb * norb;
   double* f1part = (double*)(w + L.off_f1part);
   double* F1 = (double*)(w + L.off_F1);
@@ -532,7 +541,7 @@ int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const
   NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
   if (Kpart) NOF_TRY(reduce_parts(Kpart, L.kchunks, n2, norb, true, K, stream));
   NOF_TRY(exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, (double*)(w + L.off_f2part),
-                        (float*)(w + L.off_St), F, stream));
+                        (float*)(w + L.off_St), w + L.off_i8, F, stream));
   return subtract(n2, F1, F, stream);
 }
 
@@ -545,7 +554,8 @@ size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
   if (!prec_matches(prec, bt)) return 0;
   const FockLayout L = fock_layout(naux, norb, bt, prec);
   return align256((size_t)L.f2groups * norb * norb * sizeof(double)) +
-         align256((size_t)norb * norb * sizeof(float));
+         align256((size_t)norb * norb * sizeof(float)) +
+         (prec == NOF_P_I8X10 ? i8_exchange_ws(1, naux, norb) : 0);
 }
 
 int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* cK, double* F2,
@@ -561,7 +571,8 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
     char* w = (char*)ws;
     double* part = (double*)w;
     float* St = (float*)(w + align256((size_t)L.f2groups * norb * norb * sizeof(double)));
-    return exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, part, St, F2, stream);
+    char* i8ws = (char*)St + align256((size_t)norb * norb * sizeof(float));
+    return exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, part, St, i8ws, F2, stream);
   });
 }
 

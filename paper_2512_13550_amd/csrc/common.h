@@ -128,8 +128,18 @@ struct I8Desc {
   // inner; X, ex, Y, ey, Out, Dg at inner * s? + outer * s?2
   int binner;
   long long sx2, sex2, sy2, sey2, so2, sd2;
+  double* Out64;                   // if set (not sym, no cmax): FP64 results here instead of Out
 };
 int gemm_i8(const I8Desc& d, hipStream_t st);
+// Exchange-type Fock partials of the INT8 form (gemm_i8.hip):
+//   Out[i][g][r][s] = sum_{P in group g} sum_q b_i^P[q][r] St_i[s][q] b_i^P[q][s]
+// as one INT8 product per group of `fold` slabs (grids per group and row,
+// exact int32 sums over the group, FP64 out).  b FP32 [ninst][naux][norb][norb]
+// (instance stride sb), St FP32 [ninst][norb][norb]; ws of i8_exchange_ws bytes.
+int i8_exchange_fold(int naux, int norb);
+size_t i8_exchange_ws(int ninst, int naux, int norb);
+int i8_exchange(int ninst, int naux, int norb, const float* b, long long sb, const float* St, double* Out,
+                void* ws, hipStream_t st);
 inline long long i8_ldk(int K) { return ((long long)K + 63) / 64 * 64; }
 // Bytes of the four INT8 planes of rows x K (the grid exponents follow at this offset).
 inline size_t i8_planes_bytes(long long rows, int K) { return align256((size_t)4 * rows * i8_ldk(K)); }
@@ -161,6 +171,8 @@ struct ExDesc {
   long long sb = 0, so = 0;
 };
 int exchange_fock_fx(const ExDesc& d, const double* S, float* St, hipStream_t st);
+// St_i[s][q] = (float)S_i[q][s] for ninst matrices n^2 apart.
+int fx_transpose(const double* S, int n, int ninst, float* St, hipStream_t st);
 // Grid exponents (2^E above the largest |value|) of rows of A[nrow][K] (FP64/FP32)
 // and of the columns of A_b[K][N] (FP32, batch stride sa) -> e[b*N + n].
 int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st);

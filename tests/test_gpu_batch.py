@@ -97,12 +97,14 @@ def test_batch_x10_matches_single_instance(src):
 
 def test_batch_i8x10_matches_single_instance():
     """The INT8 fixed-point plan: B as INT8 planes, the packed C split once,
-    T split into planes of its columns, stage 2 and the exchange-type term
-    instance by instance.  The INT8 sums are exact and every instance gets the
-    same grids as alone, so b is bit-identical to the single-instance INT8
-    path; lambda differs only in the grouping of FP64 partial sums (1e-12),
-    for several exchange splits and after the autotuner; one instance
-    against the oracle."""
+    T split into planes of its columns and stage 2 for all instances.  The
+    INT8 sums are exact and every instance gets the same grids as alone, so b
+    is bit-identical to the single-instance INT8 path and E (from J and K)
+    equal to 1e-12.  The plan takes the exchange-type term as the x10 product
+    of the batched fixed-point plans (one launch for every instance), the
+    single-instance INT8 path as INT8 products over groups of slabs: lambda
+    and g agree within the forms' shared bound of 3e-7, for several exchange
+    splits and after the autotuner; one instance against the oracle."""
     nof = need_gpu()
     print("case batched i8x10", flush=True)
     ninst, nbf, naux, norb = 5, 130, 90, 110
@@ -120,8 +122,9 @@ def test_batch_i8x10_matches_single_instance():
         torch.cuda.synchronize()
         for i in range(ninst):
             assert abs(float(E[i]) - ref[i][0]) <= 1e-12 * abs(ref[i][0]), (cfg, i)
-            assert normwise(host(lam[i]), ref[i][1]) <= 1e-12, (cfg, i)
-            assert normwise(host(g[i]), ref[i][2]) <= 1e-10, (cfg, i)
+            assert normwise(host(lam[i]), ref[i][1]) <= 3e-7, (cfg, i)
+            assert normwise(host(g[i]), ref[i][2]) <= 8 * 3e-7 * np.max(np.abs(ref[i][1])) / np.max(np.abs(ref[i][2])), \
+                (cfg, i)
     o = dfjk.iteration(B, C[2], H[2], n[2], cJ[2], cK[2])
     assert abs(float(E[2]) - o["E"]) <= 2e-8 * abs(o["E"])
     assert normwise(host(lam[2]), o["lam"]) <= 3e-7

@@ -243,7 +243,7 @@ def test_split_B_pieces_meet_documented_bounds():
     assert np.all(resid <= np.ldexp(1.0, E - 32)[:, :, None])
 
 
-@pytest.mark.parametrize("mode", ["f32", "x1", "x3", "x6", "x10"])
+@pytest.mark.parametrize("mode", ["f32", "x1", "x3", "x6", "x10", "i8"])
 def test_fock_terms_reduced_precision(mode):
     """Both Fock terms in one call (nof_fock_terms: F = F2 - F1) on FP32 b
     against the oracle on the same FP32 values.  F32 and the element-wise
@@ -254,8 +254,8 @@ def test_fock_terms_reduced_precision(mode):
     the FP32 form's 2e-6, x10: 3e-7)."""
     nof = need_gpu()
     prec = {"f32": nof.P_F32, "x1": nof.P_BF16X1, "x3": nof.P_BF16X3, "x6": nof.P_BF16X6,
-            "x10": nof.P_BF16X10}[mode]
-    tol = {"f32": 2e-6, "x10": 3e-7}.get(mode, BOUNDS.get(mode, (0, 0))[0])
+            "x10": nof.P_BF16X10, "i8": nof.P_I8X10}[mode]
+    tol = {"f32": 2e-6, "x10": 3e-7, "i8": 3e-7}.get(mode, BOUNDS.get(mode, (0, 0))[0])
     nbf, naux, norb, seed = 150, 11, 133, 8
     print(f"case fock terms {mode} naux={naux} norb={norb}", flush=True)
     B, C, H, n, cJ, cK = case(nbf, naux, norb, seed)

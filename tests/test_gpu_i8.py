@@ -144,6 +144,36 @@ def test_i8x10_exact_cancellation():
     assert float(host(D).__abs__().max()) == 0.0
 
 
+@pytest.mark.parametrize("naux,norb,seed", [(600, 256, 11), (450, 300, 12), (5, 70, 13)])
+def test_i8x10_exchange_groups(naux, norb, seed):
+    """The INT8 exchange-type product sums over groups of auxiliary slabs whose
+    joint contraction (slabs x 64-padded rows) stays within the exact int32
+    depth of 65536: norb = 256 gives 256 slabs a group (600 = 256 + 256 + 88),
+    norb = 300 gives 204 (450 = 204 + 204 + 42), norb = 70 one group.  Each
+    row of a group has one grid over all its slabs; a slab far below the
+    others only loses digits below 2^-29 of the row's group maximum, which
+    the normwise bound of 3e-7 (relative to max|F1|, max|F2|) covers."""
+    nof = need_gpu()
+    print(f"case i8x10 exchange groups naux={naux} norb={norb}", flush=True)
+    rng = np.random.default_rng(seed)
+    b = rng.standard_normal((naux, norb, norb))
+    b = 0.5 * (b + b.transpose(0, 2, 1))
+    b[1::7] *= 1e-6                       # slabs far below the others in the same group
+    b32 = b.astype(np.float32).astype(np.float64)
+    n = rng.uniform(0.0, 1.0, norb)
+    cJ = rng.standard_normal((norb, norb))
+    cK = rng.standard_normal((norb, norb))
+    cJ, cK = cJ + cJ.T, cK + cK.T         # the coupling matrices are symmetric
+    _, _, F1, F2 = dfjk.gen_fock(b32, n, np.zeros((norb, norb)), cJ, cK)
+    D = np.ascontiguousarray(np.diagonal(b32, axis1=1, axis2=2))
+    F = nof.fock_terms(dev(b32, torch.float32), dev(D), dev(cJ), dev(cK), prec=nof.P_I8X10)
+    torch.cuda.synchronize()
+    scale = max(np.max(np.abs(F1)), np.max(np.abs(F2)))
+    err = float(np.max(np.abs(host(F) - (F2 - F1)))) / scale
+    print("i8x10 exchange groups error", err, flush=True)
+    assert err <= 3e-7, err
+
+
 def test_i8x10_stage_entry_points_reject():
     """The INT8 form exists as the fused transform only."""
     nof = need_gpu()
