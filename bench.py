@@ -171,11 +171,11 @@ def main():
         # epilogue gives the second its column grids); the others call the
         # stages separately, so that each is timed on its own
         fused = prec in (nof.P_BF16X10, nof.P_I8X10)
-        # F64, F32 and the element-wise split forms fold the Coulomb-type term
-        # into the exchange-type product (the pass over b forms K alone); the
-        # x10 exchange-type product does not take it, so there the pass forms
-        # K and the Coulomb-type term together
-        folded = not fused
+        # F64, F32 and the x1 / x3 split forms fold the Coulomb-type term into
+        # the exchange-type product (the pass over b forms K alone); the x6,
+        # x10 and INT8 exchange-type products do not take it, so there the
+        # pass forms K and the Coulomb-type term together
+        folded = prec not in (nof.P_BF16X6, nof.P_BF16X10, nof.P_I8X10)
         names = (["rotate"] + (["a1_a2_transform"] if fused else ["a1_transform_stage1", "a2_transform_stage2"])
                  + ["h_and_J"]
                  + (["a4_k_pass", "a5_a6_fock_terms"] if folded else ["a4_a5_coulomb_pass", "a6_exchange"])

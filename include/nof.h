@@ -71,7 +71,8 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3, NOF_I8X4 
  *   NOF_P_BF16X3  operands split into BF16 hi+lo, products hi*hi+hi*lo+lo*hi.
  *   NOF_P_BF16X6  operands split into BF16 hi+mid+lo, the six products whose
  *                 combined order of magnitude is at most two splits down;
- *                 every 32-deep stage is added into FP64 accumulators.
+ *                 every 32-deep stage is added into FP64 accumulators.  The
+ *                 exchange-type Fock term is the x10 one below.
  *   NOF_P_BF16X10 fixed-point split (Ozaki-type error-free split on BF16):
  *                 every row of X and column of Y gets one grid over the whole
  *                 contraction, 2^E above its largest magnitude, and four BF16
@@ -232,8 +233,8 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  * K_opt   if not NULL, also receives K (same definition as nof_jk_diag),
  *         from one pass over the upper half of b.
  * prec    NOF_P_F64 (bt = NOF_F64), NOF_P_F32 or a split form (bt = NOF_F32)
- *         for the matrix-core contraction (X10: three element-wise BF16
- *         pieces, FP32 accumulation within a slab, FP64 across slabs; I8X10:
+ *         for the matrix-core contraction (X6 and X10: three element-wise
+ *         BF16 pieces, FP32 accumulation within a slab, FP64 across slabs; I8X10:
  *         INT8 fixed-point pieces over groups of slabs, exact int32 sums,
  *         FP64 across groups).
  * The two sums over P are one contraction (nof_fock_terms): the Coulomb-type

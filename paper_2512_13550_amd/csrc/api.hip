@@ -17,6 +17,10 @@ bool dim_ok(int x) { return x >= 1 && x <= kMaxDim; }
 // The fixed-point forms (BF16 or INT8 pieces): b in FP32, the exchange-type
 // term in three element-wise BF16 pieces, the Coulomb-type term from the pass.
 bool fixed_point(int prec) { return prec == NOF_P_BF16X10 || prec == NOF_P_I8X10; }
+// Forms whose exchange-type product takes no Coulomb-type term: F1 then comes
+// from the pass over b (with K) and is subtracted.  X6 shares the x10
+// exchange-type product (three element-wise BF16 pieces, six products).
+bool f1_from_pass(int prec) { return fixed_point(prec) || prec == NOF_P_BF16X6; }
 
 
 // Workspace of nof_jk_diag: J split partials, K chunk partials.
@@ -61,7 +65,7 @@ FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   if (prec == NOF_P_I8X10) L.f2fold = i8_exchange_fold(naux, norb);   // exact int32 depth
   L.f2groups = (naux + L.f2fold - 1) / L.f2fold;
   const size_t n2 = (size_t)norb * norb * sizeof(double);
-  const bool fx = fixed_point(prec);
+  const bool fx = f1_from_pass(prec);
   L.off_W = 0;
   L.off_f2part = align256((size_t)naux * norb * sizeof(double));
   L.off_F = align256(L.off_f2part + (size_t)L.f2groups * n2);
@@ -486,7 +490,7 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, c
     NOF_TRY(i8_exchange(1, naux, norb, (const float*)b, 0, St, f2part, i8ws, stream));
     return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
   }
-  if (fixed_point(prec)) {
+  if (f1_from_pass(prec)) {
     if (W) return NOF_E_INTERNAL;               // this product takes no W (fock_terms)
     ExDesc e{naux, norb, L.f2fold, (const float*)b, nullptr, f2part};
     NOF_TRY(exchange_fock_fx(e, cK, St, stream));
@@ -523,15 +527,16 @@ int coulomb_weights(int naux, int norb, const double* D, const double* cJ, doubl
 
 // F = F2 - F1 = sum_P sum_q b^P[r][q] (cK[q][s] b^P[q][s] - [q == s] W[P][s]):
 // the Coulomb-type term rides in the exchange-type product's operand loader.
-// The x10 exchange-type product stages element-wise pieces of FP32 values
-// and does not take it: there F1 comes from the pass over the upper half of
-// b (with K when Kpart is given: both from one read of b) and is subtracted.
+// The x6 / x10 exchange-type product stages element-wise pieces of FP32
+// values and the INT8 one fixed-point planes; neither takes it: there F1
+// comes from the pass over the upper half of b (with K when Kpart is given:
+// both from one read of b) and is subtracted.
 int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
                const double* cK, int prec, const FockLayout& L, char* w, double* F,
                double* Kpart, double* K, hipStream_t stream) {
   double* W = (double*)(w + L.off_W);
   NOF_TRY(coulomb_weights(naux, norb, D, cJ, W, stream));
-  if (!fixed_point(prec))
+  if (!f1_from_pass(prec))
     return exchange_term(naux, norb, b, bt, cK, W, prec, L, (double*)(w + L.off_f2part),
                          (float*)(w + L.off_St), w + L.off_i8, F, stream);
   const long long n2 = (long long)norb * norb;
@@ -597,7 +602,7 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D, con
     const long long n2 = (long long)norb * norb;
     double* F = (double*)(w + L.off_F);
     double* kpart = K_opt ? (double*)(w + L.off_kpart) : nullptr;
-    const bool fx = fixed_point(prec);           // K then comes with F1 from one pass
+    const bool fx = f1_from_pass(prec);          // K then comes with F1 from one pass
     NOF_TRY(fock_terms(naux, norb, b, bt, D, cJ, cK, prec, L, w, F, fx ? kpart : nullptr, K_opt,
                        stream));
     if (K_opt && !fx) {

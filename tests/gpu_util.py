@@ -14,7 +14,10 @@ def need_gpu():
 
 
 def dev(x, dtype=torch.float64):
-    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+    a = np.ascontiguousarray(x)
+    if not a.flags.writeable:          # read-only views (broadcasts) are copied
+        a = a.copy()
+    return torch.from_numpy(a).to(device="cuda", dtype=dtype)
 
 
 def host(t):

@@ -246,10 +246,10 @@ def test_split_B_pieces_meet_documented_bounds():
 @pytest.mark.parametrize("mode", ["f32", "x1", "x3", "x6", "x10", "i8"])
 def test_fock_terms_reduced_precision(mode):
     """Both Fock terms in one call (nof_fock_terms: F = F2 - F1) on FP32 b
-    against the oracle on the same FP32 values.  F32 and the element-wise
-    split forms take the Coulomb-type term into the exchange-type product's
-    right operand (each b_rs W_Ps then rounded once in that product's
-    arithmetic); x10 takes F1 from the FP64 pass over b.  Bounds, relative to
+    against the oracle on the same FP32 values.  F32, x1 and x3 take the
+    Coulomb-type term into the exchange-type product's right operand (each
+    b_rs W_Ps then rounded once in that product's arithmetic); x6, x10 and
+    the INT8 form take F1 from the FP64 pass over b.  Bounds, relative to
     the larger of max|F1| and max|F2|: the forms' normwise bounds above (f32:
     the FP32 form's 2e-6, x10: 3e-7)."""
     nof = need_gpu()
