@@ -23,8 +23,9 @@
 // fragments of v_mfma_f32_16x16x32_bf16 (lane l holds 8 consecutive k of row
 // l%16 at k offset 8*(l/16); output row 4*(l/16)+r, column l%16).  K advances
 // 32 per stage.  LDS keeps each piece as [row][k] with k contiguous so a lane
-// fetches its 8 values with one 16-byte read; rows are padded to 40 elements
-// (80 B) so the 16 lanes of a read phase hit distinct banks.
+// fetches its 8 values with one 16-byte read; the four 16-byte chunks of a
+// row are swizzled (see swz) so that reads and stores are free of bank
+// conflicts.
 #include "common.h"
 
 namespace nof {
@@ -35,7 +36,17 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 constexpr int BM = 128;
 constexpr int KT = 32;
 constexpr int NTHR = 256;
-constexpr int LROW = KT + 8;                 // padded LDS row (bf16 elements)
+constexpr int LROW = KT;                     // LDS row: 32 bf16 = four 16-byte chunks
+
+// Chunk c of LDS row r sits at position c ^ f(r), f(r) = (r / 2) mod 4
+// (element offset returned).  ds_read_b128 serves a wave in four passes of 16
+// lanes over 256 bytes of banks (lane quads {0,3,5,6}, {1,2,4,7},
+// {8,11,13,14}, {9,10,12,15}) and ds_write_b128 in eight passes of 8
+// consecutive lanes over 128 bytes (gfx950, measured with the bank-conflict
+// counter): the fragment reads (lane l: row R + l % 16, R a multiple of 16,
+// chunk l / 16) and the loader's stores (lane l: row R + l, one chunk) then
+// put every pass on distinct 16-byte slots.
+__device__ __forceinline__ int swz(int r, int c) { return (c ^ ((r >> 1) & 3)) << 3; }
 constexpr int PER_T = KT * BM / NTHR;        // operand elements per thread per stage (16)
 
 __device__ __forceinline__ int xcd_logical(int w, int G) {
@@ -200,7 +211,7 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
       const int kofs = kg * 16 + half * 8;
       if constexpr (PSX) {
 #pragma unroll
-        for (int q = 0; q < NX; ++q) *(bf8v*)&Xs[buf][q][c_t][kofs] = xp[PSX ? q : 0][half];
+        for (int q = 0; q < NX; ++q) *(bf8v*)&Xs[buf][q][c_t][swz(c_t, kofs >> 3)] = xp[PSX ? q : 0][half];
       } else {
         bf8v px[3];
 #pragma unroll
@@ -211,11 +222,11 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
           for (int q = 0; q < NX; ++q) px[q][e] = p[q];
         }
 #pragma unroll
-        for (int q = 0; q < NX; ++q) *(bf8v*)&Xs[buf][q][c_t][kofs] = px[q];
+        for (int q = 0; q < NX; ++q) *(bf8v*)&Xs[buf][q][c_t][swz(c_t, kofs >> 3)] = px[q];
       }
       if constexpr (PSY) {
 #pragma unroll
-        for (int q = 0; q < NY; ++q) *(bf8v*)&Ys[buf][q][c_t][kofs] = yp[PSY ? q : 0][half];
+        for (int q = 0; q < NY; ++q) *(bf8v*)&Ys[buf][q][c_t][swz(c_t, kofs >> 3)] = yp[PSY ? q : 0][half];
       } else {
         bf8v py[3];
 #pragma unroll
@@ -229,7 +240,7 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
           for (int q = 0; q < NY; ++q) py[q][e] = p[q];
         }
 #pragma unroll
-        for (int q = 0; q < NY; ++q) *(bf8v*)&Ys[buf][q][c_t][kofs] = py[q];
+        for (int q = 0; q < NY; ++q) *(bf8v*)&Ys[buf][q][c_t][swz(c_t, kofs >> 3)] = py[q];
       }
     }
   };
@@ -239,7 +250,7 @@ __device__ __forceinline__ void bf16_body(const GemmDesc& d, int tiles_n, int nt
     store(0);
   }
   __syncthreads();
-  const int kl = 8 * (l >> 4);
+  const int kl = swz(l & 15, l >> 4);      // fragment rows start at multiples of 16
   for (int s = 0; s < nstage; ++s) {
     const int buf = NBUF == 2 ? (s & 1) : 0;
     if (s + 1 < nstage) load(s + 1);

@@ -490,7 +490,8 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
 // b^P is symmetric, so both operands are read along rows (q contiguous); St
 // is S transposed in FP32 (St[s][q]).  Each FP32 operand value is split into
 // three BF16 pieces (x = hi + mid + lo exactly) and the six products of order
-// <= 2 are accumulated in FP32 within one auxiliary slab, then added to FP64.
+// <= 2 are accumulated in FP32 over one stage (32 q of one auxiliary slab),
+// then added to FP64.
 // The term enters lambda and the orbital gradient, not the energy.
 __device__ __forceinline__ void split3(float v, __bf16 (&p)[3]) {
   const __bf16 h = (__bf16)v;
@@ -536,16 +537,20 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   const int nkb = (n + KT - 1) / KT;
   const int p_lo = grp * d.fold;
   const int p_hi = min(d.naux, p_lo + d.fold);
-  const int nstage = (p_hi - p_lo) * nkb;
+  const int np = p_hi - p_lo;
+  const int nstage = np * nkb;
 
   const int c = tid >> 2, kq = tid & 3;       // row c of both tiles, k quarter kq
   const bool xok = m0 + c < n, yok = n0 + c < n;
   const int xrow = min(m0 + c, n - 1), yrow = min(n0 + c, n - 1);
 
-  // first q of this lane's eight in stage s
-  auto qbase = [&](int s) { return (s % nkb) * KT + 8 * kq; };
+  // Stage s covers q-block s / np of slab p_lo + s % np: the slabs of the
+  // group run inside each q-block, so the lane's eight St values are loaded
+  // once per q-block (on its first slab) and kept in sv while the slabs pass.
+  auto qbase = [&](int s) { return (s / np) * KT + 8 * kq; };
   auto load = [&](int s, ExRaw& r) {
-    const int pb = p_lo + s / nkb;
+    const int pb = p_lo + s % np;
+    const bool first = s % np == 0;
     const int k0 = qbase(s);
     const float* bp = bI + (long long)pb * n * n;
     const float* px = bp + (long long)xrow * n;
@@ -557,10 +562,12 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
         const int k = min(k0 + 4 * v, n - 4);
         const float4 fx = *(const float4*)(px + k);
         const float4 fy = *(const float4*)(py + k);
-        const float4 fs = *(const float4*)(ps + k);
         r.x[4 * v] = fx.x; r.x[4 * v + 1] = fx.y; r.x[4 * v + 2] = fx.z; r.x[4 * v + 3] = fx.w;
         r.y[4 * v] = fy.x; r.y[4 * v + 1] = fy.y; r.y[4 * v + 2] = fy.z; r.y[4 * v + 3] = fy.w;
-        r.s[4 * v] = fs.x; r.s[4 * v + 1] = fs.y; r.s[4 * v + 2] = fs.z; r.s[4 * v + 3] = fs.w;
+        if (first) {
+          const float4 fs = *(const float4*)(ps + k);
+          r.s[4 * v] = fs.x; r.s[4 * v + 1] = fs.y; r.s[4 * v + 2] = fs.z; r.s[4 * v + 3] = fs.w;
+        }
       }
     } else {
 #pragma unroll
@@ -568,17 +575,22 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
         const int k = min(k0 + j, n - 1);
         r.x[j] = px[k];
         r.y[j] = py[k];
-        r.s[j] = ps[k];
+        if (first) r.s[j] = ps[k];
       }
     }
   };
+  float sv[8];
   auto store = [&](int s, const ExRaw& r, int buf) {
     const int kl = n - qbase(s);
+    if (s % np == 0) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sv[e] = r.s[e];
+    }
     bf8v px[3], py[3];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float xv = (xok && e < kl) ? r.x[e] : 0.f;
-      const float yv = (yok && e < kl) ? r.y[e] * r.s[e] : 0.f;
+      const float yv = (yok && e < kl) ? r.y[e] * sv[e] : 0.f;
       __bf16 a[3], b[3];
       split3(xv, a);
       split3(yv, b);
@@ -628,7 +640,8 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
               acc[ip + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], b[j][py], acc[ip + i][j], 0, 0, 0);
         }
     }
-    if ((s + 1) % nkb == 0) {                 // end of an auxiliary slab
+    {   // every stage's FP32 sums (32 q of one slab) into FP64: the result
+        // does not depend on how the slabs are grouped beyond FP64 rounding
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
