@@ -97,7 +97,13 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   const long long xo = (long long)outer * d.sx2, yo = (long long)outer * d.sy2;
   const double* __restrict__ Sg = d.S ? d.S + (long long)outer * d.ss2 : nullptr;
   const int nkb = (d.K + KT - 1) / KT;
-  const int nstage = (b_hi - b_lo) * nkb;
+  const int np = b_hi - b_lo;
+  const int nstage = np * nkb;
+  // FP64 exchange-type product: the batches (slabs) of the group run inside
+  // each k block, so this thread's S values are loaded once per k block and
+  // kept while the slabs pass (the accumulation order changes at FP64
+  // rounding only; the FP32 form keeps one batch per FP32 sum)
+  constexpr bool SREUSE = HAS_S && std::is_same<TC, double>::value;
 
   const TX* __restrict__ X = (const TX*)d.X + xo;
   const TY* __restrict__ Y = (const TY*)d.Y + yo;
@@ -147,8 +153,9 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
   bool wdiag = false;
 
   auto load = [&](int s) {
-    const int bb = b_lo + s / nkb;
-    const int k0 = (s - (bb - b_lo) * nkb) * KT;
+    const int bb = SREUSE ? b_lo + s % np : b_lo + s / nkb;
+    const int k0 = SREUSE ? (s / np) * KT : (s - (bb - b_lo) * nkb) * KT;
+    const bool s_new = !SREUSE || s % np == 0;            // S rows of a new k block
     int klim = d.K - k0;                                   // rows of this stage that exist
     if (d.Ktot > 0) {
       const long long r = d.Ktot - (long long)bb * d.K - k0;
@@ -172,7 +179,7 @@ __device__ __forceinline__ void gemm_body(const GemmDesc& d, int tiles_n, int nt
     for (int j = 0; j < PY; ++j) {
       const bool ok = yn_ok && ky_t + RY * j < klim;
       yr[j] = ok ? py[(long long)(RY * j) * d.ldy] : (TY)0;
-      if (HAS_S) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : 0.0;
+      if (HAS_S && s_new) sr[HAS_S ? j : 0] = ok ? S[(long long)(k0 + ky_t + RY * j) * d.lds + (n0 + cy_t)] : 0.0;
     }
     if (HAS_S) {
       // only stages whose rows [k0, k0 + KT) meet the tile's columns (a
