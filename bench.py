@@ -529,28 +529,15 @@ def run_batched(nof, inputs, dev, steps=5, solve=True):
     return rec
 
 
-def run_batched_solve(nof, Bx, B64, Cd, Hd, w, dev, stream, outer=2, steps=10, on_maxit=2000):
-    """The NO + ON loop for all 25 finite-field instances as an x10 plan
-    (nof_plan_solve: per-instance ON steps, one graph replay per NO step of
-    all instances) against 25 single-instance solves (nof_solve), both for
-    `outer` outer iterations of `steps` NO steps.  As in a finite-field
-    calculation every instance starts from the same orbitals (the first
-    instance's); the orbital roles follow the one-electron energies of the
-    field-free H at those orbitals (aufbau); PNOF5, softmax map, cold start
-    n_g = 0.98."""
+def solve_pair(nof, Bin, prec, C0, Hd, mem, g0, norb, dev, stream, kw):
+    """One batched solve of the 25 instances (plan on Bin) and the 25
+    single-instance solves in the plan's precision; returns both results and
+    their wall times."""
     import torch
-    from paper_2512_13550_amd.warmstart import aufbau_members
-    ns, ng, norb = w.nstrong, w.ng, w.norb
-    C0 = Cd[0].clone()
-    h0 = nof.one_electron(Hd[0], C0)
-    members = aufbau_members(torch.diagonal(h0).cpu().numpy(), ns, ng)
-    mem = torch.from_numpy(members).to(dev)
-    g0 = np.full((ns, ng), np.log(0.02 / ng / 0.98))
-    kw = dict(max_outer=outer, no_steps=steps, tol_lambda=0.0, tol_energy=0.0, on_maxit=on_maxit)
     Cs = C0.unsqueeze(0).repeat(25, 1, 1).contiguous()
     nd = torch.zeros((25, norb), dtype=torch.float64, device=dev)
     Z = torch.zeros((25, norb, norb), dtype=torch.float64, device=dev)
-    plan = nof.BatchPlan(Bx, Cs, Hd, nd, Z, Z.clone())
+    plan = nof.BatchPlan(Bin, Cs, Hd, nd, Z, Z.clone())
     plan.autotune()
     gam = torch.from_numpy(np.stack([g0] * 25)).to(dev)
     torch.cuda.synchronize()
@@ -563,11 +550,40 @@ def run_batched_solve(nof, Bx, B64, Cd, Hd, w, dev, stream, outer=2, steps=10, o
     for i in range(25):
         C = C0.clone()
         g = torch.from_numpy(g0.copy()).to(dev)
-        single.append(nof.solve(Bx, C, Hd[i], mem, nof.MAP_SOFTMAX, nof.FUNC_PNOF5, g, prec=nof.P_BF16X10, **kw))
+        single.append(nof.solve(Bin, C, Hd[i], mem, nof.MAP_SOFTMAX, nof.FUNC_PNOF5, g, prec=prec, **kw))
     torch.cuda.synchronize()
     ms_s = (time.perf_counter() - t0) * 1e3
     del plan
     torch.cuda.empty_cache()
+    return res, single, ms_b, ms_s
+
+
+def run_batched_solve(nof, Bx, B64, Cd, Hd, w, dev, stream, outer=2, steps=10, on_maxit=2000):
+    """The NO + ON loop for all 25 finite-field instances as an x10 plan
+    (nof_plan_solve: per-instance ON steps, one graph replay per NO step of
+    all instances) against 25 single-instance solves (nof_solve), both for
+    `outer` outer iterations of `steps` NO steps.  As in a finite-field
+    calculation every instance starts from the same orbitals (the first
+    instance's); the orbital roles follow the one-electron energies of the
+    field-free H at those orbitals (aufbau); PNOF5, softmax map, cold start
+    n_g = 0.98.  The same pair again with an FP64 plan and FP64 single
+    solves (fp64_pair)."""
+    import torch
+    from paper_2512_13550_amd.warmstart import aufbau_members
+    ns, ng, norb = w.nstrong, w.ng, w.norb
+    C0 = Cd[0].clone()
+    h0 = nof.one_electron(Hd[0], C0)
+    members = aufbau_members(torch.diagonal(h0).cpu().numpy(), ns, ng)
+    mem = torch.from_numpy(members).to(dev)
+    g0 = np.full((ns, ng), np.log(0.02 / ng / 0.98))
+    kw = dict(max_outer=outer, no_steps=steps, tol_lambda=0.0, tol_energy=0.0, on_maxit=on_maxit)
+    res, single, ms_b, ms_s = solve_pair(nof, Bx, nof.P_BF16X10, C0, Hd, mem, g0, norb, dev, stream, kw)
+    # the same pair as an FP64 plan and FP64 single solves, whose roundings
+    # differ only in the order of some FP64 sums: how far the pairs drift
+    # apart measures how much the trajectory amplifies rounding (ADAM's first
+    # steps move every component by about lr sign(g), also where g is ~0)
+    r64, s64, ms_b64, ms_s64 = solve_pair(nof, B64, nof.P_F64, C0, Hd, mem, g0, norb, dev, stream, kw)
+    dE64 = [abs(a["E"] - b_["E"]) for a, b_ in zip(r64, s64)]
     # the two runs take the same steps in exact arithmetic; their roundings
     # differ (packed first stage, one launch for all ON steps), and the ON line
     # searches can turn such differences into different discrete choices
@@ -581,7 +597,9 @@ def run_batched_solve(nof, Bx, B64, Cd, Hd, w, dev, stream, outer=2, steps=10, o
             "on_iters_per_call_max_instance": float(max(r["on_iters"] for r in res)) / outer,
             "max_abs_dE_Eh_batched_vs_single": float(max(dEs)),
             "median_abs_dE_Eh_batched_vs_single": float(np.median(dEs)),
-            "instances_dE_above_1e-6": int(sum(x > 1e-6 for x in dEs))}
+            "instances_dE_above_1e-6": int(sum(x > 1e-6 for x in dEs)),
+            "fp64_pair": {"ms_batched": ms_b64, "ms_25_single": ms_s64, "speedup": ms_s64 / ms_b64,
+                          "max_abs_dE_Eh_batched_vs_single": float(max(dE64))}}
 
 
 def run_warmstart(nof, ntrain, nheld=20):

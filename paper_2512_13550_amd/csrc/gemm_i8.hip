@@ -85,13 +85,18 @@ __device__ __forceinline__ void split_i8(double v, int E, unsigned (&p)[4], int 
   }
 }
 
+// The same for an FP32 value, each rounding done by adding 1.5 * 2^23: for
+// |t| < 2^22 the sum lies in [2^23, 2^24), where the FP32 spacing is 1, so it
+// is M + rint(t) (ties to even, as rintf) and its low mantissa byte is
+// rint(t) mod 256, the piece's byte, with no conversion to integer.
 __device__ __forceinline__ void split_i8f(float v, int E, unsigned (&p)[4], int byte) {
+  constexpr float M = 12582912.0f;       // 1.5 * 2^23
   float t = v * __int_as_float((127 + 7 - E) << 23);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float n = rintf(t);
-    p[q] |= ((unsigned)(int)n & 0xffu) << (8 * byte);
-    t = (t - n) * 128.0f;
+    const float u = t + M;
+    p[q] |= (__float_as_uint(u) & 0xffu) << (8 * byte);
+    if (q < 3) t = (t - (u - M)) * 128.0f;
   }
 }
 
@@ -517,33 +522,43 @@ __device__ __forceinline__ void split16_i8(const float (&v)[16], int E, i4v (&p)
 // The planes: for every (instance, slab slot P < ngroups * fold, row s), the
 // segment (P - g fold) * ldk .. + ldk of rows s of X^g and Y^g (zeros for
 // q >= norb and for slots past the last slab).  Work item = one 16-byte
-// chunk (16 consecutive q) of one such row, items in row order over the
-// lanes (short rows do not leave lanes idle): one 16-byte store per plane,
-// the values loaded as four 16-byte vectors when V4 (rows of b and St
+// chunk (16 consecutive q) of one such row, items in row order; a wave takes
+// a contiguous range of items, lane l every 64th from its start, so short
+// rows do not leave lanes idle, and a lane's (row, chunk) advances by
+// additions (the divisions are done once).  One 16-byte store per plane; the
+// values are loaded as four 16-byte vectors when V4 (rows of b and St
 // 16-byte aligned) and the chunk lies inside the row.
 template <bool V4>
 __global__ void k_exch_split_i8(const float* __restrict__ b, long long sb, const float* __restrict__ St,
                                 int ninst, int naux, int norb, int fold, int ngroups, int ldk,
                                 const int* __restrict__ ex, const int* __restrict__ ey,
                                 unsigned char* __restrict__ X, unsigned char* __restrict__ Y) {
-  const long long slots = (long long)ngroups * fold;
+  const int slots = ngroups * fold;
   const int cpr = ldk >> 4;                                       // chunks per row
   const long long items = (long long)ninst * slots * norb * cpr;
   const long long rowlen = (long long)fold * ldk;                 // bytes of a row of X^g
   const long long plane = (long long)ninst * ngroups * norb * rowlen;
-  for (long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x; it < items;
-       it += (long long)gridDim.x * blockDim.x) {
-    const long long row = it / cpr;
-    const int q16 = (int)(it - row * cpr) << 4;
-    const long long i = row / (slots * norb);
-    const long long rs = row - i * slots * norb;
-    const int P = (int)(rs / norb), s = (int)(rs - (long long)P * norb);
-    const int g = P / fold, seg = P - g * fold;
-    const long long gr = (i * ngroups + g) * (long long)norb + s;  // (instance, group, row)
+  const long long nwave = (long long)gridDim.x * (blockDim.x >> 6);
+  const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long span = ((items + nwave - 1) / nwave + 63) / 64 * 64;
+  const long long it0 = wave * span + (threadIdx.x & 63);
+  const long long it1 = min(items, wave * span + span);
+  if (it0 >= it1) return;
+  // (instance i, slot P = g fold + seg, row s, chunk c) of item it0
+  const long long row0 = it0 / cpr;
+  int c = (int)(it0 - row0 * cpr);
+  const long long per_inst = (long long)slots * norb;
+  int i = (int)(row0 / per_inst);
+  const long long rs = row0 - (long long)i * per_inst;
+  int P = (int)(rs / norb), s = (int)(rs - (long long)P * norb);
+  int g = P / fold, seg = P - g * fold;
+  for (long long it = it0; it < it1; it += 64) {
+    const long long gr = ((long long)i * ngroups + g) * norb + s;  // (instance, group, row)
     const int Ex = ex[gr], Ey = ey[gr];
     const bool live = P < naux;
     const float* br = b + i * sb + ((long long)(live ? P : 0) * norb + s) * norb;
-    const float* sr = St + (i * norb + s) * (long long)norb;
+    const float* sr = St + ((long long)i * norb + s) * norb;
+    const int q16 = c << 4;
     const long long o = gr * rowlen + (long long)seg * ldk + q16;
     float x[16], y[16];
     if (V4 && live && q16 + 16 <= norb) {
@@ -566,9 +581,20 @@ __global__ void k_exch_split_i8(const float* __restrict__ b, long long sb, const
     split16_i8(x, Ex, px);
     split16_i8(y, Ey, py);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      *(i4v*)(X + c * plane + o) = px[c];
-      *(i4v*)(Y + c * plane + o) = py[c];
+    for (int cc = 0; cc < 4; ++cc) {
+      *(i4v*)(X + cc * plane + o) = px[cc];
+      *(i4v*)(Y + cc * plane + o) = py[cc];
+    }
+    // advance by 64 items
+    c += 64;
+    while (c >= cpr) {
+      c -= cpr;
+      if (++s == norb) {
+        s = 0;
+        ++P;
+        if (++seg == fold) { seg = 0; ++g; }
+        if (P == slots) { P = 0; g = 0; seg = 0; ++i; }
+      }
     }
   }
 }

@@ -619,7 +619,7 @@ class BatchPlan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:     # lib is None at interpreter exit
             lib.nof_plan_destroy(h)
             self.handle = None
 
