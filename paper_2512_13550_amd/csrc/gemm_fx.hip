@@ -493,6 +493,18 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
 // <= 2 are accumulated in FP32 over one stage (32 q of one auxiliary slab),
 // then added to FP64.
 // The term enters lambda and the orbital gradient, not the energy.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+// split3 of two values at once: each BF16 rounding of a pair is one packed
+// conversion, and the pieces come out packed as they are stored.
+__device__ __forceinline__ void split3x2(f2v v, bf2v (&p)[3]) {
+  p[0] = __builtin_convertvector(v, bf2v);
+  const f2v r1 = v - __builtin_convertvector(p[0], f2v);
+  p[1] = __builtin_convertvector(r1, bf2v);
+  p[2] = __builtin_convertvector(r1 - __builtin_convertvector(p[1], f2v), bf2v);
+}
+
 __device__ __forceinline__ void split3(float v, __bf16 (&p)[3]) {
   const __bf16 h = (__bf16)v;
   const float r1 = v - (float)h;
@@ -588,14 +600,17 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
     }
     bf8v px[3], py[3];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float xv = (xok && e < kl) ? r.x[e] : 0.f;
-      const float yv = (yok && e < kl) ? r.y[e] * sv[e] : 0.f;
-      __bf16 a[3], b[3];
-      split3(xv, a);
-      split3(yv, b);
+    for (int e = 0; e < 8; e += 2) {
+      const f2v xv = {(xok && e < kl) ? r.x[e] : 0.f, (xok && e + 1 < kl) ? r.x[e + 1] : 0.f};
+      const f2v yv = {(yok && e < kl) ? r.y[e] * sv[e] : 0.f, (yok && e + 1 < kl) ? r.y[e + 1] * sv[e + 1] : 0.f};
+      bf2v a[3], b[3];
+      split3x2(xv, a);
+      split3x2(yv, b);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) { px[q][e] = a[q]; py[q][e] = b[q]; }
+      for (int q = 0; q < 3; ++q) {
+        px[q][e] = a[q][0]; px[q][e + 1] = a[q][1];
+        py[q][e] = b[q][0]; py[q][e + 1] = b[q][1];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
