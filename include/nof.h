@@ -96,9 +96,9 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3, NOF_I8X4 
  *                 term sums groups of auxiliary slabs as one INT8 contraction
  *                 each (as many slabs as keep slabs x 64-padded rows within
  *                 65536), one grid per row of b^P and of cK o b^P over the
- *                 group, an FP64 partial per group; its workspace holds those
- *                 planes (twice the bytes of b in FP32).  The batched plan
- *                 takes that term as in NOF_P_BF16X10.
+ *                 group, an FP64 partial per group; the groups are split and
+ *                 multiplied in chunks whose planes fit 8 GiB of workspace.
+ *                 The batched plan takes that term as in NOF_P_BF16X10.
  * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
 typedef enum {
   NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4,

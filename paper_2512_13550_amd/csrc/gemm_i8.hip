@@ -530,14 +530,15 @@ __device__ __forceinline__ void split16_i8(const float (&v)[16], int E, i4v (&p)
 // 16-byte aligned) and the chunk lies inside the row.
 template <bool V4>
 __global__ void k_exch_split_i8(const float* __restrict__ b, long long sb, const float* __restrict__ St,
-                                int ninst, int naux, int norb, int fold, int ngroups, int ldk,
-                                const int* __restrict__ ex, const int* __restrict__ ey,
+                                int ninst, int naux, int norb, int fold, int ngroups, int g0, int gcnt,
+                                int ldk, const int* __restrict__ ex, const int* __restrict__ ey,
                                 unsigned char* __restrict__ X, unsigned char* __restrict__ Y) {
-  const int slots = ngroups * fold;
+  // groups g0 .. g0 + gcnt - 1 of every instance: planes [4][ninst][gcnt][norb][fold * ldk]
+  const int slots = gcnt * fold;
   const int cpr = ldk >> 4;                                       // chunks per row
   const long long items = (long long)ninst * slots * norb * cpr;
   const long long rowlen = (long long)fold * ldk;                 // bytes of a row of X^g
-  const long long plane = (long long)ninst * ngroups * norb * rowlen;
+  const long long plane = (long long)ninst * gcnt * norb * rowlen;
   const long long nwave = (long long)gridDim.x * (blockDim.x >> 6);
   const long long wave = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const long long span = ((items + nwave - 1) / nwave + 63) / 64 * 64;
@@ -553,13 +554,14 @@ __global__ void k_exch_split_i8(const float* __restrict__ b, long long sb, const
   int P = (int)(rs / norb), s = (int)(rs - (long long)P * norb);
   int g = P / fold, seg = P - g * fold;
   for (long long it = it0; it < it1; it += 64) {
-    const long long gr = ((long long)i * ngroups + g) * norb + s;  // (instance, group, row)
+    const long long gr = ((long long)i * ngroups + g0 + g) * norb + s;  // grid: (instance, group, row)
     const int Ex = ex[gr], Ey = ey[gr];
-    const bool live = P < naux;
-    const float* br = b + i * sb + ((long long)(live ? P : 0) * norb + s) * norb;
+    const int Pg = g0 * fold + P;                                       // the slab
+    const bool live = Pg < naux;
+    const float* br = b + i * sb + ((long long)(live ? Pg : 0) * norb + s) * norb;
     const float* sr = St + ((long long)i * norb + s) * norb;
     const int q16 = c << 4;
-    const long long o = gr * rowlen + (long long)seg * ldk + q16;
+    const long long o = (((long long)i * gcnt + g) * norb + s) * rowlen + (long long)seg * ldk + q16;
     float x[16], y[16];
     if (V4 && live && q16 + 16 <= norb) {
 #pragma unroll
@@ -637,8 +639,12 @@ int i8_exchange_fold(int naux, int norb) {
 }
 
 namespace {
+// Bytes of INT8 planes (X and Y together) held at a time: the groups are
+// split and multiplied in chunks of as many groups as fit (at least one).
+constexpr size_t I8_EX_PLANE_BUDGET = size_t(8) << 30;
+
 struct I8ExLayout {
-  int fold, ngroups;
+  int fold, ngroups, gchunk;
   size_t off_mx, off_my, off_ex, off_ey, off_X, off_Y, total;
 };
 I8ExLayout i8_ex_layout(int ninst, int naux, int norb) {
@@ -647,7 +653,10 @@ I8ExLayout i8_ex_layout(int ninst, int naux, int norb) {
   L.ngroups = (naux + L.fold - 1) / L.fold;
   const size_t rows = (size_t)ninst * naux * norb;
   const size_t grows = (size_t)ninst * L.ngroups * norb;
-  const size_t planes = 4 * grows * (size_t)L.fold * i8_ldk(norb);
+  const size_t per_group = 2 * 4 * (size_t)ninst * norb * (size_t)L.fold * i8_ldk(norb);
+  size_t gc = I8_EX_PLANE_BUDGET / per_group;
+  L.gchunk = (int)(gc < 1 ? 1 : (gc > (size_t)L.ngroups ? (size_t)L.ngroups : gc));
+  const size_t planes = per_group / 2 * L.gchunk;
   L.off_mx = 0;
   L.off_my = align256(L.off_mx + rows * 4);
   L.off_ex = align256(L.off_my + rows * 4);
@@ -687,28 +696,32 @@ int i8_exchange(int ninst, int naux, int norb, const float* b, long long sb, con
   hipLaunchKernelGGL(k_exch_grids_i8, dim3((unsigned)grid_of(grows, 256)), dim3(256), 0, st, mx, my, ninst,
                      naux, norb, L.fold, L.ngroups, ex, ey);
   if ((rc = launch_status()) != NOF_OK) return rc;
-  const long long sitems = (long long)ninst * L.ngroups * L.fold * norb * (ldk / 16);
-  if (v4)
-    hipLaunchKernelGGL(k_exch_split_i8<true>, dim3((unsigned)grid_of(sitems, 256)), dim3(256), 0, st, b, sb, St,
-                       ninst, naux, norb, L.fold, L.ngroups, ldk, ex, ey, X, Y);
-  else
-    hipLaunchKernelGGL(k_exch_split_i8<false>, dim3((unsigned)grid_of(sitems, 256)), dim3(256), 0, st, b, sb, St,
-                       ninst, naux, norb, L.fold, L.ngroups, ldk, ex, ey, X, Y);
-  if ((rc = launch_status()) != NOF_OK) return rc;
   const long long rowlen = (long long)L.fold * ldk;
   const long long n2 = (long long)norb * norb;
-  I8Desc d{};
-  d.M = norb; d.N = norb; d.K = (int)rowlen; d.batch = ninst * L.ngroups;
-  d.binner = ninst > 1 ? L.ngroups : 0;
-  const long long gstride = (long long)norb * rowlen;              // one group's rows
-  const long long plane = (long long)ninst * L.ngroups * gstride;
-  d.X = X; d.ldx = rowlen; d.sx = gstride; d.sx2 = (long long)L.ngroups * gstride; d.psx = plane;
-  d.ex = ex; d.sex = norb; d.sex2 = (long long)L.ngroups * norb;
-  d.Y = Y; d.ldy = rowlen; d.sy = gstride; d.sy2 = (long long)L.ngroups * gstride; d.psy = plane;
-  d.ey = ey; d.sey = norb; d.sey2 = (long long)L.ngroups * norb;
-  d.Out64 = Out; d.ldo = norb; d.so = n2; d.so2 = (long long)L.ngroups * n2;
-  d.sym = false; d.role = 3;
-  return gemm_i8(d, st);
+  for (int g0 = 0; g0 < L.ngroups; g0 += L.gchunk) {
+    const int gc = min(L.gchunk, L.ngroups - g0);
+    const long long sitems = (long long)ninst * gc * L.fold * norb * (ldk / 16);
+    if (v4)
+      hipLaunchKernelGGL(k_exch_split_i8<true>, dim3((unsigned)grid_of(sitems, 256)), dim3(256), 0, st, b, sb,
+                         St, ninst, naux, norb, L.fold, L.ngroups, g0, gc, ldk, ex, ey, X, Y);
+    else
+      hipLaunchKernelGGL(k_exch_split_i8<false>, dim3((unsigned)grid_of(sitems, 256)), dim3(256), 0, st, b, sb,
+                         St, ninst, naux, norb, L.fold, L.ngroups, g0, gc, ldk, ex, ey, X, Y);
+    if ((rc = launch_status()) != NOF_OK) return rc;
+    I8Desc d{};
+    d.M = norb; d.N = norb; d.K = (int)rowlen; d.batch = ninst * gc;
+    d.binner = ninst > 1 ? gc : 0;
+    const long long gstride = (long long)norb * rowlen;              // one group's rows
+    const long long plane = (long long)ninst * gc * gstride;
+    d.X = X; d.ldx = rowlen; d.sx = gstride; d.sx2 = (long long)gc * gstride; d.psx = plane;
+    d.ex = ex + (long long)g0 * norb; d.sex = norb; d.sex2 = (long long)L.ngroups * norb;
+    d.Y = Y; d.ldy = rowlen; d.sy = gstride; d.sy2 = (long long)gc * gstride; d.psy = plane;
+    d.ey = ey + (long long)g0 * norb; d.sey = norb; d.sey2 = (long long)L.ngroups * norb;
+    d.Out64 = Out + (long long)g0 * n2; d.ldo = norb; d.so = n2; d.so2 = (long long)L.ngroups * n2;
+    d.sym = false; d.role = 3;
+    if ((rc = gemm_i8(d, st)) != NOF_OK) return rc;
+  }
+  return NOF_OK;
 }
 
 int i8_split_rows(const void* A, int At, long long nrow, int K, int ldk, void* planes, int* e,

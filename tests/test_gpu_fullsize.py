@@ -10,8 +10,9 @@ benchmark's call sequence (stages, h, J, Coulomb-type pass with K,
 exchange-type term, lambda and g, energy) against the oracle run slab by slab
 over all 4000 slabs: E, J, K, lambda and g to 1e-10 normwise in FP64; the x10
 forms (B as planes of the FP64 B; B stored in FP32, whose rounding alone
-moves E by about 6e-7 Eh here) within 1e-6 Eh of the oracle's E; also the
-orthogonal sum rules, which hold at any size.
+moves E by about 6e-7 Eh here) and the INT8 form within 1e-6 Eh of the
+oracle's E and lambda within 3e-7 normwise; also the orthogonal sum rules,
+which hold at any size.
 """
 import numpy as np
 import pytest
@@ -82,12 +83,13 @@ def bench_step(nof, B, C, H, n, cJ, cK, prec, dt):
     """One iteration in bench.py's call sequence: the stages (one
     nof_mo_transform call for x10), h, J; then K alone and both Fock terms in
     one contraction (FP64), or K with the Coulomb-type term in one pass and
-    the exchange-type term (x10); lambda and g, E."""
+    the exchange-type term (x10, INT8); lambda and g, E."""
     naux, nbf, _ = B.shape
     norb = C.shape[1]
     b = torch.empty((naux, norb, norb), dtype=dt, device="cuda")
     D = torch.empty((naux, norb), dtype=torch.float64, device="cuda")
-    if prec == nof.P_BF16X10:
+    fixed = prec in (nof.P_BF16X10, nof.P_I8X10)
+    if fixed:
         nof.mo_transform(B, C, prec=prec, b=b, D=D)
     else:
         T = torch.empty((naux, nbf, norb), dtype=dt, device="cuda")
@@ -95,7 +97,7 @@ def bench_step(nof, B, C, H, n, cJ, cK, prec, dt):
         nof.transform_stage2(T, C, b, D, prec=prec)
         del T
     h = nof.one_electron(H, C)
-    if prec == nof.P_BF16X10:
+    if fixed:
         J, _ = nof.jk_diag(b, D, want_K=False)
         F1, K = nof.coulomb_fock(b, D, cJ)
         F2 = nof.exchange_fock(b, cK, prec=prec)
@@ -134,6 +136,12 @@ def test_chain1000_against_oracle_all_forms():
     gotx32 = bench_step(nof, Bd, Cd, Hd, nd, cJd, cKd, nof.P_BF16X10, torch.float32)
     del Bd
     torch.cuda.empty_cache()
+    # INT8 form: its exchange-type planes (33 GB here) are split and multiplied
+    # in chunks of groups that fit the 8 GiB plane budget (four chunks)
+    planes8 = nof.SplitBI8(dev(B))
+    got8 = bench_step(nof, planes8, Cd, Hd, nd, cJd, cKd, nof.P_I8X10, torch.float32)
+    del planes8
+    torch.cuda.empty_cache()
     print("gpu done; oracle over all slabs", flush=True)
     ref = dfjk.streamed_iteration(lambda lo, hi: B[lo:hi], w.naux, C, H, n, cJ, cK, pblock=100)
     errs = {k: normwise(got64[k], ref[k]) for k in ("h", "J", "K", "lam", "g")}
@@ -141,12 +149,13 @@ def test_chain1000_against_oracle_all_forms():
     print("chain1000 FP64 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, "E", ref["E"], flush=True)
     for k, v in errs.items():
         assert v <= 1e-10, (k, v)
-    for name, got in (("x10 planes of FP64 B", gotx), ("x10 FP32 B", gotx32)):
+    for name, got in (("x10 planes of FP64 B", gotx), ("x10 FP32 B", gotx32), ("INT8 planes of FP64 B", got8)):
         dE = got["E"] - ref["E"]
         print("chain1000", name, "dE (Eh)", dE, "max dJ", np.abs(got["J"] - ref["J"]).max(),
               "max dK", np.abs(got["K"] - ref["K"]).max(), "lambda normwise", normwise(got["lam"], ref["lam"]),
               flush=True)
         assert abs(dE) <= 1e-6, (name, dE)
+        assert normwise(got["lam"], ref["lam"]) <= 3e-7, name
     # orthogonal sum rules (Norb = Nbf): sum K = sum_P ||B^P||_F^2, sum J = sum_P (tr B^P)^2
     sK = float(np.einsum("Pmn,Pmn->", B, B))
     sJ = float(np.sum(np.trace(B, axis1=1, axis2=2) ** 2))
