@@ -58,13 +58,18 @@ __device__ __forceinline__ int grid_exp_bits(unsigned mbits) {
   return clamp_exp((int)(mbits >> 23) - 126);
 }
 
-// Four pieces of v on the grid of exponent E (|v| < 2^E).
-__device__ __forceinline__ void split_g(float v, int E, __bf16 (&p)[4]) {
-  float t = v * pow2f(7 - E);
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+// Four pieces of each of two values on the grid of exponent E (|v| < 2^E):
+// n_q 2^(E-7-8q) with n_q = rint of what the previous pieces left; each piece
+// pair is one packed BF16 conversion (exact: |n_q| <= 128).
+__device__ __forceinline__ void split_g2(f2v v, int E, bf2v (&p)[4]) {
+  f2v t = v * pow2f(7 - E);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float n = rintf(t);
-    p[q] = (__bf16)(n * pow2f(E - 7 - 8 * q));
+    const f2v n = {rintf(t[0]), rintf(t[1])};
+    p[q] = __builtin_convertvector(n * pow2f(E - 7 - 8 * q), bf2v);
     t = (t - n) * 256.0f;
   }
 }
@@ -318,11 +323,11 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     } else {
       bf8v pk[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        __bf16 p[4];
-        split_g(R.xr[XPS ? 0 : e], ex, p);
+      for (int e = 0; e < 8; e += 2) {
+        bf2v p[4];
+        split_g2(f2v{R.xr[XPS ? 0 : e], R.xr[XPS ? 0 : e + 1]}, ex, p);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
+        for (int q = 0; q < 4; ++q) { pk[q][e] = p[q][0]; pk[q][e + 1] = p[q][1]; }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) *(bf8v*)&Xs[buf][q][cx][swz(cx, kqx)] = pk[q];
@@ -333,11 +338,11 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     } else {
       bf8v pk[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        __bf16 p[4];
-        split_g(R.yr[YPS ? 0 : e], ey, p);
+      for (int e = 0; e < 8; e += 2) {
+        bf2v p[4];
+        split_g2(f2v{R.yr[YPS ? 0 : e], R.yr[YPS ? 0 : e + 1]}, ey, p);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pk[q][e] = p[q];
+        for (int q = 0; q < 4; ++q) { pk[q][e] = p[q][0]; pk[q][e + 1] = p[q][1]; }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) *(bf8v*)&Ys[buf][q][cy][swz(cy, kqy)] = pk[q];
@@ -493,9 +498,6 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
 // <= 2 are accumulated in FP32 over one stage (32 q of one auxiliary slab),
 // then added to FP64.
 // The term enters lambda and the orbital gradient, not the energy.
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
-
 // split3 of two values at once: each BF16 rounding of a pair is one packed
 // conversion, and the pieces come out packed as they are stored.
 __device__ __forceinline__ void split3x2(f2v v, bf2v (&p)[3]) {
