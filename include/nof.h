@@ -234,7 +234,7 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  *         from one pass over the upper half of b.
  * prec    NOF_P_F64 (bt = NOF_F64), NOF_P_F32 or a split form (bt = NOF_F32)
  *         for the matrix-core contraction (X6 and X10: three element-wise
- *         BF16 pieces, FP32 accumulation over 32 q of a slab, FP64 beyond; I8X10:
+ *         BF16 pieces, FP32 accumulation over 64 q of a slab, FP64 beyond; I8X10:
  *         INT8 fixed-point pieces over groups of slabs, exact int32 sums,
  *         FP64 across groups).
  * The two sums over P are one contraction (nof_fock_terms): the Coulomb-type

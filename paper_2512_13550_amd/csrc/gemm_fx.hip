@@ -495,7 +495,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
 // b^P is symmetric, so both operands are read along rows (q contiguous); St
 // is S transposed in FP32 (St[s][q]).  Each FP32 operand value is split into
 // three BF16 pieces (x = hi + mid + lo exactly) and the six products of order
-// <= 2 are accumulated in FP32 over one stage (32 q of one auxiliary slab),
+// <= 2 are accumulated in FP32 over two stages (64 q of one auxiliary slab),
 // then added to FP64.
 // The term enters lambda and the orbital gradient, not the energy.
 // split3 of two values at once: each BF16 rounding of a pair is one packed
@@ -548,7 +548,7 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   const int n = d.norb;
   const float* __restrict__ bI = d.b + (long long)inst * d.sb;
   const float* __restrict__ StI = d.St + (long long)inst * n * n;
-  const int nkb = (n + KT - 1) / KT;
+  const int nkb = ((n + KT - 1) / KT + 1) & ~1;    // q-blocks, padded to pairs
   const int p_lo = grp * d.fold;
   const int p_hi = min(d.naux, p_lo + d.fold);
   const int np = p_hi - p_lo;
@@ -558,13 +558,15 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   const bool xok = m0 + c < n, yok = n0 + c < n;
   const int xrow = min(m0 + c, n - 1), yrow = min(n0 + c, n - 1);
 
-  // Stage s covers q-block s / np of slab p_lo + s % np: the slabs of the
-  // group run inside each q-block, so the lane's eight St values are loaded
-  // once per q-block (on its first slab) and kept in sv while the slabs pass.
-  auto qbase = [&](int s) { return (s / np) * KT + 8 * kq; };
+  // Stages run in pairs over two consecutive q-blocks of one slab; the slabs
+  // of the group run inside each pair of q-blocks: stage s covers q-block
+  // 2 (s / 2np) + s % 2 of slab p_lo + (s / 2) % np.  The lane's St values
+  // of a q-block are loaded once (on the first slab) and kept in sv while
+  // the slabs pass; a q-block past the row end is all zeros (masked).
+  auto qbase = [&](int s) { return (2 * (s / (2 * np)) + (s & 1)) * KT + 8 * kq; };
   auto load = [&](int s, ExRaw& r) {
-    const int pb = p_lo + s % np;
-    const bool first = s % np == 0;
+    const int pb = p_lo + (s >> 1) % np;
+    const bool first = (s >> 1) % np == 0;
     const int k0 = qbase(s);
     const float* bp = bI + (long long)pb * n * n;
     const float* px = bp + (long long)xrow * n;
@@ -593,18 +595,19 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
       }
     }
   };
-  float sv[8];
+  float sv[2][8];
   auto store = [&](int s, const ExRaw& r, int buf) {
     const int kl = n - qbase(s);
-    if (s % np == 0) {
+    if ((s >> 1) % np == 0) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) sv[e] = r.s[e];
+      for (int e = 0; e < 8; ++e) sv[s & 1][e] = r.s[e];
     }
     bf8v px[3], py[3];
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
       const f2v xv = {(xok && e < kl) ? r.x[e] : 0.f, (xok && e + 1 < kl) ? r.x[e + 1] : 0.f};
-      const f2v yv = {(yok && e < kl) ? r.y[e] * sv[e] : 0.f, (yok && e + 1 < kl) ? r.y[e + 1] * sv[e + 1] : 0.f};
+      const f2v yv = {(yok && e < kl) ? r.y[e] * sv[s & 1][e] : 0.f,
+                      (yok && e + 1 < kl) ? r.y[e + 1] * sv[s & 1][e + 1] : 0.f};
       bf2v a[3], b[3];
       split3x2(xv, a);
       split3x2(yv, b);
@@ -657,8 +660,8 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
               acc[ip + i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][px], b[j][py], acc[ip + i][j], 0, 0, 0);
         }
     }
-    {   // every stage's FP32 sums (32 q of one slab) into FP64: the result
-        // does not depend on how the slabs are grouped beyond FP64 rounding
+    if (s & 1) {   // each pair's FP32 sums (64 q of one slab) into FP64: the
+                   // result does not depend on how the slabs are grouped
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
