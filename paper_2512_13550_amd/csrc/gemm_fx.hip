@@ -595,19 +595,28 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
       }
     }
   };
+  // sv[j]: St values of the q-block of the stages stored into LDS buffer j
+  // (stage s goes to buffer s % 2; the clamped repeat of the last stage at
+  // the end goes to a buffer nobody reads)
   float sv[2][8];
   auto store = [&](int s, const ExRaw& r, int buf) {
     const int kl = n - qbase(s);
     if ((s >> 1) % np == 0) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) sv[s & 1][e] = r.s[e];
+      for (int e = 0; e < 8; ++e) sv[buf][e] = r.s[e];
     }
+    // masks only where the tile or the row ends
+    const bool full = kl >= 8;
+    const bool xm = xok, ym = yok;
     bf8v px[3], py[3];
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
-      const f2v xv = {(xok && e < kl) ? r.x[e] : 0.f, (xok && e + 1 < kl) ? r.x[e + 1] : 0.f};
-      const f2v yv = {(yok && e < kl) ? r.y[e] * sv[s & 1][e] : 0.f,
-                      (yok && e + 1 < kl) ? r.y[e + 1] * sv[s & 1][e + 1] : 0.f};
+      f2v xv = {r.x[e], r.x[e + 1]};
+      f2v yv = {r.y[e] * sv[buf][e], r.y[e + 1] * sv[buf][e + 1]};
+      if (!(full && xm && ym)) {
+        xv = f2v{(xm && e < kl) ? xv[0] : 0.f, (xm && e + 1 < kl) ? xv[1] : 0.f};
+        yv = f2v{(ym && e < kl) ? yv[0] : 0.f, (ym && e + 1 < kl) ? yv[1] : 0.f};
+      }
       bf2v a[3], b[3];
       split3x2(xv, a);
       split3x2(yv, b);
