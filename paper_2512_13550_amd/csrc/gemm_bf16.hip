@@ -363,10 +363,13 @@ int dispatch_types(const GemmDesc& d, int x_t, int y_t, int out_t, hipStream_t s
   if (d.role == GemmRole::TransformStage2 && x_t == NOF_BF16 && y_t == NOF_F32 && out_t == NOF_F32 &&
       !flush)
     return launch<NX, NY, ORD, float, float, float, false, true, false, A64, 2>(d, st);
-  // exchange-type Fock: X = Y = b (f32), S = cK, Out = FP64 partials
-  if (d.role == GemmRole::ExchangeFock && x_t == NOF_F32 && y_t == NOF_F32 && out_t == NOF_F64 && d.S)
-    return flush ? launch<NX, NY, ORD, float, float, double, true, false, false, A64, 3>(d, st)
-                 : launch<NX, NY, ORD, float, float, double, false, false, false, A64, 3>(d, st);
+  // exchange-type Fock: X = Y = b (f32), S = cK, Out = FP64 partials (x1, x3;
+  // x6 takes the x10 element-wise exchange-type product in gemm_fx.hip)
+  if constexpr (ORD < 2) {
+    if (d.role == GemmRole::ExchangeFock && x_t == NOF_F32 && y_t == NOF_F32 && out_t == NOF_F64 && d.S)
+      return flush ? launch<NX, NY, ORD, float, float, double, true, false, false, A64, 3>(d, st)
+                   : launch<NX, NY, ORD, float, float, double, false, false, false, A64, 3>(d, st);
+  }
   return NOF_E_DTYPE;
 }
 

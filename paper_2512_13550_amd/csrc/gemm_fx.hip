@@ -498,22 +498,14 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
 // <= 2 are accumulated in FP32 over two stages (64 q of one auxiliary slab),
 // then added to FP64.
 // The term enters lambda and the orbital gradient, not the energy.
-// split3 of two values at once: each BF16 rounding of a pair is one packed
+// Three BF16 pieces of each of two values, x = hi + mid + lo exactly (each
+// residual is exact in FP32): each BF16 rounding of a pair is one packed
 // conversion, and the pieces come out packed as they are stored.
 __device__ __forceinline__ void split3x2(f2v v, bf2v (&p)[3]) {
   p[0] = __builtin_convertvector(v, bf2v);
   const f2v r1 = v - __builtin_convertvector(p[0], f2v);
   p[1] = __builtin_convertvector(r1, bf2v);
   p[2] = __builtin_convertvector(r1 - __builtin_convertvector(p[1], f2v), bf2v);
-}
-
-__device__ __forceinline__ void split3(float v, __bf16 (&p)[3]) {
-  const __bf16 h = (__bf16)v;
-  const float r1 = v - (float)h;
-  const __bf16 m = (__bf16)r1;
-  p[0] = h;
-  p[1] = m;
-  p[2] = (__bf16)(r1 - (float)m);
 }
 
 // Raw operands of one stage of a lane: eight consecutive q of its X row, Y
