@@ -485,7 +485,7 @@ def run_batched(nof, inputs, dev, steps=5, solve=True):
             del Bp
         torch.cuda.empty_cache()
     ms_x10, Ex10, cfg = out["x10"]
-    ms_i8, Ei8, _ = out["i8x10"]
+    ms_i8, Ei8, cfg_i8 = out["i8x10"]
     del Bi
     torch.cuda.empty_cache()
     ms_32, E32, _ = out["f32"]
@@ -520,6 +520,7 @@ def run_batched(nof, inputs, dev, steps=5, solve=True):
                             "exchange_p_split": cfg[3]},
            "max_abs_dE_Eh_vs_f64": float((Ex10 - E64).abs().max()),
            "i8x10": {"ms_per_iteration_batched_graph": ms_i8, "tflops": f / (ms_i8 * 1e-3) / 1e12,
+                     "tuned_config": {"tile_exchange": cfg_i8[2], "exchange_p_split": cfg_i8[3]},
                      "max_abs_dE_Eh_vs_f64": float((Ei8 - E64).abs().max())},
            "f32": {"ms_per_iteration_batched_graph": ms_32, "tflops": f / (ms_32 * 1e-3) / 1e12,
                    "max_abs_dE_Eh_vs_f64": float((E32 - E64).abs().max())},

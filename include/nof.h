@@ -509,9 +509,12 @@ int nof_functional_coeffs(int norb, int ns, int ng, const int* members, int func
  *   configuration and, once captured, a HIP graph of one iteration.
  * nof_plan_autotune: runs one iteration, then times each candidate workgroup
  *   tile (128 or 64) of the two transform stages and the exchange-type
- *   contraction, and its split over P, keeping the fastest (NOF_P_BF16X10:
- *   the split only, its kernels have one tile shape); finishes with one
- *   iteration in the chosen configuration.  Synchronises `stream`.
+ *   contraction, and its split over P, keeping the fastest (NOF_P_I8X10:
+ *   its INT8 transform stages have one tile shape, 128; the stage tiles are
+ *   ignored); finishes with one iteration in the chosen configuration.  The
+ *   fixed-point forms sum every output element in the same order at either
+ *   tile edge, so their results do not depend on the tiles (only on the
+ *   split).  Synchronises `stream`.
  * nof_plan_get_config / nof_plan_set_config: int[4] = {tile stage 1, tile
  *   stage 2, tile exchange, P-split count of the exchange term}, so a caller
  *   can cache a tuning result.

@@ -83,7 +83,7 @@ void plan_layout(nof_plan_s* p) {
   const bool i8 = p->prec == NOF_P_I8X10;
   const size_t ldk = (size_t)presplit_ldk(p->nbf), ldc = ni * no;
   sz[O_CPL] = !fx ? 0 : i8 ? i8_planes_bytes((long long)ldc, p->nbf) + ldc * 4 : 4 * ldc * ldk * 2;
-  sz[O_CMX] = fx ? na * (size_t)fx_tiles(p->nbf) * ldc * 4 : 0;
+  sz[O_CMX] = fx ? na * (size_t)fx_tiles(p->nbf, p->prec == NOF_P_BF16X10 ? 64 : 128) * ldc * 4 : 0;
   sz[O_EY] = fx ? na * ldc * 4 : 0;
   sz[O_ST] = fx ? ni * no * no * 4 : 0;
   sz[O_TPL] = i8 ? i8_planes_bytes((long long)na * ldc, p->nbf) : 0;
@@ -157,10 +157,11 @@ int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
     f.X = a.B; f.ldx = ldk; f.sx = (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
     f.Y = cpl; f.ldy = ldk; f.sy = 0; f.psy = ldc * ldk;
     f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = (long long)p->nbf * ldc;
-    f.sym = false; f.role = 1;
-    f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)fx_tiles(p->nbf) * ldc;
+    f.sym = false; f.role = 1; f.tile = p->tile_s1;
+    const int rt = fx_tiles(p->nbf, p->tile_s1);
+    f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)rt * ldc;
     if ((rc = gemm_fx(f, true, true, st)) != NOF_OK) return rc;
-    return fx_cmax_exps(f.cmax, p->naux, fx_tiles(p->nbf), (int)ldc, (int*)(a.ws + p->off[O_EY]), st);
+    return fx_cmax_exps(f.cmax, p->naux, rt, (int)ldc, (int*)(a.ws + p->off[O_EY]), st);
   }
   GemmDesc g{};
   g.M = p->nbf; g.N = p->ninst * p->norb; g.K = p->nbf;
@@ -206,7 +207,7 @@ int run_stage2(nof_plan_s* p, const Args& a, hipStream_t st) {
     f.ey = (const int*)(a.ws + p->off[O_EY]); f.sey = ldc; f.sey2 = p->norb;
     f.Out = (float*)(a.ws + p->off[O_B]); f.ldo = p->norb; f.so = n2; f.so2 = (long long)p->naux * n2;
     f.Dg = (double*)(a.ws + p->off[O_D]); f.sd = p->norb; f.sd2 = (long long)p->naux * p->norb;
-    f.sym = true; f.role = 2;
+    f.sym = true; f.role = 2; f.tile = p->tile_s2;
     return gemm_fx(f, true, false, st);
   }
   GemmDesc g{};
@@ -292,6 +293,7 @@ int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
     e.ninst = p->ninst;
     e.sb = (long long)p->naux * n2;
     e.so = (long long)gpi * n2;
+    e.tile = p->tile_f2;
     const int rc = exchange_fock_fx(e, a.cK, (float*)(a.ws + p->off[O_ST]), st);
     if (rc != NOF_OK) return rc;
     return reduce_parts(f2p, gpi, n2, p->norb, false, (double*)(a.ws + p->off[O_F2]), st, p->ninst,
@@ -781,14 +783,13 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     int rc = run_iteration(plan, a, stream);        // fills T, b, W with valid data
     if (rc != NOF_OK) return rc;
     const int reps = 3;
-    // the fixed-point kernels have one tile shape: only the exchange split is tuned
-    const bool fx = fixed_point_plan(plan);
-    const int tiles_all[2] = {128, 64};
-    const int ntiles = fx ? 1 : 2;
-    const int* tiles = tiles_all;
+    // the INT8 transform stages have one tile shape (128); every other
+    // product, the exchange-type term of the INT8 plan included, has two
+    const int tiles[2] = {128, 64};
+    const int nst = plan->prec == NOF_P_I8X10 ? 1 : 2;
     float best = -1.f;
     int bt1 = plan->tile_s1;
-    for (int it = 0; it < ntiles && !fx; ++it) {
+    for (int it = 0; it < nst; ++it) {
       const int t = tiles[it];
       plan->tile_s1 = t;
       const float ms = time_stage([&]() { return run_stage1(plan, a, stream); }, stream, reps);
@@ -797,7 +798,7 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     plan->tile_s1 = bt1;
     best = -1.f;
     int bt2 = plan->tile_s2;
-    for (int it = 0; it < ntiles && !fx; ++it) {
+    for (int it = 0; it < nst; ++it) {
       const int t = tiles[it];
       plan->tile_s2 = t;
       const float ms = time_stage([&]() { return run_stage2(plan, a, stream); }, stream, reps);
@@ -807,7 +808,7 @@ int nof_plan_autotune(nof_plan plan, const void* B, const double* C, const doubl
     best = -1.f;
     int btf = plan->tile_f2, bg = plan->f2gpi;
     const int gmax = f2_target_gpi(plan, 64) * 4 > plan->naux ? plan->naux : f2_target_gpi(plan, 64) * 4;
-    for (int it = 0; it < ntiles; ++it) {
+    for (int it = 0; it < 2; ++it) {
       const int t = tiles[it];
       const int g0 = f2_target_gpi(plan, t);
       const int cands[3] = {g0 / 2 > 0 ? g0 / 2 : 1, g0, 2 * g0};

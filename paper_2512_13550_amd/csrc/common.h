@@ -104,11 +104,13 @@ struct FxDesc {
   // inner; X, Y, ey, Out, Dg at inner * s? + outer * s?2
   int binner = 0;
   long long sx2 = 0, sy2 = 0, sey2 = 0, so2 = 0, sd2 = 0;
+  int tile = 128;                  // workgroup tile edge: 128, or 64 with pre-split X
 };
 int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
 // Column grid exponents e[b*N + n] from the row-tile maxima above.
 int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st);
-inline int fx_tiles(int n) { return (n + 127) / 128; }
+// Row tiles of n rows at tile edge ts (the cmax layout).
+inline int fx_tiles(int n, int ts = 128) { return (n + ts - 1) / ts; }
 // INT8 fixed-point transform stage (gemm_i8.hip, NOF_P_I8X10):
 //   Out_b[m][n] = sum_k X_b(k, m) Y_b(k, n)   (FP32 out, FP64 diagonal Dg if sym)
 // X: INT8 planes at X + q*psx + b*sx + m*ldx + k (ldx a multiple of 64, zero
@@ -169,6 +171,7 @@ struct ExDesc {
   double* Out;
   int ninst = 1;
   long long sb = 0, so = 0;
+  int tile = 128;                  // workgroup tile edge, 128 or 64
 };
 int exchange_fock_fx(const ExDesc& d, const double* S, float* St, hipStream_t st);
 // St_i[s][q] = (float)S_i[q][s] for ninst matrices n^2 apart.

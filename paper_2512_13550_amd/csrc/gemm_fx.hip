@@ -20,13 +20,17 @@
 // leave a truncation of order 2^-32 of |x||y|.  For K > 1024 the order-0 sum
 // is added to FP64 every 1024 terms (BIGK variant).
 //
-// Layout: 512 threads = 8 waves (2 x 4); the workgroup tile is 128 x 128,
-// each wave 64 x 32 as 4 x 2 fragments of v_mfma_f32_16x16x32_bf16 (lane l
-// holds 8 consecutive k of row l%16 at k offset 8*(l/16); output row
-// 4*(l/16)+r, column l%16).  LDS holds the four pieces as [row][k] (k in
-// swizzled 16-byte chunks, see swz), in two buffers: the next stage is stored
-// while the current one is multiplied.  The operand split in
-// a loader (a row of X or column of Y) is shared by 128 output columns/rows.
+// Layout: the workgroup tile is TS x TS with two rows of waves, each wave
+// TS/2 x 32 as fragments of v_mfma_f32_16x16x32_bf16 (lane l holds 8
+// consecutive k of row l%16 at k offset 8*(l/16); output row 4*(l/16)+r,
+// column l%16): TS = 128 is 512 threads = 8 waves (2 x 4), one workgroup per
+// CU; TS = 64 (for matrices of a few hundred rows, where 128-wide tiles would
+// be mostly padding) is 256 threads = 4 waves (2 x 2), two workgroups per
+// CU.  Each output element is summed in the same order either way, so the
+// two shapes give identical results.  LDS holds the four pieces as [row][k]
+// (k in swizzled 16-byte chunks, see swz), in two buffers: the next stage is
+// stored while the current one is multiplied.  The operand split in a loader
+// (a row of X or column of Y) is shared by TS output columns/rows.
 //
 // Operands are either pre-split planes (X: [4][..][m][ldk], k contiguous) or
 // FP32 values split in the loader against per-row / per-column grid
@@ -38,9 +42,19 @@ namespace {
 
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-constexpr int FT = 128;                 // tile edge (rows and columns)
 constexpr int KT = 32;
-constexpr int NTHR = 512;
+// Workgroup shape of a TS x TS tile (TS = 128 or 64): NT threads, WN waves
+// along the columns (32 columns each), two along the rows (WR rows each, FM
+// fragments of 16), MINB workgroups per CU.
+template <int TS>
+struct Tile {
+  static_assert(TS == 128 || TS == 64, "tile edge");
+  static constexpr int NT = 4 * TS;
+  static constexpr int WN = TS / 32;
+  static constexpr int WR = TS / 2;
+  static constexpr int FM = WR / 16;
+  static constexpr int MINB = TS == 128 ? 1 : 2;
+};
 constexpr int EXACT_K = 1024;           // order-0 sums stay exact in FP32 up to this depth
 constexpr int EMIN = -90, EMAX = 128;   // grid exponent range (all scales normal FP32)
 
@@ -237,15 +251,17 @@ __device__ __forceinline__ void tile_of(int t, int tiles_n, bool sym, int& tm, i
 
 // XM: X operand as planes (0), FP32 k-major X + b*sx + k*ldx + m (1), or FP32
 // with rows contiguous X + b*sx + m*ldx + k, 16-byte aligned rows (2).
-template <int XM, bool YPS, bool BIGK>
+template <int XM, bool YPS, bool BIGK, int TS>
 __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles) {
   constexpr bool XPS = XM == 0;
-  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][4][FT][KT];
-  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][4][FT][KT];
+  typedef Tile<TS> G;
+  constexpr int FM = G::FM;
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][4][TS][KT];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][4][TS][KT];
 
   const int tid = threadIdx.x;
   const int l = tid & 63, w = tid >> 6;
-  const int wm = w >> 2, wn = w & 3;          // wave tile: rows 64*wm.., columns 32*wn..
+  const int wm = w / G::WN, wn = w % G::WN;   // wave tile: rows WR*wm.., columns 32*wn..
 
   const int logical = xcd_logical(blockIdx.x, gridDim.x);
   const int bb = logical / ntiles;
@@ -257,7 +273,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     ib = bb - ob * d.binner;
   }
   const long long offx = ib * d.sx + ob * d.sx2, offy = ib * d.sy + ob * d.sy2;
-  const int m0 = tm * FT, n0 = tn * FT;
+  const int m0 = tm * TS, n0 = tn * TS;
   const int nstage = (d.K + KT - 1) / KT;
 
   // loaders: thread owns row cx of the X tile (column cy of Y) and its 8 k of
@@ -265,8 +281,8 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   // quarters of a row are neighbouring lanes, so one wave reads 16 rows of
   // 64-128 contiguous bytes; k-major FP32: lanes run along the row index.
   constexpr bool XKC = XM != 1;                 // X with k contiguous
-  const int cx = XKC ? tid >> 2 : tid & (FT - 1), kqx = XKC ? tid & 3 : tid >> 7;
-  const int cy = YPS ? tid >> 2 : tid & (FT - 1), kqy = YPS ? tid & 3 : tid >> 7;
+  const int cx = XKC ? tid >> 2 : tid % TS, kqx = XKC ? tid & 3 : tid / TS;
+  const int cy = YPS ? tid >> 2 : tid % TS, kqy = YPS ? tid & 3 : tid / TS;
   const bool xok = m0 + cx < d.M, yok = n0 + cy < d.N;
   const int ex = (!XPS && xok) ? d.ex[(long long)bb * d.sex + m0 + cx] : 0;
   const int ey = (!YPS && yok) ? d.ey[ib * d.sey + ob * d.sey2 + n0 + cy] : 0;
@@ -349,10 +365,10 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     }
   };
 
-  f4v acc0[4][2], acc1[4][2];
-  d4v acc64[BIGK ? 4 : 1][BIGK ? 2 : 1];
+  f4v acc0[FM][2], acc1[FM][2];
+  d4v acc64[BIGK ? FM : 1][BIGK ? 2 : 1];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       acc0[i][j] = f4v{0, 0, 0, 0};
@@ -371,12 +387,12 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     // two row fragments at a time (four independent accumulators per step):
     // orders 3, 2, 1 into acc1 (smallest first), then the exact order 0
 #pragma unroll
-    for (int ip = 0; ip < 4; ip += 2) {
+    for (int ip = 0; ip < FM; ip += 2) {
       bf8v a[2][4];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[i][q] = *(const bf8v*)&Xs[buf][q][wm * 64 + (ip + i) * 16 + (l & 15)][kl];
+        for (int q = 0; q < 4; ++q) a[i][q] = *(const bf8v*)&Xs[buf][q][wm * G::WR + (ip + i) * 16 + (l & 15)][kl];
 #pragma unroll
       for (int o = 3; o >= 1; --o)
 #pragma unroll
@@ -397,7 +413,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
     }
     if (BIGK && ((s + 1) % (EXACT_K / KT) == 0)) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -453,12 +469,12 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   float* __restrict__ Out = d.Out + ib * d.so + ob * d.so2;
   int cm[2] = {0, 0};      // bits of the largest |stored value| per column fragment
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+        const int gm = m0 + wm * G::WR + i * 16 + 4 * (l >> 4) + r;
         const int gn = n0 + wn * 32 + j * 16 + (l & 15);
         double v = (double)acc0[i][j][r] + (double)acc1[i][j][r];
         if (BIGK) v += acc64[BIGK ? i : 0][BIGK ? j : 0][r];
@@ -476,7 +492,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   if (d.cmax) {
     // column maxima of this tile's stored values (its rows only): over the
     // lane's rows, the four lane groups of a column, then the two row waves
-    __shared__ int cms[2][FT];
+    __shared__ int cms[2][TS];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       cm[j] = max(cm[j], __shfl_xor(cm[j], 16, 64));
@@ -484,7 +500,7 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
       if (l < 16) cms[wm][wn * 32 + j * 16 + l] = cm[j];
     }
     __syncthreads();
-    if (tid < FT && n0 + tid < d.N)
+    if (tid < TS && n0 + tid < d.N)
       d.cmax[(long long)bb * d.scm + (long long)tm * d.N + n0 + tid] = (unsigned)max(cms[0][tid], cms[1][tid]);
   }
 }
@@ -520,14 +536,16 @@ struct ExRaw {
 // VEC: norb % 4 == 0 (rows 16-byte aligned): two float4 per row and stage, at
 // addresses clamped into the row (a column block past the end re-reads the
 // last four values, masked at the store).
-template <bool VEC>
+template <bool VEC, int TS>
 __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntiles) {
-  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][3][FT][KT];
-  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][3][FT][KT];
+  typedef Tile<TS> G;
+  constexpr int FM = G::FM;
+  __shared__ __attribute__((aligned(16))) __bf16 Xs[2][3][TS][KT];
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][3][TS][KT];
 
   const int tid = threadIdx.x;
   const int l = tid & 63, w = tid >> 6;
-  const int wm = w >> 2, wn = w & 3;
+  const int wm = w / G::WN, wn = w % G::WN;
 
   const int logical = xcd_logical(blockIdx.x, gridDim.x);
   const int ngrp = (d.naux + d.fold - 1) / d.fold;
@@ -536,7 +554,7 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
   const int grp = r / ntiles;
   const int t = r - grp * ntiles;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
-  const int m0 = tm * FT, n0 = tn * FT;
+  const int m0 = tm * TS, n0 = tn * TS;
   const int n = d.norb;
   const float* __restrict__ bI = d.b + (long long)inst * d.sb;
   const float* __restrict__ StI = d.St + (long long)inst * n * n;
@@ -625,10 +643,10 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
     }
   };
 
-  f4v acc[4][2];
-  d4v acc64[4][2];
+  f4v acc[FM][2];
+  d4v acc64[FM][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       acc[i][j] = f4v{0, 0, 0, 0};
@@ -643,12 +661,12 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
 #pragma unroll
       for (int q = 0; q < 3; ++q) b[j][q] = *(const bf8v*)&Ys[buf][q][wn * 32 + j * 16 + (l & 15)][kl];
 #pragma unroll
-    for (int ip = 0; ip < 4; ip += 2) {
+    for (int ip = 0; ip < FM; ip += 2) {
       bf8v a[2][3];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) a[i][q] = *(const bf8v*)&Xs[buf][q][wm * 64 + (ip + i) * 16 + (l & 15)][kl];
+        for (int q = 0; q < 3; ++q) a[i][q] = *(const bf8v*)&Xs[buf][q][wm * G::WR + (ip + i) * 16 + (l & 15)][kl];
 #pragma unroll
       for (int o = 2; o >= 0; --o)
 #pragma unroll
@@ -664,7 +682,7 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
     if (s & 1) {   // each pair's FP32 sums (64 q of one slab) into FP64: the
                    // result does not depend on how the slabs are grouped
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -700,20 +718,21 @@ __device__ __forceinline__ void exch_body(const ExDesc& d, int tiles_n, int ntil
 
   double* __restrict__ Out = d.Out + (long long)inst * d.so + (long long)grp * n * n;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+        const int gm = m0 + wm * G::WR + i * 16 + 4 * (l >> 4) + r;
         const int gn = n0 + wn * 32 + j * 16 + (l & 15);
         if (gm < n && gn < n) Out[(long long)gm * n + gn] = acc64[i][j][r];
       }
 }
 
-template <bool VEC>
-__global__ __launch_bounds__(NTHR, 1) void k_exchange_fock_fx(ExDesc d, int tiles_n, int ntiles) {
-  exch_body<VEC>(d, tiles_n, ntiles);
+template <bool VEC, int TS>
+__global__ __launch_bounds__(Tile<TS>::NT, Tile<TS>::MINB) void k_exchange_fock_fx(ExDesc d, int tiles_n,
+                                                                                    int ntiles) {
+  exch_body<VEC, TS>(d, tiles_n, ntiles);
 }
 
 // St_i[s][q] = (float)S_i[q][s] for ninst matrices n^2 apart
@@ -727,35 +746,52 @@ __global__ void k_transpose_f32(const double* __restrict__ S, int n, int ninst, 
   }
 }
 
-#define NOF_FX_KERNEL(NAME)                                                              \
-  template <int XM, bool YPS, bool BIGK>                                                 \
-  __global__ __launch_bounds__(NTHR, 1) void NAME(FxDesc d, int tiles_n, int ntiles) {   \
-    fx_body<XM, YPS, BIGK>(d, tiles_n, ntiles);                                          \
+#define NOF_FX_KERNEL(NAME)                                                               \
+  template <int XM, bool YPS, bool BIGK, int TS>                                          \
+  __global__ __launch_bounds__(Tile<TS>::NT, Tile<TS>::MINB) void NAME(FxDesc d, int tiles_n, \
+                                                                       int ntiles) {      \
+    fx_body<XM, YPS, BIGK, TS>(d, tiles_n, ntiles);                                       \
   }
 NOF_FX_KERNEL(k_transform_stage1_fx)
 NOF_FX_KERNEL(k_transform_stage2_fx)
 #undef NOF_FX_KERNEL
 
-template <int XM, bool YPS, bool BIGK>
+template <int XM, bool YPS, bool BIGK, int TS = 128>
 int launch_fx(const FxDesc& d, hipStream_t st) {
-  const int tiles_m = (d.M + FT - 1) / FT;
-  const int tiles_n = (d.N + FT - 1) / FT;
+  const int tiles_m = (d.M + TS - 1) / TS;
+  const int tiles_n = (d.N + TS - 1) / TS;
   const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
   const long long G = (long long)ntiles * d.batch;
   if (G <= 0) return NOF_OK;
   if (G > 0x7fffffffLL) return NOF_E_DIM;
   if (d.role == 1)
-    hipLaunchKernelGGL((k_transform_stage1_fx<XM, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
-                       tiles_n, ntiles);
+    hipLaunchKernelGGL((k_transform_stage1_fx<XM, YPS, BIGK, TS>), dim3((unsigned)G), dim3(Tile<TS>::NT), 0,
+                       st, d, tiles_n, ntiles);
   else
-    hipLaunchKernelGGL((k_transform_stage2_fx<XM, YPS, BIGK>), dim3((unsigned)G), dim3(NTHR), 0, st, d,
-                       tiles_n, ntiles);
+    hipLaunchKernelGGL((k_transform_stage2_fx<XM, YPS, BIGK, TS>), dim3((unsigned)G), dim3(Tile<TS>::NT), 0,
+                       st, d, tiles_n, ntiles);
   return launch_status();
 }
 
 long long grid_for(long long items, int per_block) {
   long long g = (items + per_block - 1) / per_block;
   return g < 1 ? 1 : (g > 65536 ? 65536 : g);
+}
+
+template <int TS>
+int launch_exchange_fx(const ExDesc& d, hipStream_t st) {
+  const int tiles_n = (d.norb + TS - 1) / TS;
+  const int ntiles = tiles_n * tiles_n;
+  const int groups = (d.naux + d.fold - 1) / d.fold;
+  const long long G = (long long)ntiles * groups * d.ninst;
+  if (G > 0x7fffffffLL) return NOF_E_DIM;
+  if (d.norb % 4 == 0)
+    hipLaunchKernelGGL((k_exchange_fock_fx<true, TS>), dim3((unsigned)G), dim3(Tile<TS>::NT), 0, st, d, tiles_n,
+                       ntiles);
+  else
+    hipLaunchKernelGGL((k_exchange_fock_fx<false, TS>), dim3((unsigned)G), dim3(Tile<TS>::NT), 0, st, d,
+                       tiles_n, ntiles);
+  return launch_status();
 }
 
 }  // namespace
@@ -765,7 +801,15 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
   if (d.sym && (d.M != d.N)) return NOF_E_DIM;
   if ((!x_planes && !d.ex) || (!y_planes && !d.ey)) return NOF_E_NULL;
   if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
+  if (d.tile != 128 && d.tile != 64) return NOF_E_ARG;
   const bool big = d.K > EXACT_K;
+  // 64-wide tiles for pre-split X only (the batched transform stages)
+  if (d.tile == 64) {
+    if (!x_planes) return NOF_E_ARG;
+    if (y_planes)
+      return big ? launch_fx<0, true, true, 64>(d, st) : launch_fx<0, true, false, 64>(d, st);
+    return big ? launch_fx<0, false, true, 64>(d, st) : launch_fx<0, false, false, 64>(d, st);
+  }
   if (x_planes && y_planes)
     return big ? launch_fx<0, true, true>(d, st) : launch_fx<0, true, false>(d, st);
   if (x_planes && !y_planes)
@@ -790,6 +834,7 @@ int fx_transpose(const double* S, int n, int ninst, float* St, hipStream_t st) {
 
 int exchange_fock_fx(const ExDesc& d0, const double* S, float* St, hipStream_t st) {
   if (d0.naux <= 0 || d0.norb <= 0 || d0.fold <= 0 || d0.ninst <= 0) return NOF_E_DIM;
+  if (d0.tile != 128 && d0.tile != 64) return NOF_E_ARG;
   const long long nn = (long long)d0.norb * d0.norb;
   hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)grid_for(nn * d0.ninst, 256)), dim3(256), 0, st, S,
                      d0.norb, d0.ninst, St);
@@ -797,16 +842,7 @@ int exchange_fock_fx(const ExDesc& d0, const double* S, float* St, hipStream_t s
   if (rc != NOF_OK) return rc;
   ExDesc d = d0;
   d.St = St;
-  const int tiles_n = (d.norb + FT - 1) / FT;
-  const int ntiles = tiles_n * tiles_n;
-  const int groups = (d.naux + d.fold - 1) / d.fold;
-  const long long G = (long long)ntiles * groups * d.ninst;
-  if (G > 0x7fffffffLL) return NOF_E_DIM;
-  if (d.norb % 4 == 0)
-    hipLaunchKernelGGL(k_exchange_fock_fx<true>, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
-  else
-    hipLaunchKernelGGL(k_exchange_fock_fx<false>, dim3((unsigned)G), dim3(NTHR), 0, st, d, tiles_n, ntiles);
-  return launch_status();
+  return d.tile == 64 ? launch_exchange_fx<64>(d, st) : launch_exchange_fx<128>(d, st);
 }
 
 int fx_row_exps(const void* A, int At, long long nrow, int K, int* e, hipStream_t st) {

@@ -79,13 +79,23 @@ def test_batch_x10_matches_single_instance(src):
     plan = nof.BatchPlan(Bs, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
     assert plan.prec == nof.P_BF16X10
     ref = [single(nof, Bs, C[i], H[i], n[i], cJ[i], cK[i], nof.P_BF16X10) for i in range(ninst)]
-    for cfg in ([128, 128, 128, 1], [128, 128, 128, 3], [128, 128, 128, naux], None):
+    same = {}
+    for cfg in ([128, 128, 128, 1], [128, 128, 128, 3], [128, 128, 128, naux], [64, 64, 64, 3],
+                [64, 128, 64, 1], [128, 64, 128, naux], None):
         if cfg is None:
             plan.autotune()
         else:
             plan.config = cfg
         E, lam, g = plan.iteration()
         torch.cuda.synchronize()
+        if cfg is not None:
+            # every output element is summed in the same order at either tile
+            # edge: configurations with the same exchange split agree exactly
+            got = (host(E), host(lam), host(g))
+            if cfg[3] in same:
+                for u, v in zip(got, same[cfg[3]]):
+                    assert np.array_equal(u, v), cfg
+            same[cfg[3]] = got
         for i in range(ninst):
             assert abs(float(E[i]) - ref[i][0]) <= 1e-12 * abs(ref[i][0]), (cfg, i)
             assert normwise(host(lam[i]), ref[i][1]) <= 1e-12, (cfg, i)
@@ -113,13 +123,22 @@ def test_batch_i8x10_matches_single_instance():
     plan = nof.BatchPlan(Bs, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
     assert plan.prec == nof.P_I8X10
     ref = [single(nof, Bs, C[i], H[i], n[i], cJ[i], cK[i], nof.P_I8X10) for i in range(ninst)]
-    for cfg in ([128, 128, 128, 1], [128, 128, 128, 3], None):
+    same = {}
+    for cfg in ([128, 128, 128, 1], [128, 128, 128, 3], [128, 128, 64, 3], [64, 64, 64, 1], None):
         if cfg is None:
             plan.autotune()
         else:
             plan.config = cfg
         E, lam, g = plan.iteration()
         torch.cuda.synchronize()
+        if cfg is not None:
+            # the exchange-type product at a 64 or 128 tile edge (the INT8
+            # transform has one): same exchange split, same results
+            got = (host(E), host(lam), host(g))
+            if cfg[3] in same:
+                for u, v in zip(got, same[cfg[3]]):
+                    assert np.array_equal(u, v), cfg
+            same[cfg[3]] = got
         for i in range(ninst):
             assert abs(float(E[i]) - ref[i][0]) <= 1e-12 * abs(ref[i][0]), (cfg, i)
             assert normwise(host(lam[i]), ref[i][1]) <= 3e-7, (cfg, i)
@@ -128,6 +147,32 @@ def test_batch_i8x10_matches_single_instance():
     o = dfjk.iteration(B, C[2], H[2], n[2], cJ[2], cK[2])
     assert abs(float(E[2]) - o["E"]) <= 2e-8 * abs(o["E"])
     assert normwise(host(lam[2]), o["lam"]) <= 3e-7
+
+
+def test_batch_x10_tile_edges_long_contraction():
+    """Nbf above 1024: both transform stages of the x10 plan add their
+    order-0 FP32 sums to FP64 every 1024 terms.  The 64-wide tiles (two
+    workgroups per CU, four waves) give exactly the 128-wide tiles' results
+    there too, with ragged edges in every tiled dimension (Nbf = 1100, Norb =
+    70, two instances: 140 packed columns)."""
+    nof = need_gpu()
+    print("case batched x10 tile edges, nbf 1100", flush=True)
+    ninst, nbf, naux, norb = 2, 1100, 6, 70
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3004, 9)
+    Bs = nof.SplitB(dev(B))
+    plan = nof.BatchPlan(Bs, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
+    out = []
+    for cfg in ([128, 128, 128, 2], [64, 64, 64, 2], [64, 128, 128, 2], [128, 64, 64, 2]):
+        plan.config = cfg
+        E, lam, g = plan.iteration()
+        torch.cuda.synchronize()
+        out.append((host(E), host(lam), host(g)))
+    for o in out[1:]:
+        for u, v in zip(o, out[0]):
+            assert np.array_equal(u, v)
+    ref = single(nof, Bs, C[1], H[1], n[1], cJ[1], cK[1], nof.P_BF16X10)
+    assert abs(float(out[0][0][1]) - ref[0]) <= 1e-12 * abs(ref[0])
+    assert normwise(out[0][1][1], ref[1]) <= 1e-12
 
 
 @pytest.mark.parametrize("prec_name", ["f64", "f32", "x10", "i8x10"])
