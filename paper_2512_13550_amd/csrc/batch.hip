@@ -50,6 +50,14 @@ namespace {
 // The fixed-point forms (BF16 or INT8 pieces) share b in FP32, the x10
 // exchange-type product and the Coulomb-type term from the pass.
 bool fixed_point_plan(const nof_plan_s* p) { return p->prec == NOF_P_BF16X10 || p->prec == NOF_P_I8X10; }
+// Stage 1 of the fixed-point plans takes the rows of all slabs as one M when
+// a slab holds at least one tile of rows: no slab is padded to whole tiles.
+bool fold_stage1(const nof_plan_s* p, int tile) {
+  return p->nbf >= tile && (long long)p->naux * p->nbf + p->nbf <= 0x7fffffffLL;
+}
+long long stage1_cmax_words(const nof_plan_s* p, int tile) {
+  return cmax_words(p->naux, p->nbf, (long long)p->ninst * p->norb, tile, fold_stage1(p, tile));
+}
 
 void plan_layout(nof_plan_s* p) {
   const size_t ni = p->ninst, na = p->naux, nb = p->nbf, no = p->norb;
@@ -83,7 +91,9 @@ void plan_layout(nof_plan_s* p) {
   const bool i8 = p->prec == NOF_P_I8X10;
   const size_t ldk = (size_t)presplit_ldk(p->nbf), ldc = ni * no;
   sz[O_CPL] = !fx ? 0 : i8 ? i8_planes_bytes((long long)ldc, p->nbf) + ldc * 4 : 4 * ldc * ldk * 2;
-  sz[O_CMX] = fx ? na * (size_t)fx_tiles(p->nbf, p->prec == NOF_P_BF16X10 ? 64 : 128) * ldc * 4 : 0;
+  sz[O_CMX] = fx ? (size_t)std::max(stage1_cmax_words(p, 128),
+                                     p->prec == NOF_P_BF16X10 ? stage1_cmax_words(p, 64) : 0LL) * 4
+               : 0;
   sz[O_EY] = fx ? na * ldc * 4 : 0;
   sz[O_ST] = fx ? ni * no * no * 4 : 0;
   sz[O_TPL] = i8 ? i8_planes_bytes((long long)na * ldc, p->nbf) : 0;
@@ -129,17 +139,19 @@ int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
                            cpl, ce, st);
     if (rc != NOF_OK) return rc;
     const unsigned char* Bp = (const unsigned char*)a.B;
+    const bool fold = fold_stage1(p, 128);
     I8Desc f{};
-    f.M = p->nbf; f.N = (int)ldc; f.K = p->nbf; f.batch = p->naux;
-    f.X = Bp; f.ldx = ldk; f.sx = (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
-    f.ex = (const int*)(Bp + i8_planes_bytes((long long)p->naux * p->nbf, p->nbf)); f.sex = p->nbf;
+    f.M = fold ? p->naux * p->nbf : p->nbf; f.N = (int)ldc; f.K = p->nbf; f.batch = fold ? 1 : p->naux;
+    f.X = Bp; f.ldx = ldk; f.sx = fold ? 0 : (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
+    f.ex = (const int*)(Bp + i8_planes_bytes((long long)p->naux * p->nbf, p->nbf)); f.sex = fold ? 0 : p->nbf;
     f.Y = cpl; f.ldy = ldk; f.sy = 0; f.psy = ldc * ldk; f.ey = ce; f.sey = 0;
-    f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = (long long)p->nbf * ldc;
-    f.sym = false; f.role = 1;
-    f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)fx_tiles(p->nbf) * ldc;
+    f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = fold ? 0 : (long long)p->nbf * ldc;
+    f.sym = false; f.role = 1; f.mslab = fold ? p->nbf : 0;
+    const int rt = fx_tiles(f.M, 128);
+    f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)rt * ldc;
     if ((rc = gemm_i8(f, st)) != NOF_OK) return rc;
     int* te = (int*)(a.ws + p->off[O_EY]);
-    if ((rc = i8_cmax_exps(f.cmax, p->naux, fx_tiles(p->nbf), (int)ldc, te, st)) != NOF_OK) return rc;
+    if ((rc = i8_cmax_exps(f.cmax, p->naux, rt, (int)ldc, te, st, f.mslab)) != NOF_OK) return rc;
     return i8_split_T(f.Out, p->naux, p->nbf, (int)ldc, (long long)p->nbf * ldc, (int)ldk, te,
                       a.ws + p->off[O_TPL], st);
   }
@@ -152,16 +164,17 @@ int run_stage1(nof_plan_s* p, const Args& a, hipStream_t st) {
     int rc = fx_split_cols((const double*)(a.ws + p->off[O_CALL]), p->nbf, (int)ldc, (int)ldc, (int)ldk,
                            cpl, st);
     if (rc != NOF_OK) return rc;
+    const bool fold = fold_stage1(p, p->tile_s1);
     FxDesc f{};
-    f.M = p->nbf; f.N = (int)ldc; f.K = p->nbf; f.batch = p->naux;
-    f.X = a.B; f.ldx = ldk; f.sx = (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
+    f.M = fold ? p->naux * p->nbf : p->nbf; f.N = (int)ldc; f.K = p->nbf; f.batch = fold ? 1 : p->naux;
+    f.X = a.B; f.ldx = ldk; f.sx = fold ? 0 : (long long)p->nbf * ldk; f.psx = (long long)p->naux * p->nbf * ldk;
     f.Y = cpl; f.ldy = ldk; f.sy = 0; f.psy = ldc * ldk;
-    f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = (long long)p->nbf * ldc;
-    f.sym = false; f.role = 1; f.tile = p->tile_s1;
-    const int rt = fx_tiles(p->nbf, p->tile_s1);
+    f.Out = (float*)(a.ws + p->off[O_T]); f.ldo = ldc; f.so = fold ? 0 : (long long)p->nbf * ldc;
+    f.sym = false; f.role = 1; f.tile = p->tile_s1; f.mslab = fold ? p->nbf : 0;
+    const int rt = fx_tiles(f.M, p->tile_s1);
     f.cmax = (unsigned*)(a.ws + p->off[O_CMX]); f.scm = (long long)rt * ldc;
     if ((rc = gemm_fx(f, true, true, st)) != NOF_OK) return rc;
-    return fx_cmax_exps(f.cmax, p->naux, rt, (int)ldc, (int*)(a.ws + p->off[O_EY]), st);
+    return fx_cmax_exps(f.cmax, p->naux, rt, (int)ldc, (int*)(a.ws + p->off[O_EY]), st, f.mslab, p->tile_s1);
   }
   GemmDesc g{};
   g.M = p->nbf; g.N = p->ninst * p->norb; g.K = p->nbf;

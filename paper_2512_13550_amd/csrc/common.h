@@ -105,12 +105,38 @@ struct FxDesc {
   int binner = 0;
   long long sx2 = 0, sy2 = 0, sey2 = 0, so2 = 0, sd2 = 0;
   int tile = 128;                  // workgroup tile edge: 128, or 64 with pre-split X
+  // Slabs folded into rows (batch 1, not sym, with cmax): M = nslab * mslab
+  // rows, slab b = rows b*mslab.., mslab >= tile.  cmax then keeps per row
+  // tile t the maxima over the rows of its first slab at cmax[t*N + n] and,
+  // for a tile that reaches into slab b + 1, over those rows at
+  // cmax[scm + (b+1)*N + n] (scm = row tiles * N); see cmax_words.
+  int mslab = 0;
 };
 int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st);
 // Column grid exponents e[b*N + n] from the row-tile maxima above.
-int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st);
+// mslab > 0: cmax of a folded product over `batch` slabs of mslab rows,
+// `tiles` its row tiles at edge ts.
+int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st, int mslab = 0,
+                 int ts = 128);
 // Row tiles of n rows at tile edge ts (the cmax layout).
 inline int fx_tiles(int n, int ts = 128) { return (n + ts - 1) / ts; }
+// cmax words of a stage-1 product over nslab slabs of mslab rows and N
+// columns at tile edge ts: per slab (folded = false) or with the slabs'
+// rows folded into one M (folded = true, mslab >= ts).
+inline long long cmax_words(long long nslab, int mslab, long long N, int ts, bool folded) {
+  return folded ? ((nslab * mslab + ts - 1) / ts + nslab) * N : nslab * fx_tiles(mslab, ts) * N;
+}
+// Largest column maximum of slab b (column n) from a folded cmax: the row
+// tiles that start inside the slab, and the tile that starts in slab b - 1
+// and reaches into it (when the slab does not start on a tile edge).
+__device__ inline unsigned slab_cmax(const unsigned* cmax, long long b, int mslab, int ts, long long tiles,
+                                     int N, int n) {
+  const long long r0 = b * mslab;
+  unsigned m = 0;
+  for (long long t = (r0 + ts - 1) / ts; t * ts < r0 + mslab; ++t) m = max(m, cmax[t * N + n]);
+  if (r0 % ts) m = max(m, cmax[(tiles + b) * N + n]);
+  return m;
+}
 // INT8 fixed-point transform stage (gemm_i8.hip, NOF_P_I8X10):
 //   Out_b[m][n] = sum_k X_b(k, m) Y_b(k, n)   (FP32 out, FP64 diagonal Dg if sym)
 // X: INT8 planes at X + q*psx + b*sx + m*ldx + k (ldx a multiple of 64, zero
@@ -131,6 +157,7 @@ struct I8Desc {
   int binner;
   long long sx2, sex2, sy2, sey2, so2, sd2;
   double* Out64;                   // if set (not sym, no cmax): FP64 results here instead of Out
+  int mslab;                       // slabs folded into rows, as in FxDesc (tile edge 128)
 };
 int gemm_i8(const I8Desc& d, hipStream_t st);
 // Exchange-type Fock partials of the INT8 form (gemm_i8.hip):
@@ -154,7 +181,7 @@ int i8_split_rows(const void* A, int At, long long nrow, int K, int ldk, void* p
                   hipStream_t st);
 int i8_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* planes, int* e,
                   hipStream_t st);
-int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st);
+int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st, int mslab = 0);
 int i8_split_T(const float* T, int batch, int K, int N, long long sT, int ldk, const int* e, void* planes,
                hipStream_t st);
 

@@ -142,17 +142,22 @@ __global__ void k_col_exps(const float* __restrict__ A, int batch, int K, int N,
 }
 
 // Grid exponents of the columns of T_b from the per-row-tile column maxima
-// that the stage-1 epilogue wrote: e[b*N + n] from max_t cmax[b][t][n].
+// that the stage-1 epilogue wrote: e[b*N + n] from max_t cmax[b][t][n], or
+// (mslab > 0) from the folded layout (slab_cmax).
 __global__ void k_cmax_exps(const unsigned* __restrict__ cmax, long long batch, int tiles, int N,
-                            int* __restrict__ e) {
+                            int* __restrict__ e, int mslab, int ts) {
   const long long total = batch * N;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long b = i / N;
     const int n = (int)(i - b * N);
-    const unsigned* c = cmax + b * tiles * N + n;
     unsigned m = 0;
-    for (int t = 0; t < tiles; ++t) m = max(m, c[(long long)t * N]);
+    if (mslab > 0) {
+      m = slab_cmax(cmax, b, mslab, ts, tiles, N, n);
+    } else {
+      const unsigned* c = cmax + b * tiles * N + n;
+      for (int t = 0; t < tiles; ++t) m = max(m, c[(long long)t * N]);
+    }
     e[i] = grid_exp_bits(m);
   }
 }
@@ -467,7 +472,11 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   }
 
   float* __restrict__ Out = d.Out + ib * d.so + ob * d.so2;
-  int cm[2] = {0, 0};      // bits of the largest |stored value| per column fragment
+  // bits of the largest |stored value| per column fragment, over the rows of
+  // the tile's first slab (cm) and, with folded slabs, of the next (cm2:
+  // rows from bnd on)
+  int cm[2] = {0, 0}, cm2[2] = {0, 0};
+  const int bnd = d.mslab > 0 ? (m0 / d.mslab + 1) * d.mslab : 0x7fffffff;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -480,7 +489,11 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
         if (BIGK) v += acc64[BIGK ? i : 0][BIGK ? j : 0][r];
         if (gm >= d.M || gn >= d.N) continue;
         const float fv = (float)v;
-        cm[j] = max(cm[j], (int)(__float_as_uint(fv) & 0x7fffffffu));
+        const int vb = (int)(__float_as_uint(fv) & 0x7fffffffu);
+        if (gm < bnd)
+          cm[j] = max(cm[j], vb);
+        else
+          cm2[j] = max(cm2[j], vb);
         if (!d.sym) {
           Out[(long long)gm * d.ldo + gn] = fv;
         } else if (gm <= gn) {
@@ -492,16 +505,30 @@ __device__ __forceinline__ void fx_body(const FxDesc& d, int tiles_n, int ntiles
   if (d.cmax) {
     // column maxima of this tile's stored values (its rows only): over the
     // lane's rows, the four lane groups of a column, then the two row waves
-    __shared__ int cms[2][TS];
+    __shared__ int cms[2][2][TS];       // [slab part][wave row][column]
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       cm[j] = max(cm[j], __shfl_xor(cm[j], 16, 64));
       cm[j] = max(cm[j], __shfl_xor(cm[j], 32, 64));
-      if (l < 16) cms[wm][wn * 32 + j * 16 + l] = cm[j];
+      cm2[j] = max(cm2[j], __shfl_xor(cm2[j], 16, 64));
+      cm2[j] = max(cm2[j], __shfl_xor(cm2[j], 32, 64));
+      if (l < 16) {
+        cms[0][wm][wn * 32 + j * 16 + l] = cm[j];
+        cms[1][wm][wn * 32 + j * 16 + l] = cm2[j];
+      }
     }
     __syncthreads();
-    if (tid < TS && n0 + tid < d.N)
-      d.cmax[(long long)bb * d.scm + (long long)tm * d.N + n0 + tid] = (unsigned)max(cms[0][tid], cms[1][tid]);
+    if (tid < TS && n0 + tid < d.N) {
+      const unsigned m1 = (unsigned)max(cms[0][0][tid], cms[0][1][tid]);
+      if (d.mslab > 0) {
+        d.cmax[(long long)tm * d.N + n0 + tid] = m1;
+        if (min(m0 + TS, d.M) > bnd)      // the tile reaches into slab bnd / mslab
+          d.cmax[d.scm + (long long)(bnd / d.mslab) * d.N + n0 + tid] =
+              (unsigned)max(cms[1][0][tid], cms[1][1][tid]);
+      } else {
+        d.cmax[(long long)bb * d.scm + (long long)tm * d.N + n0 + tid] = m1;
+      }
+    }
   }
 }
 
@@ -802,6 +829,10 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
   if ((!x_planes && !d.ex) || (!y_planes && !d.ey)) return NOF_E_NULL;
   if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
   if (d.tile != 128 && d.tile != 64) return NOF_E_ARG;
+  if (d.mslab < 0) return NOF_E_ARG;
+  if (d.mslab > 0 && (d.batch != 1 || d.sym || !d.cmax || d.binner || d.mslab < d.tile || d.M % d.mslab ||
+                      (long long)d.M + d.mslab > 0x7fffffffLL))
+    return NOF_E_ARG;
   const bool big = d.K > EXACT_K;
   // 64-wide tiles for pre-split X only (the batched transform stages)
   if (d.tile == 64) {
@@ -864,10 +895,12 @@ int fx_col_exps(const float* A, int batch, int K, int N, long long sa, int* e, h
   return launch_status();
 }
 
-int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st) {
-  if (batch <= 0 || tiles <= 0 || N <= 0) return NOF_E_DIM;
+int fx_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st, int mslab,
+                 int ts) {
+  if (batch <= 0 || tiles <= 0 || N <= 0 || mslab < 0 || (mslab > 0 && (ts <= 0 || mslab < ts)))
+    return NOF_E_DIM;
   const unsigned g = (unsigned)grid_for((long long)batch * N, 256);
-  hipLaunchKernelGGL(k_cmax_exps, dim3(g), dim3(256), 0, st, cmax, (long long)batch, tiles, N, e);
+  hipLaunchKernelGGL(k_cmax_exps, dim3(g), dim3(256), 0, st, cmax, (long long)batch, tiles, N, e, mslab, ts);
   return launch_status();
 }
 

@@ -167,17 +167,22 @@ __global__ void k_split_cols_i8(const double* __restrict__ A, int K, int ncol, i
 }
 
 // Grid exponents of the columns of T_b (FP32) from the per-row-tile column
-// maxima of the stage-1 epilogue: e[b*N + n] from max_t cmax[b][t][n].
+// maxima of the stage-1 epilogue: e[b*N + n] from max_t cmax[b][t][n], or
+// (mslab > 0) from the folded layout (slab_cmax, tile edge IT).
 __global__ void k_cmax_exps_i8(const unsigned* __restrict__ cmax, long long batch, int tiles, int N,
-                               int* __restrict__ e) {
+                               int* __restrict__ e, int mslab) {
   const long long total = batch * N;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long b = i / N;
     const int n = (int)(i - b * N);
-    const unsigned* c = cmax + b * tiles * N + n;
     unsigned m = 0;
-    for (int t = 0; t < tiles; ++t) m = max(m, c[(long long)t * N]);
+    if (mslab > 0) {
+      m = slab_cmax(cmax, b, mslab, IT, tiles, N, n);
+    } else {
+      const unsigned* c = cmax + b * tiles * N + n;
+      for (int t = 0; t < tiles; ++t) m = max(m, c[(long long)t * N]);
+    }
     e[i] = grid_exp_i8_bits(m);
   }
 }
@@ -372,7 +377,11 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
     const int gn = n0 + wn * 32 + j * 16 + (l & 15);
     eyc[j] = gn < d.N ? ey[gn] : 0;
   }
-  int cm[2] = {0, 0};      // bits of the largest |stored value| per column fragment
+  // bits of the largest |stored value| per column fragment, over the rows of
+  // the tile's first slab (cm) and, with folded slabs, of the next (cm2:
+  // rows from bnd on)
+  int cm[2] = {0, 0}, cm2[2] = {0, 0};
+  const int bnd = d.mslab > 0 ? (m0 / d.mslab + 1) * d.mslab : 0x7fffffff;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -394,7 +403,11 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
           continue;
         }
         const float fv = (float)v;
-        cm[j] = max(cm[j], (int)(__float_as_uint(fv) & 0x7fffffffu));
+        const int vb = (int)(__float_as_uint(fv) & 0x7fffffffu);
+        if (gm < bnd)
+          cm[j] = max(cm[j], vb);
+        else
+          cm2[j] = max(cm2[j], vb);
         if (!d.sym) {
           Out[(long long)gm * d.ldo + gn] = fv;
         } else if (gm <= gn) {
@@ -407,16 +420,30 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
   if (d.cmax) {
     // column maxima of this tile's stored values over its rows: the lane's
     // rows, the four lane groups of a column, then the two row waves
-    __shared__ int cms[2][IT];
+    __shared__ int cms[2][2][IT];       // [slab part][wave row][column]
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       cm[j] = max(cm[j], __shfl_xor(cm[j], 16, 64));
       cm[j] = max(cm[j], __shfl_xor(cm[j], 32, 64));
-      if (l < 16) cms[wm][wn * 32 + j * 16 + l] = cm[j];
+      cm2[j] = max(cm2[j], __shfl_xor(cm2[j], 16, 64));
+      cm2[j] = max(cm2[j], __shfl_xor(cm2[j], 32, 64));
+      if (l < 16) {
+        cms[0][wm][wn * 32 + j * 16 + l] = cm[j];
+        cms[1][wm][wn * 32 + j * 16 + l] = cm2[j];
+      }
     }
     __syncthreads();
-    if (tid < IT && n0 + tid < d.N)
-      d.cmax[bb * d.scm + (long long)tm * d.N + n0 + tid] = (unsigned)max(cms[0][tid], cms[1][tid]);
+    if (tid < IT && n0 + tid < d.N) {
+      const unsigned m1 = (unsigned)max(cms[0][0][tid], cms[0][1][tid]);
+      if (d.mslab > 0) {
+        d.cmax[(long long)tm * d.N + n0 + tid] = m1;
+        if (min(m0 + IT, d.M) > bnd)      // the tile reaches into slab bnd / mslab
+          d.cmax[d.scm + (long long)(bnd / d.mslab) * d.N + n0 + tid] =
+              (unsigned)max(cms[1][0][tid], cms[1][1][tid]);
+      } else {
+        d.cmax[bb * d.scm + (long long)tm * d.N + n0 + tid] = m1;
+      }
+    }
   }
 }
 
@@ -616,6 +643,10 @@ int gemm_i8(const I8Desc& d, hipStream_t st) {
   if (d.Out64 && (d.sym || d.cmax)) return NOF_E_ARG;
   if (d.ldx % IK || d.ldy % IK || d.ldx < d.K || d.ldy < d.K) return NOF_E_DIM;
   if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
+  if (d.mslab < 0) return NOF_E_ARG;
+  if (d.mslab > 0 && (d.batch != 1 || d.sym || !d.cmax || d.Out64 || d.binner || d.mslab < IT ||
+                      d.M % d.mslab || (long long)d.M + d.mslab > 0x7fffffffLL))
+    return NOF_E_ARG;
   const int tiles_m = (d.M + IT - 1) / IT;
   const int tiles_n = (d.N + IT - 1) / IT;
   const int ntiles = d.sym ? tiles_n * (tiles_n + 1) / 2 : tiles_m * tiles_n;
@@ -748,10 +779,10 @@ int i8_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* plan
   return launch_status();
 }
 
-int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st) {
-  if (batch <= 0 || tiles <= 0 || N <= 0) return NOF_E_DIM;
+int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st, int mslab) {
+  if (batch <= 0 || tiles <= 0 || N <= 0 || mslab < 0 || (mslab > 0 && mslab < IT)) return NOF_E_DIM;
   const unsigned g = (unsigned)grid_of((long long)batch * N, 256);
-  hipLaunchKernelGGL(k_cmax_exps_i8, dim3(g), dim3(256), 0, st, cmax, (long long)batch, tiles, N, e);
+  hipLaunchKernelGGL(k_cmax_exps_i8, dim3(g), dim3(256), 0, st, cmax, (long long)batch, tiles, N, e, mslab);
   return launch_status();
 }
 

@@ -289,3 +289,36 @@ def test_batch_odd_norb_default_and_fold1(prec_name):
         for i in range(ninst):
             assert abs(float(E[i]) - ref[i][0]) <= tol * abs(ref[i][0]), (cfg, i)
             assert normwise(host(lam[i]), ref[i][1]) <= tol, (cfg, i)
+
+
+@pytest.mark.parametrize("prec_name", ["x10", "i8x10"])
+@pytest.mark.parametrize("nbf", [40, 100])
+def test_batch_fixed_point_stage1_layouts(prec_name, nbf):
+    """Stage 1 of the fixed-point plans takes the rows of all slabs as one
+    product when a slab holds a whole tile of rows (Nbf >= the tile edge: the
+    x10 plan at 64 for Nbf = 100), else one product per slab (Nbf = 40, and
+    Nbf = 100 at 128 or in the INT8 plan); T's column grids come from the
+    per-slab maxima either way.  Against the single-instance path (which
+    never folds): E to 1e-12; lambda to 1e-12 (x10: same products) or the
+    forms' 3e-7 (INT8: the plan's exchange-type term is the x10 one); the
+    x10 plan's two layouts agree exactly."""
+    nof = need_gpu()
+    print(f"case batched {prec_name} stage-1 layouts nbf {nbf}", flush=True)
+    ninst, naux, norb = 3, 20, 37
+    B, C, H, n, cJ, cK = instances(nbf, naux, norb, ninst, 3005, 9)
+    Bs = nof.SplitB(dev(B)) if prec_name == "x10" else nof.SplitBI8(dev(B))
+    prec = nof.P_BF16X10 if prec_name == "x10" else nof.P_I8X10
+    plan = nof.BatchPlan(Bs, dev(C), dev(H), dev(n), dev(cJ), dev(cK))
+    ref = [single(nof, Bs, C[i], H[i], n[i], cJ[i], cK[i], prec) for i in range(ninst)]
+    tl = 1e-12 if prec_name == "x10" else 3e-7
+    out = []
+    for cfg in ([128, 128, 128, 2], [64, 128, 128, 2]):
+        plan.config = cfg
+        E, lam, g = plan.iteration()
+        torch.cuda.synchronize()
+        out.append((host(E), host(lam), host(g)))
+        for i in range(ninst):
+            assert abs(float(E[i]) - ref[i][0]) <= 1e-12 * abs(ref[i][0]), (cfg, i)
+            assert normwise(host(lam[i]), ref[i][1]) <= tl, (cfg, i)
+    for u, v in zip(out[0], out[1]):
+        assert np.array_equal(u, v)
