@@ -182,30 +182,44 @@ int split_C(int nbf, int norb, const double* C, int prec, int Bt, void* ws, hipS
   return presplit_bf16(C, nbf, norb, norb, (int)presplit_ldk(nbf), np, ws, stream);
 }
 
+// Stage 1 of the fixed-point forms may take the rows (P, mu) of all slabs as
+// one product: when a slab holds at least one 128-row tile and the rows fit
+// int indexing.
+bool stage1_fold(int naux, int nbf) { return nbf >= 128 && (long long)naux * nbf + nbf <= 0x7fffffffLL; }
+
 // x10 stage 1 (T^P = B^P C) with the workspace w of one stage: C planes (one
 // grid per column), B planes or FP32 B with one grid per row (B^P symmetric:
 // row mu = column mu).  With cmax the epilogue also writes the column maxima
-// of T per row tile (the grids of the next stage's split).
+// of T per row tile, from which the grid exponents of T's columns (the grids
+// of the next stage's split) follow into w after the C planes.
 int fx_stage1(int naux, int nbf, int norb, const void* B, int Bt, const double* C, float* T, char* w,
               unsigned* cmax, hipStream_t stream) {
   const long long ldk = presplit_ldk(nbf);
   int* ex = (int*)(w + fx_planes_bytes(nbf, norb));
   NOF_TRY(fx_split_cols(C, nbf, norb, norb, (int)ldk, w, stream));
   FxDesc f{};
-  f.M = nbf; f.N = norb; f.K = nbf; f.batch = naux;
   const bool planes = Bt == NOF_BF16X4;
+  // planes: the rows (P, mu) of all slabs as one product when a slab holds a
+  // whole tile of rows (no slab padded to whole tiles)
+  const bool fold = planes && stage1_fold(naux, nbf);
+  f.M = fold ? naux * nbf : nbf; f.N = norb; f.K = nbf; f.batch = fold ? 1 : naux;
+  f.mslab = fold ? nbf : 0;
   f.X = B;
   if (planes) {
-    f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
+    f.ldx = ldk; f.sx = fold ? 0 : (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
   } else {
     NOF_TRY(fx_row_exps(B, Bt, (long long)naux * nbf, nbf, ex, stream));
     f.ldx = nbf; f.sx = (long long)nbf * nbf; f.ex = ex; f.sex = nbf; f.x_rows = true;
   }
   f.Y = w; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk;
-  f.Out = T; f.ldo = norb; f.so = (long long)nbf * norb;
+  f.Out = T; f.ldo = norb; f.so = fold ? 0 : (long long)nbf * norb;
   f.sym = false; f.role = 1;
-  f.cmax = cmax; f.scm = (long long)fx_tiles(nbf) * norb;
-  return gemm_fx(f, planes, true, stream);
+  f.cmax = cmax; f.scm = (long long)fx_tiles(f.M) * norb;
+  NOF_TRY(gemm_fx(f, planes, true, stream));
+  if (!cmax) return NOF_OK;
+  // the grid exponents of T's columns, per slab, after the C planes in w
+  return fx_cmax_exps(cmax, naux, fx_tiles(f.M), norb, (int*)(w + fx_planes_bytes(nbf, norb)), stream, f.mslab,
+                      128);
 }
 
 // x10 stage 2 (b^P = C^T T^P and D): C planes, T split in the loader on one
@@ -227,9 +241,12 @@ int fx_stage2(int naux, int nbf, int norb, const float* T, const double* C, floa
   return gemm_fx(f, true, false, stream);
 }
 
-// Column maxima of T per row tile (x10, nof_mo_transform only).
+// Column maxima of T per row tile (x10 and INT8, nof_mo_transform only), in
+// either stage-1 layout.
 size_t fx_cmax_bytes(int naux, int nbf, int norb) {
-  return align256((size_t)naux * fx_tiles(nbf) * norb * sizeof(unsigned));
+  long long w = cmax_words(naux, nbf, norb, 128, false);
+  if (stage1_fold(naux, nbf)) w = std::max(w, cmax_words(naux, nbf, norb, 128, true));
+  return align256((size_t)w * sizeof(unsigned));
 }
 
 // INT8 fixed-point transform.  B as written by nof_split_B_i8: planes
@@ -265,16 +282,18 @@ int i8_transform(int naux, int nbf, int norb, const void* B, const double* C, fl
   int* Te = (int*)(w + L.off_Te);
   unsigned char* Tp = (unsigned char*)(w + L.off_Tp);
   NOF_TRY(i8_split_cols(C, nbf, norb, norb, (int)ldk, Cp, Ce, stream));
+  // the rows (P, mu) of all slabs as one product when a slab holds a whole tile
+  const bool fold = stage1_fold(naux, nbf);
   I8Desc f{};
-  f.M = nbf; f.N = norb; f.K = nbf; f.batch = naux;
-  f.X = Bp; f.ldx = ldk; f.sx = (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
-  f.ex = Be; f.sex = nbf;
+  f.M = fold ? naux * nbf : nbf; f.N = norb; f.K = nbf; f.batch = fold ? 1 : naux;
+  f.X = Bp; f.ldx = ldk; f.sx = fold ? 0 : (long long)nbf * ldk; f.psx = (long long)naux * nbf * ldk;
+  f.ex = Be; f.sex = fold ? 0 : nbf;
   f.Y = Cp; f.ldy = ldk; f.sy = 0; f.psy = (long long)norb * ldk; f.ey = Ce; f.sey = 0;
-  f.Out = T; f.ldo = norb; f.so = (long long)nbf * norb;
-  f.sym = false; f.role = 1;
-  f.cmax = cmax; f.scm = (long long)fx_tiles(nbf) * norb;
+  f.Out = T; f.ldo = norb; f.so = fold ? 0 : (long long)nbf * norb;
+  f.sym = false; f.role = 1; f.mslab = fold ? nbf : 0;
+  f.cmax = cmax; f.scm = (long long)fx_tiles(f.M) * norb;
   NOF_TRY(gemm_i8(f, stream));
-  NOF_TRY(i8_cmax_exps(cmax, naux, fx_tiles(nbf), norb, Te, stream));
+  NOF_TRY(i8_cmax_exps(cmax, naux, fx_tiles(f.M), norb, Te, stream, f.mslab));
   NOF_TRY(i8_split_T(T, naux, nbf, norb, (long long)nbf * norb, (int)ldk, Te, Tp, stream));
   I8Desc g{};
   g.M = norb; g.N = norb; g.K = nbf; g.batch = naux;
@@ -425,8 +444,6 @@ int nof_mo_transform(int naux, int nbf, int norb, const void* B, int Bt, const d
       unsigned* cmax = (unsigned*)(sws + stage_ws(naux, nbf, norb, prec, Bt));
       float* T = (float*)ws;
       NOF_TRY(fx_stage1(naux, nbf, norb, B, Bt, C, T, sws, cmax, stream));
-      NOF_TRY(fx_cmax_exps(cmax, naux, fx_tiles(nbf), norb, (int*)(sws + fx_planes_bytes(nbf, norb)),
-                           stream));
       return fx_stage2(naux, nbf, norb, T, C, (float*)b, D, sws, true, stream);
     }
     const size_t sbytes = ws_bytes - tbytes;

@@ -105,7 +105,7 @@ struct FxDesc {
   int binner = 0;
   long long sx2 = 0, sy2 = 0, sey2 = 0, so2 = 0, sd2 = 0;
   int tile = 128;                  // workgroup tile edge: 128, or 64 with pre-split X
-  // Slabs folded into rows (batch 1, not sym, with cmax): M = nslab * mslab
+  // Slabs folded into rows (X as planes, batch 1, not sym): M = nslab * mslab
   // rows, slab b = rows b*mslab.., mslab >= tile.  cmax then keeps per row
   // tile t the maxima over the rows of its first slab at cmax[t*N + n] and,
   // for a tile that reaches into slab b + 1, over those rows at

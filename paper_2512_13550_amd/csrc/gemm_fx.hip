@@ -830,7 +830,8 @@ int gemm_fx(const FxDesc& d, bool x_planes, bool y_planes, hipStream_t st) {
   if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
   if (d.tile != 128 && d.tile != 64) return NOF_E_ARG;
   if (d.mslab < 0) return NOF_E_ARG;
-  if (d.mslab > 0 && (d.batch != 1 || d.sym || !d.cmax || d.binner || d.mslab < d.tile || d.M % d.mslab ||
+  // folded slabs: X as planes (rows (P, mu) contiguous), one batch entry
+  if (d.mslab > 0 && (!x_planes || d.batch != 1 || d.sym || d.binner || d.mslab < d.tile || d.M % d.mslab ||
                       (long long)d.M + d.mslab > 0x7fffffffLL))
     return NOF_E_ARG;
   const bool big = d.K > EXACT_K;

@@ -644,8 +644,8 @@ int gemm_i8(const I8Desc& d, hipStream_t st) {
   if (d.ldx % IK || d.ldy % IK || d.ldx < d.K || d.ldy < d.K) return NOF_E_DIM;
   if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
   if (d.mslab < 0) return NOF_E_ARG;
-  if (d.mslab > 0 && (d.batch != 1 || d.sym || !d.cmax || d.Out64 || d.binner || d.mslab < IT ||
-                      d.M % d.mslab || (long long)d.M + d.mslab > 0x7fffffffLL))
+  if (d.mslab > 0 && (d.batch != 1 || d.sym || d.Out64 || d.binner || d.mslab < IT || d.M % d.mslab ||
+                      (long long)d.M + d.mslab > 0x7fffffffLL))
     return NOF_E_ARG;
   const int tiles_m = (d.M + IT - 1) / IT;
   const int tiles_n = (d.N + IT - 1) / IT;
