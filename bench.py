@@ -36,9 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 def algorithmic_flops(nbf, naux, norb):
     a1 = 2.0 * naux * nbf * nbf * norb                 # T^P = B^P C
     a2 = 1.0 * naux * nbf * norb * (norb + 1)          # b^P = C^T T^P, symmetric half
-    a6 = 2.0 * naux * norb ** 3                        # exchange-type Fock contraction
+    a6 = 1.0 * naux * norb * norb * (norb + 1)         # exchange-type Fock term: the per-q
+                                                       # products G^q are symmetric (half)
     small = 6.0 * naux * norb * norb                   # J, K, W, F1
-    dense = a1 + 2.0 * naux * nbf * norb * norb + a6   # the three products as dense GEMMs
+    dense = a1 + 2.0 * naux * nbf * norb * norb + 2.0 * naux * norb ** 3   # the three products as dense GEMMs
     return dict(a1=a1, a2=a2, a6=a6, small=small, total=a1 + a2 + a6 + small, dense=dense)
 
 
@@ -171,11 +172,12 @@ def main():
         # epilogue gives the second its column grids); the others call the
         # stages separately, so that each is timed on its own
         fused = prec in (nof.P_BF16X10, nof.P_I8X10)
-        # F64, F32 and the x1 / x3 split forms fold the Coulomb-type term into
-        # the exchange-type product (the pass over b forms K alone); the x6,
-        # x10 and INT8 exchange-type products do not take it, so there the
-        # pass forms K and the Coulomb-type term together
-        folded = prec not in (nof.P_BF16X6, nof.P_BF16X10, nof.P_I8X10)
+        # F32 and the x1 / x3 split forms fold the Coulomb-type term into the
+        # exchange-type product (the pass over b forms K alone); the FP64
+        # (symmetric per-q products), x6, x10 and INT8 exchange-type terms do
+        # not take it, so there the pass forms K and the Coulomb-type term
+        # together
+        folded = prec not in (nof.P_F64, nof.P_BF16X6, nof.P_BF16X10, nof.P_I8X10)
         names = (["rotate"] + (["a1_a2_transform"] if fused else ["a1_transform_stage1", "a2_transform_stage2"])
                  + ["h_and_J"]
                  + (["a4_k_pass", "a5_a6_fock_terms"] if folded else ["a4_a5_coulomb_pass", "a6_exchange"])
@@ -269,14 +271,15 @@ def main():
     seg64 = dict(zip(r64["seg_names"], r64["seg_ms"]))
     ms = r64["ms_per_step"]
     value = flops["total"] / (ms * 1e-3) / 1e12
-    a1_ms, a2_ms, a6_ms = seg64["a1_transform_stage1"], seg64["a2_transform_stage2"], seg64["a5_a6_fock_terms"]
-    kf_ms = seg64["a4_k_pass"]
-    # dominant kernel of the FP64 step: transform stage 1 or the Fock-term contraction
+    a1_ms, a2_ms, a6_ms = seg64["a1_transform_stage1"], seg64["a2_transform_stage2"], seg64["a6_exchange"]
+    kf_ms = seg64["a4_a5_coulomb_pass"]
+    # dominant kernel of the FP64 step: transform stage 1 or the exchange-type term
     if a6_ms > a1_ms:
-        dom = dict(key="k_exchange_fock", name="Fock terms F2 - F1 in one contraction (sum_P b^P (cK o b^P "
-                   "- diag W_P)), FP64 MFMA; the segment includes the W = D cJ product and the reduction",
+        dom = dict(key="k_exchange_fock", name="exchange-type term through the symmetric per-q products "
+                   "G^q = sum_P b^P[q]^T b^P[q] (FP64 MFMA) and their cK-weighted sum over q; the "
+                   "segment includes the sum",
                    ms=a6_ms, flops=flops["a6"],
-                   bytes=8.0 * (naux * norb * norb + norb * norb + naux * norb))
+                   bytes=8.0 * (naux * norb * norb + norb * norb))
     else:
         dom = dict(key="k_transform_stage1", name="transform stage 1 (T^P = B^P C), FP64 MFMA",
                    ms=a1_ms, flops=flops["a1"], bytes=8.0 * (naux * nbf * nbf + naux * nbf * norb + nbf * norb))
@@ -344,7 +347,7 @@ def main():
     batched = run_batched(nof, inputs, dev) if args.batched else None
     warm = run_warmstart(nof, args.warmstart) if args.warmstart > 0 else None
 
-    kfb = k_bytes(naux, norb, 8.0)
+    kfb = k_bytes(naux, norb, 8.0) + 8.0 * naux * norb   # the upper half of b and W
     line = {
         "metric": "JK+gen-Fock build ms/iter and TFLOP/s; BF16 vs FP64 on one GPU at |dE|<=1e-6 Eh",
         "value": value,
@@ -368,9 +371,9 @@ def main():
         "algorithmic_flops_per_step": flops["total"],
         "tflops_dense_equivalent": flops["dense"] / (ms * 1e-3) / 1e12,
         "stage_ms": seg64,
-        "k_pass": {"what": "K in one pass over the upper half of b and the fixed-order reduction of "
-                           "its partials (the a4_k_pass segment of the step; the Coulomb-type Fock "
-                           "term rides in the Fock-term contraction)",
+        "k_pass": {"what": "K and the Coulomb-type term F1 in one pass over the upper half of b, the "
+                           "W = D cJ product and the fixed-order reductions of the partials (the "
+                           "a4_a5_coulomb_pass segment of the step)",
                    "ms": kf_ms, "bytes": kfb, "gbs": kfb / (kf_ms * 1e-3) / 1e9,
                    "frac_of_8tbs": kfb / (kf_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {"bound": "mfma", "kernel": dom["name"],

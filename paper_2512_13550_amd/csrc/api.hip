@@ -19,8 +19,19 @@ bool dim_ok(int x) { return x >= 1 && x <= kMaxDim; }
 bool fixed_point(int prec) { return prec == NOF_P_BF16X10 || prec == NOF_P_I8X10; }
 // Forms whose exchange-type product takes no Coulomb-type term: F1 then comes
 // from the pass over b (with K) and is subtracted.  X6 shares the x10
-// exchange-type product (three element-wise BF16 pieces, six products).
-bool f1_from_pass(int prec) { return fixed_point(prec) || prec == NOF_P_BF16X6; }
+// exchange-type product (three element-wise BF16 pieces, six products);
+// FP64 takes the exchange-type term through the symmetric per-q products.
+bool f1_from_pass(int prec) { return fixed_point(prec) || prec == NOF_P_BF16X6 || prec == NOF_P_F64; }
+
+// FP64 exchange-type term through G^q_rs = sum_P b^P[q][r] b^P[q][s]: q values
+// per chunk, so that a chunk of G stays within 1 GiB.
+int exchange_sym_chunk(int norb) {
+  const long long per = (long long)norb * norb * (long long)sizeof(double);
+  long long c = (1LL << 30) / per;
+  if (c < 1) c = 1;
+  if (c > norb) c = norb;
+  return (int)c;
+}
 
 
 // Workspace of nof_jk_diag: J split partials, K chunk partials.
@@ -46,11 +57,12 @@ JkLayout jk_layout(int naux, int norb, int bt) {
 }
 
 // Workspace of nof_gen_fock and nof_fock_terms: W, the partials of the
-// Fock-term product and their sum F, the FP32 cK^T of the x10 form, and (x10,
-// whose exchange-type product does not take the Coulomb-type term) the F1
-// chunk partials and F1; then (nof_gen_fock) the K chunk partials.
+// Fock-term product (FP64: a chunk of the symmetric products G^q instead) and
+// their sum F, the FP32 cK^T of the x10 form, and (the forms whose
+// exchange-type product does not take the Coulomb-type term) the F1 chunk
+// partials and F1; then (nof_gen_fock) the K chunk partials.
 struct FockLayout {
-  int kchunks, f2fold, f2groups;
+  int kchunks, f2fold, f2groups, gq;
   size_t off_W, off_f2part, off_F, off_St, off_f1part, off_F1, off_i8, terms, off_kpart, total;
 };
 FockLayout fock_layout(int naux, int norb, int bt, int prec) {
@@ -66,9 +78,10 @@ FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   L.f2groups = (naux + L.f2fold - 1) / L.f2fold;
   const size_t n2 = (size_t)norb * norb * sizeof(double);
   const bool fx = f1_from_pass(prec);
+  L.gq = prec == NOF_P_F64 ? exchange_sym_chunk(norb) : 0;
   L.off_W = 0;
   L.off_f2part = align256((size_t)naux * norb * sizeof(double));
-  L.off_F = align256(L.off_f2part + (size_t)L.f2groups * n2);
+  L.off_F = align256(L.off_f2part + (prec == NOF_P_F64 ? (size_t)L.gq : (size_t)L.f2groups) * n2);
   L.off_St = align256(L.off_F + n2);
   L.off_f1part = align256(L.off_St + (size_t)norb * norb * sizeof(float));
   L.off_F1 = align256(L.off_f1part + (fx ? (size_t)L.kchunks * n2 : 0));
@@ -494,8 +507,39 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, doub
 
 namespace {
 
+// FP64 exchange-type term through the per-q symmetric products.  b^P is
+// symmetric, so
+//   F2_rs = sum_P sum_q b^P[r][q] cK[q][s] b^P[q][s] = sum_q cK[q][s] G^q_rs,
+//   G^q_rs = sum_P b^P[q][r] b^P[q][s],
+// and G^q is symmetric in (r, s): the batched product over q computes the
+// upper tiles only (Naux Norb^2 (Norb+1) multiply-adds against 2 Naux Norb^3
+// for the product over (P, q)), L.gq values of q at a time into G, each chunk
+// then added into F in q order.  With F1, F = F2 - F1.
+int exchange_sym(int naux, int norb, const double* b, const double* cK, const FockLayout& L, double* G,
+                 const double* F1, double* F, hipStream_t stream) {
+  const long long n2 = (long long)norb * norb;
+  for (int q0 = 0; q0 < norb; q0 += L.gq) {
+    const int qn = std::min(L.gq, norb - q0);
+    // G^q = X^T X with X(k = P, m = r) = b^P[q][r]: k-major, P stride norb^2
+    GemmDesc g{};
+    g.M = norb; g.N = norb; g.K = naux; g.Ktot = 0;
+    g.batch = qn; g.fold = 1;
+    g.X = b + (long long)q0 * norb; g.ldx = n2; g.sx = norb; g.x_kmajor = true;
+    g.Y = b + (long long)q0 * norb; g.ldy = n2; g.sy = norb;
+    g.S = nullptr; g.lds = 0;
+    g.Out = G; g.ldo = norb; g.so = n2;
+    g.Dg = nullptr; g.sd = 0; g.sym = true;
+    g.role = GemmRole::ExchangeFock;
+    NOF_TRY(gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
+    const int mode = q0 > 0 ? 1 : (F1 ? 2 : 0);
+    NOF_TRY(exchange_accum(G, qn, norb, cK + (long long)q0 * norb, F1, mode, F, stream));
+  }
+  return NOF_OK;
+}
+
 // F2 (exchange-type term) into F2 from the partials in f2part (groups of
-// L.f2fold slabs); St: norb*norb FP32 scratch of the split forms.
+// L.f2fold slabs; FP64: a chunk of G); St: norb*norb FP32 scratch of the
+// split forms.
 int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, const double* W,
                   int prec, const FockLayout& L, double* f2part, float* St, char* i8ws, double* F2,
                   hipStream_t stream) {
@@ -506,6 +550,10 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, c
     NOF_TRY(fx_transpose(cK, norb, 1, St, stream));
     NOF_TRY(i8_exchange(1, naux, norb, (const float*)b, 0, St, f2part, i8ws, stream));
     return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
+  }
+  if (prec == NOF_P_F64) {
+    if (W) return NOF_E_INTERNAL;
+    return exchange_sym(naux, norb, (const double*)b, cK, L, f2part, nullptr, F2, stream);
   }
   if (f1_from_pass(prec)) {
     if (W) return NOF_E_INTERNAL;               // this product takes no W (fock_terms)
@@ -542,12 +590,13 @@ int coulomb_weights(int naux, int norb, const double* D, const double* cJ, doubl
   return gemm_tn(gw, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream);
 }
 
-// F = F2 - F1 = sum_P sum_q b^P[r][q] (cK[q][s] b^P[q][s] - [q == s] W[P][s]):
-// the Coulomb-type term rides in the exchange-type product's operand loader.
-// The x6 / x10 exchange-type product stages element-wise pieces of FP32
-// values and the INT8 one fixed-point planes; neither takes it: there F1
-// comes from the pass over the upper half of b (with K when Kpart is given:
-// both from one read of b) and is subtracted.
+// F = F2 - F1 = sum_P sum_q b^P[r][q] (cK[q][s] b^P[q][s] - [q == s] W[P][s]).
+// FP32 (and x1 / x3): the Coulomb-type term rides in the exchange-type
+// product's operand loader.  FP64 takes the exchange-type term through the
+// symmetric per-q products (exchange_sym), the x6 / x10 product stages
+// element-wise pieces of FP32 values and the INT8 one fixed-point planes; none
+// of these takes it: there F1 comes from the pass over the upper half of b
+// (with K when Kpart is given: both from one read of b) and is subtracted.
 int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const double* cJ,
                const double* cK, int prec, const FockLayout& L, char* w, double* F,
                double* Kpart, double* K, hipStream_t stream) {
@@ -562,6 +611,8 @@ int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const
   NOF_TRY(kf1_pass(naux, norb, b, bt, W, Kpart, f1part, L.kchunks, stream));
   NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
   if (Kpart) NOF_TRY(reduce_parts(Kpart, L.kchunks, n2, norb, true, K, stream));
+  if (prec == NOF_P_F64)
+    return exchange_sym(naux, norb, (const double*)b, cK, L, (double*)(w + L.off_f2part), F1, F, stream);
   NOF_TRY(exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, (double*)(w + L.off_f2part),
                         (float*)(w + L.off_St), w + L.off_i8, F, stream));
   return subtract(n2, F1, F, stream);
@@ -575,7 +626,7 @@ size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
   const FockLayout L = fock_layout(naux, norb, bt, prec);
-  return align256((size_t)L.f2groups * norb * norb * sizeof(double)) +
+  return align256((size_t)(prec == NOF_P_F64 ? L.gq : L.f2groups) * norb * norb * sizeof(double)) +
          align256((size_t)norb * norb * sizeof(float)) +
          (prec == NOF_P_I8X10 ? i8_exchange_ws(1, naux, norb) : 0);
 }
@@ -592,7 +643,8 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
     const FockLayout L = fock_layout(naux, norb, bt, prec);
     char* w = (char*)ws;
     double* part = (double*)w;
-    float* St = (float*)(w + align256((size_t)L.f2groups * norb * norb * sizeof(double)));
+    float* St = (float*)(w + align256((size_t)(prec == NOF_P_F64 ? L.gq : L.f2groups) * norb * norb *
+                                      sizeof(double)));
     char* i8ws = (char*)St + align256((size_t)norb * norb * sizeof(float));
     return exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, part, St, i8ws, F2, stream);
   });

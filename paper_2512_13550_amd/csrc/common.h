@@ -245,6 +245,12 @@ int reduce_parts(const double* part, int nparts, long long stride, int norb,
                  bool sym_upper, double* out, hipStream_t st, int ninst = 1,
                  long long pinst = 0, long long oinst = 0);
 
+// F[r][s] = start + sum_{q < qn} cK[q][s] G[q][r][s] in q order (G: qn FP64
+// norb x norb matrices; cK: the qn rows of the coefficients that go with
+// them); start = 0 (mode 0), F (mode 1) or -F1 (mode 2).
+int exchange_accum(const double* G, int qn, int norb, const double* cK, const double* F1, int mode,
+                   double* F, hipStream_t st);
+
 // y -= x (n elements; ninst instances at the given strides).
 int subtract(long long n, const double* x, double* y, hipStream_t st, int ninst = 1,
              long long xstride = 0, long long ystride = 0);

@@ -261,6 +261,24 @@ __global__ void k_reduce(const double* __restrict__ part, int nparts, long long 
   }
 }
 
+// Exchange-type term from the per-q symmetric products G^q (FP64):
+//   F[r][s] = start[r][s] + sum_{q < qn} cK[q][s] G[q][r][s]
+// summed in q order; start = F (mode 1), -F1 (mode 2) or 0 (mode 0).  One
+// thread per element (r, s): the loads of G and cK run along s (coalesced).
+__global__ void k_exchange_accum(const double* __restrict__ G, int qn, int norb,
+                                 const double* __restrict__ cK, const double* __restrict__ F1, int mode,
+                                 double* __restrict__ F) {
+  const long long n2 = (long long)norb * norb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int s = (int)(i % norb);
+    double a = mode == 1 ? F[i] : (mode == 2 ? -F1[i] : 0.0);
+#pragma unroll 4
+    for (int q = 0; q < qn; ++q) a = fma(cK[(long long)q * norb + s], G[(long long)q * n2 + i], a);
+    F[i] = a;
+  }
+}
+
 // y -= x over n elements.
 __global__ void k_subtract(long long n, const double* __restrict__ x, double* __restrict__ y) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -466,6 +484,15 @@ int lambda_grad(int norb, const double* n, const double* h, const double* F1, co
   const long long n2 = (long long)norb * norb;
   hipLaunchKernelGGL(k_lambda, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, norb, n, h, F1,
                      F2, lam, grad, nstride, mstride, fstride);
+  return launch_status();
+}
+
+int exchange_accum(const double* G, int qn, int norb, const double* cK, const double* F1, int mode,
+                   double* F, hipStream_t st) {
+  if (qn < 1 || norb < 1 || mode < 0 || mode > 2 || (mode == 2 && !F1)) return NOF_E_ARG;
+  const long long n2 = (long long)norb * norb;
+  hipLaunchKernelGGL(k_exchange_accum, dim3(grid_for(n2, 256)), dim3(256), 0, st, G, qn, norb, cK, F1, mode,
+                     F);
   return launch_status();
 }
 
