@@ -23,15 +23,6 @@ bool fixed_point(int prec) { return prec == NOF_P_BF16X10 || prec == NOF_P_I8X10
 // FP64 takes the exchange-type term through the symmetric per-q products.
 bool f1_from_pass(int prec) { return fixed_point(prec) || prec == NOF_P_BF16X6 || prec == NOF_P_F64; }
 
-// FP64 exchange-type term through G^q_rs = sum_P b^P[q][r] b^P[q][s]: q values
-// per chunk, so that a chunk of G stays within 1 GiB.
-int exchange_sym_chunk(int norb) {
-  const long long per = (long long)norb * norb * (long long)sizeof(double);
-  long long c = (1LL << 30) / per;
-  if (c < 1) c = 1;
-  if (c > norb) c = norb;
-  return (int)c;
-}
 
 
 // Workspace of nof_jk_diag: J split partials, K chunk partials.

@@ -50,6 +50,9 @@ namespace {
 // The fixed-point forms (BF16 or INT8 pieces) share b in FP32, the x10
 // exchange-type product and the Coulomb-type term from the pass.
 bool fixed_point_plan(const nof_plan_s* p) { return p->prec == NOF_P_BF16X10 || p->prec == NOF_P_I8X10; }
+// Plans whose Coulomb-type term comes from the pass over b (with K): the
+// fixed-point ones and FP64 (exchange-type term through the per-q products).
+bool f1_pass_plan(const nof_plan_s* p) { return fixed_point_plan(p) || p->prec == NOF_P_F64; }
 // Stage 1 of the fixed-point plans takes the rows of all slabs as one M when
 // a slab holds at least one tile of rows: no slab is padded to whole tiles.
 bool fold_stage1(const nof_plan_s* p, int tile) {
@@ -75,12 +78,14 @@ void plan_layout(nof_plan_s* p) {
   sz[O_K] = ni * n2;
   sz[O_W] = ni * na * no * 8;
   sz[O_KP] = ni * p->kchunks * n2;
-  // F64 / F32: the Coulomb-type term is folded into the exchange-type
-  // product (O_F2 holds F2 - F1), so its partials and sum take no space; the
-  // x10 exchange-type product does not take it (F1 from the pass with K)
-  const bool fx1 = fixed_point_plan(p);
+  // F32: the Coulomb-type term is folded into the exchange-type product
+  // (O_F2 holds F2 - F1), so its partials and sum take no space; the FP64 and
+  // fixed-point exchange-type terms do not take it (F1 from the pass with K).
+  // FP64: O_F2P holds a chunk of the per-q products G^q of every instance.
+  const bool fx1 = f1_pass_plan(p);
   sz[O_F1P] = fx1 ? ni * p->kchunks * n2 : 0;
-  sz[O_F2P] = (size_t)f2groups * n2;
+  sz[O_F2P] = p->prec == NOF_P_F64 ? ni * (size_t)exchange_sym_chunk(p->norb, p->ninst) * n2
+                                   : (size_t)f2groups * n2;
   sz[O_F1] = fx1 ? ni * n2 : 0;
   sz[O_F2] = ni * n2;
   sz[O_EP] = energy_ws((int)ni);
@@ -279,7 +284,7 @@ int run_small(nof_plan_s* p, const Args& a, hipStream_t st) {
 // x10 form also the Coulomb-type term F1 (same pass).
 int run_pass(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long n2 = (long long)p->norb * p->norb;
-  const bool fx = fixed_point_plan(p);
+  const bool fx = f1_pass_plan(p);
   double* kp = (double*)(a.ws + p->off[O_KP]);
   double* f1p = fx ? (double*)(a.ws + p->off[O_F1P]) : nullptr;
   int rc = kf1_pass(p->naux, p->norb, a.ws + p->off[O_B], p->bt,
@@ -297,6 +302,35 @@ int run_pass(nof_plan_s* p, const Args& a, hipStream_t st) {
 
 int run_f2(nof_plan_s* p, const Args& a, hipStream_t st) {
   const long long n2 = (long long)p->norb * p->norb;
+  if (p->prec == NOF_P_F64) {
+    // F2_i - F1_i = sum_q cK_i[q][s] G_i^q[r][s] - F1_i with the symmetric
+    // G_i^q = sum_P b_i^P[q]^T b_i^P[q] of every instance, a chunk of q at a
+    // time (instance outer, q inner), each chunk added in q order
+    const int gq = exchange_sym_chunk(p->norb, p->ninst);
+    double* G = (double*)(a.ws + p->off[O_F2P]);
+    const double* b = (const double*)(a.ws + p->off[O_B]);
+    const double* F1 = (const double*)(a.ws + p->off[O_F1]);
+    double* F = (double*)(a.ws + p->off[O_F2]);
+    for (int q0 = 0; q0 < p->norb; q0 += gq) {
+      const int qn = std::min(gq, p->norb - q0);
+      GemmDesc g{};
+      g.M = p->norb; g.N = p->norb; g.K = p->naux;
+      g.batch = p->ninst * qn; g.fold = 1; g.binner = qn;
+      g.X = b + (long long)q0 * p->norb; g.ldx = n2; g.sx = p->norb; g.sx2 = (long long)p->naux * n2;
+      g.x_kmajor = true;
+      g.Y = b + (long long)q0 * p->norb; g.ldy = n2; g.sy = p->norb; g.sy2 = (long long)p->naux * n2;
+      g.Out = G; g.ldo = p->norb; g.so = n2; g.so2 = (long long)qn * n2;
+      g.sym = true;
+      g.role = GemmRole::ExchangeFock;
+      g.tile = p->tile_f2;
+      int rc = gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, st);
+      if (rc != NOF_OK) return rc;
+      rc = exchange_accum(G, qn, p->norb, a.cK + (long long)q0 * p->norb, F1, q0 > 0 ? 1 : 2, F, st,
+                          p->ninst, (long long)qn * n2, n2, n2);
+      if (rc != NOF_OK) return rc;
+    }
+    return NOF_OK;
+  }
   const int fold = (p->naux + p->f2gpi - 1) / p->f2gpi;
   const int gpi = (p->naux + fold - 1) / fold;
   double* f2p = (double*)(a.ws + p->off[O_F2P]);

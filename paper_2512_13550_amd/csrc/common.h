@@ -247,9 +247,19 @@ int reduce_parts(const double* part, int nparts, long long stride, int norb,
 
 // F[r][s] = start + sum_{q < qn} cK[q][s] G[q][r][s] in q order (G: qn FP64
 // norb x norb matrices; cK: the qn rows of the coefficients that go with
-// them); start = 0 (mode 0), F (mode 1) or -F1 (mode 2).
+// them); start = 0 (mode 0), F (mode 1) or -F1 (mode 2).  ninst instances:
+// G, cK, F1 / F at the given strides.
 int exchange_accum(const double* G, int qn, int norb, const double* cK, const double* F1, int mode,
-                   double* F, hipStream_t st);
+                   double* F, hipStream_t st, int ninst = 1, long long gstride = 0, long long cstride = 0,
+                   long long fstride = 0);
+// q values per chunk of the per-q products G^q of ninst instances within 1 GiB.
+inline int exchange_sym_chunk(int norb, int ninst = 1) {
+  const long long per = (long long)norb * norb * (long long)sizeof(double) * ninst;
+  long long c = (1LL << 30) / per;
+  if (c < 1) c = 1;
+  if (c > norb) c = norb;
+  return (int)c;
+}
 
 // y -= x (n elements; ninst instances at the given strides).
 int subtract(long long n, const double* x, double* y, hipStream_t st, int ninst = 1,

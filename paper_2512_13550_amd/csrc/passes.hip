@@ -265,10 +265,16 @@ __global__ void k_reduce(const double* __restrict__ part, int nparts, long long 
 //   F[r][s] = start[r][s] + sum_{q < qn} cK[q][s] G[q][r][s]
 // summed in q order; start = F (mode 1), -F1 (mode 2) or 0 (mode 0).  One
 // thread per element (r, s): the loads of G and cK run along s (coalesced).
+// Instance blockIdx.y at G + y*gstride, cK + y*cstride, F1 and F + y*fstride.
 __global__ void k_exchange_accum(const double* __restrict__ G, int qn, int norb,
                                  const double* __restrict__ cK, const double* __restrict__ F1, int mode,
-                                 double* __restrict__ F) {
+                                 double* __restrict__ F, long long gstride, long long cstride,
+                                 long long fstride) {
   const long long n2 = (long long)norb * norb;
+  G += blockIdx.y * gstride;
+  cK += blockIdx.y * cstride;
+  F += blockIdx.y * fstride;
+  if (F1) F1 += blockIdx.y * fstride;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x) {
     const int s = (int)(i % norb);
@@ -488,11 +494,13 @@ int lambda_grad(int norb, const double* n, const double* h, const double* F1, co
 }
 
 int exchange_accum(const double* G, int qn, int norb, const double* cK, const double* F1, int mode,
-                   double* F, hipStream_t st) {
-  if (qn < 1 || norb < 1 || mode < 0 || mode > 2 || (mode == 2 && !F1)) return NOF_E_ARG;
+                   double* F, hipStream_t st, int ninst, long long gstride, long long cstride,
+                   long long fstride) {
+  if (qn < 1 || norb < 1 || ninst < 1 || ninst > 65535 || mode < 0 || mode > 2 || (mode == 2 && !F1))
+    return NOF_E_ARG;
   const long long n2 = (long long)norb * norb;
-  hipLaunchKernelGGL(k_exchange_accum, dim3(grid_for(n2, 256)), dim3(256), 0, st, G, qn, norb, cK, F1, mode,
-                     F);
+  hipLaunchKernelGGL(k_exchange_accum, dim3(grid_for(n2, 256), ninst), dim3(256), 0, st, G, qn, norb, cK, F1,
+                     mode, F, gstride, cstride, fstride);
   return launch_status();
 }
 

@@ -257,11 +257,16 @@ def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
                 "D": ninst * naux * norb * 8, "TH": ninst * nbf * norb * 8, "h": ninst * n2, "J": ninst * n2,
                 "K": ninst * n2, "W": ninst * naux * norb * 8, "Kpart": ninst * n2,
                 "F2part": ninst * gmax * n2, "F2": ninst * n2, "Epart": ninst * 8}
-        if prec in ("x10", "i8x10"):
+        if prec == "f64":
+            # the per-q symmetric products of every instance, q values at a
+            # time within 1 GiB, in place of the exchange-term partials
+            gq = min(norb, max(1, (1 << 30) // (ninst * n2)))
+            need["F2part"] = ninst * gq * n2
+        if prec in ("x10", "i8x10", "f64"):
             need.update({"F1part": ninst * n2, "F1": ninst * n2})
         else:
-            # the Coulomb-type term rides in the exchange-type product (F2
-            # holds F2 - F1): its partials and sum need no space
+            # FP32: the Coulomb-type term rides in the exchange-type product
+            # (F2 holds F2 - F1): its partials and sum need no space
             assert size[PLAN_REGIONS.index("F1part")] == 0 and size[PLAN_REGIONS.index("F1")] == 0
         if prec == "x10":
             ldk = (nbf + 31) // 32 * 32

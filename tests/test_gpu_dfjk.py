@@ -24,6 +24,9 @@ SHAPES = [
     (5, 2, 3, 3),
     (130, 1, 130, 4),
     (1, 3, 1, 5),
+    # Norb = 600: the FP64 exchange-type term's per-q products G^q take two
+    # chunks of q (372 + 228 within 1 GiB)
+    (620, 6, 600, 6),
 ]
 
 
@@ -53,8 +56,8 @@ def test_transform_jk_fock_energy_fp64(nbf, naux, norb, seed):
     assert abs(float(E) - ref["E"]) <= FP64_TOL * abs(ref["E"])
     F2 = nof.exchange_fock(b, dev(cK))
     assert normwise(host(F2), ref["F2"]) <= FP64_TOL
-    # the same build as its steps (both Fock terms in one contraction, then
-    # lambda and g): identical to the fused call bit for bit
+    # the same build as its steps (F = F2 - F1, then lambda and g): identical
+    # to the fused call bit for bit
     F = nof.fock_terms(b, D, dev(cJ), dev(cK))
     lam3, g3 = nof.lambda_grad(dev(n), h, None, F)
     torch.cuda.synchronize()
