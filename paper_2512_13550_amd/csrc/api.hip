@@ -25,6 +25,24 @@ bool f1_from_pass(int prec) { return fixed_point(prec) || prec == NOF_P_BF16X6 |
 
 
 
+// INT8 exchange-type term through the per-q symmetric products while the
+// contraction over P stays within the exact int32 depth: per-(q, r) grids
+// (norb^2 ints), then for each chunk of q the INT8 planes of the rows
+// b^P[q][:] with P contiguous, and the FP64 G^q of the chunk (in the
+// partials region); a chunk of planes and G within 4 GiB.
+bool i8_sym(int naux) { return naux <= I8_MAX_K; }
+int i8_sym_chunk(int naux, int norb) {
+  const long long per = 4LL * norb * i8_ldk(naux) + 8LL * norb * norb;
+  long long c = (4LL << 30) / per;
+  if (c < 1) c = 1;
+  if (c > norb) c = norb;
+  return (int)c;
+}
+size_t i8_sym_ws(int naux, int norb) {
+  return align256((size_t)norb * norb * sizeof(int)) +
+         i8_planes_bytes((long long)i8_sym_chunk(naux, norb) * norb, naux);
+}
+
 // Workspace of nof_jk_diag: J split partials, K chunk partials.
 struct JkLayout {
   int jsplit, jk, kchunks;
@@ -69,15 +87,17 @@ FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   L.f2groups = (naux + L.f2fold - 1) / L.f2fold;
   const size_t n2 = (size_t)norb * norb * sizeof(double);
   const bool fx = f1_from_pass(prec);
-  L.gq = prec == NOF_P_F64 ? exchange_sym_chunk(norb) : 0;
+  const bool i8s = prec == NOF_P_I8X10 && i8_sym(naux);
+  L.gq = prec == NOF_P_F64 ? exchange_sym_chunk(norb) : i8s ? i8_sym_chunk(naux, norb) : 0;
   L.off_W = 0;
   L.off_f2part = align256((size_t)naux * norb * sizeof(double));
-  L.off_F = align256(L.off_f2part + (prec == NOF_P_F64 ? (size_t)L.gq : (size_t)L.f2groups) * n2);
+  L.off_F = align256(L.off_f2part + (L.gq > 0 ? (size_t)L.gq : (size_t)L.f2groups) * n2);
   L.off_St = align256(L.off_F + n2);
   L.off_f1part = align256(L.off_St + (size_t)norb * norb * sizeof(float));
   L.off_F1 = align256(L.off_f1part + (fx ? (size_t)L.kchunks * n2 : 0));
   L.off_i8 = align256(L.off_F1 + (fx ? n2 : 0));
-  L.terms = align256(L.off_i8 + (prec == NOF_P_I8X10 ? i8_exchange_ws(1, naux, norb) : 0));
+  L.terms = align256(L.off_i8 + (i8s ? i8_sym_ws(naux, norb)
+                                     : prec == NOF_P_I8X10 ? i8_exchange_ws(1, naux, norb) : 0));
   L.off_kpart = L.terms;
   L.total = align256(L.off_kpart + (size_t)L.kchunks * n2);
   return L;
@@ -528,6 +548,37 @@ int exchange_sym(int naux, int norb, const double* b, const double* cK, const Fo
   return NOF_OK;
 }
 
+// INT8 exchange-type term through the per-q symmetric products G^q (the
+// identity of exchange_sym): every G^q_rs = sum_P b^P[q][r] b^P[q][s] is one
+// INT8 fixed-point product over P with one grid per (q, r), exact int32 sums,
+// written in FP64 (both triangles of the upper tiles); each chunk of q is
+// then added into F2 in q order.  ws: grids, then a chunk of planes.
+int i8_exchange_sym(int naux, int norb, const float* b, const double* cK, const FockLayout& L, double* G,
+                    char* ws, double* F2, hipStream_t stream) {
+  const long long n2 = (long long)norb * norb;
+  const long long ldk = i8_ldk(naux);
+  int* e = (int*)ws;
+  unsigned char* pl = (unsigned char*)(ws + align256((size_t)n2 * sizeof(int)));
+  NOF_TRY(i8_slab_grids(b, naux, norb, e, stream));
+  for (int q0 = 0; q0 < norb; q0 += L.gq) {
+    const int qn = std::min(L.gq, norb - q0);
+    // rows b^P[q][:] of the chunk as columns of T_q[k = P][n = r] (row stride norb^2)
+    NOF_TRY(i8_split_T(b + (long long)q0 * norb, qn, naux, norb, norb, (int)ldk, e + (long long)q0 * norb, pl,
+                       stream, n2));
+    I8Desc f{};
+    f.M = norb; f.N = norb; f.K = naux; f.batch = qn;
+    f.X = pl; f.ldx = ldk; f.sx = norb * ldk; f.psx = (long long)qn * norb * ldk;
+    f.ex = e + (long long)q0 * norb; f.sex = norb;
+    f.Y = pl; f.ldy = ldk; f.sy = norb * ldk; f.psy = (long long)qn * norb * ldk;
+    f.ey = e + (long long)q0 * norb; f.sey = norb;
+    f.Out64 = G; f.ldo = norb; f.so = n2;
+    f.sym = true; f.role = 3;
+    NOF_TRY(gemm_i8(f, stream));
+    NOF_TRY(exchange_accum(G, qn, norb, cK + (long long)q0 * norb, nullptr, q0 > 0 ? 1 : 0, F2, stream));
+  }
+  return NOF_OK;
+}
+
 // F2 (exchange-type term) into F2 from the partials in f2part (groups of
 // L.f2fold slabs; FP64: a chunk of G); St: norb*norb FP32 scratch of the
 // split forms.
@@ -536,8 +587,10 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, c
                   hipStream_t stream) {
   const long long n2 = (long long)norb * norb;
   if (prec == NOF_P_I8X10) {
-    // one INT8 product per group of slabs on cK^T in FP32, FP64 partials
     if (W) return NOF_E_INTERNAL;
+    if (i8_sym(naux)) return i8_exchange_sym(naux, norb, (const float*)b, cK, L, f2part, i8ws, F2, stream);
+    // beyond the exact depth: one INT8 product per group of slabs on cK^T in
+    // FP32, FP64 partials
     NOF_TRY(fx_transpose(cK, norb, 1, St, stream));
     NOF_TRY(i8_exchange(1, naux, norb, (const float*)b, 0, St, f2part, i8ws, stream));
     return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
@@ -617,9 +670,9 @@ size_t nof_exchange_fock_ws(int naux, int norb, int bt, int prec) {
   if (!dim_ok(naux) || !dim_ok(norb)) return 0;
   if (!prec_matches(prec, bt)) return 0;
   const FockLayout L = fock_layout(naux, norb, bt, prec);
-  return align256((size_t)(prec == NOF_P_F64 ? L.gq : L.f2groups) * norb * norb * sizeof(double)) +
+  return align256((size_t)(L.gq > 0 ? L.gq : L.f2groups) * norb * norb * sizeof(double)) +
          align256((size_t)norb * norb * sizeof(float)) +
-         (prec == NOF_P_I8X10 ? i8_exchange_ws(1, naux, norb) : 0);
+         (prec != NOF_P_I8X10 ? 0 : i8_sym(naux) ? i8_sym_ws(naux, norb) : i8_exchange_ws(1, naux, norb));
 }
 
 int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* cK, double* F2,
@@ -634,8 +687,7 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
     const FockLayout L = fock_layout(naux, norb, bt, prec);
     char* w = (char*)ws;
     double* part = (double*)w;
-    float* St = (float*)(w + align256((size_t)(prec == NOF_P_F64 ? L.gq : L.f2groups) * norb * norb *
-                                      sizeof(double)));
+    float* St = (float*)(w + align256((size_t)(L.gq > 0 ? L.gq : L.f2groups) * norb * norb * sizeof(double)));
     char* i8ws = (char*)St + align256((size_t)norb * norb * sizeof(float));
     return exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, part, St, i8ws, F2, stream);
   });

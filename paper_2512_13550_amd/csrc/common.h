@@ -156,7 +156,8 @@ struct I8Desc {
   // inner; X, ex, Y, ey, Out, Dg at inner * s? + outer * s?2
   int binner;
   long long sx2, sex2, sy2, sey2, so2, sd2;
-  double* Out64;                   // if set (not sym, no cmax): FP64 results here instead of Out
+  double* Out64;                   // if set (no cmax, no Dg): FP64 results here instead of Out
+                                   // (sym: both triangles)
   int mslab;                       // slabs folded into rows, as in FxDesc (tile edge 128)
 };
 int gemm_i8(const I8Desc& d, hipStream_t st);
@@ -183,7 +184,10 @@ int i8_split_cols(const double* A, int K, int ncol, int lda, int ldk, void* plan
                   hipStream_t st);
 int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipStream_t st, int mslab = 0);
 int i8_split_T(const float* T, int batch, int K, int N, long long sT, int ldk, const int* e, void* planes,
-               hipStream_t st);
+               hipStream_t st, long long ldt = 0);
+// Grids of the per-q products of the INT8 exchange-type term: e[q*norb + r]
+// from max_P |b^P[q][r]| (FP32 b [naux][norb][norb]).
+int i8_slab_grids(const float* b, int naux, int norb, int* e, hipStream_t st);
 
 // Exchange-type Fock partials of the split forms (gemm_fx.hip):
 //   Out[g][r][s] = sum_{P in [g*fold, (g+1)*fold)} sum_q b^P[q][r] S[q][s] b^P[q][s]

@@ -187,14 +187,14 @@ __global__ void k_cmax_exps_i8(const unsigned* __restrict__ cmax, long long batc
   }
 }
 
-// Planes of the columns of the k-major FP32 T_b[K][N] (batch stride sT) on
-// the grids e[b*N + n]: out[q][b][n][ldk].  Block: 64 columns x 128 k.  The
+// Planes of the columns of the k-major FP32 T_b[K][N] (batch stride sT, row
+// stride ldt) on the grids e[b*N + n]: out[q][b][n][ldk].  Block: 64 columns x 128 k.  The
 // split runs with lanes along n (coalesced reads of T's rows), 32 k per
 // thread, into an LDS tile [q][n][k]; the tile is then written with lanes
 // along k, so a wave stores eight whole 128-byte rows.
 constexpr int TS_N = 64, TS_K = 128, TS_ROW = TS_K + 16;   // LDS row: 144 bytes (no conflicts)
 __global__ void k_split_T_i8(const float* __restrict__ T, long long batch, int K, int N, long long sT,
-                             int ldk, const int* __restrict__ e, unsigned char* __restrict__ out) {
+                             long long ldt, int ldk, const int* __restrict__ e, unsigned char* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) unsigned char L[4][TS_N][TS_ROW];
   const int nkb = (ldk + TS_K - 1) / TS_K;
   const int ncb = (N + TS_N - 1) / TS_N;
@@ -222,7 +222,7 @@ __global__ void k_split_T_i8(const float* __restrict__ T, long long batch, int K
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int k = k0 + 32 * kc + 16 * h + 4 * w + i;
-            split_i8f(k < K ? tp[(long long)k * N] : 0.f, E, pw, i);
+            split_i8f(k < K ? tp[(long long)k * ldt] : 0.f, E, pw, i);
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) p[q][w] = pw[q];
@@ -399,7 +399,13 @@ __device__ __forceinline__ void i8_body(const I8Desc& d, int tiles_n, int ntiles
         v = (double)acc[0][i][j][r] + v * 0.0078125;
         v = ldexp(v, exr + eyc[j] - 14);
         if (d.Out64) {
-          d.Out64[ib * d.so + ob * d.so2 + (long long)gm * d.ldo + gn] = v;
+          double* o = d.Out64 + ib * d.so + ob * d.so2;
+          if (!d.sym) {
+            o[(long long)gm * d.ldo + gn] = v;
+          } else if (gm <= gn) {
+            o[(long long)gm * d.ldo + gn] = v;
+            o[(long long)gn * d.ldo + gm] = v;
+          }
           continue;
         }
         const float fv = (float)v;
@@ -640,7 +646,7 @@ int gemm_i8(const I8Desc& d, hipStream_t st) {
   if (d.sym && d.M != d.N) return NOF_E_DIM;
   if (d.K > I8_MAX_K) return NOF_E_DIM;
   if (!d.X || !d.Y || !d.ex || !d.ey || (!d.Out && !d.Out64)) return NOF_E_NULL;
-  if (d.Out64 && (d.sym || d.cmax)) return NOF_E_ARG;
+  if (d.Out64 && (d.cmax || d.Dg)) return NOF_E_ARG;
   if (d.ldx % IK || d.ldy % IK || d.ldx < d.K || d.ldy < d.K) return NOF_E_DIM;
   if (d.binner < 0 || (d.binner > 0 && (d.cmax || d.batch % d.binner))) return NOF_E_ARG;
   if (d.mslab < 0) return NOF_E_ARG;
@@ -787,12 +793,35 @@ int i8_cmax_exps(const unsigned* cmax, int batch, int tiles, int N, int* e, hipS
 }
 
 int i8_split_T(const float* T, int batch, int K, int N, long long sT, int ldk, const int* e, void* planes,
-               hipStream_t st) {
-  if (batch <= 0 || K <= 0 || N <= 0 || ldk < K || ldk % IK) return NOF_E_DIM;
+               hipStream_t st, long long ldt) {
+  if (batch <= 0 || K <= 0 || N <= 0 || ldk < K || ldk % IK || ldt < 0 || (ldt > 0 && ldt < N))
+    return NOF_E_DIM;
   const long long blocks = (long long)batch * ((N + 63) / 64) * ((ldk + 127) / 128);
   const unsigned g = (unsigned)(blocks < 1 ? 1 : (blocks > (1 << 20) ? (1 << 20) : blocks));
-  hipLaunchKernelGGL(k_split_T_i8, dim3(g), dim3(256), 0, st, T, (long long)batch, K, N, sT, ldk, e,
-                     (unsigned char*)planes);
+  hipLaunchKernelGGL(k_split_T_i8, dim3(g), dim3(256), 0, st, T, (long long)batch, K, N, sT, ldt > 0 ? ldt : N,
+                     ldk, e, (unsigned char*)planes);
+  return launch_status();
+}
+
+// Grids of the rows of the per-q products of the exchange-type term: for
+// every (q, r), e[q*norb + r] from max_P |b^P[q][r]| (FP32 b [naux][norb][norb]);
+// lanes along r, so each slab's row is read coalesced.
+__global__ void k_slab_grids_i8(const float* __restrict__ b, int naux, int norb, int* __restrict__ e) {
+  const long long n2 = (long long)norb * norb;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    unsigned m = 0;
+    const float* p = b + i;
+#pragma unroll 4
+    for (int P = 0; P < naux; ++P) m = max(m, __float_as_uint(p[(long long)P * n2]) & 0x7fffffffu);
+    e[i] = grid_exp_i8_bits(m);
+  }
+}
+
+int i8_slab_grids(const float* b, int naux, int norb, int* e, hipStream_t st) {
+  if (naux <= 0 || norb <= 0) return NOF_E_DIM;
+  const long long n2 = (long long)norb * norb;
+  hipLaunchKernelGGL(k_slab_grids_i8, dim3((unsigned)grid_of(n2, 256)), dim3(256), 0, st, b, naux, norb, e);
   return launch_status();
 }
 

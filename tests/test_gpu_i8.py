@@ -144,15 +144,16 @@ def test_i8x10_exact_cancellation():
     assert float(host(D).__abs__().max()) == 0.0
 
 
-@pytest.mark.parametrize("naux,norb,seed", [(600, 256, 11), (450, 300, 12), (5, 70, 13)])
+@pytest.mark.parametrize("naux,norb,seed", [(600, 256, 11), (450, 300, 12), (5, 70, 13), (65600, 8, 14)])
 def test_i8x10_exchange_groups(naux, norb, seed):
-    """The INT8 exchange-type product sums over groups of auxiliary slabs whose
-    joint contraction (slabs x 64-padded rows) stays within the exact int32
-    depth of 65536: norb = 256 gives 256 slabs a group (600 = 256 + 256 + 88),
-    norb = 300 gives 204 (450 = 204 + 204 + 42), norb = 70 one group.  Each
-    row of a group has one grid over all its slabs; a slab far below the
-    others only loses digits below 2^-29 of the row's group maximum, which
-    the normwise bound of 3e-7 (relative to max|F1|, max|F2|) covers."""
+    """The INT8 exchange-type term with slabs far below the others.  Up to the
+    exact int32 depth (Naux <= 65536) it runs through the per-q symmetric
+    products G^q_rs = sum_P b^P[q][r] b^P[q][s], one INT8 product over all
+    slabs per q with one grid per (q, r); beyond it (Naux = 65600) as one
+    INT8 product per group of slabs whose joint contraction (slabs x 64-padded
+    rows) stays within 65536 (norb = 8: 1024 slabs a group, 65 groups).  A slab
+    far below the others only loses digits below 2^-29 of its grid's maximum,
+    which the normwise bound of 3e-7 (relative to max|F1|, max|F2|) covers."""
     nof = need_gpu()
     print(f"case i8x10 exchange groups naux={naux} norb={norb}", flush=True)
     rng = np.random.default_rng(seed)
