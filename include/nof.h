@@ -93,12 +93,17 @@ typedef enum { NOF_F64 = 0, NOF_F32 = 1, NOF_BF16 = 2, NOF_BF16X4 = 3, NOF_I8X4 
  *                 products of order <= 3 in four int32 accumulators (one per
  *                 order; exact for contractions shorter than 65536), combined
  *                 exactly in FP64.  T and b stored in FP32.  The exchange-type
- *                 term sums groups of auxiliary slabs as one INT8 contraction
- *                 each (as many slabs as keep slabs x 64-padded rows within
- *                 65536), one grid per row of b^P and of cK o b^P over the
- *                 group, an FP64 partial per group; the groups are split and
- *                 multiplied in chunks whose planes fit 8 GiB of workspace.
- *                 The batched plan takes that term as in NOF_P_BF16X10.
+ *                 term (Naux <= 65536) goes through the symmetric per-q
+ *                 products G^q_rs = sum_P b^P_qr b^P_qs (see nof_gen_fock):
+ *                 one INT8 contraction over P per q with one grid per (q, r)
+ *                 over all slabs, exact int32 sums written in FP64, chunks of
+ *                 q whose planes and G fit 4 GiB of workspace, then the
+ *                 cK-weighted sum over q in FP64.  Beyond Naux = 65536 it sums
+ *                 groups of auxiliary slabs as one INT8 contraction each (as
+ *                 many slabs as keep slabs x 64-padded rows within 65536), one
+ *                 grid per row of b^P and of cK o b^P over the group, an FP64
+ *                 partial per group, in chunks whose planes fit 8 GiB.  The
+ *                 batched plan takes that term as in NOF_P_BF16X10.
  * Reductions that produce J, K, lambda, g and E always accumulate in FP64. */
 typedef enum {
   NOF_P_F64 = 0, NOF_P_F32 = 1, NOF_P_BF16X1 = 2, NOF_P_BF16X3 = 3, NOF_P_BF16X6 = 4,
@@ -235,9 +240,9 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  * prec    NOF_P_F64 (bt = NOF_F64), NOF_P_F32 or a split form (bt = NOF_F32)
  *         for the matrix-core contraction (X6 and X10: three element-wise
  *         BF16 pieces, FP32 accumulation over 64 q of a slab, FP64 beyond; I8X10:
- *         INT8 fixed-point pieces over groups of slabs, exact int32 sums,
- *         FP64 across groups).
- * FP64: b^P is symmetric, so the exchange-type sum is
+ *         the symmetric per-q products below as INT8 fixed-point
+ *         contractions over P, exact int32 sums, FP64 beyond).
+ * FP64 and I8X10: b^P is symmetric, so the exchange-type sum is
  *   sum_q cK_sq G^q_rs,   G^q_rs = sum_P b^P_qr b^P_qs,
  * and every G^q is symmetric in (r, s): the matrix cores form the upper
  * tiles of the G^q (Naux Norb^2 (Norb+1) multiply-adds, half those of the
