@@ -207,3 +207,36 @@ def test_streamed_matches_in_memory():
     for k in ("J", "K", "lam", "g"):
         assert np.allclose(st[k], ref[k], rtol=0, atol=1e-13 * np.abs(ref[k]).max())
     assert abs(st["E"] - ref["E"]) <= 1e-13 * abs(ref["E"])
+
+
+def test_exchange_term_per_q_identity():
+    """The identity behind the GPU route of the FP64 and INT8 exchange-type
+    term: for symmetric b^P and symmetric cK,
+        sum_P sum_q b^P_rq cK_sq b^P_qs = sum_q cK[q][s] G^q_rs,
+        G^q_rs = sum_P b^P[q][r] b^P[q][s]   (each G^q symmetric),
+    checked against the oracle's F2 by brute-force loops over the indices;
+    with a non-symmetric cK the right side (which reads row q of cK) differs,
+    so the route relies on the coefficient matrices' symmetry."""
+    rng = np.random.default_rng(71)
+    naux, norb = 5, 6
+    b = rng.standard_normal((naux, norb, norb))
+    b = 0.5 * (b + b.transpose(0, 2, 1))
+    cK = rng.standard_normal((norb, norb))
+    cK = cK + cK.T
+    n = rng.uniform(0.0, 1.0, norb)
+    _, _, _, F2 = dfjk.gen_fock(b, n, np.zeros((norb, norb)), np.zeros((norb, norb)), cK)
+    G = np.zeros((norb, norb, norb))
+    for q in range(norb):
+        for r in range(norb):
+            for s in range(norb):
+                G[q, r, s] = sum(b[P, q, r] * b[P, q, s] for P in range(naux))
+    assert np.array_equal(G, G.transpose(0, 2, 1))
+    via = np.zeros((norb, norb))
+    for r in range(norb):
+        for s in range(norb):
+            via[r, s] = sum(cK[q, s] * G[q, r, s] for q in range(norb))
+    assert np.max(np.abs(via - F2)) <= 1e-12 * np.max(np.abs(F2))
+    cA = cK + np.triu(rng.standard_normal((norb, norb)), 1)      # not symmetric
+    _, _, _, F2a = dfjk.gen_fock(b, n, np.zeros((norb, norb)), np.zeros((norb, norb)), cA)
+    via_a = np.einsum("qs,qrs->rs", cA, G)
+    assert np.max(np.abs(via_a - F2a)) > 1e-3 * np.max(np.abs(F2a))
