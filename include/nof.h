@@ -246,7 +246,7 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  *   sum_q cK_sq G^q_rs,   G^q_rs = sum_P b^P_qr b^P_qs,
  * and every G^q is symmetric in (r, s): the matrix cores form the upper
  * tiles of the G^q (Naux Norb^2 (Norb+1) multiply-adds, half those of the
- * product over (P, q)), at most 1 GiB of them at a time in the workspace,
+ * product over (P, q)), at most 4 GiB of them at a time in the workspace,
  * and a pass adds cK_sq G^q_rs over q in a fixed order; the Coulomb-type sum
  * comes from the pass over the upper half of b (with K).  FP32 and the
  * x1 / x3 forms: the two sums over P are one contraction (nof_fock_terms),

@@ -259,8 +259,8 @@ def test_plan_layout_regions_fit_the_workspace(ninst, naux, nbf, norb, prec):
                 "F2part": ninst * gmax * n2, "F2": ninst * n2, "Epart": ninst * 8}
         if prec == "f64":
             # the per-q symmetric products of every instance, q values at a
-            # time within 1 GiB, in place of the exchange-term partials
-            gq = min(norb, max(1, (1 << 30) // (ninst * n2)))
+            # time within 4 GiB, in place of the exchange-term partials
+            gq = min(norb, max(1, (4 << 30) // (ninst * n2)))
             need["F2part"] = ninst * gq * n2
         if prec in ("x10", "i8x10", "f64"):
             need.update({"F1part": ninst * n2, "F1": ninst * n2})

@@ -24,9 +24,9 @@ SHAPES = [
     (5, 2, 3, 3),
     (130, 1, 130, 4),
     (1, 3, 1, 5),
-    # Norb = 600: the FP64 exchange-type term's per-q products G^q take two
-    # chunks of q (372 + 228 within 1 GiB)
-    (620, 6, 600, 6),
+    # Norb = 820: the FP64 exchange-type term's per-q products G^q take two
+    # chunks of q (798 + 22 within 4 GiB)
+    (830, 4, 820, 6),
 ]
 
 
