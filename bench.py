@@ -172,12 +172,12 @@ def main():
         # epilogue gives the second its column grids); the others call the
         # stages separately, so that each is timed on its own
         fused = prec in (nof.P_BF16X10, nof.P_I8X10)
-        # F32 and the x1 / x3 split forms fold the Coulomb-type term into the
-        # exchange-type product (the pass over b forms K alone); the FP64
-        # (symmetric per-q products), x6, x10 and INT8 exchange-type terms do
-        # not take it, so there the pass forms K and the Coulomb-type term
-        # together
-        folded = prec not in (nof.P_F64, nof.P_BF16X6, nof.P_BF16X10, nof.P_I8X10)
+        # the x1 / x3 split forms fold the Coulomb-type term into the
+        # exchange-type product (the pass over b forms K alone); the FP64 and
+        # FP32 (symmetric per-q products), x6, x10 and INT8 exchange-type
+        # terms do not take it, so there the pass forms K and the Coulomb-type
+        # term together
+        folded = prec not in (nof.P_F64, nof.P_F32, nof.P_BF16X6, nof.P_BF16X10, nof.P_I8X10)
         names = (["rotate"] + (["a1_a2_transform"] if fused else ["a1_transform_stage1", "a2_transform_stage2"])
                  + ["h_and_J"]
                  + (["a4_k_pass", "a5_a6_fock_terms"] if folded else ["a4_a5_coulomb_pass", "a6_exchange"])

@@ -242,14 +242,15 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D,
  *         BF16 pieces, FP32 accumulation over 64 q of a slab, FP64 beyond; I8X10:
  *         the symmetric per-q products below as INT8 fixed-point
  *         contractions over P, exact int32 sums, FP64 beyond).
- * FP64 and I8X10: b^P is symmetric, so the exchange-type sum is
+ * FP64, FP32 and I8X10: b^P is symmetric, so the exchange-type sum is
  *   sum_q cK_sq G^q_rs,   G^q_rs = sum_P b^P_qr b^P_qs,
  * and every G^q is symmetric in (r, s): the matrix cores form the upper
  * tiles of the G^q (Naux Norb^2 (Norb+1) multiply-adds, half those of the
  * product over (P, q)), at most 4 GiB of them at a time in the workspace,
  * and a pass adds cK_sq G^q_rs over q in a fixed order; the Coulomb-type sum
- * comes from the pass over the upper half of b (with K).  FP32 and the
- * x1 / x3 forms: the two sums over P are one contraction (nof_fock_terms),
+ * comes from the pass over the upper half of b (with K); FP32 b: FP32
+ * products and sums over P, G in FP64.  The x1 / x3 forms: the two sums over
+ * P are one contraction (nof_fock_terms),
  * the Coulomb-type sum being the exchange-type one with cK_sq b^P_qs
  * replaced by -W[P][s] on q = s, applied to the right operand as it is
  * staged.
@@ -263,7 +264,7 @@ int nof_gen_fock(int naux, int norb, const void* b, int bt, const double* D,
 
 /* ---------------------------------------------------------------------------
  * Both Fock terms of lambda (NO Optimization), as nof_gen_fock computes them
- * (FP32, x1, x3: in one matrix-core contraction; FP64 and the other forms:
+ * (x1, x3: in one matrix-core contraction; FP64, FP32 and the other forms:
  * the exchange-type term minus the Coulomb-type term of the pass):
  *   W = D cJ,
  *   F_rs = F2_rs - F1_rs = sum_P sum_q b^P_rq (cK_sq b^P_qs - [q = s] W[P][s])
@@ -292,7 +293,7 @@ int nof_exchange_fock(int naux, int norb, const void* b, int bt, const double* c
 /* ---------------------------------------------------------------------------
  * The Coulomb-type term of the generalized Fock build alone (the middle sum
  * of lambda above, NO Optimization), with K from the same pass over the
- * upper half of b (an HBM-bound pass; with FP32, x1 and x3 b nof_gen_fock
+ * upper half of b (an HBM-bound pass; with the x1 and x3 forms nof_gen_fock
  * folds this term into the exchange-type contraction instead):
  *   W = D cJ,   F1_rs = sum_P b^P_rs W[P][s],   K_pq = sum_P (b^P_pq)^2
  * b, bt, D, cJ as in nof_gen_fock.  F1 out [norb][norb] FP64 (not symmetric);

@@ -21,7 +21,12 @@ bool fixed_point(int prec) { return prec == NOF_P_BF16X10 || prec == NOF_P_I8X10
 // from the pass over b (with K) and is subtracted.  X6 shares the x10
 // exchange-type product (three element-wise BF16 pieces, six products);
 // FP64 takes the exchange-type term through the symmetric per-q products.
-bool f1_from_pass(int prec) { return fixed_point(prec) || prec == NOF_P_BF16X6 || prec == NOF_P_F64; }
+bool f1_from_pass(int prec) {
+  return fixed_point(prec) || prec == NOF_P_BF16X6 || prec == NOF_P_F64 || prec == NOF_P_F32;
+}
+// FP64 and FP32 take the exchange-type term through the per-q products G^q
+// on the FP64 / FP32 matrix cores (G in FP64).
+bool sym_route(int prec) { return prec == NOF_P_F64 || prec == NOF_P_F32; }
 
 
 
@@ -88,7 +93,7 @@ FockLayout fock_layout(int naux, int norb, int bt, int prec) {
   const size_t n2 = (size_t)norb * norb * sizeof(double);
   const bool fx = f1_from_pass(prec);
   const bool i8s = prec == NOF_P_I8X10 && i8_sym(naux);
-  L.gq = prec == NOF_P_F64 ? exchange_sym_chunk(norb) : i8s ? i8_sym_chunk(naux, norb) : 0;
+  L.gq = sym_route(prec) ? exchange_sym_chunk(norb) : i8s ? i8_sym_chunk(naux, norb) : 0;
   L.off_W = 0;
   L.off_f2part = align256((size_t)naux * norb * sizeof(double));
   L.off_F = align256(L.off_f2part + (L.gq > 0 ? (size_t)L.gq : (size_t)L.f2groups) * n2);
@@ -518,16 +523,17 @@ int nof_jk_diag(int naux, int norb, const void* b, int bt, const double* D, doub
 
 namespace {
 
-// FP64 exchange-type term through the per-q symmetric products.  b^P is
-// symmetric, so
+// FP64 / FP32 exchange-type term through the per-q symmetric products.  b^P
+// is symmetric, so
 //   F2_rs = sum_P sum_q b^P[r][q] cK[q][s] b^P[q][s] = sum_q cK[q][s] G^q_rs,
 //   G^q_rs = sum_P b^P[q][r] b^P[q][s],
 // and G^q is symmetric in (r, s): the batched product over q computes the
 // upper tiles only (Naux Norb^2 (Norb+1) multiply-adds against 2 Naux Norb^3
 // for the product over (P, q)), L.gq values of q at a time into G, each chunk
 // then added into F in q order.  With F1, F = F2 - F1.
-int exchange_sym(int naux, int norb, const double* b, const double* cK, const FockLayout& L, double* G,
+int exchange_sym(int naux, int norb, const void* b, int bt, const double* cK, const FockLayout& L, double* G,
                  const double* F1, double* F, hipStream_t stream) {
+  const size_t es = dtype_size(bt);
   const long long n2 = (long long)norb * norb;
   for (int q0 = 0; q0 < norb; q0 += L.gq) {
     const int qn = std::min(L.gq, norb - q0);
@@ -535,13 +541,14 @@ int exchange_sym(int naux, int norb, const double* b, const double* cK, const Fo
     GemmDesc g{};
     g.M = norb; g.N = norb; g.K = naux; g.Ktot = 0;
     g.batch = qn; g.fold = 1;
-    g.X = b + (long long)q0 * norb; g.ldx = n2; g.sx = norb; g.x_kmajor = true;
-    g.Y = b + (long long)q0 * norb; g.ldy = n2; g.sy = norb;
+    g.X = (const char*)b + (size_t)q0 * norb * es; g.ldx = n2; g.sx = norb; g.x_kmajor = true;
+    g.Y = (const char*)b + (size_t)q0 * norb * es; g.ldy = n2; g.sy = norb;
     g.S = nullptr; g.lds = 0;
     g.Out = G; g.ldo = norb; g.so = n2;
     g.Dg = nullptr; g.sd = 0; g.sym = true;
     g.role = GemmRole::ExchangeFock;
-    NOF_TRY(gemm_tn(g, NOF_F64, NOF_F64, NOF_F64, NOF_P_F64, stream));
+    // FP32: FP32 products and sums over P on the matrix cores, G written in FP64
+    NOF_TRY(gemm_tn(g, bt, bt, NOF_F64, bt == NOF_F64 ? NOF_P_F64 : NOF_P_F32, stream));
     const int mode = q0 > 0 ? 1 : (F1 ? 2 : 0);
     NOF_TRY(exchange_accum(G, qn, norb, cK + (long long)q0 * norb, F1, mode, F, stream));
   }
@@ -595,9 +602,9 @@ int exchange_term(int naux, int norb, const void* b, int bt, const double* cK, c
     NOF_TRY(i8_exchange(1, naux, norb, (const float*)b, 0, St, f2part, i8ws, stream));
     return reduce_parts(f2part, L.f2groups, n2, norb, false, F2, stream);
   }
-  if (prec == NOF_P_F64) {
+  if (sym_route(prec)) {
     if (W) return NOF_E_INTERNAL;
-    return exchange_sym(naux, norb, (const double*)b, cK, L, f2part, nullptr, F2, stream);
+    return exchange_sym(naux, norb, b, bt, cK, L, f2part, nullptr, F2, stream);
   }
   if (f1_from_pass(prec)) {
     if (W) return NOF_E_INTERNAL;               // this product takes no W (fock_terms)
@@ -635,9 +642,9 @@ int coulomb_weights(int naux, int norb, const double* D, const double* cJ, doubl
 }
 
 // F = F2 - F1 = sum_P sum_q b^P[r][q] (cK[q][s] b^P[q][s] - [q == s] W[P][s]).
-// FP32 (and x1 / x3): the Coulomb-type term rides in the exchange-type
-// product's operand loader.  FP64 takes the exchange-type term through the
-// symmetric per-q products (exchange_sym), the x6 / x10 product stages
+// x1 / x3: the Coulomb-type term rides in the exchange-type product's operand
+// loader.  FP64 and FP32 take the exchange-type term through the symmetric
+// per-q products (exchange_sym), the x6 / x10 product stages
 // element-wise pieces of FP32 values and the INT8 one fixed-point planes; none
 // of these takes it: there F1 comes from the pass over the upper half of b
 // (with K when Kpart is given: both from one read of b) and is subtracted.
@@ -655,8 +662,8 @@ int fock_terms(int naux, int norb, const void* b, int bt, const double* D, const
   NOF_TRY(kf1_pass(naux, norb, b, bt, W, Kpart, f1part, L.kchunks, stream));
   NOF_TRY(reduce_parts(f1part, L.kchunks, n2, norb, false, F1, stream));
   if (Kpart) NOF_TRY(reduce_parts(Kpart, L.kchunks, n2, norb, true, K, stream));
-  if (prec == NOF_P_F64)
-    return exchange_sym(naux, norb, (const double*)b, cK, L, (double*)(w + L.off_f2part), F1, F, stream);
+  if (sym_route(prec))
+    return exchange_sym(naux, norb, b, bt, cK, L, (double*)(w + L.off_f2part), F1, F, stream);
   NOF_TRY(exchange_term(naux, norb, b, bt, cK, nullptr, prec, L, (double*)(w + L.off_f2part),
                         (float*)(w + L.off_St), w + L.off_i8, F, stream));
   return subtract(n2, F1, F, stream);
